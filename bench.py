@@ -1,0 +1,154 @@
+"""Throughput of the coupled LBRMT step on one MI355X.
+
+Workload (default): the 2048 x 2048 lid-driven cavity with one neo-Hookean disc
+(tau 0.6, lid 0.05, disc R = 0.15 L at (0.5 L, 0.6 L), G 0.005, density ratio 1),
+FP64, synthetic initial state (fluid at rest), every input resident in HBM.
+A step is one full pass of Alg. 1: advection, 11 extrapolation layers,
+relabel, stress divergence, SFC + Guo collision with streaming and walls.
+
+Prints ONE JSON line: whole-job MLUPS (interior nodes x steps / s), the roofline
+of the dominant kernel (the lattice Boltzmann update of the tiles outside the
+solid band, timed with HIP events on its own stream), and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "coupled LBRMT step MLUPS & % HBM roofline; FP32/batched/adjoint vs FP64 plain"
+
+
+def _workload(name):
+    import workloads
+    return getattr(workloads, name)()
+
+
+def lb_bytes_per_node(precision):
+    s = 8 if precision == "f64" else 4
+    return 18 * s  # nine populations read, nine written (pull scheme, two lattices)
+
+
+def traffic_from_profile(kernel, workload, precision):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
+    when none exists or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    src = open(os.path.join(ROOT, "paper_2402_12696_amd", "csrc", "k_lb.hip"), "rb").read()
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    m = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != digest:
+        return None
+    return float(t.group(1))
+
+
+def run_gpu(cfg, precision, steps, warmup, timing_steps):
+    import torch
+    from paper_2402_12696_amd import Sim
+    sim = Sim(device="cuda:0", precision=precision, **cfg).init()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    diag = sim.diag(raise_unstable=False)
+    band_nodes, window_nodes = sim.band_nodes()
+    # per-kernel durations: eager launches bracketed by HIP events on the
+    # stream each kernel runs on
+    sim.set_timing(True)
+    sim.step(timing_steps)
+    torch.cuda.synchronize()
+    ktimes = {k: sim.kernel_time(k) for k in
+              ("advect", "extrap", "relabel", "force", "lb_bulk", "lb_band")}
+    sim.set_timing(False)
+    sim.close()
+    return ms_per_step, ktimes, band_nodes, window_nodes, diag
+
+
+def cpu_baseline(cfg, seconds=15.0):
+    from oracle import Oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle(**cfg).init()
+    o.step(1)
+    n, t = 0, 0.0
+    while t < seconds and n < 50:
+        t0 = time.perf_counter()
+        o.step(1)
+        t += time.perf_counter() - t0
+        n += 1
+    mlups = cfg["nx"] * cfg["ny"] * n / t / 1e6
+    return {"value": mlups, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of {cfg['name']} after 1 warm-up step "
+                      f"({t:.1f} s, OpenMP threads {threads})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=120)
+    ap.add_argument("--workload", default="cavity_disc_2048")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--timing-steps", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    cfg = _workload(args.workload)
+    nodes = cfg["nx"] * cfg["ny"]
+    ms, kt, band, window, diag = run_gpu(cfg, args.precision, args.steps, args.warmup,
+                                         args.timing_steps)
+    mlups = nodes / (ms * 1e-3) / 1e6
+
+    bulk_ms, bulk_n = kt["lb_bulk"]
+    bulk_nodes = nodes - band if kt["lb_band"][1] > 0 else nodes
+    bpn = lb_bytes_per_node(args.precision)
+    alg_bytes = bpn * bulk_nodes
+    achieved = alg_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None
+    traffic = traffic_from_profile("lb_bulk", args.workload, args.precision)
+    roof = {"kernel": "lb_bulk", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic, "bytes_per_launch": alg_bytes, "nodes_per_launch": bulk_nodes,
+            "avg_launch_ms": bulk_ms, "launches": bulk_n}
+
+    extra = {"kernel_avg_ms": {k: v[0] for k, v in kt.items()},
+             "band_region_nodes": band, "window_nodes": window,
+             "n_solid": diag["n_solid"], "n_band": diag["n_band"],
+             "health": diag["health"]}
+    if args.precision == "f64" and not args.no_f32:
+        ms32, kt32, _, _, d32 = run_gpu(cfg, "f32", args.steps, args.warmup, args.timing_steps)
+        extra["f32"] = {"ms_per_step": ms32, "mlups": nodes / (ms32 * 1e-3) / 1e6,
+                        "speedup_vs_f64": ms / ms32,
+                        "lb_bulk_avg_ms": kt32["lb_bulk"][0]}
+    line = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": cfg["name"], "nx": cfg["nx"], "ny": cfg["ny"], "tau": cfg["tau"],
+                   "lid_ux": cfg["lid_ux"], "solid": cfg["solid"], "layers": cfg["layers"],
+                   "eps": cfg["eps"]},
+        "roofline": roof,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(cfg),
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

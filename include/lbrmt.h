@@ -1,0 +1,194 @@
+/*
+ * lbrmt.h -- C ABI of the MI355X (gfx950) LBRMT time-step library.
+ *
+ * The library advances the lattice Boltzmann reference map technique of Sun &
+ * Rycroft ("A fully-integrated lattice Boltzmann method for fluid-structure
+ * interaction"): a D2Q9 BGK fluid with Guo body forcing (Sec. 2.2), the smooth
+ * flux correction across solid/fluid density differences (Sec. 2.3), and
+ * neo-Hookean solids tracked by a reference map xi on the same fixed grid
+ * (Secs. 2.1, 2.4, 3.1-3.3), one time step of Alg. 1 per iteration.
+ *
+ * Conventions used by every call:
+ *   - lattice units: dx = dt = 1; node (i, j), 0 <= i < nx, 0 <= j < ny, sits at
+ *     x = (i + 1/2, j + 1/2); no-slip walls are halfway, at x = 0, nx, y = 0, ny;
+ *     the top wall (y = ny) is the lid and moves with (lid_ux, 0).
+ *   - every field buffer is row-major [ny][nx], x fastest, float64, DEVICE memory,
+ *     interior nodes only; vector fields are separate planes.
+ *   - the caller owns the workspace, every input/output buffer and the stream;
+ *     the library owns only a small host-side context (freed by lbrmt_destroy)
+ *     plus one internal stream and a few events for fork/join inside a step.
+ *     It never allocates device memory.
+ *   - every call is stream-ordered on the context's stream and asynchronous
+ *     unless stated otherwise; no call synchronises except lbrmt_diag,
+ *     lbrmt_health and lbrmt_validate (host only).
+ *   - no exception crosses the ABI; every call returns an lbrmt_status.  A
+ *     context is not thread-safe; separate contexts are independent.
+ */
+#ifndef LBRMT_H
+#define LBRMT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBRMT_OK = 0,
+    LBRMT_EINVAL = 1,      /* null pointer, nx or ny < 8, tau <= 1/2, bad shape  */
+    LBRMT_EWORKSPACE = 2,  /* workspace too small or misaligned (256 B)          */
+    LBRMT_EHIP = 3,        /* a HIP call failed; text via lbrmt_last_error       */
+    LBRMT_EUNSTABLE = 4,   /* device health counters report a failure            */
+    LBRMT_ECAPACITY = 5,   /* more solids than the context was created for       */
+    LBRMT_ESTATE = 6       /* call out of order (e.g. step before init)          */
+} lbrmt_status;
+
+typedef enum { LBRMT_FP64 = 0, LBRMT_FP32 = 1 } lbrmt_precision;
+
+/* Grid and fluid parameters (Table "sim_quantities", Secs. 2.2-2.4, 3.5). */
+typedef struct {
+    int32_t nx, ny;          /* interior nodes                                   */
+    int32_t periodic_x;      /* 1: periodic along x (Sec. 3.5), 0: halfway walls */
+    int32_t periodic_y;      /* 1: periodic along y, 0: walls with the lid on top*/
+    double tau;              /* BGK relaxation time, nu = (tau - 1/2)/3          */
+    double lid_ux;           /* top-wall velocity (ignored when periodic_y)      */
+    double gx, gy;           /* gravity g; the solid feels (1-H)(rho_s-rho_f) g  */
+    double fext_x, fext_y;   /* uniform external force density on the fluid (H-weighted) */
+    double rho_f;            /* fluid density (1 in lattice units)               */
+    double eps;              /* blur-zone half-width epsilon of H_eps            */
+    int32_t layers;          /* extrapolation-zone layers (11)                   */
+    int32_t r_max;           /* largest least-squares scan half-width (8)        */
+    double det_rel;          /* fit ill-defined if det M <= det_rel (sum w)^3 (1e-8) */
+    double detJ_min;         /* half-edge stress dropped if det(grad xi) <= this (1e-12) */
+    int32_t precision;       /* lbrmt_precision                                  */
+    int32_t reserved;
+} lbrmt_grid_desc;
+
+/* One solid (Sec. 3.6 "mat_const"/"object"): a disc (shape 0) of radius a. */
+typedef struct {
+    int32_t shape;           /* 0: disc                                          */
+    int32_t reserved;
+    double cx, cy;           /* centre of the reference (undeformed) shape       */
+    double a, b;             /* disc: radius a (b unused)                        */
+    double theta;            /* orientation (unused for a disc)                  */
+    double G;                /* small-strain shear modulus                       */
+    double rho_s;            /* solid density                                    */
+} lbrmt_solid_desc;
+
+/* Device health counters (cumulative since lbrmt_init). */
+typedef enum {
+    LBRMT_H_ADVECT_MISS = 0, /* advection stencil node without a reference map   */
+    LBRMT_H_EXTRAP_FAIL = 1, /* zone node left unset after r > r_max             */
+    LBRMT_H_STRESS_MISS = 2, /* half-edge stencil node without a reference map   */
+    LBRMT_H_DETJ = 3,        /* half-edge with det(grad xi) <= detJ_min          */
+    LBRMT_H_DETJ_SOLID = 4,  /* ... of those, edges with solid fraction > 1/2    */
+    LBRMT_H_NONFINITE = 5,   /* nodes whose density is not finite or <= 0        */
+    LBRMT_H_WINDOW_CLIP = 6, /* body window reached a periodic seam (unsupported)*/
+    LBRMT_H_COUNT = 8
+} lbrmt_health_index;
+
+/* lbrmt_diag output: FP64 reductions over interior nodes of the state f^n. */
+typedef struct {
+    int64_t step;            /* completed steps                                  */
+    double mass;             /* sum_nodes sum_i f_i                              */
+    double mom_x, mom_y;     /* sum_nodes (sum_i c_i f_i + F/2)                  */
+    double centroid_x, centroid_y; /* sum lambda x / sum lambda, lambda = 1 - H(phi) */
+    double disp_x, disp_y;   /* sum lambda (x - xi) / sum lambda                 */
+    double max_u;            /* max |u|                                          */
+    double n_solid;          /* nodes with phi < 0                               */
+    double n_band;           /* nodes holding a reference map                    */
+    uint32_t health[LBRMT_H_COUNT];
+} lbrmt_diag_t;
+
+/* lbrmt_validate output (App. A): derived numbers and warnings. */
+typedef struct {
+    double nu;               /* (tau - 1/2) / 3                                  */
+    double mach_lb;          /* Ma* = |lid| / sqrt(1/3)                           */
+    double reynolds;         /* |lid| * nx / nu                                  */
+    int32_t tau_ok;          /* 1/2 < tau <= 1                                   */
+    int32_t mach_ok;         /* Ma* <= 0.3                                       */
+    int32_t solids_inside;   /* every solid's zone fits inside the padded grid  */
+    int32_t reserved;
+} lbrmt_validation_t;
+
+typedef struct lbrmt_ctx lbrmt_ctx;
+
+/* Status text; never NULL. */
+const char* lbrmt_status_string(int status);
+/* Text of the last error on this context (empty string if none). */
+const char* lbrmt_last_error(const lbrmt_ctx* ctx);
+
+/* Bytes of device workspace a context of this shape needs (host only). */
+int lbrmt_workspace_bytes(const lbrmt_grid_desc* desc, int32_t max_solids, size_t* bytes);
+
+/* Create a context on caller workspace d_workspace (device, 256-B aligned, at
+ * least lbrmt_workspace_bytes) and caller stream hip_stream (hipStream_t, may
+ * be NULL for the null stream).  The context never frees the workspace. */
+int lbrmt_create(const lbrmt_grid_desc* desc, int32_t max_solids, void* d_workspace,
+                 size_t bytes, void* hip_stream, lbrmt_ctx** out);
+void lbrmt_destroy(lbrmt_ctx* ctx);
+
+/* Register solids (before lbrmt_init).  ECAPACITY beyond max_solids. */
+int lbrmt_add_solids(lbrmt_ctx* ctx, const lbrmt_solid_desc* solids, int32_t n);
+
+/* Alg. 1 initialisation: xi = x on the solid and its extrapolation zone, phi
+ * from the reference shape, rho = H rho_f + (1-H) rho_s, v = v0 and f = f^eq
+ * of Eq. (2_3_feq_sfc).  d_u0: NULL (fluid at rest) or device float64
+ * [2][ny][nx] (ux plane, then uy plane). */
+int lbrmt_init(lbrmt_ctx* ctx, const double* d_u0);
+
+/* Advance nsteps time steps of Alg. 1 (asynchronous). */
+int lbrmt_step(lbrmt_ctx* ctx, int64_t nsteps);
+int64_t lbrmt_step_count(const lbrmt_ctx* ctx);
+
+/* rho^n and u^n (half-force velocity of Eq. (2_2_lbm_moments_force)); any
+ * pointer may be NULL. */
+int lbrmt_read_macro(lbrmt_ctx* ctx, double* d_rho, double* d_ux, double* d_uy);
+/* pre-collision populations f_i^n, [9][ny][nx] */
+int lbrmt_read_populations(lbrmt_ctx* ctx, double* d_f9);
+/* force density F used by the last step (Eq. (2_4_F_divs)) */
+int lbrmt_read_force(lbrmt_ctx* ctx, double* d_fx, double* d_fy);
+/* reference map xi = (X, Y) and level set phi of solid `solid`; NaN where the
+ * node holds no reference map.  Any pointer may be NULL. */
+int lbrmt_read_refmap(lbrmt_ctx* ctx, int32_t solid, double* d_X, double* d_Y, double* d_phi);
+/* node average of the four blended half-edge solid stresses (1-H) tau_s
+ * (Eqs. (3_3_solid_stress), (2_4_smooth_stress)); xx, xy, yy planes. */
+int lbrmt_read_stress(lbrmt_ctx* ctx, double* d_sxx, double* d_sxy, double* d_syy);
+
+/* Reductions of the current state into host memory (synchronises the stream).
+ * Returns EUNSTABLE if a NONFINITE, DETJ_SOLID or EXTRAP_FAIL counter is set. */
+int lbrmt_diag(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
+
+/* Checkpoint: an opaque device blob of lbrmt_state_bytes bytes holding the
+ * whole step state; load restores it bit for bit (same context shape). */
+int lbrmt_state_bytes(const lbrmt_ctx* ctx, size_t* bytes);
+int lbrmt_save_state(lbrmt_ctx* ctx, void* d_buf);
+int lbrmt_load_state(lbrmt_ctx* ctx, const void* d_buf);
+
+/* Failure injection for tests: field 0 sets every population of interior node
+ * `index` (= j*nx + i) to `value`. */
+int lbrmt_debug_poke(lbrmt_ctx* ctx, int32_t field, int64_t index, double value);
+
+/* Host-only check of App. A constraints (1/2 < tau <= 1, Ma* <= 0.3) and of
+ * solid placement; EINVAL for unusable input, OK with flags otherwise. */
+int lbrmt_validate(const lbrmt_grid_desc* desc, const lbrmt_solid_desc* solids, int32_t n,
+                   lbrmt_validation_t* out);
+
+/* Average device time (ms) per launch of each step kernel, measured with HIP
+ * events on the stream each kernel runs on.  Enabling timing makes lbrmt_step
+ * launch eagerly (no graph) and bracket every kernel with events; names:
+ * "advect", "extrap", "relabel", "force", "lb_bulk", "lb_band". */
+int lbrmt_set_timing(lbrmt_ctx* ctx, int32_t enable);
+int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t* launches);
+
+/* band_nodes: nodes the next step's "lb_band" launch updates (the lattice
+ * tiles that meet the solid windows of this and the previous step; "lb_bulk"
+ * updates the rest); window_nodes: nodes of the current working window of the
+ * reference map.  Synchronises the stream. */
+int lbrmt_band_nodes(lbrmt_ctx* ctx, int64_t* band_nodes, int64_t* window_nodes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBRMT_H */

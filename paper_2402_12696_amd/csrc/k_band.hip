@@ -1,0 +1,761 @@
+// Reference-map ("band") kernels of the LBRMT step on gfx950: advection of xi
+// (Sec. 3.1), layer-by-layer least-squares extrapolation (Sec. 3.2), relabel
+// phi = phi0(xi), and the divergence of the blended half-edge solid stress
+// fed back as the LB force density (Sec. 3.3, Eq. (2_4_F_divs)).
+//
+// All of them work inside one rectangular window per body: the box of the
+// interior solid nodes dilated by the number of extrapolation layers, kept in
+// a device ring of three boxes (previous, current, next step) so no host
+// round trip is needed.  A node outside a window holds no reference map.
+//
+// These kernels make every discrete decision of the method (solid set, layer
+// membership, window growth of the fit, singular Jacobians); this file is
+// compiled without floating-point contraction so those decisions are taken in
+// plain IEEE double arithmetic.
+#include "lbrmt_internal.h"
+
+namespace lbrmt {
+
+constexpr double PI_D = 3.14159265358979323846;
+
+__device__ __forceinline__ double heaviside(double phi, double eps)
+{
+    // Eq. (2_3_heaviside)
+    if (phi <= -eps) return 0.0;
+    if (phi >= eps) return 1.0;
+    return 0.5 * (1.0 + phi / eps + sin(PI_D * phi / eps) / PI_D);
+}
+
+// reference shape level set phi0(X): disc |X - c| - R
+__device__ __forceinline__ double shape_phi(const BodyP& b, double X, double Y)
+{
+    const double dx = X - b.cx, dy = Y - b.cy;
+    return sqrt(dx * dx + dy * dy) - b.R;
+}
+
+// coordinate of node index i on an axis; on a periodic axis the image nearest
+// to the body centre keeps the reference map continuous
+__device__ __forceinline__ double node_coord(int i, int periodic, int n, double c)
+{
+    double x = i + 0.5;
+    if (periodic) {
+        const double L = n;
+        double d = x - c;
+        d -= L * floor(d / L + 0.5);
+        x = c + d;
+    }
+    return x;
+}
+
+__device__ __forceinline__ bool tag_valid_before(int8_t t, int l)
+{
+    // solid, or set by an earlier layer
+    return t == TAG_SOLID || (t > 0 && t < l);
+}
+
+__device__ __forceinline__ bool tag_set(int8_t t)
+{
+    return t == TAG_SOLID || (t > 0 && t < TAG_FAIL);
+}
+
+// ---------------------------------------------------------------- block min/max
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// reduce a box over the block, one atomic per component per block
+__device__ void box_atomic(Win* dst, int i0, int i1, int j0, int j1)
+{
+    __shared__ int sb[4][16];
+    i0 = wave_min(i0);
+    i1 = wave_max(i1);
+    j0 = wave_min(j0);
+    j1 = wave_max(j1);
+    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int nw = (blockDim.x + 63) / 64;
+    if (lane == 0) {
+        sb[0][wid] = i0;
+        sb[1][wid] = i1;
+        sb[2][wid] = j0;
+        sb[3][wid] = j1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; w++) {
+            i0 = min(i0, sb[0][w]);
+            i1 = max(i1, sb[1][w]);
+            j0 = min(j0, sb[2][w]);
+            j1 = max(j1, sb[3][w]);
+        }
+        if (i0 <= i1) {
+            atomicMin(&dst->i0, i0);
+            atomicMax(&dst->i1, i1);
+            atomicMin(&dst->j0, j0);
+            atomicMax(&dst->j1, j1);
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- window ring
+
+__global__ void k_win_reset(Win* win, int slot)
+{
+    if (threadIdx.x == 0) {
+        win[slot].i0 = 0x3fffffff;
+        win[slot].i1 = -0x3fffffff;
+        win[slot].j0 = 0x3fffffff;
+        win[slot].j1 = -0x3fffffff;
+    }
+}
+
+hipError_t launch_win_reset(Win* win, int slot, hipStream_t st)
+{
+    k_win_reset<<<1, 64, 0, st>>>(win, slot);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- initialisation
+
+// box of the initial solid set {interior nodes: phi0(x) < 0}
+__global__ __launch_bounds__(256) void k_init_solid_box(GridP g, BodyP b, Win* win, int s0, int s1)
+{
+    const long long N = (long long)g.nx * g.ny;
+    int i0 = 0x3fffffff, i1 = -0x3fffffff, j0 = 0x3fffffff, j1 = -0x3fffffff;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long first = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long iters = (N + stride - 1) / stride;
+    for (long long it = 0; it < iters; it++) {
+        const long long e = first + it * stride;
+        if (e < N) {
+            const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+            const double x = node_coord(i, g.px, g.nx, b.cx);
+            const double y = node_coord(j, g.py, g.ny, b.cy);
+            if (shape_phi(b, x, y) < 0.0) {
+                i0 = min(i0, i);
+                i1 = max(i1, i);
+                j0 = min(j0, j);
+                j1 = max(j1, j);
+            }
+        }
+    }
+    box_atomic(&win[s0], i0, i1, j0, j1);
+    box_atomic(&win[s1], i0, i1, j0, j1);
+}
+
+hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, Win* win, int slot0, int slot1,
+                                 hipStream_t st)
+{
+    k_init_solid_box<<<1024, 256, 0, st>>>(g, b, win, slot0, slot1);
+    return hipGetLastError();
+}
+
+__global__ void k_init_tags(GridP g, BodyP b, int8_t* tag, const Win* win, int wslot)
+{
+    const Rect W = window_of(win, wslot, g);
+    if (!W.ok) return;
+    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+        const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+        const double x = node_coord(i, g.px, g.nx, b.cx);
+        const double y = node_coord(j, g.py, g.ny, b.cy);
+        tag[pidx(g, i, j)] = (interior && shape_phi(b, x, y) < 0.0) ? TAG_SOLID : TAG_NONE;
+    }
+}
+
+hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
+                            hipStream_t st)
+{
+    k_init_tags<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot);
+    return hipGetLastError();
+}
+
+// xi_0 = x on the solid and its extrapolation zone, phi = phi0(x) (Alg. 1 init)
+__global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win, int wslot,
+                            double* X, double* Y, double* phi)
+{
+    const Rect W = window_of(win, wslot, g);
+    if (!W.ok) return;
+    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+        const long long k = pidx(g, i, j);
+        if (tag[k] != TAG_NONE) {
+            const double x = node_coord(i, g.px, g.nx, b.cx);
+            const double y = node_coord(j, g.py, g.ny, b.cy);
+            X[k] = x;
+            Y[k] = y;
+            phi[k] = shape_phi(b, x, y);
+        } else {
+            X[k] = NAN;
+            Y[k] = NAN;
+            phi[k] = INFINITY;
+        }
+    }
+}
+
+hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
+                            hipStream_t st)
+{
+    k_init_fill<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, bb.X[0], bb.Y[0], bb.phi[0]);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- advection
+
+// pull-gather of the nine populations of interior node (i, j) and the
+// half-force velocity of Eq. (2_2_lbm_moments_force)
+template <typename S>
+__device__ void node_velocity(const GridP& g, const S* __restrict__ A, int i, int j, double Fx,
+                              double Fy, double& ux, double& uy)
+{
+    const long long P = g.plane;
+    const bool bw = !g.px && i == 0, be = !g.px && i == g.nx - 1;
+    const bool bs = !g.py && j == 0, bn = !g.py && j == g.ny - 1;
+    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
+    im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
+    ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
+    jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
+    jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
+    const long long r0 = (long long)j * g.pitch, rm = (long long)jm * g.pitch,
+                    rp = (long long)jp * g.pitch, n = r0 + i;
+    double f[NQ];
+    f[0] = A[n];
+    f[1] = bw ? A[3 * P + n] : A[1 * P + r0 + im];
+    f[2] = bs ? A[4 * P + n] : A[2 * P + rm + i];
+    f[3] = be ? A[1 * P + n] : A[3 * P + r0 + ip];
+    f[4] = bn ? A[2 * P + n] : A[4 * P + rp + i];
+    f[5] = (bw || bs) ? A[7 * P + n] : A[5 * P + rm + im];
+    f[6] = (be || bs) ? A[8 * P + n] : A[6 * P + rm + ip];
+    f[7] = (be || bn) ? A[5 * P + n] : A[7 * P + rp + ip];
+    f[8] = (bw || bn) ? A[6 * P + n] : A[8 * P + rp + im];
+    if (sizeof(S) == 4) {
+        const double wq[NQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+        for (int k = 0; k < NQ; k++) f[k] += wq[k] * g.rho_f;
+    }
+    const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    ux = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (2.0 * rho);
+    uy = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (2.0 * rho);
+}
+
+// reference-map value at (i, j) if present (canonicalised, inside window D,
+// finite phi)
+struct RefRead {
+    const double *X, *Y, *phi;
+    Rect D;
+    __device__ __forceinline__ bool get(const GridP& g, int i, int j, double& x, double& y) const
+    {
+        if (!canon(g, i, j) || !D.has(i, j)) return false;
+        const long long k = pidx(g, i, j);
+        if (!(phi[k] < INFINITY)) return false;
+        x = X[k];
+        y = Y[k];
+        return true;
+    }
+};
+
+// one-sided second-order upwind derivative of Eq. (3_1_eno) along (di, dj)
+__device__ __forceinline__ bool upwind(const GridP& g, const RefRead& R, int i, int j, int di,
+                                       int dj, double vel, double X0, double Y0, double& dX,
+                                       double& dY)
+{
+    dX = dY = 0.0;
+    if (vel == 0.0) return true;
+    const int sg = vel > 0.0 ? 1 : -1;
+    double X1, Y1, X2, Y2;
+    if (!R.get(g, i - sg * di, j - sg * dj, X1, Y1)) return false;
+    if (!R.get(g, i - 2 * sg * di, j - 2 * sg * dj, X2, Y2)) return false;
+    if (sg > 0) {
+        dX = (3.0 * X0 - 4.0 * X1 + X2) / 2.0;
+        dY = (3.0 * Y0 - 4.0 * Y1 + Y2) / 2.0;
+    } else {
+        dX = (-3.0 * X0 + 4.0 * X1 - X2) / 2.0;
+        dY = (-3.0 * Y0 + 4.0 * Y1 - Y2) / 2.0;
+    }
+    return true;
+}
+
+// Eq. (3_1_refmap_adv) on the solid nodes S^n = {interior, phi^n < 0}; also
+// resets the step's tags (solid or none) over the window and the ring slot
+// that relabel will fill with the box of S^{n+1}.
+template <typename S>
+__global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A,
+                                                const double* __restrict__ fpx,
+                                                const double* __restrict__ fpy, double fpo_x,
+                                                double fpo_y, const double* __restrict__ X,
+                                                const double* __restrict__ Y,
+                                                const double* __restrict__ phi, double* X1,
+                                                double* Y1, int8_t* tag, Win* win, int wprev,
+                                                int wcur, int wnext, unsigned* health)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        win[wnext].i0 = 0x3fffffff;
+        win[wnext].i1 = -0x3fffffff;
+        win[wnext].j0 = 0x3fffffff;
+        win[wnext].j1 = -0x3fffffff;
+    }
+    const Rect W = window_of(win, wcur, g);
+    if (!W.ok) return;
+    RefRead R;
+    R.X = X;
+    R.Y = Y;
+    R.phi = phi;
+    R.D = window_of(win, wprev, g);
+    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+        const long long k = pidx(g, i, j);
+        const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+        const bool solid = interior && R.D.has(i, j) && phi[k] < 0.0;
+        tag[k] = solid ? TAG_SOLID : TAG_NONE;
+        if (!solid) continue;
+        const long long n = (long long)j * g.pitch + i;
+        double Fx = fpo_x, Fy = fpo_y;
+        if (R.D.has(i, j)) {
+            Fx = fpx[n];
+            Fy = fpy[n];
+        }
+        double u, v;
+        node_velocity<S>(g, A, i, j, Fx, Fy, u, v);
+        const double X0 = X[k], Y0 = Y[k];
+        double dXx, dYx, dXy, dYy;
+        const bool okx = upwind(g, R, i, j, 1, 0, u, X0, Y0, dXx, dYx);
+        const bool oky = upwind(g, R, i, j, 0, 1, v, X0, Y0, dXy, dYy);
+        if (!okx || !oky) {
+            atomicAdd(&health[0], 1u);
+            X1[k] = X0;
+            Y1[k] = Y0;
+        } else {
+            X1[k] = X0 - (u * dXx + v * dXy);
+            Y1[k] = Y0 - (u * dYx + v * dYy);
+        }
+    }
+}
+
+hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
+                         const StepSlots& s, const void* A, const double* fpx, const double* fpy,
+                         double fpo_x, double fpo_y, hipStream_t st)
+{
+    (void)b;
+    if (precision == 0)
+        k_advect<double><<<2048, 256, 0, st>>>(g, (const double*)A, fpx, fpy, fpo_x, fpo_y,
+                                               bb.X[s.cur], bb.Y[s.cur], bb.phi[s.cur],
+                                               bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
+                                               s.wcur, s.wnext, bb.health);
+    else
+        k_advect<float><<<2048, 256, 0, st>>>(g, (const float*)A, fpx, fpy, fpo_x, fpo_y,
+                                              bb.X[s.cur], bb.Y[s.cur], bb.phi[s.cur],
+                                              bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
+                                              s.wcur, s.wnext, bb.health);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- extrapolation
+
+__device__ __forceinline__ double det3(double a00, double a01, double a02, double a10,
+                                       double a11, double a12, double a20, double a21,
+                                       double a22)
+{
+    return a00 * (a11 * a22 - a12 * a21) - a01 * (a10 * a22 - a12 * a20) +
+           a02 * (a10 * a21 - a11 * a20);
+}
+
+// Layer l of Sec. 3.2: nodes without a tag that touch a layer-(l-1) node
+// (4-adjacency) join layer l; unless mark_only, each is extrapolated with a
+// weighted linear least-squares fit over the valid nodes (solid, or set in an
+// earlier layer) of a scan window grown from half-width 2 until at least three
+// valid nodes give a well-posed fit.  Targets of one layer never read each
+// other, so the result does not depend on thread order.
+__global__ __launch_bounds__(256) void k_layer(GridP g, const Win* __restrict__ win, int wcur,
+                                               int wprev, int l, int mark_only, int8_t* tag,
+                                               const double* __restrict__ phin, double* X1,
+                                               double* Y1, unsigned* health)
+{
+    const Rect W = window_of(win, wcur, g);
+    if (!W.ok) return;
+    const Rect D = window_of(win, wprev, g);
+    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+        const long long kt = pidx(g, i, j);
+        if (tag[kt] != TAG_NONE) continue;
+        bool hit = false;
+        const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+        for (int d = 0; d < 4; d++) {
+            int ni = i + nb[d][0], nj = j + nb[d][1];
+            if (!canon(g, ni, nj) || !W.has(ni, nj)) continue;
+            const int8_t t = tag[pidx(g, ni, nj)];
+            if (t != TAG_NONE && (t & 63) == l - 1) hit = true;
+        }
+        if (!hit) continue;
+        if (mark_only) {
+            tag[kt] = (int8_t)l;
+            continue;
+        }
+        // outward normal of phi^n at the target for the first two layers
+        bool use_n = false;
+        double nxh = 0.0, nyh = 0.0;
+        if (l <= 2) {
+            double pv[4];
+            bool ok = true;
+            for (int d = 0; d < 4 && ok; d++) {
+                int ni = i + nb[d][0], nj = j + nb[d][1];
+                if (!canon(g, ni, nj) || !D.has(ni, nj)) {
+                    ok = false;
+                    break;
+                }
+                pv[d] = phin[pidx(g, ni, nj)];
+                if (!(pv[d] < INFINITY)) ok = false;
+            }
+            if (ok) {
+                const double gx = (pv[0] - pv[1]) / 2.0;
+                const double gy = (pv[2] - pv[3]) / 2.0;
+                const double gn = sqrt(gx * gx + gy * gy);
+                if (gn > 0.0) {
+                    nxh = gx / gn;
+                    nyh = gy / gn;
+                    use_n = true;
+                }
+            }
+        }
+        bool done = false;
+        for (int r = 2; r <= g.r_max && !done; r++) {
+            int count = 0;
+            for (int b = -r; b <= r; b++)
+                for (int a = -r; a <= r; a++) {
+                    int ci = i + a, cj = j + b;
+                    if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
+                    if (tag_valid_before(tag[pidx(g, ci, cj)], l)) count++;
+                }
+            if (count < 3) continue;
+            double M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0;
+            double bX0 = 0, bX1 = 0, bX2 = 0, bY0 = 0, bY1 = 0, bY2 = 0;
+            for (int b = -r; b <= r; b++)
+                for (int a = -r; a <= r; a++) {
+                    int ci = i + a, cj = j + b;
+                    if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
+                    const long long k = pidx(g, ci, cj);
+                    if (!tag_valid_before(tag[k], l)) continue;
+                    double wt = ldexp(1.0, -(abs(a) + abs(b)));  // Eq. (3_2_extrap_weight)
+                    if (l <= 2 && use_n) {
+                        const double ddx = -(double)a, ddy = -(double)b;
+                        const double dn = (ddx * nxh + ddy * nyh) / sqrt(ddx * ddx + ddy * ddy);
+                        wt = dn * wt > 0.0 ? dn * wt : 0.0;
+                    }
+                    const double dx = a, dy = b;
+                    const double xv = X1[k], yv = Y1[k];
+                    M00 += wt * dx * dx;
+                    M01 += wt * dx * dy;
+                    M02 += wt * dx;
+                    M11 += wt * dy * dy;
+                    M12 += wt * dy;
+                    M22 += wt;
+                    bX0 += wt * dx * xv;
+                    bX1 += wt * dy * xv;
+                    bX2 += wt * xv;
+                    bY0 += wt * dx * yv;
+                    bY1 += wt * dy * yv;
+                    bY2 += wt * yv;
+                }
+            const double det = det3(M00, M01, M02, M01, M11, M12, M02, M12, M22);
+            if (!(det > g.det_rel * M22 * M22 * M22)) continue;
+            X1[kt] = det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det;
+            Y1[kt] = det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det;
+            done = true;
+        }
+        if (done) {
+            tag[kt] = (int8_t)l;
+        } else {
+            tag[kt] = (int8_t)(l | TAG_FAIL);
+            atomicAdd(&health[1], 1u);
+        }
+    }
+}
+
+hipError_t launch_layer_pass(const GridP& g, const BandBufs& bb, int wslot, int wprev, int l,
+                             int mark_only, const double* phin, double* X1, double* Y1,
+                             hipStream_t st)
+{
+    k_layer<<<2048, 256, 0, st>>>(g, bb.win, wslot, wprev, l, mark_only, bb.tag, phin, X1, Y1,
+                                  bb.health);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- relabel
+
+// phi^{n+1} = phi0(xi^{n+1}) on every node holding a reference map (Alg. 1);
+// box of the new interior solid set into the next ring slot
+__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t* __restrict__ tag,
+                                                 Win* win, int wcur, int wnext, double* X1,
+                                                 double* Y1, double* phi1)
+{
+    const Rect W = window_of(win, wcur, g);
+    if (!W.ok) return;
+    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+    int i0 = 0x3fffffff, i1 = -0x3fffffff, j0 = 0x3fffffff, j1 = -0x3fffffff;
+    const long long total = (long long)w * h;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long first = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long iters = (total + stride - 1) / stride;
+    for (long long it = 0; it < iters; it++) {
+        const long long e = first + it * stride;
+        if (e < total) {
+            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+            const long long k = pidx(g, i, j);
+            if (tag_set(tag[k])) {
+                const double p = shape_phi(b, X1[k], Y1[k]);
+                phi1[k] = p;
+                if (p < 0.0 && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+                    i0 = min(i0, i);
+                    i1 = max(i1, i);
+                    j0 = min(j0, j);
+                    j1 = max(j1, j);
+                }
+            } else {
+                phi1[k] = INFINITY;
+                X1[k] = NAN;
+                Y1[k] = NAN;
+            }
+        }
+    }
+    box_atomic(&win[wnext], i0, i1, j0, j1);
+}
+
+hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
+                          hipStream_t st)
+{
+    k_relabel<<<1024, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur, s.wnext, bb.X[s.nxt],
+                                    bb.Y[s.nxt], bb.phi[s.nxt]);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- stress and force
+
+constexpr int FTX = 32, FTY = 8;
+constexpr int SX = FTX + 2, SY = FTY + 2;
+
+// Blended stress (1 - H(phi_e)) tau_s of one half-edge from the LDS tile.
+// a, b: the two nodes of the edge (a before b along the normal direction);
+// s1..s4: the side nodes of the tangential difference (s1 + s2 - s3 - s4)/4
+// (Eq. (3_3_refmap_jacobian), six-node stencil); dir 0: x-edge, 1: y-edge.
+__device__ void edge_tau(const GridP& g, const BodyP& b, const double* sX, const double* sY,
+                         const double* sP, int a, int bb, int s1, int s2, int s3, int s4, int dir,
+                         bool count, unsigned* health, double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    const double pa = sP[a], pb = sP[bb];
+    if (!(pa < INFINITY) || !(pb < INFINITY)) return;
+    const double phie = 0.5 * (pa + pb);
+    const double lam = 1.0 - heaviside(phie, g.eps);
+    if (!(lam > 0.0)) return;
+    if (!(sP[s1] < INFINITY) || !(sP[s2] < INFINITY) || !(sP[s3] < INFINITY) ||
+        !(sP[s4] < INFINITY)) {
+        if (count) atomicAdd(&health[2], 1u);
+        return;
+    }
+    const double nX = sX[bb] - sX[a], nY = sY[bb] - sY[a];
+    const double tX = (sX[s1] + sX[s2] - sX[s3] - sX[s4]) / 4.0;
+    const double tY = (sY[s1] + sY[s2] - sY[s3] - sY[s4]) / 4.0;
+    double J0, J1, J2, J3;  // [dX/dx, dX/dy; dY/dx, dY/dy]
+    if (dir == 0) {
+        J0 = nX; J1 = tX; J2 = nY; J3 = tY;
+    } else {
+        J0 = tX; J1 = nX; J2 = tY; J3 = nY;
+    }
+    const double det = J0 * J3 - J1 * J2;
+    if (!(det > g.detJ_min)) {
+        if (count) {
+            atomicAdd(&health[3], 1u);
+            if (lam > 0.5) atomicAdd(&health[4], 1u);
+        }
+        return;
+    }
+    // F = J^{-1} (Eq. (3_3_refmap_deformation)); plane-strain neo-Hookean
+    // deviatoric stress (Eq. (3_3_solid_stress))
+    const double F00 = J3 / det, F01 = -J1 / det;
+    const double F10 = -J2 / det, F11 = J0 / det;
+    const double Bxx = F00 * F00 + F01 * F01;
+    const double Bxy = F00 * F10 + F01 * F11;
+    const double Byy = F10 * F10 + F11 * F11;
+    const double tr = Bxx + Byy;
+    out[0] = lam * (b.G * (Bxx - (tr + 1.0) / 3.0));
+    out[1] = lam * (b.G * Bxy);
+    out[2] = lam * (b.G * (Byy - (tr + 1.0) / 3.0));
+}
+
+// Shared body of the force kernel (MODE 0) and the stress read (MODE 1) over
+// interior tiles of region Rg: stage xi, phi of the tile plus a one-node halo
+// in LDS, compute each half-edge once, then combine per node.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, const Win* __restrict__ win,
+                                               int wvalid, int whole_grid,
+                                               const double* __restrict__ X,
+                                               const double* __restrict__ Y,
+                                               const double* __restrict__ phi, double* o0,
+                                               double* o1, double* o2, unsigned* health)
+{
+    __shared__ double sX[SY * SX], sY[SY * SX], sP[SY * SX];
+    __shared__ double ex[FTY][FTX + 1][3];
+    __shared__ double ey[FTY + 1][FTX][3];
+    const Rect V = window_of(win, wvalid, g);
+    Rect Rg;
+    if (whole_grid) {
+        Rg.i0 = 0; Rg.i1 = g.nx - 1; Rg.j0 = 0; Rg.j1 = g.ny - 1;
+        Rg.ok = true;
+    } else {
+        Rg = V;
+        if (!Rg.ok) return;
+        Rg.i0 = max(Rg.i0, 0);
+        Rg.j0 = max(Rg.j0, 0);
+        Rg.i1 = min(Rg.i1, g.nx - 1);
+        Rg.j1 = min(Rg.j1, g.ny - 1);
+        if (Rg.i0 > Rg.i1 || Rg.j0 > Rg.j1) return;
+    }
+    const int ntx = (Rg.i1 - Rg.i0) / FTX + 1, nty = (Rg.j1 - Rg.j0) / FTY + 1;
+    const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
+    for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
+        const int i0 = Rg.i0 + (t % ntx) * FTX, j0 = Rg.j0 + (t / ntx) * FTY;
+        for (int e = threadIdx.x; e < SX * SY; e += blockDim.x) {
+            int ci = i0 - 1 + e % SX, cj = j0 - 1 + e / SX;
+            double xv = NAN, yv = NAN, pv = INFINITY;
+            if (b.present && canon(g, ci, cj) && V.has(ci, cj)) {
+                const long long k = pidx(g, ci, cj);
+                const double p = phi[k];
+                if (p < INFINITY) {
+                    xv = X[k];
+                    yv = Y[k];
+                    pv = p;
+                }
+            }
+            sX[e] = xv;
+            sY[e] = yv;
+            sP[e] = pv;
+        }
+        __syncthreads();
+        const int i = i0 + tx, j = j0 + ty;
+        const bool mine = i <= Rg.i1 && j <= Rg.j1;
+        // health counting: an edge is counted once, by the node on its far
+        // side, or by its near node when the far node lies outside the region
+        const bool rowin = j <= Rg.j1, colin = i <= Rg.i1;
+        const bool cnt_l = MODE == 0 && (mine || (rowin && i == Rg.i1 + 1));
+        const bool cnt_b = MODE == 0 && (mine || (colin && j == Rg.j1 + 1));
+        // local index of node (i + di, j + dj)
+#define LI(di, dj) ((ty + 1 + (dj)) * SX + (tx + 1 + (di)))
+        // x-edge (i - 1/2, j): a = (i-1, j), b = (i, j); side (i, j+1), (i-1, j+1), (i, j-1), (i-1, j-1)
+        edge_tau(g, b, sX, sY, sP, LI(-1, 0), LI(0, 0), LI(0, 1), LI(-1, 1), LI(0, -1), LI(-1, -1),
+                 0, cnt_l, health, ex[ty][tx]);
+        // y-edge (i, j - 1/2): a = (i, j-1), b = (i, j); side (i+1, j), (i+1, j-1), (i-1, j), (i-1, j-1)
+        edge_tau(g, b, sX, sY, sP, LI(0, -1), LI(0, 0), LI(1, 0), LI(1, -1), LI(-1, 0), LI(-1, -1),
+                 1, cnt_b, health, ey[ty][tx]);
+        if (tx == FTX - 1) {
+            // right x-edge (i + 1/2, j) of the last tile column
+            edge_tau(g, b, sX, sY, sP, LI(0, 0), LI(1, 0), LI(1, 1), LI(0, 1), LI(1, -1), LI(0, -1),
+                     0, MODE == 0 && mine && i == Rg.i1, health, ex[ty][tx + 1]);
+        }
+        if (ty == FTY - 1) {
+            // top y-edge (i, j + 1/2) of the last tile row
+            edge_tau(g, b, sX, sY, sP, LI(0, 0), LI(0, 1), LI(1, 1), LI(1, 0), LI(-1, 1), LI(-1, 0),
+                     1, MODE == 0 && mine && j == Rg.j1, health, ey[ty + 1][tx]);
+        }
+#undef LI
+        __syncthreads();
+        if (mine) {
+            const double* L = ex[ty][tx];
+            const double* Rr = ex[ty][tx + 1];
+            const double* B = ey[ty][tx];
+            const double* T = ey[ty + 1][tx];
+            const long long n = (long long)j * g.pitch + i;
+            if (MODE == 0) {
+                // Eq. (3_3_div_solid_stress) in Eq. (2_4_F_divs)
+                double fx = (Rr[0] - L[0]) + (T[1] - B[1]);
+                double fy = (Rr[1] - L[1]) + (T[2] - B[2]);
+                const double p = sP[(ty + 1) * SX + tx + 1];
+                double H = 1.0, dr = 0.0;
+                if (b.present && p < INFINITY) {
+                    H = heaviside(p, g.eps);
+                    fx += (1.0 - H) * (b.rho_s - g.rho_f) * g.gx;
+                    fy += (1.0 - H) * (b.rho_s - g.rho_f) * g.gy;
+                    dr = (1.0 - H) * (b.rho_s - g.rho_f);  // Eq. (2_3_drho)
+                }
+                fx += H * g.fext_x;
+                fy += H * g.fext_y;
+                o0[n] = fx;
+                o1[n] = fy;
+                o2[n] = dr;
+            } else {
+                const long long e = (long long)j * g.nx + i;
+                o0[e] = (L[0] + Rr[0] + B[0] + T[0]) / 4.0;
+                o1[e] = (L[1] + Rr[1] + B[1] + T[1]) / 4.0;
+                o2[e] = (L[2] + Rr[2] + B[2] + T[2]) / 4.0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
+                        double* fx, double* fy, double* drho, hipStream_t st)
+{
+    k_edges<0><<<2048, 256, 0, st>>>(g, b, bb.win, s.wcur, 0, bb.X[s.nxt], bb.Y[s.nxt],
+                                     bb.phi[s.nxt], fx, fy, drho, bb.health);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
+                              int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st)
+{
+    k_edges<1><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 1, bb.X[buf], bb.Y[buf], bb.phi[buf],
+                                     sxx, sxy, syy, bb.health);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reads
+
+__global__ void k_read_refmap(GridP g, const Win* __restrict__ win, int wvalid,
+                              const double* __restrict__ X, const double* __restrict__ Y,
+                              const double* __restrict__ phi, double* Xo, double* Yo,
+                              double* Po)
+{
+    const Rect V = window_of(win, wvalid, g);
+    const long long N = (long long)g.nx * g.ny;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        double xv = NAN, yv = NAN, pv = NAN;
+        if (V.has(i, j)) {
+            const long long k = pidx(g, i, j);
+            if (phi[k] < INFINITY) {
+                xv = X[k];
+                yv = Y[k];
+                pv = phi[k];
+            }
+        }
+        if (Xo) Xo[e] = xv;
+        if (Yo) Yo[e] = yv;
+        if (Po) Po[e] = pv;
+    }
+}
+
+hipError_t launch_read_refmap(const GridP& g, const BandBufs& bb, int buf, int wvalid, double* X,
+                              double* Y, double* phi, hipStream_t st)
+{
+    k_read_refmap<<<2048, 256, 0, st>>>(g, bb.win, wvalid, bb.X[buf], bb.Y[buf], bb.phi[buf], X,
+                                        Y, phi);
+    return hipGetLastError();
+}
+
+}  // namespace lbrmt

@@ -1,0 +1,452 @@
+// Lattice Boltzmann kernels of the LBRMT step on gfx950.
+//
+// Storage: nine structure-of-arrays planes per lattice, row pitch `pitch`, two
+// lattices A/B.  A holds the post-collision populations of the previous step
+// (a "pull" scheme): a node gathers f_i(x) = fhat_i(x - c_i) from its
+// neighbours, or, when x - c_i is a wall, the reflected fhat_opp(i)(x) of its
+// own node (halfway bounce-back, Sec. 3.5).  The moving-lid term of the
+// reflected population is folded into the stored value when the top-row node
+// writes it, using that node's density, so the gather is a plain copy.
+//
+// One thread per node; a workgroup covers a TX x TY tile.  Workgroup ids are
+// remapped so that each XCD (8 on MI355X, round-robin dispatch) walks one
+// contiguous slab of tiles and keeps the shared tile-edge cache lines in its
+// own L2.
+//
+// FP64 path: f stored and computed in double.  FP32 path: the deviation
+// f_i - w_i rho_f is stored in float and the arithmetic is float, so rho =
+// rho_f + sum(df) keeps its small part.
+#include "lbrmt_internal.h"
+
+namespace lbrmt {
+
+template <typename S>
+struct Prec;
+template <>
+struct Prec<double> {
+    using C = double;
+    static constexpr bool dev = false;
+};
+template <>
+struct Prec<float> {
+    using C = float;
+    static constexpr bool dev = true;
+};
+
+// D2Q9 weights (Table "d2q9")
+#define W0 (4.0 / 9.0)
+#define W1 (1.0 / 9.0)
+#define W2 (1.0 / 36.0)
+
+struct Neigh {
+    long long n, rm, r0, rp;  // node index and row offsets of j-1, j, j+1
+    int im, ip, i;
+    bool bw, be, bs, bn;      // wall beyond the west/east/south/north side
+};
+
+__device__ __forceinline__ Neigh neigh(const GridP& g, int i, int j)
+{
+    Neigh q;
+    q.i = i;
+    q.bw = !g.px && i == 0;
+    q.be = !g.px && i == g.nx - 1;
+    q.bs = !g.py && j == 0;
+    q.bn = !g.py && j == g.ny - 1;
+    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
+    // periodic axes wrap; on walled axes the clamped index is never used for
+    // data (the reflected population is taken instead) but keeps every
+    // address inside the plane
+    im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
+    ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
+    jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
+    jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
+    q.im = im;
+    q.ip = ip;
+    q.r0 = (long long)j * g.pitch;
+    q.rm = (long long)jm * g.pitch;
+    q.rp = (long long)jp * g.pitch;
+    q.n = q.r0 + i;
+    return q;
+}
+
+// gather the nine pre-collision populations f_i^n of one node (stored form)
+template <typename S>
+__device__ __forceinline__ void gather(const GridP& g, const Neigh& q, const S* __restrict__ A,
+                                       typename Prec<S>::C f[NQ])
+{
+    const long long P = g.plane;
+    const long long n = q.n;
+    f[0] = A[n];
+    f[1] = q.bw ? A[3 * P + n] : A[1 * P + q.r0 + q.im];
+    f[2] = q.bs ? A[4 * P + n] : A[2 * P + q.rm + q.i];
+    f[3] = q.be ? A[1 * P + n] : A[3 * P + q.r0 + q.ip];
+    f[4] = q.bn ? A[2 * P + n] : A[4 * P + q.rp + q.i];
+    f[5] = (q.bw || q.bs) ? A[7 * P + n] : A[5 * P + q.rm + q.im];
+    f[6] = (q.be || q.bs) ? A[8 * P + n] : A[6 * P + q.rm + q.ip];
+    f[7] = (q.be || q.bn) ? A[5 * P + n] : A[7 * P + q.rp + q.ip];
+    f[8] = (q.bw || q.bn) ? A[6 * P + n] : A[8 * P + q.rp + q.im];
+}
+
+// density and momentum sum_i c_i f_i from the stored form
+template <typename C, bool DEV>
+__device__ __forceinline__ void moments(const C f[NQ], C rho_f, C& rho, C& drho_n, C& jx, C& jy)
+{
+    C s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    if (DEV) {
+        drho_n = s;
+        rho = rho_f + s;
+    } else {
+        rho = s;
+        drho_n = s - rho_f;
+    }
+    jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
+    jy = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
+}
+
+// Collision of Sec. 3.4: SFC equilibrium (Eq. (2_3_feq_sfc)), BGK relaxation,
+// Guo forcing (Eq. (2_2_Fi), force per unit volume).  f holds the stored form
+// (f or f - w rho_f); the same form is returned.
+template <typename C, bool DEV>
+__device__ __forceinline__ void collide(C f[NQ], C rho, C drho_n, C ux, C uy, C Fx, C Fy,
+                                        C dr_sfc, C omega, C cf)
+{
+    const C usq = ux * ux + uy * uy;
+    const C uF = ux * Fx + uy * Fy;
+    const C base = DEV ? drho_n : rho;  // rho term of w_i rho (1 + ...) in stored form
+    const C r15 = C(1.5) * rho * usq;
+    // q = 0
+    {
+        C feq = C(W0) * (base - r15) + C(5.0 / 9.0) * dr_sfc;
+        C Fi = C(W0) * (C(-3.0) * uF);
+        f[0] = f[0] + omega * (feq - f[0]) + cf * Fi;
+    }
+#define LB_DIR(Q, WQ, CU, CF)                                                          \
+    {                                                                                  \
+        const C cu = (CU), cF = (CF);                                                  \
+        C feq = C(WQ) * (base + rho * (C(3.0) * cu + C(4.5) * cu * cu) - r15 - dr_sfc); \
+        C Fi = C(WQ) * (C(3.0) * (cF - uF) + C(9.0) * cu * cF);                        \
+        f[Q] = f[Q] + omega * (feq - f[Q]) + cf * Fi;                                  \
+    }
+    LB_DIR(1, W1, ux, Fx)
+    LB_DIR(2, W1, uy, Fy)
+    LB_DIR(3, W1, -ux, -Fx)
+    LB_DIR(4, W1, -uy, -Fy)
+    LB_DIR(5, W2, ux + uy, Fx + Fy)
+    LB_DIR(6, W2, uy - ux, Fy - Fx)
+    LB_DIR(7, W2, -ux - uy, -Fx - Fy)
+    LB_DIR(8, W2, ux - uy, Fx - Fy)
+#undef LB_DIR
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int per = nb / 8, rem = nb % 8;
+    const int x = b % 8, k = b / 8;
+    return x * per + min(x, rem) + k;
+}
+
+// Band region of a step: every interior node where the force of this step or
+// of the previous one may differ from the uniform fluid force.
+__device__ __forceinline__ Rect band_region(const GridP& g, const Rect& a, const Rect& b)
+{
+    Rect u;
+    u.ok = a.ok || b.ok;
+    if (!u.ok) return u;
+    u.i0 = min(a.ok ? a.i0 : b.i0, b.ok ? b.i0 : a.i0);
+    u.i1 = max(a.ok ? a.i1 : b.i1, b.ok ? b.i1 : a.i1);
+    u.j0 = min(a.ok ? a.j0 : b.j0, b.ok ? b.j0 : a.j0);
+    u.j1 = max(a.ok ? a.j1 : b.j1, b.ok ? b.j1 : a.j1);
+    u.i0 = max(u.i0, 0);
+    u.j0 = max(u.j0, 0);
+    u.i1 = min(u.i1, g.nx - 1);
+    u.j1 = min(u.j1, g.ny - 1);
+    u.ok = u.i0 <= u.i1 && u.j0 <= u.j1;
+    return u;
+}
+
+// PART 0: every tile, per-node window tests.  PART 1: tiles outside the band
+// region only (uniform force).  PART 2: tiles of the band region only,
+// grid-stride.
+template <typename S, int PART>
+__global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
+    GridP g, const S* __restrict__ A, S* __restrict__ B, const double* __restrict__ fpx,
+    const double* __restrict__ fpy, const double* __restrict__ fcx, const double* __restrict__ fcy,
+    const double* __restrict__ drho, const Win* __restrict__ win, int wprev, int wcur,
+    double fpo_x, double fpo_y, unsigned* __restrict__ health)
+{
+    using C = typename Prec<S>::C;
+    constexpr bool DEV = Prec<S>::dev;
+    const int ntx = (g.nx + LB_TX - 1) / LB_TX;
+    const int nty = (g.ny + LB_TY - 1) / LB_TY;
+    const Rect wp = window_of(win, wprev, g);
+    const Rect wc = window_of(win, wcur, g);
+    const Rect U = band_region(g, wp, wc);
+    const int tx = threadIdx.x % LB_TX, ty = threadIdx.x / LB_TX;
+
+    int t_begin, t_step, t_end;
+    int utx0 = 0, uty0 = 0, untx = 1;
+    if (PART == 2) {
+        if (!U.ok) return;
+        utx0 = U.i0 / LB_TX;
+        uty0 = U.j0 / LB_TY;
+        untx = U.i1 / LB_TX - utx0 + 1;
+        const int unty = U.j1 / LB_TY - uty0 + 1;
+        t_begin = blockIdx.x;
+        t_step = gridDim.x;
+        t_end = untx * unty;
+    } else {
+        t_begin = xcd_remap(blockIdx.x, gridDim.x);
+        t_step = 1 << 30;
+        t_end = ntx * nty;
+    }
+    for (int t = t_begin; t < t_end; t += t_step) {
+        int tile_x, tile_y;
+        if (PART == 2) {
+            tile_x = utx0 + t % untx;
+            tile_y = uty0 + t / untx;
+        } else {
+            tile_x = t % ntx;
+            tile_y = t / ntx;
+            if (PART == 1 && U.ok) {
+                const int x0 = tile_x * LB_TX, y0 = tile_y * LB_TY;
+                if (x0 <= U.i1 && x0 + LB_TX - 1 >= U.i0 && y0 <= U.j1 && y0 + LB_TY - 1 >= U.j0)
+                    continue;
+            }
+        }
+        const int i = tile_x * LB_TX + tx, j = tile_y * LB_TY + ty;
+        if (i >= g.nx || j >= g.ny) continue;
+        const Neigh q = neigh(g, i, j);
+        C f[NQ];
+        gather<S>(g, q, A, f);
+        C rho, dn, jx, jy;
+        moments<C, DEV>(f, C(g.rho_f), rho, dn, jx, jy);
+        C Fpx = C(fpo_x), Fpy = C(fpo_y);
+        C Fx = C(g.fext_x), Fy = C(g.fext_y), dr = C(0);
+        if (PART != 1) {
+            if (wp.has(i, j)) {
+                Fpx = C(fpx[q.n]);
+                Fpy = C(fpy[q.n]);
+            }
+            if (wc.has(i, j)) {
+                Fx = C(fcx[q.n]);
+                Fy = C(fcy[q.n]);
+                dr = C(drho[q.n]);
+            }
+        }
+        const C inv = C(1) / rho;
+        const C ux = (jx + C(0.5) * Fpx) * inv;
+        const C uy = (jy + C(0.5) * Fpy) * inv;
+        collide<C, DEV>(f, rho, dn, ux, uy, Fx, Fy, dr, C(g.omega), C(g.cforce));
+        if (q.bn) {
+            // lid: the populations 5 and 6 leave through the moving top wall;
+            // store them already reflected-with-momentum, -2 w rho (c.u_w)/cs^2
+            const C m = rho * C(g.lid_ux) * C(1.0 / 6.0);
+            f[5] -= m;
+            f[6] += m;
+        }
+        if (!(rho > C(0) && rho < C(1e30))) atomicAdd(&health[5], 1u);
+        const long long P = g.plane;
+#pragma unroll
+        for (int k = 0; k < NQ; k++) B[k * P + q.n] = S(f[k]);
+    }
+}
+
+hipError_t launch_lb(const GridP& g, int precision, const void* A, void* B, const double* fpx,
+                     const double* fpy, const double* fcx, const double* fcy, const double* drho,
+                     const Win* win, int wprev, int wcur, double fpo_x, double fpo_y, int part,
+                     unsigned* health, hipStream_t st)
+{
+    const int ntiles = ((g.nx + LB_TX - 1) / LB_TX) * ((g.ny + LB_TY - 1) / LB_TY);
+    const dim3 blk(LB_TX * LB_TY);
+    const dim3 grd(part == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles);
+#define LB_LAUNCH(S, PARTV)                                                                    \
+    k_lb<S, PARTV><<<grd, blk, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx, fcy, drho, win, \
+                                        wprev, wcur, fpo_x, fpo_y, health)
+    if (precision == 0) {
+        if (part == 0) LB_LAUNCH(double, 0);
+        else if (part == 1) LB_LAUNCH(double, 1);
+        else LB_LAUNCH(double, 2);
+    } else {
+        if (part == 0) LB_LAUNCH(float, 0);
+        else if (part == 1) LB_LAUNCH(float, 1);
+        else LB_LAUNCH(float, 2);
+    }
+#undef LB_LAUNCH
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- initialisation
+
+// f^0 = f^eq_SFC(rho_0, v_0, drho_0) in natural (pre-collision) layout
+template <typename S>
+__global__ void k_init_feq(GridP g, BodyP b, const double* __restrict__ phi0,
+                           const Win* __restrict__ win, int wslot, const double* __restrict__ u0,
+                           S* __restrict__ T)
+{
+    const long long N = (long long)g.nx * g.ny;
+    const Rect w = window_of(win, wslot, g);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        double H = 1.0;
+        if (b.present && w.has(i, j)) {
+            const double ph = phi0[pidx(g, i, j)];
+            if (ph < INFINITY) {
+                // smoothed Heaviside, Eq. (2_3_heaviside)
+                if (ph <= -g.eps) H = 0.0;
+                else if (ph >= g.eps) H = 1.0;
+                else H = 0.5 * (1.0 + ph / g.eps + sin(M_PI * ph / g.eps) / M_PI);
+            }
+        }
+        const double rs = b.present ? b.rho_s : g.rho_f;
+        const double rho = H * g.rho_f + (1.0 - H) * rs;  // Eq. (2_4_smooth_density)
+        const double dr = rho - g.rho_f;                 // Eq. (2_3_drho) with rho = rho_t
+        const double ux = u0 ? u0[e] : 0.0, uy = u0 ? u0[N + e] : 0.0;
+        const double usq = ux * ux + uy * uy;
+        const long long n = (long long)j * g.pitch + i;
+        const double cu[NQ] = {0.0, ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
+        const double wq[NQ] = {W0, W1, W1, W1, W1, W2, W2, W2, W2};
+        for (int k = 0; k < NQ; k++) {
+            double fe = wq[k] * rho * (1.0 + 3.0 * cu[k] + 4.5 * cu[k] * cu[k] - 1.5 * usq);
+            fe += k == 0 ? (5.0 / 9.0) * dr : -wq[k] * dr;
+            if (Prec<S>::dev) fe -= wq[k] * g.rho_f;
+            T[k * g.plane + n] = S(fe);
+        }
+    }
+}
+
+// A such that the pull gather of A reproduces T: A_i(y) = T_i(y + c_i), or
+// T_opp(i)(y) where y + c_i lies beyond a wall.
+template <typename S>
+__global__ void k_inverse_stream(GridP g, const S* __restrict__ T, S* __restrict__ A)
+{
+    const int CXv[NQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int CYv[NQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int OPP[NQ] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const long long N = (long long)g.nx * g.ny;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        const long long n = (long long)j * g.pitch + i;
+        for (int k = 0; k < NQ; k++) {
+            int id = i + CXv[k], jd = j + CYv[k];
+            if (g.px) id = wrap_axis(id, g.nx);
+            if (g.py) jd = wrap_axis(jd, g.ny);
+            const bool inside = id >= 0 && id < g.nx && jd >= 0 && jd < g.ny;
+            A[k * g.plane + n] = inside ? T[k * g.plane + (long long)jd * g.pitch + id]
+                                        : T[OPP[k] * g.plane + n];
+        }
+    }
+}
+
+hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
+                                   const double* phi0, const Win* win, int wslot,
+                                   const double* u0, void* tmp, void* A, hipStream_t st)
+{
+    const long long N = (long long)g.nx * g.ny;
+    const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
+    if (precision == 0) {
+        k_init_feq<double><<<blocks, 256, 0, st>>>(g, b, phi0, win, wslot, u0, (double*)tmp);
+        k_inverse_stream<double><<<blocks, 256, 0, st>>>(g, (const double*)tmp, (double*)A);
+    } else {
+        k_init_feq<float><<<blocks, 256, 0, st>>>(g, b, phi0, win, wslot, u0, (float*)tmp);
+        k_inverse_stream<float><<<blocks, 256, 0, st>>>(g, (const float*)tmp, (float*)A);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reads
+
+template <typename S>
+__global__ void k_gather_macro(GridP g, const S* __restrict__ A, const double* __restrict__ fpx,
+                               const double* __restrict__ fpy, const Win* __restrict__ win,
+                               int wprev, double fpo_x, double fpo_y, double* rho_o,
+                               double* ux_o, double* uy_o, double* f9)
+{
+    const long long N = (long long)g.nx * g.ny;
+    const Rect wp = window_of(win, wprev, g);
+    const double wq[NQ] = {W0, W1, W1, W1, W1, W2, W2, W2, W2};
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        const Neigh q = neigh(g, i, j);
+        double f[NQ];
+        {
+            typename Prec<S>::C fs[NQ];
+            gather<S>(g, q, A, fs);
+            for (int k = 0; k < NQ; k++)
+                f[k] = Prec<S>::dev ? (double)fs[k] + wq[k] * g.rho_f : (double)fs[k];
+        }
+        const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        double Fx = fpo_x, Fy = fpo_y;
+        if (wp.has(i, j)) {
+            Fx = fpx[q.n];
+            Fy = fpy[q.n];
+        }
+        if (rho_o) rho_o[e] = rho;
+        if (ux_o) ux_o[e] = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (2.0 * rho);
+        if (uy_o) uy_o[e] = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (2.0 * rho);
+        if (f9)
+            for (int k = 0; k < NQ; k++) f9[k * N + e] = f[k];
+    }
+}
+
+hipError_t launch_gather_macro(const GridP& g, int precision, const void* A, const double* fpx,
+                               const double* fpy, const Win* win, int wprev, double fpo_x,
+                               double fpo_y, double* rho, double* ux, double* uy, double* f9,
+                               hipStream_t st)
+{
+    const long long N = (long long)g.nx * g.ny;
+    const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
+    if (precision == 0)
+        k_gather_macro<double><<<blocks, 256, 0, st>>>(g, (const double*)A, fpx, fpy, win, wprev,
+                                                       fpo_x, fpo_y, rho, ux, uy, f9);
+    else
+        k_gather_macro<float><<<blocks, 256, 0, st>>>(g, (const float*)A, fpx, fpy, win, wprev,
+                                                      fpo_x, fpo_y, rho, ux, uy, f9);
+    return hipGetLastError();
+}
+
+__global__ void k_read_force(GridP g, const double* __restrict__ fpx, const double* __restrict__ fpy,
+                             const Win* __restrict__ win, int wprev, double fpo_x, double fpo_y,
+                             double* fx, double* fy)
+{
+    const long long N = (long long)g.nx * g.ny;
+    const Rect wp = window_of(win, wprev, g);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        const long long n = (long long)j * g.pitch + i;
+        const bool in = wp.has(i, j);
+        fx[e] = in ? fpx[n] : fpo_x;
+        fy[e] = in ? fpy[n] : fpo_y;
+    }
+}
+
+hipError_t launch_read_force(const GridP& g, const double* fpx, const double* fpy, const Win* win,
+                             int wprev, double fpo_x, double fpo_y, double* fx, double* fy,
+                             hipStream_t st)
+{
+    const long long N = (long long)g.nx * g.ny;
+    const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
+    k_read_force<<<blocks, 256, 0, st>>>(g, fpx, fpy, win, wprev, fpo_x, fpo_y, fx, fy);
+    return hipGetLastError();
+}
+
+template <typename S>
+__global__ void k_poke(GridP g, S* A, long long node, double value)
+{
+    const int i = (int)(node % g.nx), j = (int)(node / g.nx);
+    const long long n = (long long)j * g.pitch + i;
+    if (threadIdx.x < NQ) A[threadIdx.x * g.plane + n] = S(value);
+}
+
+hipError_t launch_poke(const GridP& g, int precision, void* A, long long node, double value,
+                       hipStream_t st)
+{
+    if (precision == 0) k_poke<double><<<1, 64, 0, st>>>(g, (double*)A, node, value);
+    else k_poke<float><<<1, 64, 0, st>>>(g, (float*)A, node, value);
+    return hipGetLastError();
+}
+
+}  // namespace lbrmt

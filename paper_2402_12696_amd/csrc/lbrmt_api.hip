@@ -1,0 +1,737 @@
+// Host side of the gfx950 LBRMT library: the C ABI of include/lbrmt.h.
+//
+// One step (Alg. 1) is a fixed launch sequence.  The reference-map chain
+// (advect, 11 extrapolation layers, relabel, force) runs on an internal side
+// stream while the lattice Boltzmann update of every tile outside the band
+// region runs on the caller's stream; the band tiles are updated after the
+// chain has produced this step's force.  Buffer parities repeat every 6 steps
+// (lattice / xi / force double buffers, 3-slot window ring), so 6 steps are
+// captured once into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lbrmt.h"
+#include "lbrmt_internal.h"
+
+using namespace lbrmt;
+
+namespace {
+
+constexpr int GRAPH_STEPS = 6;
+constexpr size_t ALIGN = 256;
+constexpr uint32_t STATE_MAGIC = 0x4c42524d;  // "LBRM"
+constexpr uint32_t STATE_VERSION = 1;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    int pitch, pp;
+    size_t plane, pplane;
+    size_t off_lat[2], off_fx[2], off_fy[2], off_drho, off_X[2], off_Y[2], off_phi[2], off_tag,
+        off_win, off_health, off_dpart, off_dout, total;
+    size_t lat_bytes;
+};
+
+Layout make_layout(const lbrmt_grid_desc* d)
+{
+    Layout L;
+    L.pitch = (int)round_up((size_t)d->nx, 64);
+    L.pp = (int)round_up((size_t)d->nx + 2 * PAD, 32);
+    L.plane = (size_t)L.pitch * d->ny;
+    L.pplane = (size_t)L.pp * (d->ny + 2 * PAD);
+    const size_t s = d->precision == LBRMT_FP32 ? 4 : 8;
+    L.lat_bytes = NQ * L.plane * s;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = round_up(o + bytes, ALIGN);
+        return r;
+    };
+    for (int k = 0; k < 2; k++) L.off_lat[k] = take(L.lat_bytes);
+    for (int k = 0; k < 2; k++) {
+        L.off_fx[k] = take(L.plane * 8);
+        L.off_fy[k] = take(L.plane * 8);
+    }
+    L.off_drho = take(L.plane * 8);
+    for (int k = 0; k < 2; k++) {
+        L.off_X[k] = take(L.pplane * 8);
+        L.off_Y[k] = take(L.pplane * 8);
+        L.off_phi[k] = take(L.pplane * 8);
+    }
+    L.off_tag = take(L.pplane);
+    L.off_win = take(3 * sizeof(Win));
+    L.off_health = take(LBRMT_H_COUNT * sizeof(unsigned));
+    L.off_dpart = take(diag_partial_doubles() * 8);
+    L.off_dout = take(16 * 8);
+    L.total = o;
+    return L;
+}
+
+const char* kernel_names[] = {"advect", "extrap", "relabel", "force", "lb_bulk", "lb_band"};
+constexpr int NKERN = 6;
+
+}  // namespace
+
+struct lbrmt_ctx {
+    lbrmt_grid_desc d;
+    Layout L;
+    GridP g;
+    BodyP body;
+    int max_solids = 0, nsolid = 0;
+    lbrmt_solid_desc solid{};
+    hipStream_t st = nullptr;
+    hipStream_t side = nullptr;
+    hipStream_t cap = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    char* ws = nullptr;
+    void* lat[2];
+    double *Fx[2], *Fy[2], *drho;
+    BandBufs bb;
+    double *dpart, *dout;
+    long long step = 0;
+    bool inited = false;
+    bool overlap = true;
+    hipGraphExec_t gexec = nullptr;
+    bool timing = false;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double t_ms[NKERN] = {0};
+    long long t_n[NKERN] = {0};
+    std::string err;
+};
+
+static int fail(lbrmt_ctx* c, const char* what, hipError_t e)
+{
+    if (c) {
+        char buf[512];
+        snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+        c->err = buf;
+    }
+    return LBRMT_EHIP;
+}
+
+#define HIPCHK(c, expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return fail((c), #expr, e_); \
+    } while (0)
+
+static hipEvent_t pool_get(lbrmt_ctx* c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// timing brackets (eager launches only)
+struct Bracket {
+    lbrmt_ctx* c;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Bracket(lbrmt_ctx* c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_)
+    {
+        if (c->timing) {
+            a = pool_get(c);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    void done()
+    {
+        if (c->timing && a) {
+            hipEvent_t b = pool_get(c);
+            if (b) {
+                (void)hipEventRecord(b, s);
+                c->pending.push_back({kind, a, b});
+            }
+        }
+    }
+};
+
+static int collect_timing(lbrmt_ctx* c)
+{
+    if (c->pending.empty()) return LBRMT_OK;
+    for (auto& p : c->pending) {
+        HIPCHK(c, hipEventSynchronize(p.b));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
+        c->t_ms[p.kind] += ms;
+        c->t_n[p.kind] += 1;
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+    return LBRMT_OK;
+}
+
+static double fpo_x(const lbrmt_ctx* c, long long n) { return n == 0 ? 0.0 : c->d.fext_x; }
+static double fpo_y(const lbrmt_ctx* c, long long n) { return n == 0 ? 0.0 : c->d.fext_y; }
+
+// enqueue step n: band chain on `band`, LB on `main_s`
+static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
+{
+    const StepSlots s = slots_for(n);
+    const GridP& g = c->g;
+    const int prec = c->d.precision;
+    const double ox = fpo_x(c, n), oy = fpo_y(c, n);
+    if (c->nsolid > 0) {
+        hipStream_t band = main_s;
+        if (c->overlap) {
+            HIPCHK(c, hipEventRecord(c->ev_fork, main_s));
+            HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+            band = c->side;
+        }
+        {
+            Bracket b(c, 0, band);
+            HIPCHK(c, launch_advect(g, prec, c->body, c->bb, s, c->lat[s.cur], c->Fx[s.nxt],
+                                    c->Fy[s.nxt], ox, oy, band));
+            b.done();
+        }
+        {
+            Bracket b(c, 1, band);
+            for (int l = 1; l <= g.layers; l++)
+                HIPCHK(c, launch_layer_pass(g, c->bb, s.wcur, s.wprev, l, 0, c->bb.phi[s.cur],
+                                            c->bb.X[s.nxt], c->bb.Y[s.nxt], band));
+            b.done();
+        }
+        {
+            Bracket b(c, 2, band);
+            HIPCHK(c, launch_relabel(g, c->body, c->bb, s, band));
+            b.done();
+        }
+        {
+            Bracket b(c, 3, band);
+            HIPCHK(c, launch_force(g, c->body, c->bb, s, c->Fx[s.cur], c->Fy[s.cur], c->drho,
+                                   band));
+            b.done();
+        }
+        if (c->overlap) {
+            HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+            {
+                Bracket b(c, 4, main_s);
+                HIPCHK(c, launch_lb(g, prec, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
+                                    c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
+                                    s.wprev, s.wcur, ox, oy, 1, c->bb.health, main_s));
+                b.done();
+            }
+            HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
+            {
+                Bracket b(c, 5, main_s);
+                HIPCHK(c, launch_lb(g, prec, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
+                                    c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
+                                    s.wprev, s.wcur, ox, oy, 2, c->bb.health, main_s));
+                b.done();
+            }
+            return LBRMT_OK;
+        }
+    }
+    Bracket b(c, 4, main_s);
+    HIPCHK(c, launch_lb(g, prec, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt],
+                        c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win, s.wprev, s.wcur, ox, oy, 0,
+                        c->bb.health, main_s));
+    b.done();
+    return LBRMT_OK;
+}
+
+static int build_graph(lbrmt_ctx* c)
+{
+    // steps n0 .. n0+5 with n0 = 0 mod 6 and n0 >= 6 have identical launches
+    hipGraph_t graph = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    int rc = LBRMT_OK;
+    for (int k = 0; k < GRAPH_STEPS && rc == LBRMT_OK; k++) rc = enqueue_step(c, 6 + k, c->cap);
+    hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (rc != LBRMT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, "hipStreamEndCapture", e);
+    e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(c, "hipGraphInstantiate", e);
+    }
+    return LBRMT_OK;
+}
+
+static bool desc_ok(const lbrmt_grid_desc* d)
+{
+    return d && d->nx >= 8 && d->ny >= 8 && d->tau > 0.5 && d->layers >= 1 && d->layers <= 60 &&
+           d->r_max >= 2 && d->r_max <= 32 && d->eps > 0.0 && d->rho_f > 0.0 &&
+           (d->precision == LBRMT_FP64 || d->precision == LBRMT_FP32);
+}
+
+extern "C" {
+
+const char* lbrmt_status_string(int s)
+{
+    switch (s) {
+    case LBRMT_OK: return "ok";
+    case LBRMT_EINVAL: return "invalid argument";
+    case LBRMT_EWORKSPACE: return "workspace too small or misaligned";
+    case LBRMT_EHIP: return "HIP error";
+    case LBRMT_EUNSTABLE: return "device health counters report a failure";
+    case LBRMT_ECAPACITY: return "capacity exceeded";
+    case LBRMT_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char* lbrmt_last_error(const lbrmt_ctx* c) { return c ? c->err.c_str() : ""; }
+
+int lbrmt_workspace_bytes(const lbrmt_grid_desc* d, int32_t max_solids, size_t* bytes)
+{
+    if (!desc_ok(d) || !bytes || max_solids < 0 || max_solids > 1) return LBRMT_EINVAL;
+    *bytes = make_layout(d).total;
+    return LBRMT_OK;
+}
+
+int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t bytes,
+                 void* stream, lbrmt_ctx** out)
+{
+    if (!desc_ok(d) || !out || !ws || max_solids < 0) return LBRMT_EINVAL;
+    if (max_solids > 1) return LBRMT_ECAPACITY;
+    if ((uintptr_t)ws % ALIGN) return LBRMT_EWORKSPACE;
+    Layout L = make_layout(d);
+    if (bytes < L.total) return LBRMT_EWORKSPACE;
+    lbrmt_ctx* c = new lbrmt_ctx();
+    c->d = *d;
+    c->L = L;
+    c->max_solids = max_solids;
+    c->st = (hipStream_t)stream;
+    c->ws = (char*)ws;
+    GridP& g = c->g;
+    g.nx = d->nx;
+    g.ny = d->ny;
+    g.pitch = L.pitch;
+    g.pp = L.pp;
+    g.plane = (long long)L.plane;
+    g.pplane = (long long)L.pplane;
+    g.px = d->periodic_x ? 1 : 0;
+    g.py = d->periodic_y ? 1 : 0;
+    g.layers = d->layers;
+    g.r_max = d->r_max;
+    g.omega = 1.0 / d->tau;
+    g.cforce = 1.0 - 1.0 / (2.0 * d->tau);
+    g.lid_ux = d->periodic_y ? 0.0 : d->lid_ux;
+    g.gx = d->gx;
+    g.gy = d->gy;
+    g.fext_x = d->fext_x;
+    g.fext_y = d->fext_y;
+    g.rho_f = d->rho_f;
+    g.eps = d->eps;
+    g.det_rel = d->det_rel;
+    g.detJ_min = d->detJ_min;
+    c->body.present = 0;
+    for (int k = 0; k < 2; k++) {
+        c->lat[k] = c->ws + L.off_lat[k];
+        c->Fx[k] = (double*)(c->ws + L.off_fx[k]);
+        c->Fy[k] = (double*)(c->ws + L.off_fy[k]);
+        c->bb.X[k] = (double*)(c->ws + L.off_X[k]);
+        c->bb.Y[k] = (double*)(c->ws + L.off_Y[k]);
+        c->bb.phi[k] = (double*)(c->ws + L.off_phi[k]);
+    }
+    c->drho = (double*)(c->ws + L.off_drho);
+    c->bb.tag = (int8_t*)(c->ws + L.off_tag);
+    c->bb.win = (Win*)(c->ws + L.off_win);
+    c->bb.health = (unsigned*)(c->ws + L.off_health);
+    c->dpart = (double*)(c->ws + L.off_dpart);
+    c->dout = (double*)(c->ws + L.off_dout);
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        int rc = fail(c, "stream/event creation", e);
+        lbrmt_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LBRMT_OK;
+}
+
+void lbrmt_destroy(lbrmt_ctx* c)
+{
+    if (!c) return;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    delete c;
+}
+
+int lbrmt_add_solids(lbrmt_ctx* c, const lbrmt_solid_desc* s, int32_t n)
+{
+    if (!c || (n > 0 && !s) || n < 0) return LBRMT_EINVAL;
+    if (c->inited) return LBRMT_ESTATE;
+    if (c->nsolid + n > c->max_solids) return LBRMT_ECAPACITY;
+    for (int k = 0; k < n; k++) {
+        if (s[k].shape != 0 || !(s[k].a > 0.0) || !(s[k].rho_s > 0.0) || !(s[k].G >= 0.0))
+            return LBRMT_EINVAL;
+    }
+    if (n > 0) {
+        c->solid = s[0];
+        c->nsolid = 1;
+        c->body.present = 1;
+        c->body.cx = s[0].cx;
+        c->body.cy = s[0].cy;
+        c->body.R = s[0].a;
+        c->body.G = s[0].G;
+        c->body.rho_s = s[0].rho_s;
+    }
+    return LBRMT_OK;
+}
+
+int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
+{
+    if (!c) return LBRMT_EINVAL;
+    const GridP& g = c->g;
+    hipStream_t st = c->st;
+    HIPCHK(c, hipMemsetAsync(c->bb.health, 0, LBRMT_H_COUNT * sizeof(unsigned), st));
+    for (int k = 0; k < 2; k++) {
+        HIPCHK(c, hipMemsetAsync(c->Fx[k], 0, c->L.plane * 8, st));
+        HIPCHK(c, hipMemsetAsync(c->Fy[k], 0, c->L.plane * 8, st));
+    }
+    HIPCHK(c, hipMemsetAsync(c->drho, 0, c->L.plane * 8, st));
+    for (int k = 0; k < 3; k++) HIPCHK(c, launch_win_reset(c->bb.win, k, st));
+    if (c->nsolid > 0) {
+        // box of S^0 into the slots of "current" (0) and "previous" (2)
+        HIPCHK(c, launch_init_solid_box(g, c->body, c->bb.win, 0, 2, st));
+        HIPCHK(c, launch_init_tags(g, c->body, c->bb, 0, st));
+        for (int l = 1; l <= g.layers; l++)
+            HIPCHK(c, launch_layer_pass(g, c->bb, 0, 2, l, 1, c->bb.phi[0], c->bb.X[0],
+                                        c->bb.Y[0], st));
+        HIPCHK(c, launch_init_fill(g, c->body, c->bb, 0, st));
+    }
+    HIPCHK(c, launch_init_populations(g, c->d.precision, c->body, c->bb.phi[0], c->bb.win, 0,
+                                      d_u0, c->lat[1], c->lat[0], st));
+    c->step = 0;
+    c->inited = true;
+    return LBRMT_OK;
+}
+
+int lbrmt_step(lbrmt_ctx* c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    int64_t left = nsteps;
+    while (left > 0) {
+        const bool use_graph = !c->timing && c->step >= GRAPH_STEPS &&
+                               c->step % GRAPH_STEPS == 0 && left >= GRAPH_STEPS;
+        if (use_graph) {
+            if (!c->gexec) {
+                int rc = build_graph(c);
+                if (rc != LBRMT_OK) return rc;
+            }
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
+            c->step += GRAPH_STEPS;
+            left -= GRAPH_STEPS;
+        } else {
+            int rc = enqueue_step(c, c->step, c->st);
+            if (rc != LBRMT_OK) return rc;
+            c->step += 1;
+            left -= 1;
+        }
+    }
+    return LBRMT_OK;
+}
+
+int64_t lbrmt_step_count(const lbrmt_ctx* c) { return c ? c->step : -1; }
+
+int lbrmt_read_macro(lbrmt_ctx* c, double* rho, double* ux, double* uy)
+{
+    if (!c) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_gather_macro(c->g, c->d.precision, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt],
+                                  c->bb.win, s.wprev, fpo_x(c, c->step), fpo_y(c, c->step), rho,
+                                  ux, uy, nullptr, c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_read_populations(lbrmt_ctx* c, double* f9)
+{
+    if (!c || !f9) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_gather_macro(c->g, c->d.precision, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt],
+                                  c->bb.win, s.wprev, fpo_x(c, c->step), fpo_y(c, c->step),
+                                  nullptr, nullptr, nullptr, f9, c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_read_force(lbrmt_ctx* c, double* fx, double* fy)
+{
+    if (!c || !fx || !fy) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_read_force(c->g, c->Fx[s.nxt], c->Fy[s.nxt], c->bb.win, s.wprev,
+                                fpo_x(c, c->step), fpo_y(c, c->step), fx, fy, c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_read_refmap(lbrmt_ctx* c, int32_t solid, double* X, double* Y, double* phi)
+{
+    if (!c || solid < 0 || solid >= c->nsolid) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_read_refmap(c->g, c->bb, s.cur, s.wprev, X, Y, phi, c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_read_stress(lbrmt_ctx* c, double* sxx, double* sxy, double* syy)
+{
+    if (!c || !sxx || !sxy || !syy) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_read_stress(c->g, c->body, c->bb, s.cur, s.wprev, sxx, sxy, syy, c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
+{
+    if (!c || !out) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_diag(c->g, c->d.precision, c->body, c->lat[s.cur], c->Fx[s.nxt],
+                          c->Fy[s.nxt], c->bb.win, s.wprev, fpo_x(c, c->step), fpo_y(c, c->step),
+                          c->bb, s.cur, c->dpart, c->dout, c->st));
+    double h[16];
+    unsigned hc[LBRMT_H_COUNT];
+    HIPCHK(c, hipMemcpyAsync(h, c->dout, 11 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(hc, c->bb.health, sizeof hc, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    out->step = c->step;
+    out->mass = h[0];
+    out->mom_x = h[1];
+    out->mom_y = h[2];
+    out->centroid_x = h[3] > 0 ? h[4] / h[3] : NAN;
+    out->centroid_y = h[3] > 0 ? h[5] / h[3] : NAN;
+    out->disp_x = h[3] > 0 ? h[6] / h[3] : NAN;
+    out->disp_y = h[3] > 0 ? h[7] / h[3] : NAN;
+    out->n_solid = h[8];
+    out->n_band = h[9];
+    out->max_u = h[10];
+    for (int k = 0; k < LBRMT_H_COUNT; k++) out->health[k] = hc[k];
+    if (hc[LBRMT_H_NONFINITE] || hc[LBRMT_H_DETJ_SOLID] || hc[LBRMT_H_EXTRAP_FAIL] ||
+        !std::isfinite(h[0]))
+        return LBRMT_EUNSTABLE;
+    return LBRMT_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint
+
+struct StateHeader {
+    uint32_t magic, version;
+    int64_t step;
+    int32_t nx, ny, precision, nsolid;
+    uint64_t lat_bytes, plane_bytes, pplane_bytes;
+};
+
+static size_t state_layout(const lbrmt_ctx* c, size_t off[8])
+{
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o = round_up(o + b, ALIGN);
+        return r;
+    };
+    off[0] = take(sizeof(StateHeader));
+    off[1] = take(c->L.lat_bytes);     // lattice A
+    off[2] = take(c->L.plane * 8);     // F^{n-1} x
+    off[3] = take(c->L.plane * 8);     // F^{n-1} y
+    off[4] = take(c->L.pplane * 8);    // X
+    off[5] = take(c->L.pplane * 8);    // Y
+    off[6] = take(c->L.pplane * 8);    // phi
+    off[7] = take(3 * sizeof(Win) + LBRMT_H_COUNT * sizeof(unsigned));
+    return o;
+}
+
+int lbrmt_state_bytes(const lbrmt_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return LBRMT_EINVAL;
+    size_t off[8];
+    *bytes = state_layout(c, off);
+    return LBRMT_OK;
+}
+
+int lbrmt_save_state(lbrmt_ctx* c, void* buf)
+{
+    if (!c || !buf) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    size_t off[8];
+    state_layout(c, off);
+    char* b = (char*)buf;
+    const StepSlots s = slots_for(c->step);
+    StateHeader h{STATE_MAGIC, STATE_VERSION, c->step, c->d.nx, c->d.ny, c->d.precision,
+                  c->nsolid, c->L.lat_bytes, c->L.plane * 8, c->L.pplane * 8};
+    const hipMemcpyKind D2D = hipMemcpyDeviceToDevice;
+    HIPCHK(c, hipMemcpyAsync(b + off[1], c->lat[s.cur], c->L.lat_bytes, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[2], c->Fx[s.nxt], c->L.plane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[3], c->Fy[s.nxt], c->L.plane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[4], c->bb.X[s.cur], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[5], c->bb.Y[s.cur], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[6], c->bb.phi[s.cur], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[7], c->bb.win, 3 * sizeof(Win), D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[7] + 3 * sizeof(Win), c->bb.health,
+                             LBRMT_H_COUNT * sizeof(unsigned), D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[0], &h, sizeof h, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));  // h lives on this stack frame
+    return LBRMT_OK;
+}
+
+int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
+{
+    if (!c || !buf) return LBRMT_EINVAL;
+    size_t off[8];
+    state_layout(c, off);
+    const char* b = (const char*)buf;
+    StateHeader h;
+    HIPCHK(c, hipMemcpyAsync(&h, b + off[0], sizeof h, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (h.magic != STATE_MAGIC || h.version != STATE_VERSION || h.nx != c->d.nx ||
+        h.ny != c->d.ny || h.precision != c->d.precision || h.nsolid != c->nsolid ||
+        h.lat_bytes != c->L.lat_bytes || h.step < 0) {
+        c->err = "state blob does not match this context";
+        return LBRMT_EINVAL;
+    }
+    c->step = h.step;
+    const StepSlots s = slots_for(c->step);
+    const hipMemcpyKind D2D = hipMemcpyDeviceToDevice;
+    HIPCHK(c, hipMemcpyAsync(c->lat[s.cur], b + off[1], c->L.lat_bytes, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->Fx[s.nxt], b + off[2], c->L.plane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->Fy[s.nxt], b + off[3], c->L.plane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.X[s.cur], b + off[4], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.Y[s.cur], b + off[5], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.phi[s.cur], b + off[6], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.win, b + off[7], 3 * sizeof(Win), D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.health, b + off[7] + 3 * sizeof(Win),
+                             LBRMT_H_COUNT * sizeof(unsigned), D2D, c->st));
+    c->inited = true;
+    return LBRMT_OK;
+}
+
+int lbrmt_debug_poke(lbrmt_ctx* c, int32_t field, int64_t index, double value)
+{
+    if (!c || field != 0 || index < 0 || index >= (int64_t)c->d.nx * c->d.ny) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_poke(c->g, c->d.precision, c->lat[s.cur], index, value, c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_validate(const lbrmt_grid_desc* d, const lbrmt_solid_desc* s, int32_t n,
+                   lbrmt_validation_t* out)
+{
+    if (!d || !out || n < 0 || (n > 0 && !s)) return LBRMT_EINVAL;
+    if (!(d->tau > 0.5) || d->nx < 8 || d->ny < 8) return LBRMT_EINVAL;
+    memset(out, 0, sizeof *out);
+    // App. A: nu = c_s^2 (tau - 1/2), Ma* = U* / c_s*
+    out->nu = (d->tau - 0.5) / 3.0;
+    const double U = std::fabs(d->periodic_y ? 0.0 : d->lid_ux);
+    out->mach_lb = U / std::sqrt(1.0 / 3.0);
+    out->reynolds = out->nu > 0 ? U * d->nx / out->nu : 0.0;
+    out->tau_ok = d->tau > 0.5 && d->tau <= 1.0;
+    out->mach_ok = out->mach_lb <= 0.3;
+    out->solids_inside = 1;
+    for (int k = 0; k < n; k++) {
+        if (s[k].shape != 0 || !(s[k].a > 0.0)) return LBRMT_EINVAL;
+        const double m = s[k].a + d->layers;
+        if (!d->periodic_x && (s[k].cx - m < -2 || s[k].cx + m > d->nx + 2)) out->solids_inside = 0;
+        if (!d->periodic_y && (s[k].cy - m < -2 || s[k].cy + m > d->ny + 2)) out->solids_inside = 0;
+        if (d->periodic_x && (s[k].cx - m < 0 || s[k].cx + m > d->nx)) out->solids_inside = 0;
+        if (d->periodic_y && (s[k].cy - m < 0 || s[k].cy + m > d->ny)) out->solids_inside = 0;
+    }
+    return LBRMT_OK;
+}
+
+int lbrmt_set_timing(lbrmt_ctx* c, int32_t enable)
+{
+    if (!c) return LBRMT_EINVAL;
+    int rc = collect_timing(c);
+    if (rc != LBRMT_OK) return rc;
+    c->timing = enable != 0;
+    for (int k = 0; k < NKERN; k++) {
+        c->t_ms[k] = 0.0;
+        c->t_n[k] = 0;
+    }
+    return LBRMT_OK;
+}
+
+int lbrmt_kernel_time(lbrmt_ctx* c, const char* name, double* avg_ms, int64_t* launches)
+{
+    if (!c || !name || !avg_ms || !launches) return LBRMT_EINVAL;
+    int rc = collect_timing(c);
+    if (rc != LBRMT_OK) return rc;
+    for (int k = 0; k < NKERN; k++)
+        if (!strcmp(name, kernel_names[k])) {
+            *launches = c->t_n[k];
+            *avg_ms = c->t_n[k] ? c->t_ms[k] / c->t_n[k] : 0.0;
+            return LBRMT_OK;
+        }
+    return LBRMT_EINVAL;
+}
+
+int lbrmt_band_nodes(lbrmt_ctx* c, int64_t* band_nodes, int64_t* window_nodes)
+{
+    if (!c || !band_nodes || !window_nodes) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    Win w[3];
+    HIPCHK(c, hipMemcpyAsync(w, c->bb.win, sizeof w, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    const StepSlots s = slots_for(c->step);
+    auto dil = [&](const Win& b, int& i0, int& i1, int& j0, int& j1) {
+        if (b.i0 > b.i1) return false;
+        const int L = c->g.layers;
+        i0 = std::max(b.i0 - L, 0);
+        i1 = std::min(b.i1 + L, c->g.nx - 1);
+        j0 = std::max(b.j0 - L, 0);
+        j1 = std::min(b.j1 + L, c->g.ny - 1);
+        return i0 <= i1 && j0 <= j1;
+    };
+    int a0, a1, a2, a3, b0, b1, b2, b3;
+    const bool pa = dil(w[s.wprev], a0, a1, a2, a3), pb = dil(w[s.wcur], b0, b1, b2, b3);
+    *window_nodes = pb ? (int64_t)(b1 - b0 + 1) * (b3 - b2 + 1) : 0;
+    if (!pa && !pb) {
+        *band_nodes = 0;
+        return LBRMT_OK;
+    }
+    int u0 = pa ? a0 : b0, u1 = pa ? a1 : b1, u2 = pa ? a2 : b2, u3 = pa ? a3 : b3;
+    if (pb) {
+        u0 = std::min(u0, b0);
+        u1 = std::max(u1, b1);
+        u2 = std::min(u2, b2);
+        u3 = std::max(u3, b3);
+    }
+    // nodes of the lattice tiles the band update covers (whole tiles, clipped)
+    const int x0 = u0 / LB_TX * LB_TX, x1 = std::min((u1 / LB_TX + 1) * LB_TX, c->g.nx) - 1;
+    const int y0 = u2 / LB_TY * LB_TY, y1 = std::min((u3 / LB_TY + 1) * LB_TY, c->g.ny) - 1;
+    *band_nodes = (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1);
+    return LBRMT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// Internal declarations of the gfx950 LBRMT library: kernel parameter blocks,
+// grid helpers and the host-side launchers of every kernel.  Not installed;
+// the public ABI is include/lbrmt.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbrmt {
+
+constexpr int NQ = 9;   // D2Q9 (Sec. 2.2, Table "d2q9")
+constexpr int PAD = 2;  // buffer layers of the reference-map grid (Sec. 3)
+constexpr int LB_TX = 64;  // lattice Boltzmann tile: 64 x 4 nodes, one thread each
+constexpr int LB_TY = 4;
+
+// Tag codes of the reference-map nodes during one step (int8 per node).
+constexpr int8_t TAG_NONE = -1;   // no reference map
+constexpr int8_t TAG_SOLID = 0;   // phi^n < 0, interior
+constexpr int8_t TAG_FAIL = 64;   // OR-ed onto a layer number when the fit failed
+
+// Axis-aligned box of the interior solid nodes of one body (i0 > i1: empty).
+// The working window of a step is this box dilated by `layers` nodes.
+struct Win {
+    int i0, i1, j0, j1;
+};
+
+struct GridP {
+    int nx, ny;
+    int pitch;            // lattice row pitch (elements)
+    int pp;               // reference-map row pitch (elements), nx + 4 rounded up
+    long long plane;      // lattice plane stride = pitch * ny
+    long long pplane;     // reference-map plane stride = pp * (ny + 4)
+    int px, py;           // periodic axes
+    int layers, r_max;
+    double omega;         // 1 / tau
+    double cforce;        // 1 - 1 / (2 tau)
+    double lid_ux;
+    double gx, gy, fext_x, fext_y;
+    double rho_f, eps;
+    double det_rel, detJ_min;
+};
+
+struct BodyP {
+    int present;
+    double cx, cy, R, G, rho_s;
+};
+
+// Step-invariant pointers of the reference-map state.
+struct BandBufs {
+    double* X[2];         // reference map components, padded grid, double-buffered
+    double* Y[2];
+    double* phi[2];       // level set; +inf where no reference map
+    int8_t* tag;
+    Win* win;             // ring of 3 boxes
+    unsigned* health;
+};
+
+// Selection of the ring slots / buffers at state n (n completed steps).
+struct StepSlots {
+    int cur;      // n % 2   : state buffers (lattice A, xi^n, F^n written this step)
+    int nxt;      // (n+1)%2 : lattice B, xi^{n+1}, F^{n-1}
+    int wprev;    // (n+2)%3 : box of S^{n-1}; window over which xi^n, phi^n, F^{n-1} are valid
+    int wcur;     // n % 3   : box of S^n
+    int wnext;    // (n+1)%3 : box of S^{n+1}, built by relabel
+};
+
+inline StepSlots slots_for(long long n)
+{
+    StepSlots s;
+    s.cur = (int)(n % 2);
+    s.nxt = (int)((n + 1) % 2);
+    s.wprev = (int)((n + 2) % 3);
+    s.wcur = (int)(n % 3);
+    s.wnext = (int)((n + 1) % 3);
+    return s;
+}
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ __forceinline__ int wrap_axis(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Dilated, clipped working window of box b (false if empty).
+__device__ __forceinline__ bool dilate_window(const Win& b, const GridP& g, int& i0, int& i1,
+                                              int& j0, int& j1)
+{
+    if (b.i0 > b.i1 || b.j0 > b.j1) return false;
+    const int L = g.layers;
+    const int lox = g.px ? 0 : -PAD, hix = g.px ? g.nx - 1 : g.nx + PAD - 1;
+    const int loy = g.py ? 0 : -PAD, hiy = g.py ? g.ny - 1 : g.ny + PAD - 1;
+    i0 = max(b.i0 - L, lox);
+    i1 = min(b.i1 + L, hix);
+    j0 = max(b.j0 - L, loy);
+    j1 = min(b.j1 + L, hiy);
+    return i0 <= i1 && j0 <= j1;
+}
+
+struct Rect {
+    int i0, i1, j0, j1;
+    bool ok;
+    __device__ __forceinline__ bool has(int i, int j) const
+    {
+        return ok && i >= i0 && i <= i1 && j >= j0 && j <= j1;
+    }
+};
+
+__device__ __forceinline__ Rect window_of(const Win* win, int slot, const GridP& g)
+{
+    Rect r;
+    Win b = win[slot];
+    r.ok = dilate_window(b, g, r.i0, r.i1, r.j0, r.j1);
+    return r;
+}
+
+// Wrap periodic axes; false if (i, j) is outside the reference-map domain.
+__device__ __forceinline__ bool canon(const GridP& g, int& i, int& j)
+{
+    if (g.px) i = wrap_axis(i, g.nx);
+    else if (i < -PAD || i > g.nx + PAD - 1) return false;
+    if (g.py) j = wrap_axis(j, g.ny);
+    else if (j < -PAD || j > g.ny + PAD - 1) return false;
+    return true;
+}
+
+__device__ __forceinline__ long long pidx(const GridP& g, int i, int j)
+{
+    return (long long)(j + PAD) * g.pp + (i + PAD);
+}
+
+// ---------------------------------------------------------------- launchers
+// Every launcher enqueues on `st` and returns hipGetLastError().
+
+// lattice Boltzmann (k_lb.hip)
+hipError_t launch_lb(const GridP& g, int precision, const void* A, void* B, const double* fpx,
+                     const double* fpy, const double* fcx, const double* fcy, const double* drho,
+                     const Win* win, int wprev, int wcur, double fpo_x, double fpo_y, int part,
+                     unsigned* health, hipStream_t st);
+hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
+                                   const double* phi0, const Win* win, int wslot,
+                                   const double* u0, void* tmp, void* A, hipStream_t st);
+hipError_t launch_gather_macro(const GridP& g, int precision, const void* A, const double* fpx,
+                               const double* fpy, const Win* win, int wprev, double fpo_x,
+                               double fpo_y, double* rho, double* ux, double* uy, double* f9,
+                               hipStream_t st);
+hipError_t launch_read_force(const GridP& g, const double* fpx, const double* fpy, const Win* win,
+                             int wprev, double fpo_x, double fpo_y, double* fx, double* fy,
+                             hipStream_t st);
+hipError_t launch_poke(const GridP& g, int precision, void* A, long long node, double value,
+                       hipStream_t st);
+
+// reference map (k_band.hip)
+hipError_t launch_win_reset(Win* win, int slot, hipStream_t st);
+hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, Win* win, int slot0, int slot1,
+                                 hipStream_t st);
+hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
+                            hipStream_t st);
+hipError_t launch_layer_pass(const GridP& g, const BandBufs& bb, int wslot, int wprev, int l,
+                             int mark_only, const double* phin, double* X1, double* Y1,
+                             hipStream_t st);
+hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
+                            hipStream_t st);
+hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
+                         const StepSlots& s, const void* A, const double* fpx, const double* fpy,
+                         double fpo_x, double fpo_y, hipStream_t st);
+hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
+                          hipStream_t st);
+hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
+                        double* fx, double* fy, double* drho, hipStream_t st);
+hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
+                              int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st);
+hipError_t launch_read_refmap(const GridP& g, const BandBufs& bb, int buf, int wvalid, double* X,
+                              double* Y, double* phi, hipStream_t st);
+
+// reductions (k_diag.hip); partial: scratch of diag_partial_doubles() doubles
+int diag_blocks();
+size_t diag_partial_doubles();
+hipError_t launch_diag(const GridP& g, int precision, const BodyP& b, const void* A,
+                       const double* fpx, const double* fpy, const Win* win, int wprev,
+                       double fpo_x, double fpo_y, const BandBufs& bb, int buf, double* partial,
+                       double* out, hipStream_t st);
+
+}  // namespace lbrmt

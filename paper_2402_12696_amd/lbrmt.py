@@ -1,0 +1,391 @@
+"""Thin ctypes binding of ``liblbrmt.so`` (C ABI of ``include/lbrmt.h``).
+
+Every ``lbrmt_*`` function here has the name, arguments and meaning of the C
+call of the same name; it only marshals arguments (torch device tensors become
+raw device pointers, the stream is torch's current HIP stream).  All the
+arithmetic of the time step runs in the library's HIP kernels.  There is no
+fallback: if the library is missing or no GPU is present, calls raise.
+
+``Sim`` wraps one context with a workspace tensor for convenience.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbrmt.so")
+
+LBRMT_OK, LBRMT_EINVAL, LBRMT_EWORKSPACE, LBRMT_EHIP, LBRMT_EUNSTABLE, LBRMT_ECAPACITY, \
+    LBRMT_ESTATE = range(7)
+LBRMT_FP64, LBRMT_FP32 = 0, 1
+HEALTH_NAMES = ["advect_miss", "extrap_fail", "stress_miss", "detj", "detj_solid", "nonfinite",
+                "window_clip", "reserved"]
+KERNEL_NAMES = ["advect", "extrap", "relabel", "force", "lb_bulk", "lb_band"]
+
+
+class lbrmt_grid_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("lid_ux", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("fext_x", ctypes.c_double), ("fext_y", ctypes.c_double),
+        ("rho_f", ctypes.c_double), ("eps", ctypes.c_double),
+        ("layers", ctypes.c_int32), ("r_max", ctypes.c_int32),
+        ("det_rel", ctypes.c_double), ("detJ_min", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class lbrmt_solid_desc(ctypes.Structure):
+    _fields_ = [
+        ("shape", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("theta", ctypes.c_double),
+        ("G", ctypes.c_double), ("rho_s", ctypes.c_double),
+    ]
+
+
+class lbrmt_diag_t(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("mass", ctypes.c_double),
+        ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double),
+        ("centroid_x", ctypes.c_double), ("centroid_y", ctypes.c_double),
+        ("disp_x", ctypes.c_double), ("disp_y", ctypes.c_double),
+        ("max_u", ctypes.c_double), ("n_solid", ctypes.c_double), ("n_band", ctypes.c_double),
+        ("health", ctypes.c_uint32 * 8),
+    ]
+
+
+class lbrmt_validation_t(ctypes.Structure):
+    _fields_ = [
+        ("nu", ctypes.c_double), ("mach_lb", ctypes.c_double), ("reynolds", ctypes.c_double),
+        ("tau_ok", ctypes.c_int32), ("mach_ok", ctypes.c_int32),
+        ("solids_inside", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class LBRMTError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status}) {detail}".strip())
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load liblbrmt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "python -m paper_2402_12696_amd.build_lib")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "lbrmt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "lbrmt_last_error": (ctypes.c_char_p, [_vp]),
+            "lbrmt_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(lbrmt_grid_desc),
+                                                     ctypes.c_int32,
+                                                     ctypes.POINTER(ctypes.c_size_t)]),
+            "lbrmt_create": (ctypes.c_int, [ctypes.POINTER(lbrmt_grid_desc), ctypes.c_int32, _vp,
+                                            ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+            "lbrmt_destroy": (None, [_vp]),
+            "lbrmt_add_solids": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_solid_desc),
+                                                ctypes.c_int32]),
+            "lbrmt_init": (ctypes.c_int, [_vp, _vp]),
+            "lbrmt_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+            "lbrmt_step_count": (ctypes.c_int64, [_vp]),
+            "lbrmt_read_macro": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+            "lbrmt_read_populations": (ctypes.c_int, [_vp, _vp]),
+            "lbrmt_read_force": (ctypes.c_int, [_vp, _vp, _vp]),
+            "lbrmt_read_refmap": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
+            "lbrmt_read_stress": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+            "lbrmt_diag": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_diag_t)]),
+            "lbrmt_state_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+            "lbrmt_save_state": (ctypes.c_int, [_vp, _vp]),
+            "lbrmt_load_state": (ctypes.c_int, [_vp, _vp]),
+            "lbrmt_debug_poke": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64,
+                                                ctypes.c_double]),
+            "lbrmt_validate": (ctypes.c_int, [ctypes.POINTER(lbrmt_grid_desc),
+                                              ctypes.POINTER(lbrmt_solid_desc), ctypes.c_int32,
+                                              ctypes.POINTER(lbrmt_validation_t)]),
+            "lbrmt_set_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
+            "lbrmt_kernel_time": (ctypes.c_int, [_vp, ctypes.c_char_p,
+                                                 ctypes.POINTER(ctypes.c_double),
+                                                 ctypes.POINTER(ctypes.c_int64)]),
+            "lbrmt_band_nodes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64),
+                                                ctypes.POINTER(ctypes.c_int64)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    return lib().lbrmt_status_string(int(status)).decode()
+
+
+def _check(rc, where, ctx=None):
+    if rc != LBRMT_OK:
+        detail = ""
+        if ctx:
+            detail = lib().lbrmt_last_error(ctx).decode()
+        raise LBRMTError(rc, where, detail)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------ same-name calls
+
+def make_grid_desc(nx, ny, tau, lid_ux=0.0, periodic_x=False, periodic_y=False,
+                   gravity=(0.0, 0.0), fext=(0.0, 0.0), rho_f=1.0, eps=1.5, layers=11, r_max=8,
+                   det_rel=1e-8, detJ_min=1e-12, precision="f64", **_ignored):
+    prec = {"f64": LBRMT_FP64, "f32": LBRMT_FP32}[precision]
+    return lbrmt_grid_desc(nx, ny, int(periodic_x), int(periodic_y), tau, lid_ux,
+                           gravity[0], gravity[1], fext[0], fext[1], rho_f, eps, layers, r_max,
+                           det_rel, detJ_min, prec, 0)
+
+
+def make_solid_desc(cx, cy, R, G, rho_s, **_ignored):
+    return lbrmt_solid_desc(0, 0, cx, cy, R, 0.0, 0.0, G, rho_s)
+
+
+def lbrmt_workspace_bytes(desc, max_solids):
+    out = ctypes.c_size_t(0)
+    _check(lib().lbrmt_workspace_bytes(ctypes.byref(desc), max_solids, ctypes.byref(out)),
+           "lbrmt_workspace_bytes")
+    return out.value
+
+
+def lbrmt_create(desc, max_solids, workspace, nbytes, stream=None):
+    ctx = _vp()
+    _check(lib().lbrmt_create(ctypes.byref(desc), max_solids, _ptr(workspace), nbytes,
+                              stream if stream is not None else _stream(), ctypes.byref(ctx)),
+           "lbrmt_create")
+    return ctx
+
+
+def lbrmt_destroy(ctx):
+    lib().lbrmt_destroy(ctx)
+
+
+def lbrmt_add_solids(ctx, solids):
+    arr = (lbrmt_solid_desc * len(solids))(*solids)
+    _check(lib().lbrmt_add_solids(ctx, arr, len(solids)), "lbrmt_add_solids", ctx)
+
+
+def lbrmt_init(ctx, u0=None):
+    _check(lib().lbrmt_init(ctx, _ptr(u0)), "lbrmt_init", ctx)
+
+
+def lbrmt_step(ctx, n):
+    _check(lib().lbrmt_step(ctx, int(n)), "lbrmt_step", ctx)
+
+
+def lbrmt_step_count(ctx):
+    return lib().lbrmt_step_count(ctx)
+
+
+def lbrmt_read_macro(ctx, rho, ux, uy):
+    _check(lib().lbrmt_read_macro(ctx, _ptr(rho), _ptr(ux), _ptr(uy)), "lbrmt_read_macro", ctx)
+
+
+def lbrmt_read_populations(ctx, f9):
+    _check(lib().lbrmt_read_populations(ctx, _ptr(f9)), "lbrmt_read_populations", ctx)
+
+
+def lbrmt_read_force(ctx, fx, fy):
+    _check(lib().lbrmt_read_force(ctx, _ptr(fx), _ptr(fy)), "lbrmt_read_force", ctx)
+
+
+def lbrmt_read_refmap(ctx, solid, X, Y, phi):
+    _check(lib().lbrmt_read_refmap(ctx, solid, _ptr(X), _ptr(Y), _ptr(phi)),
+           "lbrmt_read_refmap", ctx)
+
+
+def lbrmt_read_stress(ctx, sxx, sxy, syy):
+    _check(lib().lbrmt_read_stress(ctx, _ptr(sxx), _ptr(sxy), _ptr(syy)), "lbrmt_read_stress",
+           ctx)
+
+
+def lbrmt_diag(ctx, raise_unstable=True):
+    out = lbrmt_diag_t()
+    rc = lib().lbrmt_diag(ctx, ctypes.byref(out))
+    if rc != LBRMT_EUNSTABLE or raise_unstable:
+        _check(rc, "lbrmt_diag", ctx)
+    d = {k: getattr(out, k) for k, _ in lbrmt_diag_t._fields_ if k != "health"}
+    d["health"] = dict(zip(HEALTH_NAMES, list(out.health)))
+    d["status"] = rc
+    return d
+
+
+def lbrmt_state_bytes(ctx):
+    out = ctypes.c_size_t(0)
+    _check(lib().lbrmt_state_bytes(ctx, ctypes.byref(out)), "lbrmt_state_bytes", ctx)
+    return out.value
+
+
+def lbrmt_save_state(ctx, buf):
+    _check(lib().lbrmt_save_state(ctx, _ptr(buf)), "lbrmt_save_state", ctx)
+
+
+def lbrmt_load_state(ctx, buf):
+    _check(lib().lbrmt_load_state(ctx, _ptr(buf)), "lbrmt_load_state", ctx)
+
+
+def lbrmt_debug_poke(ctx, field, index, value):
+    _check(lib().lbrmt_debug_poke(ctx, field, int(index), float(value)), "lbrmt_debug_poke", ctx)
+
+
+def lbrmt_validate(desc, solids=()):
+    arr = (lbrmt_solid_desc * max(1, len(solids)))(*solids)
+    out = lbrmt_validation_t()
+    _check(lib().lbrmt_validate(ctypes.byref(desc), arr, len(solids), ctypes.byref(out)),
+           "lbrmt_validate")
+    return {k: getattr(out, k) for k, _ in lbrmt_validation_t._fields_ if k != "reserved"}
+
+
+def lbrmt_set_timing(ctx, enable):
+    _check(lib().lbrmt_set_timing(ctx, int(bool(enable))), "lbrmt_set_timing", ctx)
+
+
+def lbrmt_kernel_time(ctx, name):
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _check(lib().lbrmt_kernel_time(ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n)),
+           "lbrmt_kernel_time", ctx)
+    return ms.value, n.value
+
+
+def lbrmt_band_nodes(ctx):
+    b = ctypes.c_int64(0)
+    w = ctypes.c_int64(0)
+    _check(lib().lbrmt_band_nodes(ctx, ctypes.byref(b), ctypes.byref(w)), "lbrmt_band_nodes", ctx)
+    return b.value, w.value
+
+
+# ------------------------------------------------------------ convenience
+
+class Sim:
+    """One LBRMT simulation on a GPU: workspace, context and typed reads.
+
+    Keywords are those of ``workloads.make`` (nx, ny, tau, lid_ux, periodic_x,
+    periodic_y, gravity, fext, rho_f, eps, layers, r_max, det_rel, detJ_min,
+    solid={cx, cy, R, G, rho_s}) plus precision="f64"|"f32".
+    """
+
+    def __init__(self, device="cuda:0", **cfg):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("Sim needs a HIP GPU (torch.cuda) device")
+        torch.cuda.set_device(self.device)
+        self.cfg = dict(cfg)
+        self.nx, self.ny = cfg["nx"], cfg["ny"]
+        self.desc = make_grid_desc(**cfg)
+        solid = cfg.get("solid")
+        self.nsolid = 1 if solid else 0
+        nbytes = lbrmt_workspace_bytes(self.desc, self.nsolid)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.ctx = lbrmt_create(self.desc, self.nsolid, self._ws, nbytes)
+        if solid:
+            lbrmt_add_solids(self.ctx, [make_solid_desc(**solid)])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.torch.cuda.synchronize(self.device)
+            lbrmt_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _plane(self, *lead):
+        return self.torch.empty(*lead, self.ny, self.nx, dtype=self.torch.float64,
+                                device=self.device)
+
+    def init(self, u0=None):
+        if u0 is not None:
+            u0 = self.torch.as_tensor(np.asarray(u0), dtype=self.torch.float64)
+            u0 = u0.reshape(2, self.ny, self.nx).contiguous().to(self.device)
+            self._u0 = u0
+        lbrmt_init(self.ctx, u0)
+        return self
+
+    def step(self, n=1):
+        lbrmt_step(self.ctx, n)
+        return self
+
+    @property
+    def step_count(self):
+        return lbrmt_step_count(self.ctx)
+
+    def macro(self):
+        r, u, v = self._plane(), self._plane(), self._plane()
+        lbrmt_read_macro(self.ctx, r, u, v)
+        return r, u, v
+
+    def populations(self):
+        f = self._plane(9)
+        lbrmt_read_populations(self.ctx, f)
+        return f
+
+    def force(self):
+        fx, fy = self._plane(), self._plane()
+        lbrmt_read_force(self.ctx, fx, fy)
+        return fx, fy
+
+    def refmap(self, solid=0):
+        X, Y, phi = self._plane(), self._plane(), self._plane()
+        lbrmt_read_refmap(self.ctx, solid, X, Y, phi)
+        return X, Y, phi
+
+    def stress(self):
+        a, b, c = self._plane(), self._plane(), self._plane()
+        lbrmt_read_stress(self.ctx, a, b, c)
+        return a, b, c
+
+    def diag(self, raise_unstable=True):
+        return lbrmt_diag(self.ctx, raise_unstable)
+
+    def save_state(self):
+        buf = self.torch.empty(lbrmt_state_bytes(self.ctx), dtype=self.torch.uint8,
+                               device=self.device)
+        lbrmt_save_state(self.ctx, buf)
+        return buf
+
+    def load_state(self, buf):
+        lbrmt_load_state(self.ctx, buf)
+
+    def poke(self, index, value):
+        lbrmt_debug_poke(self.ctx, 0, index, value)
+
+    def set_timing(self, enable):
+        lbrmt_set_timing(self.ctx, enable)
+
+    def kernel_time(self, name):
+        return lbrmt_kernel_time(self.ctx, name)
+
+    def band_nodes(self):
+        return lbrmt_band_nodes(self.ctx)

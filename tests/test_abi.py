@@ -1,0 +1,104 @@
+"""The C-ABI library loads, exports every entry point that include/lbrmt.h
+declares, agrees with the binding on struct layouts, and its host-only calls
+behave as documented (CPU only: no call here touches a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2402_12696_amd import lbrmt as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbrmt.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbrmt_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (lbrmt_[a-z_]+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbrmt.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n",'
+                   'sizeof(lbrmt_grid_desc), sizeof(lbrmt_solid_desc), sizeof(lbrmt_diag_t),'
+                   'sizeof(lbrmt_validation_t), offsetof(lbrmt_grid_desc, det_rel),'
+                   'offsetof(lbrmt_diag_t, health)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True)
+                   .stdout.split()))
+    want = [ctypes.sizeof(B.lbrmt_grid_desc), ctypes.sizeof(B.lbrmt_solid_desc),
+            ctypes.sizeof(B.lbrmt_diag_t), ctypes.sizeof(B.lbrmt_validation_t),
+            B.lbrmt_grid_desc.det_rel.offset, B.lbrmt_diag_t.health.offset]
+    assert got == want
+
+
+def test_status_strings():
+    for s in range(7):
+        assert B.status_string(s)
+    assert B.status_string(99) == "unknown status"
+
+
+def test_workspace_bytes_host_only():
+    d = B.make_grid_desc(nx=64, ny=64, tau=0.8)
+    n64 = B.lbrmt_workspace_bytes(d, 1)
+    d32 = B.make_grid_desc(nx=64, ny=64, tau=0.8, precision="f32")
+    n32 = B.lbrmt_workspace_bytes(d32, 1)
+    # two nine-plane lattices dominate: 2 * 9 * 64 * 64 * 8 bytes in FP64
+    assert n64 > 2 * 9 * 64 * 64 * 8 and n32 < n64
+    big = B.lbrmt_workspace_bytes(B.make_grid_desc(nx=2048, ny=2048, tau=0.6), 1)
+    assert 0.9e9 < big < 1.3e9
+
+
+@pytest.mark.parametrize("kw", [dict(nx=4, ny=64, tau=0.8), dict(nx=64, ny=64, tau=0.5),
+                                dict(nx=64, ny=64, tau=0.8, layers=0)])
+def test_invalid_descriptors_rejected(kw):
+    d = B.make_grid_desc(**kw)
+    with pytest.raises(B.LBRMTError) as e:
+        B.lbrmt_workspace_bytes(d, 1)
+    assert e.value.status == B.LBRMT_EINVAL
+
+
+def test_create_rejects_bad_workspace_without_gpu():
+    d = B.make_grid_desc(nx=64, ny=64, tau=0.8)
+    ctx = ctypes.c_void_p()
+    L = B.lib()
+    assert L.lbrmt_create(ctypes.byref(d), 1, None, 0, None, ctypes.byref(ctx)) == B.LBRMT_EINVAL
+    assert L.lbrmt_create(ctypes.byref(d), 1, ctypes.c_void_p(256), 16, None,
+                          ctypes.byref(ctx)) == B.LBRMT_EWORKSPACE
+    assert L.lbrmt_create(ctypes.byref(d), 1, ctypes.c_void_p(258), 1 << 40, None,
+                          ctypes.byref(ctx)) == B.LBRMT_EWORKSPACE
+    assert L.lbrmt_create(ctypes.byref(d), 2, ctypes.c_void_p(256), 1 << 40, None,
+                          ctypes.byref(ctx)) == B.LBRMT_ECAPACITY
+    assert L.lbrmt_step(None, 1) == B.LBRMT_EINVAL
+
+
+def test_validate_unit_conversions():
+    # App. A: nu = c_s^2 (tau - 1/2), Ma* = U / sqrt(1/3), Re = U L / nu
+    d = B.make_grid_desc(nx=64, ny=64, tau=0.8, lid_ux=0.1)
+    v = B.lbrmt_validate(d, [B.make_solid_desc(32, 40, 12, 0.01, 1.0)])
+    assert abs(v["nu"] - 0.1) < 1e-15
+    assert abs(v["mach_lb"] - 0.1 * 3 ** 0.5) < 1e-15
+    assert abs(v["reynolds"] - 64.0) < 1e-12
+    assert v["tau_ok"] == 1 and v["mach_ok"] == 1 and v["solids_inside"] == 1
+    v = B.lbrmt_validate(B.make_grid_desc(nx=64, ny=64, tau=1.2, lid_ux=0.3))
+    assert v["tau_ok"] == 0 and v["mach_ok"] == 0
+    v = B.lbrmt_validate(d, [B.make_solid_desc(5, 40, 12, 0.01, 1.0)])
+    assert v["solids_inside"] == 0
