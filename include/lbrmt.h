@@ -19,8 +19,7 @@
  *     plus one internal stream and a few events for fork/join inside a step.
  *     It never allocates device memory.
  *   - every call is stream-ordered on the context's stream and asynchronous
- *     unless stated otherwise; no call synchronises except lbrmt_diag,
- *     lbrmt_health and lbrmt_validate (host only).
+ *     unless stated otherwise; the calls that synchronise say so.
  *   - no exception crosses the ABI; every call returns an lbrmt_status.  A
  *     context is not thread-safe; separate contexts are independent.
  */
@@ -85,6 +84,7 @@ typedef enum {
     LBRMT_H_DETJ_SOLID = 4,  /* ... of those, edges with solid fraction > 1/2    */
     LBRMT_H_NONFINITE = 5,   /* nodes whose density is not finite or <= 0        */
     LBRMT_H_WINDOW_CLIP = 6, /* body window reached a periodic seam (unsupported)*/
+    LBRMT_H_LIST_OVERFLOW = 7, /* layer-list entries dropped at capacity          */
     LBRMT_H_COUNT = 8
 } lbrmt_health_index;
 
@@ -181,6 +181,24 @@ int lbrmt_validate(const lbrmt_grid_desc* desc, const lbrmt_solid_desc* solids, 
  * "advect", "extrap", "relabel", "force", "lb_bulk", "lb_band". */
 int lbrmt_set_timing(lbrmt_ctx* ctx, int32_t enable);
 int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t* launches);
+
+/* Launch options of a context (host only; an option change drops the
+ * captured step graph after synchronising the stream):
+ *   LBRMT_OPT_OVERLAP     1 (default): the reference-map chain runs on an
+ *                         internal stream while the lattice Boltzmann update of
+ *                         the tiles away from the solid runs on the caller's;
+ *                         0: one stream, chain then one full update.
+ *   LBRMT_OPT_LB_VARIANT  tile shape of the lattice Boltzmann update, 0 ..
+ *                         LBRMT_OPT_LB_VARIANT_COUNT - 1 (results are bitwise
+ *                         identical across variants; only speed differs).
+ * EINVAL for an unknown option or value. */
+typedef enum {
+    LBRMT_OPT_OVERLAP = 0,
+    LBRMT_OPT_LB_VARIANT = 1,
+    LBRMT_OPT_LB_VARIANT_COUNT = 2 /* read only */
+} lbrmt_option;
+int lbrmt_set_option(lbrmt_ctx* ctx, int32_t option, int64_t value);
+int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);
 
 /* band_nodes: nodes the next step's "lb_band" launch updates (the lattice
  * tiles that meet the solid windows of this and the previous step; "lb_bulk"

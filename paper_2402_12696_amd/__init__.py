@@ -6,7 +6,7 @@ fixed grid.  The step runs in hand-written HIP kernels behind the C ABI of
 ``include/lbrmt.h`` (``liblbrmt.so``); ``lbrmt`` is its thin Python binding.
 """
 from .lbrmt import (LBRMTError, Sim, lib, lbrmt_add_solids, lbrmt_band_nodes,  # noqa: F401
-                    lbrmt_create, lbrmt_debug_poke, lbrmt_destroy, lbrmt_diag, lbrmt_init,
+                    lbrmt_create, lbrmt_debug_poke, lbrmt_get_option, lbrmt_set_option, lbrmt_destroy, lbrmt_diag, lbrmt_init,
                     lbrmt_kernel_time, lbrmt_load_state, lbrmt_read_force, lbrmt_read_macro,
                     lbrmt_read_populations, lbrmt_read_refmap, lbrmt_read_stress,
                     lbrmt_save_state, lbrmt_set_timing, lbrmt_state_bytes, lbrmt_step,

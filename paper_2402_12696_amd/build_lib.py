@@ -4,7 +4,8 @@
 ``csrc/*.hip`` file for gfx950 and links them into
 ``paper_2402_12696_amd/liblbrmt.so``.  The reference-map kernels are compiled
 without floating-point contraction (their discrete decisions are taken in plain
-IEEE double); the lattice Boltzmann kernels keep FMA contraction.
+IEEE double); the lattice Boltzmann kernels fuse multiply-adds only within one
+source expression, so all their launch variants round identically.
 """
 import os
 import subprocess
@@ -22,6 +23,9 @@ COMMON = [
     "-munsafe-fp-atomics",
 ]
 PER_FILE = {
+    # contraction only inside one source expression: every launch variant of
+    # the lattice update then rounds identically
+    "k_lb.hip": ["-ffp-contract=on"],
     "k_band.hip": ["-ffp-contract=off"],
     "k_diag.hip": ["-ffp-contract=off"],
 }

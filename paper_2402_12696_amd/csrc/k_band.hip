@@ -47,18 +47,18 @@ __device__ __forceinline__ double node_coord(int i, int periodic, int n, double 
     return x;
 }
 
-__device__ __forceinline__ bool tag_valid_before(int8_t t, int l)
+__device__ __forceinline__ bool tag_valid_before(int t, int l)
 {
     // solid, or set by an earlier layer
     return t == TAG_SOLID || (t > 0 && t < l);
 }
 
-__device__ __forceinline__ bool tag_set(int8_t t)
+__device__ __forceinline__ bool tag_set(int t)
 {
     return t == TAG_SOLID || (t > 0 && t < TAG_FAIL);
 }
 
-// ---------------------------------------------------------------- block min/max
+// ---------------------------------------------------------------- wave / block helpers
 
 __device__ __forceinline__ int wave_min(int v)
 {
@@ -71,10 +71,34 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// reduce a box over the block, one atomic per component per block
-__device__ void box_atomic(Win* dst, int i0, int i1, int j0, int j1)
+// Append the lanes with `flag` set to a device list of `cap` entries: one
+// atomic per wave.  Every lane of the wave must call it (it uses a ballot).
+// Entries beyond the capacity are dropped and counted in health[7].
+__device__ __forceinline__ void wave_append(bool flag, int value, int* list, int* count, int cap,
+                                            unsigned* health)
+{
+    const unsigned long long mask = __ballot(flag);
+    if (mask == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(mask));
+    base = __shfl(base, leader);
+    if (flag) {
+        const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (slot < cap) list[slot] = value;
+        else atomicAdd(&health[7], 1u);
+    }
+}
+
+// Box of the flagged nodes over the whole grid with the last-block pattern:
+// every block stores its partial box, and the block that arrives last reduces
+// the partials into `dst` (no waiting, one counter).  Called by all threads.
+__device__ void box_reduce(int i0, int i1, int j0, int j1, int* boxpart, unsigned* ticket,
+                           Win* dst0, Win* dst1, int* counts_to_clear)
 {
     __shared__ int sb[4][16];
+    __shared__ bool last;
     i0 = wave_min(i0);
     i1 = wave_max(i1);
     j0 = wave_min(j0);
@@ -95,14 +119,55 @@ __device__ void box_atomic(Win* dst, int i0, int i1, int j0, int j1)
             j0 = min(j0, sb[2][w]);
             j1 = max(j1, sb[3][w]);
         }
-        if (i0 <= i1) {
-            atomicMin(&dst->i0, i0);
-            atomicMax(&dst->i1, i1);
-            atomicMin(&dst->j0, j0);
-            atomicMax(&dst->j1, j1);
-        }
+        int* p = boxpart + 4 * blockIdx.x;
+        p[0] = i0;
+        p[1] = i1;
+        p[2] = j0;
+        p[3] = j1;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
     }
     __syncthreads();
+    if (!last) return;
+    __threadfence();
+    int a0 = 0x3fffffff, a1 = -0x3fffffff, a2 = 0x3fffffff, a3 = -0x3fffffff;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
+        const volatile int* q = boxpart + 4 * k;
+        a0 = min(a0, q[0]);
+        a1 = max(a1, q[1]);
+        a2 = min(a2, q[2]);
+        a3 = max(a3, q[3]);
+    }
+    a0 = wave_min(a0);
+    a1 = wave_max(a1);
+    a2 = wave_min(a2);
+    a3 = wave_max(a3);
+    __syncthreads();
+    if (lane == 0) {
+        sb[0][wid] = a0;
+        sb[1][wid] = a1;
+        sb[2][wid] = a2;
+        sb[3][wid] = a3;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; w++) {
+            a0 = min(a0, sb[0][w]);
+            a1 = max(a1, sb[1][w]);
+            a2 = min(a2, sb[2][w]);
+            a3 = max(a3, sb[3][w]);
+        }
+        Win r;
+        r.i0 = a0;
+        r.i1 = a1;
+        r.j0 = a2;
+        r.j1 = a3;
+        if (a0 > a1) r.i0 = 0x3fffffff, r.i1 = -0x3fffffff, r.j0 = 0x3fffffff, r.j1 = -0x3fffffff;
+        *dst0 = r;
+        if (dst1) *dst1 = r;
+        *ticket = 0u;
+    }
+    if (counts_to_clear && threadIdx.x < MAX_COUNTS) counts_to_clear[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------- window ring
@@ -125,63 +190,84 @@ hipError_t launch_win_reset(Win* win, int slot, hipStream_t st)
 
 // ---------------------------------------------------------------- initialisation
 
+__device__ __forceinline__ bool init_solid(const GridP& g, const BodyP& b, int i, int j)
+{
+    if (i < 0 || i >= g.nx || j < 0 || j >= g.ny) return false;
+    const double x = node_coord(i, g.px, g.nx, b.cx);
+    const double y = node_coord(j, g.py, g.ny, b.cy);
+    return shape_phi(b, x, y) < 0.0;
+}
+
 // box of the initial solid set {interior nodes: phi0(x) < 0}
-__global__ __launch_bounds__(256) void k_init_solid_box(GridP g, BodyP b, Win* win, int s0, int s1)
+__global__ __launch_bounds__(256) void k_init_solid_box(GridP g, BodyP b, int* boxpart,
+                                                        unsigned* ticket, Win* win, int s0, int s1)
 {
     const long long N = (long long)g.nx * g.ny;
     int i0 = 0x3fffffff, i1 = -0x3fffffff, j0 = 0x3fffffff, j1 = -0x3fffffff;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long first = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long iters = (N + stride - 1) / stride;
-    for (long long it = 0; it < iters; it++) {
-        const long long e = first + it * stride;
-        if (e < N) {
-            const int i = (int)(e % g.nx), j = (int)(e / g.nx);
-            const double x = node_coord(i, g.px, g.nx, b.cx);
-            const double y = node_coord(j, g.py, g.ny, b.cy);
-            if (shape_phi(b, x, y) < 0.0) {
-                i0 = min(i0, i);
-                i1 = max(i1, i);
-                j0 = min(j0, j);
-                j1 = max(j1, j);
-            }
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N; e += stride) {
+        const int i = (int)(e % g.nx), j = (int)(e / g.nx);
+        if (init_solid(g, b, i, j)) {
+            i0 = min(i0, i);
+            i1 = max(i1, i);
+            j0 = min(j0, j);
+            j1 = max(j1, j);
         }
     }
-    box_atomic(&win[s0], i0, i1, j0, j1);
-    box_atomic(&win[s1], i0, i1, j0, j1);
+    box_reduce(i0, i1, j0, j1, boxpart, ticket, &win[s0], &win[s1], nullptr);
 }
 
-hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, Win* win, int slot0, int slot1,
-                                 hipStream_t st)
+hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, const BandBufs& bb, int slot0,
+                                 int slot1, hipStream_t st)
 {
-    k_init_solid_box<<<1024, 256, 0, st>>>(g, b, win, slot0, slot1);
+    k_init_solid_box<<<BOX_BLOCKS, 256, 0, st>>>(g, b, bb.boxpart, bb.ticket, bb.win, slot0,
+                                                 slot1);
     return hipGetLastError();
 }
 
-__global__ void k_init_tags(GridP g, BodyP b, int8_t* tag, const Win* win, int wslot)
+// initial tags over the window; solid nodes with a non-solid 4-neighbour
+// start the list of layer 0
+__global__ __launch_bounds__(256) void k_init_tags(GridP g, BodyP b, int* tag, const Win* win,
+                                                   int wslot, int* list0, int* count, int cap,
+                                                   unsigned* health)
 {
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-        const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-        const double x = node_coord(i, g.px, g.nx, b.cx);
-        const double y = node_coord(j, g.py, g.ny, b.cy);
-        tag[pidx(g, i, j)] = (interior && shape_phi(b, x, y) < 0.0) ? TAG_SOLID : TAG_NONE;
+    const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
+    const long long iters = (total + stride - 1) / stride;
+    for (long long it = 0; it < iters; it++) {
+        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
+        bool boundary = false;
+        int kk = 0;
+        if (e < total) {
+            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+            const long long k = pidx(g, i, j);
+            kk = (int)k;
+            const bool solid = init_solid(g, b, i, j);
+            tag[k] = solid ? TAG_SOLID : TAG_NONE;
+            if (solid) {
+                int ci[4] = {i + 1, i - 1, i, i}, cj[4] = {j, j, j + 1, j - 1};
+                for (int d = 0; d < 4; d++) {
+                    int a = ci[d], c = cj[d];
+                    if (canon(g, a, c) && !init_solid(g, b, a, c)) boundary = true;
+                }
+            }
+        }
+        wave_append(boundary, kk, list0, count, cap, health);
     }
 }
 
 hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st)
 {
-    k_init_tags<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot);
+    k_init_tags<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, bb.list[0], bb.count,
+                                      (int)g.pplane, bb.health);
     return hipGetLastError();
 }
 
 // xi_0 = x on the solid and its extrapolation zone, phi = phi0(x) (Alg. 1 init)
-__global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win, int wslot,
+__global__ void k_init_fill(GridP g, BodyP b, const int* tag, const Win* win, int wslot,
                             double* X, double* Y, double* phi)
 {
     const Rect W = window_of(win, wslot, g);
@@ -250,46 +336,40 @@ __device__ void node_velocity(const GridP& g, const S* __restrict__ A, int i, in
     uy = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (2.0 * rho);
 }
 
-// reference-map value at (i, j) if present (canonicalised, inside window D,
-// finite phi)
-struct RefRead {
-    const double *X, *Y, *phi;
-    Rect D;
-    __device__ __forceinline__ bool get(const GridP& g, int i, int j, double& x, double& y) const
-    {
-        if (!canon(g, i, j) || !D.has(i, j)) return false;
-        const long long k = pidx(g, i, j);
-        if (!(phi[k] < INFINITY)) return false;
-        x = X[k];
-        y = Y[k];
-        return true;
-    }
-};
+// reference-map node (i, j) of step n: canonical index, or -1 if it holds no
+// value (outside the domain or outside the window D where xi^n was written)
+__device__ __forceinline__ long long ref_index(const GridP& g, const Rect& D, int i, int j)
+{
+    if (!canon(g, i, j) || !D.has(i, j)) return -1;
+    return pidx(g, i, j);
+}
 
-// one-sided second-order upwind derivative of Eq. (3_1_eno) along (di, dj)
-__device__ __forceinline__ bool upwind(const GridP& g, const RefRead& R, int i, int j, int di,
-                                       int dj, double vel, double X0, double Y0, double& dX,
-                                       double& dY)
+// one-sided second-order upwind derivative of Eq. (3_1_eno) from preloaded
+// stencil values: p1/p2 are the nodes one and two steps upwind
+__device__ __forceinline__ bool upwind_d(double vel, double X0, double Y0, bool okm1, bool okm2,
+                                         double Xm1, double Ym1, double Xm2, double Ym2,
+                                         bool okp1, bool okp2, double Xp1, double Yp1,
+                                         double Xp2, double Yp2, double& dX, double& dY)
 {
     dX = dY = 0.0;
     if (vel == 0.0) return true;
-    const int sg = vel > 0.0 ? 1 : -1;
-    double X1, Y1, X2, Y2;
-    if (!R.get(g, i - sg * di, j - sg * dj, X1, Y1)) return false;
-    if (!R.get(g, i - 2 * sg * di, j - 2 * sg * dj, X2, Y2)) return false;
-    if (sg > 0) {
-        dX = (3.0 * X0 - 4.0 * X1 + X2) / 2.0;
-        dY = (3.0 * Y0 - 4.0 * Y1 + Y2) / 2.0;
+    if (vel > 0.0) {
+        if (!okm1 || !okm2) return false;
+        dX = (3.0 * X0 - 4.0 * Xm1 + Xm2) / 2.0;
+        dY = (3.0 * Y0 - 4.0 * Ym1 + Ym2) / 2.0;
     } else {
-        dX = (-3.0 * X0 + 4.0 * X1 - X2) / 2.0;
-        dY = (-3.0 * Y0 + 4.0 * Y1 - Y2) / 2.0;
+        if (!okp1 || !okp2) return false;
+        dX = (-3.0 * X0 + 4.0 * Xp1 - Xp2) / 2.0;
+        dY = (-3.0 * Y0 + 4.0 * Yp1 - Yp2) / 2.0;
     }
     return true;
 }
 
-// Eq. (3_1_refmap_adv) on the solid nodes S^n = {interior, phi^n < 0}; also
-// resets the step's tags (solid or none) over the window and the ring slot
-// that relabel will fill with the box of S^{n+1}.
+// Eq. (3_1_refmap_adv) on the solid nodes S^n = {interior, phi^n < 0}.  Also
+// resets the step's tags over the window, lists the solid nodes that touch a
+// non-solid node (layer 0 of the extrapolation), and resets the ring slot that
+// relabel fills with the box of S^{n+1}.  All stencil loads of a node are
+// issued together.
 template <typename S>
 __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A,
                                                 const double* __restrict__ fpx,
@@ -297,8 +377,9 @@ __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A
                                                 double fpo_y, const double* __restrict__ X,
                                                 const double* __restrict__ Y,
                                                 const double* __restrict__ phi, double* X1,
-                                                double* Y1, int8_t* tag, Win* win, int wprev,
-                                                int wcur, int wnext, unsigned* health)
+                                                double* Y1, int* tag, int* list0, int* count,
+                                                Win* win, int wprev, int wcur, int wnext,
+                                                unsigned* health)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         win[wnext].i0 = 0x3fffffff;
@@ -308,41 +389,71 @@ __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A
     }
     const Rect W = window_of(win, wcur, g);
     if (!W.ok) return;
-    RefRead R;
-    R.X = X;
-    R.Y = Y;
-    R.phi = phi;
-    R.D = window_of(win, wprev, g);
+    const Rect D = window_of(win, wprev, g);
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-        const long long k = pidx(g, i, j);
-        const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-        const bool solid = interior && R.D.has(i, j) && phi[k] < 0.0;
-        tag[k] = solid ? TAG_SOLID : TAG_NONE;
-        if (!solid) continue;
-        const long long n = (long long)j * g.pitch + i;
-        double Fx = fpo_x, Fy = fpo_y;
-        if (R.D.has(i, j)) {
-            Fx = fpx[n];
-            Fy = fpy[n];
+    const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
+    const long long iters = (total + stride - 1) / stride;
+    for (long long it = 0; it < iters; it++) {
+        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
+        bool boundary = false;
+        int kk = 0;
+        if (e < total) {
+            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+            const long long k = pidx(g, i, j);
+            kk = (int)k;
+            const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+            const bool solid = interior && D.has(i, j) && phi[k] < 0.0;
+            tag[k] = solid ? TAG_SOLID : TAG_NONE;
+            if (solid) {
+                // stencil nodes: x-1, x-2, x+1, x+2, y-1, y-2, y+1, y+2
+                const int di[8] = {-1, -2, 1, 2, 0, 0, 0, 0};
+                const int dj[8] = {0, 0, 0, 0, -1, -2, 1, 2};
+                long long ks[8];
+                double ps[8], xs[8], ys[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) ks[q] = ref_index(g, D, i + di[q], j + dj[q]);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const long long kq = ks[q] >= 0 ? ks[q] : k;
+                    ps[q] = ks[q] >= 0 ? phi[kq] : INFINITY;
+                    xs[q] = X[kq];
+                    ys[q] = Y[kq];
+                }
+                const long long n = (long long)j * g.pitch + i;
+                double u, v;
+                node_velocity<S>(g, A, i, j, fpx[n], fpy[n], u, v);
+                bool okq[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) okq[q] = ps[q] < INFINITY;
+                // a 4-neighbour outside S makes this node a layer-0 node
+                const int nb4[4] = {0, 2, 4, 6};
+                for (int d = 0; d < 4; d++) {
+                    const int q = nb4[d];
+                    int a = i + di[q], c = j + dj[q];
+                    if (!canon(g, a, c)) continue;
+                    const bool nint = a >= 0 && a < g.nx && c >= 0 && c < g.ny;
+                    if (!(nint && ks[q] >= 0 && ps[q] < 0.0)) boundary = true;
+                }
+                const double X0 = X[k], Y0 = Y[k];
+                double dXx, dYx, dXy, dYy;
+                const bool okx = upwind_d(u, X0, Y0, okq[0], okq[1], xs[0], ys[0], xs[1], ys[1],
+                                          okq[2], okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
+                const bool oky = upwind_d(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5],
+                                          okq[6], okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
+                if (!okx || !oky) {
+                    atomicAdd(&health[0], 1u);
+                    X1[k] = X0;
+                    Y1[k] = Y0;
+                } else {
+                    X1[k] = X0 - (u * dXx + v * dXy);
+                    Y1[k] = Y0 - (u * dYx + v * dYy);
+                }
+            }
         }
-        double u, v;
-        node_velocity<S>(g, A, i, j, Fx, Fy, u, v);
-        const double X0 = X[k], Y0 = Y[k];
-        double dXx, dYx, dXy, dYy;
-        const bool okx = upwind(g, R, i, j, 1, 0, u, X0, Y0, dXx, dYx);
-        const bool oky = upwind(g, R, i, j, 0, 1, v, X0, Y0, dXy, dYy);
-        if (!okx || !oky) {
-            atomicAdd(&health[0], 1u);
-            X1[k] = X0;
-            Y1[k] = Y0;
-        } else {
-            X1[k] = X0 - (u * dXx + v * dXy);
-            Y1[k] = Y0 - (u * dYx + v * dYy);
-        }
+        wave_append(boundary, kk, list0, count, (int)g.pplane, health);
     }
+    (void)fpo_x;
+    (void)fpo_y;
 }
 
 hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
@@ -353,13 +464,15 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
     if (precision == 0)
         k_advect<double><<<2048, 256, 0, st>>>(g, (const double*)A, fpx, fpy, fpo_x, fpo_y,
                                                bb.X[s.cur], bb.Y[s.cur], bb.phi[s.cur],
-                                               bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
-                                               s.wcur, s.wnext, bb.health);
+                                               bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.list[0],
+                                               bb.count, bb.win, s.wprev, s.wcur, s.wnext,
+                                               bb.health);
     else
         k_advect<float><<<2048, 256, 0, st>>>(g, (const float*)A, fpx, fpy, fpo_x, fpo_y,
                                               bb.X[s.cur], bb.Y[s.cur], bb.phi[s.cur],
-                                              bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
-                                              s.wcur, s.wnext, bb.health);
+                                              bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.list[0],
+                                              bb.count, bb.win, s.wprev, s.wcur, s.wnext,
+                                              bb.health);
     return hipGetLastError();
 }
 
@@ -373,116 +486,176 @@ __device__ __forceinline__ double det3(double a00, double a01, double a02, doubl
            a02 * (a10 * a21 - a11 * a20);
 }
 
-// Layer l of Sec. 3.2: nodes without a tag that touch a layer-(l-1) node
-// (4-adjacency) join layer l; unless mark_only, each is extrapolated with a
-// weighted linear least-squares fit over the valid nodes (solid, or set in an
-// earlier layer) of a scan window grown from half-width 2 until at least three
-// valid nodes give a well-posed fit.  Targets of one layer never read each
-// other, so the result does not depend on thread order.
+struct Fit {
+    double M00, M01, M02, M11, M12, M22, bX0, bX1, bX2, bY0, bY1, bY2;
+    __device__ __forceinline__ void zero()
+    {
+        M00 = M01 = M02 = M11 = M12 = M22 = 0.0;
+        bX0 = bX1 = bX2 = bY0 = bY1 = bY2 = 0.0;
+    }
+    // one valid node at offset (a, b) from the target, weight of Eq. (3_2_extrap_weight)
+    __device__ __forceinline__ void add(int a, int b, bool use_n, double nxh, double nyh,
+                                        double xv, double yv)
+    {
+        double wt = ldexp(1.0, -(abs(a) + abs(b)));
+        if (use_n) {
+            const double ddx = -(double)a, ddy = -(double)b;  // d = x_target - x_valid
+            const double dn = (ddx * nxh + ddy * nyh) / sqrt(ddx * ddx + ddy * ddy);
+            wt = dn * wt > 0.0 ? dn * wt : 0.0;
+        }
+        const double dx = a, dy = b;
+        M00 += wt * dx * dx;
+        M01 += wt * dx * dy;
+        M02 += wt * dx;
+        M11 += wt * dy * dy;
+        M12 += wt * dy;
+        M22 += wt;
+        bX0 += wt * dx * xv;
+        bX1 += wt * dy * xv;
+        bX2 += wt * xv;
+        bY0 += wt * dx * yv;
+        bY1 += wt * dy * yv;
+        bY2 += wt * yv;
+    }
+    // intercept of the weighted linear fit, if well posed
+    __device__ __forceinline__ bool solve(double det_rel, double& x, double& y) const
+    {
+        const double det = det3(M00, M01, M02, M01, M11, M12, M02, M12, M22);
+        if (!(det > det_rel * M22 * M22 * M22)) return false;
+        x = det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det;
+        y = det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det;
+        return true;
+    }
+};
+
+// Sec. 3.2 steps (i)-(iii) for target (i, j) of layer l: scan windows of
+// half-width r = 2, 3, ... r_max, count the valid nodes (solid, or set in an
+// earlier layer), fit xi = A x + B y + C by weighted least squares in
+// coordinates centred at the target and take the intercept C.  The r = 2 scan
+// loads all 25 tags and then all valid maps at once; wider scans are rare and
+// use a plain loop.  Nodes are visited row by row in both, as in the oracle.
+__device__ bool extrapolate_target(const GridP& g, const Rect& W, const Rect& D, int l, int i,
+                                   int j, long long kt, const int* tag, const double* phin,
+                                   const double* X1, const double* Y1, double& xo, double& yo)
+{
+    bool use_n = false;
+    double nxh = 0.0, nyh = 0.0;
+    if (l <= 2) {
+        const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+        long long kq[4];
+        double pv[4];
+#pragma unroll
+        for (int d = 0; d < 4; d++) kq[d] = ref_index(g, D, i + di[d], j + dj[d]);
+#pragma unroll
+        for (int d = 0; d < 4; d++) pv[d] = kq[d] >= 0 ? phin[kq[d]] : INFINITY;
+        if (pv[0] < INFINITY && pv[1] < INFINITY && pv[2] < INFINITY && pv[3] < INFINITY) {
+            const double gx = (pv[0] - pv[1]) / 2.0;
+            const double gy = (pv[2] - pv[3]) / 2.0;
+            const double gn = sqrt(gx * gx + gy * gy);
+            if (gn > 0.0) {
+                nxh = gx / gn;
+                nyh = gy / gn;
+                use_n = true;
+            }
+        }
+    }
+    {
+        long long kk[25];
+        int tg[25];
+#pragma unroll
+        for (int q = 0; q < 25; q++) {
+            int ci = i + q % 5 - 2, cj = j + q / 5 - 2;
+            kk[q] = (canon(g, ci, cj) && W.has(ci, cj)) ? pidx(g, ci, cj) : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < 25; q++) tg[q] = tag[kk[q] >= 0 ? kk[q] : kt];
+        int count = 0;
+#pragma unroll
+        for (int q = 0; q < 25; q++) count += (kk[q] >= 0 && tag_valid_before(tg[q], l)) ? 1 : 0;
+        if (count >= 3) {
+            double xv[25], yv[25];
+#pragma unroll
+            for (int q = 0; q < 25; q++) {
+                const long long kq = (kk[q] >= 0 && tag_valid_before(tg[q], l)) ? kk[q] : kt;
+                xv[q] = X1[kq];
+                yv[q] = Y1[kq];
+            }
+            Fit f;
+            f.zero();
+#pragma unroll
+            for (int q = 0; q < 25; q++)
+                if (kk[q] >= 0 && tag_valid_before(tg[q], l))
+                    f.add(q % 5 - 2, q / 5 - 2, use_n && l <= 2, nxh, nyh, xv[q], yv[q]);
+            if (f.solve(g.det_rel, xo, yo)) return true;
+        }
+    }
+    for (int r = 3; r <= g.r_max; r++) {
+        int count = 0;
+        for (int b = -r; b <= r; b++)
+            for (int a = -r; a <= r; a++) {
+                int ci = i + a, cj = j + b;
+                if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
+                if (tag_valid_before(tag[pidx(g, ci, cj)], l)) count++;
+            }
+        if (count < 3) continue;
+        Fit f;
+        f.zero();
+        for (int b = -r; b <= r; b++)
+            for (int a = -r; a <= r; a++) {
+                int ci = i + a, cj = j + b;
+                if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
+                const long long k = pidx(g, ci, cj);
+                if (!tag_valid_before(tag[k], l)) continue;
+                f.add(a, b, use_n && l <= 2, nxh, nyh, X1[k], Y1[k]);
+            }
+        if (f.solve(g.det_rel, xo, yo)) return true;
+    }
+    return false;
+}
+
+// Layer l of Sec. 3.2: the 4-neighbours of the layer-(l-1) nodes that hold no
+// tag yet form layer l.  Each is claimed by exactly one thread (atomic CAS on
+// its tag), extrapolated at once unless mark_only (valid nodes come only from
+// earlier layers, so targets of one layer never read each other) and appended
+// to the list of layer l.
 __global__ __launch_bounds__(256) void k_layer(GridP g, const Win* __restrict__ win, int wcur,
-                                               int wprev, int l, int mark_only, int8_t* tag,
+                                               int wprev, int l, int mark_only, int* tag,
+                                               const int* __restrict__ lin, const int* cin,
+                                               int* lout, int* cout,
                                                const double* __restrict__ phin, double* X1,
                                                double* Y1, unsigned* health)
 {
     const Rect W = window_of(win, wcur, g);
     if (!W.ok) return;
     const Rect D = window_of(win, wprev, g);
-    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-        const long long kt = pidx(g, i, j);
-        if (tag[kt] != TAG_NONE) continue;
-        bool hit = false;
-        const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
-        for (int d = 0; d < 4; d++) {
-            int ni = i + nb[d][0], nj = j + nb[d][1];
-            if (!canon(g, ni, nj) || !W.has(ni, nj)) continue;
-            const int8_t t = tag[pidx(g, ni, nj)];
-            if (t != TAG_NONE && (t & 63) == l - 1) hit = true;
-        }
-        if (!hit) continue;
-        if (mark_only) {
-            tag[kt] = (int8_t)l;
-            continue;
-        }
-        // outward normal of phi^n at the target for the first two layers
-        bool use_n = false;
-        double nxh = 0.0, nyh = 0.0;
-        if (l <= 2) {
-            double pv[4];
-            bool ok = true;
-            for (int d = 0; d < 4 && ok; d++) {
-                int ni = i + nb[d][0], nj = j + nb[d][1];
-                if (!canon(g, ni, nj) || !D.has(ni, nj)) {
-                    ok = false;
-                    break;
-                }
-                pv[d] = phin[pidx(g, ni, nj)];
-                if (!(pv[d] < INFINITY)) ok = false;
+    const long long total = 4ll * min(*cin, (int)g.pplane);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long iters = (total + stride - 1) / stride;
+    const int ddi[4] = {1, -1, 0, 0}, ddj[4] = {0, 0, 1, -1};
+    for (long long it = 0; it < iters; it++) {
+        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
+        bool claimed = false;
+        int kt = 0;
+        if (e < total) {
+            const int k0 = lin[e >> 2];
+            const int d = (int)(e & 3);
+            int ni = k0 % g.pp - PAD + ddi[d], nj = k0 / g.pp - PAD + ddj[d];
+            if (canon(g, ni, nj) && W.has(ni, nj)) {
+                kt = (int)pidx(g, ni, nj);
+                if (tag[kt] == TAG_NONE) claimed = atomicCAS(&tag[kt], TAG_NONE, l) == TAG_NONE;
             }
-            if (ok) {
-                const double gx = (pv[0] - pv[1]) / 2.0;
-                const double gy = (pv[2] - pv[3]) / 2.0;
-                const double gn = sqrt(gx * gx + gy * gy);
-                if (gn > 0.0) {
-                    nxh = gx / gn;
-                    nyh = gy / gn;
-                    use_n = true;
+            if (claimed && !mark_only) {
+                double xo, yo;
+                if (extrapolate_target(g, W, D, l, ni, nj, kt, tag, phin, X1, Y1, xo, yo)) {
+                    X1[kt] = xo;
+                    Y1[kt] = yo;
+                } else {
+                    tag[kt] = l | TAG_FAIL;
+                    atomicAdd(&health[1], 1u);
                 }
             }
         }
-        bool done = false;
-        for (int r = 2; r <= g.r_max && !done; r++) {
-            int count = 0;
-            for (int b = -r; b <= r; b++)
-                for (int a = -r; a <= r; a++) {
-                    int ci = i + a, cj = j + b;
-                    if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
-                    if (tag_valid_before(tag[pidx(g, ci, cj)], l)) count++;
-                }
-            if (count < 3) continue;
-            double M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0;
-            double bX0 = 0, bX1 = 0, bX2 = 0, bY0 = 0, bY1 = 0, bY2 = 0;
-            for (int b = -r; b <= r; b++)
-                for (int a = -r; a <= r; a++) {
-                    int ci = i + a, cj = j + b;
-                    if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
-                    const long long k = pidx(g, ci, cj);
-                    if (!tag_valid_before(tag[k], l)) continue;
-                    double wt = ldexp(1.0, -(abs(a) + abs(b)));  // Eq. (3_2_extrap_weight)
-                    if (l <= 2 && use_n) {
-                        const double ddx = -(double)a, ddy = -(double)b;
-                        const double dn = (ddx * nxh + ddy * nyh) / sqrt(ddx * ddx + ddy * ddy);
-                        wt = dn * wt > 0.0 ? dn * wt : 0.0;
-                    }
-                    const double dx = a, dy = b;
-                    const double xv = X1[k], yv = Y1[k];
-                    M00 += wt * dx * dx;
-                    M01 += wt * dx * dy;
-                    M02 += wt * dx;
-                    M11 += wt * dy * dy;
-                    M12 += wt * dy;
-                    M22 += wt;
-                    bX0 += wt * dx * xv;
-                    bX1 += wt * dy * xv;
-                    bX2 += wt * xv;
-                    bY0 += wt * dx * yv;
-                    bY1 += wt * dy * yv;
-                    bY2 += wt * yv;
-                }
-            const double det = det3(M00, M01, M02, M01, M11, M12, M02, M12, M22);
-            if (!(det > g.det_rel * M22 * M22 * M22)) continue;
-            X1[kt] = det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det;
-            Y1[kt] = det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det;
-            done = true;
-        }
-        if (done) {
-            tag[kt] = (int8_t)l;
-        } else {
-            tag[kt] = (int8_t)(l | TAG_FAIL);
-            atomicAdd(&health[1], 1u);
-        }
+        wave_append(claimed, kt, lout, cout, (int)g.pplane, health);
     }
 }
 
@@ -490,30 +663,29 @@ hipError_t launch_layer_pass(const GridP& g, const BandBufs& bb, int wslot, int 
                              int mark_only, const double* phin, double* X1, double* Y1,
                              hipStream_t st)
 {
-    k_layer<<<2048, 256, 0, st>>>(g, bb.win, wslot, wprev, l, mark_only, bb.tag, phin, X1, Y1,
-                                  bb.health);
+    k_layer<<<256, 256, 0, st>>>(g, bb.win, wslot, wprev, l, mark_only, bb.tag,
+                                 bb.list[(l - 1) & 1], bb.count + (l - 1), bb.list[l & 1],
+                                 bb.count + l, phin, X1, Y1, bb.health);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- relabel
 
 // phi^{n+1} = phi0(xi^{n+1}) on every node holding a reference map (Alg. 1);
-// box of the new interior solid set into the next ring slot
-__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t* __restrict__ tag,
+// box of the new interior solid set into the next ring slot; clears the list
+// counters for the next step
+__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int* __restrict__ tag,
                                                  Win* win, int wcur, int wnext, double* X1,
-                                                 double* Y1, double* phi1)
+                                                 double* Y1, double* phi1, int* boxpart,
+                                                 unsigned* ticket, int* count)
 {
     const Rect W = window_of(win, wcur, g);
-    if (!W.ok) return;
-    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
     int i0 = 0x3fffffff, i1 = -0x3fffffff, j0 = 0x3fffffff, j1 = -0x3fffffff;
-    const long long total = (long long)w * h;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long first = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long iters = (total + stride - 1) / stride;
-    for (long long it = 0; it < iters; it++) {
-        const long long e = first + it * stride;
-        if (e < total) {
+    if (W.ok) {
+        const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+        const long long total = (long long)w * h;
+        for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+             e += (long long)gridDim.x * blockDim.x) {
             const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
             const long long k = pidx(g, i, j);
             if (tag_set(tag[k])) {
@@ -532,14 +704,15 @@ __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t*
             }
         }
     }
-    box_atomic(&win[wnext], i0, i1, j0, j1);
+    box_reduce(i0, i1, j0, j1, boxpart, ticket, &win[wnext], nullptr, count);
 }
 
 hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                           hipStream_t st)
 {
-    k_relabel<<<1024, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur, s.wnext, bb.X[s.nxt],
-                                    bb.Y[s.nxt], bb.phi[s.nxt]);
+    k_relabel<<<BOX_BLOCKS, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur, s.wnext, bb.X[s.nxt],
+                                          bb.Y[s.nxt], bb.phi[s.nxt], bb.boxpart, bb.ticket,
+                                          bb.count);
     return hipGetLastError();
 }
 

@@ -167,7 +167,7 @@ __device__ __forceinline__ Rect band_region(const GridP& g, const Rect& a, const
 // PART 0: every tile, per-node window tests.  PART 1: tiles outside the band
 // region only (uniform force).  PART 2: tiles of the band region only,
 // grid-stride.
-template <typename S, int PART>
+template <typename S, int PART, int LB_TX, int LB_TY, bool NT>
 __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     GridP g, const S* __restrict__ A, S* __restrict__ B, const double* __restrict__ fpx,
     const double* __restrict__ fpy, const double* __restrict__ fcx, const double* __restrict__ fcy,
@@ -246,32 +246,87 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
         }
         if (!(rho > C(0) && rho < C(1e30))) atomicAdd(&health[5], 1u);
         const long long P = g.plane;
+        if (NT) {
 #pragma unroll
-        for (int k = 0; k < NQ; k++) B[k * P + q.n] = S(f[k]);
+            for (int k = 0; k < NQ; k++) __builtin_nontemporal_store(S(f[k]), &B[k * P + q.n]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NQ; k++) B[k * P + q.n] = S(f[k]);
+        }
     }
 }
 
-hipError_t launch_lb(const GridP& g, int precision, const void* A, void* B, const double* fpx,
-                     const double* fpy, const double* fcx, const double* fcy, const double* drho,
-                     const Win* win, int wprev, int wcur, double fpo_x, double fpo_y, int part,
-                     unsigned* health, hipStream_t st)
+// Tile shapes of the lattice Boltzmann update (one thread per node); the
+// variant is chosen per context (lbrmt_set_option) by measurement.
+struct LbVariant {
+    int tx, ty;
+    bool nt;
+};
+constexpr LbVariant LB_VARIANTS[] = {{64, 4, false},  {128, 2, false}, {256, 1, false},
+                                     {64, 4, true},   {128, 2, true},  {256, 1, true},
+                                     {32, 8, false},  {64, 2, false}};
+constexpr int N_LB_VARIANTS = sizeof(LB_VARIANTS) / sizeof(LB_VARIANTS[0]);
+
+int lb_variant_count() { return N_LB_VARIANTS; }
+void lb_variant_tile(int v, int* tx, int* ty)
 {
-    const int ntiles = ((g.nx + LB_TX - 1) / LB_TX) * ((g.ny + LB_TY - 1) / LB_TY);
-    const dim3 blk(LB_TX * LB_TY);
-    const dim3 grd(part == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles);
-#define LB_LAUNCH(S, PARTV)                                                                    \
-    k_lb<S, PARTV><<<grd, blk, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx, fcy, drho, win, \
-                                        wprev, wcur, fpo_x, fpo_y, health)
-    if (precision == 0) {
-        if (part == 0) LB_LAUNCH(double, 0);
-        else if (part == 1) LB_LAUNCH(double, 1);
-        else LB_LAUNCH(double, 2);
-    } else {
-        if (part == 0) LB_LAUNCH(float, 0);
-        else if (part == 1) LB_LAUNCH(float, 1);
-        else LB_LAUNCH(float, 2);
+    *tx = LB_VARIANTS[v].tx;
+    *ty = LB_VARIANTS[v].ty;
+}
+
+template <typename S, int PART, int TX, int TY, bool NT>
+static void lb_launch_one(const GridP& g, const void* A, void* B, const double* fpx,
+                          const double* fpy, const double* fcx, const double* fcy,
+                          const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
+                          double fpo_y, unsigned* health, hipStream_t st)
+{
+    const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    const int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles;
+    k_lb<S, PART, TX, TY, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx, fcy,
+                                                       drho, win, wprev, wcur, fpo_x, fpo_y,
+                                                       health);
+}
+
+template <typename S, int PART>
+static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, const double* fpx,
+                              const double* fpy, const double* fcx, const double* fcy,
+                              const double* drho, const Win* win, int wprev, int wcur,
+                              double fpo_x, double fpo_y, unsigned* health, hipStream_t st)
+{
+#define LBV(TX, TY, NT)                                                                       \
+    lb_launch_one<S, PART, TX, TY, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
+                                       fpo_x, fpo_y, health, st)
+    switch (v) {
+    case 1: LBV(128, 2, false); break;
+    case 2: LBV(256, 1, false); break;
+    case 3: LBV(64, 4, true); break;
+    case 4: LBV(128, 2, true); break;
+    case 5: LBV(256, 1, true); break;
+    case 6: LBV(32, 8, false); break;
+    case 7: LBV(64, 2, false); break;
+    default: LBV(64, 4, false); break;
     }
-#undef LB_LAUNCH
+#undef LBV
+}
+
+hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
+                     const double* fpx, const double* fpy, const double* fcx, const double* fcy,
+                     const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
+                     double fpo_y, int part, unsigned* health, hipStream_t st)
+{
+#define LBP(S, PARTV)                                                                        \
+    lb_launch_variant<S, PARTV>(variant, g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
+                                fpo_x, fpo_y, health, st)
+    if (precision == 0) {
+        if (part == 0) LBP(double, 0);
+        else if (part == 1) LBP(double, 1);
+        else LBP(double, 2);
+    } else {
+        if (part == 0) LBP(float, 0);
+        else if (part == 1) LBP(float, 1);
+        else LBP(float, 2);
+    }
+#undef LBP
     return hipGetLastError();
 }
 

@@ -34,7 +34,8 @@ struct Layout {
     int pitch, pp;
     size_t plane, pplane;
     size_t off_lat[2], off_fx[2], off_fy[2], off_drho, off_X[2], off_Y[2], off_phi[2], off_tag,
-        off_win, off_health, off_dpart, off_dout, total;
+        off_win, off_health, off_dpart, off_dout, off_list[2], off_count, off_boxpart,
+        off_ticket, total;
     size_t lat_bytes;
 };
 
@@ -64,7 +65,11 @@ Layout make_layout(const lbrmt_grid_desc* d)
         L.off_Y[k] = take(L.pplane * 8);
         L.off_phi[k] = take(L.pplane * 8);
     }
-    L.off_tag = take(L.pplane);
+    L.off_tag = take(L.pplane * 4);
+    for (int k = 0; k < 2; k++) L.off_list[k] = take(L.pplane * 4);
+    L.off_count = take(MAX_COUNTS * 4);
+    L.off_boxpart = take(BOX_BLOCKS * 4 * 4);
+    L.off_ticket = take(4);
     L.off_win = take(3 * sizeof(Win));
     L.off_health = take(LBRMT_H_COUNT * sizeof(unsigned));
     L.off_dpart = take(diag_partial_doubles() * 8);
@@ -97,6 +102,7 @@ struct lbrmt_ctx {
     long long step = 0;
     bool inited = false;
     bool overlap = true;
+    int lb_variant = 0;
     hipGraphExec_t gexec = nullptr;
     bool timing = false;
     struct Pending {
@@ -224,7 +230,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
             HIPCHK(c, hipEventRecord(c->ev_join, c->side));
             {
                 Bracket b(c, 4, main_s);
-                HIPCHK(c, launch_lb(g, prec, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
+                HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
                                     c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
                                     s.wprev, s.wcur, ox, oy, 1, c->bb.health, main_s));
                 b.done();
@@ -232,7 +238,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
             HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
             {
                 Bracket b(c, 5, main_s);
-                HIPCHK(c, launch_lb(g, prec, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
+                HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
                                     c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
                                     s.wprev, s.wcur, ox, oy, 2, c->bb.health, main_s));
                 b.done();
@@ -241,7 +247,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
         }
     }
     Bracket b(c, 4, main_s);
-    HIPCHK(c, launch_lb(g, prec, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt],
+    HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt],
                         c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win, s.wprev, s.wcur, ox, oy, 0,
                         c->bb.health, main_s));
     b.done();
@@ -348,7 +354,11 @@ int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t 
         c->bb.phi[k] = (double*)(c->ws + L.off_phi[k]);
     }
     c->drho = (double*)(c->ws + L.off_drho);
-    c->bb.tag = (int8_t*)(c->ws + L.off_tag);
+    c->bb.tag = (int*)(c->ws + L.off_tag);
+    for (int k = 0; k < 2; k++) c->bb.list[k] = (int*)(c->ws + L.off_list[k]);
+    c->bb.count = (int*)(c->ws + L.off_count);
+    c->bb.boxpart = (int*)(c->ws + L.off_boxpart);
+    c->bb.ticket = (unsigned*)(c->ws + L.off_ticket);
     c->bb.win = (Win*)(c->ws + L.off_win);
     c->bb.health = (unsigned*)(c->ws + L.off_health);
     c->dpart = (double*)(c->ws + L.off_dpart);
@@ -417,15 +427,18 @@ int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
         HIPCHK(c, hipMemsetAsync(c->Fy[k], 0, c->L.plane * 8, st));
     }
     HIPCHK(c, hipMemsetAsync(c->drho, 0, c->L.plane * 8, st));
+    HIPCHK(c, hipMemsetAsync(c->bb.count, 0, MAX_COUNTS * 4, st));
+    HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, st));
     for (int k = 0; k < 3; k++) HIPCHK(c, launch_win_reset(c->bb.win, k, st));
     if (c->nsolid > 0) {
         // box of S^0 into the slots of "current" (0) and "previous" (2)
-        HIPCHK(c, launch_init_solid_box(g, c->body, c->bb.win, 0, 2, st));
+        HIPCHK(c, launch_init_solid_box(g, c->body, c->bb, 0, 2, st));
         HIPCHK(c, launch_init_tags(g, c->body, c->bb, 0, st));
         for (int l = 1; l <= g.layers; l++)
             HIPCHK(c, launch_layer_pass(g, c->bb, 0, 2, l, 1, c->bb.phi[0], c->bb.X[0],
                                         c->bb.Y[0], st));
         HIPCHK(c, launch_init_fill(g, c->body, c->bb, 0, st));
+        HIPCHK(c, hipMemsetAsync(c->bb.count, 0, MAX_COUNTS * 4, st));
     }
     HIPCHK(c, launch_init_populations(g, c->d.precision, c->body, c->bb.phi[0], c->bb.win, 0,
                                       d_u0, c->lat[1], c->lat[0], st));
@@ -538,7 +551,7 @@ int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
     out->max_u = h[10];
     for (int k = 0; k < LBRMT_H_COUNT; k++) out->health[k] = hc[k];
     if (hc[LBRMT_H_NONFINITE] || hc[LBRMT_H_DETJ_SOLID] || hc[LBRMT_H_EXTRAP_FAIL] ||
-        !std::isfinite(h[0]))
+        hc[LBRMT_H_LIST_OVERFLOW] || !std::isfinite(h[0]))
         return LBRMT_EUNSTABLE;
     return LBRMT_OK;
 }
@@ -631,6 +644,8 @@ int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
     HIPCHK(c, hipMemcpyAsync(c->bb.win, b + off[7], 3 * sizeof(Win), D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bb.health, b + off[7] + 3 * sizeof(Win),
                              LBRMT_H_COUNT * sizeof(unsigned), D2D, c->st));
+    HIPCHK(c, hipMemsetAsync(c->bb.count, 0, MAX_COUNTS * 4, c->st));
+    HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, c->st));
     c->inited = true;
     return LBRMT_OK;
 }
@@ -696,6 +711,41 @@ int lbrmt_kernel_time(lbrmt_ctx* c, const char* name, double* avg_ms, int64_t* l
     return LBRMT_EINVAL;
 }
 
+int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
+{
+    if (!c) return LBRMT_EINVAL;
+    switch (option) {
+    case LBRMT_OPT_OVERLAP:
+        if (value != 0 && value != 1) return LBRMT_EINVAL;
+        c->overlap = value != 0;
+        break;
+    case LBRMT_OPT_LB_VARIANT:
+        if (value < 0 || value >= lb_variant_count()) return LBRMT_EINVAL;
+        c->lb_variant = (int)value;
+        break;
+    default:
+        return LBRMT_EINVAL;
+    }
+    // the captured step graph bakes the launch configuration in
+    if (c->gexec) {
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    return LBRMT_OK;
+}
+
+int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
+{
+    if (!c || !value) return LBRMT_EINVAL;
+    switch (option) {
+    case LBRMT_OPT_OVERLAP: *value = c->overlap ? 1 : 0; return LBRMT_OK;
+    case LBRMT_OPT_LB_VARIANT: *value = c->lb_variant; return LBRMT_OK;
+    case LBRMT_OPT_LB_VARIANT_COUNT: *value = lb_variant_count(); return LBRMT_OK;
+    default: return LBRMT_EINVAL;
+    }
+}
+
 int lbrmt_band_nodes(lbrmt_ctx* c, int64_t* band_nodes, int64_t* window_nodes)
 {
     if (!c || !band_nodes || !window_nodes) return LBRMT_EINVAL;
@@ -728,6 +778,8 @@ int lbrmt_band_nodes(lbrmt_ctx* c, int64_t* band_nodes, int64_t* window_nodes)
         u3 = std::max(u3, b3);
     }
     // nodes of the lattice tiles the band update covers (whole tiles, clipped)
+    int LB_TX, LB_TY;
+    lb_variant_tile(c->lb_variant, &LB_TX, &LB_TY);
     const int x0 = u0 / LB_TX * LB_TX, x1 = std::min((u1 / LB_TX + 1) * LB_TX, c->g.nx) - 1;
     const int y0 = u2 / LB_TY * LB_TY, y1 = std::min((u3 / LB_TY + 1) * LB_TY, c->g.ny) - 1;
     *band_nodes = (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1);

@@ -10,13 +10,15 @@ namespace lbrmt {
 
 constexpr int NQ = 9;   // D2Q9 (Sec. 2.2, Table "d2q9")
 constexpr int PAD = 2;  // buffer layers of the reference-map grid (Sec. 3)
-constexpr int LB_TX = 64;  // lattice Boltzmann tile: 64 x 4 nodes, one thread each
-constexpr int LB_TY = 4;
 
-// Tag codes of the reference-map nodes during one step (int8 per node).
-constexpr int8_t TAG_NONE = -1;   // no reference map
-constexpr int8_t TAG_SOLID = 0;   // phi^n < 0, interior
-constexpr int8_t TAG_FAIL = 64;   // OR-ed onto a layer number when the fit failed
+// Tag codes of the reference-map nodes during one step (int32 per node).
+constexpr int TAG_NONE = -1;   // no reference map
+constexpr int TAG_SOLID = 0;   // phi^n < 0, interior
+constexpr int TAG_FAIL = 64;   // OR-ed onto a layer number when the fit failed
+
+// Blocks of the reductions that build a box with the last-block pattern.
+constexpr int BOX_BLOCKS = 512;
+constexpr int MAX_COUNTS = 64;  // list counters: one per layer 0..layers
 
 // Axis-aligned box of the interior solid nodes of one body (i0 > i1: empty).
 // The working window of a step is this box dilated by `layers` nodes.
@@ -50,7 +52,11 @@ struct BandBufs {
     double* X[2];         // reference map components, padded grid, double-buffered
     double* Y[2];
     double* phi[2];       // level set; +inf where no reference map
-    int8_t* tag;
+    int* tag;
+    int* list[2];         // node lists of consecutive layers (ping-pong), padded index
+    int* count;           // entries of the list of layer l, MAX_COUNTS counters
+    int* boxpart;         // per-block partial boxes, BOX_BLOCKS x 4
+    unsigned* ticket;     // arrival counter of the last-block reduction
     Win* win;             // ring of 3 boxes
     unsigned* health;
 };
@@ -134,10 +140,12 @@ __device__ __forceinline__ long long pidx(const GridP& g, int i, int j)
 // Every launcher enqueues on `st` and returns hipGetLastError().
 
 // lattice Boltzmann (k_lb.hip)
-hipError_t launch_lb(const GridP& g, int precision, const void* A, void* B, const double* fpx,
-                     const double* fpy, const double* fcx, const double* fcy, const double* drho,
-                     const Win* win, int wprev, int wcur, double fpo_x, double fpo_y, int part,
-                     unsigned* health, hipStream_t st);
+hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
+                     const double* fpx, const double* fpy, const double* fcx, const double* fcy,
+                     const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
+                     double fpo_y, int part, unsigned* health, hipStream_t st);
+int lb_variant_count();
+void lb_variant_tile(int v, int* tx, int* ty);
 hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
                                    const double* phi0, const Win* win, int wslot,
                                    const double* u0, void* tmp, void* A, hipStream_t st);
@@ -153,8 +161,8 @@ hipError_t launch_poke(const GridP& g, int precision, void* A, long long node, d
 
 // reference map (k_band.hip)
 hipError_t launch_win_reset(Win* win, int slot, hipStream_t st);
-hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, Win* win, int slot0, int slot1,
-                                 hipStream_t st);
+hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, const BandBufs& bb, int slot0,
+                                 int slot1, hipStream_t st);
 hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st);
 hipError_t launch_layer_pass(const GridP& g, const BandBufs& bb, int wslot, int wprev, int l,

@@ -20,8 +20,9 @@ LBRMT_OK, LBRMT_EINVAL, LBRMT_EWORKSPACE, LBRMT_EHIP, LBRMT_EUNSTABLE, LBRMT_ECA
     LBRMT_ESTATE = range(7)
 LBRMT_FP64, LBRMT_FP32 = 0, 1
 HEALTH_NAMES = ["advect_miss", "extrap_fail", "stress_miss", "detj", "detj_solid", "nonfinite",
-                "window_clip", "reserved"]
+                "window_clip", "list_overflow"]
 KERNEL_NAMES = ["advect", "extrap", "relabel", "force", "lb_bulk", "lb_band"]
+LBRMT_OPT_OVERLAP, LBRMT_OPT_LB_VARIANT, LBRMT_OPT_LB_VARIANT_COUNT = 0, 1, 2
 
 
 class lbrmt_grid_desc(ctypes.Structure):
@@ -117,6 +118,9 @@ def lib():
                                                  ctypes.POINTER(ctypes.c_double),
                                                  ctypes.POINTER(ctypes.c_int64)]),
             "lbrmt_band_nodes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64),
+                                                ctypes.POINTER(ctypes.c_int64)]),
+            "lbrmt_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
+            "lbrmt_get_option": (ctypes.c_int, [_vp, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_int64)]),
         }
         for name, (res, args) in sig.items():
@@ -279,6 +283,16 @@ def lbrmt_band_nodes(ctx):
     return b.value, w.value
 
 
+def lbrmt_set_option(ctx, option, value):
+    _check(lib().lbrmt_set_option(ctx, int(option), int(value)), "lbrmt_set_option", ctx)
+
+
+def lbrmt_get_option(ctx, option):
+    v = ctypes.c_int64(0)
+    _check(lib().lbrmt_get_option(ctx, int(option), ctypes.byref(v)), "lbrmt_get_option", ctx)
+    return v.value
+
+
 # ------------------------------------------------------------ convenience
 
 class Sim:
@@ -389,3 +403,9 @@ class Sim:
 
     def band_nodes(self):
         return lbrmt_band_nodes(self.ctx)
+
+    def set_option(self, option, value):
+        lbrmt_set_option(self.ctx, option, value)
+
+    def get_option(self, option):
+        return lbrmt_get_option(self.ctx, option)

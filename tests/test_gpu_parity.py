@@ -72,7 +72,7 @@ def test_cavity_disc_64_matches_oracle_over_1000_steps():
         done = n
         compare(sim, ref, what=f"cavity_disc_64 step {n}")
     d = sim.diag()
-    assert all(v == 0 for k, v in d["health"].items() if k != "reserved")
+    assert all(v == 0 for v in d["health"].values())
 
 
 def test_ragged_periodic_grid_with_density_contrast_and_gravity():
@@ -141,8 +141,12 @@ def test_diag_matches_oracle():
     d, r = sim.diag(), ref.diag()
     for k in ("mass", "centroid_x", "centroid_y", "max_u"):
         assert abs(d[k] - r[k]) <= 1e-11 * abs(r[k]), k
-    for k in ("mom_x", "mom_y", "disp_x", "disp_y"):
-        assert abs(d[k] - r[k]) <= 1e-9 * max(abs(r[k]), 1e-12), k
+    # momentum and mean displacement are sums of cancelling terms: bars scale
+    # with the magnitude of the terms (mass * max|u|, coordinates ~ nx)
+    for k in ("mom_x", "mom_y"):
+        assert abs(d[k] - r[k]) <= 1e-12 * r["mass"] * r["max_u"], k
+    for k in ("disp_x", "disp_y"):
+        assert abs(d[k] - r[k]) <= 1e-13 * 64, k
     assert d["n_solid"] == r["n_solid"] and d["n_band"] == r["n_band"]
 
 
@@ -190,3 +194,22 @@ def test_solid_smaller_than_a_node_spacing():
     sim.step(20)
     ref.step(20)
     compare(sim, ref, what="no solid nodes")
+
+
+def test_launch_options_give_bitwise_identical_results():
+    # every lattice tile shape and both stream arrangements compute the same
+    # node updates in the same arithmetic
+    cfg = workloads.cavity_disc_64()
+    base = _gpu(cfg).step(20)
+    want = _np(base.macro()) + _np(base.refmap())
+    nvar = base.get_option(2)
+    for ov in (0, 1):
+        for v in range(nvar):
+            s = _gpu(cfg)
+            s.set_option(0, ov)
+            s.set_option(1, v)
+            s.step(20)
+            got = _np(s.macro()) + _np(s.refmap())
+            for x, y in zip(want, got):
+                assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0)), \
+                    (ov, v)
