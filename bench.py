@@ -52,10 +52,15 @@ def traffic_from_profile(kernel, workload, precision):
     return float(t.group(1))
 
 
-def run_gpu(cfg, precision, steps, warmup, timing_steps):
+def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_variant=None):
     import torch
     from paper_2402_12696_amd import Sim
+    from paper_2402_12696_amd.lbrmt import LBRMT_OPT_LB_VARIANT, LBRMT_OPT_OVERLAP
     sim = Sim(device="cuda:0", precision=precision, **cfg).init()
+    if overlap is not None:
+        sim.set_option(LBRMT_OPT_OVERLAP, overlap)
+    if lb_variant is not None:
+        sim.set_option(LBRMT_OPT_LB_VARIANT, lb_variant)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -104,6 +109,10 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--overlap", type=int, default=None, choices=[0, 1],
+                    help="1: reference-map chain on a side stream (library default 0)")
+    ap.add_argument("--lb-variant", type=int, default=None,
+                    help="lattice tile variant (library default 5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -113,7 +122,7 @@ def main():
     cfg = _workload(args.workload)
     nodes = cfg["nx"] * cfg["ny"]
     ms, kt, band, window, diag = run_gpu(cfg, args.precision, args.steps, args.warmup,
-                                         args.timing_steps)
+                                         args.timing_steps, args.overlap, args.lb_variant)
     mlups = nodes / (ms * 1e-3) / 1e6
 
     bulk_ms, bulk_n = kt["lb_bulk"]
@@ -132,7 +141,8 @@ def main():
              "n_solid": diag["n_solid"], "n_band": diag["n_band"],
              "health": diag["health"]}
     if args.precision == "f64" and not args.no_f32:
-        ms32, kt32, _, _, d32 = run_gpu(cfg, "f32", args.steps, args.warmup, args.timing_steps)
+        ms32, kt32, _, _, d32 = run_gpu(cfg, "f32", args.steps, args.warmup, args.timing_steps,
+                                        args.overlap, args.lb_variant)
         extra["f32"] = {"ms_per_step": ms32, "mlups": nodes / (ms32 * 1e-3) / 1e6,
                         "speedup_vs_f64": ms / ms32,
                         "lb_bulk_avg_ms": kt32["lb_bulk"][0]}

@@ -184,18 +184,22 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
 
 /* Launch options of a context (host only; an option change drops the
  * captured step graph after synchronising the stream):
- *   LBRMT_OPT_OVERLAP     1 (default): the reference-map chain runs on an
+ *   LBRMT_OPT_OVERLAP     0 (default): one stream, the reference-map chain
+ *                         then one full lattice update; 1: the chain runs on an
  *                         internal stream while the lattice Boltzmann update of
- *                         the tiles away from the solid runs on the caller's;
- *                         0: one stream, chain then one full update.
+ *                         the tiles away from the solid runs on the caller's.
  *   LBRMT_OPT_LB_VARIANT  tile shape of the lattice Boltzmann update, 0 ..
- *                         LBRMT_OPT_LB_VARIANT_COUNT - 1 (results are bitwise
- *                         identical across variants; only speed differs).
+ *                         LBRMT_OPT_LB_VARIANT_COUNT - 1, default 5 (results are
+ *                         bitwise identical across variants; only speed differs).
+ *   LBRMT_OPT_GRAPH       1 (default): whole blocks of six steps replay one
+ *                         captured HIP graph; 0: every kernel is launched
+ *                         eagerly (results are bitwise identical).
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,
     LBRMT_OPT_LB_VARIANT = 1,
-    LBRMT_OPT_LB_VARIANT_COUNT = 2 /* read only */
+    LBRMT_OPT_LB_VARIANT_COUNT = 2, /* read only */
+    LBRMT_OPT_GRAPH = 3
 } lbrmt_option;
 int lbrmt_set_option(lbrmt_ctx* ctx, int32_t option, int64_t value);
 int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);

@@ -1,17 +1,22 @@
 // Reference-map ("band") kernels of the LBRMT step on gfx950: advection of xi
-// (Sec. 3.1), layer-by-layer least-squares extrapolation (Sec. 3.2), relabel
-// phi = phi0(xi), and the divergence of the blended half-edge solid stress
-// fed back as the LB force density (Sec. 3.3, Eq. (2_4_F_divs)).
+// (Sec. 3.1), the extrapolation zone and its layer-by-layer least-squares
+// extrapolation (Sec. 3.2), relabel phi = phi0(xi), and the divergence of the
+// blended half-edge solid stress fed back as the LB force density (Sec. 3.3,
+// Eq. (2_4_F_divs)).
 //
-// All of them work inside one rectangular window per body: the box of the
+// Every kernel works inside one rectangular window per body: the box of the
 // interior solid nodes dilated by the number of extrapolation layers, kept in
-// a device ring of three boxes (previous, current, next step) so no host
-// round trip is needed.  A node outside a window holds no reference map.
+// a device ring of three boxes (previous, current, next step) so no host round
+// trip is needed.  A node outside a window holds no reference map.
 //
-// These kernels make every discrete decision of the method (solid set, layer
-// membership, window growth of the fit, singular Jacobians); this file is
-// compiled without floating-point contraction so those decisions are taken in
-// plain IEEE double arithmetic.
+// One step runs: advect (tags: solid / none) -> two-pass Manhattan distance
+// transform (exact layer numbers and one node list per layer) -> one fit
+// kernel per layer -> relabel (per-block boxes) -> force (LDS-tiled half
+// edges; reduces the boxes).
+//
+// These kernels take every discrete decision of the method (solid set, layers,
+// window growth of the fit, singular Jacobians); this file is compiled without
+// floating-point contraction so they are taken in plain IEEE double arithmetic.
 #include "lbrmt_internal.h"
 
 namespace lbrmt {
@@ -47,6 +52,7 @@ __device__ __forceinline__ double node_coord(int i, int periodic, int n, double 
     return x;
 }
 
+// tags: TAG_NONE, TAG_SOLID, layer l (1..layers), or layer | TAG_FAIL
 __device__ __forceinline__ bool tag_valid_before(int t, int l)
 {
     // solid, or set by an earlier layer
@@ -58,7 +64,7 @@ __device__ __forceinline__ bool tag_set(int t)
     return t == TAG_SOLID || (t > 0 && t < TAG_FAIL);
 }
 
-// ---------------------------------------------------------------- wave / block helpers
+// ---------------------------------------------------------------- block helpers
 
 __device__ __forceinline__ int wave_min(int v)
 {
@@ -71,34 +77,10 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// Append the lanes with `flag` set to a device list of `cap` entries: one
-// atomic per wave.  Every lane of the wave must call it (it uses a ballot).
-// Entries beyond the capacity are dropped and counted in health[7].
-__device__ __forceinline__ void wave_append(bool flag, int value, int* list, int* count, int cap,
-                                            unsigned* health)
-{
-    const unsigned long long mask = __ballot(flag);
-    if (mask == 0ull) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(count, __popcll(mask));
-    base = __shfl(base, leader);
-    if (flag) {
-        const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
-        if (slot < cap) list[slot] = value;
-        else atomicAdd(&health[7], 1u);
-    }
-}
-
-// Box of the flagged nodes over the whole grid with the last-block pattern:
-// every block stores its partial box, and the block that arrives last reduces
-// the partials into `dst` (no waiting, one counter).  Called by all threads.
-__device__ void box_reduce(int i0, int i1, int j0, int j1, int* boxpart, unsigned* ticket,
-                           Win* dst0, Win* dst1, int* counts_to_clear)
+// box of the block's flagged nodes, stored as one partial per block
+__device__ void block_box(int i0, int i1, int j0, int j1, int* out4)
 {
     __shared__ int sb[4][16];
-    __shared__ bool last;
     i0 = wave_min(i0);
     i1 = wave_max(i1);
     j0 = wave_min(j0);
@@ -119,20 +101,21 @@ __device__ void box_reduce(int i0, int i1, int j0, int j1, int* boxpart, unsigne
             j0 = min(j0, sb[2][w]);
             j1 = max(j1, sb[3][w]);
         }
-        int* p = boxpart + 4 * blockIdx.x;
-        p[0] = i0;
-        p[1] = i1;
-        p[2] = j0;
-        p[3] = j1;
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+        out4[0] = i0;
+        out4[1] = i1;
+        out4[2] = j0;
+        out4[3] = j1;
     }
     __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// reduce n partial boxes into one window slot (called by a whole block)
+__device__ void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1)
+{
+    __shared__ int sb[4][16];
     int a0 = 0x3fffffff, a1 = -0x3fffffff, a2 = 0x3fffffff, a3 = -0x3fffffff;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
-        const volatile int* q = boxpart + 4 * k;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const volatile int* q = part + 4 * k;
         a0 = min(a0, q[0]);
         a1 = max(a1, q[1]);
         a2 = min(a2, q[2]);
@@ -142,7 +125,8 @@ __device__ void box_reduce(int i0, int i1, int j0, int j1, int* boxpart, unsigne
     a1 = wave_max(a1);
     a2 = wave_min(a2);
     a3 = wave_max(a3);
-    __syncthreads();
+    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int nw = (blockDim.x + 63) / 64;
     if (lane == 0) {
         sb[0][wid] = a0;
         sb[1][wid] = a1;
@@ -165,9 +149,22 @@ __device__ void box_reduce(int i0, int i1, int j0, int j1, int* boxpart, unsigne
         if (a0 > a1) r.i0 = 0x3fffffff, r.i1 = -0x3fffffff, r.j0 = 0x3fffffff, r.j1 = -0x3fffffff;
         *dst0 = r;
         if (dst1) *dst1 = r;
-        *ticket = 0u;
     }
-    if (counts_to_clear && threadIdx.x < MAX_COUNTS) counts_to_clear[threadIdx.x] = 0;
+    __syncthreads();
+}
+
+// true in exactly one block: the last to arrive (all blocks must call it)
+__device__ bool last_block(unsigned* ticket)
+{
+    __shared__ bool last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
 }
 
 // ---------------------------------------------------------------- window ring
@@ -214,7 +211,11 @@ __global__ __launch_bounds__(256) void k_init_solid_box(GridP g, BodyP b, int* b
             j1 = max(j1, j);
         }
     }
-    box_reduce(i0, i1, j0, j1, boxpart, ticket, &win[s0], &win[s1], nullptr);
+    block_box(i0, i1, j0, j1, boxpart + 4 * blockIdx.x);
+    if (last_block(ticket)) {
+        reduce_boxes(boxpart, gridDim.x, &win[s0], &win[s1]);
+        if (threadIdx.x == 0) *ticket = 0u;
+    }
 }
 
 hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, const BandBufs& bb, int slot0,
@@ -225,49 +226,30 @@ hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, const BandBufs&
     return hipGetLastError();
 }
 
-// initial tags over the window; solid nodes with a non-solid 4-neighbour
-// start the list of layer 0
-__global__ __launch_bounds__(256) void k_init_tags(GridP g, BodyP b, int* tag, const Win* win,
-                                                   int wslot, int* list0, int* count, int cap,
-                                                   unsigned* health)
+// initial tags over the window (solid / none)
+__global__ __launch_bounds__(256) void k_init_tags(GridP g, BodyP b, int8_t* tag, const Win* win,
+                                                   int wslot)
 {
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
-    const long long iters = (total + stride - 1) / stride;
-    for (long long it = 0; it < iters; it++) {
-        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
-        bool boundary = false;
-        int kk = 0;
-        if (e < total) {
-            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-            const long long k = pidx(g, i, j);
-            kk = (int)k;
-            const bool solid = init_solid(g, b, i, j);
-            tag[k] = solid ? TAG_SOLID : TAG_NONE;
-            if (solid) {
-                int ci[4] = {i + 1, i - 1, i, i}, cj[4] = {j, j, j + 1, j - 1};
-                for (int d = 0; d < 4; d++) {
-                    int a = ci[d], c = cj[d];
-                    if (canon(g, a, c) && !init_solid(g, b, a, c)) boundary = true;
-                }
-            }
-        }
-        wave_append(boundary, kk, list0, count, cap, health);
+    const long long total = (long long)w * h;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+        tag[pidx(g, i, j)] = init_solid(g, b, i, j) ? TAG_SOLID : TAG_NONE;
     }
 }
 
 hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st)
 {
-    k_init_tags<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, bb.list[0], bb.count,
-                                      (int)g.pplane, bb.health);
+    k_init_tags<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot);
     return hipGetLastError();
 }
 
 // xi_0 = x on the solid and its extrapolation zone, phi = phi0(x) (Alg. 1 init)
-__global__ void k_init_fill(GridP g, BodyP b, const int* tag, const Win* win, int wslot,
+__global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win, int wslot,
                             double* X, double* Y, double* phi)
 {
     const Rect W = window_of(win, wslot, g);
@@ -300,42 +282,6 @@ hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, 
 
 // ---------------------------------------------------------------- advection
 
-// pull-gather of the nine populations of interior node (i, j) and the
-// half-force velocity of Eq. (2_2_lbm_moments_force)
-template <typename S>
-__device__ void node_velocity(const GridP& g, const S* __restrict__ A, int i, int j, double Fx,
-                              double Fy, double& ux, double& uy)
-{
-    const long long P = g.plane;
-    const bool bw = !g.px && i == 0, be = !g.px && i == g.nx - 1;
-    const bool bs = !g.py && j == 0, bn = !g.py && j == g.ny - 1;
-    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
-    im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
-    ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
-    jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
-    jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
-    const long long r0 = (long long)j * g.pitch, rm = (long long)jm * g.pitch,
-                    rp = (long long)jp * g.pitch, n = r0 + i;
-    double f[NQ];
-    f[0] = A[n];
-    f[1] = bw ? A[3 * P + n] : A[1 * P + r0 + im];
-    f[2] = bs ? A[4 * P + n] : A[2 * P + rm + i];
-    f[3] = be ? A[1 * P + n] : A[3 * P + r0 + ip];
-    f[4] = bn ? A[2 * P + n] : A[4 * P + rp + i];
-    f[5] = (bw || bs) ? A[7 * P + n] : A[5 * P + rm + im];
-    f[6] = (be || bs) ? A[8 * P + n] : A[6 * P + rm + ip];
-    f[7] = (be || bn) ? A[5 * P + n] : A[7 * P + rp + ip];
-    f[8] = (bw || bn) ? A[6 * P + n] : A[8 * P + rp + im];
-    if (sizeof(S) == 4) {
-        const double wq[NQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
-                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
-        for (int k = 0; k < NQ; k++) f[k] += wq[k] * g.rho_f;
-    }
-    const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    ux = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (2.0 * rho);
-    uy = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (2.0 * rho);
-}
-
 // reference-map node (i, j) of step n: canonical index, or -1 if it holds no
 // value (outside the domain or outside the window D where xi^n was written)
 __device__ __forceinline__ long long ref_index(const GridP& g, const Rect& D, int i, int j)
@@ -345,7 +291,7 @@ __device__ __forceinline__ long long ref_index(const GridP& g, const Rect& D, in
 }
 
 // one-sided second-order upwind derivative of Eq. (3_1_eno) from preloaded
-// stencil values: p1/p2 are the nodes one and two steps upwind
+// stencil values (m1, m2: one and two nodes behind; p1, p2: ahead)
 __device__ __forceinline__ bool upwind_d(double vel, double X0, double Y0, bool okm1, bool okm2,
                                          double Xm1, double Ym1, double Xm2, double Ym2,
                                          bool okp1, bool okp2, double Xp1, double Yp1,
@@ -365,95 +311,101 @@ __device__ __forceinline__ bool upwind_d(double vel, double X0, double Y0, bool 
     return true;
 }
 
-// Eq. (3_1_refmap_adv) on the solid nodes S^n = {interior, phi^n < 0}.  Also
-// resets the step's tags over the window, lists the solid nodes that touch a
-// non-solid node (layer 0 of the extrapolation), and resets the ring slot that
-// relabel fills with the box of S^{n+1}.  All stencil loads of a node are
-// issued together.
+// Eq. (3_1_refmap_adv) on the solid nodes S^n = {interior, phi^n < 0}, plus
+// the step's tags (solid / none) over the window and the cleared tile flags.
+// Every load of a node (its level set, the eight upwind stencil nodes, the
+// nine populations and the previous force) is issued before any is used;
+// addresses of absent nodes are clamped to the node itself.
 template <typename S>
 __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A,
                                                 const double* __restrict__ fpx,
-                                                const double* __restrict__ fpy, double fpo_x,
-                                                double fpo_y, const double* __restrict__ X,
+                                                const double* __restrict__ fpy,
+                                                const double* __restrict__ X,
                                                 const double* __restrict__ Y,
                                                 const double* __restrict__ phi, double* X1,
-                                                double* Y1, int* tag, int* list0, int* count,
-                                                Win* win, int wprev, int wcur, int wnext,
+                                                double* Y1, int8_t* tag,
+                                                const Win* __restrict__ win, int wprev, int wcur,
                                                 unsigned* health)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        win[wnext].i0 = 0x3fffffff;
-        win[wnext].i1 = -0x3fffffff;
-        win[wnext].j0 = 0x3fffffff;
-        win[wnext].j1 = -0x3fffffff;
-    }
     const Rect W = window_of(win, wcur, g);
     if (!W.ok) return;
     const Rect D = window_of(win, wprev, g);
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
-    const long long iters = (total + stride - 1) / stride;
-    for (long long it = 0; it < iters; it++) {
-        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
-        bool boundary = false;
-        int kk = 0;
-        if (e < total) {
-            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-            const long long k = pidx(g, i, j);
-            kk = (int)k;
-            const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-            const bool solid = interior && D.has(i, j) && phi[k] < 0.0;
-            tag[k] = solid ? TAG_SOLID : TAG_NONE;
-            if (solid) {
-                // stencil nodes: x-1, x-2, x+1, x+2, y-1, y-2, y+1, y+2
-                const int di[8] = {-1, -2, 1, 2, 0, 0, 0, 0};
-                const int dj[8] = {0, 0, 0, 0, -1, -2, 1, 2};
-                long long ks[8];
-                double ps[8], xs[8], ys[8];
+    const long long total = (long long)w * h;
+    const long long P = g.plane;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+        const long long k = pidx(g, i, j);
+        const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+        // stencil nodes: x-1, x-2, x+1, x+2, y-1, y-2, y+1, y+2
+        const int di[8] = {-1, -2, 1, 2, 0, 0, 0, 0};
+        const int dj[8] = {0, 0, 0, 0, -1, -2, 1, 2};
+        long long ks[8];
 #pragma unroll
-                for (int q = 0; q < 8; q++) ks[q] = ref_index(g, D, i + di[q], j + dj[q]);
+        for (int q = 0; q < 8; q++) ks[q] = ref_index(g, D, i + di[q], j + dj[q]);
+        // populations of the pull gather (clamped to the interior)
+        const int ic = min(max(i, 0), g.nx - 1), jc = min(max(j, 0), g.ny - 1);
+        const bool bw = !g.px && ic == 0, be = !g.px && ic == g.nx - 1;
+        const bool bs = !g.py && jc == 0, bn = !g.py && jc == g.ny - 1;
+        int im = ic - 1, ip = ic + 1, jm = jc - 1, jp = jc + 1;
+        im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
+        ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
+        jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
+        jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
+        const long long r0 = (long long)jc * g.pitch, rm = (long long)jm * g.pitch,
+                        rp = (long long)jp * g.pitch, n = r0 + ic;
+        // ---- all loads
+        const double p0 = phi[k], X0 = X[k], Y0 = Y[k];
+        double ps[8], xs[8], ys[8];
 #pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    const long long kq = ks[q] >= 0 ? ks[q] : k;
-                    ps[q] = ks[q] >= 0 ? phi[kq] : INFINITY;
-                    xs[q] = X[kq];
-                    ys[q] = Y[kq];
-                }
-                const long long n = (long long)j * g.pitch + i;
-                double u, v;
-                node_velocity<S>(g, A, i, j, fpx[n], fpy[n], u, v);
-                bool okq[8];
-#pragma unroll
-                for (int q = 0; q < 8; q++) okq[q] = ps[q] < INFINITY;
-                // a 4-neighbour outside S makes this node a layer-0 node
-                const int nb4[4] = {0, 2, 4, 6};
-                for (int d = 0; d < 4; d++) {
-                    const int q = nb4[d];
-                    int a = i + di[q], c = j + dj[q];
-                    if (!canon(g, a, c)) continue;
-                    const bool nint = a >= 0 && a < g.nx && c >= 0 && c < g.ny;
-                    if (!(nint && ks[q] >= 0 && ps[q] < 0.0)) boundary = true;
-                }
-                const double X0 = X[k], Y0 = Y[k];
-                double dXx, dYx, dXy, dYy;
-                const bool okx = upwind_d(u, X0, Y0, okq[0], okq[1], xs[0], ys[0], xs[1], ys[1],
-                                          okq[2], okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
-                const bool oky = upwind_d(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5],
-                                          okq[6], okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
-                if (!okx || !oky) {
-                    atomicAdd(&health[0], 1u);
-                    X1[k] = X0;
-                    Y1[k] = Y0;
-                } else {
-                    X1[k] = X0 - (u * dXx + v * dXy);
-                    Y1[k] = Y0 - (u * dYx + v * dYy);
-                }
-            }
+        for (int q = 0; q < 8; q++) {
+            const long long kq = ks[q] >= 0 ? ks[q] : k;
+            ps[q] = phi[kq];
+            xs[q] = X[kq];
+            ys[q] = Y[kq];
         }
-        wave_append(boundary, kk, list0, count, (int)g.pplane, health);
+        double f[NQ];
+        f[0] = A[n];
+        f[1] = bw ? A[3 * P + n] : A[1 * P + r0 + im];
+        f[2] = bs ? A[4 * P + n] : A[2 * P + rm + ic];
+        f[3] = be ? A[1 * P + n] : A[3 * P + r0 + ip];
+        f[4] = bn ? A[2 * P + n] : A[4 * P + rp + ic];
+        f[5] = (bw || bs) ? A[7 * P + n] : A[5 * P + rm + im];
+        f[6] = (be || bs) ? A[8 * P + n] : A[6 * P + rm + ip];
+        f[7] = (be || bn) ? A[5 * P + n] : A[7 * P + rp + ip];
+        f[8] = (bw || bn) ? A[6 * P + n] : A[8 * P + rp + im];
+        const double Fx = fpx[n], Fy = fpy[n];
+        // ---- decisions and arithmetic
+        const bool solid = interior && D.has(i, j) && p0 < 0.0;
+        tag[k] = solid ? TAG_SOLID : TAG_NONE;
+        if (!solid) continue;
+        if (sizeof(S) == 4) {
+            const double wq[NQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+            for (int q = 0; q < NQ; q++) f[q] += wq[q] * g.rho_f;
+        }
+        // half-force velocity of Eq. (2_2_lbm_moments_force)
+        const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        const double u = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (2.0 * rho);
+        const double v = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (2.0 * rho);
+        bool okq[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) okq[q] = ks[q] >= 0 && ps[q] < INFINITY;
+        double dXx, dYx, dXy, dYy;
+        const bool okx = upwind_d(u, X0, Y0, okq[0], okq[1], xs[0], ys[0], xs[1], ys[1], okq[2],
+                                  okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
+        const bool oky = upwind_d(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5], okq[6],
+                                  okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
+        if (!okx || !oky) {
+            atomicAdd(&health[0], 1u);
+            X1[k] = X0;
+            Y1[k] = Y0;
+        } else {
+            X1[k] = X0 - (u * dXx + v * dXy);
+            Y1[k] = Y0 - (u * dYx + v * dYy);
+        }
     }
-    (void)fpo_x;
-    (void)fpo_y;
 }
 
 hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
@@ -461,18 +413,117 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
                          double fpo_x, double fpo_y, hipStream_t st)
 {
     (void)b;
+    (void)fpo_x;
+    (void)fpo_y;
     if (precision == 0)
-        k_advect<double><<<2048, 256, 0, st>>>(g, (const double*)A, fpx, fpy, fpo_x, fpo_y,
-                                               bb.X[s.cur], bb.Y[s.cur], bb.phi[s.cur],
-                                               bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.list[0],
-                                               bb.count, bb.win, s.wprev, s.wcur, s.wnext,
-                                               bb.health);
+        k_advect<double><<<2048, 256, 0, st>>>(g, (const double*)A, fpx, fpy, bb.X[s.cur],
+                                               bb.Y[s.cur], bb.phi[s.cur], bb.X[s.nxt],
+                                               bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
+                                               s.wcur, bb.health);
     else
-        k_advect<float><<<2048, 256, 0, st>>>(g, (const float*)A, fpx, fpy, fpo_x, fpo_y,
-                                              bb.X[s.cur], bb.Y[s.cur], bb.phi[s.cur],
-                                              bb.X[s.nxt], bb.Y[s.nxt], bb.tag, bb.list[0],
-                                              bb.count, bb.win, s.wprev, s.wcur, s.wnext,
-                                              bb.health);
+        k_advect<float><<<2048, 256, 0, st>>>(g, (const float*)A, fpx, fpy, bb.X[s.cur],
+                                              bb.Y[s.cur], bb.phi[s.cur], bb.X[s.nxt],
+                                              bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
+                                              s.wcur, bb.health);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- layers
+
+// Layers of Sec. 3.2: layer 1 = non-solid nodes 4-adjacent to the solid,
+// layer l = unmarked nodes 4-adjacent to layer l-1.  Inside a rectangle this
+// is the Manhattan distance to the solid set, computed here exactly in two
+// separable passes: per column, the distance to the nearest solid node of the
+// column (capped at layers + 1); per row, min over |e| of |e| + that distance.
+__global__ __launch_bounds__(256) void k_dt_cols(GridP g, const Win* __restrict__ win, int wslot,
+                                                 const int8_t* __restrict__ tag, int8_t* gcol)
+{
+    const Rect W = window_of(win, wslot, g);
+    if (!W.ok) return;
+    const int L = g.layers;
+    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+        int best = L + 1;
+        for (int d = -L; d <= L; d++) {
+            const int jj = j + d;
+            const bool in = jj >= W.j0 && jj <= W.j1;
+            const int8_t t = tag[pidx(g, i, in ? jj : j)];
+            if (in && t == TAG_SOLID) best = min(best, abs(d));
+        }
+        gcol[pidx(g, i, j)] = (int8_t)best;
+    }
+}
+
+// Row pass of the distance transform: exact layer numbers (Manhattan distance
+// to S^{n+1}, up to the layer count) and, per block, one list of the zone
+// nodes of each layer.  A block counts its nodes in LDS and writes its own
+// segment, so no global atomics are needed; the order inside a segment does
+// not matter since targets of one layer are independent.
+__global__ __launch_bounds__(256) void k_dt_rows(GridP g, const Win* __restrict__ win, int wslot,
+                                                 int8_t* tag, const int8_t* __restrict__ gcol,
+                                                 int* lists, int* bcount, unsigned* health)
+{
+    __shared__ int cnt[MAX_LAYERS + 1];
+    if (threadIdx.x <= MAX_LAYERS) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const Rect W = window_of(win, wslot, g);
+    const int L = g.layers;
+    const long long seg = dt_seg(g.pplane), lstride = dt_lstride(g.pplane);
+    int* mylists = lists + (long long)blockIdx.x * seg;
+    if (W.ok) {
+        const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+        const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
+        const long long iters = (total + stride - 1) / stride;
+        const int lane = __lane_id();
+        for (long long it = 0; it < iters; it++) {
+            const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
+            int lay = 0;
+            int k = 0;
+            if (e < total) {
+                const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+                k = (int)pidx(g, i, j);
+                if (tag[k] != TAG_SOLID) {
+                    int best = 2 * L + 2;
+                    for (int d = -L; d <= L; d++) {
+                        const int ii = i + d;
+                        const bool in = ii >= W.i0 && ii <= W.i1;
+                        const int gv = gcol[pidx(g, in ? ii : i, j)];
+                        if (in) best = min(best, abs(d) + gv);
+                    }
+                    if (best <= L) {
+                        tag[k] = (int8_t)best;
+                        lay = best;
+                    }
+                }
+            }
+            // one LDS atomic per wave and layer present in it
+            for (int l = 1; l <= L; l++) {
+                const unsigned long long mask = __ballot(lay == l);
+                if (mask == 0ull) continue;
+                const int leader = __ffsll((long long)mask) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&cnt[l], __popcll(mask));
+                base = __shfl(base, leader);
+                const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+                if (lay == l) {
+                    if (slot < seg) mylists[l * lstride + slot] = k;
+                    else atomicAdd(&health[7], 1u);  // cannot happen: seg covers a block's nodes
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= MAX_LAYERS)
+        bcount[blockIdx.x * (MAX_LAYERS + 1) + threadIdx.x] = (int)min((long long)cnt[threadIdx.x], seg);
+}
+
+hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStream_t st)
+{
+    k_dt_cols<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol);
+    k_dt_rows<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol, bb.lists, bb.bcount,
+                                         bb.health);
     return hipGetLastError();
 }
 
@@ -528,68 +579,41 @@ struct Fit {
     }
 };
 
-// Sec. 3.2 steps (i)-(iii) for target (i, j) of layer l: scan windows of
-// half-width r = 2, 3, ... r_max, count the valid nodes (solid, or set in an
-// earlier layer), fit xi = A x + B y + C by weighted least squares in
-// coordinates centred at the target and take the intercept C.  The r = 2 scan
-// loads all 25 tags and then all valid maps at once; wider scans are rare and
-// use a plain loop.  Nodes are visited row by row in both, as in the oracle.
-__device__ bool extrapolate_target(const GridP& g, const Rect& W, const Rect& D, int l, int i,
-                                   int j, long long kt, const int* tag, const double* phin,
+// outward normal of phi^n at a target from its four neighbours (e, w, n, s),
+// used by the weights of layers 1 and 2
+__device__ __forceinline__ bool normal_from(double pe, double pw, double pn, double ps,
+                                            double& nxh, double& nyh)
+{
+    if (!(pe < INFINITY && pw < INFINITY && pn < INFINITY && ps < INFINITY)) return false;
+    const double gx = (pe - pw) / 2.0;
+    const double gy = (pn - ps) / 2.0;
+    const double gn = sqrt(gx * gx + gy * gy);
+    if (!(gn > 0.0)) return false;
+    nxh = gx / gn;
+    nyh = gy / gn;
+    return true;
+}
+
+// Sec. 3.2 steps (i)-(iii) for target (i, j) of layer l from global memory:
+// scan windows of half-width r = r0 .. r_max, count the valid nodes (solid, or
+// set in an earlier layer), fit xi = A x + B y + C by weighted least squares in
+// coordinates centred at the target and take C.  Nodes are visited row by row.
+__device__ bool extrapolate_global(const GridP& g, const Rect& W, const Rect& D, int l, int i,
+                                   int j, int r0, const int8_t* tag, const double* phin,
                                    const double* X1, const double* Y1, double& xo, double& yo)
 {
     bool use_n = false;
     double nxh = 0.0, nyh = 0.0;
     if (l <= 2) {
         const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
-        long long kq[4];
         double pv[4];
-#pragma unroll
-        for (int d = 0; d < 4; d++) kq[d] = ref_index(g, D, i + di[d], j + dj[d]);
-#pragma unroll
-        for (int d = 0; d < 4; d++) pv[d] = kq[d] >= 0 ? phin[kq[d]] : INFINITY;
-        if (pv[0] < INFINITY && pv[1] < INFINITY && pv[2] < INFINITY && pv[3] < INFINITY) {
-            const double gx = (pv[0] - pv[1]) / 2.0;
-            const double gy = (pv[2] - pv[3]) / 2.0;
-            const double gn = sqrt(gx * gx + gy * gy);
-            if (gn > 0.0) {
-                nxh = gx / gn;
-                nyh = gy / gn;
-                use_n = true;
-            }
+        for (int d = 0; d < 4; d++) {
+            const long long kq = ref_index(g, D, i + di[d], j + dj[d]);
+            pv[d] = kq >= 0 ? phin[kq] : INFINITY;
         }
+        use_n = normal_from(pv[0], pv[1], pv[2], pv[3], nxh, nyh);
     }
-    {
-        long long kk[25];
-        int tg[25];
-#pragma unroll
-        for (int q = 0; q < 25; q++) {
-            int ci = i + q % 5 - 2, cj = j + q / 5 - 2;
-            kk[q] = (canon(g, ci, cj) && W.has(ci, cj)) ? pidx(g, ci, cj) : -1;
-        }
-#pragma unroll
-        for (int q = 0; q < 25; q++) tg[q] = tag[kk[q] >= 0 ? kk[q] : kt];
-        int count = 0;
-#pragma unroll
-        for (int q = 0; q < 25; q++) count += (kk[q] >= 0 && tag_valid_before(tg[q], l)) ? 1 : 0;
-        if (count >= 3) {
-            double xv[25], yv[25];
-#pragma unroll
-            for (int q = 0; q < 25; q++) {
-                const long long kq = (kk[q] >= 0 && tag_valid_before(tg[q], l)) ? kk[q] : kt;
-                xv[q] = X1[kq];
-                yv[q] = Y1[kq];
-            }
-            Fit f;
-            f.zero();
-#pragma unroll
-            for (int q = 0; q < 25; q++)
-                if (kk[q] >= 0 && tag_valid_before(tg[q], l))
-                    f.add(q % 5 - 2, q / 5 - 2, use_n && l <= 2, nxh, nyh, xv[q], yv[q]);
-            if (f.solve(g.det_rel, xo, yo)) return true;
-        }
-    }
-    for (int r = 3; r <= g.r_max; r++) {
+    for (int r = r0; r <= g.r_max; r++) {
         int count = 0;
         for (int b = -r; b <= r; b++)
             for (int a = -r; a <= r; a++) {
@@ -606,78 +630,149 @@ __device__ bool extrapolate_target(const GridP& g, const Rect& W, const Rect& D,
                 if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
                 const long long k = pidx(g, ci, cj);
                 if (!tag_valid_before(tag[k], l)) continue;
-                f.add(a, b, use_n && l <= 2, nxh, nyh, X1[k], Y1[k]);
+                f.add(a, b, use_n, nxh, nyh, X1[k], Y1[k]);
             }
         if (f.solve(g.det_rel, xo, yo)) return true;
     }
     return false;
 }
 
-// Layer l of Sec. 3.2: the 4-neighbours of the layer-(l-1) nodes that hold no
-// tag yet form layer l.  Each is claimed by exactly one thread (atomic CAS on
-// its tag), extrapolated at once unless mark_only (valid nodes come only from
-// earlier layers, so targets of one layer never read each other) and appended
-// to the list of layer l.
-__global__ __launch_bounds__(256) void k_layer(GridP g, const Win* __restrict__ win, int wcur,
-                                               int wprev, int l, int mark_only, int* tag,
-                                               const int* __restrict__ lin, const int* cin,
-                                               int* lout, int* cout,
-                                               const double* __restrict__ phin, double* X1,
-                                               double* Y1, unsigned* health)
+// sum over the FIT_LANES lanes of a group; the butterfly gives every lane the
+// same bits since each addition sees the same two operands in either order
+__device__ __forceinline__ double group_sum(double v)
 {
+#pragma unroll
+    for (int m = FIT_LANES / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, FIT_LANES);
+    return v;
+}
+__device__ __forceinline__ int group_sum(int v)
+{
+#pragma unroll
+    for (int m = FIT_LANES / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, FIT_LANES);
+    return v;
+}
+
+// One layer of Sec. 3.2.  Block b takes the layer-l nodes that block b of the
+// distance transform listed; each target is fitted by a group of FIT_LANES
+// lanes that share the scan-window nodes (each lane loads its share at once),
+// and the sums of the normal equations are reduced across the group.  Scan
+// windows grow from r = 2 to r_max until they hold three valid nodes and a
+// well-posed fit.  Valid nodes come only from earlier layers, so targets of
+// one layer never read each other.
+__global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restrict__ win,
+                                                   int wcur, int wprev, int l, int8_t* tag,
+                                                   const int* __restrict__ lists,
+                                                   const int* __restrict__ bcount,
+                                                   const double* __restrict__ phin, double* X1,
+                                                   double* Y1, unsigned* health)
+{
+    constexpr int PER = 4;  // window nodes per lane and pass: 25 of r = 2 in one pass
     const Rect W = window_of(win, wcur, g);
-    if (!W.ok) return;
     const Rect D = window_of(win, wprev, g);
-    const long long total = 4ll * min(*cin, (int)g.pplane);
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long iters = (total + stride - 1) / stride;
-    const int ddi[4] = {1, -1, 0, 0}, ddj[4] = {0, 0, 1, -1};
-    for (long long it = 0; it < iters; it++) {
-        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
-        bool claimed = false;
-        int kt = 0;
-        if (e < total) {
-            const int k0 = lin[e >> 2];
-            const int d = (int)(e & 3);
-            int ni = k0 % g.pp - PAD + ddi[d], nj = k0 / g.pp - PAD + ddj[d];
-            if (canon(g, ni, nj) && W.has(ni, nj)) {
-                kt = (int)pidx(g, ni, nj);
-                if (tag[kt] == TAG_NONE) claimed = atomicCAS(&tag[kt], TAG_NONE, l) == TAG_NONE;
+    const int n = bcount[blockIdx.x * (MAX_LAYERS + 1) + l];
+    if (n == 0 || !W.ok) return;
+    const int* list = lists + l * dt_lstride(g.pplane) + blockIdx.x * dt_seg(g.pplane);
+    const int sub = threadIdx.x % FIT_LANES;
+    const int groups = blockDim.x / FIT_LANES;
+    // all lanes of a group run the same trip counts, so shuffles see full groups
+    for (int t = threadIdx.x / FIT_LANES; t < n; t += groups) {
+        const int kt = list[t];
+        const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
+        // outward normal of phi^n at the target (layers 1, 2): lanes 0..3
+        // load the four neighbours
+        double nxh = 0.0, nyh = 0.0;
+        bool use_n = false;
+        if (l <= 2) {
+            double p = INFINITY;
+            if (sub < 4) {
+                const int di = sub == 0 ? 1 : sub == 1 ? -1 : 0;
+                const int dj = sub == 2 ? 1 : sub == 3 ? -1 : 0;
+                const long long kq = ref_index(g, D, i + di, j + dj);
+                if (kq >= 0) p = phin[kq];
             }
-            if (claimed && !mark_only) {
-                double xo, yo;
-                if (extrapolate_target(g, W, D, l, ni, nj, kt, tag, phin, X1, Y1, xo, yo)) {
-                    X1[kt] = xo;
-                    Y1[kt] = yo;
-                } else {
-                    tag[kt] = l | TAG_FAIL;
-                    atomicAdd(&health[1], 1u);
+            const double pe = __shfl(p, 0, FIT_LANES), pw = __shfl(p, 1, FIT_LANES);
+            const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
+            use_n = normal_from(pe, pw, pn, ps, nxh, nyh);
+        }
+        bool done = false;
+        double xo = 0.0, yo = 0.0;
+        for (int r = 2; r <= g.r_max && !done; r++) {
+            const int side = 2 * r + 1, nq = side * side;
+            Fit f;
+            f.zero();
+            int count = 0;
+            for (int q0 = 0; q0 < nq; q0 += PER * FIT_LANES) {
+                long long kk[PER];
+                int tk[PER];
+                double xv[PER], yv[PER];
+#pragma unroll
+                for (int u = 0; u < PER; u++) {
+                    const int q = q0 + sub + u * FIT_LANES;
+                    int ci = i + q % side - r, cj = j + q / side - r;
+                    kk[u] = (q < nq && canon(g, ci, cj) && W.has(ci, cj)) ? pidx(g, ci, cj) : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < PER; u++) {
+                    const long long k = kk[u] >= 0 ? kk[u] : kt;
+                    tk[u] = tag[k];
+                    xv[u] = X1[k];
+                    yv[u] = Y1[k];
+                }
+#pragma unroll
+                for (int u = 0; u < PER; u++) {
+                    if (kk[u] < 0 || !tag_valid_before(tk[u], l)) continue;
+                    const int q = q0 + sub + u * FIT_LANES;
+                    count++;
+                    f.add(q % side - r, q / side - r, use_n, nxh, nyh, xv[u], yv[u]);
                 }
             }
+            count = group_sum(count);
+            if (count < 3) continue;
+            f.M00 = group_sum(f.M00);
+            f.M01 = group_sum(f.M01);
+            f.M02 = group_sum(f.M02);
+            f.M11 = group_sum(f.M11);
+            f.M12 = group_sum(f.M12);
+            f.M22 = group_sum(f.M22);
+            f.bX0 = group_sum(f.bX0);
+            f.bX1 = group_sum(f.bX1);
+            f.bX2 = group_sum(f.bX2);
+            f.bY0 = group_sum(f.bY0);
+            f.bY1 = group_sum(f.bY1);
+            f.bY2 = group_sum(f.bY2);
+            done = f.solve(g.det_rel, xo, yo);
         }
-        wave_append(claimed, kt, lout, cout, (int)g.pplane, health);
+        if (sub == 0) {
+            if (done) {
+                X1[kt] = xo;
+                Y1[kt] = yo;
+            } else {
+                tag[kt] = (int8_t)(l | TAG_FAIL);
+                atomicAdd(&health[1], 1u);
+            }
+        }
     }
 }
 
-hipError_t launch_layer_pass(const GridP& g, const BandBufs& bb, int wslot, int wprev, int l,
-                             int mark_only, const double* phin, double* X1, double* Y1,
-                             hipStream_t st)
+hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
+                              hipStream_t st)
 {
-    k_layer<<<256, 256, 0, st>>>(g, bb.win, wslot, wprev, l, mark_only, bb.tag,
-                                 bb.list[(l - 1) & 1], bb.count + (l - 1), bb.list[l & 1],
-                                 bb.count + l, phin, X1, Y1, bb.health);
+    for (int l = 1; l <= g.layers; l++)
+        k_layer_fit<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, s.wcur, s.wprev, l, bb.tag, bb.lists,
+                                               bb.bcount, bb.phi[s.cur], bb.X[s.nxt],
+                                               bb.Y[s.nxt], bb.health);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- relabel
 
 // phi^{n+1} = phi0(xi^{n+1}) on every node holding a reference map (Alg. 1);
-// box of the new interior solid set into the next ring slot; clears the list
-// counters for the next step
-__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int* __restrict__ tag,
-                                                 Win* win, int wcur, int wnext, double* X1,
-                                                 double* Y1, double* phi1, int* boxpart,
-                                                 unsigned* ticket, int* count)
+// one partial box of the new interior solid set per block (reduced by the
+// force kernel into the next ring slot)
+__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t* __restrict__ tag,
+                                                 const Win* __restrict__ win, int wcur,
+                                                 double* X1, double* Y1, double* phi1,
+                                                 int* boxpart)
 {
     const Rect W = window_of(win, wcur, g);
     int i0 = 0x3fffffff, i1 = -0x3fffffff, j0 = 0x3fffffff, j1 = -0x3fffffff;
@@ -688,8 +783,10 @@ __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int* __
              e += (long long)gridDim.x * blockDim.x) {
             const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
             const long long k = pidx(g, i, j);
-            if (tag_set(tag[k])) {
-                const double p = shape_phi(b, X1[k], Y1[k]);
+            const int8_t tv = tag[k];
+            const double xv = X1[k], yv = Y1[k];
+            if (tag_set(tv)) {
+                const double p = shape_phi(b, xv, yv);
                 phi1[k] = p;
                 if (p < 0.0 && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
                     i0 = min(i0, i);
@@ -704,15 +801,14 @@ __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int* __
             }
         }
     }
-    box_reduce(i0, i1, j0, j1, boxpart, ticket, &win[wnext], nullptr, count);
+    block_box(i0, i1, j0, j1, boxpart + 4 * blockIdx.x);
 }
 
 hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                           hipStream_t st)
 {
-    k_relabel<<<BOX_BLOCKS, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur, s.wnext, bb.X[s.nxt],
-                                          bb.Y[s.nxt], bb.phi[s.nxt], bb.boxpart, bb.ticket,
-                                          bb.count);
+    k_relabel<<<RELABEL_BLOCKS, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur, bb.X[s.nxt],
+                                              bb.Y[s.nxt], bb.phi[s.nxt], bb.boxpart);
     return hipGetLastError();
 }
 
@@ -722,7 +818,7 @@ constexpr int FTX = 32, FTY = 8;
 constexpr int SX = FTX + 2, SY = FTY + 2;
 
 // Blended stress (1 - H(phi_e)) tau_s of one half-edge from the LDS tile.
-// a, b: the two nodes of the edge (a before b along the normal direction);
+// a, bb: the two nodes of the edge (a before bb along the normal direction);
 // s1..s4: the side nodes of the tangential difference (s1 + s2 - s3 - s4)/4
 // (Eq. (3_3_refmap_jacobian), six-node stencil); dir 0: x-edge, 1: y-edge.
 __device__ void edge_tau(const GridP& g, const BodyP& b, const double* sX, const double* sY,
@@ -772,11 +868,13 @@ __device__ void edge_tau(const GridP& g, const BodyP& b, const double* sX, const
 
 // Shared body of the force kernel (MODE 0) and the stress read (MODE 1) over
 // interior tiles of region Rg: stage xi, phi of the tile plus a one-node halo
-// in LDS, compute each half-edge once, then combine per node.
+// in LDS (all loads issued first), compute each half-edge once, then combine
+// per node.  In MODE 0, block 0 also reduces relabel's partial boxes into the
+// next ring slot.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, const Win* __restrict__ win,
-                                               int wvalid, int whole_grid,
-                                               const double* __restrict__ X,
+__global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int wvalid, int wnext,
+                                               const int* __restrict__ boxpart, int nbox,
+                                               int whole_grid, const double* __restrict__ X,
                                                const double* __restrict__ Y,
                                                const double* __restrict__ phi, double* o0,
                                                double* o1, double* o2, unsigned* health)
@@ -785,6 +883,7 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, const Win* __re
     __shared__ double ex[FTY][FTX + 1][3];
     __shared__ double ey[FTY + 1][FTX][3];
     const Rect V = window_of(win, wvalid, g);
+    if (MODE == 0 && blockIdx.x == 0) reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
     Rect Rg;
     if (whole_grid) {
         Rg.i0 = 0; Rg.i1 = g.nx - 1; Rg.j0 = 0; Rg.j1 = g.ny - 1;
@@ -804,19 +903,13 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, const Win* __re
         const int i0 = Rg.i0 + (t % ntx) * FTX, j0 = Rg.j0 + (t / ntx) * FTY;
         for (int e = threadIdx.x; e < SX * SY; e += blockDim.x) {
             int ci = i0 - 1 + e % SX, cj = j0 - 1 + e / SX;
-            double xv = NAN, yv = NAN, pv = INFINITY;
-            if (b.present && canon(g, ci, cj) && V.has(ci, cj)) {
-                const long long k = pidx(g, ci, cj);
-                const double p = phi[k];
-                if (p < INFINITY) {
-                    xv = X[k];
-                    yv = Y[k];
-                    pv = p;
-                }
-            }
-            sX[e] = xv;
-            sY[e] = yv;
-            sP[e] = pv;
+            const bool in = b.present && canon(g, ci, cj) && V.has(ci, cj);
+            const long long k = in ? pidx(g, ci, cj) : 0;
+            const double p = phi[k], xv = X[k], yv = Y[k];
+            const bool set = in && p < INFINITY;
+            sX[e] = set ? xv : NAN;
+            sY[e] = set ? yv : NAN;
+            sP[e] = set ? p : INFINITY;
         }
         __syncthreads();
         const int i = i0 + tx, j = j0 + ty;
@@ -883,16 +976,17 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, const Win* __re
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                         double* fx, double* fy, double* drho, hipStream_t st)
 {
-    k_edges<0><<<2048, 256, 0, st>>>(g, b, bb.win, s.wcur, 0, bb.X[s.nxt], bb.Y[s.nxt],
-                                     bb.phi[s.nxt], fx, fy, drho, bb.health);
+    k_edges<0><<<2048, 256, 0, st>>>(g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS,
+                                     0, bb.X[s.nxt], bb.Y[s.nxt], bb.phi[s.nxt], fx, fy, drho,
+                                     bb.health);
     return hipGetLastError();
 }
 
 hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
                               int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st)
 {
-    k_edges<1><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 1, bb.X[buf], bb.Y[buf], bb.phi[buf],
-                                     sxx, sxy, syy, bb.health);
+    k_edges<1><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1, bb.X[buf],
+                                     bb.Y[buf], bb.phi[buf], sxx, sxy, syy, bb.health);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ struct Layout {
     int pitch, pp;
     size_t plane, pplane;
     size_t off_lat[2], off_fx[2], off_fy[2], off_drho, off_X[2], off_Y[2], off_phi[2], off_tag,
-        off_win, off_health, off_dpart, off_dout, off_list[2], off_count, off_boxpart,
+        off_win, off_health, off_dpart, off_dout, off_gcol, off_lists, off_bcount, off_boxpart,
         off_ticket, total;
     size_t lat_bytes;
 };
@@ -65,10 +65,11 @@ Layout make_layout(const lbrmt_grid_desc* d)
         L.off_Y[k] = take(L.pplane * 8);
         L.off_phi[k] = take(L.pplane * 8);
     }
-    L.off_tag = take(L.pplane * 4);
-    for (int k = 0; k < 2; k++) L.off_list[k] = take(L.pplane * 4);
-    L.off_count = take(MAX_COUNTS * 4);
-    L.off_boxpart = take(BOX_BLOCKS * 4 * 4);
+    L.off_tag = take(L.pplane);
+    L.off_gcol = take(L.pplane);
+    L.off_lists = take((size_t)dt_lstride(L.pplane) * 4 * (size_t)(d->layers + 1));
+    L.off_bcount = take((size_t)DT_BLOCKS * (MAX_LAYERS + 1) * 4);
+    L.off_boxpart = take((size_t)std::max(RELABEL_BLOCKS, BOX_BLOCKS) * 4 * 4);
     L.off_ticket = take(4);
     L.off_win = take(3 * sizeof(Win));
     L.off_health = take(LBRMT_H_COUNT * sizeof(unsigned));
@@ -101,9 +102,10 @@ struct lbrmt_ctx {
     double *dpart, *dout;
     long long step = 0;
     bool inited = false;
-    bool overlap = true;
-    int lb_variant = 0;
+    bool overlap = false;  // one stream: the chain, then one full lattice update
+    int lb_variant = 5;    // 256 x 1 tiles, nontemporal stores
     hipGraphExec_t gexec = nullptr;
+    bool graph = true;  // replay captured six-step graphs
     bool timing = false;
     struct Pending {
         int kind;
@@ -210,9 +212,8 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
         }
         {
             Bracket b(c, 1, band);
-            for (int l = 1; l <= g.layers; l++)
-                HIPCHK(c, launch_layer_pass(g, c->bb, s.wcur, s.wprev, l, 0, c->bb.phi[s.cur],
-                                            c->bb.X[s.nxt], c->bb.Y[s.nxt], band));
+            HIPCHK(c, launch_layers(g, c->bb, s.wcur, band));
+            HIPCHK(c, launch_extrapolate(g, c->bb, s, band));
             b.done();
         }
         {
@@ -278,7 +279,8 @@ static int build_graph(lbrmt_ctx* c)
 
 static bool desc_ok(const lbrmt_grid_desc* d)
 {
-    return d && d->nx >= 8 && d->ny >= 8 && d->tau > 0.5 && d->layers >= 1 && d->layers <= 60 &&
+    return d && d->nx >= 8 && d->ny >= 8 && d->tau > 0.5 && d->layers >= 1 &&
+           d->layers <= MAX_LAYERS && (long long)(d->nx + 4) * (d->ny + 4) < (1ll << 26) &&
            d->r_max >= 2 && d->r_max <= 32 && d->eps > 0.0 && d->rho_f > 0.0 &&
            (d->precision == LBRMT_FP64 || d->precision == LBRMT_FP32);
 }
@@ -354,9 +356,10 @@ int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t 
         c->bb.phi[k] = (double*)(c->ws + L.off_phi[k]);
     }
     c->drho = (double*)(c->ws + L.off_drho);
-    c->bb.tag = (int*)(c->ws + L.off_tag);
-    for (int k = 0; k < 2; k++) c->bb.list[k] = (int*)(c->ws + L.off_list[k]);
-    c->bb.count = (int*)(c->ws + L.off_count);
+    c->bb.tag = (int8_t*)(c->ws + L.off_tag);
+    c->bb.gcol = (int8_t*)(c->ws + L.off_gcol);
+    c->bb.lists = (int*)(c->ws + L.off_lists);
+    c->bb.bcount = (int*)(c->ws + L.off_bcount);
     c->bb.boxpart = (int*)(c->ws + L.off_boxpart);
     c->bb.ticket = (unsigned*)(c->ws + L.off_ticket);
     c->bb.win = (Win*)(c->ws + L.off_win);
@@ -427,18 +430,14 @@ int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
         HIPCHK(c, hipMemsetAsync(c->Fy[k], 0, c->L.plane * 8, st));
     }
     HIPCHK(c, hipMemsetAsync(c->drho, 0, c->L.plane * 8, st));
-    HIPCHK(c, hipMemsetAsync(c->bb.count, 0, MAX_COUNTS * 4, st));
     HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, st));
     for (int k = 0; k < 3; k++) HIPCHK(c, launch_win_reset(c->bb.win, k, st));
     if (c->nsolid > 0) {
         // box of S^0 into the slots of "current" (0) and "previous" (2)
         HIPCHK(c, launch_init_solid_box(g, c->body, c->bb, 0, 2, st));
         HIPCHK(c, launch_init_tags(g, c->body, c->bb, 0, st));
-        for (int l = 1; l <= g.layers; l++)
-            HIPCHK(c, launch_layer_pass(g, c->bb, 0, 2, l, 1, c->bb.phi[0], c->bb.X[0],
-                                        c->bb.Y[0], st));
+        HIPCHK(c, launch_layers(g, c->bb, 0, st));
         HIPCHK(c, launch_init_fill(g, c->body, c->bb, 0, st));
-        HIPCHK(c, hipMemsetAsync(c->bb.count, 0, MAX_COUNTS * 4, st));
     }
     HIPCHK(c, launch_init_populations(g, c->d.precision, c->body, c->bb.phi[0], c->bb.win, 0,
                                       d_u0, c->lat[1], c->lat[0], st));
@@ -453,7 +452,7 @@ int lbrmt_step(lbrmt_ctx* c, int64_t nsteps)
     if (!c->inited) return LBRMT_ESTATE;
     int64_t left = nsteps;
     while (left > 0) {
-        const bool use_graph = !c->timing && c->step >= GRAPH_STEPS &&
+        const bool use_graph = c->graph && !c->timing && c->step >= GRAPH_STEPS &&
                                c->step % GRAPH_STEPS == 0 && left >= GRAPH_STEPS;
         if (use_graph) {
             if (!c->gexec) {
@@ -644,7 +643,6 @@ int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
     HIPCHK(c, hipMemcpyAsync(c->bb.win, b + off[7], 3 * sizeof(Win), D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bb.health, b + off[7] + 3 * sizeof(Win),
                              LBRMT_H_COUNT * sizeof(unsigned), D2D, c->st));
-    HIPCHK(c, hipMemsetAsync(c->bb.count, 0, MAX_COUNTS * 4, c->st));
     HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, c->st));
     c->inited = true;
     return LBRMT_OK;
@@ -723,6 +721,10 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
         if (value < 0 || value >= lb_variant_count()) return LBRMT_EINVAL;
         c->lb_variant = (int)value;
         break;
+    case LBRMT_OPT_GRAPH:
+        if (value != 0 && value != 1) return LBRMT_EINVAL;
+        c->graph = value != 0;
+        break;
     default:
         return LBRMT_EINVAL;
     }
@@ -742,6 +744,7 @@ int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
     case LBRMT_OPT_OVERLAP: *value = c->overlap ? 1 : 0; return LBRMT_OK;
     case LBRMT_OPT_LB_VARIANT: *value = c->lb_variant; return LBRMT_OK;
     case LBRMT_OPT_LB_VARIANT_COUNT: *value = lb_variant_count(); return LBRMT_OK;
+    case LBRMT_OPT_GRAPH: *value = c->graph ? 1 : 0; return LBRMT_OK;
     default: return LBRMT_EINVAL;
     }
 }

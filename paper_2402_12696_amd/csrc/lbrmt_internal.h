@@ -11,14 +11,17 @@ namespace lbrmt {
 constexpr int NQ = 9;   // D2Q9 (Sec. 2.2, Table "d2q9")
 constexpr int PAD = 2;  // buffer layers of the reference-map grid (Sec. 3)
 
-// Tag codes of the reference-map nodes during one step (int32 per node).
+// Tag codes of the reference-map nodes during one step (int8 per node).
 constexpr int TAG_NONE = -1;   // no reference map
 constexpr int TAG_SOLID = 0;   // phi^n < 0, interior
 constexpr int TAG_FAIL = 64;   // OR-ed onto a layer number when the fit failed
+constexpr int MAX_LAYERS = 31;
 
-// Blocks of the reductions that build a box with the last-block pattern.
-constexpr int BOX_BLOCKS = 512;
-constexpr int MAX_COUNTS = 64;  // list counters: one per layer 0..layers
+// Launch shapes of the reference-map chain.
+constexpr int BOX_BLOCKS = 512;       // initial solid box
+constexpr int RELABEL_BLOCKS = 2048;  // relabel: one partial box per block
+constexpr int DT_BLOCKS = 2048;       // distance transform; also one extrapolation layer
+constexpr int FIT_LANES = 8;         // lanes sharing one extrapolation target
 
 // Axis-aligned box of the interior solid nodes of one body (i0 > i1: empty).
 // The working window of a step is this box dilated by `layers` nodes.
@@ -52,11 +55,12 @@ struct BandBufs {
     double* X[2];         // reference map components, padded grid, double-buffered
     double* Y[2];
     double* phi[2];       // level set; +inf where no reference map
-    int* tag;
-    int* list[2];         // node lists of consecutive layers (ping-pong), padded index
-    int* count;           // entries of the list of layer l, MAX_COUNTS counters
-    int* boxpart;         // per-block partial boxes, BOX_BLOCKS x 4
-    unsigned* ticket;     // arrival counter of the last-block reduction
+    int8_t* tag;          // TAG_* or layer number, padded grid
+    int8_t* gcol;         // column distance to the solid (distance transform)
+    int* lists;           // zone nodes: layer l, block b at lists + l * dt_lstride + b * dt_seg
+    int* bcount;          // entries per block and layer, DT_BLOCKS x (MAX_LAYERS + 1)
+    int* boxpart;         // per-block partial boxes, RELABEL_BLOCKS x 4
+    unsigned* ticket;     // arrival counter of last-block reductions
     Win* win;             // ring of 3 boxes
     unsigned* health;
 };
@@ -136,6 +140,19 @@ __device__ __forceinline__ long long pidx(const GridP& g, int i, int j)
     return (long long)(j + PAD) * g.pp + (i + PAD);
 }
 
+// The distance transform runs DT_BLOCKS blocks of 256 threads over a window
+// of at most pplane nodes; block b lists the zone nodes it visited in a
+// segment of dt_seg entries per layer.
+__host__ __device__ __forceinline__ long long dt_seg(long long pplane)
+{
+    const long long stride = (long long)DT_BLOCKS * 256;
+    return (pplane + stride - 1) / stride * 256;
+}
+__host__ __device__ __forceinline__ long long dt_lstride(long long pplane)
+{
+    return dt_seg(pplane) * DT_BLOCKS;
+}
+
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns hipGetLastError().
 
@@ -165,9 +182,9 @@ hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, const BandBufs&
                                  int slot1, hipStream_t st);
 hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st);
-hipError_t launch_layer_pass(const GridP& g, const BandBufs& bb, int wslot, int wprev, int l,
-                             int mark_only, const double* phin, double* X1, double* Y1,
-                             hipStream_t st);
+hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStream_t st);
+hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
+                              hipStream_t st);
 hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st);
 hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,

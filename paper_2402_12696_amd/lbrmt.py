@@ -22,7 +22,7 @@ LBRMT_FP64, LBRMT_FP32 = 0, 1
 HEALTH_NAMES = ["advect_miss", "extrap_fail", "stress_miss", "detj", "detj_solid", "nonfinite",
                 "window_clip", "list_overflow"]
 KERNEL_NAMES = ["advect", "extrap", "relabel", "force", "lb_bulk", "lb_band"]
-LBRMT_OPT_OVERLAP, LBRMT_OPT_LB_VARIANT, LBRMT_OPT_LB_VARIANT_COUNT = 0, 1, 2
+LBRMT_OPT_OVERLAP, LBRMT_OPT_LB_VARIANT, LBRMT_OPT_LB_VARIANT_COUNT, LBRMT_OPT_GRAPH = 0, 1, 2, 3
 
 
 class lbrmt_grid_desc(ctypes.Structure):

@@ -197,8 +197,8 @@ def test_solid_smaller_than_a_node_spacing():
 
 
 def test_launch_options_give_bitwise_identical_results():
-    # every lattice tile shape and both stream arrangements compute the same
-    # node updates in the same arithmetic
+    # every lattice tile shape, both stream arrangements and eager launches
+    # compute the same node updates in the same arithmetic
     cfg = workloads.cavity_disc_64()
     base = _gpu(cfg).step(20)
     want = _np(base.macro()) + _np(base.refmap())
@@ -213,3 +213,8 @@ def test_launch_options_give_bitwise_identical_results():
             for x, y in zip(want, got):
                 assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0)), \
                     (ov, v)
+    s = _gpu(cfg)
+    s.set_option(3, 0)
+    s.step(20)
+    for x, y in zip(want, _np(s.macro()) + _np(s.refmap())):
+        assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0)), "eager"
