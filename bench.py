@@ -113,11 +113,24 @@ def main():
                     help="1: reference-map chain on a side stream (library default 0)")
     ap.add_argument("--lb-variant", type=int, default=None,
                     help="lattice tile variant (library default 5)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one plain elementwise copy (FP32 negation) reading and "
+                         "writing this many bytes: the reference dispatch that scales HBM "
+                         "counters (FETCH_SIZE, WRITE_SIZE) of a profiled run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_bytes > 0:
+        import torch
+        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     cfg = _workload(args.workload)
     nodes = cfg["nx"] * cfg["ny"]
