@@ -436,8 +436,11 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
 // separable passes: per column, the distance to the nearest solid node of the
 // column (capped at layers + 1); per row, min over |e| of |e| + that distance.
 __global__ __launch_bounds__(256) void k_dt_cols(GridP g, const Win* __restrict__ win, int wslot,
-                                                 const int8_t* __restrict__ tag, int8_t* gcol)
+                                                 const int8_t* __restrict__ tag, int8_t* gcol,
+                                                 int* lcount)
 {
+    if (blockIdx.x == 0 && threadIdx.x < (MAX_LAYERS + 1) * NSUB)
+        lcount[threadIdx.x * LCOUNT_PAD] = 0;
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
     const int L = g.layers;
@@ -457,72 +460,77 @@ __global__ __launch_bounds__(256) void k_dt_cols(GridP g, const Win* __restrict_
 }
 
 // Row pass of the distance transform: exact layer numbers (Manhattan distance
-// to S^{n+1}, up to the layer count) and, per block, one list of the zone
-// nodes of each layer.  A block counts its nodes in LDS and writes its own
-// segment, so no global atomics are needed; the order inside a segment does
-// not matter since targets of one layer are independent.
+// to S^{n+1}, up to the layer count) and the lists of the zone nodes of each
+// layer, split into NSUB sub-lists by block so that few blocks share a
+// counter.  A block counts its nodes per layer in LDS, reserves room in its
+// sub-list with one global atomic per layer present, then writes.  The order
+// of a list does not matter since targets of one layer are independent.
 __global__ __launch_bounds__(256) void k_dt_rows(GridP g, const Win* __restrict__ win, int wslot,
                                                  int8_t* tag, const int8_t* __restrict__ gcol,
-                                                 int* lists, int* bcount, unsigned* health)
+                                                 int* lists, int* lcount, unsigned* health)
 {
     __shared__ int cnt[MAX_LAYERS + 1];
-    if (threadIdx.x <= MAX_LAYERS) cnt[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ int base[MAX_LAYERS + 1];
     const Rect W = window_of(win, wslot, g);
+    if (!W.ok) return;
     const int L = g.layers;
-    const long long seg = dt_seg(g.pplane), lstride = dt_lstride(g.pplane);
-    int* mylists = lists + (long long)blockIdx.x * seg;
-    if (W.ok) {
-        const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-        const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
-        const long long iters = (total + stride - 1) / stride;
-        const int lane = __lane_id();
-        for (long long it = 0; it < iters; it++) {
-            const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
-            int lay = 0;
-            int k = 0;
-            if (e < total) {
-                const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-                k = (int)pidx(g, i, j);
-                if (tag[k] != TAG_SOLID) {
-                    int best = 2 * L + 2;
-                    for (int d = -L; d <= L; d++) {
-                        const int ii = i + d;
-                        const bool in = ii >= W.i0 && ii <= W.i1;
-                        const int gv = gcol[pidx(g, in ? ii : i, j)];
-                        if (in) best = min(best, abs(d) + gv);
-                    }
-                    if (best <= L) {
-                        tag[k] = (int8_t)best;
-                        lay = best;
-                    }
+    const long long cap = sub_cap(g.pplane);
+    const int sub = blockIdx.x % NSUB;
+    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
+    const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
+    const long long iters = (total + stride - 1) / stride;
+    const int lane = __lane_id();
+    for (long long it = 0; it < iters; it++) {
+        if (threadIdx.x <= MAX_LAYERS) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
+        int lay = 0;
+        int k = 0;
+        if (e < total) {
+            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
+            k = (int)pidx(g, i, j);
+            if (tag[k] != TAG_SOLID) {
+                int best = 2 * L + 2;
+                for (int d = -L; d <= L; d++) {
+                    const int ii = i + d;
+                    const bool in = ii >= W.i0 && ii <= W.i1;
+                    const int gv = gcol[pidx(g, in ? ii : i, j)];
+                    if (in) best = min(best, abs(d) + gv);
                 }
-            }
-            // one LDS atomic per wave and layer present in it
-            for (int l = 1; l <= L; l++) {
-                const unsigned long long mask = __ballot(lay == l);
-                if (mask == 0ull) continue;
-                const int leader = __ffsll((long long)mask) - 1;
-                int base = 0;
-                if (lane == leader) base = atomicAdd(&cnt[l], __popcll(mask));
-                base = __shfl(base, leader);
-                const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
-                if (lay == l) {
-                    if (slot < seg) mylists[l * lstride + slot] = k;
-                    else atomicAdd(&health[7], 1u);  // cannot happen: seg covers a block's nodes
+                if (best <= L) {
+                    tag[k] = (int8_t)best;
+                    lay = best;
                 }
             }
         }
+        // slot inside the block: one LDS atomic per wave and layer present
+        int slot = 0;
+        for (int l = 1; l <= L; l++) {
+            const unsigned long long mask = __ballot(lay == l);
+            if (mask == 0ull) continue;
+            const int leader = __ffsll((long long)mask) - 1;
+            int wb = 0;
+            if (lane == leader) wb = atomicAdd(&cnt[l], __popcll(mask));
+            wb = __shfl(wb, leader);
+            if (lay == l) slot = wb + __popcll(mask & ((1ull << lane) - 1ull));
+        }
+        __syncthreads();
+        if (threadIdx.x >= 1 && threadIdx.x <= L && cnt[threadIdx.x] > 0)
+            base[threadIdx.x] =
+                atomicAdd(&lcount[(threadIdx.x * NSUB + sub) * LCOUNT_PAD], cnt[threadIdx.x]);
+        __syncthreads();
+        if (lay > 0) {
+            const long long at = (long long)base[lay] + slot;
+            if (at < cap) lists[(lay * NSUB + sub) * cap + at] = k;
+            else atomicAdd(&health[7], 1u);  // cannot happen: see sub_cap
+        }
     }
-    __syncthreads();
-    if (threadIdx.x <= MAX_LAYERS)
-        bcount[blockIdx.x * (MAX_LAYERS + 1) + threadIdx.x] = (int)min((long long)cnt[threadIdx.x], seg);
 }
 
 hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStream_t st)
 {
-    k_dt_cols<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol);
-    k_dt_rows<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol, bb.lists, bb.bcount,
+    k_dt_cols<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol, bb.lcount);
+    k_dt_rows<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol, bb.lists, bb.lcount,
                                          bb.health);
     return hipGetLastError();
 }
@@ -652,31 +660,83 @@ __device__ __forceinline__ int group_sum(int v)
     return v;
 }
 
-// One layer of Sec. 3.2.  Block b takes the layer-l nodes that block b of the
-// distance transform listed; each target is fitted by a group of FIT_LANES
-// lanes that share the scan-window nodes (each lane loads its share at once),
-// and the sums of the normal equations are reduced across the group.  Scan
-// windows grow from r = 2 to r_max until they hold three valid nodes and a
-// well-posed fit.  Valid nodes come only from earlier layers, so targets of
-// one layer never read each other.
+// Sums of the normal equations over the nodes of the scan window of
+// half-width r (side = 2r + 1) that fall to this lane: window node q goes to
+// lane q mod FIT_LANES; each lane issues all its loads before adding.
+template <int SIDE>
+__device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l, int i, int j,
+                                           int kt, int side, int sub, bool use_n, double nxh,
+                                           double nyh, const int8_t* tag, const double* X1,
+                                           const double* Y1, Fit& f, int& count)
+{
+    constexpr int PER = 4;  // window nodes per lane and pass: 25 of r = 2 in one pass
+    if (SIDE > 0) side = SIDE;
+    const int r = side / 2, nq = side * side;
+    for (int q0 = 0; q0 < nq; q0 += PER * FIT_LANES) {
+        long long kk[PER];
+        int tk[PER], aa[PER], bb[PER];
+        double xv[PER], yv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int q = q0 + sub + u * FIT_LANES;
+            aa[u] = q % side - r;
+            bb[u] = q / side - r;
+            int ci = i + aa[u], cj = j + bb[u];
+            kk[u] = (q < nq && canon(g, ci, cj) && W.has(ci, cj)) ? pidx(g, ci, cj) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const long long k = kk[u] >= 0 ? kk[u] : kt;
+            tk[u] = tag[k];
+            xv[u] = X1[k];
+            yv[u] = Y1[k];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            if (kk[u] < 0 || !tag_valid_before(tk[u], l)) continue;
+            count++;
+            f.add(aa[u], bb[u], use_n, nxh, nyh, xv[u], yv[u]);
+        }
+    }
+}
+
+// One layer of Sec. 3.2: every target of the layer list is fitted by a group
+// of FIT_LANES lanes that share the scan-window nodes; the sums of the normal
+// equations are reduced across the group.  Scan windows grow from r = 2 to
+// r_max until they hold three valid nodes and a well-posed fit.  Valid nodes
+// come only from earlier layers, so targets of one layer never read each other.
 __global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restrict__ win,
                                                    int wcur, int wprev, int l, int8_t* tag,
                                                    const int* __restrict__ lists,
-                                                   const int* __restrict__ bcount,
+                                                   const int* __restrict__ lcount,
                                                    const double* __restrict__ phin, double* X1,
                                                    double* Y1, unsigned* health)
 {
-    constexpr int PER = 4;  // window nodes per lane and pass: 25 of r = 2 in one pass
-    const Rect W = window_of(win, wcur, g);
-    const Rect D = window_of(win, wprev, g);
-    const int n = bcount[blockIdx.x * (MAX_LAYERS + 1) + l];
-    if (n == 0 || !W.ok) return;
-    const int* list = lists + l * dt_lstride(g.pplane) + blockIdx.x * dt_seg(g.pplane);
+    const long long cap = sub_cap(g.pplane);
+    int ns[NSUB], n = 0;
+#pragma unroll
+    for (int s = 0; s < NSUB; s++) {
+        ns[s] = (int)min((long long)lcount[(l * NSUB + s) * LCOUNT_PAD], cap);
+        n += ns[s];
+    }
     const int sub = threadIdx.x % FIT_LANES;
-    const int groups = blockDim.x / FIT_LANES;
+    const int g0 = (blockIdx.x * blockDim.x + threadIdx.x) / FIT_LANES;
+    const int gstride = gridDim.x * blockDim.x / FIT_LANES;
+    if (g0 >= n) return;  // whole groups leave together
+    const Rect W = window_of(win, wcur, g);
+    if (!W.ok) return;
+    const Rect D = window_of(win, wprev, g);
     // all lanes of a group run the same trip counts, so shuffles see full groups
-    for (int t = threadIdx.x / FIT_LANES; t < n; t += groups) {
-        const int kt = list[t];
+    for (int t = g0; t < n; t += gstride) {
+        // position t of the concatenated sub-lists
+        int s = 0, at = t;
+#pragma unroll
+        for (int u = 0; u < NSUB - 1; u++)
+            if (s == u && at >= ns[u]) {
+                at -= ns[u];
+                s = u + 1;
+            }
+        const int kt = lists[(l * NSUB + s) * cap + at];
         const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
         // outward normal of phi^n at the target (layers 1, 2): lanes 0..3
         // load the four neighbours
@@ -697,35 +757,14 @@ __global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restric
         bool done = false;
         double xo = 0.0, yo = 0.0;
         for (int r = 2; r <= g.r_max && !done; r++) {
-            const int side = 2 * r + 1, nq = side * side;
             Fit f;
             f.zero();
             int count = 0;
-            for (int q0 = 0; q0 < nq; q0 += PER * FIT_LANES) {
-                long long kk[PER];
-                int tk[PER];
-                double xv[PER], yv[PER];
-#pragma unroll
-                for (int u = 0; u < PER; u++) {
-                    const int q = q0 + sub + u * FIT_LANES;
-                    int ci = i + q % side - r, cj = j + q / side - r;
-                    kk[u] = (q < nq && canon(g, ci, cj) && W.has(ci, cj)) ? pidx(g, ci, cj) : -1;
-                }
-#pragma unroll
-                for (int u = 0; u < PER; u++) {
-                    const long long k = kk[u] >= 0 ? kk[u] : kt;
-                    tk[u] = tag[k];
-                    xv[u] = X1[k];
-                    yv[u] = Y1[k];
-                }
-#pragma unroll
-                for (int u = 0; u < PER; u++) {
-                    if (kk[u] < 0 || !tag_valid_before(tk[u], l)) continue;
-                    const int q = q0 + sub + u * FIT_LANES;
-                    count++;
-                    f.add(q % side - r, q / side - r, use_n, nxh, nyh, xv[u], yv[u]);
-                }
-            }
+            if (r == 2)
+                fit_window<5>(g, W, l, i, j, kt, 5, sub, use_n, nxh, nyh, tag, X1, Y1, f, count);
+            else
+                fit_window<0>(g, W, l, i, j, kt, 2 * r + 1, sub, use_n, nxh, nyh, tag, X1, Y1, f,
+                              count);
             count = group_sum(count);
             if (count < 3) continue;
             f.M00 = group_sum(f.M00);
@@ -758,9 +797,10 @@ hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlot
                               hipStream_t st)
 {
     for (int l = 1; l <= g.layers; l++)
-        k_layer_fit<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, s.wcur, s.wprev, l, bb.tag, bb.lists,
-                                               bb.bcount, bb.phi[s.cur], bb.X[s.nxt],
-                                               bb.Y[s.nxt], bb.health);
+        k_layer_fit<<<FIT_BLOCKS, 256, 0, st>>>(g, bb.win, s.wcur, s.wprev, l, bb.tag,
+                                                bb.lists, bb.lcount,
+                                                bb.phi[s.cur], bb.X[s.nxt], bb.Y[s.nxt],
+                                                bb.health);
     return hipGetLastError();
 }
 

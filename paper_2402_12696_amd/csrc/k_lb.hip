@@ -166,8 +166,10 @@ __device__ __forceinline__ Rect band_region(const GridP& g, const Rect& a, const
 
 // PART 0: every tile, per-node window tests.  PART 1: tiles outside the band
 // region only (uniform force).  PART 2: tiles of the band region only,
-// grid-stride.
-template <typename S, int PART, int LB_TX, int LB_TY, bool NT>
+// grid-stride.  A tile is LB_TX x (LB_TY * R) nodes: each thread updates R
+// nodes of one column, issuing all their gathers before any arithmetic so
+// that more loads are in flight per wave.
+template <typename S, int PART, int LB_TX, int LB_TY, int R, bool NT>
 __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     GridP g, const S* __restrict__ A, S* __restrict__ B, const double* __restrict__ fpx,
     const double* __restrict__ fpy, const double* __restrict__ fcx, const double* __restrict__ fcy,
@@ -176,8 +178,9 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
 {
     using C = typename Prec<S>::C;
     constexpr bool DEV = Prec<S>::dev;
+    constexpr int TH = LB_TY * R;  // tile height
     const int ntx = (g.nx + LB_TX - 1) / LB_TX;
-    const int nty = (g.ny + LB_TY - 1) / LB_TY;
+    const int nty = (g.ny + TH - 1) / TH;
     const Rect wp = window_of(win, wprev, g);
     const Rect wc = window_of(win, wcur, g);
     const Rect U = band_region(g, wp, wc);
@@ -188,9 +191,9 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     if (PART == 2) {
         if (!U.ok) return;
         utx0 = U.i0 / LB_TX;
-        uty0 = U.j0 / LB_TY;
+        uty0 = U.j0 / TH;
         untx = U.i1 / LB_TX - utx0 + 1;
-        const int unty = U.j1 / LB_TY - uty0 + 1;
+        const int unty = U.j1 / TH - uty0 + 1;
         t_begin = blockIdx.x;
         t_step = gridDim.x;
         t_end = untx * unty;
@@ -208,50 +211,63 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
             tile_x = t % ntx;
             tile_y = t / ntx;
             if (PART == 1 && U.ok) {
-                const int x0 = tile_x * LB_TX, y0 = tile_y * LB_TY;
-                if (x0 <= U.i1 && x0 + LB_TX - 1 >= U.i0 && y0 <= U.j1 && y0 + LB_TY - 1 >= U.j0)
+                const int x0 = tile_x * LB_TX, y0 = tile_y * TH;
+                if (x0 <= U.i1 && x0 + LB_TX - 1 >= U.i0 && y0 <= U.j1 && y0 + TH - 1 >= U.j0)
                     continue;
             }
         }
-        const int i = tile_x * LB_TX + tx, j = tile_y * LB_TY + ty;
-        if (i >= g.nx || j >= g.ny) continue;
-        const Neigh q = neigh(g, i, j);
-        C f[NQ];
-        gather<S>(g, q, A, f);
-        C rho, dn, jx, jy;
-        moments<C, DEV>(f, C(g.rho_f), rho, dn, jx, jy);
-        C Fpx = C(fpo_x), Fpy = C(fpo_y);
-        C Fx = C(g.fext_x), Fy = C(g.fext_y), dr = C(0);
-        if (PART != 1) {
-            if (wp.has(i, j)) {
-                Fpx = C(fpx[q.n]);
-                Fpy = C(fpy[q.n]);
-            }
-            if (wc.has(i, j)) {
-                Fx = C(fcx[q.n]);
-                Fy = C(fcy[q.n]);
-                dr = C(drho[q.n]);
-            }
-        }
-        const C inv = C(1) / rho;
-        const C ux = (jx + C(0.5) * Fpx) * inv;
-        const C uy = (jy + C(0.5) * Fpy) * inv;
-        collide<C, DEV>(f, rho, dn, ux, uy, Fx, Fy, dr, C(g.omega), C(g.cforce));
-        if (q.bn) {
-            // lid: the populations 5 and 6 leave through the moving top wall;
-            // store them already reflected-with-momentum, -2 w rho (c.u_w)/cs^2
-            const C m = rho * C(g.lid_ux) * C(1.0 / 6.0);
-            f[5] -= m;
-            f[6] += m;
-        }
-        if (!(rho > C(0) && rho < C(1e30))) atomicAdd(&health[5], 1u);
-        const long long P = g.plane;
-        if (NT) {
+        const int i = tile_x * LB_TX + tx;
+        if (i >= g.nx) continue;
+        Neigh q[R];
+        bool ok[R];
+        C f[R][NQ];
 #pragma unroll
-            for (int k = 0; k < NQ; k++) __builtin_nontemporal_store(S(f[k]), &B[k * P + q.n]);
-        } else {
+        for (int r = 0; r < R; r++) {
+            const int j = tile_y * TH + ty + r * LB_TY;
+            ok[r] = j < g.ny;
+            q[r] = neigh(g, i, ok[r] ? j : g.ny - 1);
+            gather<S>(g, q[r], A, f[r]);
+        }
 #pragma unroll
-            for (int k = 0; k < NQ; k++) B[k * P + q.n] = S(f[k]);
+        for (int r = 0; r < R; r++) {
+            if (!ok[r]) continue;
+            const int j = tile_y * TH + ty + r * LB_TY;
+            C rho, dn, jx, jy;
+            moments<C, DEV>(f[r], C(g.rho_f), rho, dn, jx, jy);
+            C Fpx = C(fpo_x), Fpy = C(fpo_y);
+            C Fx = C(g.fext_x), Fy = C(g.fext_y), dr = C(0);
+            if (PART != 1) {
+                if (wp.has(i, j)) {
+                    Fpx = C(fpx[q[r].n]);
+                    Fpy = C(fpy[q[r].n]);
+                }
+                if (wc.has(i, j)) {
+                    Fx = C(fcx[q[r].n]);
+                    Fy = C(fcy[q[r].n]);
+                    dr = C(drho[q[r].n]);
+                }
+            }
+            const C inv = C(1) / rho;
+            const C ux = (jx + C(0.5) * Fpx) * inv;
+            const C uy = (jy + C(0.5) * Fpy) * inv;
+            collide<C, DEV>(f[r], rho, dn, ux, uy, Fx, Fy, dr, C(g.omega), C(g.cforce));
+            if (q[r].bn) {
+                // lid: the populations 5 and 6 leave through the moving top wall;
+                // store them already reflected-with-momentum, -2 w rho (c.u_w)/cs^2
+                const C m = rho * C(g.lid_ux) * C(1.0 / 6.0);
+                f[r][5] -= m;
+                f[r][6] += m;
+            }
+            if (!(rho > C(0) && rho < C(1e30))) atomicAdd(&health[5], 1u);
+            const long long P = g.plane;
+            if (NT) {
+#pragma unroll
+                for (int k = 0; k < NQ; k++)
+                    __builtin_nontemporal_store(S(f[r][k]), &B[k * P + q[r].n]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NQ; k++) B[k * P + q[r].n] = S(f[r][k]);
+            }
         }
     }
 }
@@ -259,32 +275,34 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
 // Tile shapes of the lattice Boltzmann update (one thread per node); the
 // variant is chosen per context (lbrmt_set_option) by measurement.
 struct LbVariant {
-    int tx, ty;
+    int tx, ty, r;
     bool nt;
 };
-constexpr LbVariant LB_VARIANTS[] = {{64, 4, false},  {128, 2, false}, {256, 1, false},
-                                     {64, 4, true},   {128, 2, true},  {256, 1, true},
-                                     {32, 8, false},  {64, 2, false}};
+constexpr LbVariant LB_VARIANTS[] = {
+    {64, 4, 1, false}, {128, 2, 1, false}, {256, 1, 1, false}, {64, 4, 1, true},
+    {128, 2, 1, true}, {256, 1, 1, true},  {32, 8, 1, false},  {64, 2, 1, false},
+    {256, 1, 2, true}, {256, 1, 4, true},  {512, 1, 1, true},  {512, 1, 2, true},
+    {128, 2, 2, true}, {256, 1, 2, false}};
 constexpr int N_LB_VARIANTS = sizeof(LB_VARIANTS) / sizeof(LB_VARIANTS[0]);
 
 int lb_variant_count() { return N_LB_VARIANTS; }
 void lb_variant_tile(int v, int* tx, int* ty)
 {
     *tx = LB_VARIANTS[v].tx;
-    *ty = LB_VARIANTS[v].ty;
+    *ty = LB_VARIANTS[v].ty * LB_VARIANTS[v].r;
 }
 
-template <typename S, int PART, int TX, int TY, bool NT>
+template <typename S, int PART, int TX, int TY, int R, bool NT>
 static void lb_launch_one(const GridP& g, const void* A, void* B, const double* fpx,
                           const double* fpy, const double* fcx, const double* fcy,
                           const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
                           double fpo_y, unsigned* health, hipStream_t st)
 {
-    const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY * R - 1) / (TY * R));
     const int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles;
-    k_lb<S, PART, TX, TY, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx, fcy,
-                                                       drho, win, wprev, wcur, fpo_x, fpo_y,
-                                                       health);
+    k_lb<S, PART, TX, TY, R, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx,
+                                                          fcy, drho, win, wprev, wcur, fpo_x,
+                                                          fpo_y, health);
 }
 
 template <typename S, int PART>
@@ -293,18 +311,24 @@ static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, con
                               const double* drho, const Win* win, int wprev, int wcur,
                               double fpo_x, double fpo_y, unsigned* health, hipStream_t st)
 {
-#define LBV(TX, TY, NT)                                                                       \
-    lb_launch_one<S, PART, TX, TY, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
-                                       fpo_x, fpo_y, health, st)
+#define LBV(TX, TY, R, NT)                                                                       \
+    lb_launch_one<S, PART, TX, TY, R, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
+                                          fpo_x, fpo_y, health, st)
     switch (v) {
-    case 1: LBV(128, 2, false); break;
-    case 2: LBV(256, 1, false); break;
-    case 3: LBV(64, 4, true); break;
-    case 4: LBV(128, 2, true); break;
-    case 5: LBV(256, 1, true); break;
-    case 6: LBV(32, 8, false); break;
-    case 7: LBV(64, 2, false); break;
-    default: LBV(64, 4, false); break;
+    case 1: LBV(128, 2, 1, false); break;
+    case 2: LBV(256, 1, 1, false); break;
+    case 3: LBV(64, 4, 1, true); break;
+    case 4: LBV(128, 2, 1, true); break;
+    case 5: LBV(256, 1, 1, true); break;
+    case 6: LBV(32, 8, 1, false); break;
+    case 7: LBV(64, 2, 1, false); break;
+    case 8: LBV(256, 1, 2, true); break;
+    case 9: LBV(256, 1, 4, true); break;
+    case 10: LBV(512, 1, 1, true); break;
+    case 11: LBV(512, 1, 2, true); break;
+    case 12: LBV(128, 2, 2, true); break;
+    case 13: LBV(256, 1, 2, false); break;
+    default: LBV(64, 4, 1, false); break;
     }
 #undef LBV
 }

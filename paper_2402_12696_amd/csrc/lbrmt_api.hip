@@ -34,7 +34,7 @@ struct Layout {
     int pitch, pp;
     size_t plane, pplane;
     size_t off_lat[2], off_fx[2], off_fy[2], off_drho, off_X[2], off_Y[2], off_phi[2], off_tag,
-        off_win, off_health, off_dpart, off_dout, off_gcol, off_lists, off_bcount, off_boxpart,
+        off_win, off_health, off_dpart, off_dout, off_gcol, off_lists, off_lcount, off_boxpart,
         off_ticket, total;
     size_t lat_bytes;
 };
@@ -67,8 +67,8 @@ Layout make_layout(const lbrmt_grid_desc* d)
     }
     L.off_tag = take(L.pplane);
     L.off_gcol = take(L.pplane);
-    L.off_lists = take((size_t)dt_lstride(L.pplane) * 4 * (size_t)(d->layers + 1));
-    L.off_bcount = take((size_t)DT_BLOCKS * (MAX_LAYERS + 1) * 4);
+    L.off_lists = take((size_t)sub_cap((long long)L.pplane) * NSUB * 4 * (size_t)(d->layers + 1));
+    L.off_lcount = take((size_t)(MAX_LAYERS + 1) * NSUB * LCOUNT_PAD * 4);
     L.off_boxpart = take((size_t)std::max(RELABEL_BLOCKS, BOX_BLOCKS) * 4 * 4);
     L.off_ticket = take(4);
     L.off_win = take(3 * sizeof(Win));
@@ -359,7 +359,7 @@ int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t 
     c->bb.tag = (int8_t*)(c->ws + L.off_tag);
     c->bb.gcol = (int8_t*)(c->ws + L.off_gcol);
     c->bb.lists = (int*)(c->ws + L.off_lists);
-    c->bb.bcount = (int*)(c->ws + L.off_bcount);
+    c->bb.lcount = (int*)(c->ws + L.off_lcount);
     c->bb.boxpart = (int*)(c->ws + L.off_boxpart);
     c->bb.ticket = (unsigned*)(c->ws + L.off_ticket);
     c->bb.win = (Win*)(c->ws + L.off_win);

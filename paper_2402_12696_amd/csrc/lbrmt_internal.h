@@ -20,8 +20,11 @@ constexpr int MAX_LAYERS = 31;
 // Launch shapes of the reference-map chain.
 constexpr int BOX_BLOCKS = 512;       // initial solid box
 constexpr int RELABEL_BLOCKS = 2048;  // relabel: one partial box per block
-constexpr int DT_BLOCKS = 2048;       // distance transform; also one extrapolation layer
-constexpr int FIT_LANES = 8;         // lanes sharing one extrapolation target
+constexpr int DT_BLOCKS = 2048;       // distance transform
+constexpr int FIT_BLOCKS = 256;       // one extrapolation layer
+constexpr int FIT_LANES = 8;          // lanes sharing one extrapolation target
+constexpr int LCOUNT_PAD = 32;        // layer counters 128 B apart
+constexpr int NSUB = 8;               // sub-lists per layer (distance-transform block mod 8)         // lanes sharing one extrapolation target
 
 // Axis-aligned box of the interior solid nodes of one body (i0 > i1: empty).
 // The working window of a step is this box dilated by `layers` nodes.
@@ -57,8 +60,8 @@ struct BandBufs {
     double* phi[2];       // level set; +inf where no reference map
     int8_t* tag;          // TAG_* or layer number, padded grid
     int8_t* gcol;         // column distance to the solid (distance transform)
-    int* lists;           // zone nodes: layer l, block b at lists + l * dt_lstride + b * dt_seg
-    int* bcount;          // entries per block and layer, DT_BLOCKS x (MAX_LAYERS + 1)
+    int* lists;           // zone nodes of layer l, sub-list s at lists + (l * NSUB + s) * sub_cap
+    int* lcount;          // entries of (l, s) at lcount[(l * NSUB + s) * LCOUNT_PAD]
     int* boxpart;         // per-block partial boxes, RELABEL_BLOCKS x 4
     unsigned* ticket;     // arrival counter of last-block reductions
     Win* win;             // ring of 3 boxes
@@ -140,18 +143,15 @@ __device__ __forceinline__ long long pidx(const GridP& g, int i, int j)
     return (long long)(j + PAD) * g.pp + (i + PAD);
 }
 
-// The distance transform runs DT_BLOCKS blocks of 256 threads over a window
-// of at most pplane nodes; block b lists the zone nodes it visited in a
-// segment of dt_seg entries per layer.
-__host__ __device__ __forceinline__ long long dt_seg(long long pplane)
+// Capacity of one layer sub-list: the distance transform runs DT_BLOCKS
+// blocks of 256 threads over a window of at most pplane nodes, and sub-list
+// s takes the nodes of blocks b = s mod NSUB, at most pplane / NSUB + one
+// grid pass.
+__host__ __device__ __forceinline__ long long sub_cap(long long pplane)
 {
-    const long long stride = (long long)DT_BLOCKS * 256;
-    return (pplane + stride - 1) / stride * 256;
+    return pplane / NSUB + (long long)DT_BLOCKS * 256 / NSUB;
 }
-__host__ __device__ __forceinline__ long long dt_lstride(long long pplane)
-{
-    return dt_seg(pplane) * DT_BLOCKS;
-}
+
 
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns hipGetLastError().
