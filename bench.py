@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--overlap", type=int, default=None, choices=[0, 1],
                     help="1: reference-map chain on a side stream (library default 0)")
     ap.add_argument("--lb-variant", type=int, default=None,
-                    help="lattice tile variant (library default 5)")
+                    help="lattice tile variant (library default 3 for f64, 5 for f32)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain elementwise copy (FP32 negation) reading and "
                          "writing this many bytes: the reference dispatch that scales HBM "

@@ -189,8 +189,9 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         internal stream while the lattice Boltzmann update of
  *                         the tiles away from the solid runs on the caller's.
  *   LBRMT_OPT_LB_VARIANT  tile shape of the lattice Boltzmann update, 0 ..
- *                         LBRMT_OPT_LB_VARIANT_COUNT - 1, default 5 (results are
- *                         bitwise identical across variants; only speed differs).
+ *                         LBRMT_OPT_LB_VARIANT_COUNT - 1, default 3 for FP64 and
+ *                         5 for FP32 (results are bitwise identical across
+ *                         variants; only speed differs).
  *   LBRMT_OPT_GRAPH       1 (default): whole blocks of six steps replay one
  *                         captured HIP graph; 0: every kernel is launched
  *                         eagerly (results are bitwise identical).
