@@ -43,6 +43,16 @@ typedef enum {
     LBRMT_ESTATE = 6       /* call out of order (e.g. step before init)          */
 } lbrmt_status;
 
+/* Storage and arithmetic precision of a context.
+ *   LBRMT_FP64: populations f_i and the reference map xi in double.
+ *   LBRMT_FP32: populations stored as deviations f_i - w_i rho_f in float with
+ *               float lattice arithmetic; xi stored as the displacement xi - x
+ *               in float with float stencil arithmetic (advection, fit
+ *               right-hand sides, stress).  Double is kept for the level set
+ *               phi0(xi) (it decides the solid set), the fit's normal matrix
+ *               and well-posedness test, the inversion of grad xi where
+ *               det < 0.25, the force planes and every diagnostic reduction.
+ * Reads return float64 in both modes (xi, not the displacement). */
 typedef enum { LBRMT_FP64 = 0, LBRMT_FP32 = 1 } lbrmt_precision;
 
 /* Grid and fluid parameters (Table "sim_quantities", Secs. 2.2-2.4, 3.5). */

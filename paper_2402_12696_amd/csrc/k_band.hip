@@ -16,19 +16,30 @@
 //
 // These kernels take every discrete decision of the method (solid set, layers,
 // window growth of the fit, singular Jacobians); this file is compiled without
-// floating-point contraction so they are taken in plain IEEE double arithmetic.
+// floating-point contraction so they are taken in plain IEEE arithmetic.
+//
+// Storage type T of the reference map: double (FP64 mode) holds xi itself;
+// float (FP32 mode) holds the displacement d = xi - x, x the node coordinate,
+// so values stay small and stencils add the exact lattice offsets (the upwind
+// and central differences of x itself are exactly 1).  The FP32 mode runs the
+// stencil arithmetic in float and keeps FP64 for the level set phi0(x + d)
+// (it decides the solid set), the normal matrix of the fit and its
+// well-posedness test (exact sums of powers of two on a few nodes), and the
+// inversion of grad xi where det < KAPPA_J.
 #include "lbrmt_internal.h"
 
 namespace lbrmt {
 
 constexpr double PI_D = 3.14159265358979323846;
 
-__device__ __forceinline__ double heaviside(double phi, double eps)
+template <typename C>
+__device__ __forceinline__ C heaviside(C phi, C eps)
 {
     // Eq. (2_3_heaviside)
-    if (phi <= -eps) return 0.0;
-    if (phi >= eps) return 1.0;
-    return 0.5 * (1.0 + phi / eps + sin(PI_D * phi / eps) / PI_D);
+    const C pi = C(PI_D);
+    if (phi <= -eps) return C(0);
+    if (phi >= eps) return C(1);
+    return C(0.5) * (C(1) + phi / eps + sin(pi * phi / eps) / pi);
 }
 
 // reference shape level set phi0(X): disc |X - c| - R
@@ -50,6 +61,16 @@ __device__ __forceinline__ double node_coord(int i, int periodic, int n, double 
         x = c + d;
     }
     return x;
+}
+
+// a level-set value computed in double, stored as T with its sign kept (a
+// negative value too small for float is stored as the smallest negative float)
+template <typename T>
+__device__ __forceinline__ T store_phi(double p)
+{
+    T v = T(p);
+    if (p < 0.0 && !(v < T(0))) v = -T(1.401298464324817e-45);
+    return v;
 }
 
 // tags: TAG_NONE, TAG_SOLID, layer l (1..layers), or layer | TAG_FAIL
@@ -249,9 +270,11 @@ hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, 
 }
 
 // xi_0 = x on the solid and its extrapolation zone, phi = phi0(x) (Alg. 1 init)
+template <typename T>
 __global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win, int wslot,
-                            double* X, double* Y, double* phi)
+                            T* X, T* Y, T* phi)
 {
+    constexpr bool DISP = sizeof(T) == 4;
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
@@ -262,13 +285,13 @@ __global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win,
         if (tag[k] != TAG_NONE) {
             const double x = node_coord(i, g.px, g.nx, b.cx);
             const double y = node_coord(j, g.py, g.ny, b.cy);
-            X[k] = x;
-            Y[k] = y;
-            phi[k] = shape_phi(b, x, y);
+            X[k] = DISP ? T(0) : T(x);
+            Y[k] = DISP ? T(0) : T(y);
+            phi[k] = store_phi<T>(shape_phi(b, x, y));
         } else {
-            X[k] = NAN;
-            Y[k] = NAN;
-            phi[k] = INFINITY;
+            X[k] = T(NAN);
+            Y[k] = T(NAN);
+            phi[k] = T(INFINITY);
         }
     }
 }
@@ -276,7 +299,12 @@ __global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win,
 hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st)
 {
-    k_init_fill<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, bb.X[0], bb.Y[0], bb.phi[0]);
+    if (g.rm32)
+        k_init_fill<float><<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, (float*)bb.X[0],
+                                                 (float*)bb.Y[0], (float*)bb.phi[0]);
+    else
+        k_init_fill<double><<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, (double*)bb.X[0],
+                                                  (double*)bb.Y[0], (double*)bb.phi[0]);
     return hipGetLastError();
 }
 
@@ -291,42 +319,45 @@ __device__ __forceinline__ long long ref_index(const GridP& g, const Rect& D, in
 }
 
 // one-sided second-order upwind derivative of Eq. (3_1_eno) from preloaded
-// stencil values (m1, m2: one and two nodes behind; p1, p2: ahead)
-__device__ __forceinline__ bool upwind_d(double vel, double X0, double Y0, bool okm1, bool okm2,
-                                         double Xm1, double Ym1, double Xm2, double Ym2,
-                                         bool okp1, bool okp2, double Xp1, double Yp1,
-                                         double Xp2, double Yp2, double& dX, double& dY)
+// stencil values (m1, m2: one and two nodes behind; p1, p2: ahead).  For
+// displacement storage the derivative of the node coordinate itself, exactly
+// 1 along the axis, is added by the caller.
+template <typename C>
+__device__ __forceinline__ bool upwind_d(C vel, C X0, C Y0, bool okm1, bool okm2, C Xm1, C Ym1,
+                                         C Xm2, C Ym2, bool okp1, bool okp2, C Xp1, C Yp1, C Xp2,
+                                         C Yp2, C& dX, C& dY)
 {
-    dX = dY = 0.0;
-    if (vel == 0.0) return true;
-    if (vel > 0.0) {
+    dX = dY = C(0);
+    if (vel == C(0)) return true;
+    if (vel > C(0)) {
         if (!okm1 || !okm2) return false;
-        dX = (3.0 * X0 - 4.0 * Xm1 + Xm2) / 2.0;
-        dY = (3.0 * Y0 - 4.0 * Ym1 + Ym2) / 2.0;
+        dX = (C(3) * X0 - C(4) * Xm1 + Xm2) / C(2);
+        dY = (C(3) * Y0 - C(4) * Ym1 + Ym2) / C(2);
     } else {
         if (!okp1 || !okp2) return false;
-        dX = (-3.0 * X0 + 4.0 * Xp1 - Xp2) / 2.0;
-        dY = (-3.0 * Y0 + 4.0 * Yp1 - Yp2) / 2.0;
+        dX = (C(-3) * X0 + C(4) * Xp1 - Xp2) / C(2);
+        dY = (C(-3) * Y0 + C(4) * Yp1 - Yp2) / C(2);
     }
     return true;
 }
 
 // Eq. (3_1_refmap_adv) on the solid nodes S^n = {interior, phi^n < 0}, plus
-// the step's tags (solid / none) over the window and the cleared tile flags.
-// Every load of a node (its level set, the eight upwind stencil nodes, the
-// nine populations and the previous force) is issued before any is used;
-// addresses of absent nodes are clamped to the node itself.
+// the step's tags (solid / none) over the window.  Every load of a node (its
+// level set, the eight upwind stencil nodes, the nine populations and the
+// previous force) is issued before any is used; addresses of absent nodes are
+// clamped to the node itself.  S is both the population and the reference-map
+// storage type (FP64: xi; FP32: population deviations and displacement).
 template <typename S>
 __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A,
                                                 const double* __restrict__ fpx,
                                                 const double* __restrict__ fpy,
-                                                const double* __restrict__ X,
-                                                const double* __restrict__ Y,
-                                                const double* __restrict__ phi, double* X1,
-                                                double* Y1, int8_t* tag,
-                                                const Win* __restrict__ win, int wprev, int wcur,
-                                                unsigned* health)
+                                                const S* __restrict__ X, const S* __restrict__ Y,
+                                                const S* __restrict__ phi, S* X1, S* Y1,
+                                                int8_t* tag, const Win* __restrict__ win,
+                                                int wprev, int wcur, unsigned* health)
 {
+    using C = S;
+    constexpr bool DISP = sizeof(S) == 4;
     const Rect W = window_of(win, wcur, g);
     if (!W.ok) return;
     const Rect D = window_of(win, wprev, g);
@@ -356,8 +387,8 @@ __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A
         const long long r0 = (long long)jc * g.pitch, rm = (long long)jm * g.pitch,
                         rp = (long long)jp * g.pitch, n = r0 + ic;
         // ---- all loads
-        const double p0 = phi[k], X0 = X[k], Y0 = Y[k];
-        double ps[8], xs[8], ys[8];
+        const C p0 = phi[k], X0 = X[k], Y0 = Y[k];
+        C ps[8], xs[8], ys[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             const long long kq = ks[q] >= 0 ? ks[q] : k;
@@ -365,7 +396,7 @@ __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A
             xs[q] = X[kq];
             ys[q] = Y[kq];
         }
-        double f[NQ];
+        C f[NQ];
         f[0] = A[n];
         f[1] = bw ? A[3 * P + n] : A[1 * P + r0 + im];
         f[2] = bs ? A[4 * P + n] : A[2 * P + rm + ic];
@@ -375,32 +406,33 @@ __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A
         f[6] = (be || bs) ? A[8 * P + n] : A[6 * P + rm + ip];
         f[7] = (be || bn) ? A[5 * P + n] : A[7 * P + rp + ip];
         f[8] = (bw || bn) ? A[6 * P + n] : A[8 * P + rp + im];
-        const double Fx = fpx[n], Fy = fpy[n];
+        const C Fx = C(fpx[n]), Fy = C(fpy[n]);
         // ---- decisions and arithmetic
-        const bool solid = interior && D.has(i, j) && p0 < 0.0;
+        const bool solid = interior && D.has(i, j) && p0 < C(0);
         tag[k] = solid ? TAG_SOLID : TAG_NONE;
         if (!solid) continue;
-        if (sizeof(S) == 4) {
-            const double wq[NQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
-                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
-            for (int q = 0; q < NQ; q++) f[q] += wq[q] * g.rho_f;
-        }
-        // half-force velocity of Eq. (2_2_lbm_moments_force)
-        const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-        const double u = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (2.0 * rho);
-        const double v = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (2.0 * rho);
+        // half-force velocity of Eq. (2_2_lbm_moments_force); the FP32 mode
+        // stores f_i - w_i rho_f (sum w_i = 1, sum w_i c_i = 0)
+        const C s9 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        const C rho = DISP ? C(g.rho_f) + s9 : s9;
+        const C u = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (C(2) * rho);
+        const C v = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (C(2) * rho);
         bool okq[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) okq[q] = ks[q] >= 0 && ps[q] < INFINITY;
-        double dXx, dYx, dXy, dYy;
-        const bool okx = upwind_d(u, X0, Y0, okq[0], okq[1], xs[0], ys[0], xs[1], ys[1], okq[2],
-                                  okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
-        const bool oky = upwind_d(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5], okq[6],
-                                  okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
+        for (int q = 0; q < 8; q++) okq[q] = ks[q] >= 0 && ps[q] < C(INFINITY);
+        C dXx, dYx, dXy, dYy;
+        const bool okx = upwind_d<C>(u, X0, Y0, okq[0], okq[1], xs[0], ys[0], xs[1], ys[1],
+                                     okq[2], okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
+        const bool oky = upwind_d<C>(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5],
+                                     okq[6], okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
         if (!okx || !oky) {
             atomicAdd(&health[0], 1u);
             X1[k] = X0;
             Y1[k] = Y0;
+        } else if (DISP) {
+            // xi = x + d: d(X)/dx = 1 + dXx, d(Y)/dy = 1 + dYy
+            X1[k] = X0 - (u * (C(1) + dXx) + v * dXy);
+            Y1[k] = Y0 - (u * dYx + v * (C(1) + dYy));
         } else {
             X1[k] = X0 - (u * dXx + v * dXy);
             Y1[k] = Y0 - (u * dYx + v * dYy);
@@ -416,15 +448,15 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
     (void)fpo_x;
     (void)fpo_y;
     if (precision == 0)
-        k_advect<double><<<2048, 256, 0, st>>>(g, (const double*)A, fpx, fpy, bb.X[s.cur],
-                                               bb.Y[s.cur], bb.phi[s.cur], bb.X[s.nxt],
-                                               bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
-                                               s.wcur, bb.health);
+        k_advect<double><<<2048, 256, 0, st>>>(
+            g, (const double*)A, fpx, fpy, (const double*)bb.X[s.cur], (const double*)bb.Y[s.cur],
+            (const double*)bb.phi[s.cur], (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt], bb.tag,
+            bb.win, s.wprev, s.wcur, bb.health);
     else
-        k_advect<float><<<2048, 256, 0, st>>>(g, (const float*)A, fpx, fpy, bb.X[s.cur],
-                                              bb.Y[s.cur], bb.phi[s.cur], bb.X[s.nxt],
-                                              bb.Y[s.nxt], bb.tag, bb.win, s.wprev,
-                                              s.wcur, bb.health);
+        k_advect<float><<<2048, 256, 0, st>>>(
+            g, (const float*)A, fpx, fpy, (const float*)bb.X[s.cur], (const float*)bb.Y[s.cur],
+            (const float*)bb.phi[s.cur], (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt], bb.tag,
+            bb.win, s.wprev, s.wcur, bb.health);
     return hipGetLastError();
 }
 
@@ -545,16 +577,23 @@ __device__ __forceinline__ double det3(double a00, double a01, double a02, doubl
            a02 * (a10 * a21 - a11 * a20);
 }
 
+// Weighted least-squares fit of Sec. 3.2 step (ii) in coordinates centred at
+// the target.  The normal matrix and its well-posedness test are kept in
+// double (sums of w dx dy with w a power of two, or the normal weight of the
+// first two layers); the right-hand sides are accumulated in the storage
+// precision C of the reference map.
+template <typename C>
 struct Fit {
-    double M00, M01, M02, M11, M12, M22, bX0, bX1, bX2, bY0, bY1, bY2;
+    double M00, M01, M02, M11, M12, M22;
+    C bX0, bX1, bX2, bY0, bY1, bY2;
     __device__ __forceinline__ void zero()
     {
         M00 = M01 = M02 = M11 = M12 = M22 = 0.0;
-        bX0 = bX1 = bX2 = bY0 = bY1 = bY2 = 0.0;
+        bX0 = bX1 = bX2 = bY0 = bY1 = bY2 = C(0);
     }
     // one valid node at offset (a, b) from the target, weight of Eq. (3_2_extrap_weight)
-    __device__ __forceinline__ void add(int a, int b, bool use_n, double nxh, double nyh,
-                                        double xv, double yv)
+    __device__ __forceinline__ void add(int a, int b, bool use_n, double nxh, double nyh, C xv,
+                                        C yv)
     {
         double wt = ldexp(1.0, -(abs(a) + abs(b)));
         if (use_n) {
@@ -569,20 +608,30 @@ struct Fit {
         M11 += wt * dy * dy;
         M12 += wt * dy;
         M22 += wt;
-        bX0 += wt * dx * xv;
-        bX1 += wt * dy * xv;
-        bX2 += wt * xv;
-        bY0 += wt * dx * yv;
-        bY1 += wt * dy * yv;
-        bY2 += wt * yv;
+        const C wc = C(wt), cx = C(a), cy = C(b);
+        bX0 += wc * cx * xv;
+        bX1 += wc * cy * xv;
+        bX2 += wc * xv;
+        bY0 += wc * cx * yv;
+        bY1 += wc * cy * yv;
+        bY2 += wc * yv;
     }
     // intercept of the weighted linear fit, if well posed
-    __device__ __forceinline__ bool solve(double det_rel, double& x, double& y) const
+    __device__ __forceinline__ bool solve(double det_rel, C& x, C& y) const
     {
         const double det = det3(M00, M01, M02, M01, M11, M12, M02, M12, M22);
         if (!(det > det_rel * M22 * M22 * M22)) return false;
-        x = det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det;
-        y = det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det;
+        if (sizeof(C) == 8) {
+            x = C(det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det);
+            y = C(det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det);
+        } else {
+            // Cramer in float: the cofactors of the third column weigh the
+            // right-hand sides
+            const C c0 = C(M01 * M12 - M11 * M02), c1 = C(M01 * M02 - M00 * M12);
+            const C c2 = C(M00 * M11 - M01 * M01), id = C(1.0 / det);
+            x = (c0 * bX0 + c1 * bX1 + c2 * bX2) * id;
+            y = (c0 * bY0 + c1 * bY1 + c2 * bY2) * id;
+        }
         return true;
     }
 };
@@ -602,58 +651,10 @@ __device__ __forceinline__ bool normal_from(double pe, double pw, double pn, dou
     return true;
 }
 
-// Sec. 3.2 steps (i)-(iii) for target (i, j) of layer l from global memory:
-// scan windows of half-width r = r0 .. r_max, count the valid nodes (solid, or
-// set in an earlier layer), fit xi = A x + B y + C by weighted least squares in
-// coordinates centred at the target and take C.  Nodes are visited row by row.
-__device__ bool extrapolate_global(const GridP& g, const Rect& W, const Rect& D, int l, int i,
-                                   int j, int r0, const int8_t* tag, const double* phin,
-                                   const double* X1, const double* Y1, double& xo, double& yo)
-{
-    bool use_n = false;
-    double nxh = 0.0, nyh = 0.0;
-    if (l <= 2) {
-        const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
-        double pv[4];
-        for (int d = 0; d < 4; d++) {
-            const long long kq = ref_index(g, D, i + di[d], j + dj[d]);
-            pv[d] = kq >= 0 ? phin[kq] : INFINITY;
-        }
-        use_n = normal_from(pv[0], pv[1], pv[2], pv[3], nxh, nyh);
-    }
-    for (int r = r0; r <= g.r_max; r++) {
-        int count = 0;
-        for (int b = -r; b <= r; b++)
-            for (int a = -r; a <= r; a++) {
-                int ci = i + a, cj = j + b;
-                if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
-                if (tag_valid_before(tag[pidx(g, ci, cj)], l)) count++;
-            }
-        if (count < 3) continue;
-        Fit f;
-        f.zero();
-        for (int b = -r; b <= r; b++)
-            for (int a = -r; a <= r; a++) {
-                int ci = i + a, cj = j + b;
-                if (!canon(g, ci, cj) || !W.has(ci, cj)) continue;
-                const long long k = pidx(g, ci, cj);
-                if (!tag_valid_before(tag[k], l)) continue;
-                f.add(a, b, use_n, nxh, nyh, X1[k], Y1[k]);
-            }
-        if (f.solve(g.det_rel, xo, yo)) return true;
-    }
-    return false;
-}
-
 // sum over the FIT_LANES lanes of a group; the butterfly gives every lane the
 // same bits since each addition sees the same two operands in either order
-__device__ __forceinline__ double group_sum(double v)
-{
-#pragma unroll
-    for (int m = FIT_LANES / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, FIT_LANES);
-    return v;
-}
-__device__ __forceinline__ int group_sum(int v)
+template <typename V>
+__device__ __forceinline__ V group_sum(V v)
 {
 #pragma unroll
     for (int m = FIT_LANES / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, FIT_LANES);
@@ -663,11 +664,11 @@ __device__ __forceinline__ int group_sum(int v)
 // Sums of the normal equations over the nodes of the scan window of
 // half-width r (side = 2r + 1) that fall to this lane: window node q goes to
 // lane q mod FIT_LANES; each lane issues all its loads before adding.
-template <int SIDE>
+template <int SIDE, typename T>
 __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l, int i, int j,
                                            int kt, int side, int sub, bool use_n, double nxh,
-                                           double nyh, const int8_t* tag, const double* X1,
-                                           const double* Y1, Fit& f, int& count)
+                                           double nyh, const int8_t* tag, const T* X1,
+                                           const T* Y1, Fit<T>& f, int& count)
 {
     constexpr int PER = 4;  // window nodes per lane and pass: 25 of r = 2 in one pass
     if (SIDE > 0) side = SIDE;
@@ -675,7 +676,7 @@ __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l,
     for (int q0 = 0; q0 < nq; q0 += PER * FIT_LANES) {
         long long kk[PER];
         int tk[PER], aa[PER], bb[PER];
-        double xv[PER], yv[PER];
+        T xv[PER], yv[PER];
 #pragma unroll
         for (int u = 0; u < PER; u++) {
             const int q = q0 + sub + u * FIT_LANES;
@@ -704,13 +705,16 @@ __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l,
 // of FIT_LANES lanes that share the scan-window nodes; the sums of the normal
 // equations are reduced across the group.  Scan windows grow from r = 2 to
 // r_max until they hold three valid nodes and a well-posed fit.  Valid nodes
-// come only from earlier layers, so targets of one layer never read each other.
+// come only from earlier layers, so targets of one layer never read each
+// other.  With displacement storage the fit of d = xi - x gives the fit of xi
+// minus x at the target, since the weighted fit reproduces linear fields.
+template <typename T>
 __global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restrict__ win,
                                                    int wcur, int wprev, int l, int8_t* tag,
                                                    const int* __restrict__ lists,
                                                    const int* __restrict__ lcount,
-                                                   const double* __restrict__ phin, double* X1,
-                                                   double* Y1, unsigned* health)
+                                                   const T* __restrict__ phin, T* X1, T* Y1,
+                                                   unsigned* health)
 {
     const long long cap = sub_cap(g.pplane);
     int ns[NSUB], n = 0;
@@ -748,23 +752,24 @@ __global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restric
                 const int di = sub == 0 ? 1 : sub == 1 ? -1 : 0;
                 const int dj = sub == 2 ? 1 : sub == 3 ? -1 : 0;
                 const long long kq = ref_index(g, D, i + di, j + dj);
-                if (kq >= 0) p = phin[kq];
+                if (kq >= 0) p = (double)phin[kq];
             }
             const double pe = __shfl(p, 0, FIT_LANES), pw = __shfl(p, 1, FIT_LANES);
             const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
             use_n = normal_from(pe, pw, pn, ps, nxh, nyh);
         }
         bool done = false;
-        double xo = 0.0, yo = 0.0;
+        T xo = T(0), yo = T(0);
         for (int r = 2; r <= g.r_max && !done; r++) {
-            Fit f;
+            Fit<T> f;
             f.zero();
             int count = 0;
             if (r == 2)
-                fit_window<5>(g, W, l, i, j, kt, 5, sub, use_n, nxh, nyh, tag, X1, Y1, f, count);
+                fit_window<5, T>(g, W, l, i, j, kt, 5, sub, use_n, nxh, nyh, tag, X1, Y1, f,
+                                 count);
             else
-                fit_window<0>(g, W, l, i, j, kt, 2 * r + 1, sub, use_n, nxh, nyh, tag, X1, Y1, f,
-                              count);
+                fit_window<0, T>(g, W, l, i, j, kt, 2 * r + 1, sub, use_n, nxh, nyh, tag, X1, Y1,
+                                 f, count);
             count = group_sum(count);
             if (count < 3) continue;
             f.M00 = group_sum(f.M00);
@@ -797,23 +802,30 @@ hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlot
                               hipStream_t st)
 {
     for (int l = 1; l <= g.layers; l++)
-        k_layer_fit<<<FIT_BLOCKS, 256, 0, st>>>(g, bb.win, s.wcur, s.wprev, l, bb.tag,
-                                                bb.lists, bb.lcount,
-                                                bb.phi[s.cur], bb.X[s.nxt], bb.Y[s.nxt],
-                                                bb.health);
+        if (g.rm32)
+            k_layer_fit<float><<<FIT_BLOCKS, 256, 0, st>>>(
+                g, bb.win, s.wcur, s.wprev, l, bb.tag, bb.lists, bb.lcount,
+                (const float*)bb.phi[s.cur], (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt], bb.health);
+        else
+            k_layer_fit<double><<<FIT_BLOCKS, 256, 0, st>>>(
+                g, bb.win, s.wcur, s.wprev, l, bb.tag, bb.lists, bb.lcount,
+                (const double*)bb.phi[s.cur], (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt],
+                bb.health);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- relabel
 
-// phi^{n+1} = phi0(xi^{n+1}) on every node holding a reference map (Alg. 1);
-// one partial box of the new interior solid set per block (reduced by the
-// force kernel into the next ring slot)
+// phi^{n+1} = phi0(xi^{n+1}) on every node holding a reference map (Alg. 1),
+// evaluated in double (it decides the solid set); one partial box of the new
+// interior solid set per block (reduced by the force kernel into the next
+// ring slot)
+template <typename T>
 __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t* __restrict__ tag,
-                                                 const Win* __restrict__ win, int wcur,
-                                                 double* X1, double* Y1, double* phi1,
-                                                 int* boxpart)
+                                                 const Win* __restrict__ win, int wcur, T* X1,
+                                                 T* Y1, T* phi1, int* boxpart)
 {
+    constexpr bool DISP = sizeof(T) == 4;
     const Rect W = window_of(win, wcur, g);
     int i0 = 0x3fffffff, i1 = -0x3fffffff, j0 = 0x3fffffff, j1 = -0x3fffffff;
     if (W.ok) {
@@ -824,10 +836,14 @@ __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t*
             const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
             const long long k = pidx(g, i, j);
             const int8_t tv = tag[k];
-            const double xv = X1[k], yv = Y1[k];
+            double xv = (double)X1[k], yv = (double)Y1[k];
             if (tag_set(tv)) {
+                if (DISP) {
+                    xv += node_coord(i, g.px, g.nx, b.cx);
+                    yv += node_coord(j, g.py, g.ny, b.cy);
+                }
                 const double p = shape_phi(b, xv, yv);
-                phi1[k] = p;
+                phi1[k] = store_phi<T>(p);
                 if (p < 0.0 && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
                     i0 = min(i0, i);
                     i1 = max(i1, i);
@@ -835,9 +851,9 @@ __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t*
                     j1 = max(j1, j);
                 }
             } else {
-                phi1[k] = INFINITY;
-                X1[k] = NAN;
-                Y1[k] = NAN;
+                phi1[k] = T(INFINITY);
+                X1[k] = T(NAN);
+                Y1[k] = T(NAN);
             }
         }
     }
@@ -847,8 +863,14 @@ __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t*
 hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                           hipStream_t st)
 {
-    k_relabel<<<RELABEL_BLOCKS, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur, bb.X[s.nxt],
-                                              bb.Y[s.nxt], bb.phi[s.nxt], bb.boxpart);
+    if (g.rm32)
+        k_relabel<float><<<RELABEL_BLOCKS, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur,
+                                                         (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt],
+                                                         (float*)bb.phi[s.nxt], bb.boxpart);
+    else
+        k_relabel<double><<<RELABEL_BLOCKS, 256, 0, st>>>(
+            g, b, bb.tag, bb.win, s.wcur, (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt],
+            (double*)bb.phi[s.nxt], bb.boxpart);
     return hipGetLastError();
 }
 
@@ -857,53 +879,95 @@ hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, co
 constexpr int FTX = 32, FTY = 8;
 constexpr int SX = FTX + 2, SY = FTY + 2;
 
+// F = J^{-1} (Eq. (3_3_refmap_deformation)) and the plane-strain
+// neo-Hookean deviatoric stress (Eq. (3_3_solid_stress)) scaled by lam
+template <typename C>
+__device__ __forceinline__ void tau_of(C J0, C J1, C J2, C J3, C det, C G, C lam, C out[3])
+{
+    const C F00 = J3 / det, F01 = -J1 / det;
+    const C F10 = -J2 / det, F11 = J0 / det;
+    const C Bxx = F00 * F00 + F01 * F01;
+    const C Bxy = F00 * F10 + F01 * F11;
+    const C Byy = F10 * F10 + F11 * F11;
+    const C tr = Bxx + Byy;
+    out[0] = lam * (G * (Bxx - (tr + C(1)) / C(3)));
+    out[1] = lam * (G * Bxy);
+    out[2] = lam * (G * (Byy - (tr + C(1)) / C(3)));
+}
+
 // Blended stress (1 - H(phi_e)) tau_s of one half-edge from the LDS tile.
 // a, bb: the two nodes of the edge (a before bb along the normal direction);
 // s1..s4: the side nodes of the tangential difference (s1 + s2 - s3 - s4)/4
 // (Eq. (3_3_refmap_jacobian), six-node stencil); dir 0: x-edge, 1: y-edge.
-__device__ void edge_tau(const GridP& g, const BodyP& b, const double* sX, const double* sY,
-                         const double* sP, int a, int bb, int s1, int s2, int s3, int s4, int dir,
-                         bool count, unsigned* health, double out[3])
+// With displacement storage grad xi = I + grad d; where its determinant is
+// below KAPPA_J the inversion is redone in double.
+template <typename C>
+__device__ void edge_tau(const GridP& g, const BodyP& b, const C* sX, const C* sY, const C* sP,
+                         int a, int bb, int s1, int s2, int s3, int s4, int dir, bool count,
+                         unsigned* health, C out[3])
 {
-    out[0] = out[1] = out[2] = 0.0;
-    const double pa = sP[a], pb = sP[bb];
-    if (!(pa < INFINITY) || !(pb < INFINITY)) return;
-    const double phie = 0.5 * (pa + pb);
-    const double lam = 1.0 - heaviside(phie, g.eps);
-    if (!(lam > 0.0)) return;
-    if (!(sP[s1] < INFINITY) || !(sP[s2] < INFINITY) || !(sP[s3] < INFINITY) ||
-        !(sP[s4] < INFINITY)) {
+    constexpr bool DISP = sizeof(C) == 4;
+    out[0] = out[1] = out[2] = C(0);
+    const C pa = sP[a], pb = sP[bb];
+    if (!(pa < C(INFINITY)) || !(pb < C(INFINITY))) return;
+    const C phie = C(0.5) * (pa + pb);
+    const C lam = C(1) - heaviside<C>(phie, C(g.eps));
+    if (!(lam > C(0))) return;
+    if (!(sP[s1] < C(INFINITY)) || !(sP[s2] < C(INFINITY)) || !(sP[s3] < C(INFINITY)) ||
+        !(sP[s4] < C(INFINITY))) {
         if (count) atomicAdd(&health[2], 1u);
         return;
     }
-    const double nX = sX[bb] - sX[a], nY = sY[bb] - sY[a];
-    const double tX = (sX[s1] + sX[s2] - sX[s3] - sX[s4]) / 4.0;
-    const double tY = (sY[s1] + sY[s2] - sY[s3] - sY[s4]) / 4.0;
-    double J0, J1, J2, J3;  // [dX/dx, dX/dy; dY/dx, dY/dy]
+    const C nX = sX[bb] - sX[a], nY = sY[bb] - sY[a];
+    const C tX = (sX[s1] + sX[s2] - sX[s3] - sX[s4]) / C(4);
+    const C tY = (sY[s1] + sY[s2] - sY[s3] - sY[s4]) / C(4);
+    C J0, J1, J2, J3;  // [dX/dx, dX/dy; dY/dx, dY/dy]
     if (dir == 0) {
         J0 = nX; J1 = tX; J2 = nY; J3 = tY;
     } else {
         J0 = tX; J1 = nX; J2 = tY; J3 = nY;
     }
-    const double det = J0 * J3 - J1 * J2;
-    if (!(det > g.detJ_min)) {
+    if (DISP) {
+        J0 += C(1);
+        J3 += C(1);
+    }
+    const C det = J0 * J3 - J1 * J2;
+    if (DISP && !(det >= C(KAPPA_J))) {
+        // near-singular (or inverted) grad xi: decide and invert in double
+        const double dnX = (double)sX[bb] - (double)sX[a], dnY = (double)sY[bb] - (double)sY[a];
+        const double dtX =
+            ((double)sX[s1] + (double)sX[s2] - (double)sX[s3] - (double)sX[s4]) / 4.0;
+        const double dtY =
+            ((double)sY[s1] + (double)sY[s2] - (double)sY[s3] - (double)sY[s4]) / 4.0;
+        double K0, K1, K2, K3;
+        if (dir == 0) {
+            K0 = 1.0 + dnX; K1 = dtX; K2 = dnY; K3 = 1.0 + dtY;
+        } else {
+            K0 = 1.0 + dtX; K1 = dnX; K2 = dtY; K3 = 1.0 + dnY;
+        }
+        const double dd = K0 * K3 - K1 * K2;
+        if (!(dd > g.detJ_min)) {
+            if (count) {
+                atomicAdd(&health[3], 1u);
+                if (lam > C(0.5)) atomicAdd(&health[4], 1u);
+            }
+            return;
+        }
+        double o[3];
+        tau_of<double>(K0, K1, K2, K3, dd, b.G, (double)lam, o);
+        out[0] = C(o[0]);
+        out[1] = C(o[1]);
+        out[2] = C(o[2]);
+        return;
+    }
+    if (!(det > C(g.detJ_min))) {
         if (count) {
             atomicAdd(&health[3], 1u);
-            if (lam > 0.5) atomicAdd(&health[4], 1u);
+            if (lam > C(0.5)) atomicAdd(&health[4], 1u);
         }
         return;
     }
-    // F = J^{-1} (Eq. (3_3_refmap_deformation)); plane-strain neo-Hookean
-    // deviatoric stress (Eq. (3_3_solid_stress))
-    const double F00 = J3 / det, F01 = -J1 / det;
-    const double F10 = -J2 / det, F11 = J0 / det;
-    const double Bxx = F00 * F00 + F01 * F01;
-    const double Bxy = F00 * F10 + F01 * F11;
-    const double Byy = F10 * F10 + F11 * F11;
-    const double tr = Bxx + Byy;
-    out[0] = lam * (b.G * (Bxx - (tr + 1.0) / 3.0));
-    out[1] = lam * (b.G * Bxy);
-    out[2] = lam * (b.G * (Byy - (tr + 1.0) / 3.0));
+    tau_of<C>(J0, J1, J2, J3, det, C(b.G), lam, out);
 }
 
 // Shared body of the force kernel (MODE 0) and the stress read (MODE 1) over
@@ -911,17 +975,17 @@ __device__ void edge_tau(const GridP& g, const BodyP& b, const double* sX, const
 // in LDS (all loads issued first), compute each half-edge once, then combine
 // per node.  In MODE 0, block 0 also reduces relabel's partial boxes into the
 // next ring slot.
-template <int MODE>
+template <int MODE, typename C>
 __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int wvalid, int wnext,
                                                const int* __restrict__ boxpart, int nbox,
-                                               int whole_grid, const double* __restrict__ X,
-                                               const double* __restrict__ Y,
-                                               const double* __restrict__ phi, double* o0,
-                                               double* o1, double* o2, unsigned* health)
+                                               int whole_grid, const C* __restrict__ X,
+                                               const C* __restrict__ Y, const C* __restrict__ phi,
+                                               double* o0, double* o1, double* o2,
+                                               unsigned* health)
 {
-    __shared__ double sX[SY * SX], sY[SY * SX], sP[SY * SX];
-    __shared__ double ex[FTY][FTX + 1][3];
-    __shared__ double ey[FTY + 1][FTX][3];
+    __shared__ C sX[SY * SX], sY[SY * SX], sP[SY * SX];
+    __shared__ C ex[FTY][FTX + 1][3];
+    __shared__ C ey[FTY + 1][FTX][3];
     const Rect V = window_of(win, wvalid, g);
     if (MODE == 0 && blockIdx.x == 0) reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
     Rect Rg;
@@ -945,11 +1009,11 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
             int ci = i0 - 1 + e % SX, cj = j0 - 1 + e / SX;
             const bool in = b.present && canon(g, ci, cj) && V.has(ci, cj);
             const long long k = in ? pidx(g, ci, cj) : 0;
-            const double p = phi[k], xv = X[k], yv = Y[k];
-            const bool set = in && p < INFINITY;
-            sX[e] = set ? xv : NAN;
-            sY[e] = set ? yv : NAN;
-            sP[e] = set ? p : INFINITY;
+            const C p = phi[k], xv = X[k], yv = Y[k];
+            const bool set = in && p < C(INFINITY);
+            sX[e] = set ? xv : C(NAN);
+            sY[e] = set ? yv : C(NAN);
+            sP[e] = set ? p : C(INFINITY);
         }
         __syncthreads();
         const int i = i0 + tx, j = j0 + ty;
@@ -962,51 +1026,52 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
         // local index of node (i + di, j + dj)
 #define LI(di, dj) ((ty + 1 + (dj)) * SX + (tx + 1 + (di)))
         // x-edge (i - 1/2, j): a = (i-1, j), b = (i, j); side (i, j+1), (i-1, j+1), (i, j-1), (i-1, j-1)
-        edge_tau(g, b, sX, sY, sP, LI(-1, 0), LI(0, 0), LI(0, 1), LI(-1, 1), LI(0, -1), LI(-1, -1),
-                 0, cnt_l, health, ex[ty][tx]);
+        edge_tau<C>(g, b, sX, sY, sP, LI(-1, 0), LI(0, 0), LI(0, 1), LI(-1, 1), LI(0, -1),
+                    LI(-1, -1), 0, cnt_l, health, ex[ty][tx]);
         // y-edge (i, j - 1/2): a = (i, j-1), b = (i, j); side (i+1, j), (i+1, j-1), (i-1, j), (i-1, j-1)
-        edge_tau(g, b, sX, sY, sP, LI(0, -1), LI(0, 0), LI(1, 0), LI(1, -1), LI(-1, 0), LI(-1, -1),
-                 1, cnt_b, health, ey[ty][tx]);
+        edge_tau<C>(g, b, sX, sY, sP, LI(0, -1), LI(0, 0), LI(1, 0), LI(1, -1), LI(-1, 0),
+                    LI(-1, -1), 1, cnt_b, health, ey[ty][tx]);
         if (tx == FTX - 1) {
             // right x-edge (i + 1/2, j) of the last tile column
-            edge_tau(g, b, sX, sY, sP, LI(0, 0), LI(1, 0), LI(1, 1), LI(0, 1), LI(1, -1), LI(0, -1),
-                     0, MODE == 0 && mine && i == Rg.i1, health, ex[ty][tx + 1]);
+            edge_tau<C>(g, b, sX, sY, sP, LI(0, 0), LI(1, 0), LI(1, 1), LI(0, 1), LI(1, -1),
+                        LI(0, -1), 0, MODE == 0 && mine && i == Rg.i1, health, ex[ty][tx + 1]);
         }
         if (ty == FTY - 1) {
             // top y-edge (i, j + 1/2) of the last tile row
-            edge_tau(g, b, sX, sY, sP, LI(0, 0), LI(0, 1), LI(1, 1), LI(1, 0), LI(-1, 1), LI(-1, 0),
-                     1, MODE == 0 && mine && j == Rg.j1, health, ey[ty + 1][tx]);
+            edge_tau<C>(g, b, sX, sY, sP, LI(0, 0), LI(0, 1), LI(1, 1), LI(1, 0), LI(-1, 1),
+                        LI(-1, 0), 1, MODE == 0 && mine && j == Rg.j1, health, ey[ty + 1][tx]);
         }
 #undef LI
         __syncthreads();
         if (mine) {
-            const double* L = ex[ty][tx];
-            const double* Rr = ex[ty][tx + 1];
-            const double* B = ey[ty][tx];
-            const double* T = ey[ty + 1][tx];
+            const C* L = ex[ty][tx];
+            const C* Rr = ex[ty][tx + 1];
+            const C* B = ey[ty][tx];
+            const C* T = ey[ty + 1][tx];
             const long long n = (long long)j * g.pitch + i;
             if (MODE == 0) {
                 // Eq. (3_3_div_solid_stress) in Eq. (2_4_F_divs)
-                double fx = (Rr[0] - L[0]) + (T[1] - B[1]);
-                double fy = (Rr[1] - L[1]) + (T[2] - B[2]);
-                const double p = sP[(ty + 1) * SX + tx + 1];
-                double H = 1.0, dr = 0.0;
-                if (b.present && p < INFINITY) {
-                    H = heaviside(p, g.eps);
-                    fx += (1.0 - H) * (b.rho_s - g.rho_f) * g.gx;
-                    fy += (1.0 - H) * (b.rho_s - g.rho_f) * g.gy;
-                    dr = (1.0 - H) * (b.rho_s - g.rho_f);  // Eq. (2_3_drho)
+                C fx = (Rr[0] - L[0]) + (T[1] - B[1]);
+                C fy = (Rr[1] - L[1]) + (T[2] - B[2]);
+                const C p = sP[(ty + 1) * SX + tx + 1];
+                C H = C(1), dr = C(0);
+                if (b.present && p < C(INFINITY)) {
+                    H = heaviside<C>(p, C(g.eps));
+                    const C drs = C(b.rho_s - g.rho_f);
+                    fx += (C(1) - H) * drs * C(g.gx);
+                    fy += (C(1) - H) * drs * C(g.gy);
+                    dr = (C(1) - H) * drs;  // Eq. (2_3_drho)
                 }
-                fx += H * g.fext_x;
-                fy += H * g.fext_y;
-                o0[n] = fx;
-                o1[n] = fy;
-                o2[n] = dr;
+                fx += H * C(g.fext_x);
+                fy += H * C(g.fext_y);
+                o0[n] = (double)fx;
+                o1[n] = (double)fy;
+                o2[n] = (double)dr;
             } else {
                 const long long e = (long long)j * g.nx + i;
-                o0[e] = (L[0] + Rr[0] + B[0] + T[0]) / 4.0;
-                o1[e] = (L[1] + Rr[1] + B[1] + T[1]) / 4.0;
-                o2[e] = (L[2] + Rr[2] + B[2] + T[2]) / 4.0;
+                o0[e] = (double)((L[0] + Rr[0] + B[0] + T[0]) / C(4));
+                o1[e] = (double)((L[1] + Rr[1] + B[1] + T[1]) / C(4));
+                o2[e] = (double)((L[2] + Rr[2] + B[2] + T[2]) / C(4));
             }
         }
         __syncthreads();
@@ -1016,27 +1081,43 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                         double* fx, double* fy, double* drho, hipStream_t st)
 {
-    k_edges<0><<<2048, 256, 0, st>>>(g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS,
-                                     0, bb.X[s.nxt], bb.Y[s.nxt], bb.phi[s.nxt], fx, fy, drho,
-                                     bb.health);
+    if (g.rm32)
+        k_edges<0, float><<<2048, 256, 0, st>>>(
+            g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS, 0, (const float*)bb.X[s.nxt],
+            (const float*)bb.Y[s.nxt], (const float*)bb.phi[s.nxt], fx, fy, drho, bb.health);
+    else
+        k_edges<0, double><<<2048, 256, 0, st>>>(
+            g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS, 0,
+            (const double*)bb.X[s.nxt], (const double*)bb.Y[s.nxt], (const double*)bb.phi[s.nxt],
+            fx, fy, drho, bb.health);
     return hipGetLastError();
 }
 
 hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
                               int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st)
 {
-    k_edges<1><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1, bb.X[buf],
-                                     bb.Y[buf], bb.phi[buf], sxx, sxy, syy, bb.health);
+    if (g.rm32)
+        k_edges<1, float><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1,
+                                                (const float*)bb.X[buf], (const float*)bb.Y[buf],
+                                                (const float*)bb.phi[buf], sxx, sxy, syy,
+                                                bb.health);
+    else
+        k_edges<1, double><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1,
+                                                 (const double*)bb.X[buf],
+                                                 (const double*)bb.Y[buf],
+                                                 (const double*)bb.phi[buf], sxx, sxy, syy,
+                                                 bb.health);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- reads
 
-__global__ void k_read_refmap(GridP g, const Win* __restrict__ win, int wvalid,
-                              const double* __restrict__ X, const double* __restrict__ Y,
-                              const double* __restrict__ phi, double* Xo, double* Yo,
-                              double* Po)
+template <typename T>
+__global__ void k_read_refmap(GridP g, BodyP b, const Win* __restrict__ win, int wvalid,
+                              const T* __restrict__ X, const T* __restrict__ Y,
+                              const T* __restrict__ phi, double* Xo, double* Yo, double* Po)
 {
+    constexpr bool DISP = sizeof(T) == 4;
     const Rect V = window_of(win, wvalid, g);
     const long long N = (long long)g.nx * g.ny;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
@@ -1045,10 +1126,14 @@ __global__ void k_read_refmap(GridP g, const Win* __restrict__ win, int wvalid,
         double xv = NAN, yv = NAN, pv = NAN;
         if (V.has(i, j)) {
             const long long k = pidx(g, i, j);
-            if (phi[k] < INFINITY) {
-                xv = X[k];
-                yv = Y[k];
-                pv = phi[k];
+            if (phi[k] < T(INFINITY)) {
+                xv = (double)X[k];
+                yv = (double)Y[k];
+                pv = (double)phi[k];
+                if (DISP) {
+                    xv += node_coord(i, g.px, g.nx, b.cx);
+                    yv += node_coord(j, g.py, g.ny, b.cy);
+                }
             }
         }
         if (Xo) Xo[e] = xv;
@@ -1057,11 +1142,17 @@ __global__ void k_read_refmap(GridP g, const Win* __restrict__ win, int wvalid,
     }
 }
 
-hipError_t launch_read_refmap(const GridP& g, const BandBufs& bb, int buf, int wvalid, double* X,
-                              double* Y, double* phi, hipStream_t st)
+hipError_t launch_read_refmap(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
+                              int wvalid, double* X, double* Y, double* phi, hipStream_t st)
 {
-    k_read_refmap<<<2048, 256, 0, st>>>(g, bb.win, wvalid, bb.X[buf], bb.Y[buf], bb.phi[buf], X,
-                                        Y, phi);
+    if (g.rm32)
+        k_read_refmap<float><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, (const float*)bb.X[buf],
+                                                   (const float*)bb.Y[buf],
+                                                   (const float*)bb.phi[buf], X, Y, phi);
+    else
+        k_read_refmap<double><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, (const double*)bb.X[buf],
+                                                    (const double*)bb.Y[buf],
+                                                    (const double*)bb.phi[buf], X, Y, phi);
     return hipGetLastError();
 }
 

@@ -30,9 +30,9 @@ __global__ __launch_bounds__(256) void k_diag_partial(GridP g, BodyP b, const S*
                                                       const double* __restrict__ fpy,
                                                       const Win* __restrict__ win, int wprev,
                                                       double fpo_x, double fpo_y,
-                                                      const double* __restrict__ X,
-                                                      const double* __restrict__ Y,
-                                                      const double* __restrict__ phi,
+                                                      const S* __restrict__ X,
+                                                      const S* __restrict__ Y,
+                                                      const S* __restrict__ phi,
                                                       double* partial)
 {
     const long long N = (long long)g.nx * g.ny;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(GridP g, BodyP b, const S*
         acc[10] = fmax(acc[10], sqrt(ux * ux + uy * uy));
         if (b.present && D.has(i, j)) {
             const long long k = pidx(g, i, j);
-            const double p = phi[k];
+            const double p = (double)phi[k];
             if (p < INFINITY) {
                 acc[9] += 1.0;
                 if (p < 0.0) acc[8] += 1.0;
@@ -103,8 +103,11 @@ __global__ __launch_bounds__(256) void k_diag_partial(GridP g, BodyP b, const S*
                 acc[3] += lam;
                 acc[4] += lam * x;
                 acc[5] += lam * y;
-                acc[6] += lam * (x - X[k]);
-                acc[7] += lam * (y - Y[k]);
+                // x - xi; the FP32 mode stores the displacement xi - x itself
+                const double dx = sizeof(S) == 4 ? -(double)X[k] : x - (double)X[k];
+                const double dy = sizeof(S) == 4 ? -(double)Y[k] : y - (double)Y[k];
+                acc[6] += lam * dx;
+                acc[7] += lam * dy;
             }
         }
     }
@@ -124,16 +127,19 @@ __global__ __launch_bounds__(256) void k_diag_partial(GridP g, BodyP b, const S*
     }
 }
 
-__global__ void k_diag_final(const double* __restrict__ partial, int nblocks, double* out)
+// one wave per field: lane l adds partials l, l + 64, ... in order, then a
+// fixed butterfly combines the lanes, so the result is deterministic
+__global__ __launch_bounds__(DIAG_FIELDS * 64) void k_diag_final(const double* __restrict__ partial,
+                                                                 int nblocks, double* out)
 {
-    const int c = threadIdx.x;
-    if (c >= DIAG_FIELDS) return;
-    double v = partial[c];
-    for (int k = 1; k < nblocks; k++) {
+    const int c = threadIdx.x / 64, lane = threadIdx.x % 64;
+    double v = 0.0;
+    for (int k = lane; k < nblocks; k += 64) {
         const double x = partial[(long long)k * DIAG_FIELDS + c];
         v = c == 10 ? fmax(v, x) : v + x;
     }
-    out[c] = v;
+    v = c == 10 ? wave_maxd(v) : wave_sum(v);
+    if (lane == 0) out[c] = v;
 }
 
 hipError_t launch_diag(const GridP& g, int precision, const BodyP& b, const void* A,
@@ -143,13 +149,17 @@ hipError_t launch_diag(const GridP& g, int precision, const BodyP& b, const void
 {
     if (precision == 0)
         k_diag_partial<double><<<DIAG_BLOCKS, 256, 0, st>>>(g, b, (const double*)A, fpx, fpy, win,
-                                                            wprev, fpo_x, fpo_y, bb.X[buf],
-                                                            bb.Y[buf], bb.phi[buf], partial);
+                                                            wprev, fpo_x, fpo_y,
+                                                            (const double*)bb.X[buf],
+                                                            (const double*)bb.Y[buf],
+                                                            (const double*)bb.phi[buf], partial);
     else
         k_diag_partial<float><<<DIAG_BLOCKS, 256, 0, st>>>(g, b, (const float*)A, fpx, fpy, win,
-                                                           wprev, fpo_x, fpo_y, bb.X[buf],
-                                                           bb.Y[buf], bb.phi[buf], partial);
-    k_diag_final<<<1, 64, 0, st>>>(partial, DIAG_BLOCKS, out);
+                                                           wprev, fpo_x, fpo_y,
+                                                           (const float*)bb.X[buf],
+                                                           (const float*)bb.Y[buf],
+                                                           (const float*)bb.phi[buf], partial);
+    k_diag_final<<<1, DIAG_FIELDS * 64, 0, st>>>(partial, DIAG_BLOCKS, out);
     return hipGetLastError();
 }
 

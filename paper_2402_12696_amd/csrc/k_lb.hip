@@ -358,7 +358,7 @@ hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, 
 
 // f^0 = f^eq_SFC(rho_0, v_0, drho_0) in natural (pre-collision) layout
 template <typename S>
-__global__ void k_init_feq(GridP g, BodyP b, const double* __restrict__ phi0,
+__global__ void k_init_feq(GridP g, BodyP b, const S* __restrict__ phi0,
                            const Win* __restrict__ win, int wslot, const double* __restrict__ u0,
                            S* __restrict__ T)
 {
@@ -369,7 +369,7 @@ __global__ void k_init_feq(GridP g, BodyP b, const double* __restrict__ phi0,
         const int i = (int)(e % g.nx), j = (int)(e / g.nx);
         double H = 1.0;
         if (b.present && w.has(i, j)) {
-            const double ph = phi0[pidx(g, i, j)];
+            const double ph = (double)phi0[pidx(g, i, j)];
             if (ph < INFINITY) {
                 // smoothed Heaviside, Eq. (2_3_heaviside)
                 if (ph <= -g.eps) H = 0.0;
@@ -419,16 +419,18 @@ __global__ void k_inverse_stream(GridP g, const S* __restrict__ T, S* __restrict
 }
 
 hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
-                                   const double* phi0, const Win* win, int wslot,
+                                   const void* phi0, const Win* win, int wslot,
                                    const double* u0, void* tmp, void* A, hipStream_t st)
 {
     const long long N = (long long)g.nx * g.ny;
     const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
     if (precision == 0) {
-        k_init_feq<double><<<blocks, 256, 0, st>>>(g, b, phi0, win, wslot, u0, (double*)tmp);
+        k_init_feq<double><<<blocks, 256, 0, st>>>(g, b, (const double*)phi0, win, wslot, u0,
+                                                   (double*)tmp);
         k_inverse_stream<double><<<blocks, 256, 0, st>>>(g, (const double*)tmp, (double*)A);
     } else {
-        k_init_feq<float><<<blocks, 256, 0, st>>>(g, b, phi0, win, wslot, u0, (float*)tmp);
+        k_init_feq<float><<<blocks, 256, 0, st>>>(g, b, (const float*)phi0, win, wslot, u0,
+                                                  (float*)tmp);
         k_inverse_stream<float><<<blocks, 256, 0, st>>>(g, (const float*)tmp, (float*)A);
     }
     return hipGetLastError();

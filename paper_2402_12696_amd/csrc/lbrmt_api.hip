@@ -33,6 +33,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     int pitch, pp;
     size_t plane, pplane;
+    size_t rm_es;  // bytes per reference-map value: 8 (FP64 xi) or 4 (FP32 displacement)
     size_t off_lat[2], off_fx[2], off_fy[2], off_drho, off_X[2], off_Y[2], off_phi[2], off_tag,
         off_win, off_health, off_dpart, off_dout, off_gcol, off_lists, off_lcount, off_boxpart,
         off_ticket, total;
@@ -46,6 +47,7 @@ Layout make_layout(const lbrmt_grid_desc* d)
     L.pp = (int)round_up((size_t)d->nx + 2 * PAD, 32);
     L.plane = (size_t)L.pitch * d->ny;
     L.pplane = (size_t)L.pp * (d->ny + 2 * PAD);
+    L.rm_es = d->precision == LBRMT_FP64 ? 8 : 4;
     const size_t s = d->precision == LBRMT_FP32 ? 4 : 8;
     L.lat_bytes = NQ * L.plane * s;
     size_t o = 0;
@@ -61,9 +63,9 @@ Layout make_layout(const lbrmt_grid_desc* d)
     }
     L.off_drho = take(L.plane * 8);
     for (int k = 0; k < 2; k++) {
-        L.off_X[k] = take(L.pplane * 8);
-        L.off_Y[k] = take(L.pplane * 8);
-        L.off_phi[k] = take(L.pplane * 8);
+        L.off_X[k] = take(L.pplane * L.rm_es);
+        L.off_Y[k] = take(L.pplane * L.rm_es);
+        L.off_phi[k] = take(L.pplane * L.rm_es);
     }
     L.off_tag = take(L.pplane);
     L.off_gcol = take(L.pplane);
@@ -348,14 +350,15 @@ int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t 
     g.eps = d->eps;
     g.det_rel = d->det_rel;
     g.detJ_min = d->detJ_min;
+    g.rm32 = d->precision == LBRMT_FP64 ? 0 : 1;
     c->body.present = 0;
     for (int k = 0; k < 2; k++) {
         c->lat[k] = c->ws + L.off_lat[k];
         c->Fx[k] = (double*)(c->ws + L.off_fx[k]);
         c->Fy[k] = (double*)(c->ws + L.off_fy[k]);
-        c->bb.X[k] = (double*)(c->ws + L.off_X[k]);
-        c->bb.Y[k] = (double*)(c->ws + L.off_Y[k]);
-        c->bb.phi[k] = (double*)(c->ws + L.off_phi[k]);
+        c->bb.X[k] = (void*)(c->ws + L.off_X[k]);
+        c->bb.Y[k] = (void*)(c->ws + L.off_Y[k]);
+        c->bb.phi[k] = (void*)(c->ws + L.off_phi[k]);
     }
     c->drho = (double*)(c->ws + L.off_drho);
     c->bb.tag = (int8_t*)(c->ws + L.off_tag);
@@ -513,7 +516,7 @@ int lbrmt_read_refmap(lbrmt_ctx* c, int32_t solid, double* X, double* Y, double*
     if (!c || solid < 0 || solid >= c->nsolid) return LBRMT_EINVAL;
     if (!c->inited) return LBRMT_ESTATE;
     const StepSlots s = slots_for(c->step);
-    HIPCHK(c, launch_read_refmap(c->g, c->bb, s.cur, s.wprev, X, Y, phi, c->st));
+    HIPCHK(c, launch_read_refmap(c->g, c->body, c->bb, s.cur, s.wprev, X, Y, phi, c->st));
     return LBRMT_OK;
 }
 
@@ -578,9 +581,9 @@ static size_t state_layout(const lbrmt_ctx* c, size_t off[8])
     off[1] = take(c->L.lat_bytes);     // lattice A
     off[2] = take(c->L.plane * 8);     // F^{n-1} x
     off[3] = take(c->L.plane * 8);     // F^{n-1} y
-    off[4] = take(c->L.pplane * 8);    // X
-    off[5] = take(c->L.pplane * 8);    // Y
-    off[6] = take(c->L.pplane * 8);    // phi
+    off[4] = take(c->L.pplane * c->L.rm_es);    // X
+    off[5] = take(c->L.pplane * c->L.rm_es);    // Y
+    off[6] = take(c->L.pplane * c->L.rm_es);    // phi
     off[7] = take(3 * sizeof(Win) + LBRMT_H_COUNT * sizeof(unsigned));
     return o;
 }
@@ -602,14 +605,14 @@ int lbrmt_save_state(lbrmt_ctx* c, void* buf)
     char* b = (char*)buf;
     const StepSlots s = slots_for(c->step);
     StateHeader h{STATE_MAGIC, STATE_VERSION, c->step, c->d.nx, c->d.ny, c->d.precision,
-                  c->nsolid, c->L.lat_bytes, c->L.plane * 8, c->L.pplane * 8};
+                  c->nsolid, c->L.lat_bytes, c->L.plane * 8, c->L.pplane * c->L.rm_es};
     const hipMemcpyKind D2D = hipMemcpyDeviceToDevice;
     HIPCHK(c, hipMemcpyAsync(b + off[1], c->lat[s.cur], c->L.lat_bytes, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[2], c->Fx[s.nxt], c->L.plane * 8, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[3], c->Fy[s.nxt], c->L.plane * 8, D2D, c->st));
-    HIPCHK(c, hipMemcpyAsync(b + off[4], c->bb.X[s.cur], c->L.pplane * 8, D2D, c->st));
-    HIPCHK(c, hipMemcpyAsync(b + off[5], c->bb.Y[s.cur], c->L.pplane * 8, D2D, c->st));
-    HIPCHK(c, hipMemcpyAsync(b + off[6], c->bb.phi[s.cur], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[4], c->bb.X[s.cur], c->L.pplane * c->L.rm_es, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[5], c->bb.Y[s.cur], c->L.pplane * c->L.rm_es, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(b + off[6], c->bb.phi[s.cur], c->L.pplane * c->L.rm_es, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[7], c->bb.win, 3 * sizeof(Win), D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[7] + 3 * sizeof(Win), c->bb.health,
                              LBRMT_H_COUNT * sizeof(unsigned), D2D, c->st));
@@ -639,9 +642,9 @@ int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
     HIPCHK(c, hipMemcpyAsync(c->lat[s.cur], b + off[1], c->L.lat_bytes, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->Fx[s.nxt], b + off[2], c->L.plane * 8, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->Fy[s.nxt], b + off[3], c->L.plane * 8, D2D, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->bb.X[s.cur], b + off[4], c->L.pplane * 8, D2D, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->bb.Y[s.cur], b + off[5], c->L.pplane * 8, D2D, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->bb.phi[s.cur], b + off[6], c->L.pplane * 8, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.X[s.cur], b + off[4], c->L.pplane * c->L.rm_es, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.Y[s.cur], b + off[5], c->L.pplane * c->L.rm_es, D2D, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->bb.phi[s.cur], b + off[6], c->L.pplane * c->L.rm_es, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bb.win, b + off[7], 3 * sizeof(Win), D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bb.health, b + off[7] + 3 * sizeof(Win),
                              LBRMT_H_COUNT * sizeof(unsigned), D2D, c->st));

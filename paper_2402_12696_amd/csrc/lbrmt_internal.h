@@ -46,7 +46,11 @@ struct GridP {
     double gx, gy, fext_x, fext_y;
     double rho_f, eps;
     double det_rel, detJ_min;
+    int rm32;             // reference map stored in FP32 as displacement xi - x
 };
+
+// det(grad xi) below which the FP32 reference-map path inverts grad xi in FP64
+constexpr double KAPPA_J = 0.25;
 
 struct BodyP {
     int present;
@@ -55,9 +59,11 @@ struct BodyP {
 
 // Step-invariant pointers of the reference-map state.
 struct BandBufs {
-    double* X[2];         // reference map components, padded grid, double-buffered
-    double* Y[2];
-    double* phi[2];       // level set; +inf where no reference map
+    // reference map components, padded grid, double-buffered: xi itself in
+    // double (FP64 mode) or the displacement xi - x in float (FP32 mode)
+    void* X[2];
+    void* Y[2];
+    void* phi[2];         // level set (double / float); +inf where no reference map
     int8_t* tag;          // TAG_* or layer number, padded grid
     int8_t* gcol;         // column distance to the solid (distance transform)
     int* lists;           // zone nodes of layer l, sub-list s at lists + (l * NSUB + s) * sub_cap
@@ -164,7 +170,7 @@ hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, 
 int lb_variant_count();
 void lb_variant_tile(int v, int* tx, int* ty);
 hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
-                                   const double* phi0, const Win* win, int wslot,
+                                   const void* phi0, const Win* win, int wslot,
                                    const double* u0, void* tmp, void* A, hipStream_t st);
 hipError_t launch_gather_macro(const GridP& g, int precision, const void* A, const double* fpx,
                                const double* fpy, const Win* win, int wprev, double fpo_x,
@@ -196,7 +202,7 @@ hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, cons
                         double* fx, double* fy, double* drho, hipStream_t st);
 hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
                               int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st);
-hipError_t launch_read_refmap(const GridP& g, const BandBufs& bb, int buf, int wvalid, double* X,
+hipError_t launch_read_refmap(const GridP& g, const BodyP& b, const BandBufs& bb, int buf, int wvalid, double* X,
                               double* Y, double* phi, hipStream_t st);
 
 // reductions (k_diag.hip); partial: scratch of diag_partial_doubles() doubles

@@ -77,3 +77,25 @@ def test_fp32_error_against_fp64_gpu_at_full_size():
             "X": rel(X32[m], X64[m])}
     print("fp32 vs fp64, cavity_disc_2048 step 1000:", {k: f"{v:.2e}" for k, v in errs.items()})
     assert all(v <= TOL32 for v in errs.values()), errs
+
+
+def _same(xs, ys):
+    for x, y in zip(xs, ys):
+        assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0))
+
+
+def test_fp32_checkpoint_resume_and_graph_replay_are_bitwise():
+    cfg = workloads.cavity_disc_64()
+    a = _gpu32(cfg).step(37)
+    blob = a.save_state()
+    a.step(50)
+    ra = _np(a.macro()) + _np(a.refmap())
+    b = _gpu32(cfg)
+    b.load_state(blob)
+    assert b.step_count == 37
+    b.step(50)
+    _same(ra, _np(b.macro()) + _np(b.refmap()))
+    c = _gpu32(cfg)
+    c.set_option(3, 0)  # eager launches instead of graph replays
+    c.step(87)
+    _same(ra, _np(c.macro()) + _np(c.refmap()))
