@@ -82,6 +82,29 @@ def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_varian
     return ms_per_step, ktimes, band_nodes, window_nodes, diag
 
 
+def copy_ceiling(nbytes, reps=20):
+    """HBM rate of a plain streaming copy on this GPU: FP32 negation of nbytes
+    into a second buffer and back (ping-pong, as the lattice update reads one
+    lattice and writes the other), timed with events on torch's stream."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    torch.neg(b, out=a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        if r % 2:
+            torch.neg(b, out=a)
+        else:
+            torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(cfg, seconds=15.0):
     from oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -144,10 +167,13 @@ def main():
     alg_bytes = bpn * bulk_nodes
     achieved = alg_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None
     traffic = traffic_from_profile("lb_bulk", args.workload, args.precision)
+    ceiling = copy_ceiling(9 * bpn // 2 * nodes)
     roof = {"kernel": "lb_bulk", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic, "bytes_per_launch": alg_bytes, "nodes_per_launch": bulk_nodes,
-            "avg_launch_ms": bulk_ms, "launches": bulk_n}
+            "avg_launch_ms": bulk_ms, "launches": bulk_n,
+            "copy_ceiling_GBs": ceiling,
+            "frac_of_copy_ceiling": achieved / ceiling if achieved else None}
 
     extra = {"kernel_avg_ms": {k: v[0] for k, v in kt.items()},
              "band_region_nodes": band, "window_nodes": window,

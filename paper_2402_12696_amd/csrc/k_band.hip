@@ -716,31 +716,23 @@ __global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restric
                                                    const T* __restrict__ phin, T* X1, T* Y1,
                                                    unsigned* health)
 {
+    // group g takes sub-list g mod NSUB (the sub-lists come from interleaved
+    // distance-transform blocks, so they are of similar length); its first
+    // list entry is loaded together with the sub-list's count
     const long long cap = sub_cap(g.pplane);
-    int ns[NSUB], n = 0;
-#pragma unroll
-    for (int s = 0; s < NSUB; s++) {
-        ns[s] = (int)min((long long)lcount[(l * NSUB + s) * LCOUNT_PAD], cap);
-        n += ns[s];
-    }
     const int sub = threadIdx.x % FIT_LANES;
-    const int g0 = (blockIdx.x * blockDim.x + threadIdx.x) / FIT_LANES;
-    const int gstride = gridDim.x * blockDim.x / FIT_LANES;
-    if (g0 >= n) return;  // whole groups leave together
+    const int grp = (blockIdx.x * blockDim.x + threadIdx.x) / FIT_LANES;
+    const int s = grp % NSUB, a0 = grp / NSUB;
+    const int astride = gridDim.x * blockDim.x / FIT_LANES / NSUB;
+    const int* list = lists + (l * NSUB + s) * cap;
+    const int ns = (int)min((long long)lcount[(l * NSUB + s) * LCOUNT_PAD], cap);
+    const int kfirst = a0 < cap ? list[a0] : 0;
     const Rect W = window_of(win, wcur, g);
-    if (!W.ok) return;
     const Rect D = window_of(win, wprev, g);
+    if (a0 >= ns || !W.ok) return;  // whole groups leave together
     // all lanes of a group run the same trip counts, so shuffles see full groups
-    for (int t = g0; t < n; t += gstride) {
-        // position t of the concatenated sub-lists
-        int s = 0, at = t;
-#pragma unroll
-        for (int u = 0; u < NSUB - 1; u++)
-            if (s == u && at >= ns[u]) {
-                at -= ns[u];
-                s = u + 1;
-            }
-        const int kt = lists[(l * NSUB + s) * cap + at];
+    for (int at = a0; at < ns; at += astride) {
+        const int kt = at == a0 ? kfirst : list[at];
         const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
         // outward normal of phi^n at the target (layers 1, 2): lanes 0..3
         // load the four neighbours
