@@ -167,7 +167,7 @@ def main():
     alg_bytes = bpn * bulk_nodes
     achieved = alg_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None
     traffic = traffic_from_profile("lb_bulk", args.workload, args.precision)
-    ceiling = copy_ceiling(9 * bpn // 2 * nodes)
+    ceiling = copy_ceiling(bpn // 2 * nodes)  # one lattice, as the update reads one and writes one
     roof = {"kernel": "lb_bulk", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic, "bytes_per_launch": alg_bytes, "nodes_per_launch": bulk_nodes,
