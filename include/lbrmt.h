@@ -221,6 +221,56 @@ int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);
  * reference map.  Synchronises the stream. */
 int lbrmt_band_nodes(lbrmt_ctx* ctx, int64_t* band_nodes, int64_t* window_nodes);
 
+/* ---------------------------------------------------------------- autotuner
+ * Times every lattice tile shape (LBRMT_OPT_LB_VARIANT values) on the current
+ * state, reps launches each, and selects the fastest (results do not depend
+ * on the shape).  The timed launches read the state's lattice and write the
+ * other lattice, which the next step overwrites, so the state is unchanged.
+ * best_variant / best_ms (nullable): the choice and its time per launch.
+ * Synchronises the stream.  ESTATE before init or on a batch member. */
+int lbrmt_autotune(lbrmt_ctx* ctx, int32_t reps, int32_t* best_variant, double* best_ms);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent simulations (members) of any sizes stepped together: each
+ * kernel of the step is one launch over all members, so a step costs the same
+ * 17 launches whatever the member count, and blocks of six steps replay one
+ * HIP graph.  Every member follows exactly the arithmetic of a single context
+ * with the same description: results are bitwise identical to stepping each
+ * member alone.  All members share the precision and the layer count; each
+ * holds zero or one solid.  The batch carves one caller-owned device
+ * workspace (member states plus the launch tables) and never allocates. */
+typedef struct lbrmt_batch lbrmt_batch;
+
+/* Workspace bytes for members descs[0..n-1].  EINVAL for an invalid
+ * description, mixed precisions or mixed layer counts. */
+int lbrmt_batch_workspace_bytes(const lbrmt_grid_desc* descs, int32_t n, size_t* bytes);
+
+/* solids[k] is member k's solid when has_solid is NULL or has_solid[k] != 0;
+ * solids NULL: no member has a solid.  d_workspace: 256-byte aligned device
+ * memory of lbrmt_batch_workspace_bytes bytes; stream: caller's HIP stream
+ * (all work of the batch and its members is ordered on it). */
+int lbrmt_batch_create(const lbrmt_grid_desc* descs, const lbrmt_solid_desc* solids,
+                       const int32_t* has_solid, int32_t n, void* d_workspace, size_t bytes,
+                       void* hip_stream, lbrmt_batch** out);
+void lbrmt_batch_destroy(lbrmt_batch* batch);
+/* Alg. 1 initialisation of every member (fluid at rest). */
+int lbrmt_batch_init(lbrmt_batch* batch);
+/* nsteps time steps of every member; asynchronous on the stream. */
+int lbrmt_batch_step(lbrmt_batch* batch, int64_t nsteps);
+int32_t lbrmt_batch_size(const lbrmt_batch* batch);
+/* Member k as a context for reads (lbrmt_read_*, lbrmt_diag, lbrmt_save_state,
+ * lbrmt_step_count, lbrmt_band_nodes); lbrmt_step, lbrmt_load_state and
+ * lbrmt_set_option on it return ESTATE.  Owned by the batch. */
+lbrmt_ctx* lbrmt_batch_member(lbrmt_batch* batch, int32_t k);
+/* LBRMT_OPT_LB_VARIANT (one tile shape for the whole batch) and
+ * LBRMT_OPT_GRAPH; get also reads LBRMT_OPT_LB_VARIANT_COUNT. */
+int lbrmt_batch_set_option(lbrmt_batch* batch, int32_t option, int64_t value);
+int lbrmt_batch_get_option(const lbrmt_batch* batch, int32_t option, int64_t* value);
+/* lbrmt_autotune for the batched lattice update. */
+int lbrmt_batch_autotune(lbrmt_batch* batch, int32_t reps, int32_t* best_variant,
+                         double* best_ms);
+const char* lbrmt_batch_last_error(const lbrmt_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -348,7 +348,7 @@ __device__ __forceinline__ bool upwind_d(C vel, C X0, C Y0, bool okm1, bool okm2
 // clamped to the node itself.  S is both the population and the reference-map
 // storage type (FP64: xi; FP32: population deviations and displacement).
 template <typename S>
-__global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A,
+__device__ __forceinline__ void advect_body(GridP g, const S* __restrict__ A,
                                                 const double* __restrict__ fpx,
                                                 const double* __restrict__ fpy,
                                                 const S* __restrict__ X, const S* __restrict__ Y,
@@ -440,6 +440,27 @@ __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A
     }
 }
 
+template <typename S>
+__global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A,
+                                                const double* __restrict__ fpx,
+                                                const double* __restrict__ fpy,
+                                                const S* __restrict__ X, const S* __restrict__ Y,
+                                                const S* __restrict__ phi, S* X1, S* Y1,
+                                                int8_t* tag, const Win* __restrict__ win,
+                                                int wprev, int wcur, unsigned* health)
+{
+    advect_body<S>(g, A, fpx, fpy, X, Y, phi, X1, Y1, tag, win, wprev, wcur, health);
+}
+
+// batched form: member blockIdx.y of a table of arguments
+template <typename S>
+__global__ __launch_bounds__(256) void kb_advect(const AdvectArgs* __restrict__ args)
+{
+    const AdvectArgs& a = args[blockIdx.y];
+    advect_body<S>(a.g, (const S*)a.A, a.fpx, a.fpy, (const S*)a.X, (const S*)a.Y,
+                   (const S*)a.phi, (S*)a.X1, (S*)a.Y1, a.tag, a.win, a.wprev, a.wcur, a.health);
+}
+
 hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
                          const StepSlots& s, const void* A, const double* fpx, const double* fpy,
                          double fpo_x, double fpo_y, hipStream_t st)
@@ -467,7 +488,7 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
 // is the Manhattan distance to the solid set, computed here exactly in two
 // separable passes: per column, the distance to the nearest solid node of the
 // column (capped at layers + 1); per row, min over |e| of |e| + that distance.
-__global__ __launch_bounds__(256) void k_dt_cols(GridP g, const Win* __restrict__ win, int wslot,
+__device__ __forceinline__ void dt_cols_body(GridP g, const Win* __restrict__ win, int wslot,
                                                  const int8_t* __restrict__ tag, int8_t* gcol,
                                                  int* lcount)
 {
@@ -491,13 +512,26 @@ __global__ __launch_bounds__(256) void k_dt_cols(GridP g, const Win* __restrict_
     }
 }
 
+__global__ __launch_bounds__(256) void k_dt_cols(GridP g, const Win* __restrict__ win, int wslot,
+                                                 const int8_t* __restrict__ tag, int8_t* gcol,
+                                                 int* lcount)
+{
+    dt_cols_body(g, win, wslot, tag, gcol, lcount);
+}
+
+__global__ __launch_bounds__(256) void kb_dt_cols(const LayersArgs* __restrict__ args)
+{
+    const LayersArgs& a = args[blockIdx.y];
+    dt_cols_body(a.g, a.win, a.wslot, a.tag, a.gcol, a.lcount);
+}
+
 // Row pass of the distance transform: exact layer numbers (Manhattan distance
 // to S^{n+1}, up to the layer count) and the lists of the zone nodes of each
 // layer, split into NSUB sub-lists by block so that few blocks share a
 // counter.  A block counts its nodes per layer in LDS, reserves room in its
 // sub-list with one global atomic per layer present, then writes.  The order
 // of a list does not matter since targets of one layer are independent.
-__global__ __launch_bounds__(256) void k_dt_rows(GridP g, const Win* __restrict__ win, int wslot,
+__device__ __forceinline__ void dt_rows_body(GridP g, const Win* __restrict__ win, int wslot,
                                                  int8_t* tag, const int8_t* __restrict__ gcol,
                                                  int* lists, int* lcount, unsigned* health)
 {
@@ -557,6 +591,19 @@ __global__ __launch_bounds__(256) void k_dt_rows(GridP g, const Win* __restrict_
             else atomicAdd(&health[7], 1u);  // cannot happen: see sub_cap
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_dt_rows(GridP g, const Win* __restrict__ win, int wslot,
+                                                 int8_t* tag, const int8_t* __restrict__ gcol,
+                                                 int* lists, int* lcount, unsigned* health)
+{
+    dt_rows_body(g, win, wslot, tag, gcol, lists, lcount, health);
+}
+
+__global__ __launch_bounds__(256) void kb_dt_rows(const LayersArgs* __restrict__ args)
+{
+    const LayersArgs& a = args[blockIdx.y];
+    dt_rows_body(a.g, a.win, a.wslot, a.tag, a.gcol, a.lists, a.lcount, a.health);
 }
 
 hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStream_t st)
@@ -709,7 +756,7 @@ __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l,
 // other.  With displacement storage the fit of d = xi - x gives the fit of xi
 // minus x at the target, since the weighted fit reproduces linear fields.
 template <typename T>
-__global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restrict__ win,
+__device__ __forceinline__ void layer_fit_body(GridP g, const Win* __restrict__ win,
                                                    int wcur, int wprev, int l, int8_t* tag,
                                                    const int* __restrict__ lists,
                                                    const int* __restrict__ lcount,
@@ -790,6 +837,26 @@ __global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restric
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restrict__ win,
+                                                   int wcur, int wprev, int l, int8_t* tag,
+                                                   const int* __restrict__ lists,
+                                                   const int* __restrict__ lcount,
+                                                   const T* __restrict__ phin, T* X1, T* Y1,
+                                                   unsigned* health)
+{
+    layer_fit_body<T>(g, win, wcur, wprev, l, tag, lists, lcount, phin, X1, Y1, health);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_layer_fit(const FitArgs* __restrict__ args, int l)
+{
+    const FitArgs& a = args[blockIdx.y];
+    if (l > a.g.layers) return;
+    layer_fit_body<T>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
+                      (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+}
+
 hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
                               hipStream_t st)
 {
@@ -813,7 +880,7 @@ hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlot
 // interior solid set per block (reduced by the force kernel into the next
 // ring slot)
 template <typename T>
-__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t* __restrict__ tag,
+__device__ __forceinline__ void relabel_body(GridP g, BodyP b, const int8_t* __restrict__ tag,
                                                  const Win* __restrict__ win, int wcur, T* X1,
                                                  T* Y1, T* phi1, int* boxpart)
 {
@@ -850,6 +917,21 @@ __global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t*
         }
     }
     block_box(i0, i1, j0, j1, boxpart + 4 * blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t* __restrict__ tag,
+                                                 const Win* __restrict__ win, int wcur, T* X1,
+                                                 T* Y1, T* phi1, int* boxpart)
+{
+    relabel_body<T>(g, b, tag, win, wcur, X1, Y1, phi1, boxpart);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_relabel(const RelabelArgs* __restrict__ args)
+{
+    const RelabelArgs& a = args[blockIdx.y];
+    relabel_body<T>(a.g, a.b, a.tag, a.win, a.wcur, (T*)a.X1, (T*)a.Y1, (T*)a.phi1, a.boxpart);
 }
 
 hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
@@ -968,7 +1050,7 @@ __device__ void edge_tau(const GridP& g, const BodyP& b, const C* sX, const C* s
 // per node.  In MODE 0, block 0 also reduces relabel's partial boxes into the
 // next ring slot.
 template <int MODE, typename C>
-__global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int wvalid, int wnext,
+__device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvalid, int wnext,
                                                const int* __restrict__ boxpart, int nbox,
                                                int whole_grid, const C* __restrict__ X,
                                                const C* __restrict__ Y, const C* __restrict__ phi,
@@ -1070,6 +1152,26 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
     }
 }
 
+template <int MODE, typename C>
+__global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int wvalid, int wnext,
+                                               const int* __restrict__ boxpart, int nbox,
+                                               int whole_grid, const C* __restrict__ X,
+                                               const C* __restrict__ Y, const C* __restrict__ phi,
+                                               double* o0, double* o1, double* o2,
+                                               unsigned* health)
+{
+    edges_body<MODE, C>(g, b, win, wvalid, wnext, boxpart, nbox, whole_grid, X, Y, phi, o0, o1,
+                        o2, health);
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) void kb_force(const EdgesArgs* __restrict__ args)
+{
+    const EdgesArgs& a = args[blockIdx.y];
+    edges_body<0, C>(a.g, a.b, a.win, a.wvalid, a.wnext, a.boxpart, a.nbox, 0, (const C*)a.X,
+                     (const C*)a.Y, (const C*)a.phi, a.o0, a.o1, a.o2, a.health);
+}
+
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                         double* fx, double* fy, double* drho, hipStream_t st)
 {
@@ -1145,6 +1247,30 @@ hipError_t launch_read_refmap(const GridP& g, const BodyP& b, const BandBufs& bb
         k_read_refmap<double><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, (const double*)bb.X[buf],
                                                     (const double*)bb.Y[buf],
                                                     (const double*)bb.phi[buf], X, Y, phi);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched launches
+
+hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
+                             hipStream_t st)
+{
+    const dim3 gb(BATCH_BAND_BLOCKS, nsim), gd(BATCH_DT_BLOCKS, nsim), gf(BATCH_FIT_BLOCKS, nsim);
+    if (precision == 0) {
+        kb_advect<double><<<gb, 256, 0, st>>>(t.adv);
+        kb_dt_cols<<<gd, 256, 0, st>>>(t.lay);
+        kb_dt_rows<<<gd, 256, 0, st>>>(t.lay);
+        for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
+        kb_relabel<double><<<gb, 256, 0, st>>>(t.rel);
+        kb_force<double><<<gb, 256, 0, st>>>(t.edg);
+    } else {
+        kb_advect<float><<<gb, 256, 0, st>>>(t.adv);
+        kb_dt_cols<<<gd, 256, 0, st>>>(t.lay);
+        kb_dt_rows<<<gd, 256, 0, st>>>(t.lay);
+        for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
+        kb_relabel<float><<<gb, 256, 0, st>>>(t.rel);
+        kb_force<float><<<gb, 256, 0, st>>>(t.edg);
+    }
     return hipGetLastError();
 }
 

@@ -164,11 +164,83 @@ __device__ __forceinline__ Rect band_region(const GridP& g, const Rect& a, const
     return u;
 }
 
+// Update of one tile of LB_TX x (LB_TY * R) nodes: each thread updates R
+// nodes of one column, issuing all their gathers before any arithmetic so
+// that more loads are in flight per wave.  PART 1 tiles (outside the band
+// region) use the uniform fluid force; otherwise the force planes are read
+// inside the windows of this and the previous step.
+template <typename S, int PART, int LB_TX, int LB_TY, int R, bool NT>
+__device__ __forceinline__ void lb_tile(const GridP& g, const S* __restrict__ A, S* __restrict__ B,
+                                        const double* __restrict__ fpx,
+                                        const double* __restrict__ fpy,
+                                        const double* __restrict__ fcx,
+                                        const double* __restrict__ fcy,
+                                        const double* __restrict__ drho, const Rect& wp,
+                                        const Rect& wc, double fpo_x, double fpo_y,
+                                        unsigned* __restrict__ health, int tile_x, int tile_y)
+{
+    using C = typename Prec<S>::C;
+    constexpr bool DEV = Prec<S>::dev;
+    constexpr int TH = LB_TY * R;  // tile height
+    const int tx = threadIdx.x % LB_TX, ty = threadIdx.x / LB_TX;
+    const int i = tile_x * LB_TX + tx;
+    if (i >= g.nx) return;
+    Neigh q[R];
+    bool ok[R];
+    C f[R][NQ];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int j = tile_y * TH + ty + r * LB_TY;
+        ok[r] = j < g.ny;
+        q[r] = neigh(g, i, ok[r] ? j : g.ny - 1);
+        gather<S>(g, q[r], A, f[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (!ok[r]) continue;
+        const int j = tile_y * TH + ty + r * LB_TY;
+        C rho, dn, jx, jy;
+        moments<C, DEV>(f[r], C(g.rho_f), rho, dn, jx, jy);
+        C Fpx = C(fpo_x), Fpy = C(fpo_y);
+        C Fx = C(g.fext_x), Fy = C(g.fext_y), dr = C(0);
+        if (PART != 1) {
+            if (wp.has(i, j)) {
+                Fpx = C(fpx[q[r].n]);
+                Fpy = C(fpy[q[r].n]);
+            }
+            if (wc.has(i, j)) {
+                Fx = C(fcx[q[r].n]);
+                Fy = C(fcy[q[r].n]);
+                dr = C(drho[q[r].n]);
+            }
+        }
+        const C inv = C(1) / rho;
+        const C ux = (jx + C(0.5) * Fpx) * inv;
+        const C uy = (jy + C(0.5) * Fpy) * inv;
+        collide<C, DEV>(f[r], rho, dn, ux, uy, Fx, Fy, dr, C(g.omega), C(g.cforce));
+        if (q[r].bn) {
+            // lid: the populations 5 and 6 leave through the moving top wall;
+            // store them already reflected-with-momentum, -2 w rho (c.u_w)/cs^2
+            const C m = rho * C(g.lid_ux) * C(1.0 / 6.0);
+            f[r][5] -= m;
+            f[r][6] += m;
+        }
+        if (!(rho > C(0) && rho < C(1e30))) atomicAdd(&health[5], 1u);
+        const long long P = g.plane;
+        if (NT) {
+#pragma unroll
+            for (int k = 0; k < NQ; k++)
+                __builtin_nontemporal_store(S(f[r][k]), &B[k * P + q[r].n]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NQ; k++) B[k * P + q[r].n] = S(f[r][k]);
+        }
+    }
+}
+
 // PART 0: every tile, per-node window tests.  PART 1: tiles outside the band
 // region only (uniform force).  PART 2: tiles of the band region only,
-// grid-stride.  A tile is LB_TX x (LB_TY * R) nodes: each thread updates R
-// nodes of one column, issuing all their gathers before any arithmetic so
-// that more loads are in flight per wave.
+// grid-stride.
 template <typename S, int PART, int LB_TX, int LB_TY, int R, bool NT>
 __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     GridP g, const S* __restrict__ A, S* __restrict__ B, const double* __restrict__ fpx,
@@ -176,16 +248,12 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     const double* __restrict__ drho, const Win* __restrict__ win, int wprev, int wcur,
     double fpo_x, double fpo_y, unsigned* __restrict__ health)
 {
-    using C = typename Prec<S>::C;
-    constexpr bool DEV = Prec<S>::dev;
-    constexpr int TH = LB_TY * R;  // tile height
+    constexpr int TH = LB_TY * R;
     const int ntx = (g.nx + LB_TX - 1) / LB_TX;
     const int nty = (g.ny + TH - 1) / TH;
     const Rect wp = window_of(win, wprev, g);
     const Rect wc = window_of(win, wcur, g);
     const Rect U = band_region(g, wp, wc);
-    const int tx = threadIdx.x % LB_TX, ty = threadIdx.x / LB_TX;
-
     int t_begin, t_step, t_end;
     int utx0 = 0, uty0 = 0, untx = 1;
     if (PART == 2) {
@@ -216,60 +284,26 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
                     continue;
             }
         }
-        const int i = tile_x * LB_TX + tx;
-        if (i >= g.nx) continue;
-        Neigh q[R];
-        bool ok[R];
-        C f[R][NQ];
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int j = tile_y * TH + ty + r * LB_TY;
-            ok[r] = j < g.ny;
-            q[r] = neigh(g, i, ok[r] ? j : g.ny - 1);
-            gather<S>(g, q[r], A, f[r]);
-        }
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            if (!ok[r]) continue;
-            const int j = tile_y * TH + ty + r * LB_TY;
-            C rho, dn, jx, jy;
-            moments<C, DEV>(f[r], C(g.rho_f), rho, dn, jx, jy);
-            C Fpx = C(fpo_x), Fpy = C(fpo_y);
-            C Fx = C(g.fext_x), Fy = C(g.fext_y), dr = C(0);
-            if (PART != 1) {
-                if (wp.has(i, j)) {
-                    Fpx = C(fpx[q[r].n]);
-                    Fpy = C(fpy[q[r].n]);
-                }
-                if (wc.has(i, j)) {
-                    Fx = C(fcx[q[r].n]);
-                    Fy = C(fcy[q[r].n]);
-                    dr = C(drho[q[r].n]);
-                }
-            }
-            const C inv = C(1) / rho;
-            const C ux = (jx + C(0.5) * Fpx) * inv;
-            const C uy = (jy + C(0.5) * Fpy) * inv;
-            collide<C, DEV>(f[r], rho, dn, ux, uy, Fx, Fy, dr, C(g.omega), C(g.cforce));
-            if (q[r].bn) {
-                // lid: the populations 5 and 6 leave through the moving top wall;
-                // store them already reflected-with-momentum, -2 w rho (c.u_w)/cs^2
-                const C m = rho * C(g.lid_ux) * C(1.0 / 6.0);
-                f[r][5] -= m;
-                f[r][6] += m;
-            }
-            if (!(rho > C(0) && rho < C(1e30))) atomicAdd(&health[5], 1u);
-            const long long P = g.plane;
-            if (NT) {
-#pragma unroll
-                for (int k = 0; k < NQ; k++)
-                    __builtin_nontemporal_store(S(f[r][k]), &B[k * P + q[r].n]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < NQ; k++) B[k * P + q[r].n] = S(f[r][k]);
-            }
-        }
+        lb_tile<S, PART, LB_TX, LB_TY, R, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, wp, wc, fpo_x,
+                                              fpo_y, health, tile_x, tile_y);
     }
+}
+
+// Batched form over the concatenated tile lists of every member: block b
+// takes tile t = xcd_remap(b) of member tile_sim[t].
+template <typename S, int LB_TX, int LB_TY, int R, bool NT>
+__global__ __launch_bounds__(LB_TX* LB_TY) void kb_lb(const LbArgs* __restrict__ args,
+                                                     const int* __restrict__ tile_sim)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const LbArgs& a = args[tile_sim[t]];
+    const int local = t - a.tile_base;
+    const int ntx = (a.g.nx + LB_TX - 1) / LB_TX;
+    const Rect wp = window_of(a.win, a.wprev, a.g);
+    const Rect wc = window_of(a.win, a.wcur, a.g);
+    lb_tile<S, 0, LB_TX, LB_TY, R, NT>(a.g, (const S*)a.A, (S*)a.B, a.fpx, a.fpy, a.fcx, a.fcy,
+                                       a.drho, wp, wc, a.fpo_x, a.fpo_y, a.health, local % ntx,
+                                       local / ntx);
 }
 
 // Tile shapes of the lattice Boltzmann update (one thread per node); the
@@ -351,6 +385,39 @@ hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, 
         else LBP(float, 2);
     }
 #undef LBP
+    return hipGetLastError();
+}
+
+template <typename S>
+static void lb_batch_variant(int v, const LbArgs* args, const int* tile_sim, int total,
+                             hipStream_t st)
+{
+#define LBB(TX, TY, R, NT) kb_lb<S, TX, TY, R, NT><<<total, TX * TY, 0, st>>>(args, tile_sim)
+    switch (v) {
+    case 1: LBB(128, 2, 1, false); break;
+    case 2: LBB(256, 1, 1, false); break;
+    case 3: LBB(64, 4, 1, true); break;
+    case 4: LBB(128, 2, 1, true); break;
+    case 5: LBB(256, 1, 1, true); break;
+    case 6: LBB(32, 8, 1, false); break;
+    case 7: LBB(64, 2, 1, false); break;
+    case 8: LBB(256, 1, 2, true); break;
+    case 9: LBB(256, 1, 4, true); break;
+    case 10: LBB(512, 1, 1, true); break;
+    case 11: LBB(512, 1, 2, true); break;
+    case 12: LBB(128, 2, 2, true); break;
+    case 13: LBB(256, 1, 2, false); break;
+    default: LBB(64, 4, 1, false); break;
+    }
+#undef LBB
+}
+
+hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const int* tile_sim,
+                           int total_tiles, hipStream_t st)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    if (precision == 0) lb_batch_variant<double>(variant, args, tile_sim, total_tiles, st);
+    else lb_batch_variant<float>(variant, args, tile_sim, total_tiles, st);
     return hipGetLastError();
 }
 

@@ -108,6 +108,7 @@ struct lbrmt_ctx {
     int lb_variant = 3;    // set per precision by lbrmt_create
     hipGraphExec_t gexec = nullptr;
     bool graph = true;  // replay captured six-step graphs
+    bool member = false;  // member of a batch (stepped by the batch only)
     bool timing = false;
     struct Pending {
         int kind;
@@ -312,8 +313,8 @@ int lbrmt_workspace_bytes(const lbrmt_grid_desc* d, int32_t max_solids, size_t* 
     return LBRMT_OK;
 }
 
-int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t bytes,
-                 void* stream, lbrmt_ctx** out)
+static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t bytes,
+                       void* stream, lbrmt_ctx** out, bool member)
 {
     if (!desc_ok(d) || !out || !ws || max_solids < 0) return LBRMT_EINVAL;
     if (max_solids > 1) return LBRMT_ECAPACITY;
@@ -371,6 +372,13 @@ int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t 
     c->bb.health = (unsigned*)(c->ws + L.off_health);
     c->dpart = (double*)(c->ws + L.off_dpart);
     c->dout = (double*)(c->ws + L.off_dout);
+    c->member = member;
+    if (member) {
+        // a batch member is stepped by its batch, on the batch's stream
+        c->graph = false;
+        *out = c;
+        return LBRMT_OK;
+    }
     hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
@@ -382,6 +390,12 @@ int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t 
     }
     *out = c;
     return LBRMT_OK;
+}
+
+int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t bytes,
+                 void* stream, lbrmt_ctx** out)
+{
+    return create_impl(d, max_solids, ws, bytes, stream, out, false);
 }
 
 void lbrmt_destroy(lbrmt_ctx* c)
@@ -454,7 +468,7 @@ int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
 int lbrmt_step(lbrmt_ctx* c, int64_t nsteps)
 {
     if (!c || nsteps < 0) return LBRMT_EINVAL;
-    if (!c->inited) return LBRMT_ESTATE;
+    if (!c->inited || c->member) return LBRMT_ESTATE;
     int64_t left = nsteps;
     while (left > 0) {
         const bool use_graph = c->graph && !c->timing && c->step >= GRAPH_STEPS &&
@@ -623,6 +637,7 @@ int lbrmt_save_state(lbrmt_ctx* c, void* buf)
 
 int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
 {
+    if (c && c->member) return LBRMT_ESTATE;
     if (!c || !buf) return LBRMT_EINVAL;
     size_t off[8];
     state_layout(c, off);
@@ -717,6 +732,7 @@ int lbrmt_kernel_time(lbrmt_ctx* c, const char* name, double* avg_ms, int64_t* l
 int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
 {
     if (!c) return LBRMT_EINVAL;
+    if (c->member) return LBRMT_ESTATE;
     switch (option) {
     case LBRMT_OPT_OVERLAP:
         if (value != 0 && value != 1) return LBRMT_EINVAL;
@@ -793,5 +809,438 @@ int lbrmt_band_nodes(lbrmt_ctx* c, int64_t* band_nodes, int64_t* window_nodes)
     *band_nodes = (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1);
     return LBRMT_OK;
 }
+
+
+
+// ---------------------------------------------------------------- tile-shape autotuner
+
+// Times every lattice tile variant on the context's current state: the update
+// reads lattice A (the state) and writes lattice B, which the next step
+// overwrites anyway, so the state is not changed.  Picks the fastest.
+int lbrmt_autotune(lbrmt_ctx* c, int32_t reps, int32_t* best_variant, double* best_ms)
+{
+    if (!c || reps < 1) return LBRMT_EINVAL;
+    if (!c->inited || c->member) return LBRMT_ESTATE;
+    const StepSlots s = slots_for(c->step);
+    const double ox = fpo_x(c, c->step), oy = fpo_y(c, c->step);
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    int best = c->lb_variant;
+    float best_t = 1e30f;
+    for (int v = 0; v < lb_variant_count(); v++) {
+        auto launch = [&]() {
+            return launch_lb(c->g, c->d.precision, v, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
+                             c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
+                             s.wprev, s.wcur, ox, oy, 0, c->bb.health, c->st);
+        };
+        HIPCHK(c, launch());  // warm-up
+        HIPCHK(c, hipEventRecord(a, c->st));
+        for (int r = 0; r < reps; r++) HIPCHK(c, launch());
+        HIPCHK(c, hipEventRecord(b, c->st));
+        HIPCHK(c, hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, a, b));
+        if (ms < best_t) {
+            best_t = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    int rc = lbrmt_set_option(c, LBRMT_OPT_LB_VARIANT, best);
+    if (rc != LBRMT_OK) return rc;
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t / reps;
+    return LBRMT_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+// Independent members of different sizes stepped together: every kernel of
+// the step is one launch over all members (the reference-map kernels take the
+// member from blockIdx.y, the lattice update runs over the concatenated tile
+// lists), so one step costs 17 launches whatever the member count.  Members
+// are ordinary contexts on slices of the batch workspace; their argument
+// tables for the six phases n mod 6 (and n = 0) live in the workspace too.
+struct lbrmt_batch {
+    int n = 0;
+    int precision = 0, layers = 0;
+    std::vector<lbrmt_ctx*> m;
+    hipStream_t st = nullptr, cap = nullptr;
+    char* ws = nullptr;
+    BatchTables tab[7];
+    int* tile_sim = nullptr;
+    size_t tile_cap = 0;
+    int total_tiles = 0;
+    int lb_variant = 3;
+    bool graph = true;
+    hipGraphExec_t gexec = nullptr;
+    long long step = 0;
+    bool inited = false;
+    std::string err;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t tables, tiles, total;
+    std::vector<size_t> member_off, member_bytes;
+    size_t tile_cap;
+};
+
+size_t batch_tile_count(const lbrmt_grid_desc& d, int v)
+{
+    int tx, ty;
+    lb_variant_tile(v, &tx, &ty);
+    return (size_t)((d.nx + tx - 1) / tx) * (size_t)((d.ny + ty - 1) / ty);
+}
+
+bool batch_layout(const lbrmt_grid_desc* d, int32_t n, BatchLayout& B)
+{
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o = round_up(o + b, ALIGN);
+        return r;
+    };
+    const size_t per = sizeof(AdvectArgs) + sizeof(LayersArgs) + sizeof(FitArgs) +
+                       sizeof(RelabelArgs) + sizeof(EdgesArgs) + sizeof(LbArgs);
+    B.tables = take(7 * (size_t)n * per + 6 * 7 * ALIGN);
+    B.tile_cap = 0;
+    for (int v = 0; v < lb_variant_count(); v++) {
+        size_t t = 0;
+        for (int k = 0; k < n; k++) t += batch_tile_count(d[k], v);
+        B.tile_cap = std::max(B.tile_cap, t);
+    }
+    if (B.tile_cap > (size_t)0x7fffffff) return false;
+    B.tiles = take(B.tile_cap * sizeof(int));
+    B.member_off.resize(n);
+    B.member_bytes.resize(n);
+    for (int k = 0; k < n; k++) {
+        const Layout L = make_layout(&d[k]);
+        B.member_bytes[k] = L.total;
+        B.member_off[k] = take(L.total);
+    }
+    B.total = o;
+    return true;
+}
+
+int bfail(lbrmt_batch* b, const char* what, hipError_t e)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    b->err = buf;
+    return LBRMT_EHIP;
+}
+
+#define BCHK(b, expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return bfail(b, #expr, e_); \
+    } while (0)
+
+// argument tables of phase p (p = n mod 6 for n >= 1; p = 6 for n = 0)
+int batch_tables(lbrmt_batch* b)
+{
+    const int n = b->n;
+    std::vector<AdvectArgs> adv(n);
+    std::vector<LayersArgs> lay(n);
+    std::vector<FitArgs> fit(n);
+    std::vector<RelabelArgs> rel(n);
+    std::vector<EdgesArgs> edg(n);
+    std::vector<LbArgs> lb(n);
+    int base = 0;
+    std::vector<int> tile_sim;
+    for (int k = 0; k < n; k++) {
+        const size_t t = batch_tile_count(b->m[k]->d, b->lb_variant);
+        tile_sim.insert(tile_sim.end(), t, k);
+    }
+    if (tile_sim.size() > b->tile_cap) return LBRMT_EWORKSPACE;
+    b->total_tiles = (int)tile_sim.size();
+    for (int p = 0; p < 7; p++) {
+        const long long nstep = p == 6 ? 0 : (p == 0 ? 6 : p);
+        const StepSlots s = slots_for(nstep);
+        base = 0;
+        for (int k = 0; k < n; k++) {
+            lbrmt_ctx* c = b->m[k];
+            const GridP& g = c->g;
+            adv[k] = AdvectArgs{g, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt], c->bb.X[s.cur],
+                                c->bb.Y[s.cur], c->bb.phi[s.cur], c->bb.X[s.nxt], c->bb.Y[s.nxt],
+                                c->bb.tag, c->bb.win, s.wprev, s.wcur, c->bb.health};
+            lay[k] = LayersArgs{g, c->bb.win, s.wcur, c->bb.tag, c->bb.gcol, c->bb.lists,
+                                c->bb.lcount, c->bb.health};
+            fit[k] = FitArgs{g, c->bb.win, s.wcur, s.wprev, c->bb.tag, c->bb.lists, c->bb.lcount,
+                             c->bb.phi[s.cur], c->bb.X[s.nxt], c->bb.Y[s.nxt], c->bb.health};
+            rel[k] = RelabelArgs{g, c->body, c->bb.tag, c->bb.win, s.wcur, c->bb.X[s.nxt],
+                                 c->bb.Y[s.nxt], c->bb.phi[s.nxt], c->bb.boxpart};
+            edg[k] = EdgesArgs{g, c->body, c->bb.win, s.wcur, s.wnext, c->bb.boxpart,
+                               BATCH_BAND_BLOCKS, c->bb.X[s.nxt], c->bb.Y[s.nxt],
+                               c->bb.phi[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho,
+                               c->bb.health};
+            lb[k] = LbArgs{g, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt],
+                           c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win, s.wprev, s.wcur,
+                           fpo_x(c, nstep), fpo_y(c, nstep), c->bb.health, base};
+            base += (int)batch_tile_count(c->d, b->lb_variant);
+        }
+        const BatchTables& T = b->tab[p];
+        BCHK(b, hipMemcpyAsync(T.adv, adv.data(), n * sizeof(AdvectArgs), hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipMemcpyAsync(T.lay, lay.data(), n * sizeof(LayersArgs), hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipMemcpyAsync(T.fit, fit.data(), n * sizeof(FitArgs), hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipMemcpyAsync(T.rel, rel.data(), n * sizeof(RelabelArgs), hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipMemcpyAsync(T.edg, edg.data(), n * sizeof(EdgesArgs), hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipMemcpyAsync(T.lb, lb.data(), n * sizeof(LbArgs), hipMemcpyHostToDevice, b->st));
+        // the host vectors are reused for the next phase: wait for the copies
+        BCHK(b, hipStreamSynchronize(b->st));
+    }
+    if (!tile_sim.empty()) {
+        BCHK(b, hipMemcpyAsync(b->tile_sim, tile_sim.data(), tile_sim.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipStreamSynchronize(b->st));
+    }
+    return LBRMT_OK;
+}
+
+int batch_enqueue(lbrmt_batch* b, long long n, hipStream_t st)
+{
+    const int p = n == 0 ? 6 : (int)(n % 6);
+    const BatchTables& T = b->tab[p];
+    BCHK(b, launch_batch_band(b->precision, T, b->n, b->layers, st));
+    BCHK(b, launch_lb_batch(b->precision, b->lb_variant, T.lb, b->tile_sim, b->total_tiles, st));
+    return LBRMT_OK;
+}
+
+int batch_graph(lbrmt_batch* b)
+{
+    hipGraph_t graph = nullptr;
+    BCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = LBRMT_OK;
+    for (int k = 0; k < GRAPH_STEPS && rc == LBRMT_OK; k++) rc = batch_enqueue(b, 6 + k, b->cap);
+    hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (rc != LBRMT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return bfail(b, "hipStreamEndCapture", e);
+    e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return bfail(b, "hipGraphInstantiate", e);
+    }
+    return LBRMT_OK;
+}
+
+void batch_drop_graph(lbrmt_batch* b)
+{
+    if (b->gexec) {
+        (void)hipStreamSynchronize(b->st);
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+}
+
+}  // namespace
+
+int lbrmt_batch_workspace_bytes(const lbrmt_grid_desc* descs, int32_t n, size_t* bytes)
+{
+    if (!descs || n < 1 || !bytes) return LBRMT_EINVAL;
+    for (int k = 0; k < n; k++)
+        if (!desc_ok(&descs[k]) || descs[k].precision != descs[0].precision ||
+            descs[k].layers != descs[0].layers)
+            return LBRMT_EINVAL;
+    BatchLayout B;
+    if (!batch_layout(descs, n, B)) return LBRMT_EINVAL;
+    *bytes = B.total;
+    return LBRMT_OK;
+}
+
+int lbrmt_batch_create(const lbrmt_grid_desc* descs, const lbrmt_solid_desc* solids,
+                       const int32_t* has_solid, int32_t n, void* ws, size_t bytes, void* stream,
+                       lbrmt_batch** out)
+{
+    if (!descs || n < 1 || !ws || !out) return LBRMT_EINVAL;
+    size_t need = 0;
+    int rc = lbrmt_batch_workspace_bytes(descs, n, &need);
+    if (rc != LBRMT_OK) return rc;
+    if ((uintptr_t)ws % ALIGN || bytes < need) return LBRMT_EWORKSPACE;
+    BatchLayout B;
+    batch_layout(descs, n, B);
+    lbrmt_batch* b = new lbrmt_batch();
+    b->n = n;
+    b->precision = descs[0].precision;
+    b->layers = descs[0].layers;
+    b->lb_variant = b->precision == LBRMT_FP64 ? 3 : 5;
+    b->st = (hipStream_t)stream;
+    b->ws = (char*)ws;
+    size_t o = B.tables;
+    auto carve = [&](size_t bytes_) {
+        char* p_ = b->ws + o;
+        o = round_up(o + bytes_, ALIGN);
+        return p_;
+    };
+    for (int p = 0; p < 7; p++) {
+        b->tab[p].adv = (AdvectArgs*)carve(n * sizeof(AdvectArgs));
+        b->tab[p].lay = (LayersArgs*)carve(n * sizeof(LayersArgs));
+        b->tab[p].fit = (FitArgs*)carve(n * sizeof(FitArgs));
+        b->tab[p].rel = (RelabelArgs*)carve(n * sizeof(RelabelArgs));
+        b->tab[p].edg = (EdgesArgs*)carve(n * sizeof(EdgesArgs));
+        b->tab[p].lb = (LbArgs*)carve(n * sizeof(LbArgs));
+    }
+    b->tile_sim = (int*)(b->ws + B.tiles);
+    b->tile_cap = B.tile_cap;
+    b->m.assign(n, nullptr);
+    for (int k = 0; k < n && rc == LBRMT_OK; k++) {
+        rc = create_impl(&descs[k], 1, b->ws + B.member_off[k], B.member_bytes[k], stream,
+                         &b->m[k], true);
+        if (rc == LBRMT_OK && solids && (!has_solid || has_solid[k]))
+            rc = lbrmt_add_solids(b->m[k], &solids[k], 1);
+    }
+    if (rc == LBRMT_OK) {
+        hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) rc = bfail(b, "stream creation", e);
+    }
+    if (rc != LBRMT_OK) {
+        lbrmt_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBRMT_OK;
+}
+
+void lbrmt_batch_destroy(lbrmt_batch* b)
+{
+    if (!b) return;
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (auto c : b->m) lbrmt_destroy(c);
+    delete b;
+}
+
+int lbrmt_batch_init(lbrmt_batch* b)
+{
+    if (!b) return LBRMT_EINVAL;
+    for (auto c : b->m) {
+        int rc = lbrmt_init(c, nullptr);
+        if (rc != LBRMT_OK) {
+            b->err = c->err;
+            return rc;
+        }
+    }
+    batch_drop_graph(b);
+    int rc = batch_tables(b);
+    if (rc != LBRMT_OK) return rc;
+    b->step = 0;
+    b->inited = true;
+    return LBRMT_OK;
+}
+
+int lbrmt_batch_step(lbrmt_batch* b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return LBRMT_EINVAL;
+    if (!b->inited) return LBRMT_ESTATE;
+    int64_t left = nsteps;
+    while (left > 0) {
+        const bool use_graph = b->graph && b->step >= GRAPH_STEPS &&
+                               b->step % GRAPH_STEPS == 0 && left >= GRAPH_STEPS;
+        int adv = 1;
+        if (use_graph) {
+            if (!b->gexec) {
+                int rc = batch_graph(b);
+                if (rc != LBRMT_OK) return rc;
+            }
+            BCHK(b, hipGraphLaunch(b->gexec, b->st));
+            adv = GRAPH_STEPS;
+        } else {
+            int rc = batch_enqueue(b, b->step, b->st);
+            if (rc != LBRMT_OK) return rc;
+        }
+        b->step += adv;
+        left -= adv;
+        for (auto c : b->m) c->step += adv;
+    }
+    return LBRMT_OK;
+}
+
+int32_t lbrmt_batch_size(const lbrmt_batch* b) { return b ? b->n : -1; }
+
+lbrmt_ctx* lbrmt_batch_member(lbrmt_batch* b, int32_t k)
+{
+    if (!b || k < 0 || k >= b->n) return nullptr;
+    return b->m[k];
+}
+
+int lbrmt_batch_set_option(lbrmt_batch* b, int32_t option, int64_t value)
+{
+    if (!b) return LBRMT_EINVAL;
+    switch (option) {
+    case LBRMT_OPT_LB_VARIANT:
+        if (value < 0 || value >= lb_variant_count()) return LBRMT_EINVAL;
+        b->lb_variant = (int)value;
+        break;
+    case LBRMT_OPT_GRAPH:
+        if (value != 0 && value != 1) return LBRMT_EINVAL;
+        b->graph = value != 0;
+        break;
+    default:
+        return LBRMT_EINVAL;
+    }
+    batch_drop_graph(b);
+    if (b->inited) return batch_tables(b);
+    return LBRMT_OK;
+}
+
+int lbrmt_batch_get_option(const lbrmt_batch* b, int32_t option, int64_t* value)
+{
+    if (!b || !value) return LBRMT_EINVAL;
+    switch (option) {
+    case LBRMT_OPT_LB_VARIANT: *value = b->lb_variant; return LBRMT_OK;
+    case LBRMT_OPT_LB_VARIANT_COUNT: *value = lb_variant_count(); return LBRMT_OK;
+    case LBRMT_OPT_GRAPH: *value = b->graph ? 1 : 0; return LBRMT_OK;
+    default: return LBRMT_EINVAL;
+    }
+}
+
+int lbrmt_batch_autotune(lbrmt_batch* b, int32_t reps, int32_t* best_variant, double* best_ms)
+{
+    if (!b || reps < 1) return LBRMT_EINVAL;
+    if (!b->inited) return LBRMT_ESTATE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BCHK(b, hipEventCreate(&e0));
+    BCHK(b, hipEventCreate(&e1));
+    const int keep = b->lb_variant;
+    int best = keep;
+    float best_t = 1e30f;
+    const int p = b->step == 0 ? 6 : (int)(b->step % 6);
+    for (int v = 0; v < lb_variant_count(); v++) {
+        b->lb_variant = v;
+        int rc = batch_tables(b);  // tile list of this shape
+        if (rc != LBRMT_OK) return rc;
+        BCHK(b, launch_lb_batch(b->precision, v, b->tab[p].lb, b->tile_sim, b->total_tiles, b->st));
+        BCHK(b, hipEventRecord(e0, b->st));
+        for (int r = 0; r < reps; r++)
+            BCHK(b, launch_lb_batch(b->precision, v, b->tab[p].lb, b->tile_sim, b->total_tiles,
+                                    b->st));
+        BCHK(b, hipEventRecord(e1, b->st));
+        BCHK(b, hipEventSynchronize(e1));
+        float ms = 0.f;
+        BCHK(b, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_t) {
+            best_t = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)keep;
+    int rc = lbrmt_batch_set_option(b, LBRMT_OPT_LB_VARIANT, best);
+    if (rc != LBRMT_OK) return rc;
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t / reps;
+    return LBRMT_OK;
+}
+
+const char* lbrmt_batch_last_error(const lbrmt_batch* b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

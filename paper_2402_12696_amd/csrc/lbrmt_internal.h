@@ -74,6 +74,87 @@ struct BandBufs {
     unsigned* health;
 };
 
+// Arguments of the step kernels for one member of a batch (device tables,
+// one entry per member; the batched kernels take member blockIdx.y).  Plane
+// pointers are untyped: the batch precision picks the kernel instance.
+struct AdvectArgs {
+    GridP g;
+    const void* A;
+    const double *fpx, *fpy;
+    const void *X, *Y, *phi;
+    void *X1, *Y1;
+    int8_t* tag;
+    const Win* win;
+    int wprev, wcur;
+    unsigned* health;
+};
+struct LayersArgs {
+    GridP g;
+    const Win* win;
+    int wslot;
+    int8_t* tag;
+    int8_t* gcol;
+    int* lists;
+    int* lcount;
+    unsigned* health;
+};
+struct FitArgs {
+    GridP g;
+    const Win* win;
+    int wcur, wprev;
+    int8_t* tag;
+    const int* lists;
+    const int* lcount;
+    const void* phin;
+    void *X1, *Y1;
+    unsigned* health;
+};
+struct RelabelArgs {
+    GridP g;
+    BodyP b;
+    const int8_t* tag;
+    const Win* win;
+    int wcur;
+    void *X1, *Y1, *phi1;
+    int* boxpart;
+};
+struct EdgesArgs {
+    GridP g;
+    BodyP b;
+    Win* win;
+    int wvalid, wnext;
+    const int* boxpart;
+    int nbox;
+    const void *X, *Y, *phi;
+    double *o0, *o1, *o2;
+    unsigned* health;
+};
+struct LbArgs {
+    GridP g;
+    const void* A;
+    void* B;
+    const double *fpx, *fpy, *fcx, *fcy, *drho;
+    const Win* win;
+    int wprev, wcur;
+    double fpo_x, fpo_y;
+    unsigned* health;
+    int tile_base;  // first entry of this member in the flattened tile list
+};
+struct BatchTables {
+    AdvectArgs* adv;
+    LayersArgs* lay;
+    FitArgs* fit;
+    RelabelArgs* rel;
+    EdgesArgs* edg;
+    LbArgs* lb;
+};
+// blocks per member of the batched reference-map kernels (the distance
+// transform count is a multiple of NSUB and at most DT_BLOCKS, which the list
+// capacity assumes; relabel's partial boxes number BATCH_BAND_BLOCKS)
+constexpr int BATCH_BAND_BLOCKS = 128;
+constexpr int BATCH_DT_BLOCKS = 128;
+constexpr int BATCH_FIT_BLOCKS = 32;
+
 // Selection of the ring slots / buffers at state n (n completed steps).
 struct StepSlots {
     int cur;      // n % 2   : state buffers (lattice A, xi^n, F^n written this step)
@@ -163,6 +244,10 @@ __host__ __device__ __forceinline__ long long sub_cap(long long pplane)
 // Every launcher enqueues on `st` and returns hipGetLastError().
 
 // lattice Boltzmann (k_lb.hip)
+hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
+                             hipStream_t st);
+hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const int* tile_sim,
+                           int total_tiles, hipStream_t st);
 hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
                      const double* drho, const Win* win, int wprev, int wcur, double fpo_x,

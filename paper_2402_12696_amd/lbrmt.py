@@ -122,6 +122,28 @@ def lib():
             "lbrmt_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
             "lbrmt_get_option": (ctypes.c_int, [_vp, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_int64)]),
+            "lbrmt_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_double)]),
+            "lbrmt_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(lbrmt_grid_desc),
+                                                           ctypes.c_int32,
+                                                           ctypes.POINTER(ctypes.c_size_t)]),
+            "lbrmt_batch_create": (ctypes.c_int, [ctypes.POINTER(lbrmt_grid_desc),
+                                                  ctypes.POINTER(lbrmt_solid_desc),
+                                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                                  _vp, ctypes.c_size_t, _vp,
+                                                  ctypes.POINTER(_vp)]),
+            "lbrmt_batch_destroy": (None, [_vp]),
+            "lbrmt_batch_init": (ctypes.c_int, [_vp]),
+            "lbrmt_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+            "lbrmt_batch_size": (ctypes.c_int32, [_vp]),
+            "lbrmt_batch_member": (_vp, [_vp, ctypes.c_int32]),
+            "lbrmt_batch_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
+            "lbrmt_batch_get_option": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                                      ctypes.POINTER(ctypes.c_int64)]),
+            "lbrmt_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                                    ctypes.POINTER(ctypes.c_int32),
+                                                    ctypes.POINTER(ctypes.c_double)]),
+            "lbrmt_batch_last_error": (ctypes.c_char_p, [_vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -293,6 +315,81 @@ def lbrmt_get_option(ctx, option):
     return v.value
 
 
+def lbrmt_autotune(ctx, reps=5):
+    v, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().lbrmt_autotune(ctx, int(reps), ctypes.byref(v), ctypes.byref(ms)),
+           "lbrmt_autotune", ctx)
+    return v.value, ms.value
+
+
+def _bcheck(rc, where, batch=None):
+    if rc != LBRMT_OK:
+        detail = lib().lbrmt_batch_last_error(batch).decode() if batch else ""
+        raise LBRMTError(rc, where, detail)
+
+
+def lbrmt_batch_workspace_bytes(descs):
+    arr = (lbrmt_grid_desc * len(descs))(*descs)
+    out = ctypes.c_size_t(0)
+    _bcheck(lib().lbrmt_batch_workspace_bytes(arr, len(descs), ctypes.byref(out)),
+            "lbrmt_batch_workspace_bytes")
+    return out.value
+
+
+def lbrmt_batch_create(descs, solids, has_solid, workspace, nbytes, stream=None):
+    n = len(descs)
+    d = (lbrmt_grid_desc * n)(*descs)
+    s = (lbrmt_solid_desc * n)(*solids) if solids is not None else None
+    h = (ctypes.c_int32 * n)(*[int(x) for x in has_solid]) if has_solid is not None else None
+    b = _vp()
+    _bcheck(lib().lbrmt_batch_create(d, s, h, n, _ptr(workspace), nbytes,
+                                     stream if stream is not None else _stream(),
+                                     ctypes.byref(b)), "lbrmt_batch_create")
+    return b
+
+
+def lbrmt_batch_destroy(batch):
+    lib().lbrmt_batch_destroy(batch)
+
+
+def lbrmt_batch_init(batch):
+    _bcheck(lib().lbrmt_batch_init(batch), "lbrmt_batch_init", batch)
+
+
+def lbrmt_batch_step(batch, n):
+    _bcheck(lib().lbrmt_batch_step(batch, int(n)), "lbrmt_batch_step", batch)
+
+
+def lbrmt_batch_size(batch):
+    return lib().lbrmt_batch_size(batch)
+
+
+def lbrmt_batch_member(batch, k):
+    m = lib().lbrmt_batch_member(batch, int(k))
+    if not m:
+        raise LBRMTError(LBRMT_EINVAL, "lbrmt_batch_member", f"no member {k}")
+    return _vp(m)
+
+
+def lbrmt_batch_set_option(batch, option, value):
+    _bcheck(lib().lbrmt_batch_set_option(batch, int(option), int(value)),
+            "lbrmt_batch_set_option", batch)
+
+
+def lbrmt_batch_get_option(batch, option):
+    v = ctypes.c_int64(0)
+    _bcheck(lib().lbrmt_batch_get_option(batch, int(option), ctypes.byref(v)),
+            "lbrmt_batch_get_option", batch)
+    return v.value
+
+
+def lbrmt_batch_autotune(batch, reps=5):
+    v, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _bcheck(lib().lbrmt_batch_autotune(batch, int(reps), ctypes.byref(v), ctypes.byref(ms)),
+            "lbrmt_batch_autotune", batch)
+    return v.value, ms.value
+
+
 # ------------------------------------------------------------ convenience
 
 class Sim:
@@ -302,6 +399,22 @@ class Sim:
     periodic_y, gravity, fext, rho_f, eps, layers, r_max, det_rel, detJ_min,
     solid={cx, cy, R, G, rho_s}) plus precision="f64"|"f32".
     """
+
+    owner = True
+
+    @classmethod
+    def _view(cls, ctx, device, cfg):
+        """Read-only view of a context owned elsewhere (a batch member)."""
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.device = torch.device(device)
+        self.cfg = dict(cfg)
+        self.nx, self.ny = cfg["nx"], cfg["ny"]
+        self.nsolid = 1 if cfg.get("solid") else 0
+        self.ctx = ctx
+        self.owner = False
+        return self
 
     def __init__(self, device="cuda:0", **cfg):
         import torch
@@ -325,8 +438,9 @@ class Sim:
 
     def close(self):
         if getattr(self, "ctx", None):
-            self.torch.cuda.synchronize(self.device)
-            lbrmt_destroy(self.ctx)
+            if self.owner:
+                self.torch.cuda.synchronize(self.device)
+                lbrmt_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):
@@ -409,3 +523,70 @@ class Sim:
 
     def get_option(self, option):
         return lbrmt_get_option(self.ctx, option)
+
+    def autotune(self, reps=5):
+        return lbrmt_autotune(self.ctx, reps)
+
+
+class Batch:
+    """Independent simulations stepped together (one launch per kernel for all
+    members).  cfgs: a list of ``workloads.make`` configurations sharing the
+    precision and layer count; members are read through ``member(k)``, a
+    read-only ``Sim`` view."""
+
+    def __init__(self, cfgs, device="cuda:0", precision=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("Batch needs a HIP GPU (torch.cuda) device")
+        torch.cuda.set_device(self.device)
+        self.cfgs = [dict(c, precision=precision) if precision else dict(c) for c in cfgs]
+        descs = [make_grid_desc(**c) for c in self.cfgs]
+        solids = [make_solid_desc(**c["solid"]) if c.get("solid") else
+                  lbrmt_solid_desc(0, 0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0) for c in self.cfgs]
+        has = [1 if c.get("solid") else 0 for c in self.cfgs]
+        nbytes = lbrmt_batch_workspace_bytes(descs)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.batch = lbrmt_batch_create(descs, solids, has, self._ws, nbytes)
+        self.members = [Sim._view(lbrmt_batch_member(self.batch, k), device, c)
+                        for k, c in enumerate(self.cfgs)]
+
+    def __len__(self):
+        return len(self.members)
+
+    def init(self):
+        lbrmt_batch_init(self.batch)
+        return self
+
+    def step(self, n=1):
+        lbrmt_batch_step(self.batch, n)
+        return self
+
+    def member(self, k):
+        return self.members[k]
+
+    def set_option(self, option, value):
+        lbrmt_batch_set_option(self.batch, option, value)
+
+    def get_option(self, option):
+        return lbrmt_batch_get_option(self.batch, option)
+
+    def autotune(self, reps=5):
+        return lbrmt_batch_autotune(self.batch, reps)
+
+    def close(self):
+        if getattr(self, "batch", None):
+            self.torch.cuda.synchronize(self.device)
+            for m in self.members:
+                m.ctx = None
+            lbrmt_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

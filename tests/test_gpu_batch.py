@@ -1,0 +1,104 @@
+"""Batched stepping of independent simulations against single contexts.
+
+Contract: every member of a batch follows exactly the arithmetic of a single
+context with the same description, so after any number of steps (eager steps
+0..5, then six-step graph replays) its fields are bitwise identical to those
+of the member stepped alone; single contexts are themselves at oracle parity
+(test_gpu_parity, test_gpu_fp32), and one member is also checked against the
+oracle directly.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Oracle
+from test_gpu_parity import _np, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _members():
+    # uneven sizes, a ragged periodic grid with gravity and density contrast,
+    # and a member without a solid
+    return [
+        workloads.cavity_disc_64(),
+        workloads.make(nx=96, ny=96, tau=0.7, lid_ux=0.06,
+                       solid=dict(cx=48.0, cy=57.6, R=16.0, G=0.01, rho_s=1.0), name="m96"),
+        workloads.make(nx=100, ny=70, tau=0.7, periodic_x=True, lid_ux=0.04,
+                       gravity=(0.0, -2e-5),
+                       solid=dict(cx=50.0, cy=36.0, R=10.5, G=0.02, rho_s=1.3), name="ragged"),
+        workloads.make(nx=72, ny=40, tau=0.9, lid_ux=0.05, name="fluid_only"),
+        workloads.make(nx=160, ny=160, tau=0.6, lid_ux=0.08,
+                       solid=dict(cx=80.0, cy=96.0, R=30.0, G=0.005, rho_s=1.0), name="m160"),
+    ]
+
+
+def _fields(sim):
+    out = _np(sim.macro())
+    if sim.nsolid:
+        out += _np(sim.refmap())
+    return out
+
+
+def _same(a, b, what):
+    for x, y in zip(a, b):
+        assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0)), what
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_members_equal_single_contexts_bitwise(precision):
+    from paper_2402_12696_amd import Batch, Sim
+    cfgs = _members()
+    batch = Batch(cfgs, precision=precision).init()
+    batch.step(5)       # eager steps 0..4
+    batch.step(31)      # 5 eager, then graph replays from step 6
+    for k, c in enumerate(cfgs):
+        single = Sim(device="cuda:0", precision=precision, **c).init().step(36)
+        assert batch.member(k).step_count == 36
+        _same(_fields(batch.member(k)), _fields(single), f"{precision} member {k} ({c['name']})")
+        single.close()
+    for k in range(len(cfgs)):
+        assert all(v == 0 for v in batch.member(k).diag()["health"].values())
+    batch.close()
+
+
+def test_batch_member_matches_oracle():
+    from paper_2402_12696_amd import Batch
+    cfgs = _members()
+    batch = Batch(cfgs).init().step(100)
+    ref = Oracle(**cfgs[0]).init()
+    ref.step(100)
+    compare(batch.member(0), ref, what="batch member 0 step 100")
+    batch.close()
+
+
+def test_autotuners_keep_state_and_results():
+    from paper_2402_12696_amd import Batch, Sim
+    cfg = workloads.cavity_disc_64()
+    a = Sim(device="cuda:0", **cfg).init().step(20)
+    v, ms = a.autotune(reps=2)
+    assert 0 <= v < a.get_option(2) and ms > 0 and a.get_option(1) == v
+    a.step(20)
+    b = Sim(device="cuda:0", **cfg).init().step(40)
+    _same(_fields(a), _fields(b), "single autotune")
+    cfgs = _members()
+    batch = Batch(cfgs).init().step(13)
+    v, ms = batch.autotune(reps=2)
+    assert 0 <= v < batch.get_option(2) and ms > 0 and batch.get_option(1) == v
+    batch.step(27)
+    for k, c in enumerate(cfgs):
+        single = Sim(device="cuda:0", **c).init().step(40)
+        _same(_fields(batch.member(k)), _fields(single), f"batch autotune member {k}")
+        single.close()
+    batch.close()
+
+
+def test_batch_member_is_read_only():
+    from paper_2402_12696_amd import Batch, LBRMTError
+    batch = Batch(_members()[:2]).init()
+    m = batch.member(1)
+    with pytest.raises(LBRMTError):
+        m.step(1)
+    with pytest.raises(LBRMTError):
+        m.set_option(0, 1)
+    batch.close()

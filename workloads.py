@@ -77,3 +77,24 @@ def taylor_green_velocity(n, u0):
     u[0] = -u0 * np.cos(k * X) * np.sin(k * Y)
     u[1] = u0 * np.sin(k * X) * np.cos(k * Y)
     return u
+
+
+def cavity_ensemble(n=96, seed=4):
+    """Ensemble of independent cavity-disc simulations of uneven sizes (the
+    batched workload): for each member in order, side L drawn uniformly from
+    {96, 128, ..., 768}, tau ~ U[0.55, 1.0], lid ~ U[0.02, 0.1],
+    R ~ U[0.1, 0.25] L, log10 G ~ U[-3, log10 0.03]; disc at (0.5 L, 0.6 L),
+    density ratio 1; numpy default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    sides = np.arange(96, 769, 32)
+    out = []
+    for k in range(n):
+        L = int(rng.choice(sides))
+        tau = float(rng.uniform(0.55, 1.0))
+        U = float(rng.uniform(0.02, 0.1))
+        R = float(rng.uniform(0.1, 0.25)) * L
+        G = float(10.0 ** rng.uniform(-3.0, np.log10(0.03)))
+        out.append(make(nx=L, ny=L, tau=tau, lid_ux=U,
+                        solid=dict(cx=0.5 * L, cy=0.6 * L, R=R, G=G, rho_s=1.0),
+                        name=f"ensemble_{seed}_{k}"))
+    return out
