@@ -105,6 +105,48 @@ def copy_ceiling(nbytes, reps=20):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def run_ensemble(precision, steps, seq_steps=120, seq_warmup=12):
+    """The seeded 96-member cavity ensemble: one batch (autotuned tile shape)
+    for `steps` steps, against each member stepped alone (same precision and
+    FP64) for seq_steps steps after seq_warmup; sequential times are per-step
+    averages scaled to `steps`."""
+    import torch
+    import workloads
+    from paper_2402_12696_amd import Batch, Sim
+    cfgs = workloads.cavity_ensemble()
+    nodes = sum(c["nx"] * c["ny"] for c in cfgs)
+    out = {"workload": "cavity_ensemble_96 (seed 4)", "members": len(cfgs), "nodes": nodes,
+           "steps": steps, "precision": precision}
+    batch = Batch(cfgs, precision=precision).init()
+    batch.step(12)
+    out["autotuned_variant"], _ = batch.autotune(reps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps - 12)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / (steps - 12)
+    out["ms_per_step"] = ms
+    out["mlups"] = nodes / (ms * 1e-3) / 1e6
+    bad = [k for k in range(len(cfgs))
+           if any(v for v in batch.member(k).diag(raise_unstable=False)["health"].values())]
+    out["members_with_health_flags"] = bad
+    batch.close()
+    for prec in (precision, "f64") if precision != "f64" else ("f64",):
+        tot = 0.0
+        for c in cfgs:
+            sim = Sim(device="cuda:0", precision=prec, **c).init()
+            sim.step(seq_warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(seq_steps)
+            torch.cuda.synchronize()
+            tot += (time.perf_counter() - t0) * 1e3 / seq_steps
+            sim.close()
+        out[f"sequential_{prec}_ms_per_step"] = tot
+        out[f"speedup_vs_sequential_{prec}"] = tot / ms
+    return out
+
+
 def cpu_baseline(cfg, seconds=15.0):
     from oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -136,6 +178,10 @@ def main():
                     help="1: reference-map chain on a side stream (library default 0)")
     ap.add_argument("--lb-variant", type=int, default=None,
                     help="lattice tile variant (library default 3 for f64, 5 for f32)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 96-member ensemble (batched vs sequential)")
+    ap.add_argument("--batch-steps", type=int, default=600,
+                    help="steps of the ensemble (its stiffest members blow up after ~700)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain elementwise copy (FP32 negation) reading and "
                          "writing this many bytes: the reference dispatch that scales HBM "
@@ -185,6 +231,8 @@ def main():
         extra["f32"] = {"ms_per_step": ms32, "mlups": nodes / (ms32 * 1e-3) / 1e6,
                         "speedup_vs_f64": ms / ms32,
                         "lb_bulk_avg_ms": kt32["lb_bulk"][0]}
+    if not args.no_batch:
+        extra["batched"] = run_ensemble("f32", args.batch_steps)
     line = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

@@ -709,28 +709,37 @@ __device__ __forceinline__ V group_sum(V v)
 }
 
 // Sums of the normal equations over the nodes of the scan window of
-// half-width r (side = 2r + 1) that fall to this lane: window node q goes to
-// lane q mod FIT_LANES; each lane issues all its loads before adding.
-template <int SIDE, typename T>
+// half-width r (side 2r + 1, nodes q = 0 .. side^2 - 1 row by row) that fall
+// to this lane: node q goes to lane q mod FIT_LANES; each lane issues the
+// loads of PER nodes before adding them.  The offsets (a, b) of node q are
+// stepped along instead of divided out.
+template <typename T>
 __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l, int i, int j,
-                                           int kt, int side, int sub, bool use_n, double nxh,
+                                           int kt, int r, int sub, bool use_n, double nxh,
                                            double nyh, const int8_t* tag, const T* X1,
                                            const T* Y1, Fit<T>& f, int& count)
 {
     constexpr int PER = 4;  // window nodes per lane and pass: 25 of r = 2 in one pass
-    if (SIDE > 0) side = SIDE;
-    const int r = side / 2, nq = side * side;
-    for (int q0 = 0; q0 < nq; q0 += PER * FIT_LANES) {
+    const int side = 2 * r + 1, nq = side * side;
+    // offsets of this lane's first node
+    int a = sub % side - r, b = sub / side - r;
+    for (int q0 = sub; q0 < nq; q0 += PER * FIT_LANES) {
         long long kk[PER];
         int tk[PER], aa[PER], bb[PER];
         T xv[PER], yv[PER];
 #pragma unroll
         for (int u = 0; u < PER; u++) {
-            const int q = q0 + sub + u * FIT_LANES;
-            aa[u] = q % side - r;
-            bb[u] = q / side - r;
-            int ci = i + aa[u], cj = j + bb[u];
-            kk[u] = (q < nq && canon(g, ci, cj) && W.has(ci, cj)) ? pidx(g, ci, cj) : -1;
+            aa[u] = a;
+            bb[u] = b;
+            int ci = i + a, cj = j + b;
+            kk[u] = (q0 + u * FIT_LANES < nq && canon(g, ci, cj) && W.has(ci, cj))
+                        ? pidx(g, ci, cj) : -1;
+            // advance by FIT_LANES nodes along the rows
+            a += FIT_LANES;
+            while (a > r) {
+                a -= side;
+                b += 1;
+            }
         }
 #pragma unroll
         for (int u = 0; u < PER; u++) {
@@ -746,6 +755,34 @@ __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l,
             f.add(aa[u], bb[u], use_n, nxh, nyh, xv[u], yv[u]);
         }
     }
+}
+
+// scan window of half-width r = side / 2: reduced normal equations and the
+// intercept, if the window holds three valid nodes and the fit is well posed
+template <typename T>
+__device__ __forceinline__ bool fit_at(const GridP& g, const Rect& W, int l, int i, int j, int kt,
+                                       int r, int sub, bool use_n, double nxh, double nyh,
+                                       const int8_t* tag, const T* X1, const T* Y1, T& xo, T& yo)
+{
+    Fit<T> f;
+    f.zero();
+    int count = 0;
+    fit_window<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, f, count);
+    count = group_sum(count);
+    if (count < 3) return false;
+    f.M00 = group_sum(f.M00);
+    f.M01 = group_sum(f.M01);
+    f.M02 = group_sum(f.M02);
+    f.M11 = group_sum(f.M11);
+    f.M12 = group_sum(f.M12);
+    f.M22 = group_sum(f.M22);
+    f.bX0 = group_sum(f.bX0);
+    f.bX1 = group_sum(f.bX1);
+    f.bX2 = group_sum(f.bX2);
+    f.bY0 = group_sum(f.bY0);
+    f.bY1 = group_sum(f.bY1);
+    f.bY2 = group_sum(f.bY2);
+    return f.solve(g.det_rel, xo, yo);
 }
 
 // One layer of Sec. 3.2: every target of the layer list is fitted by a group
@@ -797,34 +834,10 @@ __device__ __forceinline__ void layer_fit_body(GridP g, const Win* __restrict__ 
             const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
             use_n = normal_from(pe, pw, pn, ps, nxh, nyh);
         }
-        bool done = false;
         T xo = T(0), yo = T(0);
-        for (int r = 2; r <= g.r_max && !done; r++) {
-            Fit<T> f;
-            f.zero();
-            int count = 0;
-            if (r == 2)
-                fit_window<5, T>(g, W, l, i, j, kt, 5, sub, use_n, nxh, nyh, tag, X1, Y1, f,
-                                 count);
-            else
-                fit_window<0, T>(g, W, l, i, j, kt, 2 * r + 1, sub, use_n, nxh, nyh, tag, X1, Y1,
-                                 f, count);
-            count = group_sum(count);
-            if (count < 3) continue;
-            f.M00 = group_sum(f.M00);
-            f.M01 = group_sum(f.M01);
-            f.M02 = group_sum(f.M02);
-            f.M11 = group_sum(f.M11);
-            f.M12 = group_sum(f.M12);
-            f.M22 = group_sum(f.M22);
-            f.bX0 = group_sum(f.bX0);
-            f.bX1 = group_sum(f.bX1);
-            f.bX2 = group_sum(f.bX2);
-            f.bY0 = group_sum(f.bY0);
-            f.bY1 = group_sum(f.bY1);
-            f.bY2 = group_sum(f.bY2);
-            done = f.solve(g.det_rel, xo, yo);
-        }
+        bool done = false;
+        for (int r = 2; r <= g.r_max && !done; r++)
+            done = fit_at<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, xo, yo);
         if (sub == 0) {
             if (done) {
                 X1[kt] = xo;
