@@ -73,6 +73,14 @@ __device__ __forceinline__ T store_phi(double p)
     return v;
 }
 
+// clears the layer counters of a step (block 0 of the kernel before the
+// distance transform)
+__device__ __forceinline__ void clear_lcount(int* lcount)
+{
+    if (blockIdx.x == 0 && threadIdx.x < (MAX_LAYERS + 1) * NSUB)
+        lcount[threadIdx.x * LCOUNT_PAD] = 0;
+}
+
 // tags: TAG_NONE, TAG_SOLID, layer l (1..layers), or layer | TAG_FAIL
 __device__ __forceinline__ bool tag_valid_before(int t, int l)
 {
@@ -249,8 +257,9 @@ hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, const BandBufs&
 
 // initial tags over the window (solid / none)
 __global__ __launch_bounds__(256) void k_init_tags(GridP g, BodyP b, int8_t* tag, const Win* win,
-                                                   int wslot)
+                                                   int wslot, int* lcount)
 {
+    clear_lcount(lcount);
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
@@ -265,7 +274,7 @@ __global__ __launch_bounds__(256) void k_init_tags(GridP g, BodyP b, int8_t* tag
 hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st)
 {
-    k_init_tags<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot);
+    k_init_tags<<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, bb.lcount);
     return hipGetLastError();
 }
 
@@ -354,9 +363,10 @@ __device__ __forceinline__ void advect_body(GridP g, const S* __restrict__ A,
                                                 const S* __restrict__ X, const S* __restrict__ Y,
                                                 const S* __restrict__ phi, S* X1, S* Y1,
                                                 int8_t* tag, const Win* __restrict__ win,
-                                                int wprev, int wcur, unsigned* health)
+                                                int wprev, int wcur, int* lcount, unsigned* health)
 {
     using C = S;
+    clear_lcount(lcount);
     constexpr bool DISP = sizeof(S) == 4;
     const Rect W = window_of(win, wcur, g);
     if (!W.ok) return;
@@ -447,9 +457,9 @@ __global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A
                                                 const S* __restrict__ X, const S* __restrict__ Y,
                                                 const S* __restrict__ phi, S* X1, S* Y1,
                                                 int8_t* tag, const Win* __restrict__ win,
-                                                int wprev, int wcur, unsigned* health)
+                                                int wprev, int wcur, int* lcount, unsigned* health)
 {
-    advect_body<S>(g, A, fpx, fpy, X, Y, phi, X1, Y1, tag, win, wprev, wcur, health);
+    advect_body<S>(g, A, fpx, fpy, X, Y, phi, X1, Y1, tag, win, wprev, wcur, lcount, health);
 }
 
 // batched form: member blockIdx.y of a table of arguments
@@ -458,7 +468,8 @@ __global__ __launch_bounds__(256) void kb_advect(const AdvectArgs* __restrict__ 
 {
     const AdvectArgs& a = args[blockIdx.y];
     advect_body<S>(a.g, (const S*)a.A, a.fpx, a.fpy, (const S*)a.X, (const S*)a.Y,
-                   (const S*)a.phi, (S*)a.X1, (S*)a.Y1, a.tag, a.win, a.wprev, a.wcur, a.health);
+                   (const S*)a.phi, (S*)a.X1, (S*)a.Y1, a.tag, a.win, a.wprev, a.wcur, a.lcount,
+                   a.health);
 }
 
 hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
@@ -472,12 +483,12 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
         k_advect<double><<<2048, 256, 0, st>>>(
             g, (const double*)A, fpx, fpy, (const double*)bb.X[s.cur], (const double*)bb.Y[s.cur],
             (const double*)bb.phi[s.cur], (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt], bb.tag,
-            bb.win, s.wprev, s.wcur, bb.health);
+            bb.win, s.wprev, s.wcur, bb.lcount, bb.health);
     else
         k_advect<float><<<2048, 256, 0, st>>>(
             g, (const float*)A, fpx, fpy, (const float*)bb.X[s.cur], (const float*)bb.Y[s.cur],
             (const float*)bb.phi[s.cur], (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt], bb.tag,
-            bb.win, s.wprev, s.wcur, bb.health);
+            bb.win, s.wprev, s.wcur, bb.lcount, bb.health);
     return hipGetLastError();
 }
 
@@ -488,129 +499,128 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
 // is the Manhattan distance to the solid set, computed here exactly in two
 // separable passes: per column, the distance to the nearest solid node of the
 // column (capped at layers + 1); per row, min over |e| of |e| + that distance.
-__device__ __forceinline__ void dt_cols_body(GridP g, const Win* __restrict__ win, int wslot,
-                                                 const int8_t* __restrict__ tag, int8_t* gcol,
-                                                 int* lcount)
-{
-    if (blockIdx.x == 0 && threadIdx.x < (MAX_LAYERS + 1) * NSUB)
-        lcount[threadIdx.x * LCOUNT_PAD] = 0;
-    const Rect W = window_of(win, wslot, g);
-    if (!W.ok) return;
-    const int L = g.layers;
-    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)w * h;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-        int best = L + 1;
-        for (int d = -L; d <= L; d++) {
-            const int jj = j + d;
-            const bool in = jj >= W.j0 && jj <= W.j1;
-            const int8_t t = tag[pidx(g, i, in ? jj : j)];
-            if (in && t == TAG_SOLID) best = min(best, abs(d));
-        }
-        gcol[pidx(g, i, j)] = (int8_t)best;
-    }
-}
+// One block takes a DTX x DTY tile of the window at a time: it stages the
+// solid flags of the tile plus a halo of `layers` nodes in LDS, runs both
+// passes there, writes the layer numbers and lists the zone nodes of each
+// layer (split into NSUB sub-lists by block so that few blocks share a
+// counter; the order inside a list does not matter since targets of one layer
+// are independent).  The layer counters were cleared by the kernel before.
+constexpr int DTX = 64, DTY = 16;
+constexpr int DRW = DTX + 2 * MAX_LAYERS, DRH = DTY + 2 * MAX_LAYERS;
 
-__global__ __launch_bounds__(256) void k_dt_cols(GridP g, const Win* __restrict__ win, int wslot,
-                                                 const int8_t* __restrict__ tag, int8_t* gcol,
-                                                 int* lcount)
+// LC > 0: the layer count as a compile-time constant (scans unrolled);
+// LC = 0: the count of the grid
+template <int LC>
+__device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ win, int wslot,
+                                             int8_t* tag, int* lists, int* lcount,
+                                             unsigned* health)
 {
-    dt_cols_body(g, win, wslot, tag, gcol, lcount);
-}
-
-__global__ __launch_bounds__(256) void kb_dt_cols(const LayersArgs* __restrict__ args)
-{
-    const LayersArgs& a = args[blockIdx.y];
-    dt_cols_body(a.g, a.win, a.wslot, a.tag, a.gcol, a.lcount);
-}
-
-// Row pass of the distance transform: exact layer numbers (Manhattan distance
-// to S^{n+1}, up to the layer count) and the lists of the zone nodes of each
-// layer, split into NSUB sub-lists by block so that few blocks share a
-// counter.  A block counts its nodes per layer in LDS, reserves room in its
-// sub-list with one global atomic per layer present, then writes.  The order
-// of a list does not matter since targets of one layer are independent.
-__device__ __forceinline__ void dt_rows_body(GridP g, const Win* __restrict__ win, int wslot,
-                                                 int8_t* tag, const int8_t* __restrict__ gcol,
-                                                 int* lists, int* lcount, unsigned* health)
-{
+    __shared__ int8_t sol[DRH * DRW];   // solid flags of the tile and its halo
+    __shared__ int8_t gc[DTY * DRW];    // column distances of the tile rows
     __shared__ int cnt[MAX_LAYERS + 1];
     __shared__ int base[MAX_LAYERS + 1];
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
-    const int L = g.layers;
+    const int L = LC > 0 ? LC : g.layers;
     const long long cap = sub_cap(g.pplane);
     const int sub = blockIdx.x % NSUB;
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    const long long total = (long long)w * h, stride = (long long)gridDim.x * blockDim.x;
-    const long long iters = (total + stride - 1) / stride;
+    const int ntx = (w + DTX - 1) / DTX, nty = (h + DTY - 1) / DTY;
+    const int rw = DTX + 2 * L, rh = DTY + 2 * L;  // region in use
     const int lane = __lane_id();
-    for (long long it = 0; it < iters; it++) {
+    for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
+        const int x0 = W.i0 + (t % ntx) * DTX, y0 = W.j0 + (t / ntx) * DTY;
         if (threadIdx.x <= MAX_LAYERS) cnt[threadIdx.x] = 0;
+        // solid flags of the region (nodes outside the window hold none)
+        for (int e = threadIdx.x; e < rw * rh; e += blockDim.x) {
+            const int x = x0 - L + e % rw, y = y0 - L + e / rw;
+            const bool in = W.has(x, y);
+            const int8_t tv = tag[in ? pidx(g, x, y) : pidx(g, W.i0, W.j0)];
+            sol[(e / rw) * DRW + e % rw] = (in && tv == TAG_SOLID) ? 1 : 0;
+        }
         __syncthreads();
-        const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x + it * stride;
-        int lay = 0;
-        int k = 0;
-        if (e < total) {
-            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-            k = (int)pidx(g, i, j);
-            if (tag[k] != TAG_SOLID) {
+        // column pass over the tile rows, the whole region width
+        for (int e = threadIdx.x; e < rw * DTY; e += blockDim.x) {
+            const int cx = e % rw, cy = e / rw;
+            int best = L + 1;
+#pragma unroll
+            for (int d = -L; d <= L; d++)
+                if (sol[(cy + L + d) * DRW + cx]) best = min(best, abs(d));
+            gc[cy * DRW + cx] = (int8_t)best;
+        }
+        __syncthreads();
+        // row pass: DTX x DTY nodes, NPT per thread, row-major in waves; each
+        // node's slot in the block's share of its layer list comes from one
+        // LDS atomic per wave and layer present
+        constexpr int NPT = DTX * DTY / 256;
+        int lay[NPT], kk[NPT], slot[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; u++) {
+            const int e = u * blockDim.x + threadIdx.x;
+            const int cx = e % DTX, cy = e / DTX;
+            const int x = x0 + cx, y = y0 + cy;
+            lay[u] = 0;
+            kk[u] = 0;
+            slot[u] = 0;
+            if (W.has(x, y) && !sol[(cy + L) * DRW + cx + L]) {
                 int best = 2 * L + 2;
-                for (int d = -L; d <= L; d++) {
-                    const int ii = i + d;
-                    const bool in = ii >= W.i0 && ii <= W.i1;
-                    const int gv = gcol[pidx(g, in ? ii : i, j)];
-                    if (in) best = min(best, abs(d) + gv);
-                }
-                if (best <= L) {
-                    tag[k] = (int8_t)best;
-                    lay = best;
-                }
+#pragma unroll
+                for (int d = -L; d <= L; d++) best = min(best, abs(d) + gc[cy * DRW + cx + L + d]);
+                kk[u] = (int)pidx(g, x, y);
+                if (best <= L) lay[u] = best;
+                tag[kk[u]] = lay[u] > 0 ? (int8_t)lay[u] : TAG_NONE;
+            }
+            for (int l = 1; l <= L; l++) {
+                const unsigned long long mask = __ballot(lay[u] == l);
+                if (mask == 0ull) continue;
+                const int leader = __ffsll((long long)mask) - 1;
+                int wb = 0;
+                if (lane == leader) wb = atomicAdd(&cnt[l], __popcll(mask));
+                wb = __shfl(wb, leader);
+                if (lay[u] == l) slot[u] = wb + __popcll(mask & ((1ull << lane) - 1ull));
             }
         }
-        // slot inside the block: one LDS atomic per wave and layer present
-        int slot = 0;
-        for (int l = 1; l <= L; l++) {
-            const unsigned long long mask = __ballot(lay == l);
-            if (mask == 0ull) continue;
-            const int leader = __ffsll((long long)mask) - 1;
-            int wb = 0;
-            if (lane == leader) wb = atomicAdd(&cnt[l], __popcll(mask));
-            wb = __shfl(wb, leader);
-            if (lay == l) slot = wb + __popcll(mask & ((1ull << lane) - 1ull));
-        }
         __syncthreads();
+        // one reservation per layer present in the tile
         if (threadIdx.x >= 1 && threadIdx.x <= L && cnt[threadIdx.x] > 0)
             base[threadIdx.x] =
                 atomicAdd(&lcount[(threadIdx.x * NSUB + sub) * LCOUNT_PAD], cnt[threadIdx.x]);
         __syncthreads();
-        if (lay > 0) {
-            const long long at = (long long)base[lay] + slot;
-            if (at < cap) lists[(lay * NSUB + sub) * cap + at] = k;
-            else atomicAdd(&health[7], 1u);  // cannot happen: see sub_cap
+#pragma unroll
+        for (int u = 0; u < NPT; u++) {
+            if (lay[u] > 0) {
+                const long long at = (long long)base[lay[u]] + slot[u];
+                if (at < cap) lists[(lay[u] * NSUB + sub) * cap + at] = kk[u];
+                else atomicAdd(&health[7], 1u);  // beyond the sub-list capacity
+            }
         }
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void k_dt_rows(GridP g, const Win* __restrict__ win, int wslot,
-                                                 int8_t* tag, const int8_t* __restrict__ gcol,
-                                                 int* lists, int* lcount, unsigned* health)
+template <int LC>
+__global__ __launch_bounds__(256) void k_dt_tile(GridP g, const Win* __restrict__ win, int wslot,
+                                                 int8_t* tag, int* lists, int* lcount,
+                                                 unsigned* health)
 {
-    dt_rows_body(g, win, wslot, tag, gcol, lists, lcount, health);
+    dt_tile_body<LC>(g, win, wslot, tag, lists, lcount, health);
 }
 
-__global__ __launch_bounds__(256) void kb_dt_rows(const LayersArgs* __restrict__ args)
+template <int LC>
+__global__ __launch_bounds__(256) void kb_dt_tile(const LayersArgs* __restrict__ args)
 {
     const LayersArgs& a = args[blockIdx.y];
-    dt_rows_body(a.g, a.win, a.wslot, a.tag, a.gcol, a.lists, a.lcount, a.health);
+    dt_tile_body<LC>(a.g, a.win, a.wslot, a.tag, a.lists, a.lcount, a.health);
 }
 
 hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStream_t st)
 {
-    k_dt_cols<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol, bb.lcount);
-    k_dt_rows<<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.gcol, bb.lists, bb.lcount,
-                                         bb.health);
+    if (g.layers == 11)
+        k_dt_tile<11><<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.lists, bb.lcount,
+                                                 bb.health);
+    else
+        k_dt_tile<0><<<DT_BLOCKS, 256, 0, st>>>(g, bb.win, wslot, bb.tag, bb.lists, bb.lcount,
+                                                bb.health);
     return hipGetLastError();
 }
 
@@ -1271,15 +1281,15 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
     const dim3 gb(BATCH_BAND_BLOCKS, nsim), gd(BATCH_DT_BLOCKS, nsim), gf(BATCH_FIT_BLOCKS, nsim);
     if (precision == 0) {
         kb_advect<double><<<gb, 256, 0, st>>>(t.adv);
-        kb_dt_cols<<<gd, 256, 0, st>>>(t.lay);
-        kb_dt_rows<<<gd, 256, 0, st>>>(t.lay);
+        if (layers == 11) kb_dt_tile<11><<<gd, 256, 0, st>>>(t.lay);
+        else kb_dt_tile<0><<<gd, 256, 0, st>>>(t.lay);
         for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
         kb_relabel<double><<<gb, 256, 0, st>>>(t.rel);
         kb_force<double><<<gb, 256, 0, st>>>(t.edg);
     } else {
         kb_advect<float><<<gb, 256, 0, st>>>(t.adv);
-        kb_dt_cols<<<gd, 256, 0, st>>>(t.lay);
-        kb_dt_rows<<<gd, 256, 0, st>>>(t.lay);
+        if (layers == 11) kb_dt_tile<11><<<gd, 256, 0, st>>>(t.lay);
+        else kb_dt_tile<0><<<gd, 256, 0, st>>>(t.lay);
         for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
         kb_relabel<float><<<gb, 256, 0, st>>>(t.rel);
         kb_force<float><<<gb, 256, 0, st>>>(t.edg);

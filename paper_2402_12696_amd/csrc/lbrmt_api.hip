@@ -967,7 +967,8 @@ int batch_tables(lbrmt_batch* b)
             const GridP& g = c->g;
             adv[k] = AdvectArgs{g, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt], c->bb.X[s.cur],
                                 c->bb.Y[s.cur], c->bb.phi[s.cur], c->bb.X[s.nxt], c->bb.Y[s.nxt],
-                                c->bb.tag, c->bb.win, s.wprev, s.wcur, c->bb.health};
+                                c->bb.tag, c->bb.win, s.wprev, s.wcur, c->bb.lcount,
+                                c->bb.health};
             lay[k] = LayersArgs{g, c->bb.win, s.wcur, c->bb.tag, c->bb.gcol, c->bb.lists,
                                 c->bb.lcount, c->bb.health};
             fit[k] = FitArgs{g, c->bb.win, s.wcur, s.wprev, c->bb.tag, c->bb.lists, c->bb.lcount,

@@ -86,6 +86,7 @@ struct AdvectArgs {
     int8_t* tag;
     const Win* win;
     int wprev, wcur;
+    int* lcount;
     unsigned* health;
 };
 struct LayersArgs {
