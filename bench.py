@@ -78,6 +78,16 @@ def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_varian
     ktimes = {k: sim.kernel_time(k) for k in
               ("advect", "extrap", "relabel", "force", "lb_bulk", "lb_band")}
     sim.set_timing(False)
+    # the full-grid lattice update alone (one stream), for reference
+    from paper_2402_12696_amd.lbrmt import LBRMT_OPT_OVERLAP as _OV
+    keep = sim.get_option(_OV)
+    sim.set_option(_OV, 0)
+    sim.set_timing(True)
+    sim.step(timing_steps // 2)
+    torch.cuda.synchronize()
+    ktimes["lb_full_alone"] = sim.kernel_time("lb_bulk")
+    sim.set_timing(False)
+    sim.set_option(_OV, keep)
     sim.close()
     return ms_per_step, ktimes, band_nodes, window_nodes, diag
 
@@ -175,7 +185,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--overlap", type=int, default=None, choices=[0, 1],
-                    help="1: reference-map chain on a side stream (library default 0)")
+                    help="1: reference-map chain on a side stream (library default 1)")
     ap.add_argument("--lb-variant", type=int, default=None,
                     help="lattice tile variant (library default 3 for f64, 5 for f32)")
     ap.add_argument("--no-batch", action="store_true",
@@ -214,12 +224,17 @@ def main():
     achieved = alg_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None
     traffic = traffic_from_profile("lb_bulk", args.workload, args.precision)
     ceiling = copy_ceiling(bpn // 2 * nodes)  # one lattice, as the update reads one and writes one
+    alone_ms = kt["lb_full_alone"][0]
+    alone = bpn * nodes / (alone_ms * 1e-3) / 1e9 if alone_ms > 0 else None
     roof = {"kernel": "lb_bulk", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic, "bytes_per_launch": alg_bytes, "nodes_per_launch": bulk_nodes,
             "avg_launch_ms": bulk_ms, "launches": bulk_n,
             "copy_ceiling_GBs": ceiling,
-            "frac_of_copy_ceiling": achieved / ceiling if achieved else None}
+            "frac_of_copy_ceiling": achieved / ceiling if achieved else None,
+            "full_grid_update_alone": {"avg_launch_ms": alone_ms, "achieved": alone,
+                                       "frac": alone / HBM_PEAK_GBS if alone else None,
+                                       "frac_of_copy_ceiling": alone / ceiling if alone else None}}
 
     extra = {"kernel_avg_ms": {k: v[0] for k, v in kt.items()},
              "band_region_nodes": band, "window_nodes": window,

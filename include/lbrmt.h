@@ -194,10 +194,11 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
 
 /* Launch options of a context (host only; an option change drops the
  * captured step graph after synchronising the stream):
- *   LBRMT_OPT_OVERLAP     0 (default): one stream, the reference-map chain
- *                         then one full lattice update; 1: the chain runs on an
+ *   LBRMT_OPT_OVERLAP     1 (default): the reference-map chain runs on an
  *                         internal stream while the lattice Boltzmann update of
- *                         the tiles away from the solid runs on the caller's.
+ *                         the tiles away from the solid runs on the caller's,
+ *                         then the tiles meeting the solid windows are updated;
+ *                         0: one stream, the chain then one full lattice update.
  *   LBRMT_OPT_LB_VARIANT  tile shape of the lattice Boltzmann update, 0 ..
  *                         LBRMT_OPT_LB_VARIANT_COUNT - 1, default 3 for FP64 and
  *                         5 for FP32 (results are bitwise identical across

@@ -104,7 +104,7 @@ struct lbrmt_ctx {
     double *dpart, *dout;
     long long step = 0;
     bool inited = false;
-    bool overlap = false;  // one stream: the chain, then one full lattice update
+    bool overlap = true;  // the chain on an internal stream beside the bulk lattice update
     int lb_variant = 3;    // set per precision by lbrmt_create
     hipGraphExec_t gexec = nullptr;
     bool graph = true;  // replay captured six-step graphs
