@@ -206,12 +206,18 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *   LBRMT_OPT_GRAPH       1 (default): whole blocks of six steps replay one
  *                         captured HIP graph; 0: every kernel is launched
  *                         eagerly (results are bitwise identical).
+ *   LBRMT_OPT_BULK_BLOCKS with overlap: the most workgroups the bulk lattice
+ *                         update may use (they stride over its tiles), which
+ *                         leaves HBM bandwidth to the reference-map chain
+ *                         running beside it; 0: one workgroup per tile.
+ *                         Results do not depend on it.
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,
     LBRMT_OPT_LB_VARIANT = 1,
     LBRMT_OPT_LB_VARIANT_COUNT = 2, /* read only */
-    LBRMT_OPT_GRAPH = 3
+    LBRMT_OPT_GRAPH = 3,
+    LBRMT_OPT_BULK_BLOCKS = 4
 } lbrmt_option;
 int lbrmt_set_option(lbrmt_ctx* ctx, int32_t option, int64_t value);
 int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);

@@ -266,8 +266,9 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
         t_step = gridDim.x;
         t_end = untx * unty;
     } else {
+        // one tile per block, or a capped grid striding over the tiles
         t_begin = xcd_remap(blockIdx.x, gridDim.x);
-        t_step = 1 << 30;
+        t_step = gridDim.x;
         t_end = ntx * nty;
     }
     for (int t = t_begin; t < t_end; t += t_step) {
@@ -330,10 +331,11 @@ template <typename S, int PART, int TX, int TY, int R, bool NT>
 static void lb_launch_one(const GridP& g, const void* A, void* B, const double* fpx,
                           const double* fpy, const double* fcx, const double* fcy,
                           const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
-                          double fpo_y, unsigned* health, hipStream_t st)
+                          double fpo_y, int max_blocks, unsigned* health, hipStream_t st)
 {
     const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY * R - 1) / (TY * R));
-    const int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles;
+    int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles;
+    if (PART == 1 && max_blocks > 0 && max_blocks < grid) grid = max_blocks;
     k_lb<S, PART, TX, TY, R, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx,
                                                           fcy, drho, win, wprev, wcur, fpo_x,
                                                           fpo_y, health);
@@ -343,11 +345,12 @@ template <typename S, int PART>
 static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, const double* fpx,
                               const double* fpy, const double* fcx, const double* fcy,
                               const double* drho, const Win* win, int wprev, int wcur,
-                              double fpo_x, double fpo_y, unsigned* health, hipStream_t st)
+                              double fpo_x, double fpo_y, int max_blocks, unsigned* health,
+                              hipStream_t st)
 {
 #define LBV(TX, TY, R, NT)                                                                       \
     lb_launch_one<S, PART, TX, TY, R, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
-                                          fpo_x, fpo_y, health, st)
+                                          fpo_x, fpo_y, max_blocks, health, st)
     switch (v) {
     case 1: LBV(128, 2, 1, false); break;
     case 2: LBV(256, 1, 1, false); break;
@@ -370,11 +373,11 @@ static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, con
 hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
                      const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
-                     double fpo_y, int part, unsigned* health, hipStream_t st)
+                     double fpo_y, int part, unsigned* health, hipStream_t st, int max_blocks)
 {
 #define LBP(S, PARTV)                                                                        \
     lb_launch_variant<S, PARTV>(variant, g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
-                                fpo_x, fpo_y, health, st)
+                                fpo_x, fpo_y, max_blocks, health, st)
     if (precision == 0) {
         if (part == 0) LBP(double, 0);
         else if (part == 1) LBP(double, 1);

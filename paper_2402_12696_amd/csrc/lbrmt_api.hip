@@ -109,6 +109,7 @@ struct lbrmt_ctx {
     hipGraphExec_t gexec = nullptr;
     bool graph = true;  // replay captured six-step graphs
     bool member = false;  // member of a batch (stepped by the batch only)
+    int bulk_blocks = 0;  // cap on the blocks of the overlapped bulk update (0: one per tile)
     bool timing = false;
     struct Pending {
         int kind;
@@ -236,7 +237,8 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
                 Bracket b(c, 4, main_s);
                 HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
                                     c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
-                                    s.wprev, s.wcur, ox, oy, 1, c->bb.health, main_s));
+                                    s.wprev, s.wcur, ox, oy, 1, c->bb.health, main_s,
+                                    c->bulk_blocks));
                 b.done();
             }
             HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
@@ -746,6 +748,10 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
         if (value != 0 && value != 1) return LBRMT_EINVAL;
         c->graph = value != 0;
         break;
+    case LBRMT_OPT_BULK_BLOCKS:
+        if (value < 0 || value > (1 << 24)) return LBRMT_EINVAL;
+        c->bulk_blocks = (int)value;
+        break;
     default:
         return LBRMT_EINVAL;
     }
@@ -766,6 +772,7 @@ int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
     case LBRMT_OPT_LB_VARIANT: *value = c->lb_variant; return LBRMT_OK;
     case LBRMT_OPT_LB_VARIANT_COUNT: *value = lb_variant_count(); return LBRMT_OK;
     case LBRMT_OPT_GRAPH: *value = c->graph ? 1 : 0; return LBRMT_OK;
+    case LBRMT_OPT_BULK_BLOCKS: *value = c->bulk_blocks; return LBRMT_OK;
     default: return LBRMT_EINVAL;
     }
 }

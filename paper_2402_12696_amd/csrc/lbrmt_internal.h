@@ -252,7 +252,8 @@ hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const
 hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
                      const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
-                     double fpo_y, int part, unsigned* health, hipStream_t st);
+                     double fpo_y, int part, unsigned* health, hipStream_t st,
+                     int max_blocks = 0);
 int lb_variant_count();
 void lb_variant_tile(int v, int* tx, int* ty);
 hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,

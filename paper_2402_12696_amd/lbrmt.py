@@ -23,6 +23,7 @@ HEALTH_NAMES = ["advect_miss", "extrap_fail", "stress_miss", "detj", "detj_solid
                 "window_clip", "list_overflow"]
 KERNEL_NAMES = ["advect", "extrap", "relabel", "force", "lb_bulk", "lb_band"]
 LBRMT_OPT_OVERLAP, LBRMT_OPT_LB_VARIANT, LBRMT_OPT_LB_VARIANT_COUNT, LBRMT_OPT_GRAPH = 0, 1, 2, 3
+LBRMT_OPT_BULK_BLOCKS = 4
 
 
 class lbrmt_grid_desc(ctypes.Structure):
