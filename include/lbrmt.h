@@ -188,7 +188,10 @@ int lbrmt_validate(const lbrmt_grid_desc* desc, const lbrmt_solid_desc* solids, 
 /* Average device time (ms) per launch of each step kernel, measured with HIP
  * events on the stream each kernel runs on.  Enabling timing makes lbrmt_step
  * launch eagerly (no graph) and bracket every kernel with events; names:
- * "advect", "extrap", "relabel", "force", "lb_bulk", "lb_band". */
+ * "advect" (advection with the layers of the extrapolation zone), "extrap"
+ * (the layer-by-layer fits), "relabel", "force", "lb_bulk" (the whole lattice
+ * with overlap off; the tiles away from the solid with overlap on), "lb_band"
+ * (the tiles meeting the solid windows, overlap on). */
 int lbrmt_set_timing(lbrmt_ctx* ctx, int32_t enable);
 int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t* launches);
 

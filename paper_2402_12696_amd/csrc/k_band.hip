@@ -281,9 +281,10 @@ hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, 
 // xi_0 = x on the solid and its extrapolation zone, phi = phi0(x) (Alg. 1 init)
 template <typename T>
 __global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win, int wslot,
-                            T* X, T* Y, T* phi)
+                            T* X, T* Y, T* phi, int* lcount)
 {
     constexpr bool DISP = sizeof(T) == 4;
+    clear_lcount(lcount);  // for the first step's distance transform
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
@@ -310,10 +311,11 @@ hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, 
 {
     if (g.rm32)
         k_init_fill<float><<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, (float*)bb.X[0],
-                                                 (float*)bb.Y[0], (float*)bb.phi[0]);
+                                                 (float*)bb.Y[0], (float*)bb.phi[0], bb.lcount);
     else
         k_init_fill<double><<<2048, 256, 0, st>>>(g, b, bb.tag, bb.win, wslot, (double*)bb.X[0],
-                                                  (double*)bb.Y[0], (double*)bb.phi[0]);
+                                                  (double*)bb.Y[0], (double*)bb.phi[0],
+                                                  bb.lcount);
     return hipGetLastError();
 }
 
@@ -350,147 +352,89 @@ __device__ __forceinline__ bool upwind_d(C vel, C X0, C Y0, bool okm1, bool okm2
     return true;
 }
 
-// Eq. (3_1_refmap_adv) on the solid nodes S^n = {interior, phi^n < 0}, plus
-// the step's tags (solid / none) over the window.  Every load of a node (its
-// level set, the eight upwind stencil nodes, the nine populations and the
-// previous force) is issued before any is used; addresses of absent nodes are
-// clamped to the node itself.  S is both the population and the reference-map
-// storage type (FP64: xi; FP32: population deviations and displacement).
+// Eq. (3_1_refmap_adv) at one solid node (i, j) of S^n = {interior,
+// phi^n < 0}.  Every load (the eight upwind stencil nodes with their level
+// sets, the nine populations and the previous force) is issued before any is
+// used; addresses of absent nodes are clamped to the node itself.  S is both
+// the population and the reference-map storage type (FP64: xi; FP32:
+// population deviations and displacement).
 template <typename S>
-__device__ __forceinline__ void advect_body(GridP g, const S* __restrict__ A,
-                                                const double* __restrict__ fpx,
-                                                const double* __restrict__ fpy,
-                                                const S* __restrict__ X, const S* __restrict__ Y,
-                                                const S* __restrict__ phi, S* X1, S* Y1,
-                                                int8_t* tag, const Win* __restrict__ win,
-                                                int wprev, int wcur, int* lcount, unsigned* health)
+__device__ __forceinline__ void advect_node(const GridP& g, const S* __restrict__ A,
+                                            const double* __restrict__ fpx,
+                                            const double* __restrict__ fpy,
+                                            const S* __restrict__ X, const S* __restrict__ Y,
+                                            const S* __restrict__ phi, S* X1, S* Y1,
+                                            const Rect& D, int i, int j, unsigned* health)
 {
     using C = S;
-    clear_lcount(lcount);
     constexpr bool DISP = sizeof(S) == 4;
-    const Rect W = window_of(win, wcur, g);
-    if (!W.ok) return;
-    const Rect D = window_of(win, wprev, g);
-    const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-    const long long total = (long long)w * h;
     const long long P = g.plane;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-        const long long k = pidx(g, i, j);
-        const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-        // stencil nodes: x-1, x-2, x+1, x+2, y-1, y-2, y+1, y+2
-        const int di[8] = {-1, -2, 1, 2, 0, 0, 0, 0};
-        const int dj[8] = {0, 0, 0, 0, -1, -2, 1, 2};
-        long long ks[8];
+    const long long k = pidx(g, i, j);
+    // stencil nodes: x-1, x-2, x+1, x+2, y-1, y-2, y+1, y+2
+    const int di[8] = {-1, -2, 1, 2, 0, 0, 0, 0};
+    const int dj[8] = {0, 0, 0, 0, -1, -2, 1, 2};
+    long long ks[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) ks[q] = ref_index(g, D, i + di[q], j + dj[q]);
-        // populations of the pull gather (clamped to the interior)
-        const int ic = min(max(i, 0), g.nx - 1), jc = min(max(j, 0), g.ny - 1);
-        const bool bw = !g.px && ic == 0, be = !g.px && ic == g.nx - 1;
-        const bool bs = !g.py && jc == 0, bn = !g.py && jc == g.ny - 1;
-        int im = ic - 1, ip = ic + 1, jm = jc - 1, jp = jc + 1;
-        im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
-        ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
-        jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
-        jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
-        const long long r0 = (long long)jc * g.pitch, rm = (long long)jm * g.pitch,
-                        rp = (long long)jp * g.pitch, n = r0 + ic;
-        // ---- all loads
-        const C p0 = phi[k], X0 = X[k], Y0 = Y[k];
-        C ps[8], xs[8], ys[8];
+    for (int q = 0; q < 8; q++) ks[q] = ref_index(g, D, i + di[q], j + dj[q]);
+    // populations of the pull gather (the node is interior)
+    const bool bw = !g.px && i == 0, be = !g.px && i == g.nx - 1;
+    const bool bs = !g.py && j == 0, bn = !g.py && j == g.ny - 1;
+    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
+    im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
+    ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
+    jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
+    jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
+    const long long r0 = (long long)j * g.pitch, rm = (long long)jm * g.pitch,
+                    rp = (long long)jp * g.pitch, n = r0 + i;
+    // ---- all loads
+    const C X0 = X[k], Y0 = Y[k];
+    C ps[8], xs[8], ys[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const long long kq = ks[q] >= 0 ? ks[q] : k;
-            ps[q] = phi[kq];
-            xs[q] = X[kq];
-            ys[q] = Y[kq];
-        }
-        C f[NQ];
-        f[0] = A[n];
-        f[1] = bw ? A[3 * P + n] : A[1 * P + r0 + im];
-        f[2] = bs ? A[4 * P + n] : A[2 * P + rm + ic];
-        f[3] = be ? A[1 * P + n] : A[3 * P + r0 + ip];
-        f[4] = bn ? A[2 * P + n] : A[4 * P + rp + ic];
-        f[5] = (bw || bs) ? A[7 * P + n] : A[5 * P + rm + im];
-        f[6] = (be || bs) ? A[8 * P + n] : A[6 * P + rm + ip];
-        f[7] = (be || bn) ? A[5 * P + n] : A[7 * P + rp + ip];
-        f[8] = (bw || bn) ? A[6 * P + n] : A[8 * P + rp + im];
-        const C Fx = C(fpx[n]), Fy = C(fpy[n]);
-        // ---- decisions and arithmetic
-        const bool solid = interior && D.has(i, j) && p0 < C(0);
-        tag[k] = solid ? TAG_SOLID : TAG_NONE;
-        if (!solid) continue;
-        // half-force velocity of Eq. (2_2_lbm_moments_force); the FP32 mode
-        // stores f_i - w_i rho_f (sum w_i = 1, sum w_i c_i = 0)
-        const C s9 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-        const C rho = DISP ? C(g.rho_f) + s9 : s9;
-        const C u = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (C(2) * rho);
-        const C v = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (C(2) * rho);
-        bool okq[8];
+    for (int q = 0; q < 8; q++) {
+        const long long kq = ks[q] >= 0 ? ks[q] : k;
+        ps[q] = phi[kq];
+        xs[q] = X[kq];
+        ys[q] = Y[kq];
+    }
+    C f[NQ];
+    f[0] = A[n];
+    f[1] = bw ? A[3 * P + n] : A[1 * P + r0 + im];
+    f[2] = bs ? A[4 * P + n] : A[2 * P + rm + i];
+    f[3] = be ? A[1 * P + n] : A[3 * P + r0 + ip];
+    f[4] = bn ? A[2 * P + n] : A[4 * P + rp + i];
+    f[5] = (bw || bs) ? A[7 * P + n] : A[5 * P + rm + im];
+    f[6] = (be || bs) ? A[8 * P + n] : A[6 * P + rm + ip];
+    f[7] = (be || bn) ? A[5 * P + n] : A[7 * P + rp + ip];
+    f[8] = (bw || bn) ? A[6 * P + n] : A[8 * P + rp + im];
+    const C Fx = C(fpx[n]), Fy = C(fpy[n]);
+    // ---- arithmetic: half-force velocity of Eq. (2_2_lbm_moments_force); the
+    // FP32 mode stores f_i - w_i rho_f (sum w_i = 1, sum w_i c_i = 0)
+    const C s9 = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const C rho = DISP ? C(g.rho_f) + s9 : s9;
+    const C u = (f[1] + f[5] + f[8] - f[3] - f[6] - f[7]) / rho + Fx / (C(2) * rho);
+    const C v = (f[2] + f[5] + f[6] - f[4] - f[7] - f[8]) / rho + Fy / (C(2) * rho);
+    bool okq[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) okq[q] = ks[q] >= 0 && ps[q] < C(INFINITY);
-        C dXx, dYx, dXy, dYy;
-        const bool okx = upwind_d<C>(u, X0, Y0, okq[0], okq[1], xs[0], ys[0], xs[1], ys[1],
-                                     okq[2], okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
-        const bool oky = upwind_d<C>(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5],
-                                     okq[6], okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
-        if (!okx || !oky) {
-            atomicAdd(&health[0], 1u);
-            X1[k] = X0;
-            Y1[k] = Y0;
-        } else if (DISP) {
-            // xi = x + d: d(X)/dx = 1 + dXx, d(Y)/dy = 1 + dYy
-            X1[k] = X0 - (u * (C(1) + dXx) + v * dXy);
-            Y1[k] = Y0 - (u * dYx + v * (C(1) + dYy));
-        } else {
-            X1[k] = X0 - (u * dXx + v * dXy);
-            Y1[k] = Y0 - (u * dYx + v * dYy);
-        }
+    for (int q = 0; q < 8; q++) okq[q] = ks[q] >= 0 && ps[q] < C(INFINITY);
+    C dXx, dYx, dXy, dYy;
+    const bool okx = upwind_d<C>(u, X0, Y0, okq[0], okq[1], xs[0], ys[0], xs[1], ys[1], okq[2],
+                                 okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
+    const bool oky = upwind_d<C>(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5], okq[6],
+                                 okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
+    if (!okx || !oky) {
+        atomicAdd(&health[0], 1u);
+        X1[k] = X0;
+        Y1[k] = Y0;
+    } else if (DISP) {
+        // xi = x + d: d(X)/dx = 1 + dXx, d(Y)/dy = 1 + dYy
+        X1[k] = X0 - (u * (C(1) + dXx) + v * dXy);
+        Y1[k] = Y0 - (u * dYx + v * (C(1) + dYy));
+    } else {
+        X1[k] = X0 - (u * dXx + v * dXy);
+        Y1[k] = Y0 - (u * dYx + v * dYy);
     }
 }
 
-template <typename S>
-__global__ __launch_bounds__(256) void k_advect(GridP g, const S* __restrict__ A,
-                                                const double* __restrict__ fpx,
-                                                const double* __restrict__ fpy,
-                                                const S* __restrict__ X, const S* __restrict__ Y,
-                                                const S* __restrict__ phi, S* X1, S* Y1,
-                                                int8_t* tag, const Win* __restrict__ win,
-                                                int wprev, int wcur, int* lcount, unsigned* health)
-{
-    advect_body<S>(g, A, fpx, fpy, X, Y, phi, X1, Y1, tag, win, wprev, wcur, lcount, health);
-}
-
-// batched form: member blockIdx.y of a table of arguments
-template <typename S>
-__global__ __launch_bounds__(256) void kb_advect(const AdvectArgs* __restrict__ args)
-{
-    const AdvectArgs& a = args[blockIdx.y];
-    advect_body<S>(a.g, (const S*)a.A, a.fpx, a.fpy, (const S*)a.X, (const S*)a.Y,
-                   (const S*)a.phi, (S*)a.X1, (S*)a.Y1, a.tag, a.win, a.wprev, a.wcur, a.lcount,
-                   a.health);
-}
-
-hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
-                         const StepSlots& s, const void* A, const double* fpx, const double* fpy,
-                         double fpo_x, double fpo_y, hipStream_t st)
-{
-    (void)b;
-    (void)fpo_x;
-    (void)fpo_y;
-    if (precision == 0)
-        k_advect<double><<<2048, 256, 0, st>>>(
-            g, (const double*)A, fpx, fpy, (const double*)bb.X[s.cur], (const double*)bb.Y[s.cur],
-            (const double*)bb.phi[s.cur], (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt], bb.tag,
-            bb.win, s.wprev, s.wcur, bb.lcount, bb.health);
-    else
-        k_advect<float><<<2048, 256, 0, st>>>(
-            g, (const float*)A, fpx, fpy, (const float*)bb.X[s.cur], (const float*)bb.Y[s.cur],
-            (const float*)bb.phi[s.cur], (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt], bb.tag,
-            bb.win, s.wprev, s.wcur, bb.lcount, bb.health);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------- layers
 
@@ -505,15 +449,23 @@ hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const Ba
 // layer (split into NSUB sub-lists by block so that few blocks share a
 // counter; the order inside a list does not matter since targets of one layer
 // are independent).  The layer counters were cleared by the kernel before.
-constexpr int DTX = 64, DTY = 16;
+constexpr int DTX = 32, DTY = 16;
 constexpr int DRW = DTX + 2 * MAX_LAYERS, DRH = DTY + 2 * MAX_LAYERS;
 
 // LC > 0: the layer count as a compile-time constant (scans unrolled);
-// LC = 0: the count of the grid
-template <int LC>
+// LC = 0: the count of the grid.  ADV = false (initialisation): the solid set
+// is read from the tags.  ADV = true (a step): the solid set S^n = {interior,
+// phi^n < 0, inside the previous window} is read from the level set, the
+// tile's solid nodes are tagged and advected (Sec. 3.1) in the same pass, and
+// the tags of the window are all written here.
+template <int LC, bool ADV, typename S>
 __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ win, int wslot,
-                                             int8_t* tag, int* lists, int* lcount,
-                                             unsigned* health)
+                                             int wprev, int8_t* tag, int* lists, int* lcount,
+                                             unsigned* health, const S* __restrict__ A,
+                                             const double* __restrict__ fpx,
+                                             const double* __restrict__ fpy,
+                                             const S* __restrict__ X, const S* __restrict__ Y,
+                                             const S* __restrict__ phi, S* X1, S* Y1)
 {
     __shared__ int8_t sol[DRH * DRW];   // solid flags of the tile and its halo
     __shared__ int8_t gc[DTY * DRW];    // column distances of the tile rows
@@ -521,6 +473,7 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
     __shared__ int base[MAX_LAYERS + 1];
     const Rect W = window_of(win, wslot, g);
     if (!W.ok) return;
+    const Rect D = window_of(win, wprev, g);
     const int L = LC > 0 ? LC : g.layers;
     const long long cap = sub_cap(g.pplane);
     const int sub = blockIdx.x % NSUB;
@@ -534,9 +487,18 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
         // solid flags of the region (nodes outside the window hold none)
         for (int e = threadIdx.x; e < rw * rh; e += blockDim.x) {
             const int x = x0 - L + e % rw, y = y0 - L + e / rw;
-            const bool in = W.has(x, y);
-            const int8_t tv = tag[in ? pidx(g, x, y) : pidx(g, W.i0, W.j0)];
-            sol[(e / rw) * DRW + e % rw] = (in && tv == TAG_SOLID) ? 1 : 0;
+            bool s = false;
+            if (ADV) {
+                const bool in = W.has(x, y) && x >= 0 && x < g.nx && y >= 0 && y < g.ny &&
+                                D.has(x, y);
+                const S p = phi[in ? pidx(g, x, y) : pidx(g, W.i0, W.j0)];
+                s = in && p < S(0);
+            } else {
+                const bool in = W.has(x, y);
+                const int8_t tv = tag[in ? pidx(g, x, y) : pidx(g, W.i0, W.j0)];
+                s = in && tv == TAG_SOLID;
+            }
+            sol[(e / rw) * DRW + e % rw] = s ? 1 : 0;
         }
         __syncthreads();
         // column pass over the tile rows, the whole region width
@@ -562,7 +524,9 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
             lay[u] = 0;
             kk[u] = 0;
             slot[u] = 0;
-            if (W.has(x, y) && !sol[(cy + L) * DRW + cx + L]) {
+            const bool solid = sol[(cy + L) * DRW + cx + L];
+            if (ADV && W.has(x, y) && solid) tag[pidx(g, x, y)] = TAG_SOLID;
+            if (W.has(x, y) && !solid) {
                 int best = 2 * L + 2;
 #pragma unroll
                 for (int d = -L; d <= L; d++) best = min(best, abs(d) + gc[cy * DRW + cx + L + d]);
@@ -594,23 +558,72 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
                 else atomicAdd(&health[7], 1u);  // beyond the sub-list capacity
             }
         }
+        if (ADV) {
+            // advection of the tile's solid nodes
+            for (int e = threadIdx.x; e < DTX * DTY; e += blockDim.x) {
+                const int cx = e % DTX, cy = e / DTX;
+                const int x = x0 + cx, y = y0 + cy;
+                if (W.has(x, y) && sol[(cy + L) * DRW + cx + L])
+                    advect_node<S>(g, A, fpx, fpy, X, Y, phi, X1, Y1, D, x, y, health);
+            }
+        }
         __syncthreads();
     }
 }
 
+// initialisation: layers of the initial solid set (from the tags)
 template <int LC>
 __global__ __launch_bounds__(256) void k_dt_tile(GridP g, const Win* __restrict__ win, int wslot,
                                                  int8_t* tag, int* lists, int* lcount,
                                                  unsigned* health)
 {
-    dt_tile_body<LC>(g, win, wslot, tag, lists, lcount, health);
+    dt_tile_body<LC, false, double>(g, win, wslot, 0, tag, lists, lcount, health, nullptr,
+                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
-template <int LC>
-__global__ __launch_bounds__(256) void kb_dt_tile(const LayersArgs* __restrict__ args)
+// a step: advection of xi plus the layers of the extrapolation zone
+template <int LC, typename S>
+__global__ __launch_bounds__(256) void k_advect_dt(GridP g, const S* __restrict__ A,
+                                                   const double* __restrict__ fpx,
+                                                   const double* __restrict__ fpy,
+                                                   const S* __restrict__ X,
+                                                   const S* __restrict__ Y,
+                                                   const S* __restrict__ phi, S* X1, S* Y1,
+                                                   int8_t* tag, const Win* __restrict__ win,
+                                                   int wprev, int wcur, int* lists, int* lcount,
+                                                   unsigned* health)
 {
-    const LayersArgs& a = args[blockIdx.y];
-    dt_tile_body<LC>(a.g, a.win, a.wslot, a.tag, a.lists, a.lcount, a.health);
+    dt_tile_body<LC, true, S>(g, win, wcur, wprev, tag, lists, lcount, health, A, fpx, fpy, X,
+                              Y, phi, X1, Y1);
+}
+
+template <int LC, typename S>
+__global__ __launch_bounds__(256) void kb_advect_dt(const AdvectArgs* __restrict__ args)
+{
+    const AdvectArgs& a = args[blockIdx.y];
+    dt_tile_body<LC, true, S>(a.g, a.win, a.wcur, a.wprev, a.tag, a.lists, a.lcount, a.health,
+                              (const S*)a.A, a.fpx, a.fpy, (const S*)a.X, (const S*)a.Y,
+                              (const S*)a.phi, (S*)a.X1, (S*)a.Y1);
+}
+
+hipError_t launch_advect_layers(const GridP& g, int precision, const BandBufs& bb,
+                                const StepSlots& s, const void* A, const double* fpx,
+                                const double* fpy, hipStream_t st)
+{
+#define ADT(LC, S)                                                                                \
+    k_advect_dt<LC, S><<<DT_BLOCKS, 256, 0, st>>>(                                              \
+        g, (const S*)A, fpx, fpy, (const S*)bb.X[s.cur], (const S*)bb.Y[s.cur],                   \
+        (const S*)bb.phi[s.cur], (S*)bb.X[s.nxt], (S*)bb.Y[s.nxt], bb.tag, bb.win, s.wprev,      \
+        s.wcur, bb.lists, bb.lcount, bb.health)
+    if (precision == 0) {
+        if (g.layers == 11) ADT(11, double);
+        else ADT(0, double);
+    } else {
+        if (g.layers == 11) ADT(11, float);
+        else ADT(0, float);
+    }
+#undef ADT
+    return hipGetLastError();
 }
 
 hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStream_t st)
@@ -1077,9 +1090,12 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
                                                const int* __restrict__ boxpart, int nbox,
                                                int whole_grid, const C* __restrict__ X,
                                                const C* __restrict__ Y, const C* __restrict__ phi,
-                                               double* o0, double* o1, double* o2,
+                                               double* o0, double* o1, double* o2, int* lcount,
                                                unsigned* health)
 {
+    // the force pass ends the reference-map chain of a step: clear the layer
+    // counters of the next step's distance transform
+    if (MODE == 0) clear_lcount(lcount);
     __shared__ C sX[SY * SX], sY[SY * SX], sP[SY * SX];
     __shared__ C ex[FTY][FTX + 1][3];
     __shared__ C ey[FTY + 1][FTX][3];
@@ -1180,11 +1196,11 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
                                                const int* __restrict__ boxpart, int nbox,
                                                int whole_grid, const C* __restrict__ X,
                                                const C* __restrict__ Y, const C* __restrict__ phi,
-                                               double* o0, double* o1, double* o2,
+                                               double* o0, double* o1, double* o2, int* lcount,
                                                unsigned* health)
 {
     edges_body<MODE, C>(g, b, win, wvalid, wnext, boxpart, nbox, whole_grid, X, Y, phi, o0, o1,
-                        o2, health);
+                        o2, lcount, health);
 }
 
 template <typename C>
@@ -1192,7 +1208,7 @@ __global__ __launch_bounds__(256) void kb_force(const EdgesArgs* __restrict__ ar
 {
     const EdgesArgs& a = args[blockIdx.y];
     edges_body<0, C>(a.g, a.b, a.win, a.wvalid, a.wnext, a.boxpart, a.nbox, 0, (const C*)a.X,
-                     (const C*)a.Y, (const C*)a.phi, a.o0, a.o1, a.o2, a.health);
+                     (const C*)a.Y, (const C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health);
 }
 
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
@@ -1201,12 +1217,13 @@ hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, cons
     if (g.rm32)
         k_edges<0, float><<<2048, 256, 0, st>>>(
             g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS, 0, (const float*)bb.X[s.nxt],
-            (const float*)bb.Y[s.nxt], (const float*)bb.phi[s.nxt], fx, fy, drho, bb.health);
+            (const float*)bb.Y[s.nxt], (const float*)bb.phi[s.nxt], fx, fy, drho, bb.lcount,
+            bb.health);
     else
         k_edges<0, double><<<2048, 256, 0, st>>>(
             g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS, 0,
             (const double*)bb.X[s.nxt], (const double*)bb.Y[s.nxt], (const double*)bb.phi[s.nxt],
-            fx, fy, drho, bb.health);
+            fx, fy, drho, bb.lcount, bb.health);
     return hipGetLastError();
 }
 
@@ -1217,13 +1234,13 @@ hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb
         k_edges<1, float><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1,
                                                 (const float*)bb.X[buf], (const float*)bb.Y[buf],
                                                 (const float*)bb.phi[buf], sxx, sxy, syy,
-                                                bb.health);
+                                                nullptr, bb.health);
     else
         k_edges<1, double><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1,
                                                  (const double*)bb.X[buf],
                                                  (const double*)bb.Y[buf],
                                                  (const double*)bb.phi[buf], sxx, sxy, syy,
-                                                 bb.health);
+                                                 nullptr, bb.health);
     return hipGetLastError();
 }
 
@@ -1280,16 +1297,14 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
 {
     const dim3 gb(BATCH_BAND_BLOCKS, nsim), gd(BATCH_DT_BLOCKS, nsim), gf(BATCH_FIT_BLOCKS, nsim);
     if (precision == 0) {
-        kb_advect<double><<<gb, 256, 0, st>>>(t.adv);
-        if (layers == 11) kb_dt_tile<11><<<gd, 256, 0, st>>>(t.lay);
-        else kb_dt_tile<0><<<gd, 256, 0, st>>>(t.lay);
+        if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv);
+        else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv);
         for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
         kb_relabel<double><<<gb, 256, 0, st>>>(t.rel);
         kb_force<double><<<gb, 256, 0, st>>>(t.edg);
     } else {
-        kb_advect<float><<<gb, 256, 0, st>>>(t.adv);
-        if (layers == 11) kb_dt_tile<11><<<gd, 256, 0, st>>>(t.lay);
-        else kb_dt_tile<0><<<gd, 256, 0, st>>>(t.lay);
+        if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv);
+        else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv);
         for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
         kb_relabel<float><<<gb, 256, 0, st>>>(t.rel);
         kb_force<float><<<gb, 256, 0, st>>>(t.edg);

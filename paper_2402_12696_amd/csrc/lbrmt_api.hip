@@ -209,14 +209,14 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
             band = c->side;
         }
         {
+            // advection and the layers of the extrapolation zone (one pass)
             Bracket b(c, 0, band);
-            HIPCHK(c, launch_advect(g, prec, c->body, c->bb, s, c->lat[s.cur], c->Fx[s.nxt],
-                                    c->Fy[s.nxt], ox, oy, band));
+            HIPCHK(c, launch_advect_layers(g, prec, c->bb, s, c->lat[s.cur], c->Fx[s.nxt],
+                                           c->Fy[s.nxt], band));
             b.done();
         }
         {
             Bracket b(c, 1, band);
-            HIPCHK(c, launch_layers(g, c->bb, s.wcur, band));
             HIPCHK(c, launch_extrapolate(g, c->bb, s, band));
             b.done();
         }
@@ -665,6 +665,8 @@ int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
     HIPCHK(c, hipMemcpyAsync(c->bb.win, b + off[7], 3 * sizeof(Win), D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bb.health, b + off[7] + 3 * sizeof(Win),
                              LBRMT_H_COUNT * sizeof(unsigned), D2D, c->st));
+    HIPCHK(c, hipMemsetAsync(c->bb.lcount, 0, (size_t)(MAX_LAYERS + 1) * NSUB * LCOUNT_PAD * 4,
+                             c->st));
     HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, c->st));
     c->inited = true;
     return LBRMT_OK;
@@ -974,8 +976,8 @@ int batch_tables(lbrmt_batch* b)
             const GridP& g = c->g;
             adv[k] = AdvectArgs{g, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt], c->bb.X[s.cur],
                                 c->bb.Y[s.cur], c->bb.phi[s.cur], c->bb.X[s.nxt], c->bb.Y[s.nxt],
-                                c->bb.tag, c->bb.win, s.wprev, s.wcur, c->bb.lcount,
-                                c->bb.health};
+                                c->bb.tag, c->bb.win, s.wprev, s.wcur, c->bb.lists,
+                                c->bb.lcount, c->bb.health};
             lay[k] = LayersArgs{g, c->bb.win, s.wcur, c->bb.tag, c->bb.gcol, c->bb.lists,
                                 c->bb.lcount, c->bb.health};
             fit[k] = FitArgs{g, c->bb.win, s.wcur, s.wprev, c->bb.tag, c->bb.lists, c->bb.lcount,
@@ -985,7 +987,7 @@ int batch_tables(lbrmt_batch* b)
             edg[k] = EdgesArgs{g, c->body, c->bb.win, s.wcur, s.wnext, c->bb.boxpart,
                                BATCH_BAND_BLOCKS, c->bb.X[s.nxt], c->bb.Y[s.nxt],
                                c->bb.phi[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho,
-                               c->bb.health};
+                               c->bb.lcount, c->bb.health};
             lb[k] = LbArgs{g, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt],
                            c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win, s.wprev, s.wcur,
                            fpo_x(c, nstep), fpo_y(c, nstep), c->bb.health, base};

@@ -86,6 +86,7 @@ struct AdvectArgs {
     int8_t* tag;
     const Win* win;
     int wprev, wcur;
+    int* lists;
     int* lcount;
     unsigned* health;
 };
@@ -128,6 +129,7 @@ struct EdgesArgs {
     int nbox;
     const void *X, *Y, *phi;
     double *o0, *o1, *o2;
+    int* lcount;
     unsigned* health;
 };
 struct LbArgs {
@@ -280,9 +282,9 @@ hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlot
                               hipStream_t st);
 hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st);
-hipError_t launch_advect(const GridP& g, int precision, const BodyP& b, const BandBufs& bb,
-                         const StepSlots& s, const void* A, const double* fpx, const double* fpy,
-                         double fpo_x, double fpo_y, hipStream_t st);
+hipError_t launch_advect_layers(const GridP& g, int precision, const BandBufs& bb,
+                                const StepSlots& s, const void* A, const double* fpx,
+                                const double* fpy, hipStream_t st);
 hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                           hipStream_t st);
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
