@@ -95,17 +95,6 @@ __device__ __forceinline__ bool tag_set(int t)
 
 // ---------------------------------------------------------------- block helpers
 
-__device__ __forceinline__ int wave_min(int v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
 // box of the block's flagged nodes, stored as one partial per block
 __device__ void block_box(int i0, int i1, int j0, int j1, int* out4)
 {
@@ -139,48 +128,6 @@ __device__ void block_box(int i0, int i1, int j0, int j1, int* out4)
 }
 
 // reduce n partial boxes into one window slot (called by a whole block)
-__device__ void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1)
-{
-    __shared__ int sb[4][16];
-    int a0 = 0x3fffffff, a1 = -0x3fffffff, a2 = 0x3fffffff, a3 = -0x3fffffff;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const volatile int* q = part + 4 * k;
-        a0 = min(a0, q[0]);
-        a1 = max(a1, q[1]);
-        a2 = min(a2, q[2]);
-        a3 = max(a3, q[3]);
-    }
-    a0 = wave_min(a0);
-    a1 = wave_max(a1);
-    a2 = wave_min(a2);
-    a3 = wave_max(a3);
-    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int nw = (blockDim.x + 63) / 64;
-    if (lane == 0) {
-        sb[0][wid] = a0;
-        sb[1][wid] = a1;
-        sb[2][wid] = a2;
-        sb[3][wid] = a3;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < nw; w++) {
-            a0 = min(a0, sb[0][w]);
-            a1 = max(a1, sb[1][w]);
-            a2 = min(a2, sb[2][w]);
-            a3 = max(a3, sb[3][w]);
-        }
-        Win r;
-        r.i0 = a0;
-        r.i1 = a1;
-        r.j0 = a2;
-        r.j1 = a3;
-        if (a0 > a1) r.i0 = 0x3fffffff, r.i1 = -0x3fffffff, r.j0 = 0x3fffffff, r.j1 = -0x3fffffff;
-        *dst0 = r;
-        if (dst1) *dst1 = r;
-    }
-    __syncthreads();
-}
 
 // true in exactly one block: the last to arrive (all blocks must call it)
 __device__ bool last_block(unsigned* ticket)
@@ -242,7 +189,7 @@ __global__ __launch_bounds__(256) void k_init_solid_box(GridP g, BodyP b, int* b
     }
     block_box(i0, i1, j0, j1, boxpart + 4 * blockIdx.x);
     if (last_block(ticket)) {
-        reduce_boxes(boxpart, gridDim.x, &win[s0], &win[s1]);
+        reduce_boxes<true>(boxpart, gridDim.x, &win[s0], &win[s1]);
         if (threadIdx.x == 0) *ticket = 0u;
     }
 }
@@ -909,81 +856,6 @@ hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlot
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- relabel
-
-// phi^{n+1} = phi0(xi^{n+1}) on every node holding a reference map (Alg. 1),
-// evaluated in double (it decides the solid set); one partial box of the new
-// interior solid set per block (reduced by the force kernel into the next
-// ring slot)
-template <typename T>
-__device__ __forceinline__ void relabel_body(GridP g, BodyP b, const int8_t* __restrict__ tag,
-                                                 const Win* __restrict__ win, int wcur, T* X1,
-                                                 T* Y1, T* phi1, int* boxpart)
-{
-    constexpr bool DISP = sizeof(T) == 4;
-    const Rect W = window_of(win, wcur, g);
-    int i0 = 0x3fffffff, i1 = -0x3fffffff, j0 = 0x3fffffff, j1 = -0x3fffffff;
-    if (W.ok) {
-        const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
-        const long long total = (long long)w * h;
-        for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-             e += (long long)gridDim.x * blockDim.x) {
-            const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
-            const long long k = pidx(g, i, j);
-            const int8_t tv = tag[k];
-            double xv = (double)X1[k], yv = (double)Y1[k];
-            if (tag_set(tv)) {
-                if (DISP) {
-                    xv += node_coord(i, g.px, g.nx, b.cx);
-                    yv += node_coord(j, g.py, g.ny, b.cy);
-                }
-                const double p = shape_phi(b, xv, yv);
-                phi1[k] = store_phi<T>(p);
-                if (p < 0.0 && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
-                    i0 = min(i0, i);
-                    i1 = max(i1, i);
-                    j0 = min(j0, j);
-                    j1 = max(j1, j);
-                }
-            } else {
-                phi1[k] = T(INFINITY);
-                X1[k] = T(NAN);
-                Y1[k] = T(NAN);
-            }
-        }
-    }
-    block_box(i0, i1, j0, j1, boxpart + 4 * blockIdx.x);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_relabel(GridP g, BodyP b, const int8_t* __restrict__ tag,
-                                                 const Win* __restrict__ win, int wcur, T* X1,
-                                                 T* Y1, T* phi1, int* boxpart)
-{
-    relabel_body<T>(g, b, tag, win, wcur, X1, Y1, phi1, boxpart);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void kb_relabel(const RelabelArgs* __restrict__ args)
-{
-    const RelabelArgs& a = args[blockIdx.y];
-    relabel_body<T>(a.g, a.b, a.tag, a.win, a.wcur, (T*)a.X1, (T*)a.Y1, (T*)a.phi1, a.boxpart);
-}
-
-hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
-                          hipStream_t st)
-{
-    if (g.rm32)
-        k_relabel<float><<<RELABEL_BLOCKS, 256, 0, st>>>(g, b, bb.tag, bb.win, s.wcur,
-                                                         (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt],
-                                                         (float*)bb.phi[s.nxt], bb.boxpart);
-    else
-        k_relabel<double><<<RELABEL_BLOCKS, 256, 0, st>>>(
-            g, b, bb.tag, bb.win, s.wcur, (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt],
-            (double*)bb.phi[s.nxt], bb.boxpart);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------- stress and force
 
 constexpr int FTX = 32, FTY = 8;
@@ -1080,18 +952,36 @@ __device__ void edge_tau(const GridP& g, const BodyP& b, const C* sX, const C* s
     tau_of<C>(J0, J1, J2, J3, det, C(b.G), lam, out);
 }
 
+// reference-map node k at (i, j) after the extrapolation of a step: its level
+// set phi0(xi) in double (it decides the solid set), or +inf if it holds no map
+template <typename C>
+__device__ __forceinline__ double relabel_phi(const GridP& g, const BodyP& b, int8_t tv, C xv,
+                                              C yv, int i, int j)
+{
+    if (!tag_set(tv)) return INFINITY;
+    double X = (double)xv, Y = (double)yv;
+    if (sizeof(C) == 4) {  // displacement storage
+        X += node_coord(i, g.px, g.nx, b.cx);
+        Y += node_coord(j, g.py, g.ny, b.cy);
+    }
+    return shape_phi(b, X, Y);
+}
+
 // Shared body of the force kernel (MODE 0) and the stress read (MODE 1) over
 // interior tiles of region Rg: stage xi, phi of the tile plus a one-node halo
 // in LDS (all loads issued first), compute each half-edge once, then combine
-// per node.  In MODE 0, block 0 also reduces relabel's partial boxes into the
-// next ring slot.
+// per node.  MODE 0 also relabels (Alg. 1): phi^{n+1} = phi0(xi^{n+1}) is
+// evaluated for every staged node from its tag and map, written for the
+// tile's own nodes (with the map cleared where none is held), and for the
+// window's nodes outside the interior by a strided pass; each block writes
+// the partial box of the new interior solid set it saw, which the next
+// lattice update reduces into the next ring slot.
 template <int MODE, typename C>
-__device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvalid, int wnext,
-                                               const int* __restrict__ boxpart, int nbox,
-                                               int whole_grid, const C* __restrict__ X,
-                                               const C* __restrict__ Y, const C* __restrict__ phi,
-                                               double* o0, double* o1, double* o2, int* lcount,
-                                               unsigned* health)
+__device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvalid,
+                                           int* boxpart, int whole_grid, C* X, C* Y,
+                                           const C* __restrict__ phi, const int8_t* __restrict__ tag,
+                                           C* phi1, double* o0, double* o1, double* o2,
+                                           int* lcount, unsigned* health)
 {
     // the force pass ends the reference-map chain of a step: clear the layer
     // counters of the next step's distance transform
@@ -1100,21 +990,21 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
     __shared__ C ex[FTY][FTX + 1][3];
     __shared__ C ey[FTY + 1][FTX][3];
     const Rect V = window_of(win, wvalid, g);
-    if (MODE == 0 && blockIdx.x == 0) reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
+    int bi0 = 0x3fffffff, bi1 = -0x3fffffff, bj0 = 0x3fffffff, bj1 = -0x3fffffff;
     Rect Rg;
     if (whole_grid) {
         Rg.i0 = 0; Rg.i1 = g.nx - 1; Rg.j0 = 0; Rg.j1 = g.ny - 1;
         Rg.ok = true;
     } else {
         Rg = V;
-        if (!Rg.ok) return;
         Rg.i0 = max(Rg.i0, 0);
         Rg.j0 = max(Rg.j0, 0);
         Rg.i1 = min(Rg.i1, g.nx - 1);
         Rg.j1 = min(Rg.j1, g.ny - 1);
-        if (Rg.i0 > Rg.i1 || Rg.j0 > Rg.j1) return;
+        Rg.ok = V.ok && Rg.i0 <= Rg.i1 && Rg.j0 <= Rg.j1;
     }
-    const int ntx = (Rg.i1 - Rg.i0) / FTX + 1, nty = (Rg.j1 - Rg.j0) / FTY + 1;
+    const int ntx = Rg.ok ? (Rg.i1 - Rg.i0) / FTX + 1 : 0;
+    const int nty = Rg.ok ? (Rg.j1 - Rg.j0) / FTY + 1 : 0;
     const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
     for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
         const int i0 = Rg.i0 + (t % ntx) * FTX, j0 = Rg.j0 + (t / ntx) * FTY;
@@ -1122,7 +1012,10 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
             int ci = i0 - 1 + e % SX, cj = j0 - 1 + e / SX;
             const bool in = b.present && canon(g, ci, cj) && V.has(ci, cj);
             const long long k = in ? pidx(g, ci, cj) : 0;
-            const C p = phi[k], xv = X[k], yv = Y[k];
+            const C xv = X[k], yv = Y[k];
+            C p;
+            if (MODE == 0) p = store_phi<C>(relabel_phi<C>(g, b, tag[k], xv, yv, ci, cj));
+            else p = phi[k];
             const bool set = in && p < C(INFINITY);
             sX[e] = set ? xv : C(NAN);
             sY[e] = set ? yv : C(NAN);
@@ -1131,6 +1024,24 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
         __syncthreads();
         const int i = i0 + tx, j = j0 + ty;
         const bool mine = i <= Rg.i1 && j <= Rg.j1;
+        if (MODE == 0 && mine) {
+            // relabel output of the tile's own node
+            const long long k = pidx(g, i, j);
+            const C p = sP[(ty + 1) * SX + tx + 1];
+            if (p < C(INFINITY)) {
+                phi1[k] = p;
+                if (p < C(0)) {
+                    bi0 = min(bi0, i);
+                    bi1 = max(bi1, i);
+                    bj0 = min(bj0, j);
+                    bj1 = max(bj1, j);
+                }
+            } else if (V.has(i, j)) {
+                phi1[k] = C(INFINITY);
+                X[k] = C(NAN);
+                Y[k] = C(NAN);
+            }
+        }
         // health counting: an edge is counted once, by the node on its far
         // side, or by its near node when the far node lies outside the region
         const bool rowin = j <= Rg.j1, colin = i <= Rg.i1;
@@ -1189,17 +1100,38 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
         }
         __syncthreads();
     }
+    if (MODE == 0) {
+        // relabel of the window's nodes outside the interior (buffer nodes)
+        if (V.ok && b.present) {
+            const int w = V.i1 - V.i0 + 1, h = V.j1 - V.j0 + 1;
+            for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+                 e < (long long)w * h; e += (long long)gridDim.x * blockDim.x) {
+                const int i = V.i0 + (int)(e % w), j = V.j0 + (int)(e / w);
+                if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) continue;
+                const long long k = pidx(g, i, j);
+                const double p = relabel_phi<C>(g, b, tag[k], X[k], Y[k], i, j);
+                if (p < INFINITY) {
+                    phi1[k] = store_phi<C>(p);
+                } else {
+                    phi1[k] = C(INFINITY);
+                    X[k] = C(NAN);
+                    Y[k] = C(NAN);
+                }
+            }
+        }
+        block_box(bi0, bi1, bj0, bj1, boxpart + 4 * blockIdx.x);
+    }
 }
 
 template <int MODE, typename C>
-__global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int wvalid, int wnext,
-                                               const int* __restrict__ boxpart, int nbox,
-                                               int whole_grid, const C* __restrict__ X,
-                                               const C* __restrict__ Y, const C* __restrict__ phi,
+__global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int wvalid,
+                                               int* boxpart, int whole_grid, C* X, C* Y,
+                                               const C* __restrict__ phi,
+                                               const int8_t* __restrict__ tag, C* phi1,
                                                double* o0, double* o1, double* o2, int* lcount,
                                                unsigned* health)
 {
-    edges_body<MODE, C>(g, b, win, wvalid, wnext, boxpart, nbox, whole_grid, X, Y, phi, o0, o1,
+    edges_body<MODE, C>(g, b, win, wvalid, boxpart, whole_grid, X, Y, phi, tag, phi1, o0, o1,
                         o2, lcount, health);
 }
 
@@ -1207,23 +1139,21 @@ template <typename C>
 __global__ __launch_bounds__(256) void kb_force(const EdgesArgs* __restrict__ args)
 {
     const EdgesArgs& a = args[blockIdx.y];
-    edges_body<0, C>(a.g, a.b, a.win, a.wvalid, a.wnext, a.boxpart, a.nbox, 0, (const C*)a.X,
-                     (const C*)a.Y, (const C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health);
+    edges_body<0, C>(a.g, a.b, a.win, a.wvalid, a.boxpart, 0, (C*)a.X, (C*)a.Y, nullptr, a.tag,
+                     (C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health);
 }
 
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                         double* fx, double* fy, double* drho, hipStream_t st)
 {
     if (g.rm32)
-        k_edges<0, float><<<2048, 256, 0, st>>>(
-            g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS, 0, (const float*)bb.X[s.nxt],
-            (const float*)bb.Y[s.nxt], (const float*)bb.phi[s.nxt], fx, fy, drho, bb.lcount,
-            bb.health);
+        k_edges<0, float><<<RELABEL_BLOCKS, 256, 0, st>>>(
+            g, b, bb.win, s.wcur, bb.boxpart, 0, (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt],
+            nullptr, bb.tag, (float*)bb.phi[s.nxt], fx, fy, drho, bb.lcount, bb.health);
     else
-        k_edges<0, double><<<2048, 256, 0, st>>>(
-            g, b, bb.win, s.wcur, s.wnext, bb.boxpart, RELABEL_BLOCKS, 0,
-            (const double*)bb.X[s.nxt], (const double*)bb.Y[s.nxt], (const double*)bb.phi[s.nxt],
-            fx, fy, drho, bb.lcount, bb.health);
+        k_edges<0, double><<<RELABEL_BLOCKS, 256, 0, st>>>(
+            g, b, bb.win, s.wcur, bb.boxpart, 0, (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt],
+            nullptr, bb.tag, (double*)bb.phi[s.nxt], fx, fy, drho, bb.lcount, bb.health);
     return hipGetLastError();
 }
 
@@ -1231,16 +1161,15 @@ hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb
                               int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st)
 {
     if (g.rm32)
-        k_edges<1, float><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1,
-                                                (const float*)bb.X[buf], (const float*)bb.Y[buf],
-                                                (const float*)bb.phi[buf], sxx, sxy, syy,
-                                                nullptr, bb.health);
+        k_edges<1, float><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, nullptr, 1,
+                                                (float*)bb.X[buf], (float*)bb.Y[buf],
+                                                (const float*)bb.phi[buf], nullptr, nullptr, sxx,
+                                                sxy, syy, nullptr, bb.health);
     else
-        k_edges<1, double><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, 0, nullptr, 0, 1,
-                                                 (const double*)bb.X[buf],
-                                                 (const double*)bb.Y[buf],
-                                                 (const double*)bb.phi[buf], sxx, sxy, syy,
-                                                 nullptr, bb.health);
+        k_edges<1, double><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, nullptr, 1,
+                                                 (double*)bb.X[buf], (double*)bb.Y[buf],
+                                                 (const double*)bb.phi[buf], nullptr, nullptr,
+                                                 sxx, sxy, syy, nullptr, bb.health);
     return hipGetLastError();
 }
 
@@ -1300,13 +1229,11 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
         if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv);
         for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
-        kb_relabel<double><<<gb, 256, 0, st>>>(t.rel);
         kb_force<double><<<gb, 256, 0, st>>>(t.edg);
     } else {
         if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv);
         for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
-        kb_relabel<float><<<gb, 256, 0, st>>>(t.rel);
         kb_force<float><<<gb, 256, 0, st>>>(t.edg);
     }
     return hipGetLastError();

@@ -241,13 +241,16 @@ __device__ __forceinline__ void lb_tile(const GridP& g, const S* __restrict__ A,
 // PART 0: every tile, per-node window tests.  PART 1: tiles outside the band
 // region only (uniform force).  PART 2: tiles of the band region only,
 // grid-stride.
+// PART 0 and PART 2 also reduce the force pass's nbox partial boxes of the
+// new solid set into ring slot wnext (block 0, before anything else).
 template <typename S, int PART, int LB_TX, int LB_TY, int R, bool NT>
 __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     GridP g, const S* __restrict__ A, S* __restrict__ B, const double* __restrict__ fpx,
     const double* __restrict__ fpy, const double* __restrict__ fcx, const double* __restrict__ fcy,
-    const double* __restrict__ drho, const Win* __restrict__ win, int wprev, int wcur,
-    double fpo_x, double fpo_y, unsigned* __restrict__ health)
+    const double* __restrict__ drho, Win* win, int wprev, int wcur, double fpo_x, double fpo_y,
+    unsigned* __restrict__ health, const int* __restrict__ boxpart, int nbox, int wnext)
 {
+    if (PART != 1 && nbox > 0 && blockIdx.x == 0) reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
     constexpr int TH = LB_TY * R;
     const int ntx = (g.nx + LB_TX - 1) / LB_TX;
     const int nty = (g.ny + TH - 1) / TH;
@@ -299,6 +302,8 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void kb_lb(const LbArgs* __restrict__
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const LbArgs& a = args[tile_sim[t]];
     const int local = t - a.tile_base;
+    // the member's first tile reduces the force pass's partial boxes
+    if (local == 0 && a.nbox > 0) reduce_boxes(a.boxpart, a.nbox, &a.winw[a.wnext], nullptr);
     const int ntx = (a.g.nx + LB_TX - 1) / LB_TX;
     const Rect wp = window_of(a.win, a.wprev, a.g);
     const Rect wc = window_of(a.win, a.wcur, a.g);
@@ -330,27 +335,29 @@ void lb_variant_tile(int v, int* tx, int* ty)
 template <typename S, int PART, int TX, int TY, int R, bool NT>
 static void lb_launch_one(const GridP& g, const void* A, void* B, const double* fpx,
                           const double* fpy, const double* fcx, const double* fcy,
-                          const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
-                          double fpo_y, int max_blocks, unsigned* health, hipStream_t st)
+                          const double* drho, Win* win, int wprev, int wcur, double fpo_x,
+                          double fpo_y, int max_blocks, unsigned* health, hipStream_t st,
+                          const int* boxpart, int nbox, int wnext)
 {
     const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY * R - 1) / (TY * R));
     int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles;
     if (PART == 1 && max_blocks > 0 && max_blocks < grid) grid = max_blocks;
     k_lb<S, PART, TX, TY, R, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx,
                                                           fcy, drho, win, wprev, wcur, fpo_x,
-                                                          fpo_y, health);
+                                                          fpo_y, health, boxpart, nbox, wnext);
 }
 
 template <typename S, int PART>
 static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, const double* fpx,
                               const double* fpy, const double* fcx, const double* fcy,
-                              const double* drho, const Win* win, int wprev, int wcur,
+                              const double* drho, Win* win, int wprev, int wcur,
                               double fpo_x, double fpo_y, int max_blocks, unsigned* health,
-                              hipStream_t st)
+                              hipStream_t st, const int* boxpart, int nbox, int wnext)
 {
 #define LBV(TX, TY, R, NT)                                                                       \
     lb_launch_one<S, PART, TX, TY, R, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
-                                          fpo_x, fpo_y, max_blocks, health, st)
+                                          fpo_x, fpo_y, max_blocks, health, st, boxpart, nbox,  \
+                                          wnext)
     switch (v) {
     case 1: LBV(128, 2, 1, false); break;
     case 2: LBV(256, 1, 1, false); break;
@@ -372,12 +379,14 @@ static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, con
 
 hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
-                     const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
-                     double fpo_y, int part, unsigned* health, hipStream_t st, int max_blocks)
+                     const double* drho, Win* win, int wprev, int wcur, double fpo_x,
+                     double fpo_y, int part, unsigned* health, hipStream_t st, int max_blocks,
+                     const int* boxpart, int nbox, Win* winw, int wnext)
 {
+    (void)winw;
 #define LBP(S, PARTV)                                                                        \
     lb_launch_variant<S, PARTV>(variant, g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
-                                fpo_x, fpo_y, max_blocks, health, st)
+                                fpo_x, fpo_y, max_blocks, health, st, boxpart, nbox, wnext)
     if (precision == 0) {
         if (part == 0) LBP(double, 0);
         else if (part == 1) LBP(double, 1);

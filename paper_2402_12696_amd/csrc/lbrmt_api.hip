@@ -221,11 +221,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
             b.done();
         }
         {
-            Bracket b(c, 2, band);
-            HIPCHK(c, launch_relabel(g, c->body, c->bb, s, band));
-            b.done();
-        }
-        {
+            // relabel and the stress divergence (one pass)
             Bracket b(c, 3, band);
             HIPCHK(c, launch_force(g, c->body, c->bb, s, c->Fx[s.cur], c->Fy[s.cur], c->drho,
                                    band));
@@ -246,16 +242,18 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
                 Bracket b(c, 5, main_s);
                 HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
                                     c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
-                                    s.wprev, s.wcur, ox, oy, 2, c->bb.health, main_s));
+                                    s.wprev, s.wcur, ox, oy, 2, c->bb.health, main_s, 0,
+                                    c->bb.boxpart, RELABEL_BLOCKS, c->bb.win, s.wnext));
                 b.done();
             }
             return LBRMT_OK;
         }
     }
     Bracket b(c, 4, main_s);
-    HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt],
-                        c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win, s.wprev, s.wcur, ox, oy, 0,
-                        c->bb.health, main_s));
+    HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
+                        c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win, s.wprev,
+                        s.wcur, ox, oy, 0, c->bb.health, main_s, 0, c->bb.boxpart,
+                        c->nsolid > 0 ? RELABEL_BLOCKS : 0, c->bb.win, s.wnext));
     b.done();
     return LBRMT_OK;
 }
@@ -914,7 +912,7 @@ bool batch_layout(const lbrmt_grid_desc* d, int32_t n, BatchLayout& B)
         return r;
     };
     const size_t per = sizeof(AdvectArgs) + sizeof(LayersArgs) + sizeof(FitArgs) +
-                       sizeof(RelabelArgs) + sizeof(EdgesArgs) + sizeof(LbArgs);
+                       sizeof(EdgesArgs) + sizeof(LbArgs);
     B.tables = take(7 * (size_t)n * per + 6 * 7 * ALIGN);
     B.tile_cap = 0;
     for (int v = 0; v < lb_variant_count(); v++) {
@@ -956,7 +954,6 @@ int batch_tables(lbrmt_batch* b)
     std::vector<AdvectArgs> adv(n);
     std::vector<LayersArgs> lay(n);
     std::vector<FitArgs> fit(n);
-    std::vector<RelabelArgs> rel(n);
     std::vector<EdgesArgs> edg(n);
     std::vector<LbArgs> lb(n);
     int base = 0;
@@ -982,22 +979,19 @@ int batch_tables(lbrmt_batch* b)
                                 c->bb.lcount, c->bb.health};
             fit[k] = FitArgs{g, c->bb.win, s.wcur, s.wprev, c->bb.tag, c->bb.lists, c->bb.lcount,
                              c->bb.phi[s.cur], c->bb.X[s.nxt], c->bb.Y[s.nxt], c->bb.health};
-            rel[k] = RelabelArgs{g, c->body, c->bb.tag, c->bb.win, s.wcur, c->bb.X[s.nxt],
-                                 c->bb.Y[s.nxt], c->bb.phi[s.nxt], c->bb.boxpart};
-            edg[k] = EdgesArgs{g, c->body, c->bb.win, s.wcur, s.wnext, c->bb.boxpart,
-                               BATCH_BAND_BLOCKS, c->bb.X[s.nxt], c->bb.Y[s.nxt],
-                               c->bb.phi[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho,
-                               c->bb.lcount, c->bb.health};
+            edg[k] = EdgesArgs{g, c->body, c->bb.win, s.wcur, c->bb.boxpart, c->bb.X[s.nxt],
+                               c->bb.Y[s.nxt], c->bb.tag, c->bb.phi[s.nxt], c->Fx[s.cur],
+                               c->Fy[s.cur], c->drho, c->bb.lcount, c->bb.health};
             lb[k] = LbArgs{g, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt],
                            c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win, s.wprev, s.wcur,
-                           fpo_x(c, nstep), fpo_y(c, nstep), c->bb.health, base};
+                           fpo_x(c, nstep), fpo_y(c, nstep), c->bb.health, base, c->bb.win,
+                           c->bb.boxpart, c->nsolid > 0 ? BATCH_BAND_BLOCKS : 0, s.wnext};
             base += (int)batch_tile_count(c->d, b->lb_variant);
         }
         const BatchTables& T = b->tab[p];
         BCHK(b, hipMemcpyAsync(T.adv, adv.data(), n * sizeof(AdvectArgs), hipMemcpyHostToDevice, b->st));
         BCHK(b, hipMemcpyAsync(T.lay, lay.data(), n * sizeof(LayersArgs), hipMemcpyHostToDevice, b->st));
         BCHK(b, hipMemcpyAsync(T.fit, fit.data(), n * sizeof(FitArgs), hipMemcpyHostToDevice, b->st));
-        BCHK(b, hipMemcpyAsync(T.rel, rel.data(), n * sizeof(RelabelArgs), hipMemcpyHostToDevice, b->st));
         BCHK(b, hipMemcpyAsync(T.edg, edg.data(), n * sizeof(EdgesArgs), hipMemcpyHostToDevice, b->st));
         BCHK(b, hipMemcpyAsync(T.lb, lb.data(), n * sizeof(LbArgs), hipMemcpyHostToDevice, b->st));
         // the host vectors are reused for the next phase: wait for the copies
@@ -1093,7 +1087,6 @@ int lbrmt_batch_create(const lbrmt_grid_desc* descs, const lbrmt_solid_desc* sol
         b->tab[p].adv = (AdvectArgs*)carve(n * sizeof(AdvectArgs));
         b->tab[p].lay = (LayersArgs*)carve(n * sizeof(LayersArgs));
         b->tab[p].fit = (FitArgs*)carve(n * sizeof(FitArgs));
-        b->tab[p].rel = (RelabelArgs*)carve(n * sizeof(RelabelArgs));
         b->tab[p].edg = (EdgesArgs*)carve(n * sizeof(EdgesArgs));
         b->tab[p].lb = (LbArgs*)carve(n * sizeof(LbArgs));
     }

@@ -74,6 +74,79 @@ struct BandBufs {
     unsigned* health;
 };
 
+// ---- box reductions (wave64 shuffles + LDS)
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Reduces n partial boxes {i0, i1, j0, j1} (one block; every thread calls it)
+// into *dst0 (and *dst1 when not null); an empty result is the empty box.
+// SAME_KERNEL: the partials were written by other blocks of the running
+// kernel (read through volatile loads after the last-block handshake);
+// otherwise by an earlier kernel (plain loads, all issued at once).
+template <bool SAME_KERNEL = false>
+__device__ inline void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1)
+{
+    __shared__ int sb[4][16];
+    int a0 = 0x3fffffff, a1 = -0x3fffffff, a2 = 0x3fffffff, a3 = -0x3fffffff;
+    if (SAME_KERNEL) {
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const volatile int* q = part + 4 * k;
+            a0 = min(a0, q[0]);
+            a1 = max(a1, q[1]);
+            a2 = min(a2, q[2]);
+            a3 = max(a3, q[3]);
+        }
+    } else {
+        const int4* p4 = reinterpret_cast<const int4*>(part);
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int4 q = p4[k];
+            a0 = min(a0, q.x);
+            a1 = max(a1, q.y);
+            a2 = min(a2, q.z);
+            a3 = max(a3, q.w);
+        }
+    }
+    a0 = wave_min(a0);
+    a1 = wave_max(a1);
+    a2 = wave_min(a2);
+    a3 = wave_max(a3);
+    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int nw = (blockDim.x + 63) / 64;
+    if (lane == 0) {
+        sb[0][wid] = a0;
+        sb[1][wid] = a1;
+        sb[2][wid] = a2;
+        sb[3][wid] = a3;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; w++) {
+            a0 = min(a0, sb[0][w]);
+            a1 = max(a1, sb[1][w]);
+            a2 = min(a2, sb[2][w]);
+            a3 = max(a3, sb[3][w]);
+        }
+        Win r;
+        r.i0 = a0;
+        r.i1 = a1;
+        r.j0 = a2;
+        r.j1 = a3;
+        if (a0 > a1) r.i0 = 0x3fffffff, r.i1 = -0x3fffffff, r.j0 = 0x3fffffff, r.j1 = -0x3fffffff;
+        *dst0 = r;
+        if (dst1) *dst1 = r;
+    }
+    __syncthreads();
+}
+
 // Arguments of the step kernels for one member of a batch (device tables,
 // one entry per member; the batched kernels take member blockIdx.y).  Plane
 // pointers are untyped: the batch precision picks the kernel instance.
@@ -111,23 +184,15 @@ struct FitArgs {
     void *X1, *Y1;
     unsigned* health;
 };
-struct RelabelArgs {
-    GridP g;
-    BodyP b;
-    const int8_t* tag;
-    const Win* win;
-    int wcur;
-    void *X1, *Y1, *phi1;
-    int* boxpart;
-};
 struct EdgesArgs {
     GridP g;
     BodyP b;
     Win* win;
-    int wvalid, wnext;
-    const int* boxpart;
-    int nbox;
-    const void *X, *Y, *phi;
+    int wvalid;
+    int* boxpart;
+    void *X, *Y;
+    const int8_t* tag;
+    void* phi;  // written: the relabelled level set
     double *o0, *o1, *o2;
     int* lcount;
     unsigned* health;
@@ -142,12 +207,14 @@ struct LbArgs {
     double fpo_x, fpo_y;
     unsigned* health;
     int tile_base;  // first entry of this member in the flattened tile list
+    Win* winw;      // the ring, for the reduction of the force pass's boxes
+    const int* boxpart;
+    int nbox, wnext;
 };
 struct BatchTables {
     AdvectArgs* adv;
     LayersArgs* lay;
     FitArgs* fit;
-    RelabelArgs* rel;
     EdgesArgs* edg;
     LbArgs* lb;
 };
@@ -251,11 +318,14 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
                              hipStream_t st);
 hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const int* tile_sim,
                            int total_tiles, hipStream_t st);
+// PART 0 / 2 launches with nbox > 0 also reduce the force pass's partial
+// boxes (boxpart) into ring slot wnext of win
 hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
-                     const double* drho, const Win* win, int wprev, int wcur, double fpo_x,
+                     const double* drho, Win* win, int wprev, int wcur, double fpo_x,
                      double fpo_y, int part, unsigned* health, hipStream_t st,
-                     int max_blocks = 0);
+                     int max_blocks = 0, const int* boxpart = nullptr, int nbox = 0,
+                     Win* winw = nullptr, int wnext = 0);
 int lb_variant_count();
 void lb_variant_tile(int v, int* tx, int* ty);
 hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
@@ -285,8 +355,6 @@ hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, 
 hipError_t launch_advect_layers(const GridP& g, int precision, const BandBufs& bb,
                                 const StepSlots& s, const void* A, const double* fpx,
                                 const double* fpy, hipStream_t st);
-hipError_t launch_relabel(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
-                          hipStream_t st);
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                         double* fx, double* fy, double* drho, hipStream_t st);
 hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
