@@ -190,12 +190,25 @@ static double node_y(const orc_sim* s, int j)
     return y;
 }
 
-/* reference level set of the disc: phi0(X) = |X - c| - R (Alg. 1 init) */
-static double phi0(const orc_sim* s, double X, double Y)
+/* Reference level set phi0(X) of a solid (Alg. 1 init and relabel).  Disc:
+ * |X - c| - R.  Ellipse (semi-axes a = R and b, a axis at angle theta): the
+ * paper gives no formula; we take |X - c| (1 - 1/q) with q the ellipse's
+ * normalised radius sqrt((x'/a)^2 + (y'/b)^2) in the body frame, which is
+ * zero exactly on the ellipse, negative inside, and equal to the disc's
+ * |X - c| - R when a = b.  At the centre itself it is -min(a, b). */
+double orc_phi0(const orc_solid* body, double X, double Y)
 {
-    double dx = X - s->body.cx, dy = Y - s->body.cy;
-    return sqrt(dx * dx + dy * dy) - s->body.R;
+    double dx = X - body->cx, dy = Y - body->cy;
+    double d = sqrt(dx * dx + dy * dy);
+    if (body->shape != 1) return d - body->R;
+    if (d == 0.0) return -(body->R < body->b ? body->R : body->b);
+    double c = cos(body->theta), sn = sin(body->theta);
+    double xp = c * dx + sn * dy, yp = -sn * dx + c * dy;
+    double q = sqrt((xp / body->R) * (xp / body->R) + (yp / body->b) * (yp / body->b));
+    return d * (1.0 - 1.0 / q);
 }
+
+static double phi0(const orc_sim* s, double X, double Y) { return orc_phi0(&s->body, X, Y); }
 
 /* loop bounds of the reference-map domain along an axis */
 static int dom_lo(int periodic) { return periodic ? 0 : -2; }
@@ -215,6 +228,9 @@ static int solid_node(const orc_sim* s, int i, int j)
 orc_sim* orc_create(const orc_params* p, const orc_solid* solids, int32_t nsolid)
 {
     if (!p || p->nx < 4 || p->ny < 4 || nsolid < 0 || nsolid > 1) return NULL;
+    if (nsolid && (solids[0].shape < 0 || solids[0].shape > 1 || !(solids[0].R > 0.0) ||
+                   (solids[0].shape == 1 && !(solids[0].b > 0.0))))
+        return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
     s->nsolid = nsolid;

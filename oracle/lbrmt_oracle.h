@@ -42,10 +42,14 @@ typedef struct {
 } orc_params;
 
 typedef struct {
-    double cx, cy;      /* disc centre in the reference configuration        */
-    double R;           /* disc radius                                       */
+    double cx, cy;      /* centre in the reference configuration             */
+    double R;           /* disc radius; the ellipse's semi-axis a            */
     double G;           /* small-strain shear modulus                        */
     double rho_s;       /* solid density                                     */
+    int32_t shape;      /* 0 disc, 1 ellipse                                 */
+    int32_t reserved;
+    double b;           /* ellipse: semi-axis b                              */
+    double theta;       /* ellipse: angle of the a axis to the x axis        */
 } orc_solid;
 
 /* counters kept by the oracle (index into orc_counters' output) */
@@ -103,6 +107,7 @@ void   orc_feq_sfc(double rho, double ux, double uy, double drho, double* feq9);
 void   orc_guo(double ux, double uy, double fx, double fy, double* fi9);
 /* J = [dX/dx, dX/dy, dY/dx, dY/dy]; returns 0 and tau = 0 if det J <= detJ_min */
 int    orc_solid_stress(const double* J4, double G, double detJ_min, double* tau3);
+double orc_phi0(const orc_solid* body, double X, double Y);
 /* layers on an arbitrary nx*ny mask grid (4-adjacency, non-periodic), literal
  * layer-by-layer marking; solid != 0 marks S; out: 0 solid, l, or -1 */
 void   orc_layers_mask(int32_t nx, int32_t ny, const uint8_t* solid, int32_t L, int32_t* out);

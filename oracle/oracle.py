@@ -36,7 +36,28 @@ class _Params(ctypes.Structure):
 
 class _Solid(ctypes.Structure):
     _fields_ = [("cx", ctypes.c_double), ("cy", ctypes.c_double), ("R", ctypes.c_double),
-                ("G", ctypes.c_double), ("rho_s", ctypes.c_double)]
+                ("G", ctypes.c_double), ("rho_s", ctypes.c_double),
+                ("shape", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("b", ctypes.c_double), ("theta", ctypes.c_double)]
+
+
+def _solid(d):
+    """A solid description (``workloads`` keywords): a disc of radius R, or
+    with ``shape="ellipse"`` an ellipse of semi-axes a = R and b whose a axis
+    makes the angle theta with the x axis."""
+    shape = d.get("shape", "disc")
+    if shape not in ("disc", "ellipse"):
+        raise ValueError(f"unknown solid shape {shape!r}")
+    ell = shape == "ellipse"
+    return _Solid(d["cx"], d["cy"], d["R"], d["G"], d["rho_s"], int(ell), 0,
+                  float(d.get("b", d["R"])) if ell else d["R"],
+                  float(d.get("theta", 0.0)) if ell else 0.0)
+
+
+def phi0(solid, X, Y):
+    """Reference level set of a solid description at reference point (X, Y)."""
+    s = _solid(solid)
+    return lib().orc_phi0(ctypes.byref(s), float(X), float(Y))
 
 
 _lib = None
@@ -75,6 +96,8 @@ def lib():
         L.orc_guo.argtypes = [ctypes.c_double] * 4 + [_dp]
         L.orc_solid_stress.restype = ctypes.c_int
         L.orc_solid_stress.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_phi0.restype = ctypes.c_double
+        L.orc_phi0.argtypes = [ctypes.POINTER(_Solid), ctypes.c_double, ctypes.c_double]
         L.orc_layers_mask.argtypes = [ctypes.c_int32, ctypes.c_int32, _u8p, ctypes.c_int32, _ip]
         L.orc_d2q9.argtypes = [_ip, _ip, _dp]
         _lib = L
@@ -140,7 +163,7 @@ class Oracle:
                     det_rel, detJ_min, int(reverse_order))
         self.nx, self.ny = nx, ny
         if solid is not None:
-            s = _Solid(solid["cx"], solid["cy"], solid["R"], solid["G"], solid["rho_s"])
+            s = _solid(solid)
             self._h = lib().orc_create(ctypes.byref(p), ctypes.byref(s), 1)
         else:
             self._h = lib().orc_create(ctypes.byref(p), None, 0)

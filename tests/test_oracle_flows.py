@@ -129,13 +129,14 @@ def test_undeformed_solid_at_rest_keeps_xi_equal_x():
     assert np.max(np.abs(X[m] - x[m])) < tol and np.max(np.abs(Y[m] - y[m])) < tol
 
 
-def test_rigid_translation():
-    # uniform flow through a periodic box with a neutrally buoyant disc: grad xi
-    # stays the identity (no stress, no force), the flow stays uniform and
-    # xi(x, t) = x - u t exactly
+@pytest.mark.parametrize("shape", [dict(), dict(shape="ellipse", b=5.0, theta=0.7)])
+def test_rigid_translation(shape):
+    # uniform flow through a periodic box with a neutrally buoyant disc or
+    # ellipse: grad xi stays the identity (no stress, no force), the flow stays
+    # uniform and xi(x, t) = x - u t exactly
     n, u = 64, np.array([0.05, 0.02])
     cfg = workloads.make(nx=n, ny=n, tau=0.7, periodic_x=True, periodic_y=True,
-                         solid=dict(cx=24.0, cy=28.0, R=8.0, G=0.01, rho_s=1.0))
+                         solid=dict(cx=24.0, cy=28.0, R=8.0, G=0.01, rho_s=1.0, **shape))
     o = Oracle(**cfg).init(workloads.uniform_velocity(n, n, *u))
     steps = 200
     o.step(steps)
