@@ -74,13 +74,18 @@ typedef struct {
     int32_t reserved;
 } lbrmt_grid_desc;
 
-/* One solid (Sec. 3.6 "mat_const"/"object"): a disc (shape 0) of radius a. */
+/* One solid (Sec. 3.6 "mat_const"/"object"): a disc (shape 0) of radius a, or
+ * an ellipse (shape 1) of semi-axes a and b whose a axis makes the angle theta
+ * with the x axis.  The reference level set is the disc's signed distance
+ * |X - c| - a, and for the ellipse |X - c| (1 - 1/q) with
+ * q = sqrt((x'/a)^2 + (y'/b)^2) in the body frame (negative inside, zero on
+ * the boundary, the disc's when a = b).  Other shapes: LBRMT_EINVAL. */
 typedef struct {
-    int32_t shape;           /* 0: disc                                          */
+    int32_t shape;           /* 0: disc, 1: ellipse                              */
     int32_t reserved;
     double cx, cy;           /* centre of the reference (undeformed) shape       */
-    double a, b;             /* disc: radius a (b unused)                        */
-    double theta;            /* orientation (unused for a disc)                  */
+    double a, b;             /* disc: radius a (b unused); ellipse: semi-axes    */
+    double theta;            /* ellipse: angle of the a axis (radians)           */
     double G;                /* small-strain shear modulus                       */
     double rho_s;            /* solid density                                    */
 } lbrmt_solid_desc;

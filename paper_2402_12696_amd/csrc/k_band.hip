@@ -42,11 +42,21 @@ __device__ __forceinline__ C heaviside(C phi, C eps)
     return C(0.5) * (C(1) + phi / eps + sin(pi * phi / eps) / pi);
 }
 
-// reference shape level set phi0(X): disc |X - c| - R
+// reference shape level set phi0(X) (Sec. 3.1): the disc's signed distance
+// |X - c| - R; for an ellipse the radial form |X - c| (1 - 1/q), with q the
+// normalised radius sqrt((x'/R)^2 + (y'/Rb)^2) in the body frame, zero on the
+// boundary and negative inside (at the centre: minus the smaller semi-axis).
+// Built without contraction: the sign taken at initialisation and relabel
+// decides node sets, so the arithmetic is the plain sequence of rounded ops.
 __device__ __forceinline__ double shape_phi(const BodyP& b, double X, double Y)
 {
     const double dx = X - b.cx, dy = Y - b.cy;
-    return sqrt(dx * dx + dy * dy) - b.R;
+    const double d = sqrt(dx * dx + dy * dy);
+    if (b.shape != 1) return d - b.R;
+    if (d == 0.0) return -(b.R < b.Rb ? b.R : b.Rb);
+    const double xp = b.ct * dx + b.st * dy, yp = -b.st * dx + b.ct * dy;
+    const double q = sqrt((xp / b.R) * (xp / b.R) + (yp / b.Rb) * (yp / b.Rb));
+    return d * (1.0 - 1.0 / q);
 }
 
 // coordinate of node index i on an axis; on a periodic axis the image nearest

@@ -9,6 +9,7 @@
 // captured once into a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -416,22 +417,38 @@ void lbrmt_destroy(lbrmt_ctx* c)
     delete c;
 }
 
+// disc of radius a > 0, or ellipse of semi-axes a, b > 0
+static bool solid_shape_ok(const lbrmt_solid_desc& s)
+{
+    return (s.shape == 0 && s.a > 0.0) || (s.shape == 1 && s.a > 0.0 && s.b > 0.0);
+}
+
+// largest distance from the centre to the reference shape's boundary
+static double solid_extent(const lbrmt_solid_desc& s)
+{
+    return s.shape == 1 ? std::max(s.a, s.b) : s.a;
+}
+
 int lbrmt_add_solids(lbrmt_ctx* c, const lbrmt_solid_desc* s, int32_t n)
 {
     if (!c || (n > 0 && !s) || n < 0) return LBRMT_EINVAL;
     if (c->inited) return LBRMT_ESTATE;
     if (c->nsolid + n > c->max_solids) return LBRMT_ECAPACITY;
     for (int k = 0; k < n; k++) {
-        if (s[k].shape != 0 || !(s[k].a > 0.0) || !(s[k].rho_s > 0.0) || !(s[k].G >= 0.0))
+        if (!solid_shape_ok(s[k]) || !(s[k].rho_s > 0.0) || !(s[k].G >= 0.0))
             return LBRMT_EINVAL;
     }
     if (n > 0) {
         c->solid = s[0];
         c->nsolid = 1;
         c->body.present = 1;
+        c->body.shape = s[0].shape;
         c->body.cx = s[0].cx;
         c->body.cy = s[0].cy;
         c->body.R = s[0].a;
+        c->body.Rb = s[0].shape == 1 ? s[0].b : s[0].a;
+        c->body.ct = s[0].shape == 1 ? std::cos(s[0].theta) : 1.0;
+        c->body.st = s[0].shape == 1 ? std::sin(s[0].theta) : 0.0;
         c->body.G = s[0].G;
         c->body.rho_s = s[0].rho_s;
     }
@@ -694,8 +711,8 @@ int lbrmt_validate(const lbrmt_grid_desc* d, const lbrmt_solid_desc* s, int32_t 
     out->mach_ok = out->mach_lb <= 0.3;
     out->solids_inside = 1;
     for (int k = 0; k < n; k++) {
-        if (s[k].shape != 0 || !(s[k].a > 0.0)) return LBRMT_EINVAL;
-        const double m = s[k].a + d->layers;
+        if (!solid_shape_ok(s[k])) return LBRMT_EINVAL;
+        const double m = solid_extent(s[k]) + d->layers;
         if (!d->periodic_x && (s[k].cx - m < -2 || s[k].cx + m > d->nx + 2)) out->solids_inside = 0;
         if (!d->periodic_y && (s[k].cy - m < -2 || s[k].cy + m > d->ny + 2)) out->solids_inside = 0;
         if (d->periodic_x && (s[k].cx - m < 0 || s[k].cx + m > d->nx)) out->solids_inside = 0;

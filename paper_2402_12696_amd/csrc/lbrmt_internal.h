@@ -54,7 +54,10 @@ constexpr double KAPPA_J = 0.25;
 
 struct BodyP {
     int present;
+    int shape;            // 0 disc of radius R; 1 ellipse of semi-axes R and Rb
     double cx, cy, R, G, rho_s;
+    double Rb;            // ellipse semi-axis b
+    double ct, st;        // cos, sin of the angle of the R axis (host libm)
 };
 
 // Step-invariant pointers of the reference-map state.

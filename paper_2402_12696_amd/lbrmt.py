@@ -188,8 +188,14 @@ def make_grid_desc(nx, ny, tau, lid_ux=0.0, periodic_x=False, periodic_y=False,
                            det_rel, detJ_min, prec, 0)
 
 
-def make_solid_desc(cx, cy, R, G, rho_s, **_ignored):
-    return lbrmt_solid_desc(0, 0, cx, cy, R, 0.0, 0.0, G, rho_s)
+def make_solid_desc(cx, cy, R, G, rho_s, shape="disc", b=None, theta=0.0, **_ignored):
+    """A disc of radius R, or (shape="ellipse") an ellipse of semi-axes R and
+    b with its R axis at angle theta to the x axis."""
+    if shape == "disc":
+        return lbrmt_solid_desc(0, 0, cx, cy, R, 0.0, 0.0, G, rho_s)
+    if shape == "ellipse":
+        return lbrmt_solid_desc(1, 0, cx, cy, R, R if b is None else b, theta, G, rho_s)
+    raise ValueError(f"unknown solid shape {shape!r}")
 
 
 def lbrmt_workspace_bytes(desc, max_solids):
@@ -398,7 +404,8 @@ class Sim:
 
     Keywords are those of ``workloads.make`` (nx, ny, tau, lid_ux, periodic_x,
     periodic_y, gravity, fext, rho_f, eps, layers, r_max, det_rel, detJ_min,
-    solid={cx, cy, R, G, rho_s}) plus precision="f64"|"f32".
+    solid={cx, cy, R, G, rho_s[, shape="ellipse", b, theta]}) plus
+    precision="f64"|"f32".
     """
 
     owner = True

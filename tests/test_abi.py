@@ -102,3 +102,20 @@ def test_validate_unit_conversions():
     assert v["tau_ok"] == 0 and v["mach_ok"] == 0
     v = B.lbrmt_validate(d, [B.make_solid_desc(5, 40, 12, 0.01, 1.0)])
     assert v["solids_inside"] == 0
+
+
+def test_validate_solid_shapes():
+    d = B.make_grid_desc(nx=64, ny=64, tau=0.8, lid_ux=0.1)
+    ell = B.make_solid_desc(32, 40, 12, 0.01, 1.0, shape="ellipse", b=6.0, theta=0.3)
+    assert (ell.shape, ell.a, ell.b, ell.theta) == (1, 12.0, 6.0, 0.3)
+    assert B.lbrmt_validate(d, [ell])["solids_inside"] == 1
+    # the extent is the larger semi-axis
+    wide = B.make_solid_desc(32, 32, 6, 0.01, 1.0, shape="ellipse", b=30.0)
+    assert B.lbrmt_validate(d, [wide])["solids_inside"] == 0
+    for bad in (B.lbrmt_solid_desc(2, 0, 32, 40, 12, 6, 0, 0.01, 1.0),
+                B.lbrmt_solid_desc(1, 0, 32, 40, 12, 0, 0, 0.01, 1.0),
+                B.lbrmt_solid_desc(0, 0, 32, 40, 0, 0, 0, 0.01, 1.0)):
+        with pytest.raises(B.LBRMTError):
+            B.lbrmt_validate(d, [bad])
+    with pytest.raises(ValueError):
+        B.make_solid_desc(32, 40, 12, 0.01, 1.0, shape="square")
