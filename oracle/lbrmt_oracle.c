@@ -6,6 +6,12 @@
  * the whole grid, in the order of Alg. 1, with the formulas in the paper's own
  * notation.  OpenMP only splits independent per-node loops; nothing is fused,
  * blocked or reordered.  Built with -ffp-contract=off.
+ *
+ * Several solids (Sec. 3.6): every solid keeps its own reference map, level
+ * set and extrapolation zone on the whole padded grid (the role of the
+ * paper's per-node list of maps), each advected, extrapolated and relabelled
+ * exactly as a single solid is.  They meet only in the stress, force and
+ * density of the shared lattice.
  */
 #define _GNU_SOURCE
 #include "lbrmt_oracle.h"
@@ -23,10 +29,20 @@ static const double WQ[NQ] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 
 static const double CS2 = 1.0 / 3.0; /* c_s^2, Sec. 2.2 */
 static const double PI = 3.14159265358979323846;
 
+/* one solid's reference map state on the padded grid */
+typedef struct {
+    orc_solid body;
+    double *X, *Y, *phi;    /* xi^n, phi^n                                 */
+    unsigned char* set;     /* node holds a value of this map              */
+    double *X1, *Y1, *phi1; /* new values being built during a step        */
+    unsigned char* set1;
+    int* layer;             /* 0 solid, l = 1..L layer, -1 none            */
+} orc_map;
+
 struct orc_sim {
     orc_params p;
     int nsolid;
-    orc_solid body;
+    orc_map* m;             /* nsolid maps                                 */
     int nxp, nyp;           /* padded extents                              */
     int ox, oy;             /* padding offset: 2 on walled axes, 0 periodic */
     long N, NP;
@@ -39,15 +55,9 @@ struct orc_sim {
     double* uy;
     double* Fx;             /* force density of the last step */
     double* Fy;
-    /* reference map state (padded grid) at step n */
-    double *X, *Y, *phi;
-    unsigned char* set;
-    /* new values being built during a step */
-    double *X1, *Y1, *phi1;
-    unsigned char* set1;
-    int* layer;             /* 0 solid, l = 1..L layer, -1 none */
     int have_new;           /* advect/extrapolate done, relabel pending */
-    /* half-edge blended solid stress: x-edges and y-edges, (xx, xy, yy) */
+    /* half-edge global solid stress (blend of all solids plus contact):
+     * x-edges and y-edges, (xx, xy, yy) */
     double *ex, *ey;
     long step;
     long cnt[ORC_CNT_N];
@@ -143,6 +153,7 @@ void orc_layers_mask(int32_t nx, int32_t ny, const uint8_t* solid, int32_t L, in
 }
 
 /* ------------------------------------------------------------------ */
+/* ------------------------------------------------------------------ */
 /* grid helpers                                                       */
 /* ------------------------------------------------------------------ */
 
@@ -167,25 +178,26 @@ static int is_interior(const orc_sim* s, int i, int j)
     return i >= 0 && i < s->p.nx && j >= 0 && j < s->p.ny;
 }
 
-/* position of node index i along an axis; on a periodic axis the nearest
- * image to the body centre is used, so a reference map stays continuous */
-static double node_x(const orc_sim* s, int i)
+/* position of node index i along an axis, seen by solid m; on a periodic
+ * axis the nearest image to the solid's reference centre is used, so its
+ * reference map stays continuous across the boundary */
+static double node_x(const orc_sim* s, const orc_map* m, int i)
 {
     double x = i + 0.5;
-    if (s->p.periodic_x && s->nsolid) {
-        double L = s->p.nx, d = x - s->body.cx;
+    if (s->p.periodic_x) {
+        double L = s->p.nx, d = x - m->body.cx;
         d -= L * floor(d / L + 0.5);
-        x = s->body.cx + d;
+        x = m->body.cx + d;
     }
     return x;
 }
-static double node_y(const orc_sim* s, int j)
+static double node_y(const orc_sim* s, const orc_map* m, int j)
 {
     double y = j + 0.5;
-    if (s->p.periodic_y && s->nsolid) {
-        double L = s->p.ny, d = y - s->body.cy;
+    if (s->p.periodic_y) {
+        double L = s->p.ny, d = y - m->body.cy;
         d -= L * floor(d / L + 0.5);
-        y = s->body.cy + d;
+        y = m->body.cy + d;
     }
     return y;
 }
@@ -208,33 +220,46 @@ double orc_phi0(const orc_solid* body, double X, double Y)
     return d * (1.0 - 1.0 / q);
 }
 
-static double phi0(const orc_sim* s, double X, double Y) { return orc_phi0(&s->body, X, Y); }
+static double phi0(const orc_map* m, double X, double Y) { return orc_phi0(&m->body, X, Y); }
 
 /* loop bounds of the reference-map domain along an axis */
 static int dom_lo(int periodic) { return periodic ? 0 : -2; }
 static int dom_hi(int periodic, int n) { return periodic ? n - 1 : n + 1; }
 
-static int solid_node(const orc_sim* s, int i, int j)
+static int solid_node(const orc_sim* s, const orc_map* m, int i, int j)
 {
     long k = pidx(s, i, j);
     if (k < 0 || !is_interior(s, i, j)) return 0;
-    return s->set[k] && s->phi[k] < 0.0;
+    return m->set[k] && m->phi[k] < 0.0;
+}
+
+/* solid fraction lambda = 1 - H(phi) of map m at padded index k (0 where the
+ * map holds no value) */
+static double lambda_at(const orc_sim* s, const orc_map* m, long k)
+{
+    return m->set[k] ? 1.0 - orc_heaviside(m->phi[k], s->p.eps) : 0.0;
 }
 
 /* ------------------------------------------------------------------ */
 /* lifecycle                                                          */
 /* ------------------------------------------------------------------ */
 
+static int solid_ok(const orc_solid* b)
+{
+    if (b->shape < 0 || b->shape > 1 || !(b->R > 0.0)) return 0;
+    if (b->shape == 1 && !(b->b > 0.0)) return 0;
+    return b->rho_s > 0.0 && b->G >= 0.0;
+}
+
 orc_sim* orc_create(const orc_params* p, const orc_solid* solids, int32_t nsolid)
 {
-    if (!p || p->nx < 4 || p->ny < 4 || nsolid < 0 || nsolid > 1) return NULL;
-    if (nsolid && (solids[0].shape < 0 || solids[0].shape > 1 || !(solids[0].R > 0.0) ||
-                   (solids[0].shape == 1 && !(solids[0].b > 0.0))))
-        return NULL;
+    if (!p || p->nx < 4 || p->ny < 4 || nsolid < 0 || nsolid > ORC_MAX_SOLIDS) return NULL;
+    if (nsolid && !solids) return NULL;
+    for (int b = 0; b < nsolid; b++)
+        if (!solid_ok(&solids[b])) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
     s->nsolid = nsolid;
-    if (nsolid) s->body = solids[0];
     s->ox = p->periodic_x ? 0 : 2;
     s->oy = p->periodic_y ? 0 : 2;
     s->nxp = p->nx + 2 * s->ox;
@@ -249,15 +274,20 @@ orc_sim* orc_create(const orc_params* p, const orc_solid* solids, int32_t nsolid
     s->uy = (double*)calloc(s->N, sizeof(double));
     s->Fx = (double*)calloc(s->N, sizeof(double));
     s->Fy = (double*)calloc(s->N, sizeof(double));
-    s->X = (double*)calloc(s->NP, sizeof(double));
-    s->Y = (double*)calloc(s->NP, sizeof(double));
-    s->phi = (double*)calloc(s->NP, sizeof(double));
-    s->set = (unsigned char*)calloc(s->NP, 1);
-    s->X1 = (double*)calloc(s->NP, sizeof(double));
-    s->Y1 = (double*)calloc(s->NP, sizeof(double));
-    s->phi1 = (double*)calloc(s->NP, sizeof(double));
-    s->set1 = (unsigned char*)calloc(s->NP, 1);
-    s->layer = (int*)calloc(s->NP, sizeof(int));
+    s->m = (orc_map*)calloc(nsolid > 0 ? nsolid : 1, sizeof(orc_map));
+    for (int b = 0; b < nsolid; b++) {
+        orc_map* m = &s->m[b];
+        m->body = solids[b];
+        m->X = (double*)calloc(s->NP, sizeof(double));
+        m->Y = (double*)calloc(s->NP, sizeof(double));
+        m->phi = (double*)calloc(s->NP, sizeof(double));
+        m->set = (unsigned char*)calloc(s->NP, 1);
+        m->X1 = (double*)calloc(s->NP, sizeof(double));
+        m->Y1 = (double*)calloc(s->NP, sizeof(double));
+        m->phi1 = (double*)calloc(s->NP, sizeof(double));
+        m->set1 = (unsigned char*)calloc(s->NP, 1);
+        m->layer = (int*)calloc(s->NP, sizeof(int));
+    }
     s->ex = (double*)calloc(3 * (long)(p->nx + 2) * (p->ny + 2), sizeof(double));
     s->ey = (double*)calloc(3 * (long)(p->nx + 2) * (p->ny + 2), sizeof(double));
     return s;
@@ -268,34 +298,56 @@ void orc_destroy(orc_sim* s)
     if (!s) return;
     free(s->f); free(s->fhat); free(s->fnew);
     free(s->rho); free(s->ux); free(s->uy); free(s->Fx); free(s->Fy);
-    free(s->X); free(s->Y); free(s->phi); free(s->set);
-    free(s->X1); free(s->Y1); free(s->phi1); free(s->set1);
-    free(s->layer); free(s->ex); free(s->ey);
+    for (int b = 0; b < s->nsolid; b++) {
+        orc_map* m = &s->m[b];
+        free(m->X); free(m->Y); free(m->phi); free(m->set);
+        free(m->X1); free(m->Y1); free(m->phi1); free(m->set1);
+        free(m->layer);
+    }
+    free(s->m);
+    free(s->ex); free(s->ey);
     free(s);
 }
 
-/* mark layers 1..L around the current solid set S = {interior, phi < 0} */
-static void mark_layers(orc_sim* s)
+/* mark layers 1..L around solid m's current solid set S = {interior, phi < 0} */
+static void mark_layers(orc_sim* s, orc_map* m)
 {
     const int nx = s->p.nx, ny = s->p.ny, L = s->p.layers;
     const int i0 = dom_lo(s->p.periodic_x), i1 = dom_hi(s->p.periodic_x, nx);
     const int j0 = dom_lo(s->p.periodic_y), j1 = dom_hi(s->p.periodic_y, ny);
     for (int j = j0; j <= j1; j++)
-        for (int i = i0; i <= i1; i++) s->layer[pidx(s, i, j)] = solid_node(s, i, j) ? 0 : -1;
+        for (int i = i0; i <= i1; i++) m->layer[pidx(s, i, j)] = solid_node(s, m, i, j) ? 0 : -1;
     static const int NB[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
     for (int l = 1; l <= L; l++) {
         for (int j = j0; j <= j1; j++)
             for (int i = i0; i <= i1; i++) {
                 long k = pidx(s, i, j);
-                if (s->layer[k] != -1) continue;
+                if (m->layer[k] != -1) continue;
                 int hit = 0;
                 for (int d = 0; d < 4; d++) {
                     long kn = pidx(s, i + NB[d][0], j + NB[d][1]);
-                    if (kn >= 0 && s->layer[kn] == l - 1) hit = 1;
+                    if (kn >= 0 && m->layer[kn] == l - 1) hit = 1;
                 }
-                if (hit) s->layer[k] = l;
+                if (hit) m->layer[k] = l;
             }
     }
+}
+
+/* Density of the mixture at padded index k, Eq. (2_4_smooth_density) for
+ * one solid; for several, each solid's fraction replaces that much fluid and
+ * the fractions are normalised where they sum above one:
+ * rho_f + sum_i lambda_i (rho_s,i - rho_f) / max(1, sum_i lambda_i). */
+static double mixture_drho(const orc_sim* s, long k)
+{
+    double lsum = 0.0, acc = 0.0;
+    for (int b = 0; b < s->nsolid; b++) {
+        const orc_map* m = &s->m[b];
+        if (!m->set[k]) continue;
+        double lam = 1.0 - orc_heaviside(m->phi[k], s->p.eps);
+        lsum += lam;
+        acc += lam * (m->body.rho_s - s->p.rho_f);
+    }
+    return lsum > 1.0 ? acc / lsum : acc;
 }
 
 void orc_init(orc_sim* s, const double* u0)
@@ -303,46 +355,49 @@ void orc_init(orc_sim* s, const double* u0)
     const int nx = s->p.nx, ny = s->p.ny;
     const int i0 = dom_lo(s->p.periodic_x), i1 = dom_hi(s->p.periodic_x, nx);
     const int j0 = dom_lo(s->p.periodic_y), j1 = dom_hi(s->p.periodic_y, ny);
-    memset(s->set, 0, s->NP);
     memset(s->cnt, 0, sizeof(s->cnt));
     s->step = 0;
     s->have_new = 0;
-    if (s->nsolid) {
+    for (int b = 0; b < s->nsolid; b++) {
+        orc_map* m = &s->m[b];
         /* solid set from phi0(x) (Alg. 1: label by phi(xi_0) with xi_0 = x) */
         for (int j = j0; j <= j1; j++)
             for (int i = i0; i <= i1; i++) {
                 long k = pidx(s, i, j);
-                s->X[k] = node_x(s, i);
-                s->Y[k] = node_y(s, j);
-                s->phi[k] = phi0(s, s->X[k], s->Y[k]);
-                s->set[k] = 1;
+                m->X[k] = node_x(s, m, i);
+                m->Y[k] = node_y(s, m, j);
+                m->phi[k] = phi0(m, m->X[k], m->Y[k]);
+                m->set[k] = 1;
             }
-        mark_layers(s);
+        mark_layers(s, m);
         /* xi_0 = x on the solid and its extrapolation zone (Sec. 3) */
         for (long k = 0; k < s->NP; k++) {
-            s->set[k] = s->layer[k] >= 0;
-            if (!s->set[k]) {
-                s->X[k] = s->Y[k] = NAN;
-                s->phi[k] = INFINITY;
+            m->set[k] = m->layer[k] >= 0;
+            if (!m->set[k]) {
+                m->X[k] = m->Y[k] = NAN;
+                m->phi[k] = INFINITY;
             }
         }
-    } else {
-        for (long k = 0; k < s->NP; k++) {
-            s->X[k] = s->Y[k] = NAN;
-            s->phi[k] = INFINITY;
-        }
     }
-    /* global density, Eq. (2_4_smooth_density); velocity v0; f = f^eq */
+    /* global density, Eq. (2_4_smooth_density) (several solids: rho_f plus
+     * the mixture term); velocity v0; f = f^eq */
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
             long n = (long)j * nx + i;
             long k = pidx(s, i, j);
-            double H = s->set[k] ? orc_heaviside(s->phi[k], s->p.eps) : 1.0;
-            double rs = s->nsolid ? s->body.rho_s : s->p.rho_f;
-            s->rho[n] = H * s->p.rho_f + (1.0 - H) * rs;
+            double drho; /* Eq. (2_3_drho) with rho = rho_t */
+            if (s->nsolid <= 1) {
+                const orc_map* m = s->nsolid ? &s->m[0] : NULL;
+                double H = (m && m->set[k]) ? orc_heaviside(m->phi[k], s->p.eps) : 1.0;
+                double rs = m ? m->body.rho_s : s->p.rho_f;
+                s->rho[n] = H * s->p.rho_f + (1.0 - H) * rs;
+                drho = s->rho[n] - s->p.rho_f;
+            } else {
+                drho = mixture_drho(s, k);
+                s->rho[n] = s->p.rho_f + drho;
+            }
             s->ux[n] = u0 ? u0[n] : 0.0;
             s->uy[n] = u0 ? u0[s->N + n] : 0.0;
-            double drho = s->rho[n] - s->p.rho_f; /* Eq. (2_3_drho) with rho = rho_t */
             double feq[NQ];
             orc_feq_sfc(s->rho[n], s->ux[n], s->uy[n], drho, feq);
             for (int q = 0; q < NQ; q++) s->f[q * s->N + n] = feq[q];
@@ -357,7 +412,7 @@ void orc_init(orc_sim* s, const double* u0)
 /* one-sided second-order upwind derivative, Eq. (3_1_eno), along (di, dj);
  * vel > 0 uses the nodes behind, vel < 0 the nodes ahead.  Returns 0 if a
  * stencil node holds no reference map. */
-static int upwind(const orc_sim* s, int i, int j, int di, int dj, double vel,
+static int upwind(const orc_sim* s, const orc_map* m, int i, int j, int di, int dj, double vel,
                   double* dX, double* dY)
 {
     *dX = *dY = 0.0;
@@ -366,44 +421,48 @@ static int upwind(const orc_sim* s, int i, int j, int di, int dj, double vel,
     long k0 = pidx(s, i, j);
     long k1 = pidx(s, i - sg * di, j - sg * dj);
     long k2 = pidx(s, i - 2 * sg * di, j - 2 * sg * dj);
-    if (k1 < 0 || k2 < 0 || !s->set[k1] || !s->set[k2]) return 0;
+    if (k1 < 0 || k2 < 0 || !m->set[k1] || !m->set[k2]) return 0;
     if (sg > 0) {
-        *dX = (3.0 * s->X[k0] - 4.0 * s->X[k1] + s->X[k2]) / 2.0;
-        *dY = (3.0 * s->Y[k0] - 4.0 * s->Y[k1] + s->Y[k2]) / 2.0;
+        *dX = (3.0 * m->X[k0] - 4.0 * m->X[k1] + m->X[k2]) / 2.0;
+        *dY = (3.0 * m->Y[k0] - 4.0 * m->Y[k1] + m->Y[k2]) / 2.0;
     } else {
-        *dX = (-3.0 * s->X[k0] + 4.0 * s->X[k1] - s->X[k2]) / 2.0;
-        *dY = (-3.0 * s->Y[k0] + 4.0 * s->Y[k1] - s->Y[k2]) / 2.0;
+        *dX = (-3.0 * m->X[k0] + 4.0 * m->X[k1] - m->X[k2]) / 2.0;
+        *dY = (-3.0 * m->Y[k0] + 4.0 * m->Y[k1] - m->Y[k2]) / 2.0;
     }
     return 1;
 }
 
 /* Sec. 3.1, Eq. (3_1_refmap_adv): xi^{n+1} = xi^n - (u d/dx + v d/dy) xi^n on
- * solid nodes (phi^n < 0, blur zone excluded), forward Euler, dt = 1. */
+ * solid nodes (phi^n < 0, blur zone excluded), forward Euler, dt = 1; every
+ * solid's map is advected by the one velocity field. */
 void orc_phase_advect(orc_sim* s)
 {
     const int nx = s->p.nx, ny = s->p.ny;
-    memset(s->set1, 0, s->NP);
     long miss = 0;
+    for (int b = 0; b < s->nsolid; b++) {
+        orc_map* m = &s->m[b];
+        memset(m->set1, 0, s->NP);
 #pragma omp parallel for reduction(+ : miss) schedule(static)
-    for (int j = 0; j < ny; j++)
-        for (int i = 0; i < nx; i++) {
-            if (!solid_node(s, i, j)) continue;
-            long k = pidx(s, i, j);
-            long n = (long)j * nx + i;
-            double u = s->ux[n], v = s->uy[n];
-            double dXx, dYx, dXy, dYy;
-            int okx = upwind(s, i, j, 1, 0, u, &dXx, &dYx);
-            int oky = upwind(s, i, j, 0, 1, v, &dXy, &dYy);
-            if (!okx || !oky) {
-                miss++;
-                s->X1[k] = s->X[k];
-                s->Y1[k] = s->Y[k];
-            } else {
-                s->X1[k] = s->X[k] - (u * dXx + v * dXy);
-                s->Y1[k] = s->Y[k] - (u * dYx + v * dYy);
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                if (!solid_node(s, m, i, j)) continue;
+                long k = pidx(s, i, j);
+                long n = (long)j * nx + i;
+                double u = s->ux[n], v = s->uy[n];
+                double dXx, dYx, dXy, dYy;
+                int okx = upwind(s, m, i, j, 1, 0, u, &dXx, &dYx);
+                int oky = upwind(s, m, i, j, 0, 1, v, &dXy, &dYy);
+                if (!okx || !oky) {
+                    miss++;
+                    m->X1[k] = m->X[k];
+                    m->Y1[k] = m->Y[k];
+                } else {
+                    m->X1[k] = m->X[k] - (u * dXx + v * dXy);
+                    m->Y1[k] = m->Y[k] - (u * dYx + v * dYy);
+                }
+                m->set1[k] = 1;
             }
-            s->set1[k] = 1;
-        }
+    }
     s->cnt[ORC_CNT_ADVECT_MISS] += miss;
     s->have_new = 1;
 }
@@ -415,8 +474,9 @@ static double det3(double a00, double a01, double a02, double a10, double a11, d
            a02 * (a10 * a21 - a11 * a20);
 }
 
-/* extrapolate one target node t = (i, j) of layer l (Sec. 3.2 steps (i)-(iii)) */
-static int extrap_target(orc_sim* s, int i, int j, int l)
+/* extrapolate one target node t = (i, j) of layer l of map m (Sec. 3.2
+ * steps (i)-(iii)) */
+static int extrap_target(orc_sim* s, orc_map* m, int i, int j, int l)
 {
     long kt = pidx(s, i, j);
     /* approximated outward surface normal of phi^n at the target (l <= 2) */
@@ -425,10 +485,10 @@ static int extrap_target(orc_sim* s, int i, int j, int l)
     if (l <= 2) {
         long ke = pidx(s, i + 1, j), kw = pidx(s, i - 1, j);
         long kn = pidx(s, i, j + 1), ks = pidx(s, i, j - 1);
-        if (ke >= 0 && kw >= 0 && kn >= 0 && ks >= 0 && s->set[ke] && s->set[kw] &&
-            s->set[kn] && s->set[ks]) {
-            double gx = (s->phi[ke] - s->phi[kw]) / 2.0;
-            double gy = (s->phi[kn] - s->phi[ks]) / 2.0;
+        if (ke >= 0 && kw >= 0 && kn >= 0 && ks >= 0 && m->set[ke] && m->set[kw] &&
+            m->set[kn] && m->set[ks]) {
+            double gx = (m->phi[ke] - m->phi[kw]) / 2.0;
+            double gy = (m->phi[kn] - m->phi[ks]) / 2.0;
             double g = sqrt(gx * gx + gy * gy);
             if (g > 0.0) {
                 nxh = gx / g;
@@ -444,8 +504,8 @@ static int extrap_target(orc_sim* s, int i, int j, int l)
             for (int a = -r; a <= r; a++) {
                 long k = pidx(s, i + a, j + b);
                 if (k < 0) continue;
-                int lk = s->layer[k];
-                if (lk == 0 || (lk > 0 && lk < l && s->set1[k])) count++;
+                int lk = m->layer[k];
+                if (lk == 0 || (lk > 0 && lk < l && m->set1[k])) count++;
             }
         if (count < 3) continue;
         /* step (ii): weighted least-squares fit xi = A x + B y + C, in
@@ -456,8 +516,8 @@ static int extrap_target(orc_sim* s, int i, int j, int l)
             for (int a = -r; a <= r; a++) {
                 long k = pidx(s, i + a, j + b);
                 if (k < 0) continue;
-                int lk = s->layer[k];
-                if (!(lk == 0 || (lk > 0 && lk < l && s->set1[k]))) continue;
+                int lk = m->layer[k];
+                if (!(lk == 0 || (lk > 0 && lk < l && m->set1[k]))) continue;
                 double w = ldexp(1.0, -(abs(a) + abs(b)));
                 if (l <= 2 && use_n) {
                     /* d = x_target - x_valid */
@@ -468,43 +528,47 @@ static int extrap_target(orc_sim* s, int i, int j, int l)
                 double dx = a, dy = b;
                 M00 += w * dx * dx; M01 += w * dx * dy; M02 += w * dx;
                 M11 += w * dy * dy; M12 += w * dy; M22 += w;
-                bX0 += w * dx * s->X1[k]; bX1 += w * dy * s->X1[k]; bX2 += w * s->X1[k];
-                bY0 += w * dx * s->Y1[k]; bY1 += w * dy * s->Y1[k]; bY2 += w * s->Y1[k];
+                bX0 += w * dx * m->X1[k]; bX1 += w * dy * m->X1[k]; bX2 += w * m->X1[k];
+                bY0 += w * dx * m->Y1[k]; bY1 += w * dy * m->Y1[k]; bY2 += w * m->Y1[k];
             }
         double det = det3(M00, M01, M02, M01, M11, M12, M02, M12, M22);
         if (!(det > s->p.det_rel * M22 * M22 * M22)) continue; /* ill-defined: grow r */
         /* step (iii): the fitted map at the target is its intercept C (Cramer) */
-        s->X1[kt] = det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det;
-        s->Y1[kt] = det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det;
-        s->set1[kt] = 1;
+        m->X1[kt] = det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det;
+        m->Y1[kt] = det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det;
+        m->set1[kt] = 1;
         return 1;
     }
     return 0;
 }
 
-/* Sec. 3.2: layers around S^n, then layer-by-layer LSQ extrapolation.  Valid
- * nodes are solid nodes or already-set nodes of earlier layers only, so the
- * targets of one layer are independent of each other. */
+/* Sec. 3.2: layers around S^n, then layer-by-layer LSQ extrapolation, for
+ * each solid on its own.  Valid nodes are solid nodes or already-set nodes
+ * of earlier layers only, so the targets of one layer are independent of
+ * each other. */
 void orc_phase_extrapolate(orc_sim* s)
 {
     const int nx = s->p.nx, ny = s->p.ny;
     const int i0 = dom_lo(s->p.periodic_x), i1 = dom_hi(s->p.periodic_x, nx);
     const int j0 = dom_lo(s->p.periodic_y), j1 = dom_hi(s->p.periodic_y, ny);
-    mark_layers(s);
     const int W = i1 - i0 + 1, H = j1 - j0 + 1;
-    for (int l = 1; l <= s->p.layers; l++) {
-        long fail = 0;
+    for (int bi = 0; bi < s->nsolid; bi++) {
+        orc_map* m = &s->m[bi];
+        mark_layers(s, m);
+        for (int l = 1; l <= s->p.layers; l++) {
+            long fail = 0;
 #pragma omp parallel for reduction(+ : fail) schedule(dynamic, 4)
-        for (int jj = 0; jj < H; jj++) {
-            int j = s->p.reverse_order ? j1 - jj : j0 + jj;
-            for (int ii = 0; ii < W; ii++) {
-                int i = s->p.reverse_order ? i1 - ii : i0 + ii;
-                long k = pidx(s, i, j);
-                if (s->layer[k] != l) continue;
-                if (!extrap_target(s, i, j, l)) fail++;
+            for (int jj = 0; jj < H; jj++) {
+                int j = s->p.reverse_order ? j1 - jj : j0 + jj;
+                for (int ii = 0; ii < W; ii++) {
+                    int i = s->p.reverse_order ? i1 - ii : i0 + ii;
+                    long k = pidx(s, i, j);
+                    if (m->layer[k] != l) continue;
+                    if (!extrap_target(s, m, i, j, l)) fail++;
+                }
             }
+            s->cnt[ORC_CNT_EXTRAP_FAIL] += fail;
         }
-        s->cnt[ORC_CNT_EXTRAP_FAIL] += fail;
     }
 }
 
@@ -512,68 +576,172 @@ void orc_phase_extrapolate(orc_sim* s)
  * holds a reference map, then make the new map the current one. */
 void orc_phase_relabel(orc_sim* s)
 {
-    for (long k = 0; k < s->NP; k++) {
-        if (s->set1[k]) {
-            s->phi1[k] = phi0(s, s->X1[k], s->Y1[k]);
-        } else {
-            s->X1[k] = s->Y1[k] = NAN;
-            s->phi1[k] = INFINITY;
+    for (int b = 0; b < s->nsolid; b++) {
+        orc_map* m = &s->m[b];
+        for (long k = 0; k < s->NP; k++) {
+            if (m->set1[k]) {
+                m->phi1[k] = phi0(m, m->X1[k], m->Y1[k]);
+            } else {
+                m->X1[k] = m->Y1[k] = NAN;
+                m->phi1[k] = INFINITY;
+            }
         }
+        double* t;
+        unsigned char* tc;
+        t = m->X; m->X = m->X1; m->X1 = t;
+        t = m->Y; m->Y = m->Y1; m->Y1 = t;
+        t = m->phi; m->phi = m->phi1; m->phi1 = t;
+        tc = m->set; m->set = m->set1; m->set1 = tc;
     }
-    double* t;
-    unsigned char* tc;
-    t = s->X; s->X = s->X1; s->X1 = t;
-    t = s->Y; s->Y = s->Y1; s->Y1 = t;
-    t = s->phi; s->phi = s->phi1; s->phi1 = t;
-    tc = s->set; s->set = s->set1; s->set1 = tc;
     s->have_new = 0;
 }
 
-/* blended stress (1 - H(phi_e)) tau_s on the half-edge between nodes a and b.
- * dir = 0: x-edge (i-1/2, j) with a = (i-1, j), b = (i, j);
- * dir = 1: y-edge (i, j-1/2) with a = (i, j-1), b = (i, j).
- * Gradients of Eq. (3_3_refmap_jacobian); the tangential one averages the
- * four nodes beside the edge. */
-static void edge_stress(orc_sim* s, int i, int j, int dir, double* out, long* miss, long* sing)
+/* The stencil of a half-edge: dir = 0: x-edge (i-1/2, j) between a = (i-1, j)
+ * and b = (i, j); dir = 1: y-edge (i, j-1/2) between a = (i, j-1) and
+ * b = (i, j).  k1..k4 are the four nodes beside the edge: (+t, b), (+t, a),
+ * (-t, b), (-t, a) along the tangent t.  A derivative at the edge is the
+ * difference b - a along the normal and the average of the two side
+ * differences along the tangent (the stencil of Eq. (3_3_refmap_jacobian)). */
+typedef struct {
+    long ka, kb, k1, k2, k3, k4;
+    int full; /* all six nodes exist */
+} edge_st;
+
+static edge_st edge_stencil(const orc_sim* s, int i, int j, int dir)
+{
+    edge_st e;
+    int ia = dir == 0 ? i - 1 : i, ja = dir == 0 ? j : j - 1;
+    e.ka = pidx(s, ia, ja);
+    e.kb = pidx(s, i, j);
+    if (dir == 0) {
+        e.k1 = pidx(s, i, j + 1); e.k2 = pidx(s, i - 1, j + 1);
+        e.k3 = pidx(s, i, j - 1); e.k4 = pidx(s, i - 1, j - 1);
+    } else {
+        e.k1 = pidx(s, i + 1, j); e.k2 = pidx(s, i + 1, j - 1);
+        e.k3 = pidx(s, i - 1, j); e.k4 = pidx(s, i - 1, j - 1);
+    }
+    e.full = e.ka >= 0 && e.kb >= 0 && e.k1 >= 0 && e.k2 >= 0 && e.k3 >= 0 && e.k4 >= 0;
+    return e;
+}
+
+static int edge_all_set(const edge_st* e, const unsigned char* set)
+{
+    return e->full && set[e->k1] && set[e->k2] && set[e->k3] && set[e->k4];
+}
+
+/* gradient (d/dx, d/dy) at the half-edge of a field whose values on the
+ * stencil nodes (a, b, k1, k2, k3, k4) are v[0..5] */
+static void edge_grad(const double* v, int dir, double* gx, double* gy)
+{
+    double gn = v[1] - v[0];
+    double gt = (v[2] + v[3] - v[4] - v[5]) / 4.0;
+    *gx = dir == 0 ? gn : gt;
+    *gy = dir == 0 ? gt : gn;
+}
+
+static void edge_values(const edge_st* e, const double* f, double* v)
+{
+    v[0] = f[e->ka]; v[1] = f[e->kb];
+    v[2] = f[e->k1]; v[3] = f[e->k2]; v[4] = f[e->k3]; v[5] = f[e->k4];
+}
+
+/* solid m's blended stress lambda_m tau_s,m on a half-edge, with lambda_m =
+ * 1 - H(phi_e) at the edge's mean level set; returns lambda_m (0 where the
+ * map does not cover both ends of the edge) */
+static double solid_edge(const orc_sim* s, const orc_map* m, const edge_st* e, int dir,
+                         double* out, long* miss, long* sing)
 {
     out[0] = out[1] = out[2] = 0.0;
-    if (!s->nsolid) return;
-    int ia = dir == 0 ? i - 1 : i, ja = dir == 0 ? j : j - 1;
-    long ka = pidx(s, ia, ja), kb = pidx(s, i, j);
-    if (ka < 0 || kb < 0 || !s->set[ka] || !s->set[kb]) return;
-    double phie = 0.5 * (s->phi[ka] + s->phi[kb]);
+    if (e->ka < 0 || e->kb < 0 || !m->set[e->ka] || !m->set[e->kb]) return 0.0;
+    double phie = 0.5 * (m->phi[e->ka] + m->phi[e->kb]);
     double lam = 1.0 - orc_heaviside(phie, s->p.eps);
-    if (!(lam > 0.0)) return;
-    long k1, k2, k3, k4; /* (+t, a), (+t, b) ... side nodes */
-    double J[4];
-    if (dir == 0) {
-        k1 = pidx(s, i, j + 1); k2 = pidx(s, i - 1, j + 1);
-        k3 = pidx(s, i, j - 1); k4 = pidx(s, i - 1, j - 1);
-    } else {
-        k1 = pidx(s, i + 1, j); k2 = pidx(s, i + 1, j - 1);
-        k3 = pidx(s, i - 1, j); k4 = pidx(s, i - 1, j - 1);
-    }
-    if (k1 < 0 || k2 < 0 || k3 < 0 || k4 < 0 || !s->set[k1] || !s->set[k2] || !s->set[k3] ||
-        !s->set[k4]) {
+    if (!(lam > 0.0)) return 0.0;
+    if (!edge_all_set(e, m->set)) {
         (*miss)++;
-        return;
+        return lam;
     }
-    double nX = s->X[kb] - s->X[ka], nY = s->Y[kb] - s->Y[ka];
-    double tX = (s->X[k1] + s->X[k2] - s->X[k3] - s->X[k4]) / 4.0;
-    double tY = (s->Y[k1] + s->Y[k2] - s->Y[k3] - s->Y[k4]) / 4.0;
-    if (dir == 0) {
-        J[0] = nX; J[1] = tX; J[2] = nY; J[3] = tY;
-    } else {
-        J[0] = tX; J[1] = nX; J[2] = tY; J[3] = nY;
-    }
+    double J[4], v[6];
+    edge_values(e, m->X, v);
+    edge_grad(v, dir, &J[0], &J[1]);
+    edge_values(e, m->Y, v);
+    edge_grad(v, dir, &J[2], &J[3]);
     double tau[3];
-    if (!orc_solid_stress(J, s->body.G, s->p.detJ_min, tau)) {
+    if (!orc_solid_stress(J, m->body.G, s->p.detJ_min, tau)) {
         (*sing)++;
-        return;
+        return lam;
     }
     out[0] = lam * tau[0];
     out[1] = lam * tau[1];
     out[2] = lam * tau[2];
+    return lam;
+}
+
+/* contact function of Eq. (3_6_collision_force): (1 - x / eps) / 2 below
+ * eps, zero above; not capped for deep overlap */
+static double contact_f(double x, double eps) { return x < eps ? 0.5 * (1.0 - x / eps) : 0.0; }
+
+/* Eq. (3_6_collision_stress) for the pair (p, q) on a half-edge, added to
+ * out: -eta min(f(phi_p), f(phi_q)) (G_p + G_q) (n n^T - I/2), with the level
+ * sets taken at the edge's mean and n the unit gradient of phi_p - phi_q
+ * (Eq. (3_6_normal)) on the edge stencil.  Only where both maps cover the
+ * whole stencil. */
+static void contact_edge(const orc_sim* s, const orc_map* mp, const orc_map* mq,
+                         const edge_st* e, int dir, double* out)
+{
+    if (!edge_all_set(e, mp->set) || !mp->set[e->ka] || !mp->set[e->kb]) return;
+    if (!edge_all_set(e, mq->set) || !mq->set[e->ka] || !mq->set[e->kb]) return;
+    double fp = contact_f(0.5 * (mp->phi[e->ka] + mp->phi[e->kb]), s->p.eps);
+    double fq = contact_f(0.5 * (mq->phi[e->ka] + mq->phi[e->kb]), s->p.eps);
+    double fmin = fp < fq ? fp : fq;
+    if (!(fmin > 0.0)) return;
+    /* phi_p - phi_q on the six stencil nodes */
+    double vp[6], vq[6], d[6];
+    edge_values(e, mp->phi, vp);
+    edge_values(e, mq->phi, vq);
+    for (int t = 0; t < 6; t++) d[t] = vp[t] - vq[t];
+    double gx, gy;
+    edge_grad(d, dir, &gx, &gy);
+    double g = sqrt(gx * gx + gy * gy);
+    if (!(g > 0.0)) return;
+    double nx = gx / g, ny = gy / g;
+    double c = -s->p.eta * fmin * (mp->body.G + mq->body.G);
+    out[0] += c * (nx * nx - 0.5);
+    out[1] += c * (nx * ny);
+    out[2] += c * (ny * ny - 0.5);
+}
+
+/* Global solid stress on one half-edge (Eq. (3_6_global_stress) without the
+ * fluid part, which the lattice carries): sum_m lambda_m tau_s,m, divided by
+ * sum_m lambda_m where that exceeds one, plus the contact stress of every
+ * pair of solids.  For one solid this is Eq. (2_4_smooth_stress)'s solid
+ * term (1 - H) tau_s. */
+static void edge_stress(orc_sim* s, int i, int j, int dir, double* out, long* miss, long* sing)
+{
+    out[0] = out[1] = out[2] = 0.0;
+    if (!s->nsolid) return;
+    edge_st e = edge_stencil(s, i, j, dir);
+    double lsum = 0.0, acc[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < s->nsolid; b++) {
+        double t[3];
+        double lam = solid_edge(s, &s->m[b], &e, dir, t, miss, sing);
+        if (!(lam > 0.0)) continue;
+        lsum += lam;
+        acc[0] += t[0];
+        acc[1] += t[1];
+        acc[2] += t[2];
+    }
+    if (lsum > 1.0) {
+        acc[0] /= lsum;
+        acc[1] /= lsum;
+        acc[2] /= lsum;
+    }
+    out[0] = acc[0];
+    out[1] = acc[1];
+    out[2] = acc[2];
+    if (s->p.eta != 0.0)
+        for (int p = 0; p < s->nsolid; p++)
+            for (int q = p + 1; q < s->nsolid; q++)
+                contact_edge(s, &s->m[p], &s->m[q], &e, dir, out);
 }
 
 /* half-edge arrays: x-edge (i-1/2, j) and y-edge (i, j-1/2) stored at
@@ -611,7 +779,11 @@ static void node_edges(const orc_sim* s, int i, int j, const double** L, const d
 /* Eq. (3_3_div_solid_stress) assembled into the force density of
  * Eq. (2_4_F_divs): div[(1-H) tau_s] + (1-H) f_ext,s + H f_ext,f, with the
  * solid's external force in the buoyancy form (rho_s - rho_f) g of Sec. 4.3
- * and f_ext,f a uniform force density on the fluid. */
+ * and f_ext,f a uniform force density on the fluid.  Several solids: the
+ * stress is the global one of Eq. (3_6_global_stress) with contact; the
+ * buoyancy is sum_m lambda_m (rho_s,m - rho_f) g, normalised like the density
+ * where the fractions sum above one; the fluid's share of f_ext,f is
+ * 1 - min(1, sum_m lambda_m) (H for one solid). */
 void orc_phase_force(orc_sim* s)
 {
     const int nx = s->p.nx, ny = s->p.ny;
@@ -625,14 +797,26 @@ void orc_phase_force(orc_sim* s)
             double fx = (R[0] - L[0]) + (T[1] - B[1]);
             double fy = (R[1] - L[1]) + (T[2] - B[2]);
             long k = pidx(s, i, j);
-            double H = 1.0;
-            if (s->nsolid && s->set[k]) {
-                H = orc_heaviside(s->phi[k], s->p.eps);
-                fx += (1.0 - H) * (s->body.rho_s - s->p.rho_f) * s->p.gx;
-                fy += (1.0 - H) * (s->body.rho_s - s->p.rho_f) * s->p.gy;
+            double hf = 1.0;
+            if (s->nsolid == 1) {
+                /* the single-solid form, as written in Eq. (2_4_F_divs) */
+                const orc_map* m = &s->m[0];
+                if (m->set[k]) {
+                    double H = orc_heaviside(m->phi[k], s->p.eps);
+                    fx += (1.0 - H) * (m->body.rho_s - s->p.rho_f) * s->p.gx;
+                    fy += (1.0 - H) * (m->body.rho_s - s->p.rho_f) * s->p.gy;
+                    hf = H;
+                }
+            } else if (s->nsolid > 1) {
+                double lsum = 0.0;
+                for (int b = 0; b < s->nsolid; b++) lsum += lambda_at(s, &s->m[b], k);
+                double drho = mixture_drho(s, k);
+                fx += drho * s->p.gx;
+                fy += drho * s->p.gy;
+                hf = lsum < 1.0 ? 1.0 - lsum : 0.0;
             }
-            fx += H * s->p.fext_x;
-            fy += H * s->p.fext_y;
+            fx += hf * s->p.fext_x;
+            fy += hf * s->p.fext_y;
             s->Fx[n] = fx;
             s->Fy[n] = fy;
         }
@@ -654,9 +838,7 @@ void orc_phase_collide_stream(orc_sim* s)
         for (int i = 0; i < nx; i++) {
             long n = (long)j * nx + i;
             long k = pidx(s, i, j);
-            double drho = 0.0;
-            if (s->nsolid && s->set[k])
-                drho = (1.0 - orc_heaviside(s->phi[k], s->p.eps)) * (s->body.rho_s - s->p.rho_f);
+            double drho = mixture_drho(s, k);
             double feq[NQ], Fi[NQ];
             orc_feq_sfc(s->rho[n], s->ux[n], s->uy[n], drho, feq);
             orc_guo(s->ux[n], s->uy[n], s->Fx[n], s->Fy[n], Fi);
@@ -733,6 +915,7 @@ void orc_step(orc_sim* s, int64_t n)
 /* ------------------------------------------------------------------ */
 
 int64_t orc_step_count(const orc_sim* s) { return s->step; }
+int32_t orc_nsolid(const orc_sim* s) { return s->nsolid; }
 
 void orc_read_macro(const orc_sim* s, double* rho, double* ux, double* uy)
 {
@@ -754,16 +937,22 @@ void orc_read_force(const orc_sim* s, double* fx, double* fy)
     memcpy(fy, s->Fy, sizeof(double) * s->N);
 }
 
-void orc_read_refmap(const orc_sim* s, double* X, double* Y, double* phi)
+void orc_read_refmap_body(const orc_sim* s, int32_t b, double* X, double* Y, double* phi)
 {
+    const orc_map* m = (b >= 0 && b < s->nsolid) ? &s->m[b] : NULL;
     for (int j = 0; j < s->p.ny; j++)
         for (int i = 0; i < s->p.nx; i++) {
             long n = (long)j * s->p.nx + i, k = pidx(s, i, j);
-            int ok = s->set[k];
-            if (X) X[n] = ok ? s->X[k] : NAN;
-            if (Y) Y[n] = ok ? s->Y[k] : NAN;
-            if (phi) phi[n] = ok ? s->phi[k] : NAN;
+            int ok = m && m->set[k];
+            if (X) X[n] = ok ? m->X[k] : NAN;
+            if (Y) Y[n] = ok ? m->Y[k] : NAN;
+            if (phi) phi[n] = ok ? m->phi[k] : NAN;
         }
+}
+
+void orc_read_refmap(const orc_sim* s, double* X, double* Y, double* phi)
+{
+    orc_read_refmap_body(s, 0, X, Y, phi);
 }
 
 /* the padded layout used by the read/set calls: [(ny+4)][(nx+4)], node (i, j)
@@ -774,16 +963,18 @@ void orc_read_refmap_padded(const orc_sim* s, double* X, double* Y, double* phi)
 {
     long NE = (long)(s->p.nx + 4) * (s->p.ny + 4);
     for (long e = 0; e < NE; e++) X[e] = Y[e] = phi[e] = NAN;
+    if (!s->nsolid) return;
+    const orc_map* m = &s->m[0];
     for (int j = -2; j <= s->p.ny + 1; j++)
         for (int i = -2; i <= s->p.nx + 1; i++) {
             if ((s->p.periodic_x && (i < 0 || i >= s->p.nx)) ||
                 (s->p.periodic_y && (j < 0 || j >= s->p.ny)))
                 continue;
             long k = pidx(s, i, j), e = ext_idx(s, i, j);
-            if (s->set[k]) {
-                X[e] = s->X[k];
-                Y[e] = s->Y[k];
-                phi[e] = s->phi[k];
+            if (m->set[k]) {
+                X[e] = m->X[k];
+                Y[e] = m->Y[k];
+                phi[e] = m->phi[k];
             }
         }
 }
@@ -792,17 +983,21 @@ void orc_read_layers_padded(const orc_sim* s, int32_t* layer)
 {
     long NE = (long)(s->p.nx + 4) * (s->p.ny + 4);
     for (long e = 0; e < NE; e++) layer[e] = -1;
+    if (!s->nsolid) return;
+    const orc_map* m = &s->m[0];
     for (int j = -2; j <= s->p.ny + 1; j++)
         for (int i = -2; i <= s->p.nx + 1; i++) {
             if ((s->p.periodic_x && (i < 0 || i >= s->p.nx)) ||
                 (s->p.periodic_y && (j < 0 || j >= s->p.ny)))
                 continue;
-            layer[ext_idx(s, i, j)] = s->layer[pidx(s, i, j)];
+            layer[ext_idx(s, i, j)] = m->layer[pidx(s, i, j)];
         }
 }
 
 void orc_set_refmap_padded(orc_sim* s, const double* X, const double* Y)
 {
+    if (!s->nsolid) return;
+    orc_map* m = &s->m[0];
     for (int j = -2; j <= s->p.ny + 1; j++)
         for (int i = -2; i <= s->p.nx + 1; i++) {
             if ((s->p.periodic_x && (i < 0 || i >= s->p.nx)) ||
@@ -810,14 +1005,14 @@ void orc_set_refmap_padded(orc_sim* s, const double* X, const double* Y)
                 continue;
             long k = pidx(s, i, j), e = ext_idx(s, i, j);
             if (isnan(X[e])) {
-                s->set[k] = 0;
-                s->X[k] = s->Y[k] = NAN;
-                s->phi[k] = INFINITY;
+                m->set[k] = 0;
+                m->X[k] = m->Y[k] = NAN;
+                m->phi[k] = INFINITY;
             } else {
-                s->set[k] = 1;
-                s->X[k] = X[e];
-                s->Y[k] = Y[e];
-                s->phi[k] = s->nsolid ? phi0(s, X[e], Y[e]) : INFINITY;
+                m->set[k] = 1;
+                m->X[k] = X[e];
+                m->Y[k] = Y[e];
+                m->phi[k] = phi0(m, X[e], Y[e]);
             }
         }
 }
@@ -855,12 +1050,46 @@ void orc_counters(const orc_sim* s, int64_t* out)
     for (int c = 0; c < ORC_CNT_N; c++) out[c] = s->cnt[c];
 }
 
+/* solid fraction moments of map m over interior nodes: sum lambda, sum
+ * lambda x, sum lambda y, sum lambda (x - X), sum lambda (y - Y), solid
+ * nodes, nodes with a value */
+static void body_moments(const orc_sim* s, const orc_map* m, double* acc7)
+{
+    for (int t = 0; t < 7; t++) acc7[t] = 0.0;
+    for (int j = 0; j < s->p.ny; j++)
+        for (int i = 0; i < s->p.nx; i++) {
+            long k = pidx(s, i, j);
+            if (!m->set[k]) continue;
+            acc7[6] += 1;
+            if (m->phi[k] < 0) acc7[5] += 1;
+            double lam = 1.0 - orc_heaviside(m->phi[k], s->p.eps);
+            double x = node_x(s, m, i), y = node_y(s, m, j);
+            acc7[0] += lam;
+            acc7[1] += lam * x;
+            acc7[2] += lam * y;
+            acc7[3] += lam * (x - m->X[k]);
+            acc7[4] += lam * (y - m->Y[k]);
+        }
+}
+
+void orc_diag_body(const orc_sim* s, int32_t b, double* out)
+{
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (b >= 0 && b < s->nsolid) body_moments(s, &s->m[b], a);
+    double lw = a[0];
+    out[0] = lw > 0 ? a[1] / lw : NAN;
+    out[1] = lw > 0 ? a[2] / lw : NAN;
+    out[2] = lw > 0 ? a[3] / lw : NAN;
+    out[3] = lw > 0 ? a[4] / lw : NAN;
+    out[4] = a[5];
+    out[5] = a[6];
+}
+
 void orc_diag(const orc_sim* s, double* out)
 {
     const int nx = s->p.nx, ny = s->p.ny;
     const long N = s->N;
-    double mass = 0, px = 0, py = 0, lw = 0, lx = 0, ly = 0, dx = 0, dy = 0, umax = 0;
-    double nsol = 0, nband = 0;
+    double mass = 0, px = 0, py = 0, umax = 0;
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
             long n = (long)j * nx + i;
@@ -876,27 +1105,24 @@ void orc_diag(const orc_sim* s, double* out)
             py += jy + 0.5 * s->Fy[n];
             double um = sqrt(s->ux[n] * s->ux[n] + s->uy[n] * s->uy[n]);
             if (um > umax) umax = um;
-            long k = pidx(s, i, j);
-            if (s->nsolid && s->set[k]) {
-                nband += 1;
-                if (s->phi[k] < 0) nsol += 1;
-                double lam = 1.0 - orc_heaviside(s->phi[k], s->p.eps);
-                double x = node_x(s, i), y = node_y(s, j);
-                lw += lam;
-                lx += lam * x;
-                ly += lam * y;
-                dx += lam * (x - s->X[k]);
-                dy += lam * (y - s->Y[k]);
-            }
         }
+    /* the solids' moments, summed over solids (each in its own unwrapped
+     * frame) */
+    double tot[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < s->nsolid; b++) {
+        double a[7];
+        body_moments(s, &s->m[b], a);
+        for (int t = 0; t < 7; t++) tot[t] += a[t];
+    }
+    double lw = tot[0];
     out[0] = mass;
     out[1] = px;
     out[2] = py;
-    out[3] = lw > 0 ? lx / lw : NAN;
-    out[4] = lw > 0 ? ly / lw : NAN;
-    out[5] = lw > 0 ? dx / lw : NAN;
-    out[6] = lw > 0 ? dy / lw : NAN;
+    out[3] = lw > 0 ? tot[1] / lw : NAN;
+    out[4] = lw > 0 ? tot[2] / lw : NAN;
+    out[5] = lw > 0 ? tot[3] / lw : NAN;
+    out[6] = lw > 0 ? tot[4] / lw : NAN;
     out[7] = umax;
-    out[8] = nsol;
-    out[9] = nband;
+    out[8] = tot[5];
+    out[9] = tot[6];
 }

@@ -39,7 +39,12 @@ typedef struct {
     double det_rel;     /* LSQ fit ill-defined if det M <= det_rel*(sum w)^3 */
     double detJ_min;    /* half-edge stress dropped if det(grad xi) <= this  */
     int32_t reverse_order; /* process extrapolation targets in reverse order */
+    int32_t reserved;
+    double eta;         /* contact factor of Eq. (3_6_collision_stress)      */
 } orc_params;
+
+/* most solids one simulation may hold */
+#define ORC_MAX_SOLIDS 64
 
 typedef struct {
     double cx, cy;      /* centre in the reference configuration             */
@@ -63,7 +68,7 @@ enum {
 
 typedef struct orc_sim orc_sim;
 
-/* lifecycle (nsolid is 0 or 1) */
+/* lifecycle (0 <= nsolid <= ORC_MAX_SOLIDS; NULL on a bad parameter) */
 orc_sim* orc_create(const orc_params* p, const orc_solid* solids, int32_t nsolid);
 void     orc_destroy(orc_sim* s);
 /* Alg. 1 initialisation; u0 = NULL or 2*ny*nx (ux plane then uy plane) */
@@ -84,19 +89,26 @@ int64_t orc_step_count(const orc_sim* s);
 void orc_read_macro(const orc_sim* s, double* rho, double* ux, double* uy);
 void orc_read_populations(const orc_sim* s, double* f9);      /* [9][ny][nx] */
 void orc_read_force(const orc_sim* s, double* fx, double* fy); /* last F    */
-/* xi and phi on interior nodes; NaN where the node holds no reference map */
+/* xi and phi of solid b (orc_read_refmap: solid 0) on interior nodes; NaN
+ * where the node holds no value of that map */
 void orc_read_refmap(const orc_sim* s, double* X, double* Y, double* phi);
-/* padded-grid versions: [(ny+4)][(nx+4)], offset 2 in each walled axis    */
+void orc_read_refmap_body(const orc_sim* s, int32_t b, double* X, double* Y, double* phi);
+int32_t orc_nsolid(const orc_sim* s);
+/* padded-grid versions (solid 0): [(ny+4)][(nx+4)], offset 2 in each
+ * walled axis */
 void orc_read_refmap_padded(const orc_sim* s, double* X, double* Y, double* phi);
 void orc_read_layers_padded(const orc_sim* s, int32_t* layer);
-/* node average of the four blended half-edge solid stresses (xx, xy, yy) */
+/* node average of the four global half-edge solid stresses (xx, xy, yy) */
 void orc_read_stress(orc_sim* s, double* sxx, double* sxy, double* syy);
 void orc_counters(const orc_sim* s, int64_t* out8);
 /* diag: [mass, mom_x, mom_y, centroid_x, centroid_y, disp_x, disp_y,
- *        max|u|, n_solid, n_band]                                         */
+ *        max|u|, n_solid, n_band]; the solid terms summed over all solids */
 void orc_diag(const orc_sim* s, double* out10);
+/* one solid: [centroid_x, centroid_y, disp_x, disp_y, n_solid, n_band] */
+void orc_diag_body(const orc_sim* s, int32_t b, double* out6);
 
-/* overwrite state (tests): xi/phi on the padded grid, NaN X = no value */
+/* overwrite state (tests): xi/phi of solid 0 on the padded grid, NaN X = no
+ * value */
 void orc_set_refmap_padded(orc_sim* s, const double* X, const double* Y);
 void orc_set_populations(orc_sim* s, const double* f9);
 void orc_set_moments(orc_sim* s, const double* rho, const double* ux, const double* uy);

@@ -30,7 +30,8 @@ class _Params(ctypes.Structure):
         ("rho_f", ctypes.c_double), ("eps", ctypes.c_double),
         ("layers", ctypes.c_int32), ("r_max", ctypes.c_int32),
         ("det_rel", ctypes.c_double), ("detJ_min", ctypes.c_double),
-        ("reverse_order", ctypes.c_int32),
+        ("reverse_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("eta", ctypes.c_double),
     ]
 
 
@@ -96,6 +97,10 @@ def lib():
         L.orc_guo.argtypes = [ctypes.c_double] * 4 + [_dp]
         L.orc_solid_stress.restype = ctypes.c_int
         L.orc_solid_stress.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_read_refmap_body.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, _dp]
+        L.orc_diag_body.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp]
+        L.orc_nsolid.restype = ctypes.c_int32
+        L.orc_nsolid.argtypes = [ctypes.c_void_p]
         L.orc_phi0.restype = ctypes.c_double
         L.orc_phi0.argtypes = [ctypes.POINTER(_Solid), ctypes.c_double, ctypes.c_double]
         L.orc_layers_mask.argtypes = [ctypes.c_int32, ctypes.c_int32, _u8p, ctypes.c_int32, _ip]
@@ -157,14 +162,18 @@ class Oracle:
     def __init__(self, nx, ny, tau, lid_ux=0.0, periodic_x=False, periodic_y=False,
                  gravity=(0.0, 0.0), fext=(0.0, 0.0), rho_f=1.0, eps=1.5, layers=11,
                  r_max=8, det_rel=1e-8, detJ_min=1e-12, reverse_order=False, solid=None,
-                 **_ignored):
+                 solids=None, eta=1.0, **_ignored):
         p = _Params(nx, ny, int(periodic_x), int(periodic_y), tau, lid_ux,
                     gravity[0], gravity[1], fext[0], fext[1], rho_f, eps, layers, r_max,
-                    det_rel, detJ_min, int(reverse_order))
+                    det_rel, detJ_min, int(reverse_order), 0, eta)
         self.nx, self.ny = nx, ny
-        if solid is not None:
-            s = _solid(solid)
-            self._h = lib().orc_create(ctypes.byref(p), ctypes.byref(s), 1)
+        if solid is not None and solids is not None:
+            raise ValueError("give either solid or solids")
+        bodies = [solid] if solid is not None else list(solids or [])
+        self.nsolid = len(bodies)
+        if bodies:
+            arr = (_Solid * len(bodies))(*[_solid(b) for b in bodies])
+            self._h = lib().orc_create(ctypes.byref(p), arr, len(bodies))
         else:
             self._h = lib().orc_create(ctypes.byref(p), None, 0)
         if not self._h:
@@ -213,9 +222,10 @@ class Oracle:
         lib().orc_read_force(self._h, _d(fx), _d(fy))
         return fx, fy
 
-    def refmap(self):
+    def refmap(self, body=0):
+        """xi and phi of one solid on the interior nodes (NaN: no value)."""
         X, Y, phi = self._plane(), self._plane(), self._plane()
-        lib().orc_read_refmap(self._h, _d(X), _d(Y), _d(phi))
+        lib().orc_read_refmap_body(self._h, int(body), _d(X), _d(Y), _d(phi))
         return X, Y, phi
 
     def refmap_padded(self):
@@ -257,4 +267,10 @@ class Oracle:
         lib().orc_diag(self._h, _d(out))
         keys = ["mass", "mom_x", "mom_y", "centroid_x", "centroid_y", "disp_x", "disp_y",
                 "max_u", "n_solid", "n_band"]
+        return dict(zip(keys, out.tolist()))
+
+    def diag_body(self, body):
+        out = np.zeros(6)
+        lib().orc_diag_body(self._h, int(body), _d(out))
+        keys = ["centroid_x", "centroid_y", "disp_x", "disp_y", "n_solid", "n_band"]
         return dict(zip(keys, out.tolist()))

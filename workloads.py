@@ -13,7 +13,7 @@ import numpy as np
 
 _DEFAULTS = dict(
     periodic_x=False, periodic_y=False, lid_ux=0.0, gravity=(0.0, 0.0), fext=(0.0, 0.0),
-    rho_f=1.0, eps=1.5, layers=11, r_max=8, det_rel=1e-8, detJ_min=1e-12, solid=None,
+    rho_f=1.0, eps=1.5, layers=11, r_max=8, det_rel=1e-8, detJ_min=1e-12, eta=1.0, solid=None,
 )
 
 
@@ -98,3 +98,40 @@ def cavity_ensemble(n=96, seed=4):
                         solid=dict(cx=0.5 * L, cy=0.6 * L, R=R, G=G, rho_s=1.0),
                         name=f"ensemble_{seed}_{k}"))
     return out
+
+
+def suspension(n=4096, nbody=400, seed=240212696, tau=0.7, g=1e-6, eps=1.5, eta=1.0,
+               a_range=(12.0, 24.0), gap=3.0, max_draws=100000):
+    """Many soft bodies in a periodic box under gravity (the paper's mixing
+    scenes of Sec. 4.5 at a synthetic scale): an n x n periodic box, tau,
+    gravity g along -y acting on the density contrast.  For each body in order
+    (numpy default_rng(seed)): semi-major axis a ~ U[a_range], aspect ~ U[1, 2]
+    (b = a / aspect; an ellipse, a disc when b = a), angle ~ U[0, pi),
+    log10 G ~ U[-3, -2], rho_s ~ U[1.2, 2.0]; then the centre ~ U[0, n)^2,
+    drawn again until its minimum-image distance to every earlier centre is at
+    least a_i + a_j + 2 eps + gap."""
+    rng = np.random.default_rng(seed)
+    bodies = []
+    for k in range(nbody):
+        a = float(rng.uniform(*a_range))
+        b = a / float(rng.uniform(1.0, 2.0))
+        th = float(rng.uniform(0.0, np.pi))
+        G = float(10.0 ** rng.uniform(-3.0, -2.0))
+        rs = float(rng.uniform(1.2, 2.0))
+        for _ in range(max_draws):
+            c = rng.uniform(0.0, n, size=2)
+            ok = True
+            for o in bodies:
+                d = np.abs(c - np.array([o["cx"], o["cy"]]))
+                d = np.minimum(d, n - d)
+                if np.hypot(*d) < a + o["R"] + 2 * eps + gap:
+                    ok = False
+                    break
+            if ok:
+                break
+        else:
+            raise ValueError("could not place every body")
+        bodies.append(dict(cx=float(c[0]), cy=float(c[1]), R=a, G=G, rho_s=rs,
+                           shape="ellipse", b=b, theta=th))
+    return make(nx=n, ny=n, tau=tau, periodic_x=True, periodic_y=True, gravity=(0.0, -g),
+                eps=eps, eta=eta, solids=bodies, name=f"suspension_{n}_{nbody}")
