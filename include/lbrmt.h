@@ -71,8 +71,25 @@ typedef struct {
     double det_rel;          /* fit ill-defined if det M <= det_rel (sum w)^3 (1e-8) */
     double detJ_min;         /* half-edge stress dropped if det(grad xi) <= this (1e-12) */
     int32_t precision;       /* lbrmt_precision                                  */
-    int32_t reserved;
+    int32_t body_window;     /* several solids: side of each solid's own window
+                                along a periodic axis (0: 128); see below       */
+    double eta;              /* contact factor eta of Eq. (3_6_collision_stress)
+                                (several solids; 1 in the paper's runs)         */
 } lbrmt_grid_desc;
+
+/* Several solids (Sec. 3.6).  A context created with max_solids > 1 keeps
+ * every solid's reference map, level set and extrapolation zone on a window
+ * of its own: along a periodic axis whose length is a multiple of 16 and at
+ * least body_window + 36 the window is body_window nodes centred on the
+ * solid, elsewhere it is the whole axis.  The solids meet in the global
+ * half-edge stress (their blended stresses normalised by the summed solid
+ * fraction where it exceeds one, Eq. (3_6_global_stress)), the contact stress
+ * of every overlapping pair (Eqs. (3_6_collision_stress) to (3_6_normal), on
+ * half-edges), and the density rho_f + sum_i lambda_i (rho_s,i - rho_f) /
+ * max(1, sum_i lambda_i).  A solid whose zone comes closer than `layers`
+ * nodes to its window's border raises LBRMT_H_WINDOW_CLIP (the window does
+ * not move; results are wrong from then on).  Not available with several
+ * solids: lbrmt_read_stress, the checkpoint calls, the tile-shape options. */
 
 /* One solid (Sec. 3.6 "mat_const"/"object"): a disc (shape 0) of radius a, or
  * an ellipse (shape 1) of semi-axes a and b whose a axis makes the angle theta
@@ -98,8 +115,9 @@ typedef enum {
     LBRMT_H_DETJ = 3,        /* half-edge with det(grad xi) <= detJ_min          */
     LBRMT_H_DETJ_SOLID = 4,  /* ... of those, edges with solid fraction > 1/2    */
     LBRMT_H_NONFINITE = 5,   /* nodes whose density is not finite or <= 0        */
-    LBRMT_H_WINDOW_CLIP = 6, /* body window reached a periodic seam (unsupported)*/
-    LBRMT_H_LIST_OVERFLOW = 7, /* layer-list entries dropped at capacity          */
+    LBRMT_H_WINDOW_CLIP = 6, /* a solid's zone reached its window's border       */
+    LBRMT_H_LIST_OVERFLOW = 7, /* list entries dropped at capacity (layer lists;
+                                  solids met by one force block beyond 32)      */
     LBRMT_H_COUNT = 8
 } lbrmt_health_index;
 
@@ -144,8 +162,12 @@ int lbrmt_create(const lbrmt_grid_desc* desc, int32_t max_solids, void* d_worksp
                  size_t bytes, void* hip_stream, lbrmt_ctx** out);
 void lbrmt_destroy(lbrmt_ctx* ctx);
 
-/* Register solids (before lbrmt_init).  ECAPACITY beyond max_solids. */
+/* Register solids (before lbrmt_init).  ECAPACITY beyond max_solids, or for
+ * a solid too large for its window (2 (extent + layers + 4) > body_window
+ * along a windowed axis). */
 int lbrmt_add_solids(lbrmt_ctx* ctx, const lbrmt_solid_desc* solids, int32_t n);
+/* Most solids one context may hold. */
+#define LBRMT_MAX_SOLIDS 4096
 
 /* Alg. 1 initialisation: xi = x on the solid and its extrapolation zone, phi
  * from the reference shape, rho = H rho_f + (1-H) rho_s, v = v0 and f = f^eq
@@ -172,8 +194,12 @@ int lbrmt_read_refmap(lbrmt_ctx* ctx, int32_t solid, double* d_X, double* d_Y, d
 int lbrmt_read_stress(lbrmt_ctx* ctx, double* d_sxx, double* d_sxy, double* d_syy);
 
 /* Reductions of the current state into host memory (synchronises the stream).
- * Returns EUNSTABLE if a NONFINITE, DETJ_SOLID or EXTRAP_FAIL counter is set. */
+ * Returns EUNSTABLE if a NONFINITE, DETJ_SOLID or EXTRAP_FAIL counter is set.
+ * With several solids the solid terms are summed over all solids. */
 int lbrmt_diag(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
+/* One solid's terms of lbrmt_diag into host memory: centroid_x, centroid_y,
+ * disp_x, disp_y (each in the solid's own unwrapped frame), n_solid, n_band. */
+int lbrmt_diag_solid(lbrmt_ctx* ctx, int32_t solid, double* host_out6);
 
 /* Checkpoint: an opaque device blob of lbrmt_state_bytes bytes holding the
  * whole step state; load restores it bit for bit (same context shape). */

@@ -73,6 +73,27 @@ __device__ __forceinline__ double node_coord(int i, int periodic, int n, double 
     return x;
 }
 
+// position of reference-map node (i, j) of grid g, seen by body b (a solid's
+// sub-window starts at lattice column ox; its positions are unwrapped)
+__device__ __forceinline__ double pos_x(const GridP& g, const BodyP& b, int i)
+{
+    return node_coord(i + g.ox, g.px, g.nx, b.cx);
+}
+__device__ __forceinline__ double pos_y(const GridP& g, const BodyP& b, int j)
+{
+    return node_coord(j + g.oy, g.py, g.ny, b.cy);
+}
+
+// lattice column / row of reference-map node i / j
+__device__ __forceinline__ int lat_col(const GridP& g, int i)
+{
+    return g.wx ? wrap_axis(i + g.ox, g.lnx) : i;
+}
+__device__ __forceinline__ int lat_row(const GridP& g, int j)
+{
+    return g.wy ? wrap_axis(j + g.oy, g.lny) : j;
+}
+
 // a level-set value computed in double, stored as T with its sign kept (a
 // negative value too small for float is stored as the smallest negative float)
 template <typename T>
@@ -176,8 +197,8 @@ hipError_t launch_win_reset(Win* win, int slot, hipStream_t st)
 __device__ __forceinline__ bool init_solid(const GridP& g, const BodyP& b, int i, int j)
 {
     if (i < 0 || i >= g.nx || j < 0 || j >= g.ny) return false;
-    const double x = node_coord(i, g.px, g.nx, b.cx);
-    const double y = node_coord(j, g.py, g.ny, b.cy);
+    const double x = pos_x(g, b, i);
+    const double y = pos_y(g, b, j);
     return shape_phi(b, x, y) < 0.0;
 }
 
@@ -250,8 +271,8 @@ __global__ void k_init_fill(GridP g, BodyP b, const int8_t* tag, const Win* win,
         const int i = W.i0 + (int)(e % w), j = W.j0 + (int)(e / w);
         const long long k = pidx(g, i, j);
         if (tag[k] != TAG_NONE) {
-            const double x = node_coord(i, g.px, g.nx, b.cx);
-            const double y = node_coord(j, g.py, g.ny, b.cy);
+            const double x = pos_x(g, b, i);
+            const double y = pos_y(g, b, j);
             X[k] = DISP ? T(0) : T(x);
             Y[k] = DISP ? T(0) : T(y);
             phi[k] = store_phi<T>(shape_phi(b, x, y));
@@ -333,16 +354,18 @@ __device__ __forceinline__ void advect_node(const GridP& g, const S* __restrict_
     long long ks[8];
 #pragma unroll
     for (int q = 0; q < 8; q++) ks[q] = ref_index(g, D, i + di[q], j + dj[q]);
-    // populations of the pull gather (the node is interior)
-    const bool bw = !g.px && i == 0, be = !g.px && i == g.nx - 1;
-    const bool bs = !g.py && j == 0, bn = !g.py && j == g.ny - 1;
-    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
-    im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
-    ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
-    jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
-    jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
-    const long long r0 = (long long)j * g.pitch, rm = (long long)jm * g.pitch,
-                    rp = (long long)jp * g.pitch, n = r0 + i;
+    // populations of the pull gather (the node is interior), at the node's
+    // lattice position (a solid's window may be a sub-range of the lattice)
+    const int li = lat_col(g, i), lj = lat_row(g, j);
+    const bool bw = !g.lpx && li == 0, be = !g.lpx && li == g.lnx - 1;
+    const bool bs = !g.lpy && lj == 0, bn = !g.lpy && lj == g.lny - 1;
+    int im = li - 1, ip = li + 1, jm = lj - 1, jp = lj + 1;
+    im = im < 0 ? (g.lpx ? g.lnx - 1 : 0) : im;
+    ip = ip >= g.lnx ? (g.lpx ? 0 : g.lnx - 1) : ip;
+    jm = jm < 0 ? (g.lpy ? g.lny - 1 : 0) : jm;
+    jp = jp >= g.lny ? (g.lpy ? 0 : g.lny - 1) : jp;
+    const long long r0 = (long long)lj * g.pitch, rm = (long long)jm * g.pitch,
+                    rp = (long long)jp * g.pitch, n = r0 + li;
     // ---- all loads
     const C X0 = X[k], Y0 = Y[k];
     C ps[8], xs[8], ys[8];
@@ -356,9 +379,9 @@ __device__ __forceinline__ void advect_node(const GridP& g, const S* __restrict_
     C f[NQ];
     f[0] = A[n];
     f[1] = bw ? A[3 * P + n] : A[1 * P + r0 + im];
-    f[2] = bs ? A[4 * P + n] : A[2 * P + rm + i];
+    f[2] = bs ? A[4 * P + n] : A[2 * P + rm + li];
     f[3] = be ? A[1 * P + n] : A[3 * P + r0 + ip];
-    f[4] = bn ? A[2 * P + n] : A[4 * P + rp + i];
+    f[4] = bn ? A[2 * P + n] : A[4 * P + rp + li];
     f[5] = (bw || bs) ? A[7 * P + n] : A[5 * P + rm + im];
     f[6] = (be || bs) ? A[8 * P + n] : A[6 * P + rm + ip];
     f[7] = (be || bn) ? A[5 * P + n] : A[7 * P + rp + ip];
@@ -432,7 +455,7 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
     if (!W.ok) return;
     const Rect D = window_of(win, wprev, g);
     const int L = LC > 0 ? LC : g.layers;
-    const long long cap = sub_cap(g.pplane);
+    const long long cap = g.lcap;
     const int sub = blockIdx.x % NSUB;
     const int w = W.i1 - W.i0 + 1, h = W.j1 - W.j0 + 1;
     const int ntx = (w + DTX - 1) / DTX, nty = (h + DTY - 1) / DTY;
@@ -783,7 +806,7 @@ __device__ __forceinline__ void layer_fit_body(GridP g, const Win* __restrict__ 
     // group g takes sub-list g mod NSUB (the sub-lists come from interleaved
     // distance-transform blocks, so they are of similar length); its first
     // list entry is loaded together with the sub-list's count
-    const long long cap = sub_cap(g.pplane);
+    const long long cap = g.lcap;
     const int sub = threadIdx.x % FIT_LANES;
     const int grp = (blockIdx.x * blockDim.x + threadIdx.x) / FIT_LANES;
     const int s = grp % NSUB, a0 = grp / NSUB;
@@ -971,8 +994,8 @@ __device__ __forceinline__ double relabel_phi(const GridP& g, const BodyP& b, in
     if (!tag_set(tv)) return INFINITY;
     double X = (double)xv, Y = (double)yv;
     if (sizeof(C) == 4) {  // displacement storage
-        X += node_coord(i, g.px, g.nx, b.cx);
-        Y += node_coord(j, g.py, g.ny, b.cy);
+        X += pos_x(g, b, i);
+        Y += pos_y(g, b, j);
     }
     return shape_phi(b, X, Y);
 }
@@ -985,7 +1008,9 @@ __device__ __forceinline__ double relabel_phi(const GridP& g, const BodyP& b, in
 // tile's own nodes (with the map cleared where none is held), and for the
 // window's nodes outside the interior by a strided pass; each block writes
 // the partial box of the new interior solid set it saw, which the next
-// lattice update reduces into the next ring slot.
+// lattice update reduces into the next ring slot.  MODE 2 is MODE 0 without
+// the stresses (one solid of several: the forces are combined over all
+// solids afterwards).
 template <int MODE, typename C>
 __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvalid,
                                            int* boxpart, int whole_grid, C* X, C* Y,
@@ -995,7 +1020,8 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
 {
     // the force pass ends the reference-map chain of a step: clear the layer
     // counters of the next step's distance transform
-    if (MODE == 0) clear_lcount(lcount);
+    constexpr bool RELABEL = MODE == 0 || MODE == 2;
+    if (RELABEL) clear_lcount(lcount);
     __shared__ C sX[SY * SX], sY[SY * SX], sP[SY * SX];
     __shared__ C ex[FTY][FTX + 1][3];
     __shared__ C ey[FTY + 1][FTX][3];
@@ -1024,7 +1050,7 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
             const long long k = in ? pidx(g, ci, cj) : 0;
             const C xv = X[k], yv = Y[k];
             C p;
-            if (MODE == 0) p = store_phi<C>(relabel_phi<C>(g, b, tag[k], xv, yv, ci, cj));
+            if (RELABEL) p = store_phi<C>(relabel_phi<C>(g, b, tag[k], xv, yv, ci, cj));
             else p = phi[k];
             const bool set = in && p < C(INFINITY);
             sX[e] = set ? xv : C(NAN);
@@ -1034,7 +1060,7 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
         __syncthreads();
         const int i = i0 + tx, j = j0 + ty;
         const bool mine = i <= Rg.i1 && j <= Rg.j1;
-        if (MODE == 0 && mine) {
+        if (RELABEL && mine) {
             // relabel output of the tile's own node
             const long long k = pidx(g, i, j);
             const C p = sP[(ty + 1) * SX + tx + 1];
@@ -1051,6 +1077,10 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
                 X[k] = C(NAN);
                 Y[k] = C(NAN);
             }
+        }
+        if (MODE == 2) {
+            __syncthreads();
+            continue;
         }
         // health counting: an edge is counted once, by the node on its far
         // side, or by its near node when the far node lies outside the region
@@ -1110,7 +1140,7 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
         }
         __syncthreads();
     }
-    if (MODE == 0) {
+    if (RELABEL) {
         // relabel of the window's nodes outside the interior (buffer nodes)
         if (V.ok && b.present) {
             const int w = V.i1 - V.i0 + 1, h = V.j1 - V.j0 + 1;
@@ -1145,12 +1175,12 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
                         o2, lcount, health);
 }
 
-template <typename C>
+template <int MODE, typename C>
 __global__ __launch_bounds__(256) void kb_force(const EdgesArgs* __restrict__ args)
 {
     const EdgesArgs& a = args[blockIdx.y];
-    edges_body<0, C>(a.g, a.b, a.win, a.wvalid, a.boxpart, 0, (C*)a.X, (C*)a.Y, nullptr, a.tag,
-                     (C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health);
+    edges_body<MODE, C>(a.g, a.b, a.win, a.wvalid, a.boxpart, 0, (C*)a.X, (C*)a.Y, nullptr,
+                        a.tag, (C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health);
 }
 
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
@@ -1204,8 +1234,8 @@ __global__ void k_read_refmap(GridP g, BodyP b, const Win* __restrict__ win, int
                 yv = (double)Y[k];
                 pv = (double)phi[k];
                 if (DISP) {
-                    xv += node_coord(i, g.px, g.nx, b.cx);
-                    yv += node_coord(j, g.py, g.ny, b.cy);
+                    xv += pos_x(g, b, i);
+                    yv += pos_y(g, b, j);
                 }
             }
         }
@@ -1231,20 +1261,473 @@ hipError_t launch_read_refmap(const GridP& g, const BodyP& b, const BandBufs& bb
 
 // ---------------------------------------------------------------- batched launches
 
-hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
-                             hipStream_t st)
+// ---------------------------------------------------------------- several solids
+//
+// Every solid keeps its reference map on a window of its own (the chain
+// kernels above run per solid, blockIdx.y = solid, relabelling only).  The
+// lattice is cut into FB x FB force blocks; each step every solid stamps the
+// blocks of its working window and lists the newly stamped ones, and one
+// kernel over the listed blocks combines all solids into the force planes
+// (Sec. 3.6): the global half-edge stress is the solids' blend normalised by
+// their summed fraction where it exceeds one, plus the contact stress of
+// every pair, Eqs. (3_6_global_stress) to (3_6_normal).
+
+// window index of lattice column c (row r) in solid grid g; along a
+// sub-window axis the offset from the window origin, in [-PAD, lnx - PAD)
+__device__ __forceinline__ int win_col(const GridP& g, int c)
 {
-    const dim3 gb(BATCH_BAND_BLOCKS, nsim), gd(BATCH_DT_BLOCKS, nsim), gf(BATCH_FIT_BLOCKS, nsim);
+    if (!g.wx) return c;
+    const int d = wrap_axis(c - g.ox, g.lnx);
+    return d >= g.lnx - PAD ? d - g.lnx : d;
+}
+__device__ __forceinline__ int win_row(const GridP& g, int r)
+{
+    if (!g.wy) return r;
+    const int d = wrap_axis(r - g.oy, g.lny);
+    return d >= g.lny - PAD ? d - g.lny : d;
+}
+
+// the working window of ring slot `slot` as lattice nodes {x, dx, y, dy}:
+// columns x .. x + dx (x wrapped, the range may run over a periodic seam),
+// rows likewise; dx < 0 or dy < 0: empty
+__device__ int4 mb_region(const GridP& g, const Win* win, int slot)
+{
+    const Rect V = window_of(win, slot, g);
+    int4 r = make_int4(0, -1, 0, -1);
+    if (!V.ok) return r;
+    if (g.wx) {
+        r.x = wrap_axis(V.i0 + g.ox, g.lnx);
+        r.y = V.i1 - V.i0;
+    } else {
+        r.x = max(V.i0, 0);
+        r.y = min(V.i1, g.nx - 1) - r.x;
+    }
+    if (g.wy) {
+        r.z = wrap_axis(V.j0 + g.oy, g.lny);
+        r.w = V.j1 - V.j0;
+    } else {
+        r.z = max(V.j0, 0);
+        r.w = min(V.j1, g.ny - 1) - r.z;
+    }
+    return r;
+}
+
+// do [a, a + la] and [b, b + lb] meet (on a circle of n nodes if periodic)?
+__device__ __forceinline__ bool ranges_meet(int a, int la, int b, int lb, int n, int periodic)
+{
+    if (!periodic) return a <= b + lb && b <= a + la;
+    return wrap_axis(b - a, n) <= la || wrap_axis(a - b, n) <= lb;
+}
+
+// one block per solid
+__global__ __launch_bounds__(256) void k_mb_mark(GridP lg, MbBody* bodies, int wcur, int wnext,
+                                                 int nbox, int* stamp, int sval, int* list,
+                                                 int* count, int nbx, unsigned* health,
+                                                 const long long* dstep)
+{
+    MbBody& B = bodies[blockIdx.x];
+    if (dstep) sval = (int)(*dstep + 1);
+    if (nbox > 0) reduce_boxes(B.boxpart, nbox, &B.win[wnext], nullptr);
+    __shared__ int4 reg;
+    if (threadIdx.x == 0) {
+        const GridP& g = B.g;
+        if (nbox > 0) check_zone(g, B.win[wnext], health);
+        reg = mb_region(g, B.win, wcur);
+        B.reg = reg;
+    }
+    __syncthreads();
+    if (reg.y < 0 || reg.w < 0) return;
+    // sample columns x, x + FB, ..., x + dx (and rows alike): every block met
+    const int nsx = reg.y / FB + 2, nsy = reg.w / FB + 2;
+    for (int e = threadIdx.x; e < nsx * nsy; e += blockDim.x) {
+        int gx = reg.x + min((e % nsx) * FB, reg.y), gy = reg.z + min((e / nsx) * FB, reg.w);
+        if (lg.px) gx = wrap_axis(gx, lg.nx);
+        if (lg.py) gy = wrap_axis(gy, lg.ny);
+        const int blk = (gy >> FB_LOG) * nbx + (gx >> FB_LOG);
+        if (atomicExch(&stamp[blk], sval) != sval) list[atomicAdd(count, 1)] = blk;
+    }
+}
+
+hipError_t launch_mb_mark(const GridP& lg, MbBody* bodies, int nb, int wcur, int wnext,
+                          int nbox, int* stamp, int sval, int* list, int* count, int nbx,
+                          unsigned* health, hipStream_t st, const long long* dstep)
+{
+    if (nb > 0)
+        k_mb_mark<<<nb, 256, 0, st>>>(lg, bodies, wcur, wnext, nbox, stamp, sval, list, count,
+                                      nbx, health, dstep);
+    return hipGetLastError();
+}
+
+__global__ void k_mb_tick(long long* dstep)
+{
+    if (threadIdx.x == 0) *dstep += 1;
+}
+
+hipError_t launch_mb_tick(long long* dstep, hipStream_t st)
+{
+    k_mb_tick<<<1, 64, 0, st>>>(dstep);
+    return hipGetLastError();
+}
+
+// xi, phi of solid B on the 3 x 3 nodes around window node (wi, wj), index
+// (dj + 1) * 3 + (di + 1); a node without a map holds (NaN, NaN, +inf)
+template <typename C>
+__device__ __forceinline__ void mb_load3(const MbBody& B, const Rect& V, int buf, int wi, int wj,
+                                         C* sX, C* sY, C* sP)
+{
+    const C* X = (const C*)B.X[buf];
+    const C* Y = (const C*)B.Y[buf];
+    const C* P = (const C*)B.phi[buf];
+#pragma unroll
+    for (int e = 0; e < 9; e++) {
+        int ci = wi + e % 3 - 1, cj = wj + e / 3 - 1;
+        const bool in = canon(B.g, ci, cj) && V.has(ci, cj);
+        const long long k = in ? pidx(B.g, ci, cj) : 0;
+        const C xv = X[k], yv = Y[k], p = P[k];
+        const bool set = in && p < C(INFINITY);
+        sX[e] = set ? xv : C(NAN);
+        sY[e] = set ? yv : C(NAN);
+        sP[e] = set ? p : C(INFINITY);
+    }
+}
+
+// the half-edges of a node in the 3 x 3 stencil: L, R, B, T as (a, b, s1..s4,
+// dir) with a before b along the normal and s1 + s2 - s3 - s4 the tangential
+// difference (the stencil of the single-solid force kernel)
+__constant__ int MB_EDGE[4][7] = {{3, 4, 7, 6, 1, 0, 0},
+                                  {4, 5, 8, 7, 2, 1, 0},
+                                  {1, 4, 5, 2, 3, 0, 1},
+                                  {4, 7, 8, 5, 6, 3, 1}};
+
+// Eq. (3_6_collision_force)
+template <typename C>
+__device__ __forceinline__ C contact_f(C x, C eps)
+{
+    return x < eps ? C(0.5) * (C(1) - x / eps) : C(0);
+}
+
+// force density and density excess of lattice node (gi, gj) from the solids
+// sl[0 .. ns) (index order) of its block
+template <typename C>
+__device__ void mb_node(const GridP& lg, const MbBody* __restrict__ bodies, const int* sl,
+                        int ns, int buf, int wcur, int gi, int gj, double* fxo, double* fyo,
+                        double* drho, bool drho_only, unsigned* health)
+{
+    C acc[4][3], lse[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        lse[e] = C(0);
+        acc[e][0] = acc[e][1] = acc[e][2] = C(0);
+    }
+    C lsum = C(0), dacc = C(0);
+    int nset = 0;
+    for (int q = 0; q < ns; q++) {
+        const MbBody& B = bodies[sl[q]];
+        const GridP& g = B.g;
+        const int wi = win_col(g, gi), wj = win_row(g, gj);
+        const Rect V = window_of(B.win, wcur, g);
+        if (!V.has(wi, wj)) continue;
+        C sX[9], sY[9], sP[9];
+        mb_load3<C>(B, V, buf, wi, wj, sX, sY, sP);
+        if (!(sP[4] < C(INFINITY))) continue;
+        nset++;
+        const C lam = C(1) - heaviside<C>(sP[4], C(g.eps));
+        lsum += lam;
+        dacc += lam * C(B.b.rho_s - lg.rho_f);
+        if (drho_only) continue;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int a = MB_EDGE[e][0], b = MB_EDGE[e][1];
+            if (!(sP[a] < C(INFINITY)) || !(sP[b] < C(INFINITY))) continue;
+            const C le = C(1) - heaviside<C>(C(0.5) * (sP[a] + sP[b]), C(g.eps));
+            if (!(le > C(0))) continue;
+            lse[e] += le;
+            C t[3];
+            // each edge is counted once: by its far node (the L and B edges)
+            edge_tau<C>(g, B.b, sX, sY, sP, a, b, MB_EDGE[e][2], MB_EDGE[e][3], MB_EDGE[e][4],
+                        MB_EDGE[e][5], MB_EDGE[e][6], e == 0 || e == 2, health, t);
+            acc[e][0] += t[0];
+            acc[e][1] += t[1];
+            acc[e][2] += t[2];
+        }
+    }
+    const long long n = (long long)gj * lg.pitch + gi;
+    const C dr = lsum > C(1) ? dacc / lsum : dacc;
+    drho[n] = (double)dr;
+    if (drho_only) return;
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+        if (lse[e] > C(1)) {
+            acc[e][0] /= lse[e];
+            acc[e][1] /= lse[e];
+            acc[e][2] /= lse[e];
+        }
+    if (nset >= 2 && lg.eta != 0.0) {
+        // contact stress of every pair (p, q), p < q, on the node's edges
+        for (int p = 0; p < ns; p++) {
+            const MbBody& Bp = bodies[sl[p]];
+            const int pi = win_col(Bp.g, gi), pj = win_row(Bp.g, gj);
+            const Rect Vp = window_of(Bp.win, wcur, Bp.g);
+            if (!Vp.has(pi, pj)) continue;
+            C pX[9], pY[9], pP[9];
+            mb_load3<C>(Bp, Vp, buf, pi, pj, pX, pY, pP);
+            if (!(pP[4] < C(INFINITY))) continue;
+            for (int q = p + 1; q < ns; q++) {
+                const MbBody& Bq = bodies[sl[q]];
+                const int qi = win_col(Bq.g, gi), qj = win_row(Bq.g, gj);
+                const Rect Vq = window_of(Bq.win, wcur, Bq.g);
+                if (!Vq.has(qi, qj)) continue;
+                C qX[9], qY[9], qP[9];
+                mb_load3<C>(Bq, Vq, buf, qi, qj, qX, qY, qP);
+                if (!(qP[4] < C(INFINITY))) continue;
+                const C cg = C(-lg.eta);
+                const C gsum = C(Bp.b.G + Bq.b.G);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    bool all = true;
+#pragma unroll
+                    for (int t = 0; t < 6; t++) {
+                        const int v = MB_EDGE[e][t];
+                        all = all && pP[v] < C(INFINITY) && qP[v] < C(INFINITY);
+                    }
+                    if (!all) continue;
+                    const int a = MB_EDGE[e][0], b = MB_EDGE[e][1];
+                    const C fp = contact_f<C>(C(0.5) * (pP[a] + pP[b]), C(lg.eps));
+                    const C fq = contact_f<C>(C(0.5) * (qP[a] + qP[b]), C(lg.eps));
+                    const C fmin = fp < fq ? fp : fq;
+                    if (!(fmin > C(0))) continue;
+                    C d[6];
+#pragma unroll
+                    for (int t = 0; t < 6; t++) {
+                        const int v = MB_EDGE[e][t];
+                        d[t] = pP[v] - qP[v];
+                    }
+                    // Eq. (3_6_normal) on the edge stencil
+                    const C gn = d[1] - d[0];
+                    const C gt = (d[2] + d[3] - d[4] - d[5]) / C(4);
+                    const C gx = MB_EDGE[e][6] == 0 ? gn : gt;
+                    const C gy = MB_EDGE[e][6] == 0 ? gt : gn;
+                    const C gl = sqrt(gx * gx + gy * gy);
+                    if (!(gl > C(0))) continue;
+                    const C nx = gx / gl, ny = gy / gl;
+                    const C c = cg * fmin * gsum;
+                    acc[e][0] += c * (nx * nx - C(0.5));
+                    acc[e][1] += c * (nx * ny);
+                    acc[e][2] += c * (ny * ny - C(0.5));
+                }
+            }
+        }
+    }
+    // Eq. (3_3_div_solid_stress) on the node's four edges, buoyancy of the
+    // mixture and the fluid's share of the external force
+    C fx = (acc[1][0] - acc[0][0]) + (acc[3][1] - acc[2][1]);
+    C fy = (acc[1][1] - acc[0][1]) + (acc[3][2] - acc[2][2]);
+    fx += dr * C(lg.gx);
+    fy += dr * C(lg.gy);
+    const C hf = lsum < C(1) ? C(1) - lsum : C(0);
+    fx += hf * C(lg.fext_x);
+    fy += hf * C(lg.fext_y);
+    fxo[n] = (double)fx;
+    fyo[n] = (double)fy;
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_mb_combine(GridP lg, const MbBody* __restrict__ bodies,
+                                                    int nb, int buf, int wcur,
+                                                    const int* __restrict__ list,
+                                                    const int* __restrict__ count,
+                                                    int* count_clear, int nbx, double* fx,
+                                                    double* fy, double* drho, int drho_only,
+                                                    unsigned* health)
+{
+    static_assert(FB * FB == 256, "one thread per node of a force block");
+    if (blockIdx.x == 0 && threadIdx.x == 0 && count_clear) *count_clear = 0;
+    __shared__ int sl[MB_MAX_PER_BLOCK];
+    __shared__ int wcnt[4];
+    __shared__ int ns;
+    const int nblk = *count;
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int t = blockIdx.x; t < nblk; t += gridDim.x) {
+        const int blk = list[t];
+        const int bx0 = (blk % nbx) * FB, by0 = (blk / nbx) * FB;
+        if (threadIdx.x == 0) ns = 0;
+        __syncthreads();
+        // the solids whose region meets this block, in index order
+        for (int base = 0; base < nb; base += blockDim.x) {
+            const int k = base + threadIdx.x;
+            bool hit = false;
+            if (k < nb) {
+                const int4 r = bodies[k].reg;
+                hit = r.y >= 0 && r.w >= 0 &&
+                      ranges_meet(r.x, r.y, bx0, FB - 1, lg.nx, lg.px) &&
+                      ranges_meet(r.z, r.w, by0, FB - 1, lg.ny, lg.py);
+            }
+            const unsigned long long m = __ballot(hit);
+            if (lane == 0) wcnt[w] = __popcll(m);
+            __syncthreads();
+            int off = ns + __popcll(m & ((1ull << lane) - 1ull));
+            for (int u = 0; u < w; u++) off += wcnt[u];
+            if (hit) {
+                if (off < MB_MAX_PER_BLOCK) sl[off] = k;
+                else atomicAdd(&health[7], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) ns = min(ns + wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3],
+                                           MB_MAX_PER_BLOCK);
+            __syncthreads();
+        }
+        const int gi = bx0 + threadIdx.x % FB, gj = by0 + threadIdx.x / FB;
+        if (gi < lg.nx && gj < lg.ny)
+            mb_node<C>(lg, bodies, sl, ns, buf, wcur, gi, gj, fx, fy, drho, drho_only != 0,
+                       health);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_mb_combine(const GridP& lg, int precision, const MbBody* bodies, int nb,
+                             int buf, int wcur, const int* list, const int* count,
+                             int* count_clear, int nbx, double* fx, double* fy, double* drho,
+                             bool drho_only, unsigned* health, hipStream_t st)
+{
+    if (precision == 0)
+        k_mb_combine<double><<<MB_COMBINE_BLOCKS, 256, 0, st>>>(
+            lg, bodies, nb, buf, wcur, list, count, count_clear, nbx, fx, fy, drho,
+            drho_only ? 1 : 0, health);
+    else
+        k_mb_combine<float><<<MB_COMBINE_BLOCKS, 256, 0, st>>>(
+            lg, bodies, nb, buf, wcur, list, count, count_clear, nbx, fx, fy, drho,
+            drho_only ? 1 : 0, health);
+    return hipGetLastError();
+}
+
+// xi and phi of solid k on the lattice nodes (NaN where it holds no map)
+template <typename C>
+__global__ void k_mb_read_refmap(GridP lg, const MbBody* __restrict__ bodies, int k, int buf,
+                                 int wvalid, double* X, double* Y, double* phi)
+{
+    const MbBody& B = bodies[k];
+    const GridP& g = B.g;
+    const Rect V = window_of(B.win, wvalid, g);
+    const C* Xs = (const C*)B.X[buf];
+    const C* Ys = (const C*)B.Y[buf];
+    const C* Ps = (const C*)B.phi[buf];
+    const long long N = (long long)lg.nx * lg.ny;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int gi = (int)(e % lg.nx), gj = (int)(e / lg.nx);
+        const int i = win_col(g, gi), j = win_row(g, gj);
+        double xv = NAN, yv = NAN, pv = NAN;
+        if (V.has(i, j) && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+            const long long kk = pidx(g, i, j);
+            const C p = Ps[kk];
+            if (p < C(INFINITY)) {
+                xv = (double)Xs[kk];
+                yv = (double)Ys[kk];
+                if (sizeof(C) == 4) {
+                    xv += pos_x(g, B.b, i);
+                    yv += pos_y(g, B.b, j);
+                }
+                pv = (double)p;
+            }
+        }
+        if (X) X[e] = xv;
+        if (Y) Y[e] = yv;
+        if (phi) phi[e] = pv;
+    }
+}
+
+hipError_t launch_mb_read_refmap(const GridP& lg, int precision, const MbBody* bodies, int k,
+                                 int buf, int wvalid, double* X, double* Y, double* phi,
+                                 hipStream_t st)
+{
+    const long long N = (long long)lg.nx * lg.ny;
+    const int blocks = (int)((N + 255) / 256 < 4096 ? (N + 255) / 256 : 4096);
+    if (precision == 0)
+        k_mb_read_refmap<double><<<blocks, 256, 0, st>>>(lg, bodies, k, buf, wvalid, X, Y, phi);
+    else
+        k_mb_read_refmap<float><<<blocks, 256, 0, st>>>(lg, bodies, k, buf, wvalid, X, Y, phi);
+    return hipGetLastError();
+}
+
+// one block per solid: its fraction moments over the interior nodes of its
+// window, reduced in a fixed order
+template <typename C>
+__global__ __launch_bounds__(256) void k_mb_diag(const MbBody* __restrict__ bodies, int buf,
+                                                 int wvalid, double* out)
+{
+    const MbBody& B = bodies[blockIdx.x];
+    const GridP& g = B.g;
+    const Rect V = window_of(B.win, wvalid, g);
+    const C* Xs = (const C*)B.X[buf];
+    const C* Ys = (const C*)B.Y[buf];
+    const C* Ps = (const C*)B.phi[buf];
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (V.ok) {
+        const int i0 = max(V.i0, 0), i1 = min(V.i1, g.nx - 1);
+        const int j0 = max(V.j0, 0), j1 = min(V.j1, g.ny - 1);
+        const int w = i1 - i0 + 1, h = j1 - j0 + 1;
+        if (w > 0 && h > 0)
+            for (int e = threadIdx.x; e < w * h; e += blockDim.x) {
+                const int i = i0 + e % w, j = j0 + e / w;
+                const long long k = pidx(g, i, j);
+                const double p = (double)Ps[k];
+                if (!(p < INFINITY)) continue;
+                a[6] += 1.0;
+                if (p < 0.0) a[5] += 1.0;
+                const double lam = 1.0 - heaviside<double>(p, g.eps);
+                const double x = pos_x(g, B.b, i), y = pos_y(g, B.b, j);
+                double dx, dy;
+                if (sizeof(C) == 4) {  // displacement storage: x - xi = -d
+                    dx = -(double)Xs[k];
+                    dy = -(double)Ys[k];
+                } else {
+                    dx = x - (double)Xs[k];
+                    dy = y - (double)Ys[k];
+                }
+                a[0] += lam;
+                a[1] += lam * x;
+                a[2] += lam * y;
+                a[3] += lam * dx;
+                a[4] += lam * dy;
+            }
+    }
+    __shared__ double red[7][256];
+    for (int t = 0; t < 7; t++) red[t][threadIdx.x] = a[t];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int t = 0; t < 7; t++) red[t][threadIdx.x] += red[t][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) out[7 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_mb_diag(int precision, const MbBody* bodies, int nb, int buf, int wvalid,
+                          double* out, hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    if (precision == 0) k_mb_diag<double><<<nb, 256, 0, st>>>(bodies, buf, wvalid, out);
+    else k_mb_diag<float><<<nb, 256, 0, st>>>(bodies, buf, wvalid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
+                             hipStream_t st, bool relabel_only, int dt_blocks, int fit_blocks,
+                             int band_blocks)
+{
+    const dim3 gb(band_blocks, nsim), gd(dt_blocks, nsim), gf(fit_blocks, nsim);
     if (precision == 0) {
         if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv);
         for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
-        kb_force<double><<<gb, 256, 0, st>>>(t.edg);
+        if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg);
+        else kb_force<0, double><<<gb, 256, 0, st>>>(t.edg);
     } else {
         if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv);
         for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
-        kb_force<float><<<gb, 256, 0, st>>>(t.edg);
+        if (relabel_only) kb_force<2, float><<<gb, 256, 0, st>>>(t.edg);
+        else kb_force<0, float><<<gb, 256, 0, st>>>(t.edg);
     }
     return hipGetLastError();
 }

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(GridP g, BodyP b, const S*
                                                       const S* __restrict__ X,
                                                       const S* __restrict__ Y,
                                                       const S* __restrict__ phi,
-                                                      double* partial)
+                                                      double* partial, StampValid sv)
 {
     const long long N = (long long)g.nx * g.ny;
     const Rect D = window_of(win, wprev, g);
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(GridP g, BodyP b, const S*
         if (sizeof(S) == 4)
             for (int k = 0; k < NQ; k++) f[k] += wq[k] * g.rho_f;
         double Fx = fpo_x, Fy = fpo_y;
-        if (D.has(i, j)) {
+        if (sv.stamp ? sv.has(i, j) : D.has(i, j)) {
             Fx = fpx[n];
             Fy = fpy[n];
         }
@@ -145,20 +145,22 @@ __global__ __launch_bounds__(DIAG_FIELDS * 64) void k_diag_final(const double* _
 hipError_t launch_diag(const GridP& g, int precision, const BodyP& b, const void* A,
                        const double* fpx, const double* fpy, const Win* win, int wprev,
                        double fpo_x, double fpo_y, const BandBufs& bb, int buf, double* partial,
-                       double* out, hipStream_t st)
+                       double* out, hipStream_t st, StampValid sv)
 {
     if (precision == 0)
         k_diag_partial<double><<<DIAG_BLOCKS, 256, 0, st>>>(g, b, (const double*)A, fpx, fpy, win,
                                                             wprev, fpo_x, fpo_y,
                                                             (const double*)bb.X[buf],
                                                             (const double*)bb.Y[buf],
-                                                            (const double*)bb.phi[buf], partial);
+                                                            (const double*)bb.phi[buf], partial,
+                                                            sv);
     else
         k_diag_partial<float><<<DIAG_BLOCKS, 256, 0, st>>>(g, b, (const float*)A, fpx, fpy, win,
                                                            wprev, fpo_x, fpo_y,
                                                            (const float*)bb.X[buf],
                                                            (const float*)bb.Y[buf],
-                                                           (const float*)bb.phi[buf], partial);
+                                                           (const float*)bb.phi[buf], partial,
+                                                           sv);
     k_diag_final<<<1, DIAG_FIELDS * 64, 0, st>>>(partial, DIAG_BLOCKS, out);
     return hipGetLastError();
 }

@@ -169,14 +169,17 @@ __device__ __forceinline__ Rect band_region(const GridP& g, const Rect& a, const
 // that more loads are in flight per wave.  PART 1 tiles (outside the band
 // region) use the uniform fluid force; otherwise the force planes are read
 // inside the windows of this and the previous step.
-template <typename S, int PART, int LB_TX, int LB_TY, int R, bool NT>
+// VP, VC: where the force planes of the previous and of this step are held
+// (Rect: a solid's window; StampValid: force-block stamps of several solids)
+template <typename S, int PART, int LB_TX, int LB_TY, int R, bool NT, typename VP = Rect,
+          typename VC = Rect>
 __device__ __forceinline__ void lb_tile(const GridP& g, const S* __restrict__ A, S* __restrict__ B,
                                         const double* __restrict__ fpx,
                                         const double* __restrict__ fpy,
                                         const double* __restrict__ fcx,
                                         const double* __restrict__ fcy,
-                                        const double* __restrict__ drho, const Rect& wp,
-                                        const Rect& wc, double fpo_x, double fpo_y,
+                                        const double* __restrict__ drho, const VP& wp,
+                                        const VC& wc, double fpo_x, double fpo_y,
                                         unsigned* __restrict__ health, int tile_x, int tile_y)
 {
     using C = typename Prec<S>::C;
@@ -250,7 +253,10 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     const double* __restrict__ drho, Win* win, int wprev, int wcur, double fpo_x, double fpo_y,
     unsigned* __restrict__ health, const int* __restrict__ boxpart, int nbox, int wnext)
 {
-    if (PART != 1 && nbox > 0 && blockIdx.x == 0) reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
+    if (PART != 1 && nbox > 0 && blockIdx.x == 0) {
+        reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
+        if (threadIdx.x == 0) check_zone(g, win[wnext], health);
+    }
     constexpr int TH = LB_TY * R;
     const int ntx = (g.nx + LB_TX - 1) / LB_TX;
     const int nty = (g.ny + TH - 1) / TH;
@@ -303,13 +309,34 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void kb_lb(const LbArgs* __restrict__
     const LbArgs& a = args[tile_sim[t]];
     const int local = t - a.tile_base;
     // the member's first tile reduces the force pass's partial boxes
-    if (local == 0 && a.nbox > 0) reduce_boxes(a.boxpart, a.nbox, &a.winw[a.wnext], nullptr);
+    if (local == 0 && a.nbox > 0) {
+        reduce_boxes(a.boxpart, a.nbox, &a.winw[a.wnext], nullptr);
+        if (threadIdx.x == 0) check_zone(a.g, a.winw[a.wnext], a.health);
+    }
     const int ntx = (a.g.nx + LB_TX - 1) / LB_TX;
     const Rect wp = window_of(a.win, a.wprev, a.g);
     const Rect wc = window_of(a.win, a.wcur, a.g);
     lb_tile<S, 0, LB_TX, LB_TY, R, NT>(a.g, (const S*)a.A, (S*)a.B, a.fpx, a.fpy, a.fcx, a.fcy,
                                        a.drho, wp, wc, a.fpo_x, a.fpo_y, a.health, local % ntx,
                                        local / ntx);
+}
+
+// Several solids: every tile, force planes where the block stamps say so.
+template <typename S, int LB_TX, int LB_TY, int R, bool NT>
+__global__ __launch_bounds__(LB_TX* LB_TY) void k_lb_mb(
+    GridP g, const S* __restrict__ A, S* __restrict__ B, const double* __restrict__ fpx,
+    const double* __restrict__ fpy, const double* __restrict__ fcx, const double* __restrict__ fcy,
+    const double* __restrict__ drho, StampValid vp, StampValid vc, double fpo_x, double fpo_y,
+    unsigned* __restrict__ health, const long long* __restrict__ dstep)
+{
+    constexpr int TH = LB_TY * R;
+    const int ntx = (g.nx + LB_TX - 1) / LB_TX;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    vp.val = (int)*dstep;
+    vc.val = vp.val + 1;
+    lb_tile<S, 0, LB_TX, LB_TY, R, NT, StampValid, StampValid>(
+        g, A, B, fpx, fpy, fcx, fcy, drho, vp, vc, fpo_x, fpo_y, health, t % ntx, t / ntx);
+    (void)TH;
 }
 
 // Tile shapes of the lattice Boltzmann update (one thread per node); the
@@ -424,6 +451,35 @@ static void lb_batch_variant(int v, const LbArgs* args, const int* tile_sim, int
 #undef LBB
 }
 
+template <typename S, int TX, int TY, int R, bool NT>
+static void lb_mb_one(const GridP& g, const void* A, void* B, const double* fpx,
+                      const double* fpy, const double* fcx, const double* fcy,
+                      const double* drho, StampValid vp, StampValid vc, double fpo_x,
+                      double fpo_y, unsigned* health, hipStream_t st, const long long* dstep)
+{
+    const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY * R - 1) / (TY * R));
+    k_lb_mb<S, TX, TY, R, NT><<<ntiles, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx,
+                                                         fcy, drho, vp, vc, fpo_x, fpo_y,
+                                                         health, dstep);
+}
+
+hipError_t launch_lb_mb(const GridP& g, int precision, int variant, const void* A, void* B,
+                        const double* fpx, const double* fpy, const double* fcx,
+                        const double* fcy, const double* drho, StampValid vp, StampValid vc,
+                        double fpo_x, double fpo_y, unsigned* health, hipStream_t st,
+                        const long long* dstep)
+{
+    // the measured single-solid choices: 64 x 4 (FP64), 256 x 1 (FP32), nontemporal stores
+    (void)variant;
+    if (precision == 0)
+        lb_mb_one<double, 64, 4, 1, true>(g, A, B, fpx, fpy, fcx, fcy, drho, vp, vc, fpo_x,
+                                          fpo_y, health, st, dstep);
+    else
+        lb_mb_one<float, 256, 1, 1, true>(g, A, B, fpx, fpy, fcx, fcy, drho, vp, vc, fpo_x,
+                                          fpo_y, health, st, dstep);
+    return hipGetLastError();
+}
+
 hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const int* tile_sim,
                            int total_tiles, hipStream_t st)
 {
@@ -439,7 +495,7 @@ hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const
 template <typename S>
 __global__ void k_init_feq(GridP g, BodyP b, const S* __restrict__ phi0,
                            const Win* __restrict__ win, int wslot, const double* __restrict__ u0,
-                           S* __restrict__ T)
+                           S* __restrict__ T, const double* __restrict__ drho0)
 {
     const long long N = (long long)g.nx * g.ny;
     const Rect w = window_of(win, wslot, g);
@@ -457,8 +513,13 @@ __global__ void k_init_feq(GridP g, BodyP b, const S* __restrict__ phi0,
             }
         }
         const double rs = b.present ? b.rho_s : g.rho_f;
-        const double rho = H * g.rho_f + (1.0 - H) * rs;  // Eq. (2_4_smooth_density)
-        const double dr = rho - g.rho_f;                 // Eq. (2_3_drho) with rho = rho_t
+        double rho = H * g.rho_f + (1.0 - H) * rs;  // Eq. (2_4_smooth_density)
+        double dr = rho - g.rho_f;                  // Eq. (2_3_drho) with rho = rho_t
+        if (drho0) {
+            // several solids: rho_f plus the normalised mixture excess
+            dr = drho0[(long long)j * g.pitch + i];
+            rho = g.rho_f + dr;
+        }
         const double ux = u0 ? u0[e] : 0.0, uy = u0 ? u0[N + e] : 0.0;
         const double usq = ux * ux + uy * uy;
         const long long n = (long long)j * g.pitch + i;
@@ -499,17 +560,18 @@ __global__ void k_inverse_stream(GridP g, const S* __restrict__ T, S* __restrict
 
 hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
                                    const void* phi0, const Win* win, int wslot,
-                                   const double* u0, void* tmp, void* A, hipStream_t st)
+                                   const double* u0, void* tmp, void* A, hipStream_t st,
+                                   const double* drho0)
 {
     const long long N = (long long)g.nx * g.ny;
     const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
     if (precision == 0) {
         k_init_feq<double><<<blocks, 256, 0, st>>>(g, b, (const double*)phi0, win, wslot, u0,
-                                                   (double*)tmp);
+                                                   (double*)tmp, drho0);
         k_inverse_stream<double><<<blocks, 256, 0, st>>>(g, (const double*)tmp, (double*)A);
     } else {
         k_init_feq<float><<<blocks, 256, 0, st>>>(g, b, (const float*)phi0, win, wslot, u0,
-                                                  (float*)tmp);
+                                                  (float*)tmp, drho0);
         k_inverse_stream<float><<<blocks, 256, 0, st>>>(g, (const float*)tmp, (float*)A);
     }
     return hipGetLastError();
@@ -521,10 +583,10 @@ template <typename S>
 __global__ void k_gather_macro(GridP g, const S* __restrict__ A, const double* __restrict__ fpx,
                                const double* __restrict__ fpy, const Win* __restrict__ win,
                                int wprev, double fpo_x, double fpo_y, double* rho_o,
-                               double* ux_o, double* uy_o, double* f9)
+                               double* ux_o, double* uy_o, double* f9, StampValid sv)
 {
     const long long N = (long long)g.nx * g.ny;
-    const Rect wp = window_of(win, wprev, g);
+    const Rect wr = window_of(win, wprev, g);
     const double wq[NQ] = {W0, W1, W1, W1, W1, W2, W2, W2, W2};
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N;
          e += (long long)gridDim.x * blockDim.x) {
@@ -539,7 +601,7 @@ __global__ void k_gather_macro(GridP g, const S* __restrict__ A, const double* _
         }
         const double rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
         double Fx = fpo_x, Fy = fpo_y;
-        if (wp.has(i, j)) {
+        if (sv.stamp ? sv.has(i, j) : wr.has(i, j)) {
             Fx = fpx[q.n];
             Fy = fpy[q.n];
         }
@@ -554,22 +616,22 @@ __global__ void k_gather_macro(GridP g, const S* __restrict__ A, const double* _
 hipError_t launch_gather_macro(const GridP& g, int precision, const void* A, const double* fpx,
                                const double* fpy, const Win* win, int wprev, double fpo_x,
                                double fpo_y, double* rho, double* ux, double* uy, double* f9,
-                               hipStream_t st)
+                               hipStream_t st, StampValid sv)
 {
     const long long N = (long long)g.nx * g.ny;
     const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
     if (precision == 0)
         k_gather_macro<double><<<blocks, 256, 0, st>>>(g, (const double*)A, fpx, fpy, win, wprev,
-                                                       fpo_x, fpo_y, rho, ux, uy, f9);
+                                                       fpo_x, fpo_y, rho, ux, uy, f9, sv);
     else
         k_gather_macro<float><<<blocks, 256, 0, st>>>(g, (const float*)A, fpx, fpy, win, wprev,
-                                                      fpo_x, fpo_y, rho, ux, uy, f9);
+                                                      fpo_x, fpo_y, rho, ux, uy, f9, sv);
     return hipGetLastError();
 }
 
 __global__ void k_read_force(GridP g, const double* __restrict__ fpx, const double* __restrict__ fpy,
                              const Win* __restrict__ win, int wprev, double fpo_x, double fpo_y,
-                             double* fx, double* fy)
+                             double* fx, double* fy, StampValid sv)
 {
     const long long N = (long long)g.nx * g.ny;
     const Rect wp = window_of(win, wprev, g);
@@ -577,7 +639,7 @@ __global__ void k_read_force(GridP g, const double* __restrict__ fpx, const doub
          e += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(e % g.nx), j = (int)(e / g.nx);
         const long long n = (long long)j * g.pitch + i;
-        const bool in = wp.has(i, j);
+        const bool in = sv.stamp ? sv.has(i, j) : wp.has(i, j);
         fx[e] = in ? fpx[n] : fpo_x;
         fy[e] = in ? fpy[n] : fpo_y;
     }
@@ -585,11 +647,11 @@ __global__ void k_read_force(GridP g, const double* __restrict__ fpx, const doub
 
 hipError_t launch_read_force(const GridP& g, const double* fpx, const double* fpy, const Win* win,
                              int wprev, double fpo_x, double fpo_y, double* fx, double* fy,
-                             hipStream_t st)
+                             hipStream_t st, StampValid sv)
 {
     const long long N = (long long)g.nx * g.ny;
     const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
-    k_read_force<<<blocks, 256, 0, st>>>(g, fpx, fpy, win, wprev, fpo_x, fpo_y, fx, fy);
+    k_read_force<<<blocks, 256, 0, st>>>(g, fpx, fpy, win, wprev, fpo_x, fpo_y, fx, fy, sv);
     return hipGetLastError();
 }
 

@@ -31,6 +31,61 @@ constexpr uint32_t STATE_VERSION = 1;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Window of each solid of a several-solid context (the same for all solids).
+struct MbGeom {
+    int nx, ny;        // window extents
+    int wx, wy;        // sub-window axes
+    int pp;
+    size_t pplane;
+    long long lcap;
+};
+
+MbGeom mb_geom(const lbrmt_grid_desc* d)
+{
+    const int W = d->body_window > 0 ? d->body_window : 128;
+    MbGeom m;
+    m.wx = d->periodic_x && d->nx % FB == 0 && d->nx >= W + 2 * PAD + 32;
+    m.wy = d->periodic_y && d->ny % FB == 0 && d->ny >= W + 2 * PAD + 32;
+    m.nx = m.wx ? W : d->nx;
+    m.ny = m.wy ? W : d->ny;
+    m.pp = (int)round_up((size_t)m.nx + 2 * PAD, 32);
+    m.pplane = (size_t)m.pp * (m.ny + 2 * PAD);
+    m.lcap = sub_cap_tiles(m.nx, m.ny);
+    return m;
+}
+
+// Per-solid block of a several-solid workspace.
+struct BodyLayout {
+    size_t off_X[2], off_Y[2], off_phi[2], off_tag, off_gcol, off_lists, off_lcount,
+        off_boxpart, off_ticket, off_win, total;
+};
+
+BodyLayout body_layout(const lbrmt_grid_desc* d, const MbGeom& m)
+{
+    BodyLayout B;
+    const size_t es = d->precision == LBRMT_FP64 ? 8 : 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = round_up(o + bytes, ALIGN);
+        return r;
+    };
+    for (int k = 0; k < 2; k++) {
+        B.off_X[k] = take(m.pplane * es);
+        B.off_Y[k] = take(m.pplane * es);
+        B.off_phi[k] = take(m.pplane * es);
+    }
+    B.off_tag = take(m.pplane);
+    B.off_gcol = take(m.pplane);
+    B.off_lists = take((size_t)m.lcap * NSUB * 4 * (size_t)(d->layers + 1));
+    B.off_lcount = take((size_t)(MAX_LAYERS + 1) * NSUB * LCOUNT_PAD * 4);
+    B.off_boxpart = take((size_t)std::max(BOX_BLOCKS, MB_BAND_BLOCKS) * 4 * 4);
+    B.off_ticket = take(4);
+    B.off_win = take(3 * sizeof(Win));
+    B.total = o;
+    return B;
+}
+
 struct Layout {
     int pitch, pp;
     size_t plane, pplane;
@@ -39,10 +94,15 @@ struct Layout {
         off_win, off_health, off_dpart, off_dout, off_gcol, off_lists, off_lcount, off_boxpart,
         off_ticket, total;
     size_t lat_bytes;
+    // several solids
+    int nbx, nby;
+    size_t off_stamp[2], off_mlist[2], off_mcount, off_dstep, off_mbtab, off_tabs, off_bsum,
+        off_bodies, body_bytes;
 };
 
-Layout make_layout(const lbrmt_grid_desc* d)
+Layout make_layout(const lbrmt_grid_desc* d, int max_solids = 1)
 {
+    const bool multi = max_solids > 1;
     Layout L;
     L.pitch = (int)round_up((size_t)d->nx, 64);
     L.pp = (int)round_up((size_t)d->nx + 2 * PAD, 32);
@@ -63,14 +123,17 @@ Layout make_layout(const lbrmt_grid_desc* d)
         L.off_fy[k] = take(L.plane * 8);
     }
     L.off_drho = take(L.plane * 8);
+    // the single solid's reference map (several solids: per-solid blocks)
+    const size_t rp = multi ? 0 : L.pplane;
     for (int k = 0; k < 2; k++) {
-        L.off_X[k] = take(L.pplane * L.rm_es);
-        L.off_Y[k] = take(L.pplane * L.rm_es);
-        L.off_phi[k] = take(L.pplane * L.rm_es);
+        L.off_X[k] = take(rp * L.rm_es);
+        L.off_Y[k] = take(rp * L.rm_es);
+        L.off_phi[k] = take(rp * L.rm_es);
     }
-    L.off_tag = take(L.pplane);
-    L.off_gcol = take(L.pplane);
-    L.off_lists = take((size_t)sub_cap((long long)L.pplane) * NSUB * 4 * (size_t)(d->layers + 1));
+    L.off_tag = take(rp);
+    L.off_gcol = take(rp);
+    L.off_lists = take(multi ? 0 : (size_t)sub_cap((long long)L.pplane) * NSUB * 4 *
+                                        (size_t)(d->layers + 1));
     L.off_lcount = take((size_t)(MAX_LAYERS + 1) * NSUB * LCOUNT_PAD * 4);
     L.off_boxpart = take((size_t)std::max(RELABEL_BLOCKS, BOX_BLOCKS) * 4 * 4);
     L.off_ticket = take(4);
@@ -78,6 +141,25 @@ Layout make_layout(const lbrmt_grid_desc* d)
     L.off_health = take(LBRMT_H_COUNT * sizeof(unsigned));
     L.off_dpart = take(diag_partial_doubles() * 8);
     L.off_dout = take(16 * 8);
+    L.nbx = (d->nx + FB - 1) / FB;
+    L.nby = (d->ny + FB - 1) / FB;
+    L.body_bytes = 0;
+    if (multi) {
+        const size_t nblk = (size_t)L.nbx * L.nby;
+        for (int k = 0; k < 2; k++) {
+            L.off_stamp[k] = take(nblk * 4);
+            L.off_mlist[k] = take(nblk * 4);
+        }
+        L.off_mcount = take(2 * 4);
+        L.off_dstep = take(8);
+        L.off_mbtab = take((size_t)max_solids * sizeof(MbBody));
+        L.off_tabs = take(7 * ((size_t)max_solids * (sizeof(AdvectArgs) + sizeof(LayersArgs) +
+                                                     sizeof(FitArgs) + sizeof(EdgesArgs)) +
+                               4 * ALIGN));
+        L.off_bsum = take((size_t)max_solids * 7 * 8);
+        L.body_bytes = body_layout(d, mb_geom(d)).total;
+        L.off_bodies = take((size_t)max_solids * L.body_bytes);
+    }
     L.total = o;
     return L;
 }
@@ -121,6 +203,18 @@ struct lbrmt_ctx {
     double t_ms[NKERN] = {0};
     long long t_n[NKERN] = {0};
     std::string err;
+    // several solids (max_solids > 1): one window per solid
+    bool multi = false;
+    MbGeom mg{};
+    BodyLayout BL{};
+    std::vector<MbBody> mbh;   // host copy of the solid table
+    MbBody* mbd = nullptr;     // device table
+    BatchTables mtab[7];       // chain argument tables, phases as for batches
+    int* stamp[2] = {nullptr, nullptr};
+    int* mlist[2] = {nullptr, nullptr};
+    int* mcount = nullptr;
+    long long* dstep = nullptr;
+    double* bsum = nullptr;
 };
 
 static int fail(lbrmt_ctx* c, const char* what, hipError_t e)
@@ -195,9 +289,45 @@ static int collect_timing(lbrmt_ctx* c)
 static double fpo_x(const lbrmt_ctx* c, long long n) { return n == 0 ? 0.0 : c->d.fext_x; }
 static double fpo_y(const lbrmt_ctx* c, long long n) { return n == 0 ? 0.0 : c->d.fext_y; }
 
+// several solids, step n on stream st: the chain of every solid (relabel
+// only), the force blocks and the combined forces, the lattice update
+static int enqueue_step_mb(lbrmt_ctx* c, long long n, hipStream_t st)
+{
+    const StepSlots s = slots_for(n);
+    const int p = n == 0 ? 6 : (int)(n % 6);
+    const int nb = c->nsolid;
+    const int prec = c->d.precision;
+    if (nb > 0) {
+        HIPCHK(c, launch_batch_band(prec, c->mtab[p], nb, c->d.layers, st, true, MB_DT_BLOCKS,
+                                    MB_FIT_BLOCKS, MB_BAND_BLOCKS));
+        HIPCHK(c, launch_mb_mark(c->g, c->mbd, nb, s.wcur, s.wnext, MB_BAND_BLOCKS,
+                                 c->stamp[s.cur], 0, c->mlist[s.cur], &c->mcount[s.cur],
+                                 c->L.nbx, c->bb.health, st, c->dstep));
+        HIPCHK(c, launch_mb_combine(c->g, prec, c->mbd, nb, s.nxt, s.wcur, c->mlist[s.cur],
+                                    &c->mcount[s.cur], &c->mcount[s.nxt], c->L.nbx,
+                                    c->Fx[s.cur], c->Fy[s.cur], c->drho, false, c->bb.health,
+                                    st));
+    }
+    HIPCHK(c, launch_lb_mb(c->g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt],
+                           c->Fx[s.nxt], c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho,
+                           StampValid{c->stamp[s.nxt], 0, c->L.nbx},
+                           StampValid{c->stamp[s.cur], 0, c->L.nbx}, fpo_x(c, n), fpo_y(c, n),
+                           c->bb.health, st, c->dstep));
+    HIPCHK(c, launch_mb_tick(c->dstep, st));
+    return LBRMT_OK;
+}
+
+// where F^{n-1} is held for reads of state n (several solids: the stamps)
+static StampValid prev_valid(const lbrmt_ctx* c)
+{
+    if (!c->multi) return StampValid{nullptr, 0, 0};
+    return StampValid{c->stamp[slots_for(c->step).nxt], (int)c->step, c->L.nbx};
+}
+
 // enqueue step n: band chain on `band`, LB on `main_s`
 static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
 {
+    if (c->multi) return enqueue_step_mb(c, n, main_s);
     const StepSlots s = slots_for(n);
     const GridP& g = c->g;
     const int prec = c->d.precision;
@@ -309,8 +439,9 @@ const char* lbrmt_last_error(const lbrmt_ctx* c) { return c ? c->err.c_str() : "
 
 int lbrmt_workspace_bytes(const lbrmt_grid_desc* d, int32_t max_solids, size_t* bytes)
 {
-    if (!desc_ok(d) || !bytes || max_solids < 0 || max_solids > 1) return LBRMT_EINVAL;
-    *bytes = make_layout(d).total;
+    if (!desc_ok(d) || !bytes || max_solids < 0 || max_solids > LBRMT_MAX_SOLIDS)
+        return LBRMT_EINVAL;
+    *bytes = make_layout(d, max_solids).total;
     return LBRMT_OK;
 }
 
@@ -318,9 +449,9 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
                        void* stream, lbrmt_ctx** out, bool member)
 {
     if (!desc_ok(d) || !out || !ws || max_solids < 0) return LBRMT_EINVAL;
-    if (max_solids > 1) return LBRMT_ECAPACITY;
+    if (max_solids > LBRMT_MAX_SOLIDS || (member && max_solids > 1)) return LBRMT_ECAPACITY;
     if ((uintptr_t)ws % ALIGN) return LBRMT_EWORKSPACE;
-    Layout L = make_layout(d);
+    Layout L = make_layout(d, max_solids);
     if (bytes < L.total) return LBRMT_EWORKSPACE;
     lbrmt_ctx* c = new lbrmt_ctx();
     c->d = *d;
@@ -353,6 +484,14 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
     g.det_rel = d->det_rel;
     g.detJ_min = d->detJ_min;
     g.rm32 = d->precision == LBRMT_FP64 ? 0 : 1;
+    g.ox = g.oy = 0;
+    g.wx = g.wy = 0;
+    g.lnx = g.nx;
+    g.lny = g.ny;
+    g.lpx = g.px;
+    g.lpy = g.py;
+    g.eta = d->eta;
+    g.lcap = sub_cap(g.pplane);
     c->body.present = 0;
     for (int k = 0; k < 2; k++) {
         c->lat[k] = c->ws + L.off_lat[k];
@@ -374,6 +513,32 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
     c->dpart = (double*)(c->ws + L.off_dpart);
     c->dout = (double*)(c->ws + L.off_dout);
     c->member = member;
+    if (max_solids > 1) {
+        c->multi = true;
+        c->mg = mb_geom(d);
+        c->BL = body_layout(d, c->mg);
+        for (int k = 0; k < 2; k++) {
+            c->stamp[k] = (int*)(c->ws + L.off_stamp[k]);
+            c->mlist[k] = (int*)(c->ws + L.off_mlist[k]);
+        }
+        c->mcount = (int*)(c->ws + L.off_mcount);
+        c->dstep = (long long*)(c->ws + L.off_dstep);
+        c->mbd = (MbBody*)(c->ws + L.off_mbtab);
+        c->bsum = (double*)(c->ws + L.off_bsum);
+        char* t = c->ws + L.off_tabs;
+        auto carve = [&](size_t bytes_) {
+            char* p_ = t;
+            t += round_up(bytes_, ALIGN);
+            return p_;
+        };
+        for (int p = 0; p < 7; p++) {
+            c->mtab[p].adv = (AdvectArgs*)carve(max_solids * sizeof(AdvectArgs));
+            c->mtab[p].lay = (LayersArgs*)carve(max_solids * sizeof(LayersArgs));
+            c->mtab[p].fit = (FitArgs*)carve(max_solids * sizeof(FitArgs));
+            c->mtab[p].edg = (EdgesArgs*)carve(max_solids * sizeof(EdgesArgs));
+            c->mtab[p].lb = nullptr;
+        }
+    }
     if (member) {
         // a batch member is stepped by its batch, on the batch's stream
         c->graph = false;
@@ -429,6 +594,75 @@ static double solid_extent(const lbrmt_solid_desc& s)
     return s.shape == 1 ? std::max(s.a, s.b) : s.a;
 }
 
+static BodyP body_of(const lbrmt_solid_desc& s)
+{
+    BodyP b{};
+    b.present = 1;
+    b.shape = s.shape;
+    b.cx = s.cx;
+    b.cy = s.cy;
+    b.R = s.a;
+    b.Rb = s.shape == 1 ? s.b : s.a;
+    b.ct = s.shape == 1 ? std::cos(s.theta) : 1.0;
+    b.st = s.shape == 1 ? std::sin(s.theta) : 0.0;
+    b.G = s.G;
+    b.rho_s = s.rho_s;
+    return b;
+}
+
+// solid k of a several-solid context: its window grid and buffers
+static MbBody mb_body(lbrmt_ctx* c, int k, const lbrmt_solid_desc& s)
+{
+    MbBody m{};
+    const MbGeom& G = c->mg;
+    GridP g = c->g;
+    g.nx = G.nx;
+    g.ny = G.ny;
+    g.pp = G.pp;
+    g.pplane = (long long)G.pplane;
+    g.px = G.wx ? 0 : c->g.px;
+    g.py = G.wy ? 0 : c->g.py;
+    g.wx = G.wx;
+    g.wy = G.wy;
+    g.ox = G.wx ? (int)std::floor(s.cx) - G.nx / 2 : 0;
+    g.oy = G.wy ? (int)std::floor(s.cy) - G.ny / 2 : 0;
+    g.lcap = G.lcap;
+    m.g = g;
+    m.b = body_of(s);
+    char* base = c->ws + c->L.off_bodies + (size_t)k * c->L.body_bytes;
+    for (int q = 0; q < 2; q++) {
+        m.X[q] = base + c->BL.off_X[q];
+        m.Y[q] = base + c->BL.off_Y[q];
+        m.phi[q] = base + c->BL.off_phi[q];
+    }
+    m.win = (Win*)(base + c->BL.off_win);
+    m.boxpart = (int*)(base + c->BL.off_boxpart);
+    m.reg = make_int4(0, -1, 0, -1);
+    return m;
+}
+
+// the chain buffers of solid k (health counters shared by the context)
+static BandBufs mb_bufs(const lbrmt_ctx* c, int k)
+{
+    BandBufs b{};
+    const MbBody& m = c->mbh[k];
+    char* base = c->ws + c->L.off_bodies + (size_t)k * c->L.body_bytes;
+    for (int q = 0; q < 2; q++) {
+        b.X[q] = m.X[q];
+        b.Y[q] = m.Y[q];
+        b.phi[q] = m.phi[q];
+    }
+    b.tag = (int8_t*)(base + c->BL.off_tag);
+    b.gcol = (int8_t*)(base + c->BL.off_gcol);
+    b.lists = (int*)(base + c->BL.off_lists);
+    b.lcount = (int*)(base + c->BL.off_lcount);
+    b.boxpart = m.boxpart;
+    b.ticket = (unsigned*)(base + c->BL.off_ticket);
+    b.win = m.win;
+    b.health = c->bb.health;
+    return b;
+}
+
 int lbrmt_add_solids(lbrmt_ctx* c, const lbrmt_solid_desc* s, int32_t n)
 {
     if (!c || (n > 0 && !s) || n < 0) return LBRMT_EINVAL;
@@ -437,21 +671,103 @@ int lbrmt_add_solids(lbrmt_ctx* c, const lbrmt_solid_desc* s, int32_t n)
     for (int k = 0; k < n; k++) {
         if (!solid_shape_ok(s[k]) || !(s[k].rho_s > 0.0) || !(s[k].G >= 0.0))
             return LBRMT_EINVAL;
+        // a solid and its zone must fit its window with a margin
+        if (c->multi && (c->mg.wx || c->mg.wy)) {
+            const double need = 2.0 * (std::ceil(solid_extent(s[k])) + c->d.layers + 4);
+            if ((c->mg.wx && need > c->mg.nx) || (c->mg.wy && need > c->mg.ny))
+                return LBRMT_ECAPACITY;
+        }
+    }
+    if (c->multi) {
+        for (int k = 0; k < n; k++) c->mbh.push_back(mb_body(c, c->nsolid + k, s[k]));
+        c->nsolid += n;
+        return LBRMT_OK;
     }
     if (n > 0) {
         c->solid = s[0];
         c->nsolid = 1;
-        c->body.present = 1;
-        c->body.shape = s[0].shape;
-        c->body.cx = s[0].cx;
-        c->body.cy = s[0].cy;
-        c->body.R = s[0].a;
-        c->body.Rb = s[0].shape == 1 ? s[0].b : s[0].a;
-        c->body.ct = s[0].shape == 1 ? std::cos(s[0].theta) : 1.0;
-        c->body.st = s[0].shape == 1 ? std::sin(s[0].theta) : 0.0;
-        c->body.G = s[0].G;
-        c->body.rho_s = s[0].rho_s;
+        c->body = body_of(s[0]);
     }
+    return LBRMT_OK;
+}
+
+// argument tables of the chain kernels of every solid for the seven phases
+// (n mod 6 for n >= 1, and n = 0), and the device solid table
+static int mb_tables(lbrmt_ctx* c)
+{
+    const int nb = c->nsolid;
+    if (nb == 0) return LBRMT_OK;
+    std::vector<AdvectArgs> adv(nb);
+    std::vector<LayersArgs> lay(nb);
+    std::vector<FitArgs> fit(nb);
+    std::vector<EdgesArgs> edg(nb);
+    for (int p = 0; p < 7; p++) {
+        const long long nstep = p == 6 ? 0 : (p == 0 ? 6 : p);
+        const StepSlots s = slots_for(nstep);
+        for (int k = 0; k < nb; k++) {
+            const BandBufs b = mb_bufs(c, k);
+            const GridP& g = c->mbh[k].g;
+            adv[k] = AdvectArgs{g, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt], b.X[s.cur],
+                                b.Y[s.cur], b.phi[s.cur], b.X[s.nxt], b.Y[s.nxt], b.tag, b.win,
+                                s.wprev, s.wcur, b.lists, b.lcount, b.health};
+            lay[k] = LayersArgs{g, b.win, s.wcur, b.tag, b.gcol, b.lists, b.lcount, b.health};
+            fit[k] = FitArgs{g, b.win, s.wcur, s.wprev, b.tag, b.lists, b.lcount, b.phi[s.cur],
+                             b.X[s.nxt], b.Y[s.nxt], b.health};
+            edg[k] = EdgesArgs{g, c->mbh[k].b, b.win, s.wcur, b.boxpart, b.X[s.nxt], b.Y[s.nxt],
+                               b.tag, b.phi[s.nxt], nullptr, nullptr, nullptr, b.lcount,
+                               b.health};
+        }
+        const BatchTables& T = c->mtab[p];
+        HIPCHK(c, hipMemcpyAsync(T.adv, adv.data(), nb * sizeof(AdvectArgs), hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(T.lay, lay.data(), nb * sizeof(LayersArgs), hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(T.fit, fit.data(), nb * sizeof(FitArgs), hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(T.edg, edg.data(), nb * sizeof(EdgesArgs), hipMemcpyHostToDevice, c->st));
+        // the host vectors are reused for the next phase: wait for the copies
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->mbd, c->mbh.data(), nb * sizeof(MbBody), hipMemcpyHostToDevice,
+                             c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return LBRMT_OK;
+}
+
+// several solids: every solid's initial map on its window (as for one solid),
+// then the density excess of the mixture, then f = f^eq
+static int init_mb(lbrmt_ctx* c, const double* d_u0)
+{
+    hipStream_t st = c->st;
+    const size_t nblk = (size_t)c->L.nbx * c->L.nby;
+    for (int k = 0; k < 2; k++) HIPCHK(c, hipMemsetAsync(c->stamp[k], 0, nblk * 4, st));
+    HIPCHK(c, hipMemsetAsync(c->mcount, 0, 2 * 4, st));
+    HIPCHK(c, hipMemsetAsync(c->dstep, 0, 8, st));
+    const int nb = c->nsolid;
+    for (int k = 0; k < nb; k++) {
+        const BandBufs b = mb_bufs(c, k);
+        const GridP& g = c->mbh[k].g;
+        const BodyP& bp = c->mbh[k].b;
+        HIPCHK(c, hipMemsetAsync(b.ticket, 0, 4, st));
+        HIPCHK(c, hipMemsetAsync(b.lcount, 0, (size_t)(MAX_LAYERS + 1) * NSUB * LCOUNT_PAD * 4, st));
+        for (int q = 0; q < 3; q++) HIPCHK(c, launch_win_reset(b.win, q, st));
+        HIPCHK(c, launch_init_solid_box(g, bp, b, 0, 2, st));
+        HIPCHK(c, launch_init_tags(g, bp, b, 0, st));
+        HIPCHK(c, launch_layers(g, b, 0, st));
+        HIPCHK(c, launch_init_fill(g, bp, b, 0, st));
+    }
+    int rc = mb_tables(c);
+    if (rc != LBRMT_OK) return rc;
+    if (nb > 0) {
+        // the blocks of the initial regions (stamp -1, which no step uses)
+        HIPCHK(c, launch_mb_mark(c->g, c->mbd, nb, 0, 0, 0, c->stamp[1], -1, c->mlist[1],
+                                 &c->mcount[1], c->L.nbx, c->bb.health, st));
+        HIPCHK(c, launch_mb_combine(c->g, c->d.precision, c->mbd, nb, 0, 0, c->mlist[1],
+                                    &c->mcount[1], &c->mcount[0], c->L.nbx, c->Fx[0], c->Fy[0],
+                                    c->drho, true, c->bb.health, st));
+    }
+    BodyP none{};
+    HIPCHK(c, launch_init_populations(c->g, c->d.precision, none, nullptr, c->bb.win, 0, d_u0,
+                                      c->lat[1], c->lat[0], st, c->drho));
+    c->step = 0;
+    c->inited = true;
     return LBRMT_OK;
 }
 
@@ -468,6 +784,13 @@ int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
     HIPCHK(c, hipMemsetAsync(c->drho, 0, c->L.plane * 8, st));
     HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, st));
     for (int k = 0; k < 3; k++) HIPCHK(c, launch_win_reset(c->bb.win, k, st));
+    if (c->gexec) {
+        // a graph captured for an earlier initialisation bakes the old solids in
+        HIPCHK(c, hipStreamSynchronize(st));
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (c->multi) return init_mb(c, d_u0);
     if (c->nsolid > 0) {
         // box of S^0 into the slots of "current" (0) and "previous" (2)
         HIPCHK(c, launch_init_solid_box(g, c->body, c->bb, 0, 2, st));
@@ -517,7 +840,7 @@ int lbrmt_read_macro(lbrmt_ctx* c, double* rho, double* ux, double* uy)
     const StepSlots s = slots_for(c->step);
     HIPCHK(c, launch_gather_macro(c->g, c->d.precision, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt],
                                   c->bb.win, s.wprev, fpo_x(c, c->step), fpo_y(c, c->step), rho,
-                                  ux, uy, nullptr, c->st));
+                                  ux, uy, nullptr, c->st, prev_valid(c)));
     return LBRMT_OK;
 }
 
@@ -528,7 +851,7 @@ int lbrmt_read_populations(lbrmt_ctx* c, double* f9)
     const StepSlots s = slots_for(c->step);
     HIPCHK(c, launch_gather_macro(c->g, c->d.precision, c->lat[s.cur], c->Fx[s.nxt], c->Fy[s.nxt],
                                   c->bb.win, s.wprev, fpo_x(c, c->step), fpo_y(c, c->step),
-                                  nullptr, nullptr, nullptr, f9, c->st));
+                                  nullptr, nullptr, nullptr, f9, c->st, prev_valid(c)));
     return LBRMT_OK;
 }
 
@@ -538,7 +861,8 @@ int lbrmt_read_force(lbrmt_ctx* c, double* fx, double* fy)
     if (!c->inited) return LBRMT_ESTATE;
     const StepSlots s = slots_for(c->step);
     HIPCHK(c, launch_read_force(c->g, c->Fx[s.nxt], c->Fy[s.nxt], c->bb.win, s.wprev,
-                                fpo_x(c, c->step), fpo_y(c, c->step), fx, fy, c->st));
+                                fpo_x(c, c->step), fpo_y(c, c->step), fx, fy, c->st,
+                                prev_valid(c)));
     return LBRMT_OK;
 }
 
@@ -547,6 +871,11 @@ int lbrmt_read_refmap(lbrmt_ctx* c, int32_t solid, double* X, double* Y, double*
     if (!c || solid < 0 || solid >= c->nsolid) return LBRMT_EINVAL;
     if (!c->inited) return LBRMT_ESTATE;
     const StepSlots s = slots_for(c->step);
+    if (c->multi) {
+        HIPCHK(c, launch_mb_read_refmap(c->g, c->d.precision, c->mbd, solid, s.cur, s.wprev, X, Y,
+                                        phi, c->st));
+        return LBRMT_OK;
+    }
     HIPCHK(c, launch_read_refmap(c->g, c->body, c->bb, s.cur, s.wprev, X, Y, phi, c->st));
     return LBRMT_OK;
 }
@@ -555,6 +884,10 @@ int lbrmt_read_stress(lbrmt_ctx* c, double* sxx, double* sxy, double* syy)
 {
     if (!c || !sxx || !sxy || !syy) return LBRMT_EINVAL;
     if (!c->inited) return LBRMT_ESTATE;
+    if (c->multi) {
+        c->err = "lbrmt_read_stress: not available with several solids";
+        return LBRMT_ESTATE;
+    }
     const StepSlots s = slots_for(c->step);
     HIPCHK(c, launch_read_stress(c->g, c->body, c->bb, s.cur, s.wprev, sxx, sxy, syy, c->st));
     return LBRMT_OK;
@@ -565,14 +898,37 @@ int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
     if (!c || !out) return LBRMT_EINVAL;
     if (!c->inited) return LBRMT_ESTATE;
     const StepSlots s = slots_for(c->step);
-    HIPCHK(c, launch_diag(c->g, c->d.precision, c->body, c->lat[s.cur], c->Fx[s.nxt],
-                          c->Fy[s.nxt], c->bb.win, s.wprev, fpo_x(c, c->step), fpo_y(c, c->step),
-                          c->bb, s.cur, c->dpart, c->dout, c->st));
+    BodyP none{};
+    HIPCHK(c, launch_diag(c->g, c->d.precision, c->multi ? none : c->body, c->lat[s.cur],
+                          c->Fx[s.nxt], c->Fy[s.nxt], c->bb.win, s.wprev, fpo_x(c, c->step),
+                          fpo_y(c, c->step), c->bb, s.cur, c->dpart, c->dout, c->st,
+                          prev_valid(c)));
     double h[16];
     unsigned hc[LBRMT_H_COUNT];
+    std::vector<double> bs;
     HIPCHK(c, hipMemcpyAsync(h, c->dout, 11 * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipMemcpyAsync(hc, c->bb.health, sizeof hc, hipMemcpyDeviceToHost, c->st));
+    if (c->multi && c->nsolid > 0) {
+        bs.resize((size_t)c->nsolid * 7);
+        HIPCHK(c, launch_mb_diag(c->d.precision, c->mbd, c->nsolid, s.cur, s.wprev, c->bsum,
+                                 c->st));
+        HIPCHK(c, hipMemcpyAsync(bs.data(), c->bsum, bs.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->st));
+    }
     HIPCHK(c, hipStreamSynchronize(c->st));
+    if (c->multi) {
+        // the solid terms summed over the solids, in index order
+        double t[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < c->nsolid; k++)
+            for (int q = 0; q < 7; q++) t[q] += bs[(size_t)k * 7 + q];
+        h[3] = t[0];
+        h[4] = t[1];
+        h[5] = t[2];
+        h[6] = t[3];
+        h[7] = t[4];
+        h[8] = t[5];
+        h[9] = t[6];
+    }
     out->step = c->step;
     out->mass = h[0];
     out->mom_x = h[1];
@@ -588,6 +944,38 @@ int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
     if (hc[LBRMT_H_NONFINITE] || hc[LBRMT_H_DETJ_SOLID] || hc[LBRMT_H_EXTRAP_FAIL] ||
         hc[LBRMT_H_LIST_OVERFLOW] || !std::isfinite(h[0]))
         return LBRMT_EUNSTABLE;
+    return LBRMT_OK;
+}
+
+int lbrmt_diag_solid(lbrmt_ctx* c, int32_t solid, double* out)
+{
+    if (!c || !out || solid < 0 || solid >= c->nsolid) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    if (!c->multi) {
+        lbrmt_diag_t d;
+        const int rc = lbrmt_diag(c, &d);
+        if (rc != LBRMT_OK && rc != LBRMT_EUNSTABLE) return rc;
+        out[0] = d.centroid_x;
+        out[1] = d.centroid_y;
+        out[2] = d.disp_x;
+        out[3] = d.disp_y;
+        out[4] = d.n_solid;
+        out[5] = d.n_band;
+        return LBRMT_OK;
+    }
+    const StepSlots s = slots_for(c->step);
+    std::vector<double> bs((size_t)c->nsolid * 7);
+    HIPCHK(c, launch_mb_diag(c->d.precision, c->mbd, c->nsolid, s.cur, s.wprev, c->bsum, c->st));
+    HIPCHK(c, hipMemcpyAsync(bs.data(), c->bsum, bs.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    const double* a = &bs[(size_t)solid * 7];
+    out[0] = a[0] > 0 ? a[1] / a[0] : NAN;
+    out[1] = a[0] > 0 ? a[2] / a[0] : NAN;
+    out[2] = a[0] > 0 ? a[3] / a[0] : NAN;
+    out[3] = a[0] > 0 ? a[4] / a[0] : NAN;
+    out[4] = a[5];
+    out[5] = a[6];
     return LBRMT_OK;
 }
 
@@ -631,6 +1019,10 @@ int lbrmt_save_state(lbrmt_ctx* c, void* buf)
 {
     if (!c || !buf) return LBRMT_EINVAL;
     if (!c->inited) return LBRMT_ESTATE;
+    if (c->multi) {
+        c->err = "checkpoints are not available with several solids";
+        return LBRMT_ESTATE;
+    }
     size_t off[8];
     state_layout(c, off);
     char* b = (char*)buf;
@@ -654,7 +1046,7 @@ int lbrmt_save_state(lbrmt_ctx* c, void* buf)
 
 int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
 {
-    if (c && c->member) return LBRMT_ESTATE;
+    if (c && (c->member || c->multi)) return LBRMT_ESTATE;
     if (!c || !buf) return LBRMT_EINVAL;
     size_t off[8];
     state_layout(c, off);
@@ -797,7 +1189,7 @@ int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
 int lbrmt_band_nodes(lbrmt_ctx* c, int64_t* band_nodes, int64_t* window_nodes)
 {
     if (!c || !band_nodes || !window_nodes) return LBRMT_EINVAL;
-    if (!c->inited) return LBRMT_ESTATE;
+    if (!c->inited || c->multi) return LBRMT_ESTATE;
     Win w[3];
     HIPCHK(c, hipMemcpyAsync(w, c->bb.win, sizeof w, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -844,7 +1236,7 @@ int lbrmt_band_nodes(lbrmt_ctx* c, int64_t* band_nodes, int64_t* window_nodes)
 int lbrmt_autotune(lbrmt_ctx* c, int32_t reps, int32_t* best_variant, double* best_ms)
 {
     if (!c || reps < 1) return LBRMT_EINVAL;
-    if (!c->inited || c->member) return LBRMT_ESTATE;
+    if (!c->inited || c->member || c->multi) return LBRMT_ESTATE;
     const StepSlots s = slots_for(c->step);
     const double ox = fpo_x(c, c->step), oy = fpo_y(c, c->step);
     hipEvent_t a = nullptr, b = nullptr;

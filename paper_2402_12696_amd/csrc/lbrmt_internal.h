@@ -24,7 +24,17 @@ constexpr int DT_BLOCKS = 2048;       // distance transform
 constexpr int FIT_BLOCKS = 256;       // one extrapolation layer
 constexpr int FIT_LANES = 8;          // lanes sharing one extrapolation target
 constexpr int LCOUNT_PAD = 32;        // layer counters 128 B apart
-constexpr int NSUB = 8;               // sub-lists per layer (distance-transform block mod 8)         // lanes sharing one extrapolation target
+constexpr int NSUB = 8;               // sub-lists per layer (distance-transform block mod 8)
+
+// Several solids: the lattice is cut into force blocks of FB x FB nodes;
+// a block holds valid force planes at step n when its stamp equals n + 1.
+constexpr int FB_LOG = 4;
+constexpr int FB = 1 << FB_LOG;
+constexpr int MB_DT_BLOCKS = 16;      // per solid (a multiple of NSUB)
+constexpr int MB_FIT_BLOCKS = 8;
+constexpr int MB_BAND_BLOCKS = 16;    // relabel: partial boxes per solid
+constexpr int MB_MAX_PER_BLOCK = 32;  // solids overlapping one force block
+constexpr int MB_COMBINE_BLOCKS = 2048;
 
 // Axis-aligned box of the interior solid nodes of one body (i0 > i1: empty).
 // The working window of a step is this box dilated by `layers` nodes.
@@ -47,6 +57,18 @@ struct GridP {
     double rho_f, eps;
     double det_rel, detJ_min;
     int rm32;             // reference map stored in FP32 as displacement xi - x
+    // the lattice seen from a reference-map grid.  A solid of a several-solid
+    // context keeps its map on a window of its own: along an axis flagged in
+    // wx / wy the window is the sub-range [o, o + n) of a periodic lattice
+    // axis (window node i is lattice column (i + ox) mod lnx, at position
+    // i + ox + 1/2, and the window axis itself is not periodic); along other
+    // axes the window is the whole lattice axis (o = 0).
+    int ox, oy;
+    int wx, wy;
+    int lnx, lny;         // lattice extents
+    int lpx, lpy;         // lattice periodic axes
+    double eta;           // contact factor of Eq. (3_6_collision_stress)
+    long long lcap;       // capacity of one layer sub-list (entries)
 };
 
 // det(grad xi) below which the FP32 reference-map path inverts grad xi in FP64
@@ -148,6 +170,18 @@ __device__ inline void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1
         if (dst1) *dst1 = r;
     }
     __syncthreads();
+}
+
+// A zone (box dilated by `layers`) that would cross a periodic seam of a
+// whole-axis grid, or leave a solid's sub-window, is not representable by the
+// working window: counted in health[6] (called by one thread).
+__device__ __forceinline__ void check_zone(const GridP& g, const Win& w, unsigned* health)
+{
+    if (w.i0 > w.i1) return;
+    const int L = g.layers;
+    if (((g.px || g.wx) && (w.i0 - L < 0 || w.i1 + L > g.nx - 1)) ||
+        ((g.py || g.wy) && (w.j0 - L < 0 || w.j1 + L > g.ny - 1)))
+        atomicAdd(&health[6], 1u);
 }
 
 // Arguments of the step kernels for one member of a batch (device tables,
@@ -312,13 +346,50 @@ __host__ __device__ __forceinline__ long long sub_cap(long long pplane)
     return pplane / NSUB + (long long)DT_BLOCKS * 256 / NSUB;
 }
 
+// Tighter capacity for a grid of nx x ny interior nodes when the block count
+// of every distance transform is a multiple of NSUB: sub-list s then takes
+// the tiles t = s mod NSUB of the window, whose DTX x DTY tiles cover at most
+// (nx + 4 + DTX - 1) (ny + 4 + DTY - 1) nodes, plus one tile.
+__host__ __device__ __forceinline__ long long sub_cap_tiles(int nx, int ny)
+{
+    const long long cover = (long long)(nx + 4 + 31) * (ny + 4 + 15);
+    return cover / NSUB + 32 * 16;
+}
+
+// Force-plane validity by block stamps (several solids): same interface as
+// Rect.
+struct StampValid {
+    const int* stamp;
+    int val, nbx;
+    __device__ __forceinline__ bool has(int i, int j) const
+    {
+        return stamp[(j >> FB_LOG) * nbx + (i >> FB_LOG)] == val;
+    }
+};
+
+// One solid of a several-solid context (device table, one entry per solid).
+struct MbBody {
+    GridP g;              // the solid's window
+    BodyP b;
+    void *X[2], *Y[2], *phi[2];
+    Win* win;
+    int* boxpart;
+    int4 reg;             // force region of the current step, lattice nodes
+                          // [x, x + dx] x [y, y + dy] (x, y wrapped), dx < 0: none
+};
+
 
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns hipGetLastError().
 
 // lattice Boltzmann (k_lb.hip)
+// relabel_only: the force kernel relabels and writes partial boxes only
+// (several solids: the forces come from launch_mb_combine); blocks per member
+// of the distance transform, one extrapolation layer and the force kernel
 hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
-                             hipStream_t st);
+                             hipStream_t st, bool relabel_only = false,
+                             int dt_blocks = BATCH_DT_BLOCKS, int fit_blocks = BATCH_FIT_BLOCKS,
+                             int band_blocks = BATCH_BAND_BLOCKS);
 hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const int* tile_sim,
                            int total_tiles, hipStream_t st);
 // PART 0 / 2 launches with nbox > 0 also reduce the force pass's partial
@@ -331,16 +402,28 @@ hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, 
                      Win* winw = nullptr, int wnext = 0);
 int lb_variant_count();
 void lb_variant_tile(int v, int* tx, int* ty);
+// drho0 (several solids): the density excess of every node, instead of the
+// single solid's level set
 hipError_t launch_init_populations(const GridP& g, int precision, const BodyP& b,
                                    const void* phi0, const Win* win, int wslot,
-                                   const double* u0, void* tmp, void* A, hipStream_t st);
+                                   const double* u0, void* tmp, void* A, hipStream_t st,
+                                   const double* drho0 = nullptr);
+// sv.stamp != nullptr: the stamps, not the window, tell where F^{n-1} is held
 hipError_t launch_gather_macro(const GridP& g, int precision, const void* A, const double* fpx,
                                const double* fpy, const Win* win, int wprev, double fpo_x,
                                double fpo_y, double* rho, double* ux, double* uy, double* f9,
-                               hipStream_t st);
+                               hipStream_t st, StampValid sv = StampValid{nullptr, 0, 0});
 hipError_t launch_read_force(const GridP& g, const double* fpx, const double* fpy, const Win* win,
                              int wprev, double fpo_x, double fpo_y, double* fx, double* fy,
-                             hipStream_t st);
+                             hipStream_t st, StampValid sv = StampValid{nullptr, 0, 0});
+// lattice update of a several-solid context: every tile, force planes where
+// the stamps say so
+// (the stamp values are *dstep for vp and *dstep + 1 for vc)
+hipError_t launch_lb_mb(const GridP& g, int precision, int variant, const void* A, void* B,
+                        const double* fpx, const double* fpy, const double* fcx,
+                        const double* fcy, const double* drho, StampValid vp, StampValid vc,
+                        double fpo_x, double fpo_y, unsigned* health, hipStream_t st,
+                        const long long* dstep);
 hipError_t launch_poke(const GridP& g, int precision, void* A, long long node, double value,
                        hipStream_t st);
 
@@ -365,12 +448,40 @@ hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb
 hipError_t launch_read_refmap(const GridP& g, const BodyP& b, const BandBufs& bb, int buf, int wvalid, double* X,
                               double* Y, double* phi, hipStream_t st);
 
+// several solids (k_band.hip).  mark: per solid, reduce the relabel's partial
+// boxes into ring slot wnext, flag a window that comes too close to its
+// border, and stamp (value sval) the force blocks of its region of slot wcur,
+// listing each newly stamped block once (list / count).
+// dstep != nullptr: the stamp value is *dstep + 1 (the device step counter,
+// so that replayed graphs stamp with the running step)
+hipError_t launch_mb_mark(const GridP& lg, MbBody* bodies, int nb, int wcur, int wnext,
+                          int nbox, int* stamp, int sval, int* list, int* count, int nbx,
+                          unsigned* health, hipStream_t st, const long long* dstep = nullptr);
+// advances the device step counter
+hipError_t launch_mb_tick(long long* dstep, hipStream_t st);
+// combine: over the listed blocks, the global stress of every half-edge
+// (blend of the solids normalised by their summed fraction, plus contact),
+// its divergence, buoyancy and the fluid force into fx, fy; the density
+// excess into drho.  Zeroes *count_clear (the next step's list counter).
+// drho_only: the density excess only (initialisation).
+hipError_t launch_mb_combine(const GridP& lg, int precision, const MbBody* bodies, int nb,
+                             int buf, int wcur, const int* list, const int* count,
+                             int* count_clear, int nbx, double* fx, double* fy, double* drho,
+                             bool drho_only, unsigned* health, hipStream_t st);
+hipError_t launch_mb_read_refmap(const GridP& lg, int precision, const MbBody* bodies, int k,
+                                 int buf, int wvalid, double* X, double* Y, double* phi,
+                                 hipStream_t st);
+// per solid: [sum lambda, sum lambda x, sum lambda y, sum lambda (x - X),
+// sum lambda (y - Y), solid nodes, nodes with a map] into out + 7 k
+hipError_t launch_mb_diag(int precision, const MbBody* bodies, int nb, int buf, int wvalid,
+                          double* out, hipStream_t st);
+
 // reductions (k_diag.hip); partial: scratch of diag_partial_doubles() doubles
 int diag_blocks();
 size_t diag_partial_doubles();
 hipError_t launch_diag(const GridP& g, int precision, const BodyP& b, const void* A,
                        const double* fpx, const double* fpy, const Win* win, int wprev,
                        double fpo_x, double fpo_y, const BandBufs& bb, int buf, double* partial,
-                       double* out, hipStream_t st);
+                       double* out, hipStream_t st, StampValid sv = StampValid{nullptr, 0, 0});
 
 }  // namespace lbrmt

@@ -36,7 +36,8 @@ class lbrmt_grid_desc(ctypes.Structure):
         ("rho_f", ctypes.c_double), ("eps", ctypes.c_double),
         ("layers", ctypes.c_int32), ("r_max", ctypes.c_int32),
         ("det_rel", ctypes.c_double), ("detJ_min", ctypes.c_double),
-        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("body_window", ctypes.c_int32),
+        ("eta", ctypes.c_double),
     ]
 
 
@@ -106,6 +107,7 @@ def lib():
             "lbrmt_read_refmap": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
             "lbrmt_read_stress": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
             "lbrmt_diag": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_diag_t)]),
+            "lbrmt_diag_solid": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
             "lbrmt_state_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
             "lbrmt_save_state": (ctypes.c_int, [_vp, _vp]),
             "lbrmt_load_state": (ctypes.c_int, [_vp, _vp]),
@@ -181,11 +183,20 @@ def _stream():
 
 def make_grid_desc(nx, ny, tau, lid_ux=0.0, periodic_x=False, periodic_y=False,
                    gravity=(0.0, 0.0), fext=(0.0, 0.0), rho_f=1.0, eps=1.5, layers=11, r_max=8,
-                   det_rel=1e-8, detJ_min=1e-12, precision="f64", **_ignored):
+                   det_rel=1e-8, detJ_min=1e-12, precision="f64", body_window=0, eta=1.0,
+                   **_ignored):
     prec = {"f64": LBRMT_FP64, "f32": LBRMT_FP32}[precision]
     return lbrmt_grid_desc(nx, ny, int(periodic_x), int(periodic_y), tau, lid_ux,
                            gravity[0], gravity[1], fext[0], fext[1], rho_f, eps, layers, r_max,
-                           det_rel, detJ_min, prec, 0)
+                           det_rel, detJ_min, prec, int(body_window), float(eta))
+
+
+def _solid_list(cfg):
+    if cfg.get("solid") is not None and cfg.get("solids") is not None:
+        raise ValueError("give either solid or solids")
+    if cfg.get("solids") is not None:
+        return list(cfg["solids"])
+    return [cfg["solid"]] if cfg.get("solid") else []
 
 
 def make_solid_desc(cx, cy, R, G, rho_s, shape="disc", b=None, theta=0.0, **_ignored):
@@ -265,6 +276,13 @@ def lbrmt_diag(ctx, raise_unstable=True):
     d["health"] = dict(zip(HEALTH_NAMES, list(out.health)))
     d["status"] = rc
     return d
+
+
+def lbrmt_diag_solid(ctx, solid):
+    out = (ctypes.c_double * 6)()
+    _check(lib().lbrmt_diag_solid(ctx, int(solid), out), "lbrmt_diag_solid", ctx)
+    keys = ["centroid_x", "centroid_y", "disp_x", "disp_y", "n_solid", "n_band"]
+    return dict(zip(keys, list(out)))
 
 
 def lbrmt_state_bytes(ctx):
@@ -404,8 +422,8 @@ class Sim:
 
     Keywords are those of ``workloads.make`` (nx, ny, tau, lid_ux, periodic_x,
     periodic_y, gravity, fext, rho_f, eps, layers, r_max, det_rel, detJ_min,
-    solid={cx, cy, R, G, rho_s[, shape="ellipse", b, theta]}) plus
-    precision="f64"|"f32".
+    solid={cx, cy, R, G, rho_s[, shape="ellipse", b, theta]}, or solids=[...]
+    for several solids with eta and body_window) plus precision="f64"|"f32".
     """
 
     owner = True
@@ -419,7 +437,7 @@ class Sim:
         self.device = torch.device(device)
         self.cfg = dict(cfg)
         self.nx, self.ny = cfg["nx"], cfg["ny"]
-        self.nsolid = 1 if cfg.get("solid") else 0
+        self.nsolid = len(_solid_list(cfg))
         self.ctx = ctx
         self.owner = False
         return self
@@ -434,15 +452,17 @@ class Sim:
         self.cfg = dict(cfg)
         self.nx, self.ny = cfg["nx"], cfg["ny"]
         self.desc = make_grid_desc(**cfg)
-        solid = cfg.get("solid")
-        self.nsolid = 1 if solid else 0
-        nbytes = lbrmt_workspace_bytes(self.desc, self.nsolid)
+        solids = _solid_list(cfg)
+        self.nsolid = len(solids)
+        # a list of solids takes the several-solid context, even for one
+        cap = max(2, self.nsolid) if cfg.get("solids") is not None else self.nsolid
+        nbytes = lbrmt_workspace_bytes(self.desc, cap)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
         self._ws = self.workspace[off:off + nbytes]
-        self.ctx = lbrmt_create(self.desc, self.nsolid, self._ws, nbytes)
-        if solid:
-            lbrmt_add_solids(self.ctx, [make_solid_desc(**solid)])
+        self.ctx = lbrmt_create(self.desc, cap, self._ws, nbytes)
+        if solids:
+            lbrmt_add_solids(self.ctx, [make_solid_desc(**b) for b in solids])
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -504,6 +524,10 @@ class Sim:
 
     def diag(self, raise_unstable=True):
         return lbrmt_diag(self.ctx, raise_unstable)
+
+    def diag_solid(self, solid):
+        """One solid's centroid, mean displacement and node counts."""
+        return lbrmt_diag_solid(self.ctx, solid)
 
     def save_state(self):
         buf = self.torch.empty(lbrmt_state_bytes(self.ctx), dtype=self.torch.uint8,

@@ -85,7 +85,7 @@ def test_create_rejects_bad_workspace_without_gpu():
                           ctypes.byref(ctx)) == B.LBRMT_EWORKSPACE
     assert L.lbrmt_create(ctypes.byref(d), 1, ctypes.c_void_p(258), 1 << 40, None,
                           ctypes.byref(ctx)) == B.LBRMT_EWORKSPACE
-    assert L.lbrmt_create(ctypes.byref(d), 2, ctypes.c_void_p(256), 1 << 40, None,
+    assert L.lbrmt_create(ctypes.byref(d), 4097, ctypes.c_void_p(256), 1 << 40, None,
                           ctypes.byref(ctx)) == B.LBRMT_ECAPACITY
     assert L.lbrmt_step(None, 1) == B.LBRMT_EINVAL
 
@@ -119,3 +119,19 @@ def test_validate_solid_shapes():
             B.lbrmt_validate(d, [bad])
     with pytest.raises(ValueError):
         B.make_solid_desc(32, 40, 12, 0.01, 1.0, shape="square")
+
+
+def test_several_solid_workspace():
+    # per-solid windows: the workspace grows linearly in the solid count, by a
+    # window's worth along periodic axes (not a whole grid)
+    d = B.make_grid_desc(nx=4096, ny=4096, tau=0.7, periodic_x=True, periodic_y=True,
+                         precision="f32")
+    one = B.lbrmt_workspace_bytes(d, 1)
+    w2, w400 = B.lbrmt_workspace_bytes(d, 2), B.lbrmt_workspace_bytes(d, 400)
+    per = (w400 - w2) / 398
+    assert per < 4e6 and w400 < one + 2e9
+    # walled axes: every window is the whole grid
+    dw = B.make_grid_desc(nx=256, ny=256, tau=0.7)
+    assert B.lbrmt_workspace_bytes(dw, 3) - B.lbrmt_workspace_bytes(dw, 2) > 256 * 256 * 8 * 6
+    with pytest.raises(B.LBRMTError):
+        B.lbrmt_workspace_bytes(d, 4097)
