@@ -873,6 +873,21 @@ __global__ __launch_bounds__(256) void kb_layer_fit(const FitArgs* __restrict__ 
                       (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
 }
 
+// Every layer of one solid in one block (several solids: a solid's layers
+// are short, so one block per solid runs them in order, separated by block
+// barriers, instead of one launch per layer over all solids).  The barrier
+// makes a layer's fitted values visible to the next layer's block.
+template <typename T>
+__global__ __launch_bounds__(1024) void kb_fit_layers(const FitArgs* __restrict__ args, int layers)
+{
+    const FitArgs& a = args[blockIdx.y];
+    for (int l = 1; l <= layers; l++) {
+        layer_fit_body<T>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
+                          (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+        __syncthreads();
+    }
+}
+
 hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
                               hipStream_t st)
 {
@@ -1027,6 +1042,9 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
     __shared__ C ey[FTY + 1][FTX][3];
     const Rect V = window_of(win, wvalid, g);
     int bi0 = 0x3fffffff, bi1 = -0x3fffffff, bj0 = 0x3fffffff, bj1 = -0x3fffffff;
+    // MODE 2: also the box of the nodes with phi < eps (where the solid
+    // fraction is positive), partials after the solid box's
+    int ei0 = 0x3fffffff, ei1 = -0x3fffffff, ej0 = 0x3fffffff, ej1 = -0x3fffffff;
     Rect Rg;
     if (whole_grid) {
         Rg.i0 = 0; Rg.i1 = g.nx - 1; Rg.j0 = 0; Rg.j1 = g.ny - 1;
@@ -1071,6 +1089,12 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
                     bi1 = max(bi1, i);
                     bj0 = min(bj0, j);
                     bj1 = max(bj1, j);
+                }
+                if (MODE == 2 && p < C(g.eps)) {
+                    ei0 = min(ei0, i);
+                    ei1 = max(ei1, i);
+                    ej0 = min(ej0, j);
+                    ej1 = max(ej1, j);
                 }
             } else if (V.has(i, j)) {
                 phi1[k] = C(INFINITY);
@@ -1152,6 +1176,12 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
                 const double p = relabel_phi<C>(g, b, tag[k], X[k], Y[k], i, j);
                 if (p < INFINITY) {
                     phi1[k] = store_phi<C>(p);
+                    if (MODE == 2 && store_phi<C>(p) < C(g.eps)) {
+                        ei0 = min(ei0, i);
+                        ei1 = max(ei1, i);
+                        ej0 = min(ej0, j);
+                        ej1 = max(ej1, j);
+                    }
                 } else {
                     phi1[k] = C(INFINITY);
                     X[k] = C(NAN);
@@ -1160,6 +1190,7 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
             }
         }
         block_box(bi0, bi1, bj0, bj1, boxpart + 4 * blockIdx.x);
+        if (MODE == 2) block_box(ei0, ei1, ej0, ej1, boxpart + 4 * (gridDim.x + blockIdx.x));
     }
 }
 
@@ -1287,12 +1318,11 @@ __device__ __forceinline__ int win_row(const GridP& g, int r)
     return d >= g.lny - PAD ? d - g.lny : d;
 }
 
-// the working window of ring slot `slot` as lattice nodes {x, dx, y, dy}:
-// columns x .. x + dx (x wrapped, the range may run over a periodic seam),
-// rows likewise; dx < 0 or dy < 0: empty
-__device__ int4 mb_region(const GridP& g, const Win* win, int slot)
+// rectangle V of a solid's window as lattice nodes {x, dx, y, dy}: columns
+// x .. x + dx (x wrapped, the range may run over a periodic seam), rows
+// likewise; dx < 0 or dy < 0: empty
+__device__ int4 mb_region(const GridP& g, const Rect& V)
 {
-    const Rect V = window_of(win, slot, g);
     int4 r = make_int4(0, -1, 0, -1);
     if (!V.ok) return r;
     if (g.wx) {
@@ -1327,12 +1357,32 @@ __global__ __launch_bounds__(256) void k_mb_mark(GridP lg, MbBody* bodies, int w
 {
     MbBody& B = bodies[blockIdx.x];
     if (dstep) sval = (int)(*dstep + 1);
-    if (nbox > 0) reduce_boxes(B.boxpart, nbox, &B.win[wnext], nullptr);
+    __shared__ Win feps;
+    if (nbox > 0) {
+        reduce_boxes(B.boxpart, nbox, &B.win[wnext], nullptr);
+        reduce_boxes(B.boxpart + 4 * nbox, nbox, &feps, nullptr);
+    }
     __shared__ int4 reg;
     if (threadIdx.x == 0) {
         const GridP& g = B.g;
-        if (nbox > 0) check_zone(g, B.win[wnext], health);
-        reg = mb_region(g, B.win, wcur);
+        Rect R;
+        if (nbox > 0) {
+            check_zone(g, B.win[wnext], health);
+            // the force region of this step: the nodes with phi < eps and
+            // their neighbours (elsewhere every solid fraction is zero on the
+            // node and its edges, and the force is the uniform one), inside
+            // the working window
+            const Win e = feps;
+            const Rect V = window_of(B.win, wcur, g);
+            R.i0 = max(e.i0 - 1, V.i0);
+            R.i1 = min(e.i1 + 1, V.i1);
+            R.j0 = max(e.j0 - 1, V.j0);
+            R.j1 = min(e.j1 + 1, V.j1);
+            R.ok = V.ok && e.i0 <= e.i1 && R.i0 <= R.i1 && R.j0 <= R.j1;
+        } else {
+            R = window_of(B.win, wcur, g);
+        }
+        reg = mb_region(g, R);
         B.reg = reg;
     }
     __syncthreads();
@@ -1716,16 +1766,22 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
                              int band_blocks)
 {
     const dim3 gb(band_blocks, nsim), gd(dt_blocks, nsim), gf(fit_blocks, nsim);
+    // fit_blocks == 0: every layer of a member in one block of 1024 threads
+    const dim3 g1(1, nsim);
     if (precision == 0) {
         if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv);
-        for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
+        if (fit_blocks == 0) kb_fit_layers<double><<<g1, 1024, 0, st>>>(t.fit, layers);
+        else
+            for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
         if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg);
         else kb_force<0, double><<<gb, 256, 0, st>>>(t.edg);
     } else {
         if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv);
-        for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
+        if (fit_blocks == 0) kb_fit_layers<float><<<g1, 1024, 0, st>>>(t.fit, layers);
+        else
+            for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
         if (relabel_only) kb_force<2, float><<<gb, 256, 0, st>>>(t.edg);
         else kb_force<0, float><<<gb, 256, 0, st>>>(t.edg);
     }

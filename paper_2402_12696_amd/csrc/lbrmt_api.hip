@@ -299,7 +299,7 @@ static int enqueue_step_mb(lbrmt_ctx* c, long long n, hipStream_t st)
     const int prec = c->d.precision;
     if (nb > 0) {
         HIPCHK(c, launch_batch_band(prec, c->mtab[p], nb, c->d.layers, st, true, MB_DT_BLOCKS,
-                                    MB_FIT_BLOCKS, MB_BAND_BLOCKS));
+                                    0, MB_BAND_BLOCKS));
         HIPCHK(c, launch_mb_mark(c->g, c->mbd, nb, s.wcur, s.wnext, MB_BAND_BLOCKS,
                                  c->stamp[s.cur], 0, c->mlist[s.cur], &c->mcount[s.cur],
                                  c->L.nbx, c->bb.health, st, c->dstep));

@@ -31,8 +31,7 @@ constexpr int NSUB = 8;               // sub-lists per layer (distance-transform
 constexpr int FB_LOG = 4;
 constexpr int FB = 1 << FB_LOG;
 constexpr int MB_DT_BLOCKS = 16;      // per solid (a multiple of NSUB)
-constexpr int MB_FIT_BLOCKS = 8;
-constexpr int MB_BAND_BLOCKS = 16;    // relabel: partial boxes per solid
+constexpr int MB_BAND_BLOCKS = 16;    // relabel: two partial boxes per block
 constexpr int MB_MAX_PER_BLOCK = 32;  // solids overlapping one force block
 constexpr int MB_COMBINE_BLOCKS = 2048;
 
@@ -375,7 +374,8 @@ struct MbBody {
     Win* win;
     int* boxpart;
     int4 reg;             // force region of the current step, lattice nodes
-                          // [x, x + dx] x [y, y + dy] (x, y wrapped), dx < 0: none
+                          // [x, x + dx] x [y, y + dy] (x, y wrapped), dx < 0: none:
+                          // the nodes with phi < eps and their neighbours
 };
 
 
@@ -385,7 +385,8 @@ struct MbBody {
 // lattice Boltzmann (k_lb.hip)
 // relabel_only: the force kernel relabels and writes partial boxes only
 // (several solids: the forces come from launch_mb_combine); blocks per member
-// of the distance transform, one extrapolation layer and the force kernel
+// of the distance transform, one extrapolation layer (0: all layers of a
+// member in one block) and the force kernel
 hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
                              hipStream_t st, bool relabel_only = false,
                              int dt_blocks = BATCH_DT_BLOCKS, int fit_blocks = BATCH_FIT_BLOCKS,
