@@ -157,6 +157,29 @@ def run_ensemble(precision, steps, seq_steps=120, seq_warmup=12):
     return out
 
 
+def run_suspension(precision, steps, warmup=24):
+    """The seeded 4096^2 periodic suspension of 400 soft discs and ellipses
+    (several-solid path with contact): whole-step time after `warmup` steps."""
+    import torch
+    import workloads
+    from paper_2402_12696_amd import Sim
+    cfg = workloads.suspension()
+    sim = Sim(device="cuda:0", precision=precision, **cfg).init()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    nodes = cfg["nx"] * cfg["ny"]
+    d = sim.diag(raise_unstable=False)
+    sim.close()
+    return {"workload": cfg["name"] + " (seed 240212696)", "solids": len(cfg["solids"]),
+            "precision": precision, "steps": steps, "ms_per_step": ms,
+            "mlups": nodes / (ms * 1e-3) / 1e6,
+            "health_flags": {k: v for k, v in d["health"].items() if v}}
+
+
 def cpu_baseline(cfg, seconds=15.0):
     from oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -192,6 +215,12 @@ def main():
                     help="skip the 96-member ensemble (batched vs sequential)")
     ap.add_argument("--batch-steps", type=int, default=600,
                     help="steps of the ensemble (its stiffest members blow up after ~700)")
+    ap.add_argument("--no-suspension", action="store_true",
+                    help="skip the 4096^2 suspension of 400 solids (several-solid path)")
+    ap.add_argument("--suspension-steps", type=int, default=400)
+    ap.add_argument("--suspension-only", action="store_true",
+                    help="run only the suspension (in --precision) and print its record "
+                         "(for profiling; not the benchmark line)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain elementwise copy (FP32 negation) reading and "
                          "writing this many bytes: the reference dispatch that scales HBM "
@@ -201,6 +230,10 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.suspension_only:
+        print(json.dumps(run_suspension(args.precision, args.suspension_steps)), flush=True)
+        return
 
     if args.copy_bytes > 0:
         import torch
@@ -248,6 +281,9 @@ def main():
                         "lb_bulk_avg_ms": kt32["lb_bulk"][0]}
     if not args.no_batch:
         extra["batched"] = run_ensemble("f32", args.batch_steps)
+    if not args.no_suspension:
+        extra["suspension"] = {p: run_suspension(p, args.suspension_steps)
+                               for p in ("f32", "f64")}
     line = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
