@@ -131,6 +131,7 @@ typedef struct {
     double max_u;            /* max |u|                                          */
     double n_solid;          /* nodes with phi < 0                               */
     double n_band;           /* nodes holding a reference map                    */
+    double lambda_sum;       /* sum lambda (the centroid's denominator)          */
     uint32_t health[LBRMT_H_COUNT];
 } lbrmt_diag_t;
 
@@ -215,6 +216,37 @@ int lbrmt_debug_poke(lbrmt_ctx* ctx, int32_t field, int64_t index, double value)
  * solid placement; EINVAL for unusable input, OK with flags otherwise. */
 int lbrmt_validate(const lbrmt_grid_desc* desc, const lbrmt_solid_desc* solids, int32_t n,
                    lbrmt_validation_t* out);
+
+/* Discrete adjoint (NEXT-3 of the build plan; FP64 contexts with one solid,
+ * ESTATE otherwise).  The reverse of one step n needs what the forward step
+ * used and made: lbrmt_step_snapshot advances the context one step (eager
+ * launches) and copies that into a caller device buffer of
+ * lbrmt_snapshot_bytes bytes (the state n lattice, F^{n-1}, F^n, xi^n, phi^n,
+ * xi^{n+1}, phi^{n+1}, the layer tags and the windows).
+ *
+ * Adjoint state: a caller device buffer of lbrmt_adjoint_bytes bytes holding
+ * dL/df (natural populations), dL/dxi, dL/dphi, dL/dF and the accumulated
+ * dL/dG, dL/d(lid speed).  lbrmt_adjoint_zero clears it; lbrmt_adjoint_loss
+ * adds the gradient of L_s = (|c - c*|^2 + |d - d*|^2) w of one state s,
+ * with c = sum lambda x / sum lambda and d = sum lambda (x - xi) / sum
+ * lambda, lambda = 1 - H(phi) (the centroid and mean displacement of
+ * lbrmt_diag); coef = {c_x, c_y, d_x, d_y, dL/dc_x, dL/dc_y, dL/dd_x,
+ * dL/dd_y} (host), with which = 0 for the snapshot's state n, 1 for its
+ * state n + 1.  lbrmt_adjoint_step takes the adjoint of state n + 1 to state
+ * n (snapshots are consumed last step first); lbrmt_adjoint_init turns the
+ * adjoint of state 0 (after the step of snapshot 0) into dL/du_0 (device
+ * float64 [2][ny][nx]) and returns {dL/dG, dL/dU} in host_GU.  Discrete
+ * decisions (solid set, layers, scan windows, upwind sides, fallbacks) are
+ * those the forward step took. */
+int lbrmt_snapshot_bytes(const lbrmt_ctx* ctx, size_t* bytes);
+int lbrmt_step_snapshot(lbrmt_ctx* ctx, void* d_snap);
+int lbrmt_adjoint_bytes(const lbrmt_ctx* ctx, size_t* bytes);
+int lbrmt_adjoint_zero(lbrmt_ctx* ctx, void* d_adj);
+int lbrmt_adjoint_loss(lbrmt_ctx* ctx, void* d_adj, const void* d_snap, int32_t which,
+                       const double* host_coef8);
+int lbrmt_adjoint_step(lbrmt_ctx* ctx, void* d_adj, const void* d_snap);
+int lbrmt_adjoint_init(lbrmt_ctx* ctx, void* d_adj, const void* d_snap0, double* d_u0bar,
+                       double* host_GU);
 
 /* Average device time (ms) per launch of each step kernel, measured with HIP
  * events on the stream each kernel runs on.  Enabling timing makes lbrmt_step

@@ -28,8 +28,9 @@ PER_FILE = {
     "k_lb.hip": ["-ffp-contract=on"],
     "k_band.hip": ["-ffp-contract=off"],
     "k_diag.hip": ["-ffp-contract=off"],
+    "k_adjoint.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["k_lb.hip", "k_band.hip", "k_diag.hip", "lbrmt_api.hip"]
+SOURCES = ["k_lb.hip", "k_band.hip", "k_diag.hip", "k_adjoint.hip", "lbrmt_api.hip"]
 
 
 def _run(cmd):

@@ -215,6 +215,7 @@ struct lbrmt_ctx {
     int* mcount = nullptr;
     long long* dstep = nullptr;
     double* bsum = nullptr;
+    int adj_flip = 0;  // which half of an adjoint buffer holds state n + 1
 };
 
 static int fail(lbrmt_ctx* c, const char* what, hipError_t e)
@@ -939,6 +940,7 @@ int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
     out->disp_y = h[3] > 0 ? h[7] / h[3] : NAN;
     out->n_solid = h[8];
     out->n_band = h[9];
+    out->lambda_sum = h[3];
     out->max_u = h[10];
     for (int k = 0; k < LBRMT_H_COUNT; k++) out->health[k] = hc[k];
     if (hc[LBRMT_H_NONFINITE] || hc[LBRMT_H_DETJ_SOLID] || hc[LBRMT_H_EXTRAP_FAIL] ||
@@ -976,6 +978,232 @@ int lbrmt_diag_solid(lbrmt_ctx* c, int32_t solid, double* out)
     out[3] = a[0] > 0 ? a[4] / a[0] : NAN;
     out[4] = a[5];
     out[5] = a[6];
+    return LBRMT_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+
+namespace {
+
+struct SnapLayout {
+    size_t A, fpx, fpy, fcx, fcy, X0, Y0, P0, X1, Y1, P1, tag, win, fpo, total;
+};
+
+SnapLayout snap_layout(const lbrmt_ctx* c)
+{
+    SnapLayout S;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o = round_up(o + b, ALIGN);
+        return r;
+    };
+    const size_t pl = c->L.plane * 8, rp = c->L.pplane * 8;
+    S.A = take(c->L.lat_bytes);
+    S.fpx = take(pl);
+    S.fpy = take(pl);
+    S.fcx = take(pl);
+    S.fcy = take(pl);
+    S.X0 = take(rp);
+    S.Y0 = take(rp);
+    S.P0 = take(rp);
+    S.X1 = take(rp);
+    S.Y1 = take(rp);
+    S.P1 = take(rp);
+    S.tag = take(c->L.pplane);
+    S.win = take(2 * sizeof(Win));
+    S.fpo = take(2 * 8);
+    S.total = o;
+    return S;
+}
+
+AdjSnap adj_snap(const lbrmt_ctx* c, const void* snap)
+{
+    const SnapLayout S = snap_layout(c);
+    const char* b = (const char*)snap;
+    AdjSnap a;
+    a.A = (const double*)(b + S.A);
+    a.fpx = (const double*)(b + S.fpx);
+    a.fpy = (const double*)(b + S.fpy);
+    a.fcx = (const double*)(b + S.fcx);
+    a.fcy = (const double*)(b + S.fcy);
+    a.X0 = (const double*)(b + S.X0);
+    a.Y0 = (const double*)(b + S.Y0);
+    a.P0 = (const double*)(b + S.P0);
+    a.X1 = (const double*)(b + S.X1);
+    a.Y1 = (const double*)(b + S.Y1);
+    a.P1 = (const double*)(b + S.P1);
+    a.tag = (const int8_t*)(b + S.tag);
+    a.win = (const Win*)(b + S.win);
+    a.fpo = (const double*)(b + S.fpo);
+    return a;
+}
+
+struct AdjLayout {
+    size_t fb[2], x[2], y[2], p[2], Fx[2], Fy[2], acc, total;
+};
+
+AdjLayout adj_layout(const lbrmt_ctx* c)
+{
+    AdjLayout A;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o = round_up(o + b, ALIGN);
+        return r;
+    };
+    const size_t N = (size_t)c->d.nx * c->d.ny, rp = c->L.pplane * 8;
+    for (int k = 0; k < 2; k++) {
+        A.fb[k] = take(NQ * N * 8);
+        A.x[k] = take(rp);
+        A.y[k] = take(rp);
+        A.p[k] = take(rp);
+        A.Fx[k] = take(N * 8);
+        A.Fy[k] = take(N * 8);
+    }
+    A.acc = take(2 * 8);
+    A.total = o;
+    return A;
+}
+
+AdjBufs adj_bufs(const lbrmt_ctx* c, void* adj)
+{
+    const AdjLayout L = adj_layout(c);
+    char* b = (char*)adj;
+    const int f = c->adj_flip, h = 1 - f;
+    AdjBufs a;
+    a.fb_in = (const double*)(b + L.fb[f]);
+    a.fb_out = (double*)(b + L.fb[h]);
+    a.xbar1 = (double*)(b + L.x[f]);
+    a.ybar1 = (double*)(b + L.y[f]);
+    a.pbar1 = (double*)(b + L.p[f]);
+    a.xbar0 = (double*)(b + L.x[h]);
+    a.ybar0 = (double*)(b + L.y[h]);
+    a.pbar0 = (double*)(b + L.p[h]);
+    a.Fcbar_x = (double*)(b + L.Fx[f]);
+    a.Fcbar_y = (double*)(b + L.Fy[f]);
+    a.Fpbar_x = (double*)(b + L.Fx[h]);
+    a.Fpbar_y = (double*)(b + L.Fy[h]);
+    a.acc = (double*)(b + L.acc);
+    return a;
+}
+
+bool adj_ok(const lbrmt_ctx* c)
+{
+    return c && !c->multi && !c->member && c->d.precision == LBRMT_FP64 && c->nsolid <= 1;
+}
+
+}  // namespace
+
+int lbrmt_snapshot_bytes(const lbrmt_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return LBRMT_EINVAL;
+    if (!adj_ok(c)) return LBRMT_ESTATE;
+    *bytes = snap_layout(c).total;
+    return LBRMT_OK;
+}
+
+int lbrmt_step_snapshot(lbrmt_ctx* c, void* snap)
+{
+    if (!c || !snap) return LBRMT_EINVAL;
+    if (!c->inited || !adj_ok(c)) return LBRMT_ESTATE;
+    const long long n = c->step;
+    const StepSlots s = slots_for(n);
+    // eager launches; with the chain on the internal stream the step ends
+    // joined into the context stream, so the copies below follow all of it
+    int rc = enqueue_step(c, n, c->st);
+    if (rc != LBRMT_OK) return rc;
+    c->step = n + 1;
+    const SnapLayout S = snap_layout(c);
+    char* b = (char*)snap;
+    const hipMemcpyKind D2D = hipMemcpyDeviceToDevice;
+    const size_t pl = c->L.plane * 8, rp = c->L.pplane * 8;
+    hipStream_t st = c->st;
+    HIPCHK(c, hipMemcpyAsync(b + S.A, c->lat[s.cur], c->L.lat_bytes, D2D, st));
+    HIPCHK(c, hipMemcpyAsync(b + S.fpx, c->Fx[s.nxt], pl, D2D, st));
+    HIPCHK(c, hipMemcpyAsync(b + S.fpy, c->Fy[s.nxt], pl, D2D, st));
+    HIPCHK(c, hipMemcpyAsync(b + S.fcx, c->Fx[s.cur], pl, D2D, st));
+    HIPCHK(c, hipMemcpyAsync(b + S.fcy, c->Fy[s.cur], pl, D2D, st));
+    if (c->nsolid > 0) {
+        HIPCHK(c, hipMemcpyAsync(b + S.X0, c->bb.X[s.cur], rp, D2D, st));
+        HIPCHK(c, hipMemcpyAsync(b + S.Y0, c->bb.Y[s.cur], rp, D2D, st));
+        HIPCHK(c, hipMemcpyAsync(b + S.P0, c->bb.phi[s.cur], rp, D2D, st));
+        HIPCHK(c, hipMemcpyAsync(b + S.X1, c->bb.X[s.nxt], rp, D2D, st));
+        HIPCHK(c, hipMemcpyAsync(b + S.Y1, c->bb.Y[s.nxt], rp, D2D, st));
+        HIPCHK(c, hipMemcpyAsync(b + S.P1, c->bb.phi[s.nxt], rp, D2D, st));
+        HIPCHK(c, hipMemcpyAsync(b + S.tag, c->bb.tag, c->L.pplane, D2D, st));
+    }
+    HIPCHK(c, hipMemcpyAsync(b + S.win, c->bb.win + s.wprev, sizeof(Win), D2D, st));
+    HIPCHK(c, hipMemcpyAsync(b + S.win + sizeof(Win), c->bb.win + s.wcur, sizeof(Win), D2D, st));
+    HIPCHK(c, launch_set2((double*)(b + S.fpo), fpo_x(c, n), fpo_y(c, n), st));
+    return LBRMT_OK;
+}
+
+int lbrmt_adjoint_bytes(const lbrmt_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return LBRMT_EINVAL;
+    if (!adj_ok(c)) return LBRMT_ESTATE;
+    *bytes = adj_layout(c).total;
+    return LBRMT_OK;
+}
+
+int lbrmt_adjoint_zero(lbrmt_ctx* c, void* adj)
+{
+    if (!c || !adj) return LBRMT_EINVAL;
+    if (!adj_ok(c)) return LBRMT_ESTATE;
+    HIPCHK(c, hipMemsetAsync(adj, 0, adj_layout(c).total, c->st));
+    c->adj_flip = 0;
+    return LBRMT_OK;
+}
+
+int lbrmt_adjoint_loss(lbrmt_ctx* c, void* adj, const void* snap, int32_t which,
+                       const double* coef)
+{
+    if (!c || !adj || !snap || !coef || (which != 0 && which != 1)) return LBRMT_EINVAL;
+    if (!adj_ok(c)) return LBRMT_ESTATE;
+    LossCoef lc;
+    lc.c[0] = coef[0];
+    lc.c[1] = coef[1];
+    lc.d[0] = coef[2];
+    lc.d[1] = coef[3];
+    lc.gc[0] = coef[4];
+    lc.gc[1] = coef[5];
+    lc.gd[0] = coef[6];
+    lc.gd[1] = coef[7];
+    HIPCHK(c, launch_adjoint_loss(c->g, c->body, adj_snap(c, snap), adj_bufs(c, adj), which, lc,
+                                  c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_adjoint_step(lbrmt_ctx* c, void* adj, const void* snap)
+{
+    if (!c || !adj || !snap) return LBRMT_EINVAL;
+    if (!adj_ok(c)) return LBRMT_ESTATE;
+    HIPCHK(c, launch_adjoint_step(c->g, c->body, adj_snap(c, snap), adj_bufs(c, adj), c->st));
+    // state n becomes the next step's state n + 1; the spent half is cleared
+    c->adj_flip = 1 - c->adj_flip;
+    const AdjLayout L = adj_layout(c);
+    const int h = 1 - c->adj_flip;
+    char* b = (char*)adj;
+    const size_t rp = c->L.pplane * 8;
+    HIPCHK(c, hipMemsetAsync(b + L.x[h], 0, rp, c->st));
+    HIPCHK(c, hipMemsetAsync(b + L.y[h], 0, rp, c->st));
+    HIPCHK(c, hipMemsetAsync(b + L.p[h], 0, rp, c->st));
+    return LBRMT_OK;
+}
+
+int lbrmt_adjoint_init(lbrmt_ctx* c, void* adj, const void* snap0, double* u0bar,
+                       double* host_GU)
+{
+    if (!c || !adj || !snap0) return LBRMT_EINVAL;
+    if (!adj_ok(c)) return LBRMT_ESTATE;
+    const AdjBufs a = adj_bufs(c, adj);
+    if (u0bar) HIPCHK(c, launch_adjoint_init(c->g, c->body, adj_snap(c, snap0), a, u0bar, c->st));
+    if (host_GU) {
+        HIPCHK(c, hipMemcpyAsync(host_GU, a.acc, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
     return LBRMT_OK;
 }
 

@@ -379,6 +379,43 @@ struct MbBody {
 };
 
 
+// ---- adjoint (k_adjoint.hip; FP64, one solid)
+
+// One forward step n as the adjoint reads it (a snapshot taken right after
+// the step): window slot 0 is the ring slot wprev of step n (validity of
+// xi^n, phi^n, F^{n-1}), slot 1 the slot wcur (validity of xi^{n+1},
+// phi^{n+1}, F^n and the layers).
+struct AdjSnap {
+    const double* A;             // pull-stored lattice of state n
+    const double *fpx, *fpy;     // F^{n-1}
+    const double *fcx, *fcy;     // F^n
+    const double *X0, *Y0, *P0;  // xi^n, phi^n (padded grid)
+    const double *X1, *Y1, *P1;  // xi^{n+1}, phi^{n+1}
+    const int8_t* tag;           // solid / layer tags of step n
+    const Win* win;              // [0] = wprev, [1] = wcur
+    const double* fpo;           // F^{n-1} outside the window (x, y)
+};
+
+// Adjoint fields of one reverse step: *1 belong to state n+1 (read), *0 to
+// state n (written); fb_in = dL/df^{n+1}, fb_out = dL/df^n (natural
+// populations, [9][ny][nx]); Fcbar = dL/dF^n, Fpbar = dL/dF^{n-1}
+// ([ny][nx]); acc = {dL/dG, dL/dU_lid}.
+struct AdjBufs {
+    const double* fb_in;
+    double* fb_out;
+    double *xbar1, *ybar1, *pbar1;
+    double *xbar0, *ybar0, *pbar0;
+    double *Fcbar_x, *Fcbar_y;
+    double *Fpbar_x, *Fpbar_y;
+    double* acc;
+};
+
+// loss coefficients of one state: centroid c, mean displacement d, and
+// gc = dL/dc / sum lambda, gd = dL/dd / sum lambda
+struct LossCoef {
+    double c[2], d[2], gc[2], gd[2];
+};
+
 // ---------------------------------------------------------------- launchers
 // Every launcher enqueues on `st` and returns hipGetLastError().
 
@@ -476,6 +513,18 @@ hipError_t launch_mb_read_refmap(const GridP& lg, int precision, const MbBody* b
 // sum lambda (y - Y), solid nodes, nodes with a map] into out + 7 k
 hipError_t launch_mb_diag(int precision, const MbBody* bodies, int nb, int buf, int wvalid,
                           double* out, hipStream_t st);
+
+// adjoint (k_adjoint.hip): one reverse step (lattice, force, relabel, the
+// layers from last to first, advection); the loss of one state (which = 0:
+// the step's input state, 1: its output); the initial velocity
+hipError_t launch_adjoint_step(const GridP& g, const BodyP& b, const AdjSnap& s,
+                               const AdjBufs& a, hipStream_t st);
+hipError_t launch_adjoint_loss(const GridP& g, const BodyP& b, const AdjSnap& s,
+                               const AdjBufs& a, int which, const LossCoef& c, hipStream_t st);
+hipError_t launch_adjoint_init(const GridP& g, const BodyP& b, const AdjSnap& s,
+                               const AdjBufs& a, double* u0bar, hipStream_t st);
+// dst[0] = x, dst[1] = y (device, stream-ordered)
+hipError_t launch_set2(double* dst, double x, double y, hipStream_t st);
 
 // reductions (k_diag.hip); partial: scratch of diag_partial_doubles() doubles
 int diag_blocks();

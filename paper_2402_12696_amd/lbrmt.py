@@ -57,6 +57,7 @@ class lbrmt_diag_t(ctypes.Structure):
         ("centroid_x", ctypes.c_double), ("centroid_y", ctypes.c_double),
         ("disp_x", ctypes.c_double), ("disp_y", ctypes.c_double),
         ("max_u", ctypes.c_double), ("n_solid", ctypes.c_double), ("n_band", ctypes.c_double),
+        ("lambda_sum", ctypes.c_double),
         ("health", ctypes.c_uint32 * 8),
     ]
 
@@ -108,6 +109,13 @@ def lib():
             "lbrmt_read_stress": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
             "lbrmt_diag": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_diag_t)]),
             "lbrmt_diag_solid": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
+            "lbrmt_snapshot_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+            "lbrmt_step_snapshot": (ctypes.c_int, [_vp, _vp]),
+            "lbrmt_adjoint_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+            "lbrmt_adjoint_zero": (ctypes.c_int, [_vp, _vp]),
+            "lbrmt_adjoint_loss": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp]),
+            "lbrmt_adjoint_step": (ctypes.c_int, [_vp, _vp, _vp]),
+            "lbrmt_adjoint_init": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
             "lbrmt_state_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
             "lbrmt_save_state": (ctypes.c_int, [_vp, _vp]),
             "lbrmt_load_state": (ctypes.c_int, [_vp, _vp]),
@@ -283,6 +291,43 @@ def lbrmt_diag_solid(ctx, solid):
     _check(lib().lbrmt_diag_solid(ctx, int(solid), out), "lbrmt_diag_solid", ctx)
     keys = ["centroid_x", "centroid_y", "disp_x", "disp_y", "n_solid", "n_band"]
     return dict(zip(keys, list(out)))
+
+
+def lbrmt_snapshot_bytes(ctx):
+    out = ctypes.c_size_t(0)
+    _check(lib().lbrmt_snapshot_bytes(ctx, ctypes.byref(out)), "lbrmt_snapshot_bytes", ctx)
+    return out.value
+
+
+def lbrmt_step_snapshot(ctx, snap):
+    _check(lib().lbrmt_step_snapshot(ctx, _ptr(snap)), "lbrmt_step_snapshot", ctx)
+
+
+def lbrmt_adjoint_bytes(ctx):
+    out = ctypes.c_size_t(0)
+    _check(lib().lbrmt_adjoint_bytes(ctx, ctypes.byref(out)), "lbrmt_adjoint_bytes", ctx)
+    return out.value
+
+
+def lbrmt_adjoint_zero(ctx, adj):
+    _check(lib().lbrmt_adjoint_zero(ctx, _ptr(adj)), "lbrmt_adjoint_zero", ctx)
+
+
+def lbrmt_adjoint_loss(ctx, adj, snap, which, coef):
+    c = (ctypes.c_double * 8)(*[float(v) for v in coef])
+    _check(lib().lbrmt_adjoint_loss(ctx, _ptr(adj), _ptr(snap), int(which), c),
+           "lbrmt_adjoint_loss", ctx)
+
+
+def lbrmt_adjoint_step(ctx, adj, snap):
+    _check(lib().lbrmt_adjoint_step(ctx, _ptr(adj), _ptr(snap)), "lbrmt_adjoint_step", ctx)
+
+
+def lbrmt_adjoint_init(ctx, adj, snap0, u0bar):
+    gu = (ctypes.c_double * 2)()
+    _check(lib().lbrmt_adjoint_init(ctx, _ptr(adj), _ptr(snap0), _ptr(u0bar), gu),
+           "lbrmt_adjoint_init", ctx)
+    return gu[0], gu[1]
 
 
 def lbrmt_state_bytes(ctx):

@@ -1,0 +1,146 @@
+"""The discrete adjoint of the coupled step (FP64, one solid) against central
+finite differences.
+
+Loss: L = (1/T) sum_{n=1..T} |c^n - c*^n|^2 + |d^n - d*^n|^2, c the solid's
+centroid and d its mean displacement (lambda-weighted, lambda = 1 - H(phi)),
+against a target trajectory made with G* = 0.008; gradients with respect to
+G, the lid speed U and the initial velocity field u_0 (directional
+derivatives along seeded random directions).  The adjoint follows every
+discrete decision of the forward step, so it is the exact derivative of the
+discrete map wherever the perturbed runs take the same decisions; the steps h
+are chosen where the central differences themselves are accurate (they
+converge onto the adjoint as h shrinks until rounding takes over: dG at
+T = 3 agrees to 7e-10 with h = 1e-4, a u_0 direction at T = 5 to 1e-9 with
+h = 1e-6; dL/dU is small, so its difference quotient is noise-limited at
+~3e-4).  The reference differences come from the GPU forward and, as the
+independent check, from the CPU oracle's forward.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+CFG = workloads.make(nx=48, ny=48, tau=0.8, lid_ux=0.08,
+                     solid=dict(cx=24.0, cy=28.0, R=9.0, G=0.01, rho_s=1.0))
+G0, U0 = 0.01, 0.08
+
+
+def _u0():
+    return np.random.default_rng(5).normal(0.0, 1e-3, size=(2, 48, 48))
+
+
+def _target(T):
+    from paper_2402_12696_amd import adjoint as AD
+    return AD.trajectory(CFG, 0.008, U0, T)
+
+
+def _adjoint(T, every=3, u0=None):
+    from paper_2402_12696_amd import adjoint as AD
+    tr = AD.Trajectory(CFG, G0, U0, _u0() if u0 is None else u0, T, _target(T), every=every)
+    gG, gU, gu0 = tr.backward()
+    out = (tr.loss, gG, gU, gu0.cpu().numpy())
+    tr.close()
+    return out
+
+
+def _gpu_loss(T, G, U, u0, target):
+    from paper_2402_12696_amd import adjoint as AD
+    t = AD.Trajectory(CFG, G, U, u0, T, target, every=T)
+    out = t.loss
+    t.close()
+    return out
+
+
+def _oracle_loss(T, G, U, u0, target):
+    cfg = dict(CFG, lid_ux=U, solid=dict(CFG["solid"], G=G))
+    o = Oracle(**cfg).init(u0)
+    acc = 0.0
+    for n in range(T):
+        o.step(1)
+        d = o.diag()
+        e = np.array([d["centroid_x"], d["centroid_y"], d["disp_x"], d["disp_y"]]) - target[n]
+        acc += float(np.sum(e * e))
+    return acc / T
+
+
+@pytest.mark.parametrize("loss_fn", [_gpu_loss, _oracle_loss], ids=["gpu_fd", "oracle_fd"])
+def test_gradient_wrt_shear_modulus(loss_fn):
+    T, h = 3, 1e-4
+    _, gG, _, _ = _adjoint(T)
+    u0, tgt = _u0(), _target(T)
+    fd = (loss_fn(T, G0 + h, U0, u0, tgt) - loss_fn(T, G0 - h, U0, u0, tgt)) / (2 * h)
+    print("dL/dG adjoint", gG, "central difference", fd)
+    assert abs(gG - fd) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("loss_fn", [_gpu_loss, _oracle_loss], ids=["gpu_fd", "oracle_fd"])
+def test_gradient_wrt_initial_velocity(loss_fn):
+    T, h = 5, 1e-6
+    _, _, _, gu0 = _adjoint(T)
+    u0, tgt = _u0(), _target(T)
+    rng = np.random.default_rng(17)
+    for k in range(3):
+        v = rng.normal(0.0, 1.0, size=u0.shape)
+        fd = (loss_fn(T, G0, U0, u0 + h * v, tgt) - loss_fn(T, G0, U0, u0 - h * v, tgt)) / (2 * h)
+        ad = float(np.sum(gu0 * v))
+        print("direction", k, "adjoint", ad, "central difference", fd)
+        assert abs(ad - fd) <= 1e-6 * abs(fd)
+
+
+def test_gradient_wrt_lid_speed():
+    T, h = 20, 1e-5
+    _, _, gU, _ = _adjoint(T)
+    u0, tgt = _u0(), _target(T)
+    fd = (_gpu_loss(T, G0, U0 + h, u0, tgt) - _gpu_loss(T, G0, U0 - h, u0, tgt)) / (2 * h)
+    print("dL/dU adjoint", gU, "central difference", fd)
+    assert abs(gU) > 0 and abs(gU - fd) <= 3e-3 * abs(fd)
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient():
+    a = _adjoint(12, every=1)
+    b = _adjoint(12, every=5)
+    c = _adjoint(12, every=12)
+    for x, y in ((a, b), (a, c)):
+        assert x[0] == y[0]
+        assert abs(x[1] - y[1]) <= 1e-12 * abs(x[1])
+        assert abs(x[2] - y[2]) <= 1e-12 * abs(x[2]) + 1e-30
+        assert np.max(np.abs(x[3] - y[3])) <= 1e-12 * np.max(np.abs(x[3]))
+
+
+def test_autograd_function_and_cost_ratio():
+    import time
+    import torch
+    from paper_2402_12696_amd import adjoint as AD
+    Fn = AD.make_function()
+    T = 12
+    G = torch.tensor(G0, dtype=torch.float64, requires_grad=True)
+    U = torch.tensor(U0, dtype=torch.float64, requires_grad=True)
+    u0 = torch.tensor(_u0(), dtype=torch.float64, device="cuda:0", requires_grad=True)
+    L = Fn.apply(G, U, u0, CFG, T, _target(T), 4)
+    L.backward()
+    ref = _adjoint(T, every=4)
+    assert float(L) == ref[0]
+    assert abs(float(G.grad) - ref[1]) <= 1e-12 * abs(ref[1])
+    assert np.max(np.abs(u0.grad.cpu().numpy() - ref[3])) <= 1e-12 * np.max(np.abs(ref[3]))
+    # the 256^2 inverse-problem scene: adjoint (replay + reverse steps) within
+    # four times the forward (which keeps sqrt(T) checkpoints)
+    cfg = workloads.make(nx=256, ny=256, tau=0.7, lid_ux=0.08,
+                         solid=dict(cx=128.0, cy=153.6, R=40.0, G=0.01, rho_s=1.0))
+    T = 300
+    tgt = AD.trajectory(cfg, 0.008, 0.08, T)
+    u0n = np.random.default_rng(5).normal(0.0, 1e-3, size=(2, 256, 256))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = AD.Trajectory(cfg, 0.01, 0.08, u0n, T, tgt)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gG, gU, gu0 = tr.backward()
+    tb = time.perf_counter() - t0
+    tr.close()
+    print("256^2, T = 300: forward", tf, "s, adjoint", tb, "s, ratio", tb / tf)
+    assert not tr.health and np.isfinite(gG) and np.isfinite(gU)
+    assert tb / tf <= 4.0
