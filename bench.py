@@ -180,6 +180,37 @@ def run_suspension(precision, steps, warmup=24):
             "health_flags": {k: v for k, v in d["health"].items() if v}}
 
 
+def run_adjoint(T=600):
+    """The 256^2 inverse-problem scene (disc R 40 at (128, 153.6), tau 0.7, lid
+    0.08, G 0.01, u_0 ~ N(0, 1e-3^2) from default_rng(5)); the loss follows
+    the centroid and mean displacement of a G* = 0.008 run.  Forward with
+    sqrt(T) checkpoints, then the adjoint (replays and reverse steps); T = 600:
+    this scene blows up after ~700 steps with that noise (explicit stress
+    update at tau 0.7)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2402_12696_amd import adjoint as AD
+    cfg = workloads.make(nx=256, ny=256, tau=0.7, lid_ux=0.08,
+                         solid=dict(cx=128.0, cy=153.6, R=40.0, G=0.01, rho_s=1.0))
+    tgt = AD.trajectory(cfg, 0.008, 0.08, T)
+    u0 = np.random.default_rng(5).normal(0.0, 1e-3, size=(2, 256, 256))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = AD.Trajectory(cfg, 0.01, 0.08, u0, T, tgt)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gG, gU, gu0 = tr.backward()
+    tb = time.perf_counter() - t0
+    out = {"workload": "cavity_disc_256 inverse problem", "steps": T, "checkpoints": tr.K,
+           "loss": tr.loss, "forward_s": tf, "adjoint_s": tb, "adjoint_over_forward": tb / tf,
+           "dL_dG": gG, "dL_dU": gU, "max_abs_dL_du0": float(gu0.abs().max()),
+           "health_flags": tr.health}
+    tr.close()
+    return out
+
+
 def cpu_baseline(cfg, seconds=15.0):
     from oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -218,6 +249,8 @@ def main():
     ap.add_argument("--no-suspension", action="store_true",
                     help="skip the 4096^2 suspension of 400 solids (several-solid path)")
     ap.add_argument("--suspension-steps", type=int, default=400)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint of the 256^2 inverse-problem scene")
     ap.add_argument("--suspension-only", action="store_true",
                     help="run only the suspension (in --precision) and print its record "
                          "(for profiling; not the benchmark line)")
@@ -284,6 +317,8 @@ def main():
     if not args.no_suspension:
         extra["suspension"] = {p: run_suspension(p, args.suspension_steps)
                                for p in ("f32", "f64")}
+    if not args.no_adjoint:
+        extra["adjoint"] = run_adjoint()
     line = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
