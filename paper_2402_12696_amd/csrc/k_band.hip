@@ -1766,12 +1766,12 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
                              int band_blocks)
 {
     const dim3 gb(band_blocks, nsim), gd(dt_blocks, nsim), gf(fit_blocks, nsim);
-    // fit_blocks == 0: every layer of a member in one block of 1024 threads
+    // fit_blocks == 0: every layer of a member in one block of MB_FIT_THREADS
     const dim3 g1(1, nsim);
     if (precision == 0) {
         if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv);
-        if (fit_blocks == 0) kb_fit_layers<double><<<g1, 1024, 0, st>>>(t.fit, layers);
+        if (fit_blocks == 0) kb_fit_layers<double><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
         else
             for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
         if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg);
@@ -1779,7 +1779,7 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
     } else {
         if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv);
-        if (fit_blocks == 0) kb_fit_layers<float><<<g1, 1024, 0, st>>>(t.fit, layers);
+        if (fit_blocks == 0) kb_fit_layers<float><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
         else
             for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
         if (relabel_only) kb_force<2, float><<<gb, 256, 0, st>>>(t.edg);

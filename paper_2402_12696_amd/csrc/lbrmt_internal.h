@@ -32,6 +32,7 @@ constexpr int FB_LOG = 4;
 constexpr int FB = 1 << FB_LOG;
 constexpr int MB_DT_BLOCKS = 16;      // per solid (a multiple of NSUB)
 constexpr int MB_BAND_BLOCKS = 16;    // relabel: two partial boxes per block
+constexpr int MB_FIT_THREADS = 1024;  // one block per solid runs all its layers
 constexpr int MB_MAX_PER_BLOCK = 32;  // solids overlapping one force block
 constexpr int MB_COMBINE_BLOCKS = 2048;
 

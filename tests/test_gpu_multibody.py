@@ -175,3 +175,12 @@ def test_suspension_4096_invariants():
     s1 = [sim.diag_solid(k)["n_solid"] for k in range(0, 400, 37)]
     assert all(abs(a - b) <= 0.05 * a for a, b in zip(s0, s1))
     sim.close()
+
+
+def test_suspension_recipe_at_reduced_size_matches_oracle():
+    # the suspension's own recipe (seeded ellipses, density contrast, gravity,
+    # periodic box, 128-node sub-windows) on a 384^2 box with 8 solids, 50
+    # steps in FP64 against the oracle; a uniform stream sets the velocity
+    # scale (from rest, gravity 1e-6 alone leaves max |u| ~ 1e-6 at step 1)
+    cfg = workloads.suspension(n=384, nbody=8, seed=7)
+    _run(cfg, (1, 10, 50), u0=workloads.uniform_velocity(384, 384, 0.01, 0.005))
