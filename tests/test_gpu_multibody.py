@@ -162,6 +162,26 @@ def test_graph_replay_equals_eager_with_several_solids():
         assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0))
 
 
+def test_suspension_4096_conserves_momentum_without_gravity():
+    # the full-size suspension with g = 0 in a stream (FP64): the elastic and
+    # contact stresses enter as divergences on a periodic grid, so the total
+    # momentum (sum of c f + F/2) stays fixed up to rounding.  (FP32 storage
+    # drifts by ~3e-6 of it in 200 steps: 16.8 M nodes x 200 steps of float
+    # rounding.)
+    cfg = dict(workloads.suspension(), gravity=(0.0, 0.0))
+    n = cfg["nx"]
+    sim = _sim(cfg, "f64", workloads.uniform_velocity(n, n, 0.01, -0.004))
+    d0 = sim.diag()
+    sim.step(200)
+    d1 = sim.diag()
+    assert all(v == 0 for v in d1["health"].values()), d1["health"]
+    p0 = np.hypot(d0["mom_x"], d0["mom_y"])
+    print("momentum change", d1["mom_x"] - d0["mom_x"], d1["mom_y"] - d0["mom_y"], "of", p0)
+    assert abs(d1["mom_x"] - d0["mom_x"]) < 1e-9 * p0
+    assert abs(d1["mom_y"] - d0["mom_y"]) < 1e-9 * p0
+    sim.close()
+
+
 def test_suspension_4096_invariants():
     # the full-size suspension: 400 solids on a 4096^2 periodic box, FP32
     cfg = workloads.suspension()
