@@ -217,8 +217,9 @@ int lbrmt_debug_poke(lbrmt_ctx* ctx, int32_t field, int64_t index, double value)
 int lbrmt_validate(const lbrmt_grid_desc* desc, const lbrmt_solid_desc* solids, int32_t n,
                    lbrmt_validation_t* out);
 
-/* Discrete adjoint (NEXT-3 of the build plan; FP64 contexts with one solid,
- * ESTATE otherwise).  The reverse of one step n needs what the forward step
+/* Discrete adjoint: the exact reverse-mode derivative of the step of Alg. 1
+ * as the forward kernels compute it (FP64 contexts with one solid, ESTATE
+ * otherwise).  The reverse of one step n needs what the forward step
  * used and made: lbrmt_step_snapshot advances the context one step (eager
  * launches) and copies that into a caller device buffer of
  * lbrmt_snapshot_bytes bytes (the state n lattice, F^{n-1}, F^n, xi^n, phi^n,

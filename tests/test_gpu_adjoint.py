@@ -148,3 +148,61 @@ def test_autograd_function_and_cost_ratio():
     print("256^2, T = 300: forward", tf, "s, adjoint", tb, "s, ratio", tb / tf)
     assert not tr.health and np.isfinite(gG) and np.isfinite(gU)
     assert tb / tf <= 4.0
+
+
+# a heavier-than-fluid ellipse under gravity on an x-periodic channel: the
+# adjoint of the density-excess force (rho_s - rho_f) lambda g, of the wrap of
+# the lattice and of the map across the periodic seam, and of the ellipse's
+# level set; the solid keeps clear of the lid over these few steps, so dL/dU
+# is exactly zero on both sides
+CFG_HEAVY = workloads.make(nx=56, ny=48, tau=0.8, lid_ux=0.06, periodic_x=True,
+                           gravity=(0.0, -2e-4),
+                           solid=dict(cx=28.0, cy=26.0, R=11.0, G=0.01, rho_s=1.4,
+                                      shape="ellipse", b=7.0, theta=0.5))
+
+
+def _heavy_loss(loss_name, T, G, u0, target):
+    from paper_2402_12696_amd import adjoint as AD
+    if loss_name == "gpu_fd":
+        t = AD.Trajectory(CFG_HEAVY, G, 0.06, u0, T, target, every=T)
+        out = t.loss
+        t.close()
+        return out
+    cfg = dict(CFG_HEAVY, solid=dict(CFG_HEAVY["solid"], G=G))
+    o = Oracle(**cfg).init(u0)
+    acc = 0.0
+    for n in range(T):
+        o.step(1)
+        d = o.diag()
+        e = np.array([d["centroid_x"], d["centroid_y"], d["disp_x"], d["disp_y"]]) - target[n]
+        acc += float(np.sum(e * e))
+    return acc / T
+
+
+@pytest.mark.parametrize("loss_name", ["gpu_fd", "oracle_fd"])
+def test_gradient_heavy_ellipse_periodic_gravity(loss_name):
+    from paper_2402_12696_amd import adjoint as AD
+    T = 8
+    u0 = (workloads.uniform_velocity(56, 48, 0.02, 0.01) +
+          np.random.default_rng(5).normal(0.0, 1e-3, size=(2, 48, 56)))
+    tgt = AD.trajectory(CFG_HEAVY, 0.008, 0.06, T)
+    tr = AD.Trajectory(CFG_HEAVY, 0.01, 0.06, u0, T, tgt, every=3)
+    gG, gU, gu0 = tr.backward()
+    gu0 = gu0.cpu().numpy()
+    assert not tr.health
+    tr.close()
+    h = 1e-4
+    fd = (_heavy_loss(loss_name, T, 0.01 + h, u0, tgt) -
+          _heavy_loss(loss_name, T, 0.01 - h, u0, tgt)) / (2 * h)
+    print("dL/dG adjoint", gG, "central difference", fd)
+    assert abs(gG - fd) <= 1e-6 * abs(fd)
+    assert gU == 0.0
+    rng = np.random.default_rng(17)
+    h = 1e-6
+    for k in range(2):
+        v = rng.normal(0.0, 1.0, size=u0.shape)
+        fd = (_heavy_loss(loss_name, T, 0.01, u0 + h * v, tgt) -
+              _heavy_loss(loss_name, T, 0.01, u0 - h * v, tgt)) / (2 * h)
+        ad = float(np.sum(gu0 * v))
+        print("direction", k, "adjoint", ad, "central difference", fd)
+        assert abs(ad - fd) <= 1e-6 * abs(fd)
