@@ -14,6 +14,14 @@ T = 3 agrees to 7e-10 with h = 1e-4, a u_0 direction at T = 5 to 1e-9 with
 h = 1e-6; dL/dU is small, so its difference quotient is noise-limited at
 ~3e-4).  The reference differences come from the GPU forward and, as the
 independent check, from the CPU oracle's forward.
+
+The sharper check is the tangent-linear oracle (the oracle's source compiled
+with dual numbers): it takes the same discrete decisions as the forward step
+and returns the exact directional derivative of the same discrete map, so the
+adjoint must agree with it to rounding, also where a difference quotient
+cannot be used (a zero-mean u_0 whose velocities cross zero).  Measured
+agreement: 1e-10 or better for dL/dG and dL/dU, 4e-12 or better over 16
+random u_0 directions.
 """
 import numpy as np
 import pytest
@@ -206,3 +214,75 @@ def test_gradient_heavy_ellipse_periodic_gravity(loss_name):
         ad = float(np.sum(gu0 * v))
         print("direction", k, "adjoint", ad, "central difference", fd)
         assert abs(ad - fd) <= 1e-6 * abs(fd)
+
+
+
+# ------------------------------------------------ tangent-linear oracle
+
+def _tangent_loss(cfg, G, U, u0, T, target, dsolid=None, dparam=None, du0=None):
+    """(L, dL along the seeded direction) from the tangent-linear oracle."""
+    from oracle.tangent import TangentOracle
+    c = dict(cfg, lid_ux=U, solid=dict(cfg["solid"], G=G))
+    o = TangentOracle(**c, dsolids=[dsolid or {}], dparams=dparam or {}).init(u0, du0)
+    L = dL = 0.0
+    for n in range(T):
+        o.step(1)
+        v, d = o.diag()
+        e = np.array([v["centroid_x"], v["centroid_y"], v["disp_x"], v["disp_y"]]) - target[n]
+        de = np.array([d["centroid_x"], d["centroid_y"], d["disp_x"], d["disp_y"]])
+        L += float(np.sum(e * e))
+        dL += float(np.sum(2.0 * e * de))
+    return L / T, dL / T
+
+
+def _noise_u0(nx, ny):
+    return np.random.default_rng(5).normal(0.0, 1e-3, size=(2, ny, nx))
+
+
+@pytest.mark.parametrize("scene,T", [("cavity_stream", 20), ("cavity_noise", 20),
+                                     ("cavity_stream", 60), ("heavy_ellipse", 40)])
+def test_adjoint_equals_the_tangent_linear_oracle(scene, T):
+    from paper_2402_12696_amd import adjoint as AD
+    if scene.startswith("cavity"):
+        cfg, G, U = CFG, G0, U0
+        u0 = _u0() if scene == "cavity_stream" else _noise_u0(48, 48)
+    else:
+        cfg, G, U = CFG_HEAVY, 0.01, 0.06
+        u0 = (workloads.uniform_velocity(56, 48, 0.02, 0.01) + _noise_u0(56, 48))
+    tgt = AD.trajectory(cfg, 0.008, U, T)
+    tr = AD.Trajectory(cfg, G, U, u0, T, tgt)
+    gG, gU, gu0 = tr.backward()
+    gu0 = gu0.cpu().numpy()
+    loss, health = tr.loss, tr.health
+    tr.close()
+    assert not health
+    L, dG = _tangent_loss(cfg, G, U, u0, T, tgt, dsolid={"G": 1.0})
+    _, dU = _tangent_loss(cfg, G, U, u0, T, tgt, dparam={"lid_ux": 1.0})
+    print(scene, T, "loss", loss, L, "dG", gG, dG, "dU", gU, dU)
+    assert abs(loss - L) <= 1e-12 * L
+    assert abs(gG - dG) <= 1e-9 * abs(dG)
+    assert abs(dU) > 0 and abs(gU - dU) <= 1e-9 * abs(dU)
+    rng = np.random.default_rng(17)
+    for k in range(16):
+        v = rng.normal(0.0, 1.0, size=u0.shape)
+        _, dv = _tangent_loss(cfg, G, U, u0, T, tgt, du0=v)
+        ad = float(np.sum(gu0 * v))
+        assert abs(ad - dv) <= 1e-10 * abs(dv), (k, ad, dv)
+
+
+def test_adjoint_equals_the_tangent_linear_oracle_on_the_256_scene():
+    # the 256^2 inverse-problem scene (disc R 40, tau 0.7, lid 0.08, u_0 noise)
+    from paper_2402_12696_amd import adjoint as AD
+    cfg = workloads.make(nx=256, ny=256, tau=0.7, lid_ux=0.08,
+                         solid=dict(cx=128.0, cy=153.6, R=40.0, G=0.01, rho_s=1.0))
+    T = 100
+    u0 = _noise_u0(256, 256)
+    tgt = AD.trajectory(cfg, 0.008, 0.08, T)
+    tr = AD.Trajectory(cfg, 0.01, 0.08, u0, T, tgt)
+    gG, gU, _ = tr.backward()
+    tr.close()
+    _, dG = _tangent_loss(cfg, 0.01, 0.08, u0, T, tgt, dsolid={"G": 1.0})
+    _, dU = _tangent_loss(cfg, 0.01, 0.08, u0, T, tgt, dparam={"lid_ux": 1.0})
+    print("256^2 T = 100: dG", gG, dG, "dU", gU, dU)
+    assert abs(gG - dG) <= 1e-9 * abs(dG)
+    assert abs(gU - dU) <= 1e-9 * abs(dU)
