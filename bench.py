@@ -225,7 +225,50 @@ def cpu_baseline(cfg, seconds=15.0):
     mlups = cfg["nx"] * cfg["ny"] * n / t / 1e6
     return {"value": mlups, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{n} steps of {cfg['name']} after 1 warm-up step "
-                      f"({t:.1f} s, OpenMP threads {threads})"}
+                      f"({t:.1f} s, OpenMP threads {threads})",
+            "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
+            "single_thread": _oracle_one_thread(cfg)}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_THREAD = """
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import Oracle
+cfg = json.loads(sys.argv[2])
+o = Oracle(**cfg).init()
+o.step(1)
+n, t = 0, 0.0
+while t < float(sys.argv[3]) and n < 20:
+    t0 = time.perf_counter()
+    o.step(1)
+    t += time.perf_counter() - t0
+    n += 1
+print(json.dumps({"steps": n, "seconds": t}))
+"""
+
+
+def _oracle_one_thread(cfg, seconds=8.0):
+    """The same oracle on one OpenMP thread, in a child process (the thread
+    count of this process's OpenMP runtime is already fixed)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD, ROOT, json.dumps(cfg), str(seconds)],
+                       env=env, capture_output=True, text=True, timeout=300, check=True)
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": cfg["nx"] * cfg["ny"] * d["steps"] / d["seconds"] / 1e6, "unit": "MLUPS",
+            "cores": 1, "sample": f"{d['steps']} steps of {cfg['name']} after 1 warm-up step "
+                                  f"({d['seconds']:.1f} s, OpenMP threads 1)"}
 
 
 def main():

@@ -278,13 +278,28 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         leaves HBM bandwidth to the reference-map chain
  *                         running beside it; 0: one workgroup per tile.
  *                         Results do not depend on it.
+ *   LBRMT_OPT_FUSED_FIT   1024, 512 or 256: one solid on walled axes
+ *                         with at most 11 layers fits all layers of the
+ *                         extrapolation (Sec. 3.2) in one launch of blocks of
+ *                         that many threads, each taking a tile of the window
+ *                         with the margin its later layers read; tiles whose
+ *                         targets need wider scan windows than the margin
+ *                         holds are finished by a second, one-block launch.
+ *                         0: one launch per layer; 1: 1024 threads with the
+ *                         margin check one node tighter, so that the second
+ *                         launch finishes most tiles (a check of that
+ *                         launch); -1 (default): 1024, except 0 for
+ *                         graph-replayed overlapped steps of lattices above
+ *                         2^21 nodes, where the bulk update beside it crowds
+ *                         out its blocks.  Results are bitwise identical.
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,
     LBRMT_OPT_LB_VARIANT = 1,
     LBRMT_OPT_LB_VARIANT_COUNT = 2, /* read only */
     LBRMT_OPT_GRAPH = 3,
-    LBRMT_OPT_BULK_BLOCKS = 4
+    LBRMT_OPT_BULK_BLOCKS = 4,
+    LBRMT_OPT_FUSED_FIT = 5
 } lbrmt_option;
 int lbrmt_set_option(lbrmt_ctx* ctx, int32_t option, int64_t value);
 int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);

@@ -430,6 +430,7 @@ __device__ __forceinline__ void advect_node(const GridP& g, const S* __restrict_
 // counter; the order inside a list does not matter since targets of one layer
 // are independent).  The layer counters were cleared by the kernel before.
 constexpr int DTX = 32, DTY = 16;
+static_assert(DTX == FF_TILE && FF_TILE % DTY == 0, "a distance-transform tile lies in one fused-fit tile");
 constexpr int DRW = DTX + 2 * MAX_LAYERS, DRH = DTY + 2 * MAX_LAYERS;
 
 // LC > 0: the layer count as a compile-time constant (scans unrolled);
@@ -445,7 +446,9 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
                                              const double* __restrict__ fpx,
                                              const double* __restrict__ fpy,
                                              const S* __restrict__ X, const S* __restrict__ Y,
-                                             const S* __restrict__ phi, S* X1, S* Y1)
+                                             const S* __restrict__ phi, S* X1, S* Y1,
+                                             int* ff_flag = nullptr, int* ff_list = nullptr,
+                                             int* ff_n = nullptr)
 {
     __shared__ int8_t sol[DRH * DRW];   // solid flags of the tile and its halo
     __shared__ int8_t gc[DTY * DRW];    // column distances of the tile rows
@@ -529,6 +532,17 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
         if (threadIdx.x >= 1 && threadIdx.x <= L && cnt[threadIdx.x] > 0)
             base[threadIdx.x] =
                 atomicAdd(&lcount[(threadIdx.x * NSUB + sub) * LCOUNT_PAD], cnt[threadIdx.x]);
+        // the fused extrapolation's tile (FF_TILE square, same origin) holding
+        // this one is listed once if the zone reaches it
+        if (ff_list && threadIdx.x == 0) {
+            bool zone = false;
+            for (int l = 1; l <= L; l++) zone = zone || cnt[l] > 0;
+            if (zone) {
+                const int ft = (x0 - W.i0) / FF_TILE +
+                               ((y0 - W.j0) / FF_TILE) * ((w + FF_TILE - 1) / FF_TILE);
+                if (atomicExch(&ff_flag[ft], 1) == 0) ff_list[atomicAdd(ff_n, 1)] = ft;
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NPT; u++) {
@@ -571,10 +585,11 @@ __global__ __launch_bounds__(256) void k_advect_dt(GridP g, const S* __restrict_
                                                    const S* __restrict__ phi, S* X1, S* Y1,
                                                    int8_t* tag, const Win* __restrict__ win,
                                                    int wprev, int wcur, int* lists, int* lcount,
-                                                   unsigned* health)
+                                                   unsigned* health, int* ff_flag, int* ff_list,
+                                                   int* ff_n)
 {
     dt_tile_body<LC, true, S>(g, win, wcur, wprev, tag, lists, lcount, health, A, fpx, fpy, X,
-                              Y, phi, X1, Y1);
+                              Y, phi, X1, Y1, ff_flag, ff_list, ff_n);
 }
 
 template <int LC, typename S>
@@ -588,13 +603,16 @@ __global__ __launch_bounds__(256) void kb_advect_dt(const AdvectArgs* __restrict
 
 hipError_t launch_advect_layers(const GridP& g, int precision, const BandBufs& bb,
                                 const StepSlots& s, const void* A, const double* fpx,
-                                const double* fpy, hipStream_t st)
+                                const double* fpy, hipStream_t st, bool fused)
 {
+    int* ffl = fused ? bb.ff_flag : nullptr;
+    int* ffs = fused ? bb.ff_list : nullptr;
+    int* ffn = fused ? bb.ff_n : nullptr;
 #define ADT(LC, S)                                                                                \
     k_advect_dt<LC, S><<<DT_BLOCKS, 256, 0, st>>>(                                              \
         g, (const S*)A, fpx, fpy, (const S*)bb.X[s.cur], (const S*)bb.Y[s.cur],                   \
         (const S*)bb.phi[s.cur], (S*)bb.X[s.nxt], (S*)bb.Y[s.nxt], bb.tag, bb.win, s.wprev,      \
-        s.wcur, bb.lists, bb.lcount, bb.health)
+        s.wcur, bb.lists, bb.lcount, bb.health, ffl, ffs, ffn)
     if (precision == 0) {
         if (g.layers == 11) ADT(11, double);
         else ADT(0, double);
@@ -788,6 +806,45 @@ __device__ __forceinline__ bool fit_at(const GridP& g, const Rect& W, int l, int
     return f.solve(g.det_rel, xo, yo);
 }
 
+// Fit of one target kt = (i, j) of layer l by the FIT_LANES lanes of a group
+// (every lane of the group calls it with the same target): the outward normal
+// of phi^n for layers 1 and 2, then scan windows of half-width r = 2 .. r_max
+// until one holds three valid nodes and a well-posed fit.  Windows wider than
+// rlim are not tried: if the fit needs one, the result is false with cut set.
+template <typename T>
+__device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const Rect& D, int l,
+                                           int kt, int i, int j, int sub, int rlim,
+                                           const int8_t* tag, const T* __restrict__ phin,
+                                           const T* X1, const T* Y1, T& xo, T& yo, bool& cut)
+{
+    // outward normal of phi^n at the target (layers 1, 2): lanes 0..3 load
+    // the four neighbours
+    double nxh = 0.0, nyh = 0.0;
+    bool use_n = false;
+    if (l <= 2) {
+        double p = INFINITY;
+        if (sub < 4) {
+            const int di = sub == 0 ? 1 : sub == 1 ? -1 : 0;
+            const int dj = sub == 2 ? 1 : sub == 3 ? -1 : 0;
+            const long long kq = ref_index(g, D, i + di, j + dj);
+            if (kq >= 0) p = (double)phin[kq];
+        }
+        const double pe = __shfl(p, 0, FIT_LANES), pw = __shfl(p, 1, FIT_LANES);
+        const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
+        use_n = normal_from(pe, pw, pn, ps, nxh, nyh);
+    }
+    cut = false;
+    for (int r = 2; r <= g.r_max; r++) {
+        if (r > rlim) {
+            cut = true;
+            return false;
+        }
+        if (fit_at<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, xo, yo))
+            return true;
+    }
+    return false;
+}
+
 // One layer of Sec. 3.2: every target of the layer list is fitted by a group
 // of FIT_LANES lanes that share the scan-window nodes; the sums of the normal
 // equations are reduced across the group.  Scan windows grow from r = 2 to
@@ -821,26 +878,10 @@ __device__ __forceinline__ void layer_fit_body(GridP g, const Win* __restrict__ 
     for (int at = a0; at < ns; at += astride) {
         const int kt = at == a0 ? kfirst : list[at];
         const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
-        // outward normal of phi^n at the target (layers 1, 2): lanes 0..3
-        // load the four neighbours
-        double nxh = 0.0, nyh = 0.0;
-        bool use_n = false;
-        if (l <= 2) {
-            double p = INFINITY;
-            if (sub < 4) {
-                const int di = sub == 0 ? 1 : sub == 1 ? -1 : 0;
-                const int dj = sub == 2 ? 1 : sub == 3 ? -1 : 0;
-                const long long kq = ref_index(g, D, i + di, j + dj);
-                if (kq >= 0) p = (double)phin[kq];
-            }
-            const double pe = __shfl(p, 0, FIT_LANES), pw = __shfl(p, 1, FIT_LANES);
-            const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
-            use_n = normal_from(pe, pw, pn, ps, nxh, nyh);
-        }
         T xo = T(0), yo = T(0);
-        bool done = false;
-        for (int r = 2; r <= g.r_max && !done; r++)
-            done = fit_at<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, xo, yo);
+        bool cut;
+        const bool done = fit_target<T>(g, W, D, l, kt, i, j, sub, g.r_max, tag, phin, X1, Y1,
+                                        xo, yo, cut);
         if (sub == 0) {
             if (done) {
                 X1[kt] = xo;
@@ -888,9 +929,213 @@ __global__ __launch_bounds__(1024) void kb_fit_layers(const FitArgs* __restrict_
     }
 }
 
-hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
-                              hipStream_t st)
+// All layers of one solid in one launch.  Block b takes FF_TILE x FF_TILE
+// tiles of the window from the list the distance transform made of the tiles
+// the zone reaches; for layer l it fits every layer-l target within
+// M_l = 2 (L - l) nodes of its tile, its own and those of the tiles around
+// (recomputed, with the same arithmetic, so a node fitted by several blocks
+// gets the same bits from each), then a block barrier, then layer l + 1.  A
+// scan window of half-width 2 around a target within M_l of the tile stays
+// within M_l + 2 = M_{l-1}, where the block has fitted every earlier layer,
+// so the block never reads a value another block has yet to write.  A target
+// that needs a wider window than that region allows stops the tile at that
+// layer: the tile is listed, with the layer, for k_fit_rest, which finishes
+// the listed tiles layer by layer; its layers before that one are final.
+// Layer-1 windows read solid nodes only, which the advection pass wrote.
+// reach = 2; reach = 1 stops every tile with a target on the rim of its
+// margin at layer 2 (the second launch then fits most of the zone: a check
+// of that launch).
+// Walled axes only (a window across a periodic seam would reach another
+// tile's nodes).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict__ win, int wcur,
+                                                  int wprev, int8_t* tag,
+                                                  const T* __restrict__ phin, T* X1, T* Y1,
+                                                  unsigned* health, int8_t* cut_layer,
+                                                  int* cut_tiles, int* ncut,
+                                                  const int* __restrict__ ff_list,
+                                                  const int* __restrict__ ff_n, int reach)
 {
+    constexpr int RW = FF_TILE + 4 * (FF_LAYERS - 1);
+    constexpr int NG = NT / FIT_LANES;
+    __shared__ int8_t st[RW * RW];  // tags of the tile and its layer-1 margin
+    __shared__ int lst[RW * RW];    // targets of the current layer
+    __shared__ int s_n, s_cut, s_fail;
+    const int ntile = *ff_n;
+    if (blockIdx.x >= ntile) return;
+    const Rect W = window_of(win, wcur, g);
+    if (!W.ok) return;
+    const Rect D = window_of(win, wprev, g);
+    const int L = g.layers;
+    const int MR = 2 * (L - 1), rw = FF_TILE + 2 * MR;
+    const int ntx = (W.i1 - W.i0 + FF_TILE) / FF_TILE;
+    const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
+    for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
+        const int t = ff_list[k];
+        const int x0 = W.i0 + (t % ntx) * FF_TILE, y0 = W.j0 + (t / ntx) * FF_TILE;
+        __syncthreads();  // the previous tile's shared state is no longer read
+        if (threadIdx.x == 0) {
+            s_n = 0;
+            s_cut = 0;
+            s_fail = 0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < rw * rw; e += NT) {
+            const int x = x0 - MR + e % rw, y = y0 - MR + e / rw;
+            int8_t tv = W.has(x, y) ? tag[pidx(g, x, y)] : (int8_t)TAG_NONE;
+            // a block that fitted this node in its margin may have marked it
+            // failed already: it is fitted here again (to the same verdict),
+            // so that the tile's own failures are counted by the tile's block
+            if (tv > 0) tv = (int8_t)(tv & (TAG_FAIL - 1));
+            st[e] = tv;
+        }
+        __syncthreads();
+        for (int l = 1; l <= L; l++) {
+            const int M = 2 * (L - l), side = FF_TILE + 2 * M, off = MR - M;
+            for (int e = threadIdx.x; e < side * side; e += NT) {
+                const int lx = off + e % side, ly = off + e / side;
+                if (st[ly * rw + lx] == l)
+                    lst[atomicAdd(&s_n, 1)] = (int)pidx(g, x0 - MR + lx, y0 - MR + ly);
+            }
+            __syncthreads();
+            const int n = s_n;
+            // earlier layers are fitted within M + 2 of the tile (reach < 2
+            // narrows what a fit may read, so that more tiles stop)
+            const int K = M + reach;
+            for (int a = grp; a < n; a += NG) {
+                const int kt = lst[a];
+                const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
+                int rlim = g.r_max;
+                if (l > 1)
+                    rlim = min(rlim, min(min(i - (x0 - K), x0 + FF_TILE - 1 + K - i),
+                                         min(j - (y0 - K), y0 + FF_TILE - 1 + K - j)));
+                T xo = T(0), yo = T(0);
+                bool cut;
+                const bool done = fit_target<T>(g, W, D, l, kt, i, j, sub, rlim, tag, phin, X1,
+                                                Y1, xo, yo, cut);
+                if (sub == 0) {
+                    if (done) {
+                        X1[kt] = xo;
+                        Y1[kt] = yo;
+                    } else if (cut) {
+                        s_cut = 1;
+                    } else {
+                        tag[kt] = (int8_t)(l | TAG_FAIL);
+                        if (i >= x0 && i < x0 + FF_TILE && j >= y0 && j < y0 + FF_TILE)
+                            atomicAdd(&s_fail, 1);
+                    }
+                }
+            }
+            __syncthreads();
+            const bool stop = s_cut != 0;
+            if (threadIdx.x == 0) {
+                if (stop) {
+                    cut_layer[t] = (int8_t)l;
+                    cut_tiles[atomicAdd(ncut, 1)] = t;
+                } else if (s_fail > 0) {
+                    atomicAdd(&health[1], (unsigned)s_fail);
+                }
+                s_n = 0;
+                s_fail = 0;
+            }
+            __syncthreads();
+            if (stop) break;
+        }
+    }
+}
+
+// The tiles k_fit_fused stopped: one block fits, layer by layer from the
+// first to the last, every target of the layer lists that lies in a listed
+// tile at or after the layer where that tile stopped (full scan windows up to
+// r_max, the per-layer path's fit), then clears that list and the list of
+// zone tiles.  With no tile stopped it only clears the lists.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fit_rest(GridP g, const Win* __restrict__ win, int wcur,
+                                                   int wprev, int8_t* tag,
+                                                   const int* __restrict__ lists,
+                                                   const int* __restrict__ lcount,
+                                                   const T* __restrict__ phin, T* X1, T* Y1,
+                                                   unsigned* health, int8_t* cut_layer,
+                                                   const int* cut_tiles, int* ncut,
+                                                   int* ff_flag, const int* ff_list, int* ff_n)
+{
+    constexpr int NG = 1024 / FIT_LANES;
+    // the tile list of the next step starts empty
+    const int nt = *ff_n;
+    for (int a = threadIdx.x; a < nt; a += blockDim.x) ff_flag[ff_list[a]] = 0;
+    const int nc = *ncut;
+    if (nc == 0) {
+        __syncthreads();
+        if (threadIdx.x == 0) *ff_n = 0;
+        return;
+    }
+    const Rect W = window_of(win, wcur, g);
+    const Rect D = window_of(win, wprev, g);
+    const long long cap = g.lcap;
+    const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
+    if (W.ok) {
+        const int ntx = (W.i1 - W.i0 + FF_TILE) / FF_TILE;
+        for (int l = 1; l <= g.layers; l++) {
+            for (int s = 0; s < NSUB; s++) {
+                const int* list = lists + (l * NSUB + s) * cap;
+                const int ns = (int)min((long long)lcount[(l * NSUB + s) * LCOUNT_PAD], cap);
+                for (int a = grp; a < ns; a += NG) {
+                    const int kt = list[a];
+                    const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
+                    const int t = (i - W.i0) / FF_TILE + ((j - W.j0) / FF_TILE) * ntx;
+                    if (cut_layer[t] > l) continue;
+                    T xo = T(0), yo = T(0);
+                    bool cut;
+                    const bool done = fit_target<T>(g, W, D, l, kt, i, j, sub, g.r_max, tag,
+                                                    phin, X1, Y1, xo, yo, cut);
+                    if (sub == 0) {
+                        if (done) {
+                            X1[kt] = xo;
+                            Y1[kt] = yo;
+                        } else {
+                            tag[kt] = (int8_t)(l | TAG_FAIL);
+                            atomicAdd(&health[1], 1u);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int a = threadIdx.x; a < nc; a += blockDim.x) cut_layer[cut_tiles[a]] = FF_NO_CUT;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *ncut = 0;
+        *ff_n = 0;
+    }
+}
+
+hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
+                              hipStream_t st, int fused_threads)
+{
+    if (fused_threads > 0 && fused_fit_ok(g)) {
+#define FUSED(T, NT)                                                                              \
+    k_fit_fused<T, NT><<<FF_BLOCKS, NT, 0, st>>>(                                                 \
+        g, bb.win, s.wcur, s.wprev, bb.tag, (const T*)bb.phi[s.cur], (T*)bb.X[s.nxt],             \
+        (T*)bb.Y[s.nxt], bb.health, bb.cut_layer, bb.cut_tiles, bb.ncut, bb.ff_list, bb.ff_n,    \
+        fused_threads == 1 ? 1 : 2)
+#define FUSED_T(T)                                                                                \
+    do {                                                                                          \
+        if (fused_threads == 256) FUSED(T, 256);                                                  \
+        else if (fused_threads == 512) FUSED(T, 512);                                             \
+        else FUSED(T, 1024);                                                                      \
+        k_fit_rest<T><<<1, 1024, 0, st>>>(g, bb.win, s.wcur, s.wprev, bb.tag, bb.lists,           \
+                                          bb.lcount, (const T*)bb.phi[s.cur], (T*)bb.X[s.nxt],    \
+                                          (T*)bb.Y[s.nxt], bb.health, bb.cut_layer,               \
+                                          bb.cut_tiles, bb.ncut, bb.ff_flag, bb.ff_list,          \
+                                          bb.ff_n);                                               \
+    } while (0)
+        if (g.rm32) FUSED_T(float);
+        else FUSED_T(double);
+#undef FUSED_T
+#undef FUSED
+        return hipGetLastError();
+    }
     for (int l = 1; l <= g.layers; l++)
         if (g.rm32)
             k_layer_fit<float><<<FIT_BLOCKS, 256, 0, st>>>(

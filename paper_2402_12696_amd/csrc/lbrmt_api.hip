@@ -92,7 +92,8 @@ struct Layout {
     size_t rm_es;  // bytes per reference-map value: 8 (FP64 xi) or 4 (FP32 displacement)
     size_t off_lat[2], off_fx[2], off_fy[2], off_drho, off_X[2], off_Y[2], off_phi[2], off_tag,
         off_win, off_health, off_dpart, off_dout, off_gcol, off_lists, off_lcount, off_boxpart,
-        off_ticket, total;
+        off_ticket, off_cut_layer, off_cut_tiles, off_ncut, off_ff_flag, off_ff_list, off_ff_n,
+        total;
     size_t lat_bytes;
     // several solids
     int nbx, nby;
@@ -137,6 +138,13 @@ Layout make_layout(const lbrmt_grid_desc* d, int max_solids = 1)
     L.off_lcount = take((size_t)(MAX_LAYERS + 1) * NSUB * LCOUNT_PAD * 4);
     L.off_boxpart = take((size_t)std::max(RELABEL_BLOCKS, BOX_BLOCKS) * 4 * 4);
     L.off_ticket = take(4);
+    const size_t ntile = multi ? 0 : (size_t)fused_tiles(d->nx, d->ny);
+    L.off_cut_layer = take(ntile);
+    L.off_cut_tiles = take(ntile * 4);
+    L.off_ncut = take(4);
+    L.off_ff_flag = take(ntile * 4);
+    L.off_ff_list = take(ntile * 4);
+    L.off_ff_n = take(4);
     L.off_win = take(3 * sizeof(Win));
     L.off_health = take(LBRMT_H_COUNT * sizeof(unsigned));
     L.off_dpart = take(diag_partial_doubles() * 8);
@@ -193,6 +201,7 @@ struct lbrmt_ctx {
     bool graph = true;  // replay captured six-step graphs
     bool member = false;  // member of a batch (stepped by the batch only)
     int bulk_blocks = 0;  // cap on the blocks of the overlapped bulk update (0: one per tile)
+    int fused_fit = -1;  // block size of the one-launch extrapolation (0: one launch per layer, -1: by size)
     bool timing = false;
     struct Pending {
         int kind;
@@ -326,6 +335,18 @@ static StampValid prev_valid(const lbrmt_ctx* c)
 }
 
 // enqueue step n: band chain on `band`, LB on `main_s`
+// Block size of the one-launch extrapolation, 0 for one launch per layer.
+// By default the one launch, except for graph-replayed steps that overlap the
+// chain with the bulk update of a lattice above 2^21 nodes: there the bulk
+// update crowds out its 1024-thread blocks (measured on MI355X, FP64 cavity:
+// 12-16 % faster steps at 64^2 to 1024^2, 7 % slower at 2048^2).
+static int fused_threads(const lbrmt_ctx* c)
+{
+    if (c->fused_fit >= 0) return c->fused_fit;
+    const bool crowded = c->overlap && c->graph && (long long)c->d.nx * c->d.ny > (1ll << 21);
+    return crowded ? 0 : 1024;
+}
+
 static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
 {
     if (c->multi) return enqueue_step_mb(c, n, main_s);
@@ -340,16 +361,20 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
             HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
             band = c->side;
         }
+        // the extrapolation in one launch (its tile list comes from the
+        // distance transform)
+        const int ff = fused_threads(c);
+        const bool fused = ff > 0 && fused_fit_ok(g);
         {
             // advection and the layers of the extrapolation zone (one pass)
             Bracket b(c, 0, band);
             HIPCHK(c, launch_advect_layers(g, prec, c->bb, s, c->lat[s.cur], c->Fx[s.nxt],
-                                           c->Fy[s.nxt], band));
+                                           c->Fy[s.nxt], band, fused));
             b.done();
         }
         {
             Bracket b(c, 1, band);
-            HIPCHK(c, launch_extrapolate(g, c->bb, s, band));
+            HIPCHK(c, launch_extrapolate(g, c->bb, s, band, fused ? ff : 0));
             b.done();
         }
         {
@@ -509,6 +534,12 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
     c->bb.lcount = (int*)(c->ws + L.off_lcount);
     c->bb.boxpart = (int*)(c->ws + L.off_boxpart);
     c->bb.ticket = (unsigned*)(c->ws + L.off_ticket);
+    c->bb.cut_layer = (int8_t*)(c->ws + L.off_cut_layer);
+    c->bb.cut_tiles = (int*)(c->ws + L.off_cut_tiles);
+    c->bb.ncut = (int*)(c->ws + L.off_ncut);
+    c->bb.ff_flag = (int*)(c->ws + L.off_ff_flag);
+    c->bb.ff_list = (int*)(c->ws + L.off_ff_list);
+    c->bb.ff_n = (int*)(c->ws + L.off_ff_n);
     c->bb.win = (Win*)(c->ws + L.off_win);
     c->bb.health = (unsigned*)(c->ws + L.off_health);
     c->dpart = (double*)(c->ws + L.off_dpart);
@@ -661,6 +692,12 @@ static BandBufs mb_bufs(const lbrmt_ctx* c, int k)
     b.ticket = (unsigned*)(base + c->BL.off_ticket);
     b.win = m.win;
     b.health = c->bb.health;
+    b.cut_layer = nullptr;  // one launch per layer for several solids
+    b.cut_tiles = nullptr;
+    b.ncut = nullptr;
+    b.ff_flag = nullptr;
+    b.ff_list = nullptr;
+    b.ff_n = nullptr;
     return b;
 }
 
@@ -772,6 +809,18 @@ static int init_mb(lbrmt_ctx* c, const double* d_u0)
     return LBRMT_OK;
 }
 
+// the fused extrapolation's tile list starts empty (k_fit_rest leaves it so)
+static hipError_t clear_cut_tiles(lbrmt_ctx* c, hipStream_t st)
+{
+    if (c->multi) return hipSuccess;  // several solids: no fused extrapolation
+    const size_t nt = (size_t)fused_tiles(c->d.nx, c->d.ny);
+    hipError_t e = hipMemsetAsync(c->bb.cut_layer, FF_NO_CUT, nt, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->bb.ncut, 0, 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->bb.ff_flag, 0, nt * 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->bb.ff_n, 0, 4, st);
+    return e;
+}
+
 int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
 {
     if (!c) return LBRMT_EINVAL;
@@ -784,6 +833,7 @@ int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
     }
     HIPCHK(c, hipMemsetAsync(c->drho, 0, c->L.plane * 8, st));
     HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, st));
+    HIPCHK(c, clear_cut_tiles(c, st));
     for (int k = 0; k < 3; k++) HIPCHK(c, launch_win_reset(c->bb.win, k, st));
     if (c->gexec) {
         // a graph captured for an earlier initialisation bakes the old solids in
@@ -1303,6 +1353,7 @@ int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
     HIPCHK(c, hipMemsetAsync(c->bb.lcount, 0, (size_t)(MAX_LAYERS + 1) * NSUB * LCOUNT_PAD * 4,
                              c->st));
     HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, c->st));
+    HIPCHK(c, clear_cut_tiles(c, c->st));
     c->inited = true;
     return LBRMT_OK;
 }
@@ -1389,6 +1440,12 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
         if (value < 0 || value > (1 << 24)) return LBRMT_EINVAL;
         c->bulk_blocks = (int)value;
         break;
+    case LBRMT_OPT_FUSED_FIT:
+        if (value != -1 && value != 0 && value != 1 && value != 256 && value != 512 &&
+            value != 1024)
+            return LBRMT_EINVAL;
+        c->fused_fit = (int)value;
+        break;
     default:
         return LBRMT_EINVAL;
     }
@@ -1410,6 +1467,7 @@ int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
     case LBRMT_OPT_LB_VARIANT_COUNT: *value = lb_variant_count(); return LBRMT_OK;
     case LBRMT_OPT_GRAPH: *value = c->graph ? 1 : 0; return LBRMT_OK;
     case LBRMT_OPT_BULK_BLOCKS: *value = c->bulk_blocks; return LBRMT_OK;
+    case LBRMT_OPT_FUSED_FIT: *value = c->fused_fit; return LBRMT_OK;
     default: return LBRMT_EINVAL;
     }
 }

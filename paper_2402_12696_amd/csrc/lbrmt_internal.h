@@ -25,6 +25,10 @@ constexpr int FIT_BLOCKS = 256;       // one extrapolation layer
 constexpr int FIT_LANES = 8;          // lanes sharing one extrapolation target
 constexpr int LCOUNT_PAD = 32;        // layer counters 128 B apart
 constexpr int NSUB = 8;               // sub-lists per layer (distance-transform block mod 8)
+constexpr int FF_TILE = 32;           // fused extrapolation: tile side
+constexpr int FF_LAYERS = 11;         // fused extrapolation: most layers
+constexpr int FF_BLOCKS = 256;        // fused extrapolation: blocks striding over its tile list
+constexpr int FF_NO_CUT = 127;        // tile not stopped (cut_layer)
 
 // Several solids: the lattice is cut into force blocks of FB x FB nodes;
 // a block holds valid force planes at step n when its stamp equals n + 1.
@@ -97,6 +101,16 @@ struct BandBufs {
     unsigned* ticket;     // arrival counter of last-block reductions
     Win* win;             // ring of 3 boxes
     unsigned* health;
+    // fused extrapolation: per window tile the layer where it stopped
+    // (FF_NO_CUT between steps), the stopped tiles and their count
+    int8_t* cut_layer;
+    int* cut_tiles;
+    int* ncut;
+    // fused extrapolation: the tiles the zone reaches, listed once each by
+    // the distance transform (flag per tile, list, count; cleared each step)
+    int* ff_flag;
+    int* ff_list;
+    int* ff_n;
 };
 
 // ---- box reductions (wave64 shuffles + LDS)
@@ -473,13 +487,23 @@ hipError_t launch_init_solid_box(const GridP& g, const BodyP& b, const BandBufs&
 hipError_t launch_init_tags(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st);
 hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStream_t st);
+// fused_threads 256 / 512 / 1024: all layers in one k_fit_fused launch of
+// that block size (walled axes, at most FF_LAYERS layers; else, and for 0,
+// one launch per layer); 1: 1024 threads with the fits' reach narrowed by one
+// node, so that the second launch takes over most tiles
 hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
-                              hipStream_t st);
+                              hipStream_t st, int fused_threads);
+inline bool fused_fit_ok(const GridP& g) { return !g.px && !g.py && g.layers <= FF_LAYERS; }
+inline long long fused_tiles(int nx, int ny)
+{
+    return (long long)((nx + 2 * PAD + FF_TILE - 1) / FF_TILE) *
+           ((ny + 2 * PAD + FF_TILE - 1) / FF_TILE);
+}
 hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, int wslot,
                             hipStream_t st);
 hipError_t launch_advect_layers(const GridP& g, int precision, const BandBufs& bb,
                                 const StepSlots& s, const void* A, const double* fpx,
-                                const double* fpy, hipStream_t st);
+                                const double* fpy, hipStream_t st, bool fused);
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
                         double* fx, double* fy, double* drho, hipStream_t st);
 hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,

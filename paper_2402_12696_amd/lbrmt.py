@@ -24,6 +24,7 @@ HEALTH_NAMES = ["advect_miss", "extrap_fail", "stress_miss", "detj", "detj_solid
 KERNEL_NAMES = ["advect", "extrap", "relabel", "force", "lb_bulk", "lb_band"]
 LBRMT_OPT_OVERLAP, LBRMT_OPT_LB_VARIANT, LBRMT_OPT_LB_VARIANT_COUNT, LBRMT_OPT_GRAPH = 0, 1, 2, 3
 LBRMT_OPT_BULK_BLOCKS = 4
+LBRMT_OPT_FUSED_FIT = 5
 
 
 class lbrmt_grid_desc(ctypes.Structure):
