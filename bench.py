@@ -52,7 +52,8 @@ def traffic_from_profile(kernel, workload, precision):
     return float(t.group(1))
 
 
-def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_variant=None):
+def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_variant=None,
+            autotune=True):
     import torch
     from paper_2402_12696_amd import Sim
     from paper_2402_12696_amd.lbrmt import LBRMT_OPT_LB_VARIANT, LBRMT_OPT_OVERLAP
@@ -62,6 +63,14 @@ def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_varian
     if lb_variant is not None:
         sim.set_option(LBRMT_OPT_LB_VARIANT, lb_variant)
     sim.step(warmup)
+    # extrapolation launch mode (one launch for all layers, or one per layer)
+    # chosen by timing whole steps, untimed here; the steps it takes are extra
+    # warm-up
+    if autotune:
+        fused, _ = sim.autotune_steps(60)
+    else:
+        from paper_2402_12696_amd.lbrmt import LBRMT_OPT_FUSED_FIT
+        fused = sim.get_option(LBRMT_OPT_FUSED_FIT)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
@@ -89,6 +98,7 @@ def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_varian
     sim.set_timing(False)
     sim.set_option(_OV, keep)
     sim.close()
+    ktimes["fused_fit"] = fused
     return ms_per_step, ktimes, band_nodes, window_nodes, diag
 
 
@@ -276,6 +286,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=120)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default extrapolation launch mode")
     ap.add_argument("--workload", default="cavity_disc_2048")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--timing-steps", type=int, default=300)
@@ -323,7 +335,8 @@ def main():
     cfg = _workload(args.workload)
     nodes = cfg["nx"] * cfg["ny"]
     ms, kt, band, window, diag = run_gpu(cfg, args.precision, args.steps, args.warmup,
-                                         args.timing_steps, args.overlap, args.lb_variant)
+                                         args.timing_steps, args.overlap, args.lb_variant,
+                                         not args.no_autotune)
     mlups = nodes / (ms * 1e-3) / 1e6
 
     bulk_ms, bulk_n = kt["lb_bulk"]
@@ -345,16 +358,20 @@ def main():
                                        "frac": alone / HBM_PEAK_GBS if alone else None,
                                        "frac_of_copy_ceiling": alone / ceiling if alone else None}}
 
+    fused = kt.pop("fused_fit")
     extra = {"kernel_avg_ms": {k: v[0] for k, v in kt.items()},
+             "extrapolation_launch": "one launch, all layers" if fused else "one launch per layer",
              "band_region_nodes": band, "window_nodes": window,
              "n_solid": diag["n_solid"], "n_band": diag["n_band"],
              "health": diag["health"]}
     if args.precision == "f64" and not args.no_f32:
         ms32, kt32, _, _, d32 = run_gpu(cfg, "f32", args.steps, args.warmup, args.timing_steps,
-                                        args.overlap, args.lb_variant)
+                                        args.overlap, args.lb_variant, not args.no_autotune)
         extra["f32"] = {"ms_per_step": ms32, "mlups": nodes / (ms32 * 1e-3) / 1e6,
                         "speedup_vs_f64": ms / ms32,
-                        "lb_bulk_avg_ms": kt32["lb_bulk"][0]}
+                        "lb_bulk_avg_ms": kt32["lb_bulk"][0],
+                        "extrapolation_launch": "one launch, all layers" if kt32["fused_fit"]
+                        else "one launch per layer"}
     if not args.no_batch:
         extra["batched"] = run_ensemble("f32", args.batch_steps)
     if not args.no_suspension:

@@ -288,10 +288,11 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         0: one launch per layer; 1: 1024 threads with the
  *                         margin check one node tighter, so that the second
  *                         launch finishes most tiles (a check of that
- *                         launch); -1 (default): 1024, except 0 for
- *                         graph-replayed overlapped steps of lattices above
- *                         2^21 nodes, where the bulk update beside it crowds
- *                         out its blocks.  Results are bitwise identical.
+ *                         launch); -1 (default): 1024.  With overlap, the
+ *                         bulk lattice update then starts when the advection
+ *                         pass has finished, so that these blocks are
+ *                         resident before the bulk update fills the compute
+ *                         units.  Results are bitwise identical.
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,
@@ -318,6 +319,18 @@ int lbrmt_band_nodes(lbrmt_ctx* ctx, int64_t* band_nodes, int64_t* window_nodes)
  * best_variant / best_ms (nullable): the choice and its time per launch.
  * Synchronises the stream.  ESTATE before init or on a batch member. */
 int lbrmt_autotune(lbrmt_ctx* ctx, int32_t reps, int32_t* best_variant, double* best_ms);
+
+/* Chooses LBRMT_OPT_FUSED_FIT between the one-launch extrapolation (1024) and
+ * one launch per layer (0) by timing `steps` whole steps with each (rounded
+ * up to whole six-step graphs, after about `steps` / 4 + 6 untimed ones); the
+ * simulation advances by every step taken,
+ * as lbrmt_step would (results do not depend on the choice).  Only a context
+ * with one solid on walled axes and at most 11 layers has the choice; any
+ * other leaves the option and the state as they are.  best_fused / best_ms
+ * (nullable): the choice and its time per step.  Synchronises the stream.
+ * ESTATE before init, on a batch member or with several solids; EINVAL for
+ * steps < 1. */
+int lbrmt_autotune_steps(lbrmt_ctx* ctx, int32_t steps, int32_t* best_fused, double* best_ms);
 
 /* ---------------------------------------------------------------- batches
  * Many independent simulations (members) of any sizes stepped together: each

@@ -1048,18 +1048,17 @@ __global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict
 // first to the last, every target of the layer lists that lies in a listed
 // tile at or after the layer where that tile stopped (full scan windows up to
 // r_max, the per-layer path's fit), then clears that list and the list of
-// zone tiles.  With no tile stopped it only clears the lists.
+// zone tiles.  With no tile stopped it only clears the lists.  A block of
+// FF_REST_THREADS threads finds a free slot beside the bulk update sooner
+// than one that needs a whole compute unit.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_fit_rest(GridP g, const Win* __restrict__ win, int wcur,
-                                                   int wprev, int8_t* tag,
-                                                   const int* __restrict__ lists,
-                                                   const int* __restrict__ lcount,
-                                                   const T* __restrict__ phin, T* X1, T* Y1,
-                                                   unsigned* health, int8_t* cut_layer,
-                                                   const int* cut_tiles, int* ncut,
-                                                   int* ff_flag, const int* ff_list, int* ff_n)
+__global__ __launch_bounds__(FF_REST_THREADS) void k_fit_rest(
+    GridP g, const Win* __restrict__ win, int wcur, int wprev, int8_t* tag,
+    const int* __restrict__ lists, const int* __restrict__ lcount, const T* __restrict__ phin,
+    T* X1, T* Y1, unsigned* health, int8_t* cut_layer, const int* cut_tiles, int* ncut,
+    int* ff_flag, const int* ff_list, int* ff_n)
 {
-    constexpr int NG = 1024 / FIT_LANES;
+    constexpr int NG = FF_REST_THREADS / FIT_LANES;
     // the tile list of the next step starts empty
     const int nt = *ff_n;
     for (int a = threadIdx.x; a < nt; a += blockDim.x) ff_flag[ff_list[a]] = 0;
@@ -1124,7 +1123,7 @@ hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlot
         if (fused_threads == 256) FUSED(T, 256);                                                  \
         else if (fused_threads == 512) FUSED(T, 512);                                             \
         else FUSED(T, 1024);                                                                      \
-        k_fit_rest<T><<<1, 1024, 0, st>>>(g, bb.win, s.wcur, s.wprev, bb.tag, bb.lists,           \
+        k_fit_rest<T><<<1, FF_REST_THREADS, 0, st>>>(g, bb.win, s.wcur, s.wprev, bb.tag, bb.lists,\
                                           bb.lcount, (const T*)bb.phi[s.cur], (T*)bb.X[s.nxt],    \
                                           (T*)bb.Y[s.nxt], bb.health, bb.cut_layer,               \
                                           bb.cut_tiles, bb.ncut, bb.ff_flag, bb.ff_list,          \

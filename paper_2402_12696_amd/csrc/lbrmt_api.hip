@@ -187,7 +187,7 @@ struct lbrmt_ctx {
     hipStream_t st = nullptr;
     hipStream_t side = nullptr;
     hipStream_t cap = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_adv = nullptr;
     char* ws = nullptr;
     void* lat[2];
     double *Fx[2], *Fy[2], *drho;
@@ -335,17 +335,9 @@ static StampValid prev_valid(const lbrmt_ctx* c)
 }
 
 // enqueue step n: band chain on `band`, LB on `main_s`
-// Block size of the one-launch extrapolation, 0 for one launch per layer.
-// By default the one launch, except for graph-replayed steps that overlap the
-// chain with the bulk update of a lattice above 2^21 nodes: there the bulk
-// update crowds out its 1024-thread blocks (measured on MI355X, FP64 cavity:
-// 12-16 % faster steps at 64^2 to 1024^2, 7 % slower at 2048^2).
-static int fused_threads(const lbrmt_ctx* c)
-{
-    if (c->fused_fit >= 0) return c->fused_fit;
-    const bool crowded = c->overlap && c->graph && (long long)c->d.nx * c->d.ny > (1ll << 21);
-    return crowded ? 0 : 1024;
-}
+// Block size of the one-launch extrapolation (default 1024), 0 for one
+// launch per layer.
+static int fused_threads(const lbrmt_ctx* c) { return c->fused_fit >= 0 ? c->fused_fit : 1024; }
 
 static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
 {
@@ -372,6 +364,11 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
                                            c->Fy[s.nxt], band, fused));
             b.done();
         }
+        // with the one-launch extrapolation the bulk update starts when the
+        // advection pass ends: the extrapolation's few large blocks are then
+        // resident before the bulk update's many fill the compute units
+        const bool hold_bulk = c->overlap && fused;
+        if (hold_bulk) HIPCHK(c, hipEventRecord(c->ev_adv, band));
         {
             Bracket b(c, 1, band);
             HIPCHK(c, launch_extrapolate(g, c->bb, s, band, fused ? ff : 0));
@@ -386,6 +383,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
         }
         if (c->overlap) {
             HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+            if (hold_bulk) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_adv, 0));
             {
                 Bracket b(c, 4, main_s);
                 HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
@@ -581,6 +579,7 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_adv, hipEventDisableTiming);
     if (e != hipSuccess) {
         int rc = fail(c, "stream/event creation", e);
         lbrmt_destroy(c);
@@ -609,6 +608,7 @@ void lbrmt_destroy(lbrmt_ctx* c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_adv) (void)hipEventDestroy(c->ev_adv);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
@@ -1554,6 +1554,53 @@ int lbrmt_autotune(lbrmt_ctx* c, int32_t reps, int32_t* best_variant, double* be
     if (rc != LBRMT_OK) return rc;
     if (best_variant) *best_variant = best;
     if (best_ms) *best_ms = best_t / reps;
+    return LBRMT_OK;
+}
+
+int lbrmt_autotune_steps(lbrmt_ctx* c, int32_t steps, int32_t* best_fused, double* best_ms)
+{
+    if (!c || steps < 1) return LBRMT_EINVAL;
+    if (!c->inited || c->member || c->multi) return LBRMT_ESTATE;
+    if (c->nsolid == 0 || !fused_fit_ok(c->g)) {
+        if (best_fused) *best_fused = c->fused_fit;
+        if (best_ms) *best_ms = 0.0;
+        return LBRMT_OK;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    const int modes[2] = {1024, 0};
+    const long long timed = ((long long)steps + GRAPH_STEPS - 1) / GRAPH_STEPS * GRAPH_STEPS;
+    int best = modes[0];
+    float best_t = 1e30f;
+    int rc = LBRMT_OK;
+    for (int m = 0; m < 2 && rc == LBRMT_OK; m++) {
+        rc = lbrmt_set_option(c, LBRMT_OPT_FUSED_FIT, modes[m]);
+        // warm-up (and graph capture), ending on a six-step boundary so that
+        // the timed steps are whole graph replays
+        long long warm = steps / 4 + GRAPH_STEPS;
+        warm += (GRAPH_STEPS - (c->step + warm) % GRAPH_STEPS) % GRAPH_STEPS;
+        if (rc == LBRMT_OK) rc = lbrmt_step(c, warm);
+        if (rc != LBRMT_OK) break;
+        HIPCHK(c, hipEventRecord(a, c->st));
+        rc = lbrmt_step(c, timed);
+        if (rc != LBRMT_OK) break;
+        HIPCHK(c, hipEventRecord(b, c->st));
+        HIPCHK(c, hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, a, b));
+        if (ms < best_t) {
+            best_t = ms;
+            best = modes[m];
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != LBRMT_OK) return rc;
+    rc = lbrmt_set_option(c, LBRMT_OPT_FUSED_FIT, best);
+    if (rc != LBRMT_OK) return rc;
+    if (best_fused) *best_fused = best;
+    if (best_ms) *best_ms = best_t / (double)timed;
     return LBRMT_OK;
 }
 

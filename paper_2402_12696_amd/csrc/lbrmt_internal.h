@@ -29,6 +29,7 @@ constexpr int FF_TILE = 32;           // fused extrapolation: tile side
 constexpr int FF_LAYERS = 11;         // fused extrapolation: most layers
 constexpr int FF_BLOCKS = 256;        // fused extrapolation: blocks striding over its tile list
 constexpr int FF_NO_CUT = 127;        // tile not stopped (cut_layer)
+constexpr int FF_REST_THREADS = 256;  // fused extrapolation: the one-block pass
 
 // Several solids: the lattice is cut into force blocks of FB x FB nodes;
 // a block holds valid force planes at step n when its stamp equals n + 1.

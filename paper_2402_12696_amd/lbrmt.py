@@ -136,6 +136,8 @@ def lib():
                                                 ctypes.POINTER(ctypes.c_int64)]),
             "lbrmt_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_double)]),
+            "lbrmt_autotune_steps": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_double)]),
             "lbrmt_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(lbrmt_grid_desc),
                                                            ctypes.c_int32,
                                                            ctypes.POINTER(ctypes.c_size_t)]),
@@ -393,6 +395,13 @@ def lbrmt_autotune(ctx, reps=5):
     return v.value, ms.value
 
 
+def lbrmt_autotune_steps(ctx, steps=60):
+    v, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().lbrmt_autotune_steps(ctx, int(steps), ctypes.byref(v), ctypes.byref(ms)),
+           "lbrmt_autotune_steps", ctx)
+    return v.value, ms.value
+
+
 def _bcheck(rc, where, batch=None):
     if rc != LBRMT_OK:
         detail = lib().lbrmt_batch_last_error(batch).decode() if batch else ""
@@ -604,6 +613,11 @@ class Sim:
 
     def autotune(self, reps=5):
         return lbrmt_autotune(self.ctx, reps)
+
+    def autotune_steps(self, steps=60):
+        """Chooses the extrapolation launch mode by timing whole steps (the
+        simulation advances by them); returns (LBRMT_OPT_FUSED_FIT, ms/step)."""
+        return lbrmt_autotune_steps(self.ctx, steps)
 
 
 class Batch:

@@ -76,3 +76,33 @@ def test_fused_fit_option_values():
         with pytest.raises(Exception):
             sim.set_option(B.LBRMT_OPT_FUSED_FIT, v)
     sim.close()
+
+
+def test_autotune_steps_chooses_a_mode_and_steps_like_lbrmt_step():
+    from paper_2402_12696_amd import Sim
+    from paper_2402_12696_amd import lbrmt as B
+    cfg = workloads.cavity_disc_64()
+    a = Sim(device="cuda:0", precision="f64", **cfg).init()
+    a.step(5)
+    mode, ms = a.autotune_steps(30)
+    assert mode in (0, 1024) and ms > 0.0
+    assert a.get_option(B.LBRMT_OPT_FUSED_FIT) == mode
+    n = a.step_count
+    assert n >= 5 + 2 * 30
+    a.step(7)
+    sa = _state(a)
+    a.close()
+    b = Sim(device="cuda:0", precision="f64", **cfg)
+    b.set_option(B.LBRMT_OPT_FUSED_FIT, 0)
+    b.init()
+    b.step(n + 7)
+    assert _equal(sa, _state(b))
+    b.close()
+    # several solids: no choice to make
+    s = Sim(device="cuda:0", precision="f64", **workloads.make(
+        nx=64, ny=64, tau=0.8, lid_ux=0.05,
+        solids=[dict(cx=20.0, cy=32.0, R=6.0, G=0.01, rho_s=1.0),
+                dict(cx=44.0, cy=32.0, R=6.0, G=0.01, rho_s=1.0)])).init()
+    with pytest.raises(Exception):
+        s.autotune_steps(12)
+    s.close()
