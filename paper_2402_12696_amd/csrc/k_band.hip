@@ -778,17 +778,11 @@ __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l,
     }
 }
 
-// scan window of half-width r = side / 2: reduced normal equations and the
-// intercept, if the window holds three valid nodes and the fit is well posed
+// the group's sums reduced across its lanes, then the intercept, if the
+// window held three valid nodes and the fit is well posed
 template <typename T>
-__device__ __forceinline__ bool fit_at(const GridP& g, const Rect& W, int l, int i, int j, int kt,
-                                       int r, int sub, bool use_n, double nxh, double nyh,
-                                       const int8_t* tag, const T* X1, const T* Y1, T& xo, T& yo)
+__device__ __forceinline__ bool fit_finish(const GridP& g, Fit<T>& f, int count, T& xo, T& yo)
 {
-    Fit<T> f;
-    f.zero();
-    int count = 0;
-    fit_window<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, f, count);
     count = group_sum(count);
     if (count < 3) return false;
     f.M00 = group_sum(f.M00);
@@ -806,33 +800,89 @@ __device__ __forceinline__ bool fit_at(const GridP& g, const Rect& W, int l, int
     return f.solve(g.det_rel, xo, yo);
 }
 
+// scan window of half-width r = side / 2: reduced normal equations and the
+// intercept, if the window holds three valid nodes and the fit is well posed
+template <typename T>
+__device__ __forceinline__ bool fit_at(const GridP& g, const Rect& W, int l, int i, int j, int kt,
+                                       int r, int sub, bool use_n, double nxh, double nyh,
+                                       const int8_t* tag, const T* X1, const T* Y1, T& xo, T& yo)
+{
+    Fit<T> f;
+    f.zero();
+    int count = 0;
+    fit_window<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, f, count);
+    return fit_finish<T>(g, f, count, xo, yo);
+}
+
+// fit_window over the block's staged copy of the zone (tags st, values sx,
+// sy on a row-major region of rw columns; (li, lj) the target's place in it):
+// the same nodes in the same lanes and the same order of additions, so the
+// same bits
+template <typename T>
+__device__ __forceinline__ void fit_window_lds(int l, int li, int lj, int r, int sub, bool use_n,
+                                               double nxh, double nyh, const int8_t* st,
+                                               const T* sx, const T* sy, int rw, Fit<T>& f,
+                                               int& count)
+{
+    constexpr int PER = 4;
+    const int side = 2 * r + 1, nq = side * side;
+    int a = sub % side - r, b = sub / side - r;
+    for (int q0 = sub; q0 < nq; q0 += PER * FIT_LANES) {
+        int kk[PER], aa[PER], bb[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            aa[u] = a;
+            bb[u] = b;
+            kk[u] = q0 + u * FIT_LANES < nq ? (lj + b) * rw + li + a : -1;
+            a += FIT_LANES;
+            while (a > r) {
+                a -= side;
+                b += 1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            if (kk[u] < 0 || !tag_valid_before(st[kk[u]], l)) continue;
+            count++;
+            f.add(aa[u], bb[u], use_n, nxh, nyh, sx[kk[u]], sy[kk[u]]);
+        }
+    }
+}
+
 // Fit of one target kt = (i, j) of layer l by the FIT_LANES lanes of a group
 // (every lane of the group calls it with the same target): the outward normal
 // of phi^n for layers 1 and 2, then scan windows of half-width r = 2 .. r_max
 // until one holds three valid nodes and a well-posed fit.  Windows wider than
 // rlim are not tried: if the fit needs one, the result is false with cut set.
+// outward normal of phi^n at target (i, j) for the weights of layers 1 and 2:
+// lanes 0..3 of the group load the four neighbours
+template <typename T>
+__device__ __forceinline__ bool target_normal(const GridP& g, const Rect& D, int l, int i, int j,
+                                              int sub, const T* __restrict__ phin, double& nxh,
+                                              double& nyh)
+{
+    nxh = nyh = 0.0;
+    if (l > 2) return false;
+    double p = INFINITY;
+    if (sub < 4) {
+        const int di = sub == 0 ? 1 : sub == 1 ? -1 : 0;
+        const int dj = sub == 2 ? 1 : sub == 3 ? -1 : 0;
+        const long long kq = ref_index(g, D, i + di, j + dj);
+        if (kq >= 0) p = (double)phin[kq];
+    }
+    const double pe = __shfl(p, 0, FIT_LANES), pw = __shfl(p, 1, FIT_LANES);
+    const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
+    return normal_from(pe, pw, pn, ps, nxh, nyh);
+}
+
 template <typename T>
 __device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const Rect& D, int l,
                                            int kt, int i, int j, int sub, int rlim,
                                            const int8_t* tag, const T* __restrict__ phin,
                                            const T* X1, const T* Y1, T& xo, T& yo, bool& cut)
 {
-    // outward normal of phi^n at the target (layers 1, 2): lanes 0..3 load
-    // the four neighbours
-    double nxh = 0.0, nyh = 0.0;
-    bool use_n = false;
-    if (l <= 2) {
-        double p = INFINITY;
-        if (sub < 4) {
-            const int di = sub == 0 ? 1 : sub == 1 ? -1 : 0;
-            const int dj = sub == 2 ? 1 : sub == 3 ? -1 : 0;
-            const long long kq = ref_index(g, D, i + di, j + dj);
-            if (kq >= 0) p = (double)phin[kq];
-        }
-        const double pe = __shfl(p, 0, FIT_LANES), pw = __shfl(p, 1, FIT_LANES);
-        const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
-        use_n = normal_from(pe, pw, pn, ps, nxh, nyh);
-    }
+    double nxh, nyh;
+    const bool use_n = target_normal<T>(g, D, l, i, j, sub, phin, nxh, nyh);
     cut = false;
     for (int r = 2; r <= g.r_max; r++) {
         if (r > rlim) {
@@ -841,6 +891,32 @@ __device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const 
         }
         if (fit_at<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, xo, yo))
             return true;
+    }
+    return false;
+}
+
+// fit_target with the scan windows read from the block's staged copy of the
+// zone ((li, lj): the target's place in it)
+template <typename T>
+__device__ __forceinline__ bool fit_target_lds(const GridP& g, const Rect& D, int l, int i, int j,
+                                               int li, int lj, int sub, int rlim,
+                                               const T* __restrict__ phin, const int8_t* st,
+                                               const T* sx, const T* sy, int rw, T& xo, T& yo,
+                                               bool& cut)
+{
+    double nxh, nyh;
+    const bool use_n = target_normal<T>(g, D, l, i, j, sub, phin, nxh, nyh);
+    cut = false;
+    for (int r = 2; r <= g.r_max; r++) {
+        if (r > rlim) {
+            cut = true;
+            return false;
+        }
+        Fit<T> f;
+        f.zero();
+        int count = 0;
+        fit_window_lds<T>(l, li, lj, r, sub, use_n, nxh, nyh, st, sx, sy, rw, f, count);
+        if (fit_finish<T>(g, f, count, xo, yo)) return true;
     }
     return false;
 }
@@ -929,150 +1005,23 @@ __global__ __launch_bounds__(1024) void kb_fit_layers(const FitArgs* __restrict_
     }
 }
 
-// All layers of one solid in one launch.  Block b takes FF_TILE x FF_TILE
-// tiles of the window from the list the distance transform made of the tiles
-// the zone reaches; for layer l it fits every layer-l target within
-// M_l = 2 (L - l) nodes of its tile, its own and those of the tiles around
-// (recomputed, with the same arithmetic, so a node fitted by several blocks
-// gets the same bits from each), then a block barrier, then layer l + 1.  A
-// scan window of half-width 2 around a target within M_l of the tile stays
-// within M_l + 2 = M_{l-1}, where the block has fitted every earlier layer,
-// so the block never reads a value another block has yet to write.  A target
-// that needs a wider window than that region allows stops the tile at that
-// layer: the tile is listed, with the layer, for k_fit_rest, which finishes
-// the listed tiles layer by layer; its layers before that one are final.
-// Layer-1 windows read solid nodes only, which the advection pass wrote.
-// reach = 2; reach = 1 stops every tile with a target on the rim of its
-// margin at layer 2 (the second launch then fits most of the zone: a check
-// of that launch).
-// Walled axes only (a window across a periodic seam would reach another
-// tile's nodes).
+// The tiles k_fit_fused stopped (k_fit_rest, one block): fits, layer by
+// layer from the first to the last, every target of the layer lists that
+// lies in a stopped tile at or after the layer where that tile stopped (full
+// scan windows up to r_max, the per-layer path's fit), then clears that list
+// and the list of zone tiles.  With no tile stopped it only clears the lists.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict__ win, int wcur,
-                                                  int wprev, int8_t* tag,
-                                                  const T* __restrict__ phin, T* X1, T* Y1,
-                                                  unsigned* health, int8_t* cut_layer,
-                                                  int* cut_tiles, int* ncut,
-                                                  const int* __restrict__ ff_list,
-                                                  const int* __restrict__ ff_n, int reach)
+__device__ void fit_rest(const GridP& g, const Rect& W, const Rect& D, int8_t* tag,
+                         const int* __restrict__ lists, const int* __restrict__ lcount,
+                         const T* __restrict__ phin, T* X1, T* Y1, unsigned* health,
+                         int8_t* cut_layer, const int* cut_tiles, int* ncut, int* ff_flag,
+                         const int* ff_list, int* ff_n)
 {
-    constexpr int RW = FF_TILE + 4 * (FF_LAYERS - 1);
     constexpr int NG = NT / FIT_LANES;
-    __shared__ int8_t st[RW * RW];  // tags of the tile and its layer-1 margin
-    __shared__ int lst[RW * RW];    // targets of the current layer
-    __shared__ int s_n, s_cut, s_fail;
-    const int ntile = *ff_n;
-    if (blockIdx.x >= ntile) return;
-    const Rect W = window_of(win, wcur, g);
-    if (!W.ok) return;
-    const Rect D = window_of(win, wprev, g);
-    const int L = g.layers;
-    const int MR = 2 * (L - 1), rw = FF_TILE + 2 * MR;
-    const int ntx = (W.i1 - W.i0 + FF_TILE) / FF_TILE;
-    const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
-    for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
-        const int t = ff_list[k];
-        const int x0 = W.i0 + (t % ntx) * FF_TILE, y0 = W.j0 + (t / ntx) * FF_TILE;
-        __syncthreads();  // the previous tile's shared state is no longer read
-        if (threadIdx.x == 0) {
-            s_n = 0;
-            s_cut = 0;
-            s_fail = 0;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < rw * rw; e += NT) {
-            const int x = x0 - MR + e % rw, y = y0 - MR + e / rw;
-            int8_t tv = W.has(x, y) ? tag[pidx(g, x, y)] : (int8_t)TAG_NONE;
-            // a block that fitted this node in its margin may have marked it
-            // failed already: it is fitted here again (to the same verdict),
-            // so that the tile's own failures are counted by the tile's block
-            if (tv > 0) tv = (int8_t)(tv & (TAG_FAIL - 1));
-            st[e] = tv;
-        }
-        __syncthreads();
-        for (int l = 1; l <= L; l++) {
-            const int M = 2 * (L - l), side = FF_TILE + 2 * M, off = MR - M;
-            for (int e = threadIdx.x; e < side * side; e += NT) {
-                const int lx = off + e % side, ly = off + e / side;
-                if (st[ly * rw + lx] == l)
-                    lst[atomicAdd(&s_n, 1)] = (int)pidx(g, x0 - MR + lx, y0 - MR + ly);
-            }
-            __syncthreads();
-            const int n = s_n;
-            // earlier layers are fitted within M + 2 of the tile (reach < 2
-            // narrows what a fit may read, so that more tiles stop)
-            const int K = M + reach;
-            for (int a = grp; a < n; a += NG) {
-                const int kt = lst[a];
-                const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
-                int rlim = g.r_max;
-                if (l > 1)
-                    rlim = min(rlim, min(min(i - (x0 - K), x0 + FF_TILE - 1 + K - i),
-                                         min(j - (y0 - K), y0 + FF_TILE - 1 + K - j)));
-                T xo = T(0), yo = T(0);
-                bool cut;
-                const bool done = fit_target<T>(g, W, D, l, kt, i, j, sub, rlim, tag, phin, X1,
-                                                Y1, xo, yo, cut);
-                if (sub == 0) {
-                    if (done) {
-                        X1[kt] = xo;
-                        Y1[kt] = yo;
-                    } else if (cut) {
-                        s_cut = 1;
-                    } else {
-                        tag[kt] = (int8_t)(l | TAG_FAIL);
-                        if (i >= x0 && i < x0 + FF_TILE && j >= y0 && j < y0 + FF_TILE)
-                            atomicAdd(&s_fail, 1);
-                    }
-                }
-            }
-            __syncthreads();
-            const bool stop = s_cut != 0;
-            if (threadIdx.x == 0) {
-                if (stop) {
-                    cut_layer[t] = (int8_t)l;
-                    cut_tiles[atomicAdd(ncut, 1)] = t;
-                } else if (s_fail > 0) {
-                    atomicAdd(&health[1], (unsigned)s_fail);
-                }
-                s_n = 0;
-                s_fail = 0;
-            }
-            __syncthreads();
-            if (stop) break;
-        }
-    }
-}
-
-// The tiles k_fit_fused stopped: one block fits, layer by layer from the
-// first to the last, every target of the layer lists that lies in a listed
-// tile at or after the layer where that tile stopped (full scan windows up to
-// r_max, the per-layer path's fit), then clears that list and the list of
-// zone tiles.  With no tile stopped it only clears the lists.  A block of
-// FF_REST_THREADS threads finds a free slot beside the bulk update sooner
-// than one that needs a whole compute unit.
-template <typename T>
-__global__ __launch_bounds__(FF_REST_THREADS) void k_fit_rest(
-    GridP g, const Win* __restrict__ win, int wcur, int wprev, int8_t* tag,
-    const int* __restrict__ lists, const int* __restrict__ lcount, const T* __restrict__ phin,
-    T* X1, T* Y1, unsigned* health, int8_t* cut_layer, const int* cut_tiles, int* ncut,
-    int* ff_flag, const int* ff_list, int* ff_n)
-{
-    constexpr int NG = FF_REST_THREADS / FIT_LANES;
-    // the tile list of the next step starts empty
-    const int nt = *ff_n;
-    for (int a = threadIdx.x; a < nt; a += blockDim.x) ff_flag[ff_list[a]] = 0;
-    const int nc = *ncut;
-    if (nc == 0) {
-        __syncthreads();
-        if (threadIdx.x == 0) *ff_n = 0;
-        return;
-    }
-    const Rect W = window_of(win, wcur, g);
-    const Rect D = window_of(win, wprev, g);
+    const int nt = *ff_n, nc = *ncut;
     const long long cap = g.lcap;
     const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
-    if (W.ok) {
+    if (nc > 0) {
         const int ntx = (W.i1 - W.i0 + FF_TILE) / FF_TILE;
         for (int l = 1; l <= g.layers; l++) {
             for (int s = 0; s < NSUB; s++) {
@@ -1101,12 +1050,157 @@ __global__ __launch_bounds__(FF_REST_THREADS) void k_fit_rest(
             __syncthreads();
         }
     }
-    for (int a = threadIdx.x; a < nc; a += blockDim.x) cut_layer[cut_tiles[a]] = FF_NO_CUT;
+    // the lists of the next step start empty
+    for (int a = threadIdx.x; a < nt; a += NT) ff_flag[ff_list[a]] = 0;
+    for (int a = threadIdx.x; a < nc; a += NT) cut_layer[cut_tiles[a]] = FF_NO_CUT;
     __syncthreads();
     if (threadIdx.x == 0) {
         *ncut = 0;
         *ff_n = 0;
     }
+}
+
+// All layers of one solid in one launch.  Block b takes FF_TILE x FF_TILE
+// tiles of the window from the list the distance transform made of the tiles
+// the zone reaches; for layer l it fits every layer-l target within
+// M_l = 2 (L - l) nodes of its tile, its own and those of the tiles around
+// (recomputed, with the same arithmetic, so the same bits as their own
+// blocks find), then a block barrier, then layer l + 1.  The block works on a
+// copy in LDS: the tags and the advected solid values of the tile and a
+// margin of M_1 + 2 nodes are staged once, and each fitted value (or failure)
+// goes into the copy; only the tile's own targets are written back.  A scan
+// window of half-width 2 around a target within M_l of the tile stays within
+// M_l + 2 = M_{l-1}, where the copy holds every earlier layer, and layer-1
+// windows read solid nodes only, which the copy holds across the margin.  A
+// target that needs a wider window than that stops the tile at that layer:
+// the tile is listed, with the layer, for k_fit_rest, which finishes the
+// listed tiles layer by layer; the tile's layers before that one are final.
+// reach = 2; reach = 1 stops every tile with a target on the rim of its
+// margin at layer 2 (k_fit_rest then fits most of the zone: a check of that
+// launch).  Walled axes only (a window across a periodic seam would
+// reach another tile's nodes).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict__ win, int wcur,
+                                                  int wprev, int8_t* tag,
+                                                  const T* __restrict__ phin, T* X1, T* Y1,
+                                                  unsigned* health, int8_t* cut_layer,
+                                                  int* cut_tiles, int* ncut,
+                                                  const int* __restrict__ ff_list,
+                                                  const int* __restrict__ ff_n, int reach)
+{
+    constexpr int RW = FF_TILE + 4 * (FF_LAYERS - 1) + 4;
+    constexpr int NG = NT / FIT_LANES;
+    __shared__ int8_t st[RW * RW];  // tags of the tile and its margin
+    __shared__ T sx[RW * RW];       // xi (or the displacement): solid nodes, then fitted ones
+    __shared__ T sy[RW * RW];
+    __shared__ short lst[RW * RW];  // targets of the current layer (places in the copy)
+    __shared__ int s_n, s_cut, s_fail;
+    const int ntile = *ff_n;
+    if (blockIdx.x >= ntile) return;
+    const Rect W = window_of(win, wcur, g);
+    if (!W.ok) return;
+    const Rect D = window_of(win, wprev, g);
+    const int L = g.layers;
+    const int S = 2 * (L - 1) + 2, rw = FF_TILE + 2 * S;  // margin of the copy, its width
+    const int ntx = (W.i1 - W.i0 + FF_TILE) / FF_TILE;
+    const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
+    for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
+        const int t = ff_list[k];
+        const int x0 = W.i0 + (t % ntx) * FF_TILE, y0 = W.j0 + (t / ntx) * FF_TILE;
+        __syncthreads();  // the previous tile's shared state is no longer read
+        if (threadIdx.x == 0) {
+            s_n = 0;
+            s_cut = 0;
+            s_fail = 0;
+        }
+        for (int e = threadIdx.x; e < rw * rw; e += NT) {
+            const int x = x0 - S + e % rw, y = y0 - S + e / rw;
+            const bool in = W.has(x, y);
+            const long long kq = pidx(g, in ? x : W.i0, in ? y : W.j0);
+            int8_t tv = in ? tag[kq] : (int8_t)TAG_NONE;
+            // the owner of a margin node may have marked it failed already:
+            // it is fitted here again, to the same verdict
+            if (tv > 0) tv = (int8_t)(tv & (TAG_FAIL - 1));
+            st[e] = tv;
+            if (tv == TAG_SOLID) {
+                sx[e] = X1[kq];
+                sy[e] = Y1[kq];
+            }
+        }
+        __syncthreads();
+        for (int l = 1; l <= L; l++) {
+            const int M = 2 * (L - l), side = FF_TILE + 2 * M, off = S - M;
+            for (int e = threadIdx.x; e < side * side; e += NT) {
+                const int q = (off + e / side) * rw + off + e % side;
+                if (st[q] == l) lst[atomicAdd(&s_n, 1)] = (short)q;
+            }
+            __syncthreads();
+            const int n = s_n;
+            // the copy holds layer-(l-1) values within K of the tile (layer
+            // 1: solid values across the whole copy); reach < 2 narrows it
+            const int K = l == 1 ? S : M + reach;
+            for (int a = grp; a < n; a += NG) {
+                const int q = lst[a];
+                const int li = q % rw, lj = q / rw;
+                const int i = x0 - S + li, j = y0 - S + lj;
+                const int rlim = min(g.r_max, min(min(li - (S - K), S + FF_TILE - 1 + K - li),
+                                                  min(lj - (S - K), S + FF_TILE - 1 + K - lj)));
+                T xo = T(0), yo = T(0);
+                bool cut;
+                const bool done = fit_target_lds<T>(g, D, l, i, j, li, lj, sub, rlim, phin, st,
+                                                    sx, sy, rw, xo, yo, cut);
+                if (sub == 0) {
+                    const bool own = i >= x0 && i < x0 + FF_TILE && j >= y0 && j < y0 + FF_TILE;
+                    const long long kt = pidx(g, i, j);
+                    if (done) {
+                        sx[q] = xo;
+                        sy[q] = yo;
+                        if (own) {
+                            X1[kt] = xo;
+                            Y1[kt] = yo;
+                        }
+                    } else if (cut) {
+                        s_cut = 1;
+                    } else {
+                        st[q] = (int8_t)(l | TAG_FAIL);
+                        if (own) {
+                            tag[kt] = (int8_t)(l | TAG_FAIL);
+                            atomicAdd(&s_fail, 1);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const bool stop = s_cut != 0;
+            if (threadIdx.x == 0) {
+                if (stop) {
+                    cut_layer[t] = (int8_t)l;
+                    cut_tiles[atomicAdd(ncut, 1)] = t;
+                } else if (s_fail > 0) {
+                    atomicAdd(&health[1], (unsigned)s_fail);
+                }
+                s_n = 0;
+                s_fail = 0;
+            }
+            __syncthreads();
+            if (stop) break;
+        }
+    }
+}
+
+// fit_rest in a block of FF_REST_THREADS threads, which finds a free slot
+// beside the bulk update sooner than one that needs a whole compute unit
+template <typename T>
+__global__ __launch_bounds__(FF_REST_THREADS) void k_fit_rest(
+    GridP g, const Win* __restrict__ win, int wcur, int wprev, int8_t* tag,
+    const int* __restrict__ lists, const int* __restrict__ lcount, const T* __restrict__ phin,
+    T* X1, T* Y1, unsigned* health, int8_t* cut_layer, const int* cut_tiles, int* ncut,
+    int* ff_flag, const int* ff_list, int* ff_n)
+{
+    const Rect W = window_of(win, wcur, g);
+    const Rect D = window_of(win, wprev, g);
+    fit_rest<T, FF_REST_THREADS>(g, W, D, tag, lists, lcount, phin, X1, Y1, health, cut_layer,
+                                 cut_tiles, ncut, ff_flag, ff_list, ff_n);
 }
 
 hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
@@ -1123,11 +1217,10 @@ hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlot
         if (fused_threads == 256) FUSED(T, 256);                                                  \
         else if (fused_threads == 512) FUSED(T, 512);                                             \
         else FUSED(T, 1024);                                                                      \
-        k_fit_rest<T><<<1, FF_REST_THREADS, 0, st>>>(g, bb.win, s.wcur, s.wprev, bb.tag, bb.lists,\
-                                          bb.lcount, (const T*)bb.phi[s.cur], (T*)bb.X[s.nxt],    \
-                                          (T*)bb.Y[s.nxt], bb.health, bb.cut_layer,               \
-                                          bb.cut_tiles, bb.ncut, bb.ff_flag, bb.ff_list,          \
-                                          bb.ff_n);                                               \
+        k_fit_rest<T><<<1, FF_REST_THREADS, 0, st>>>(                                             \
+            g, bb.win, s.wcur, s.wprev, bb.tag, bb.lists, bb.lcount, (const T*)bb.phi[s.cur],     \
+            (T*)bb.X[s.nxt], (T*)bb.Y[s.nxt], bb.health, bb.cut_layer, bb.cut_tiles, bb.ncut,     \
+            bb.ff_flag, bb.ff_list, bb.ff_n);                                                     \
     } while (0)
         if (g.rm32) FUSED_T(float);
         else FUSED_T(double);

@@ -809,7 +809,7 @@ static int init_mb(lbrmt_ctx* c, const double* d_u0)
     return LBRMT_OK;
 }
 
-// the fused extrapolation's tile list starts empty (k_fit_rest leaves it so)
+// the fused extrapolation's tile lists start empty (k_fit_rest leaves them so)
 static hipError_t clear_cut_tiles(lbrmt_ctx* c, hipStream_t st)
 {
     if (c->multi) return hipSuccess;  // several solids: no fused extrapolation

@@ -491,7 +491,7 @@ hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStrea
 // fused_threads 256 / 512 / 1024: all layers in one k_fit_fused launch of
 // that block size (walled axes, at most FF_LAYERS layers; else, and for 0,
 // one launch per layer); 1: 1024 threads with the fits' reach narrowed by one
-// node, so that the second launch takes over most tiles
+// node, so that the one-block pass over stopped tiles takes most of them
 hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
                               hipStream_t st, int fused_threads);
 inline bool fused_fit_ok(const GridP& g) { return !g.px && !g.py && g.layers <= FF_LAYERS; }
