@@ -106,3 +106,33 @@ def test_autotune_steps_chooses_a_mode_and_steps_like_lbrmt_step():
     with pytest.raises(Exception):
         s.autotune_steps(12)
     s.close()
+
+
+NEAR_WALL = workloads.make(nx=96, ny=80, tau=0.8, lid_ux=0.06,
+                           solid=dict(cx=30.0, cy=14.5, R=11.0, G=0.01, rho_s=1.0))
+
+
+@pytest.mark.parametrize("name,cfg,steps", [
+    ("near_wall", NEAR_WALL, 120),
+    ("layers3", dict(workloads.cavity_disc_64(), layers=3), 150),
+    ("layers7", dict(workloads.cavity_disc_64(), layers=7), 150),
+    ("rmax2_thin", dict(THIN, r_max=2), 120),
+])
+def test_one_launch_extrapolation_edge_cases(name, cfg, steps):
+    # a window clipped by the walls; fewer layers (narrower margins); scan
+    # windows capped at r = 2, so that fits fail and are counted
+    for prec in ("f64", "f32"):
+        ref = _run(cfg, prec, 0, steps)
+        print(name, prec, ref[6])
+        if name == "rmax2_thin":
+            assert ref[6]["extrap_fail"] > 0  # the case exercises failed fits
+        for opt in (1024, 1):
+            assert _equal(ref, _run(cfg, prec, opt, steps)), (name, prec, opt, ref[6])
+
+
+def test_one_launch_extrapolation_with_more_zone_tiles_than_blocks():
+    # a disc of radius 1200 on 4096^2: some 600 zone tiles for 256 blocks
+    cfg = workloads.make(nx=4096, ny=4096, tau=0.6, lid_ux=0.05,
+                         solid=dict(cx=2048.0, cy=2200.0, R=1200.0, G=0.005, rho_s=1.0))
+    ref = _run(cfg, "f32", 0, 12)
+    assert _equal(ref, _run(cfg, "f32", 1024, 12))
