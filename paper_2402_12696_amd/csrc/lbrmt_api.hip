@@ -335,9 +335,14 @@ static StampValid prev_valid(const lbrmt_ctx* c)
 }
 
 // enqueue step n: band chain on `band`, LB on `main_s`
-// Block size of the one-launch extrapolation (default 1024), 0 for one
-// launch per layer.
-static int fused_threads(const lbrmt_ctx* c) { return c->fused_fit >= 0 ? c->fused_fit : 1024; }
+// Block size of the one-launch extrapolation (default 1024; one launch per
+// layer, 0, by default when the bulk update's workgroups are capped), 0 for
+// one launch per layer.
+static int fused_threads(const lbrmt_ctx* c)
+{
+    if (c->fused_fit >= 0) return c->fused_fit;
+    return c->bulk_blocks > 0 ? 0 : 1024;
+}
 
 static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
 {
@@ -366,8 +371,10 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
         }
         // with the one-launch extrapolation the bulk update starts when the
         // advection pass ends: the extrapolation's few large blocks are then
-        // resident before the bulk update's many fill the compute units
-        const bool hold_bulk = c->overlap && fused;
+        // resident before the bulk update's many fill the compute units (not
+        // with a capped bulk update: held and capped at 512 workgroups, steps
+        // stalled for about 0.1 s on MI355X)
+        const bool hold_bulk = c->overlap && fused && c->bulk_blocks == 0;
         if (hold_bulk) HIPCHK(c, hipEventRecord(c->ev_adv, band));
         {
             Bracket b(c, 1, band);
