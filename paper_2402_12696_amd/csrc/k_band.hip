@@ -467,8 +467,31 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
     for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
         const int x0 = W.i0 + (t % ntx) * DTX, y0 = W.j0 + (t / ntx) * DTY;
         if (threadIdx.x <= MAX_LAYERS) cnt[threadIdx.x] = 0;
-        // solid flags of the region (nodes outside the window hold none)
-        for (int e = threadIdx.x; e < rw * rh; e += blockDim.x) {
+        // solid flags of the region (nodes outside the window hold none).
+        // FP32 steps with a compile-time layer count issue all of a thread's
+        // level-set loads before using any (advection pass 25.0 -> 23.1 us
+        // at 2048^2; with FP64 values the extra registers cost as much)
+        constexpr bool PRELOAD = ADV && LC > 0 && sizeof(S) == 4;
+        if (PRELOAD) {
+            constexpr int NE = (DTX + 2 * LC) * (DTY + 2 * LC);
+            constexpr int NS = (NE + 255) / 256;  // 256 threads per block
+            S pv[NS];
+            bool inv[NS];
+#pragma unroll
+            for (int u = 0; u < NS; u++) {
+                const int e = threadIdx.x + u * 256;
+                const int x = x0 - L + e % rw, y = y0 - L + e / rw;
+                inv[u] = e < NE && W.has(x, y) && x >= 0 && x < g.nx && y >= 0 && y < g.ny &&
+                         D.has(x, y);
+                pv[u] = phi[inv[u] ? pidx(g, x, y) : pidx(g, W.i0, W.j0)];
+            }
+#pragma unroll
+            for (int u = 0; u < NS; u++) {
+                const int e = threadIdx.x + u * 256;
+                if (e < NE) sol[(e / rw) * DRW + e % rw] = inv[u] && pv[u] < S(0) ? 1 : 0;
+            }
+        }
+        for (int e = threadIdx.x; !PRELOAD && e < rw * rh; e += blockDim.x) {
             const int x = x0 - L + e % rw, y = y0 - L + e / rw;
             bool s = false;
             if (ADV) {
