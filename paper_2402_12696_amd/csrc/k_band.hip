@@ -742,13 +742,36 @@ __device__ __forceinline__ bool normal_from(double pe, double pw, double pn, dou
     return true;
 }
 
-// sum over the FIT_LANES lanes of a group; the butterfly gives every lane the
-// same bits since each addition sees the same two operands in either order
+// a lane's partner value by a DPP move within its row (no LDS round trip;
+// 64-bit values move as two halves)
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(dpp_move<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    return __hiloint2double(dpp_move<CTRL>(__double2hiint(v)), dpp_move<CTRL>(__double2loint(v)));
+}
+
+// sum over the FIT_LANES = 8 lanes of a group (8 aligned lanes, all active
+// together): lane i adds lane i ^ 1 (quad_perm 1,0,3,2), then lane i ^ 2
+// (quad_perm 2,3,0,1), then the other quad's sum from lane 7 - i (row half
+// mirror).  Every lane ends with the same bits, since each addition sees the
+// same two operands in either order.
+static_assert(FIT_LANES == 8, "group_sum pairs the lanes of an 8-lane group");
 template <typename V>
 __device__ __forceinline__ V group_sum(V v)
 {
-#pragma unroll
-    for (int m = FIT_LANES / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, FIT_LANES);
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
     return v;
 }
 
