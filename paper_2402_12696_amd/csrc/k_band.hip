@@ -874,7 +874,8 @@ __device__ __forceinline__ void fit_window_lds(int l, int li, int lj, int r, int
     const int side = 2 * r + 1, nq = side * side;
     int a = sub % side - r, b = sub / side - r;
     for (int q0 = sub; q0 < nq; q0 += PER * FIT_LANES) {
-        int kk[PER], aa[PER], bb[PER];
+        int kk[PER], aa[PER], bb[PER], tk[PER];
+        T xv[PER], yv[PER];
 #pragma unroll
         for (int u = 0; u < PER; u++) {
             aa[u] = a;
@@ -886,11 +887,20 @@ __device__ __forceinline__ void fit_window_lds(int l, int li, int lj, int r, int
                 b += 1;
             }
         }
+        // every read before any use (a value read for a node that holds none
+        // is never used)
 #pragma unroll
         for (int u = 0; u < PER; u++) {
-            if (kk[u] < 0 || !tag_valid_before(st[kk[u]], l)) continue;
+            const int k = kk[u] >= 0 ? kk[u] : 0;
+            tk[u] = st[k];
+            xv[u] = sx[k];
+            yv[u] = sy[k];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            if (kk[u] < 0 || !tag_valid_before(tk[u], l)) continue;
             count++;
-            f.add(aa[u], bb[u], use_n, nxh, nyh, sx[kk[u]], sy[kk[u]]);
+            f.add(aa[u], bb[u], use_n, nxh, nyh, xv[u], yv[u]);
         }
     }
 }
@@ -1139,7 +1149,9 @@ __global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict
     __shared__ int8_t st[RW * RW];  // tags of the tile and its margin
     __shared__ T sx[RW * RW];       // xi (or the displacement): solid nodes, then fitted ones
     __shared__ T sy[RW * RW];
-    __shared__ short lst[RW * RW];  // targets of the current layer (places in the copy)
+    __shared__ short lst[RW * RW];  // the block's targets, layer by layer (places in the copy)
+    __shared__ short cand[RW * RW];  // the same, in staging order
+    __shared__ int s_cnt[FF_LAYERS + 1], s_base[FF_LAYERS + 2], s_fill[FF_LAYERS + 1];
     __shared__ int s_n, s_cut, s_fail;
     const int ntile = *ff_n;
     if (blockIdx.x >= ntile) return;
@@ -1159,6 +1171,11 @@ __global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict
             s_cut = 0;
             s_fail = 0;
         }
+        if (threadIdx.x <= FF_LAYERS) {
+            s_cnt[threadIdx.x] = 0;
+            s_fill[threadIdx.x] = 0;
+        }
+        __syncthreads();
         for (int e = threadIdx.x; e < rw * rw; e += NT) {
             const int x = x0 - S + e % rw, y = y0 - S + e / rw;
             const bool in = W.has(x, y);
@@ -1172,21 +1189,39 @@ __global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict
                 sx[e] = X1[kq];
                 sy[e] = Y1[kq];
             }
+            // a layer-l node is this block's target within M_l of the tile
+            if (tv >= 1 && tv <= L) {
+                const int dx = max(max(x0 - x, x - (x0 + FF_TILE - 1)), 0);
+                const int dy = max(max(y0 - y, y - (y0 + FF_TILE - 1)), 0);
+                if (max(dx, dy) <= 2 * (L - tv)) {
+                    atomicAdd(&s_cnt[tv], 1);
+                    cand[atomicAdd(&s_n, 1)] = (short)e;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_base[1] = 0;
+            for (int l = 1; l <= L; l++) s_base[l + 1] = s_base[l] + s_cnt[l];
+        }
+        __syncthreads();
+        // the targets sorted by layer (the order within a layer does not
+        // matter: a layer's targets do not read each other)
+        for (int a = threadIdx.x; a < s_n; a += NT) {
+            const int q = cand[a];
+            const int l = st[q];
+            lst[s_base[l] + atomicAdd(&s_fill[l], 1)] = (short)q;
         }
         __syncthreads();
         for (int l = 1; l <= L; l++) {
-            const int M = 2 * (L - l), side = FF_TILE + 2 * M, off = S - M;
-            for (int e = threadIdx.x; e < side * side; e += NT) {
-                const int q = (off + e / side) * rw + off + e % side;
-                if (st[q] == l) lst[atomicAdd(&s_n, 1)] = (short)q;
-            }
-            __syncthreads();
-            const int n = s_n;
+            const int M = 2 * (L - l);
+            const int n = s_cnt[l];
+            const short* lt = lst + s_base[l];
             // the copy holds layer-(l-1) values within K of the tile (layer
             // 1: solid values across the whole copy); reach < 2 narrows it
             const int K = l == 1 ? S : M + reach;
             for (int a = grp; a < n; a += NG) {
-                const int q = lst[a];
+                const int q = lt[a];
                 const int li = q % rw, lj = q / rw;
                 const int i = x0 - S + li, j = y0 - S + lj;
                 const int rlim = min(g.r_max, min(min(li - (S - K), S + FF_TILE - 1 + K - li),
@@ -1225,7 +1260,6 @@ __global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict
                 } else if (s_fail > 0) {
                     atomicAdd(&health[1], (unsigned)s_fail);
                 }
-                s_n = 0;
                 s_fail = 0;
             }
             __syncthreads();
