@@ -439,7 +439,7 @@ constexpr int DRW = DTX + 2 * MAX_LAYERS, DRH = DTY + 2 * MAX_LAYERS;
 // phi^n < 0, inside the previous window} is read from the level set, the
 // tile's solid nodes are tagged and advected (Sec. 3.1) in the same pass, and
 // the tags of the window are all written here.
-template <int LC, bool ADV, typename S>
+template <int LC, bool ADV, typename S, bool PRE = false>
 __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ win, int wslot,
                                              int wprev, int8_t* tag, int* lists, int* lcount,
                                              unsigned* health, const S* __restrict__ A,
@@ -468,10 +468,12 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
         const int x0 = W.i0 + (t % ntx) * DTX, y0 = W.j0 + (t / ntx) * DTY;
         if (threadIdx.x <= MAX_LAYERS) cnt[threadIdx.x] = 0;
         // solid flags of the region (nodes outside the window hold none).
-        // FP32 steps with a compile-time layer count issue all of a thread's
-        // level-set loads before using any (advection pass 25.0 -> 23.1 us
-        // at 2048^2; with FP64 values the extra registers cost as much)
-        constexpr bool PRELOAD = ADV && LC > 0 && sizeof(S) == 4;
+        // With PRE, FP32 steps with a compile-time layer count issue all of a
+        // thread's level-set loads before using any (one solid: advection
+        // pass 25.0 -> 23.1 us at 2048^2; with FP64 values the extra
+        // registers cost as much, and the several-solid pass at 4096^2 slows
+        // from 139 to 154 us)
+        constexpr bool PRELOAD = PRE && ADV && LC > 0 && sizeof(S) == 4;
         if (PRELOAD) {
             constexpr int NE = (DTX + 2 * LC) * (DTY + 2 * LC);
             constexpr int NS = (NE + 255) / 256;  // 256 threads per block
@@ -611,8 +613,8 @@ __global__ __launch_bounds__(256) void k_advect_dt(GridP g, const S* __restrict_
                                                    unsigned* health, int* ff_flag, int* ff_list,
                                                    int* ff_n)
 {
-    dt_tile_body<LC, true, S>(g, win, wcur, wprev, tag, lists, lcount, health, A, fpx, fpy, X,
-                              Y, phi, X1, Y1, ff_flag, ff_list, ff_n);
+    dt_tile_body<LC, true, S, true>(g, win, wcur, wprev, tag, lists, lcount, health, A, fpx, fpy,
+                                    X, Y, phi, X1, Y1, ff_flag, ff_list, ff_n);
 }
 
 template <int LC, typename S>
