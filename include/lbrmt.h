@@ -366,8 +366,13 @@ int32_t lbrmt_batch_size(const lbrmt_batch* batch);
  * lbrmt_step_count, lbrmt_band_nodes); lbrmt_step, lbrmt_load_state and
  * lbrmt_set_option on it return ESTATE.  Owned by the batch. */
 lbrmt_ctx* lbrmt_batch_member(lbrmt_batch* batch, int32_t k);
-/* LBRMT_OPT_LB_VARIANT (one tile shape for the whole batch) and
- * LBRMT_OPT_GRAPH; get also reads LBRMT_OPT_LB_VARIANT_COUNT. */
+/* LBRMT_OPT_LB_VARIANT (one tile shape for the whole batch),
+ * LBRMT_OPT_GRAPH and LBRMT_OPT_FUSED_FIT (1024: every member's
+ * extrapolation layers in one launch, member per grid row, when every member
+ * has one solid on walled axes and at most 11 layers; 0, default, or -1: one
+ * launch per layer over all members, faster for batches of many members;
+ * results are bitwise identical); get also reads
+ * LBRMT_OPT_LB_VARIANT_COUNT. */
 int lbrmt_batch_set_option(lbrmt_batch* batch, int32_t option, int64_t value);
 int lbrmt_batch_get_option(const lbrmt_batch* batch, int32_t option, int64_t* value);
 /* lbrmt_autotune for the batched lattice update. */

@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256) void kb_advect_dt(const AdvectArgs* __restrict
     const AdvectArgs& a = args[blockIdx.y];
     dt_tile_body<LC, true, S>(a.g, a.win, a.wcur, a.wprev, a.tag, a.lists, a.lcount, a.health,
                               (const S*)a.A, a.fpx, a.fpy, (const S*)a.X, (const S*)a.Y,
-                              (const S*)a.phi, (S*)a.X1, (S*)a.Y1);
+                              (const S*)a.phi, (S*)a.X1, (S*)a.Y1, a.ff_flag, a.ff_list, a.ff_n);
 }
 
 hipError_t launch_advect_layers(const GridP& g, int precision, const BandBufs& bb,
@@ -1138,13 +1138,13 @@ __device__ void fit_rest(const GridP& g, const Rect& W, const Rect& D, int8_t* t
 // launch).  Walled axes only (a window across a periodic seam would
 // reach another tile's nodes).
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict__ win, int wcur,
-                                                  int wprev, int8_t* tag,
-                                                  const T* __restrict__ phin, T* X1, T* Y1,
-                                                  unsigned* health, int8_t* cut_layer,
-                                                  int* cut_tiles, int* ncut,
-                                                  const int* __restrict__ ff_list,
-                                                  const int* __restrict__ ff_n, int reach)
+__device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __restrict__ win,
+                                               int wcur, int wprev, int8_t* tag,
+                                               const T* __restrict__ phin, T* X1, T* Y1,
+                                               unsigned* health, int8_t* cut_layer,
+                                               int* cut_tiles, int* ncut,
+                                               const int* __restrict__ ff_list,
+                                               const int* __restrict__ ff_n, int reach)
 {
     constexpr int RW = FF_TILE + 4 * (FF_LAYERS - 1) + 4;
     constexpr int NG = NT / FIT_LANES;
@@ -1268,6 +1268,40 @@ __global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict
             if (stop) break;
         }
     }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_fit_fused(GridP g, const Win* __restrict__ win, int wcur,
+                                                  int wprev, int8_t* tag,
+                                                  const T* __restrict__ phin, T* X1, T* Y1,
+                                                  unsigned* health, int8_t* cut_layer,
+                                                  int* cut_tiles, int* ncut,
+                                                  const int* __restrict__ ff_list,
+                                                  const int* __restrict__ ff_n, int reach)
+{
+    fit_fused_body<T, NT>(g, win, wcur, wprev, tag, phin, X1, Y1, health, cut_layer, cut_tiles,
+                          ncut, ff_list, ff_n, reach);
+}
+
+// a batch: member blockIdx.y
+template <typename T>
+__global__ __launch_bounds__(1024) void kb_fit_fused(const FitArgs* __restrict__ args)
+{
+    const FitArgs& a = args[blockIdx.y];
+    fit_fused_body<T, 1024>(a.g, a.win, a.wcur, a.wprev, a.tag, (const T*)a.phin, (T*)a.X1,
+                            (T*)a.Y1, a.health, a.cut_layer, a.cut_tiles, a.ncut, a.ff_list,
+                            a.ff_n, 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(FF_REST_THREADS) void kb_fit_rest(const FitArgs* __restrict__ args)
+{
+    const FitArgs& a = args[blockIdx.y];
+    const Rect W = window_of(a.win, a.wcur, a.g);
+    const Rect D = window_of(a.win, a.wprev, a.g);
+    fit_rest<T, FF_REST_THREADS>(a.g, W, D, a.tag, a.lists, a.lcount, (const T*)a.phin,
+                                 (T*)a.X1, (T*)a.Y1, a.health, a.cut_layer, a.cut_tiles, a.ncut,
+                                 a.ff_flag, a.ff_list, a.ff_n);
 }
 
 // fit_rest in a block of FF_REST_THREADS threads, which finds a free slot
@@ -2182,15 +2216,20 @@ hipError_t launch_mb_diag(int precision, const MbBody* bodies, int nb, int buf, 
 
 hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
                              hipStream_t st, bool relabel_only, int dt_blocks, int fit_blocks,
-                             int band_blocks)
+                             int band_blocks, bool fused)
 {
     const dim3 gb(band_blocks, nsim), gd(dt_blocks, nsim), gf(fit_blocks, nsim);
-    // fit_blocks == 0: every layer of a member in one block of MB_FIT_THREADS
-    const dim3 g1(1, nsim);
+    // fit_blocks == 0: every layer of a member in one block of MB_FIT_THREADS;
+    // fused: every layer of a member in one launch over its zone tiles (the
+    // members' advection pass lists those tiles)
+    const dim3 g1(1, nsim), gz(FF_BATCH_BLOCKS, nsim);
     if (precision == 0) {
         if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv);
-        if (fit_blocks == 0) kb_fit_layers<double><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
+        if (fused) {
+            kb_fit_fused<double><<<gz, 1024, 0, st>>>(t.fit);
+            kb_fit_rest<double><<<g1, FF_REST_THREADS, 0, st>>>(t.fit);
+        } else if (fit_blocks == 0) kb_fit_layers<double><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
         else
             for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
         if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg);
@@ -2198,7 +2237,10 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
     } else {
         if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv);
         else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv);
-        if (fit_blocks == 0) kb_fit_layers<float><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
+        if (fused) {
+            kb_fit_fused<float><<<gz, 1024, 0, st>>>(t.fit);
+            kb_fit_rest<float><<<g1, FF_REST_THREADS, 0, st>>>(t.fit);
+        } else if (fit_blocks == 0) kb_fit_layers<float><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
         else
             for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
         if (relabel_only) kb_force<2, float><<<gb, 256, 0, st>>>(t.edg);

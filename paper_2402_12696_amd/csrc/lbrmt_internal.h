@@ -30,6 +30,7 @@ constexpr int FF_LAYERS = 11;         // fused extrapolation: most layers
 constexpr int FF_BLOCKS = 256;        // fused extrapolation: blocks striding over its tile list
 constexpr int FF_NO_CUT = 127;        // tile not stopped (cut_layer)
 constexpr int FF_REST_THREADS = 256;  // fused extrapolation: the one-block pass
+constexpr int FF_BATCH_BLOCKS = 64;   // fused extrapolation of a batch: blocks per member
 
 // Several solids: the lattice is cut into force blocks of FB x FB nodes;
 // a block holds valid force planes at step n when its stamp equals n + 1.
@@ -214,6 +215,8 @@ struct AdvectArgs {
     int* lists;
     int* lcount;
     unsigned* health;
+    // the fused extrapolation's zone-tile list (null: not built)
+    int *ff_flag, *ff_list, *ff_n;
 };
 struct LayersArgs {
     GridP g;
@@ -235,6 +238,9 @@ struct FitArgs {
     const void* phin;
     void *X1, *Y1;
     unsigned* health;
+    // the fused extrapolation's buffers (batches of single-solid members)
+    int8_t* cut_layer;
+    int *cut_tiles, *ncut, *ff_flag, *ff_list, *ff_n;
 };
 struct EdgesArgs {
     GridP g;
@@ -443,7 +449,7 @@ struct LossCoef {
 hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int layers,
                              hipStream_t st, bool relabel_only = false,
                              int dt_blocks = BATCH_DT_BLOCKS, int fit_blocks = BATCH_FIT_BLOCKS,
-                             int band_blocks = BATCH_BAND_BLOCKS);
+                             int band_blocks = BATCH_BAND_BLOCKS, bool fused = false);
 hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const int* tile_sim,
                            int total_tiles, hipStream_t st);
 // PART 0 / 2 launches with nbox > 0 also reduce the force pass's partial

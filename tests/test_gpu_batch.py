@@ -102,3 +102,40 @@ def test_batch_member_is_read_only():
     with pytest.raises(LBRMTError):
         m.set_option(0, 1)
     batch.close()
+
+
+def _walled_members():
+    # every member one solid on walled axes: the batch fits all layers of
+    # every member in one launch
+    return [
+        workloads.cavity_disc_64(),
+        workloads.make(nx=96, ny=96, tau=0.7, lid_ux=0.06,
+                       solid=dict(cx=48.0, cy=57.6, R=16.0, G=0.01, rho_s=1.0), name="m96"),
+        workloads.make(nx=128, ny=120, tau=0.8, lid_ux=0.08,
+                       solid=dict(cx=64.0, cy=66.0, R=30.0, G=0.01, rho_s=1.0, shape="ellipse",
+                                  b=3.0, theta=0.3), name="thin"),
+        workloads.make(nx=96, ny=80, tau=0.8, lid_ux=0.06, gravity=(0.0, -1e-4),
+                       solid=dict(cx=30.0, cy=14.5, R=11.0, G=0.01, rho_s=1.4), name="near_wall"),
+        workloads.make(nx=160, ny=160, tau=0.6, lid_ux=0.08,
+                       solid=dict(cx=80.0, cy=96.0, R=30.0, G=0.005, rho_s=1.0), name="m160"),
+    ]
+
+
+@pytest.mark.parametrize("fused", [1024, 0])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_with_one_extrapolation_launch_equals_single_contexts(precision, fused):
+    from paper_2402_12696_amd import Batch, Sim
+    from paper_2402_12696_amd import lbrmt as B
+    cfgs = _walled_members()
+    batch = Batch(cfgs, precision=precision)
+    batch.set_option(B.LBRMT_OPT_FUSED_FIT, fused)
+    assert batch.get_option(B.LBRMT_OPT_FUSED_FIT) == fused
+    batch.init()
+    batch.step(5)
+    batch.step(31)
+    for k, c in enumerate(cfgs):
+        single = Sim(device="cuda:0", precision=precision, **c).init().step(36)
+        _same(_fields(batch.member(k)), _fields(single), f"{precision} {fused} member {k}")
+        assert batch.member(k).diag()["health"] == single.diag()["health"]
+        single.close()
+    batch.close()
