@@ -136,3 +136,24 @@ def test_one_launch_extrapolation_with_more_zone_tiles_than_blocks():
                          solid=dict(cx=2048.0, cy=2200.0, R=1200.0, G=0.005, rho_s=1.0))
     ref = _run(cfg, "f32", 0, 12)
     assert _equal(ref, _run(cfg, "f32", 1024, 12))
+
+
+def test_one_launch_extrapolation_over_a_long_deforming_run():
+    # the 256^2 inverse-problem scene from a noisy initial velocity, 600 steps
+    # (the solid deforms strongly; the run stays finite): bitwise equal
+    from paper_2402_12696_amd import Sim
+    from paper_2402_12696_amd import lbrmt as B
+    cfg = workloads.make(nx=256, ny=256, tau=0.7, lid_ux=0.08,
+                         solid=dict(cx=128.0, cy=153.6, R=40.0, G=0.01, rho_s=1.0))
+    u0 = np.random.default_rng(5).normal(0.0, 1e-3, size=(2, 256, 256))
+    out = []
+    for prec in ("f64", "f32"):
+        for opt in (0, 1024):
+            sim = Sim(device="cuda:0", precision=prec, **cfg)
+            sim.set_option(B.LBRMT_OPT_FUSED_FIT, opt)
+            sim.init(u0)
+            sim.step(600)
+            out.append(_state(sim))
+            sim.close()
+    assert _equal(out[0], out[1]) and _equal(out[2], out[3])
+    assert not out[0][6]["nonfinite"]
