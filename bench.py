@@ -9,7 +9,11 @@ relabel, stress divergence, SFC + Guo collision with streaming and walls.
 Prints ONE JSON line: whole-job MLUPS (interior nodes x steps / s), the roofline
 of the dominant kernel (the lattice Boltzmann update of the tiles outside the
 solid band, timed with HIP events on its own stream), and the CPU oracle timed
-on a bounded sample of the same workload.
+on a bounded sample of the same workload (all OpenMP threads, and one).
+During the untimed warm-up the extrapolation launch mode (all layers in one
+launch, or one launch per layer) is chosen by timing whole steps
+(lbrmt_autotune_steps; --no-autotune keeps the library default); the choice
+is reported in extra.extrapolation_launch.
 """
 import argparse
 import hashlib
