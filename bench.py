@@ -319,8 +319,8 @@ def main():
                          "counters (FETCH_SIZE, WRITE_SIZE) of a profiled run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the "
+              "multi-GPU slab decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.suspension_only:
