@@ -34,7 +34,13 @@ def rel(a, b):
     return d / s if s > 0 else d
 
 
-def compare(sim, ref, tol=TOL64, what=""):
+def compare(sim, ref, tol=TOL64, what="", dev_tol=None, eps=1.5):
+    """Errors of the GPU state against the oracle's (printed); asserts rho,
+    ux, uy, X, Y within tol.  With dev_tol it also asserts the stricter
+    errors of Sec. 8(c)'s deviations -- rho - rho_f, xi - x (over the nodes
+    with phi < eps), and each velocity component against its own maximum --
+    wherever the reference deviation is well above rounding (|rho - rho_f| >
+    1e-9, |xi - x| > 1e-6, a component above 1 % of max |u|)."""
     rho, ux, uy = _np(sim.macro())
     rr, ru, rv = ref.macro()
     umax = max(np.max(np.abs(ru)), np.max(np.abs(rv)))
@@ -42,6 +48,13 @@ def compare(sim, ref, tol=TOL64, what=""):
             "ux": np.max(np.abs(ux - ru)) / umax if umax > 0 else np.max(np.abs(ux)),
             "uy": np.max(np.abs(uy - rv)) / umax if umax > 0 else np.max(np.abs(uy)),
             "drho": rel(rho - 1.0, rr - 1.0) if np.max(np.abs(rr - 1)) > 0 else 0.0}
+    dev_keys = []
+    if np.max(np.abs(rr - 1.0)) > 1e-9:
+        dev_keys.append("drho")
+    for k, a, b in (("ux_own", ux, ru), ("uy_own", uy, rv)):
+        if np.max(np.abs(b)) > 0.01 * umax > 0:
+            errs[k] = rel(a, b)
+            dev_keys.append(k)
     if ref.diag()["n_band"] > 0 or sim.nsolid:
         X, Y, P = _np(sim.refmap())
         RX, RY, RP = ref.refmap()
@@ -52,12 +65,24 @@ def compare(sim, ref, tol=TOL64, what=""):
         if mr.any():
             errs["X"] = rel(X[mr], RX[mr])
             errs["Y"] = rel(Y[mr], RY[mr])
+            # the displacement over the nodes with phi < eps (the solid and
+            # its blur zone), the set of Sec. 8(c)'s xi norm; farther zone
+            # layers are extrapolations of extrapolations, where the rounding
+            # of |xi| ~ n is amplified layer by layer
             y, x = np.mgrid[0:ref.ny, 0:ref.nx] + 0.5
-            errs["disp"] = max(rel(X[mr] - x[mr], RX[mr] - x[mr]),
-                               rel(Y[mr] - y[mr], RY[mr] - y[mr]))
+            ms = mr & (RP < eps)
+            if ms.any():
+                errs["disp"] = max(rel(X[ms] - x[ms], RX[ms] - x[ms]),
+                                   rel(Y[ms] - y[ms], RY[ms] - y[ms]))
+                if max(np.max(np.abs(RX[ms] - x[ms])), np.max(np.abs(RY[ms] - y[ms]))) > 1e-6:
+                    dev_keys.append("disp")
     print(what, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    bad = {k: v for k, v in errs.items() if k not in ("drho", "disp") and not v <= tol}
+    main = ("rho", "ux", "uy", "X", "Y")
+    bad = {k: v for k, v in errs.items() if k in main and not v <= tol}
     assert not bad, f"{what}: {bad}"
+    if dev_tol is not None:
+        bad = {k: errs[k] for k in dev_keys if not errs[k] <= dev_tol}
+        assert not bad, f"{what}: deviation errors {bad}"
     return errs
 
 
@@ -175,6 +200,36 @@ def test_graph_replay_equals_eager_launches():
         assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0))
     ms, n = b.kernel_time("lb_bulk")
     assert n == 30 and ms > 0
+
+
+def test_partial_graphs_equal_eager_launches():
+    # runs that start or end off a six-step boundary replay captured shorter
+    # graphs (steps p .. p + r - 1 of the six-step period); any split of the
+    # steps gives the eager result bit for bit, and an option set to its
+    # current value keeps the captured graphs
+    cfg = workloads.cavity_disc_64()
+    a = _gpu(cfg)
+    for n in (7, 5, 1, 13, 2, 6, 3, 4, 11):
+        a.step(n)
+        a.set_option(0, a.get_option(0))
+    b = _gpu(cfg)
+    b.set_option(3, 0)
+    b.step(52)
+    assert a.step_count == b.step_count == 52
+    for x, y in zip(_np(a.macro()) + _np(a.refmap()), _np(b.macro()) + _np(b.refmap())):
+        assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0))
+
+
+def test_lid_with_fluid_density_matches_oracle():
+    # reading R6 with rho_w = rho_f (lid_rho_mode 1) on a compressible cavity
+    cfg = workloads.cavity_disc_64()
+    cfg["solid"]["rho_s"] = 1.3
+    cfg["gravity"] = (0.0, -1e-4)
+    cfg["lid_rho_mode"] = 1
+    sim, ref = _gpu(cfg), Oracle(**cfg).init()
+    sim.step(300)
+    ref.step(300)
+    compare(sim, ref, what="lid rho_f")
 
 
 def test_nonfinite_population_is_reported():

@@ -14,6 +14,7 @@ import numpy as np
 _DEFAULTS = dict(
     periodic_x=False, periodic_y=False, lid_ux=0.0, gravity=(0.0, 0.0), fext=(0.0, 0.0),
     rho_f=1.0, eps=1.5, layers=11, r_max=8, det_rel=1e-8, detJ_min=1e-12, eta=1.0, solid=None,
+    kappa_J=0.25, lid_rho_mode=0,
 )
 
 
@@ -59,6 +60,24 @@ def gaussian_velocity(nx, ny, std, seed):
     """i.i.d. Gaussian initial velocity, shape (2, ny, nx) (ux plane, uy plane)."""
     rng = np.random.default_rng(seed)
     return rng.normal(0.0, std, size=(2, ny, nx))
+
+
+def cellular_velocity(nx, ny, amp, cells, seed):
+    """Divergence-free cellular flow of shape (2, ny, nx): stream function
+    psi = amp / k * sin(k x + a) * sin(k y + b), k = 2 pi cells / max(nx, ny),
+    phases a, b from numpy default_rng(seed); u = dpsi/dy, v = -dpsi/dx, so
+    |u| <= amp.  A solid placed in it is sheared and carried from the first
+    step."""
+    rng = np.random.default_rng(seed)
+    a, b = rng.uniform(0.0, 2.0 * np.pi, size=2)
+    k = 2.0 * np.pi * cells / max(nx, ny)
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    X, Y = np.meshgrid(x, y)
+    u = np.zeros((2, ny, nx))
+    u[0] = amp * np.sin(k * X + a) * np.cos(k * Y + b)
+    u[1] = -amp * np.cos(k * X + a) * np.sin(k * Y + b)
+    return u
 
 
 def uniform_velocity(nx, ny, ux, uy):
