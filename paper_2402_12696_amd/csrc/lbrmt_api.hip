@@ -198,6 +198,9 @@ struct lbrmt_ctx {
     bool overlap = true;  // the chain on an internal stream beside the bulk lattice update
     int lb_variant = 3;    // set per precision by lbrmt_create
     hipGraphExec_t gexec = nullptr;
+    // steps 6 + p .. 6 + p + r - 1 (r < 6): replayed for step runs that do not
+    // start or end on a six-step boundary, captured on first use
+    hipGraphExec_t pexec[GRAPH_STEPS][GRAPH_STEPS] = {};
     bool graph = true;  // replay captured six-step graphs
     bool member = false;  // member of a batch (stepped by the batch only)
     int bulk_blocks = 0;  // cap on the blocks of the overlapped bulk update (0: one per tile)
@@ -420,25 +423,50 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
     return LBRMT_OK;
 }
 
-static int build_graph(lbrmt_ctx* c)
+// Capture steps 6 + p .. 6 + p + r - 1 into *out.  Steps n and n + 6 (n >= 6)
+// enqueue identical launches (every buffer parity and ring slot repeats with
+// period six), so such a graph replays any run of r steps that starts at a
+// step count = p mod 6, p + r <= 6.
+static int capture_steps(lbrmt_ctx* c, int p, int r, hipGraphExec_t* out)
 {
-    // steps n0 .. n0+5 with n0 = 0 mod 6 and n0 >= 6 have identical launches
     hipGraph_t graph = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     int rc = LBRMT_OK;
-    for (int k = 0; k < GRAPH_STEPS && rc == LBRMT_OK; k++) rc = enqueue_step(c, 6 + k, c->cap);
+    for (int k = 0; k < r && rc == LBRMT_OK; k++) rc = enqueue_step(c, GRAPH_STEPS + p + k, c->cap);
     hipError_t e = hipStreamEndCapture(c->cap, &graph);
     if (rc != LBRMT_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return rc;
     }
     if (e != hipSuccess) return fail(c, "hipStreamEndCapture", e);
-    e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        c->gexec = nullptr;
+        *out = nullptr;
         return fail(c, "hipGraphInstantiate", e);
     }
+    return LBRMT_OK;
+}
+
+static int build_graph(lbrmt_ctx* c) { return capture_steps(c, 0, GRAPH_STEPS, &c->gexec); }
+
+// Destroy every captured graph (after synchronising the stream that replays
+// them): they bake the launch configuration and the solids in.
+static int drop_graphs(lbrmt_ctx* c)
+{
+    bool any = c->gexec != nullptr;
+    for (int p = 0; p < GRAPH_STEPS; p++)
+        for (int r = 0; r < GRAPH_STEPS; r++) any = any || c->pexec[p][r];
+    if (!any) return LBRMT_OK;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    for (int p = 0; p < GRAPH_STEPS; p++)
+        for (int r = 0; r < GRAPH_STEPS; r++)
+            if (c->pexec[p][r]) {
+                (void)hipGraphExecDestroy(c->pexec[p][r]);
+                c->pexec[p][r] = nullptr;
+            }
     return LBRMT_OK;
 }
 
@@ -447,6 +475,7 @@ static bool desc_ok(const lbrmt_grid_desc* d)
     return d && d->nx >= 8 && d->ny >= 8 && d->tau > 0.5 && d->layers >= 1 &&
            d->layers <= MAX_LAYERS && (long long)(d->nx + 4) * (d->ny + 4) < (1ll << 26) &&
            d->r_max >= 2 && d->r_max <= 32 && d->eps > 0.0 && d->rho_f > 0.0 &&
+           (d->lid_rho_mode == 0 || d->lid_rho_mode == 1) && !std::isnan(d->kappa_J) &&
            (d->precision == LBRMT_FP64 || d->precision == LBRMT_FP32);
 }
 
@@ -523,6 +552,8 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
     g.lpy = g.py;
     g.eta = d->eta;
     g.lcap = sub_cap(g.pplane);
+    g.kappa_J = d->kappa_J > 0.0 ? d->kappa_J : 0.25;
+    g.lid_rho_mode = d->lid_rho_mode;
     c->body.present = 0;
     for (int k = 0; k < 2; k++) {
         c->lat[k] = c->ws + L.off_lat[k];
@@ -613,6 +644,9 @@ void lbrmt_destroy(lbrmt_ctx* c)
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (int p = 0; p < GRAPH_STEPS; p++)
+        for (int r = 0; r < GRAPH_STEPS; r++)
+            if (c->pexec[p][r]) (void)hipGraphExecDestroy(c->pexec[p][r]);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_adv) (void)hipEventDestroy(c->ev_adv);
@@ -842,11 +876,10 @@ int lbrmt_init(lbrmt_ctx* c, const double* d_u0)
     HIPCHK(c, hipMemsetAsync(c->bb.ticket, 0, 4, st));
     HIPCHK(c, clear_cut_tiles(c, st));
     for (int k = 0; k < 3; k++) HIPCHK(c, launch_win_reset(c->bb.win, k, st));
-    if (c->gexec) {
-        // a graph captured for an earlier initialisation bakes the old solids in
-        HIPCHK(c, hipStreamSynchronize(st));
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
+    {
+        // graphs captured for an earlier initialisation bake the old solids in
+        int rc = drop_graphs(c);
+        if (rc != LBRMT_OK) return rc;
     }
     if (c->multi) return init_mb(c, d_u0);
     if (c->nsolid > 0) {
@@ -869,9 +902,9 @@ int lbrmt_step(lbrmt_ctx* c, int64_t nsteps)
     if (!c->inited || c->member) return LBRMT_ESTATE;
     int64_t left = nsteps;
     while (left > 0) {
-        const bool use_graph = c->graph && !c->timing && c->step >= GRAPH_STEPS &&
-                               c->step % GRAPH_STEPS == 0 && left >= GRAPH_STEPS;
-        if (use_graph) {
+        const bool use_graph = c->graph && !c->timing && c->step >= GRAPH_STEPS;
+        const int p = (int)(c->step % GRAPH_STEPS);
+        if (use_graph && p == 0 && left >= GRAPH_STEPS) {
             if (!c->gexec) {
                 int rc = build_graph(c);
                 if (rc != LBRMT_OK) return rc;
@@ -879,6 +912,16 @@ int lbrmt_step(lbrmt_ctx* c, int64_t nsteps)
             HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
             c->step += GRAPH_STEPS;
             left -= GRAPH_STEPS;
+        } else if (use_graph) {
+            // up to the next six-step boundary, or the end of the run
+            const int r = (int)std::min<int64_t>(left, GRAPH_STEPS - p);
+            if (!c->pexec[p][r]) {
+                int rc = capture_steps(c, p, r, &c->pexec[p][r]);
+                if (rc != LBRMT_OK) return rc;
+            }
+            HIPCHK(c, hipGraphLaunch(c->pexec[p][r], c->st));
+            c->step += r;
+            left -= r;
         } else {
             int rc = enqueue_step(c, c->step, c->st);
             if (rc != LBRMT_OK) return rc;
@@ -1430,6 +1473,10 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
 {
     if (!c) return LBRMT_EINVAL;
     if (c->member) return LBRMT_ESTATE;
+    int64_t cur = 0;
+    if (option != LBRMT_OPT_LB_VARIANT_COUNT && lbrmt_get_option(c, option, &cur) == LBRMT_OK &&
+        cur == value)
+        return LBRMT_OK;  // unchanged: the captured graphs stay valid
     switch (option) {
     case LBRMT_OPT_OVERLAP:
         if (value != 0 && value != 1) return LBRMT_EINVAL;
@@ -1456,13 +1503,8 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
     default:
         return LBRMT_EINVAL;
     }
-    // the captured step graph bakes the launch configuration in
-    if (c->gexec) {
-        HIPCHK(c, hipStreamSynchronize(c->st));
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
-    }
-    return LBRMT_OK;
+    // the captured step graphs bake the launch configuration in
+    return drop_graphs(c);
 }
 
 int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
@@ -1606,6 +1648,12 @@ int lbrmt_autotune_steps(lbrmt_ctx* c, int32_t steps, int32_t* best_fused, doubl
     if (rc != LBRMT_OK) return rc;
     rc = lbrmt_set_option(c, LBRMT_OPT_FUSED_FIT, best);
     if (rc != LBRMT_OK) return rc;
+    // capture the chosen mode's six-step graph now, so that the first steps
+    // after the choice do not pay for it
+    if (c->graph && !c->gexec) {
+        rc = build_graph(c);
+        if (rc != LBRMT_OK) return rc;
+    }
     if (best_fused) *best_fused = best;
     if (best_ms) *best_ms = best_t / (double)timed;
     return LBRMT_OK;
