@@ -35,7 +35,8 @@ extern "C" {
 
 typedef enum {
     LBRMT_OK = 0,
-    LBRMT_EINVAL = 1,      /* null pointer, nx or ny < 8, tau <= 1/2, bad shape  */
+    LBRMT_EINVAL = 1,      /* null pointer, nx or ny < 8, tau <= 1/2, bad shape,
+                              lid_rho_mode not 0 or 1                            */
     LBRMT_EWORKSPACE = 2,  /* workspace too small or misaligned (256 B)          */
     LBRMT_EHIP = 3,        /* a HIP call failed; text via lbrmt_last_error       */
     LBRMT_EUNSTABLE = 4,   /* device health counters report a failure            */
@@ -51,7 +52,8 @@ typedef enum {
  *               right-hand sides, stress).  Double is kept for the level set
  *               phi0(xi) (it decides the solid set), the fit's normal matrix
  *               and well-posedness test, the inversion of grad xi where
- *               det < 0.25, the force planes and every diagnostic reduction.
+ *               det < kappa_J (0.25 by default), the force planes and every
+ *               diagnostic reduction.
  * Reads return float64 in both modes (xi, not the displacement). */
 typedef enum { LBRMT_FP64 = 0, LBRMT_FP32 = 1 } lbrmt_precision;
 
@@ -75,6 +77,13 @@ typedef struct {
                                 along a periodic axis (0: 128); see below       */
     double eta;              /* contact factor eta of Eq. (3_6_collision_stress)
                                 (several solids; 1 in the paper's runs)         */
+    double kappa_J;          /* FP32: grad xi is inverted in double where its
+                                determinant (the J of Eq. (3_3_refmap_deformation))
+                                is below kappa_J; <= 0 selects 0.25            */
+    int32_t lid_rho_mode;    /* density rho_w in the moving-lid term of the
+                                bounce-back (Sec. 3.5): 0 the node's rho^n
+                                (default), 1 the fluid density rho_f            */
+    int32_t reserved;
 } lbrmt_grid_desc;
 
 /* Several solids (Sec. 3.6).  A context created with max_solids > 1 keeps

@@ -254,6 +254,7 @@ static int solid_ok(const orc_solid* b)
 orc_sim* orc_create(const orc_params* p, const orc_solid* solids, int32_t nsolid)
 {
     if (!p || p->nx < 4 || p->ny < 4 || nsolid < 0 || nsolid > ORC_MAX_SOLIDS) return NULL;
+    if (p->lid_rho_mode != 0 && p->lid_rho_mode != 1) return NULL;
     if (nsolid && !solids) return NULL;
     for (int b = 0; b < nsolid; b++)
         if (!solid_ok(&solids[b])) return NULL;
@@ -850,7 +851,8 @@ void orc_phase_collide_stream(orc_sim* s)
     /* streaming; a population leaving through a wall is reflected back into
      * the opposite direction at its own node (halfway bounce-back).  The top
      * buffer row, corners included, moves with the lid velocity u_w, which
-     * adds -2 w_i rho_w (c_i . u_w) / c_s^2 with rho_w the node's density. */
+     * adds -2 w_i rho_w (c_i . u_w) / c_s^2 with rho_w the node's density
+     * (or the fluid density rho_f, lid_rho_mode 1). */
     static const int OPP[NQ] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; j++)
@@ -866,7 +868,8 @@ void orc_phase_collide_stream(orc_sim* s)
                 } else {
                     double uw = (jd == ny) ? s->p.lid_ux : 0.0;
                     double cu = CX[q] * uw;
-                    s->fnew[OPP[q] * N + n] = fh - 2.0 * WQ[q] * s->rho[n] * cu / CS2;
+                    double rw = s->p.lid_rho_mode ? s->p.rho_f : s->rho[n];
+                    s->fnew[OPP[q] * N + n] = fh - 2.0 * WQ[q] * rw * cu / CS2;
                 }
             }
         }

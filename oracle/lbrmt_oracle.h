@@ -39,7 +39,7 @@ typedef struct {
     double det_rel;     /* LSQ fit ill-defined if det M <= det_rel*(sum w)^3 */
     double detJ_min;    /* half-edge stress dropped if det(grad xi) <= this  */
     int32_t reverse_order; /* process extrapolation targets in reverse order */
-    int32_t reserved;
+    int32_t lid_rho_mode;  /* moving-lid density: 0 the node's rho, 1 rho_f */
     double eta;         /* contact factor of Eq. (3_6_collision_stress)      */
 } orc_params;
 

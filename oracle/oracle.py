@@ -30,7 +30,7 @@ class _Params(ctypes.Structure):
         ("rho_f", ctypes.c_double), ("eps", ctypes.c_double),
         ("layers", ctypes.c_int32), ("r_max", ctypes.c_int32),
         ("det_rel", ctypes.c_double), ("detJ_min", ctypes.c_double),
-        ("reverse_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("reverse_order", ctypes.c_int32), ("lid_rho_mode", ctypes.c_int32),
         ("eta", ctypes.c_double),
     ]
 
@@ -162,10 +162,10 @@ class Oracle:
     def __init__(self, nx, ny, tau, lid_ux=0.0, periodic_x=False, periodic_y=False,
                  gravity=(0.0, 0.0), fext=(0.0, 0.0), rho_f=1.0, eps=1.5, layers=11,
                  r_max=8, det_rel=1e-8, detJ_min=1e-12, reverse_order=False, solid=None,
-                 solids=None, eta=1.0, **_ignored):
+                 solids=None, eta=1.0, lid_rho_mode=0, **_ignored):
         p = _Params(nx, ny, int(periodic_x), int(periodic_y), tau, lid_ux,
                     gravity[0], gravity[1], fext[0], fext[1], rho_f, eps, layers, r_max,
-                    det_rel, detJ_min, int(reverse_order), 0, eta)
+                    det_rel, detJ_min, int(reverse_order), int(lid_rho_mode), eta)
         self.nx, self.ny = nx, ny
         if solid is not None and solids is not None:
             raise ValueError("give either solid or solids")

@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void k_adj_lattice(GridP g, BodyP b, AdjSnap s
                 // f_opp(q)(x) = fhat_q(x) -/+ rho U / 6 through the lid (Sec. 3.5)
                 const double sg = q == 5 ? -1.0 : 1.0;
                 const double fo = a.fb_in[AOPP[q] * N + e];
-                rhobar += fo * sg * g.lid_ux / 6.0;
-                ubar_lid += fo * sg * rho / 6.0;
+                if (!g.lid_rho_mode) rhobar += fo * sg * g.lid_ux / 6.0;
+                ubar_lid += fo * sg * (g.lid_rho_mode ? g.rho_f : rho) / 6.0;
             }
         }
         // collision: fhat_q = f_q + om (feq_q - f_q) + cf Fi_q

@@ -25,7 +25,7 @@
 // stencil arithmetic in float and keeps FP64 for the level set phi0(x + d)
 // (it decides the solid set), the normal matrix of the fit and its
 // well-posedness test (exact sums of powers of two on a few nodes), and the
-// inversion of grad xi where det < KAPPA_J.
+// inversion of grad xi where det < kappa_J.
 #include "lbrmt_internal.h"
 
 namespace lbrmt {
@@ -1383,7 +1383,7 @@ __device__ __forceinline__ void tau_of(C J0, C J1, C J2, C J3, C det, C G, C lam
 // s1..s4: the side nodes of the tangential difference (s1 + s2 - s3 - s4)/4
 // (Eq. (3_3_refmap_jacobian), six-node stencil); dir 0: x-edge, 1: y-edge.
 // With displacement storage grad xi = I + grad d; where its determinant is
-// below KAPPA_J the inversion is redone in double.
+// below kappa_J the inversion is redone in double.
 template <typename C>
 __device__ void edge_tau(const GridP& g, const BodyP& b, const C* sX, const C* sY, const C* sP,
                          int a, int bb, int s1, int s2, int s3, int s4, int dir, bool count,
@@ -1415,7 +1415,7 @@ __device__ void edge_tau(const GridP& g, const BodyP& b, const C* sX, const C* s
         J3 += C(1);
     }
     const C det = J0 * J3 - J1 * J2;
-    if (DISP && !(det >= C(KAPPA_J))) {
+    if (DISP && !(det >= C(g.kappa_J))) {
         // near-singular (or inverted) grad xi: decide and invert in double
         const double dnX = (double)sX[bb] - (double)sX[a], dnY = (double)sY[bb] - (double)sY[a];
         const double dtX =

@@ -224,7 +224,8 @@ __device__ __forceinline__ void lb_tile(const GridP& g, const S* __restrict__ A,
         if (q[r].bn) {
             // lid: the populations 5 and 6 leave through the moving top wall;
             // store them already reflected-with-momentum, -2 w rho (c.u_w)/cs^2
-            const C m = rho * C(g.lid_ux) * C(1.0 / 6.0);
+            const C rw = g.lid_rho_mode ? C(g.rho_f) : rho;
+            const C m = rw * C(g.lid_ux) * C(1.0 / 6.0);
             f[r][5] -= m;
             f[r][6] += m;
         }

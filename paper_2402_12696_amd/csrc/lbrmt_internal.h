@@ -75,10 +75,11 @@ struct GridP {
     int lpx, lpy;         // lattice periodic axes
     double eta;           // contact factor of Eq. (3_6_collision_stress)
     long long lcap;       // capacity of one layer sub-list (entries)
+    // det(grad xi) below which the FP32 reference-map path inverts grad xi
+    // in FP64 (near-singular maps, J -> 0 of Eq. (3_3_refmap_deformation))
+    double kappa_J;
+    int lid_rho_mode;     // moving-lid density: 0 the node's rho, 1 rho_f
 };
-
-// det(grad xi) below which the FP32 reference-map path inverts grad xi in FP64
-constexpr double KAPPA_J = 0.25;
 
 struct BodyP {
     int present;

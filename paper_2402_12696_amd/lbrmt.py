@@ -38,7 +38,8 @@ class lbrmt_grid_desc(ctypes.Structure):
         ("layers", ctypes.c_int32), ("r_max", ctypes.c_int32),
         ("det_rel", ctypes.c_double), ("detJ_min", ctypes.c_double),
         ("precision", ctypes.c_int32), ("body_window", ctypes.c_int32),
-        ("eta", ctypes.c_double),
+        ("eta", ctypes.c_double), ("kappa_J", ctypes.c_double),
+        ("lid_rho_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -195,11 +196,12 @@ def _stream():
 def make_grid_desc(nx, ny, tau, lid_ux=0.0, periodic_x=False, periodic_y=False,
                    gravity=(0.0, 0.0), fext=(0.0, 0.0), rho_f=1.0, eps=1.5, layers=11, r_max=8,
                    det_rel=1e-8, detJ_min=1e-12, precision="f64", body_window=0, eta=1.0,
-                   **_ignored):
+                   kappa_J=0.25, lid_rho_mode=0, **_ignored):
     prec = {"f64": LBRMT_FP64, "f32": LBRMT_FP32}[precision]
     return lbrmt_grid_desc(nx, ny, int(periodic_x), int(periodic_y), tau, lid_ux,
                            gravity[0], gravity[1], fext[0], fext[1], rho_f, eps, layers, r_max,
-                           det_rel, detJ_min, prec, int(body_window), float(eta))
+                           det_rel, detJ_min, prec, int(body_window), float(eta),
+                           float(kappa_J), int(lid_rho_mode), 0)
 
 
 def _solid_list(cfg):

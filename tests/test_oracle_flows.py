@@ -151,3 +151,34 @@ def test_rigid_translation(shape):
     d = o.diag()
     assert abs(d["centroid_x"] - (24.0 + steps * u[0])) < 0.05
     assert abs(d["centroid_y"] - (28.0 + steps * u[1])) < 0.05
+
+
+def test_lid_with_fluid_density_conserves_mass_and_differs_only_where_rho_does():
+    # reading R6, lid_rho_mode 1: the moving-lid term uses rho_f instead of the
+    # node's density.  Both lid links of a top node still cancel (mass is
+    # exact); a flow whose top-row density stays rho_f is unchanged, and a
+    # compressible cavity flow is not.
+    base = workloads.cavity_disc_64()
+    base["solid"]["rho_s"] = 1.3
+    base["gravity"] = (0.0, -1e-4)
+    o0 = Oracle(**base).init()
+    o1 = Oracle(**dict(base, lid_rho_mode=1)).init()
+    m0 = o1.diag()["mass"]
+    o0.step(300)
+    o1.step(300)
+    assert abs(o1.diag()["mass"] - m0) < 1e-12 * m0
+    r0, u0, _ = o0.macro()
+    r1, u1, _ = o1.macro()
+    assert np.max(np.abs(r0[-1] - 1.0)) > 1e-5
+    assert np.max(np.abs(u1 - u0)) > 1e-9
+    # the steady Couette profile, whose density is uniform, is still exact
+    U, ny = 0.05, 16
+    c1 = Oracle(**workloads.make(nx=4, ny=ny, tau=0.8, lid_ux=U, periodic_x=True,
+                                 lid_rho_mode=1)).init()
+    c1.step(20000)
+    _, ux, uy = c1.macro()
+    y = np.arange(ny) + 0.5
+    assert np.max(np.abs(ux - U * y[:, None] / ny)) < 1e-12
+    assert np.max(np.abs(uy)) < 1e-12 * U
+    with pytest.raises(ValueError):
+        Oracle(**dict(base, lid_rho_mode=2))
