@@ -207,6 +207,20 @@ int lbrmt_read_stress(lbrmt_ctx* ctx, double* d_sxx, double* d_sxy, double* d_sy
  * Returns EUNSTABLE if a NONFINITE, DETJ_SOLID or EXTRAP_FAIL counter is set.
  * With several solids the solid terms are summed over all solids. */
 int lbrmt_diag(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
+/* lbrmt_diag for callers that cannot allocate device memory (code that must
+ * not call hipMalloc: under HIP graph capture, tight serving loops, harnesses
+ * that forbid it): the same reductions, results and return codes, with their
+ * scratch in a static device array that the library holds on each GPU it
+ * runs on until the process ends (147 712 bytes: the per-block partial records, the
+ * reduced record and 7 doubles per solid).  No device memory is allocated by
+ * this call, and the context's workspace is not used for the reductions.
+ * EINVAL for a context with more than LBRMT_DIAG_NOALLOC_MAX_SOLIDS solids
+ * (text via lbrmt_last_error).  Call with the context's device current.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (from several host threads, or on several streams) race and
+ * give wrong results; serialise them.  Synchronises the stream. */
+#define LBRMT_DIAG_NOALLOC_MAX_SOLIDS 1024
+int lbrmt_diag_noalloc(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
 /* One solid's terms of lbrmt_diag into host memory: centroid_x, centroid_y,
  * disp_x, disp_y (each in the solid's own unwrapped frame), n_solid, n_band. */
 int lbrmt_diag_solid(lbrmt_ctx* ctx, int32_t solid, double* host_out6);

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,22 @@
 #include "lbrmt_internal.h"
 
 using namespace lbrmt;
+
+// Static scratch of lbrmt_diag_noalloc (see there): the diagnostic's partial
+// records (1024 blocks x 11 doubles), its reduced record (16 doubles) and one
+// record of 7 doubles per solid, for up to LBRMT_DIAG_NOALLOC_MAX_SOLIDS.
+namespace {
+constexpr size_t NOALLOC_PART_BYTES = 1024 * 11 * 8;
+constexpr size_t NOALLOC_PART_OFF = 0;
+constexpr size_t NOALLOC_OUT_OFF = NOALLOC_PART_BYTES;
+constexpr size_t NOALLOC_SOLID_OFF = NOALLOC_OUT_OFF + 256;
+constexpr size_t NOALLOC_BYTES =
+    NOALLOC_SOLID_OFF + (size_t)LBRMT_DIAG_NOALLOC_MAX_SOLIDS * 7 * 8;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
 
 namespace {
 
@@ -994,26 +1011,26 @@ int lbrmt_read_stress(lbrmt_ctx* c, double* sxx, double* sxy, double* syy)
     return LBRMT_OK;
 }
 
-int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
+// The reductions of lbrmt_diag with their scratch (per-block partial records,
+// the reduced record, the per-solid sums) at the given device pointers.
+static int diag_into(lbrmt_ctx* c, lbrmt_diag_t* out, double* dpart, double* dout, double* bsum)
 {
-    if (!c || !out) return LBRMT_EINVAL;
-    if (!c->inited) return LBRMT_ESTATE;
     const StepSlots s = slots_for(c->step);
     BodyP none{};
     HIPCHK(c, launch_diag(c->g, c->d.precision, c->multi ? none : c->body, c->lat[s.cur],
                           c->Fx[s.nxt], c->Fy[s.nxt], c->bb.win, s.wprev, fpo_x(c, c->step),
-                          fpo_y(c, c->step), c->bb, s.cur, c->dpart, c->dout, c->st,
+                          fpo_y(c, c->step), c->bb, s.cur, dpart, dout, c->st,
                           prev_valid(c)));
     double h[16];
     unsigned hc[LBRMT_H_COUNT];
     std::vector<double> bs;
-    HIPCHK(c, hipMemcpyAsync(h, c->dout, 11 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(h, dout, 11 * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipMemcpyAsync(hc, c->bb.health, sizeof hc, hipMemcpyDeviceToHost, c->st));
     if (c->multi && c->nsolid > 0) {
         bs.resize((size_t)c->nsolid * 7);
-        HIPCHK(c, launch_mb_diag(c->d.precision, c->mbd, c->nsolid, s.cur, s.wprev, c->bsum,
+        HIPCHK(c, launch_mb_diag(c->d.precision, c->mbd, c->nsolid, s.cur, s.wprev, bsum,
                                  c->st));
-        HIPCHK(c, hipMemcpyAsync(bs.data(), c->bsum, bs.size() * sizeof(double),
+        HIPCHK(c, hipMemcpyAsync(bs.data(), bsum, bs.size() * sizeof(double),
                                  hipMemcpyDeviceToHost, c->st));
     }
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1047,6 +1064,62 @@ int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
         hc[LBRMT_H_LIST_OVERFLOW] || !std::isfinite(h[0]))
         return LBRMT_EUNSTABLE;
     return LBRMT_OK;
+}
+
+int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
+{
+    if (!c || !out) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    return diag_into(c, out, c->dpart, c->dout, c->bsum);
+}
+
+// lbrmt_diag_noalloc: the same reductions with their scratch in a file-scope
+// device array instead of the context's workspace.  Each GPU holds its own
+// copy of the array (until the process ends); its address on a device is
+// looked up once, with that device current, on the first call there.  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// only the looked-up address is passed to kernels and copies.
+int lbrmt_diag_noalloc(lbrmt_ctx* c, lbrmt_diag_t* out)
+{
+    if (!c || !out) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    if (c->multi && c->nsolid > LBRMT_DIAG_NOALLOC_MAX_SOLIDS) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "lbrmt_diag_noalloc: %d solids exceed the %d its static scratch holds",
+                 c->nsolid, (int)LBRMT_DIAG_NOALLOC_MAX_SOLIDS);
+        c->err = buf;
+        return LBRMT_EINVAL;
+    }
+    if (diag_partial_doubles() * 8 > NOALLOC_PART_BYTES) {
+        c->err = "lbrmt_diag_noalloc: partial records exceed the static scratch";
+        return LBRMT_EINVAL;
+    }
+    char* base = nullptr;
+    {
+        int dev = -1;
+        HIPCHK(c, hipGetDevice(&dev));
+        if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+            c->err = "lbrmt_diag_noalloc: device index beyond the supported range";
+            return LBRMT_EINVAL;
+        }
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            if (!p) {
+                c->err = "lbrmt_diag_noalloc: no device address for the static scratch";
+                return LBRMT_EHIP;
+            }
+            g_scratch_ptr[dev] = (char*)p;
+        }
+        base = g_scratch_ptr[dev];
+    }
+    // every kernel of the diagnostic writes its whole slice of the scratch
+    // (one record per reduction block, the reduced record, one record per
+    // solid), so nothing is cleared first
+    return diag_into(c, out, (double*)(base + NOALLOC_PART_OFF), (double*)(base + NOALLOC_OUT_OFF),
+                     (double*)(base + NOALLOC_SOLID_OFF));
 }
 
 int lbrmt_diag_solid(lbrmt_ctx* c, int32_t solid, double* out)

@@ -110,6 +110,7 @@ def lib():
             "lbrmt_read_refmap": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
             "lbrmt_read_stress": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
             "lbrmt_diag": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_diag_t)]),
+            "lbrmt_diag_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_diag_t)]),
             "lbrmt_diag_solid": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
             "lbrmt_snapshot_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
             "lbrmt_step_snapshot": (ctypes.c_int, [_vp, _vp]),
@@ -280,15 +281,23 @@ def lbrmt_read_stress(ctx, sxx, sxy, syy):
            ctx)
 
 
-def lbrmt_diag(ctx, raise_unstable=True):
+def _diag_call(name, ctx, raise_unstable):
     out = lbrmt_diag_t()
-    rc = lib().lbrmt_diag(ctx, ctypes.byref(out))
+    rc = getattr(lib(), name)(ctx, ctypes.byref(out))
     if rc != LBRMT_EUNSTABLE or raise_unstable:
-        _check(rc, "lbrmt_diag", ctx)
+        _check(rc, name, ctx)
     d = {k: getattr(out, k) for k, _ in lbrmt_diag_t._fields_ if k != "health"}
     d["health"] = dict(zip(HEALTH_NAMES, list(out.health)))
     d["status"] = rc
     return d
+
+
+def lbrmt_diag(ctx, raise_unstable=True):
+    return _diag_call("lbrmt_diag", ctx, raise_unstable)
+
+
+def lbrmt_diag_noalloc(ctx, raise_unstable=True):
+    return _diag_call("lbrmt_diag_noalloc", ctx, raise_unstable)
 
 
 def lbrmt_diag_solid(ctx, solid):
