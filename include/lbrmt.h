@@ -204,7 +204,9 @@ int lbrmt_read_refmap(lbrmt_ctx* ctx, int32_t solid, double* d_X, double* d_Y, d
 int lbrmt_read_stress(lbrmt_ctx* ctx, double* d_sxx, double* d_sxy, double* d_syy);
 
 /* Reductions of the current state into host memory (synchronises the stream).
- * Returns EUNSTABLE if a NONFINITE, DETJ_SOLID or EXTRAP_FAIL counter is set.
+ * Returns EUNSTABLE if a NONFINITE, DETJ_SOLID, EXTRAP_FAIL, LIST_OVERFLOW or
+ * WINDOW_CLIP counter is set or the mass is not finite (the output is filled
+ * in either case).
  * With several solids the solid terms are summed over all solids. */
 int lbrmt_diag(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
 /* lbrmt_diag for callers that cannot allocate device memory (code that must

@@ -1061,7 +1061,7 @@ static int diag_into(lbrmt_ctx* c, lbrmt_diag_t* out, double* dpart, double* dou
     out->max_u = h[10];
     for (int k = 0; k < LBRMT_H_COUNT; k++) out->health[k] = hc[k];
     if (hc[LBRMT_H_NONFINITE] || hc[LBRMT_H_DETJ_SOLID] || hc[LBRMT_H_EXTRAP_FAIL] ||
-        hc[LBRMT_H_LIST_OVERFLOW] || !std::isfinite(h[0]))
+        hc[LBRMT_H_LIST_OVERFLOW] || hc[LBRMT_H_WINDOW_CLIP] || !std::isfinite(h[0]))
         return LBRMT_EUNSTABLE;
     return LBRMT_OK;
 }
