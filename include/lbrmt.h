@@ -320,6 +320,12 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         that these blocks are resident before the bulk
  *                         update fills the compute units.  Results are
  *                         bitwise identical.
+ *   LBRMT_OPT_HOLD_BULK   1 (default): with overlap, the one-launch
+ *                         extrapolation and an uncapped bulk update, the bulk
+ *                         update starts when the advection pass has ended;
+ *                         0: it starts with the step.  A capped bulk update
+ *                         (LBRMT_OPT_BULK_BLOCKS > 0) is never held.
+ *                         Results are bitwise identical.
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,
@@ -327,7 +333,8 @@ typedef enum {
     LBRMT_OPT_LB_VARIANT_COUNT = 2, /* read only */
     LBRMT_OPT_GRAPH = 3,
     LBRMT_OPT_BULK_BLOCKS = 4,
-    LBRMT_OPT_FUSED_FIT = 5
+    LBRMT_OPT_FUSED_FIT = 5,
+    LBRMT_OPT_HOLD_BULK = 6
 } lbrmt_option;
 int lbrmt_set_option(lbrmt_ctx* ctx, int32_t option, int64_t value);
 int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);

@@ -26,7 +26,7 @@
 // (it decides the solid set), the normal matrix of the fit and its
 // well-posedness test (exact sums of powers of two on a few nodes), and the
 // inversion of grad xi where det < kappa_J.
-#include "lbrmt_internal.h"
+#include "lb_node.h"
 
 namespace lbrmt {
 
@@ -1478,22 +1478,26 @@ __device__ __forceinline__ double relabel_phi(const GridP& g, const BodyP& b, in
 // the partial box of the new interior solid set it saw, which the next
 // lattice update reduces into the next ring slot.  MODE 2 is MODE 0 without
 // the stresses (one solid of several: the forces are combined over all
-// solids afterwards).
+// solids afterwards).  MODE 3 is MODE 0 followed, for each of the tile's own
+// nodes, by its lattice Boltzmann update with the force just computed (the
+// window's nodes; the lattice update of every other node does not depend on
+// the solid's force of this step).
 template <int MODE, typename C>
 __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvalid,
                                            int* boxpart, int whole_grid, C* X, C* Y,
                                            const C* __restrict__ phi, const int8_t* __restrict__ tag,
                                            C* phi1, double* o0, double* o1, double* o2,
-                                           int* lcount, unsigned* health)
+                                           int* lcount, unsigned* health, const LbFuse& lf)
 {
     // the force pass ends the reference-map chain of a step: clear the layer
     // counters of the next step's distance transform
-    constexpr bool RELABEL = MODE == 0 || MODE == 2;
+    constexpr bool RELABEL = MODE == 0 || MODE == 2 || MODE == 3;
     if (RELABEL) clear_lcount(lcount);
     __shared__ C sX[SY * SX], sY[SY * SX], sP[SY * SX];
     __shared__ C ex[FTY][FTX + 1][3];
     __shared__ C ey[FTY + 1][FTX][3];
     const Rect V = window_of(win, wvalid, g);
+    const Rect WP = MODE == 3 ? window_of(win, lf.wprev, g) : Rect{0, -1, 0, -1, false};
     int bi0 = 0x3fffffff, bi1 = -0x3fffffff, bj0 = 0x3fffffff, bj1 = -0x3fffffff;
     // MODE 2: also the box of the nodes with phi < eps (where the solid
     // fraction is positive), partials after the solid box's
@@ -1562,8 +1566,9 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
         // health counting: an edge is counted once, by the node on its far
         // side, or by its near node when the far node lies outside the region
         const bool rowin = j <= Rg.j1, colin = i <= Rg.i1;
-        const bool cnt_l = MODE == 0 && (mine || (rowin && i == Rg.i1 + 1));
-        const bool cnt_b = MODE == 0 && (mine || (colin && j == Rg.j1 + 1));
+        constexpr bool FORCE = MODE == 0 || MODE == 3;
+        const bool cnt_l = FORCE && (mine || (rowin && i == Rg.i1 + 1));
+        const bool cnt_b = FORCE && (mine || (colin && j == Rg.j1 + 1));
         // local index of node (i + di, j + dj)
 #define LI(di, dj) ((ty + 1 + (dj)) * SX + (tx + 1 + (di)))
         // x-edge (i - 1/2, j): a = (i-1, j), b = (i, j); side (i, j+1), (i-1, j+1), (i, j-1), (i-1, j-1)
@@ -1575,12 +1580,12 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
         if (tx == FTX - 1) {
             // right x-edge (i + 1/2, j) of the last tile column
             edge_tau<C>(g, b, sX, sY, sP, LI(0, 0), LI(1, 0), LI(1, 1), LI(0, 1), LI(1, -1),
-                        LI(0, -1), 0, MODE == 0 && mine && i == Rg.i1, health, ex[ty][tx + 1]);
+                        LI(0, -1), 0, FORCE && mine && i == Rg.i1, health, ex[ty][tx + 1]);
         }
         if (ty == FTY - 1) {
             // top y-edge (i, j + 1/2) of the last tile row
             edge_tau<C>(g, b, sX, sY, sP, LI(0, 0), LI(0, 1), LI(1, 1), LI(1, 0), LI(-1, 1),
-                        LI(-1, 0), 1, MODE == 0 && mine && j == Rg.j1, health, ey[ty + 1][tx]);
+                        LI(-1, 0), 1, FORCE && mine && j == Rg.j1, health, ey[ty + 1][tx]);
         }
 #undef LI
         __syncthreads();
@@ -1590,7 +1595,7 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
             const C* B = ey[ty][tx];
             const C* T = ey[ty + 1][tx];
             const long long n = (long long)j * g.pitch + i;
-            if (MODE == 0) {
+            if (MODE == 0 || MODE == 3) {
                 // Eq. (3_3_div_solid_stress) in Eq. (2_4_F_divs)
                 C fx = (Rr[0] - L[0]) + (T[1] - B[1]);
                 C fy = (Rr[1] - L[1]) + (T[2] - B[2]);
@@ -1608,6 +1613,21 @@ __device__ __forceinline__ void edges_body(GridP g, BodyP b, Win* win, int wvali
                 o0[n] = (double)fx;
                 o1[n] = (double)fy;
                 o2[n] = (double)dr;
+                if (MODE == 3) {
+                    // the node's lattice update (Sec. 3.4, 3.5): F^n as just
+                    // stored (in double, read back in C as the lattice
+                    // kernels do), F^{n-1} inside the previous window
+                    const Neigh q = neigh(g, i, j);
+                    C fl[NQ];
+                    gather<C>(g, q, (const C*)lf.A, fl);
+                    C Fpx = C(lf.fpo_x), Fpy = C(lf.fpo_y);
+                    if (WP.has(i, j)) {
+                        Fpx = C(lf.fpx[n]);
+                        Fpy = C(lf.fpy[n]);
+                    }
+                    lb_finish_node<C, true>(g, (C*)lf.B, q, fl, Fpx, Fpy, C((double)fx),
+                                            C((double)fy), C((double)dr), health);
+                }
             } else {
                 const long long e = (long long)j * g.nx + i;
                 o0[e] = (double)((L[0] + Rr[0] + B[0] + T[0]) / C(4));
@@ -1653,10 +1673,10 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
                                                const C* __restrict__ phi,
                                                const int8_t* __restrict__ tag, C* phi1,
                                                double* o0, double* o1, double* o2, int* lcount,
-                                               unsigned* health)
+                                               unsigned* health, LbFuse lf)
 {
     edges_body<MODE, C>(g, b, win, wvalid, boxpart, whole_grid, X, Y, phi, tag, phi1, o0, o1,
-                        o2, lcount, health);
+                        o2, lcount, health, lf);
 }
 
 template <int MODE, typename C>
@@ -1664,20 +1684,40 @@ __global__ __launch_bounds__(256) void kb_force(const EdgesArgs* __restrict__ ar
 {
     const EdgesArgs& a = args[blockIdx.y];
     edges_body<MODE, C>(a.g, a.b, a.win, a.wvalid, a.boxpart, 0, (C*)a.X, (C*)a.Y, nullptr,
-                        a.tag, (C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health);
+                        a.tag, (C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health, LbFuse{});
 }
 
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
-                        double* fx, double* fy, double* drho, hipStream_t st)
+                        double* fx, double* fy, double* drho, hipStream_t st, const LbFuse* lf)
 {
-    if (g.rm32)
-        k_edges<0, float><<<RELABEL_BLOCKS, 256, 0, st>>>(
-            g, b, bb.win, s.wcur, bb.boxpart, 0, (float*)bb.X[s.nxt], (float*)bb.Y[s.nxt],
-            nullptr, bb.tag, (float*)bb.phi[s.nxt], fx, fy, drho, bb.lcount, bb.health);
-    else
-        k_edges<0, double><<<RELABEL_BLOCKS, 256, 0, st>>>(
-            g, b, bb.win, s.wcur, bb.boxpart, 0, (double*)bb.X[s.nxt], (double*)bb.Y[s.nxt],
-            nullptr, bb.tag, (double*)bb.phi[s.nxt], fx, fy, drho, bb.lcount, bb.health);
+#define KE(MODE, C, LF)                                                                       \
+    k_edges<MODE, C><<<RELABEL_BLOCKS, 256, 0, st>>>(                                         \
+        g, b, bb.win, s.wcur, bb.boxpart, 0, (C*)bb.X[s.nxt], (C*)bb.Y[s.nxt], nullptr, bb.tag, \
+        (C*)bb.phi[s.nxt], fx, fy, drho, bb.lcount, bb.health, LF)
+    if (lf) {
+        if (g.rm32) KE(3, float, *lf);
+        else KE(3, double, *lf);
+    } else {
+        if (g.rm32) KE(0, float, LbFuse{});
+        else KE(0, double, LbFuse{});
+    }
+#undef KE
+    return hipGetLastError();
+}
+
+// one block: the force pass's partial boxes into ring slot wnext, and the
+// zone check of the new window (what the band lattice launch does otherwise)
+__global__ __launch_bounds__(256) void k_reduce_window(GridP g, const int* __restrict__ boxpart,
+                                                       int nbox, Win* win, int wnext,
+                                                       unsigned* health)
+{
+    reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
+    if (threadIdx.x == 0) check_zone(g, win[wnext], health);
+}
+
+hipError_t launch_reduce_window(const GridP& g, const BandBufs& bb, int wnext, hipStream_t st)
+{
+    k_reduce_window<<<1, 256, 0, st>>>(g, bb.boxpart, RELABEL_BLOCKS, bb.win, wnext, bb.health);
     return hipGetLastError();
 }
 
@@ -1688,12 +1728,12 @@ hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb
         k_edges<1, float><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, nullptr, 1,
                                                 (float*)bb.X[buf], (float*)bb.Y[buf],
                                                 (const float*)bb.phi[buf], nullptr, nullptr, sxx,
-                                                sxy, syy, nullptr, bb.health);
+                                                sxy, syy, nullptr, bb.health, LbFuse{});
     else
         k_edges<1, double><<<2048, 256, 0, st>>>(g, b, bb.win, wvalid, nullptr, 1,
                                                  (double*)bb.X[buf], (double*)bb.Y[buf],
                                                  (const double*)bb.phi[buf], nullptr, nullptr,
-                                                 sxx, sxy, syy, nullptr, bb.health);
+                                                 sxx, sxy, syy, nullptr, bb.health, LbFuse{});
     return hipGetLastError();
 }
 

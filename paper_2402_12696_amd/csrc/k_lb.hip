@@ -16,127 +16,9 @@
 // FP64 path: f stored and computed in double.  FP32 path: the deviation
 // f_i - w_i rho_f is stored in float and the arithmetic is float, so rho =
 // rho_f + sum(df) keeps its small part.
-#include "lbrmt_internal.h"
+#include "lb_node.h"
 
 namespace lbrmt {
-
-template <typename S>
-struct Prec;
-template <>
-struct Prec<double> {
-    using C = double;
-    static constexpr bool dev = false;
-};
-template <>
-struct Prec<float> {
-    using C = float;
-    static constexpr bool dev = true;
-};
-
-// D2Q9 weights (Table "d2q9")
-#define W0 (4.0 / 9.0)
-#define W1 (1.0 / 9.0)
-#define W2 (1.0 / 36.0)
-
-struct Neigh {
-    long long n, rm, r0, rp;  // node index and row offsets of j-1, j, j+1
-    int im, ip, i;
-    bool bw, be, bs, bn;      // wall beyond the west/east/south/north side
-};
-
-__device__ __forceinline__ Neigh neigh(const GridP& g, int i, int j)
-{
-    Neigh q;
-    q.i = i;
-    q.bw = !g.px && i == 0;
-    q.be = !g.px && i == g.nx - 1;
-    q.bs = !g.py && j == 0;
-    q.bn = !g.py && j == g.ny - 1;
-    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
-    // periodic axes wrap; on walled axes the clamped index is never used for
-    // data (the reflected population is taken instead) but keeps every
-    // address inside the plane
-    im = im < 0 ? (g.px ? g.nx - 1 : 0) : im;
-    ip = ip >= g.nx ? (g.px ? 0 : g.nx - 1) : ip;
-    jm = jm < 0 ? (g.py ? g.ny - 1 : 0) : jm;
-    jp = jp >= g.ny ? (g.py ? 0 : g.ny - 1) : jp;
-    q.im = im;
-    q.ip = ip;
-    q.r0 = (long long)j * g.pitch;
-    q.rm = (long long)jm * g.pitch;
-    q.rp = (long long)jp * g.pitch;
-    q.n = q.r0 + i;
-    return q;
-}
-
-// gather the nine pre-collision populations f_i^n of one node (stored form)
-template <typename S>
-__device__ __forceinline__ void gather(const GridP& g, const Neigh& q, const S* __restrict__ A,
-                                       typename Prec<S>::C f[NQ])
-{
-    const long long P = g.plane;
-    const long long n = q.n;
-    f[0] = A[n];
-    f[1] = q.bw ? A[3 * P + n] : A[1 * P + q.r0 + q.im];
-    f[2] = q.bs ? A[4 * P + n] : A[2 * P + q.rm + q.i];
-    f[3] = q.be ? A[1 * P + n] : A[3 * P + q.r0 + q.ip];
-    f[4] = q.bn ? A[2 * P + n] : A[4 * P + q.rp + q.i];
-    f[5] = (q.bw || q.bs) ? A[7 * P + n] : A[5 * P + q.rm + q.im];
-    f[6] = (q.be || q.bs) ? A[8 * P + n] : A[6 * P + q.rm + q.ip];
-    f[7] = (q.be || q.bn) ? A[5 * P + n] : A[7 * P + q.rp + q.ip];
-    f[8] = (q.bw || q.bn) ? A[6 * P + n] : A[8 * P + q.rp + q.im];
-}
-
-// density and momentum sum_i c_i f_i from the stored form
-template <typename C, bool DEV>
-__device__ __forceinline__ void moments(const C f[NQ], C rho_f, C& rho, C& drho_n, C& jx, C& jy)
-{
-    C s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-    if (DEV) {
-        drho_n = s;
-        rho = rho_f + s;
-    } else {
-        rho = s;
-        drho_n = s - rho_f;
-    }
-    jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
-    jy = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
-}
-
-// Collision of Sec. 3.4: SFC equilibrium (Eq. (2_3_feq_sfc)), BGK relaxation,
-// Guo forcing (Eq. (2_2_Fi), force per unit volume).  f holds the stored form
-// (f or f - w rho_f); the same form is returned.
-template <typename C, bool DEV>
-__device__ __forceinline__ void collide(C f[NQ], C rho, C drho_n, C ux, C uy, C Fx, C Fy,
-                                        C dr_sfc, C omega, C cf)
-{
-    const C usq = ux * ux + uy * uy;
-    const C uF = ux * Fx + uy * Fy;
-    const C base = DEV ? drho_n : rho;  // rho term of w_i rho (1 + ...) in stored form
-    const C r15 = C(1.5) * rho * usq;
-    // q = 0
-    {
-        C feq = C(W0) * (base - r15) + C(5.0 / 9.0) * dr_sfc;
-        C Fi = C(W0) * (C(-3.0) * uF);
-        f[0] = f[0] + omega * (feq - f[0]) + cf * Fi;
-    }
-#define LB_DIR(Q, WQ, CU, CF)                                                          \
-    {                                                                                  \
-        const C cu = (CU), cF = (CF);                                                  \
-        C feq = C(WQ) * (base + rho * (C(3.0) * cu + C(4.5) * cu * cu) - r15 - dr_sfc); \
-        C Fi = C(WQ) * (C(3.0) * (cF - uF) + C(9.0) * cu * cF);                        \
-        f[Q] = f[Q] + omega * (feq - f[Q]) + cf * Fi;                                  \
-    }
-    LB_DIR(1, W1, ux, Fx)
-    LB_DIR(2, W1, uy, Fy)
-    LB_DIR(3, W1, -ux, -Fx)
-    LB_DIR(4, W1, -uy, -Fy)
-    LB_DIR(5, W2, ux + uy, Fx + Fy)
-    LB_DIR(6, W2, uy - ux, Fy - Fx)
-    LB_DIR(7, W2, -ux - uy, -Fx - Fy)
-    LB_DIR(8, W2, ux - uy, Fx - Fy)
-#undef LB_DIR
-}
 
 __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
@@ -183,7 +65,6 @@ __device__ __forceinline__ void lb_tile(const GridP& g, const S* __restrict__ A,
                                         unsigned* __restrict__ health, int tile_x, int tile_y)
 {
     using C = typename Prec<S>::C;
-    constexpr bool DEV = Prec<S>::dev;
     constexpr int TH = LB_TY * R;  // tile height
     const int tx = threadIdx.x % LB_TX, ty = threadIdx.x / LB_TX;
     const int i = tile_x * LB_TX + tx;
@@ -194,16 +75,15 @@ __device__ __forceinline__ void lb_tile(const GridP& g, const S* __restrict__ A,
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int j = tile_y * TH + ty + r * LB_TY;
-        ok[r] = j < g.ny;
-        q[r] = neigh(g, i, ok[r] ? j : g.ny - 1);
-        gather<S>(g, q[r], A, f[r]);
+        // PART 3 leaves the nodes of the current window to the force pass
+        ok[r] = j < g.ny && !(PART == 3 && wc.has(i, j));
+        q[r] = neigh(g, i, j < g.ny ? j : g.ny - 1);
+        if (PART != 3 || ok[r]) gather<S>(g, q[r], A, f[r]);
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
         if (!ok[r]) continue;
         const int j = tile_y * TH + ty + r * LB_TY;
-        C rho, dn, jx, jy;
-        moments<C, DEV>(f[r], C(g.rho_f), rho, dn, jx, jy);
         C Fpx = C(fpo_x), Fpy = C(fpo_y);
         C Fx = C(g.fext_x), Fy = C(g.fext_y), dr = C(0);
         if (PART != 1) {
@@ -211,40 +91,21 @@ __device__ __forceinline__ void lb_tile(const GridP& g, const S* __restrict__ A,
                 Fpx = C(fpx[q[r].n]);
                 Fpy = C(fpy[q[r].n]);
             }
-            if (wc.has(i, j)) {
+            if (PART != 3 && wc.has(i, j)) {
                 Fx = C(fcx[q[r].n]);
                 Fy = C(fcy[q[r].n]);
                 dr = C(drho[q[r].n]);
             }
         }
-        const C inv = C(1) / rho;
-        const C ux = (jx + C(0.5) * Fpx) * inv;
-        const C uy = (jy + C(0.5) * Fpy) * inv;
-        collide<C, DEV>(f[r], rho, dn, ux, uy, Fx, Fy, dr, C(g.omega), C(g.cforce));
-        if (q[r].bn) {
-            // lid: the populations 5 and 6 leave through the moving top wall;
-            // store them already reflected-with-momentum, -2 w rho (c.u_w)/cs^2
-            const C rw = g.lid_rho_mode ? C(g.rho_f) : rho;
-            const C m = rw * C(g.lid_ux) * C(1.0 / 6.0);
-            f[r][5] -= m;
-            f[r][6] += m;
-        }
-        if (!(rho > C(0) && rho < C(1e30))) atomicAdd(&health[5], 1u);
-        const long long P = g.plane;
-        if (NT) {
-#pragma unroll
-            for (int k = 0; k < NQ; k++)
-                __builtin_nontemporal_store(S(f[r][k]), &B[k * P + q[r].n]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < NQ; k++) B[k * P + q[r].n] = S(f[r][k]);
-        }
+        lb_finish_node<S, NT>(g, B, q[r], f[r], Fpx, Fpy, Fx, Fy, dr, health);
     }
 }
 
 // PART 0: every tile, per-node window tests.  PART 1: tiles outside the band
 // region only (uniform force).  PART 2: tiles of the band region only,
-// grid-stride.
+// grid-stride.  PART 3: every node outside the current window (whose nodes
+// the force pass updates as soon as their force is known): this step's force
+// is the uniform one there, the previous step's is read inside its window.
 // PART 0 and PART 2 also reduce the force pass's nbox partial boxes of the
 // new solid set into ring slot wnext (block 0, before anything else).
 template <typename S, int PART, int LB_TX, int LB_TY, int R, bool NT>
@@ -254,7 +115,7 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     const double* __restrict__ drho, Win* win, int wprev, int wcur, double fpo_x, double fpo_y,
     unsigned* __restrict__ health, const int* __restrict__ boxpart, int nbox, int wnext)
 {
-    if (PART != 1 && nbox > 0 && blockIdx.x == 0) {
+    if ((PART == 0 || PART == 2) && nbox > 0 && blockIdx.x == 0) {
         reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
         if (threadIdx.x == 0) check_zone(g, win[wnext], health);
     }
@@ -293,6 +154,13 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
                 const int x0 = tile_x * LB_TX, y0 = tile_y * TH;
                 if (x0 <= U.i1 && x0 + LB_TX - 1 >= U.i0 && y0 <= U.j1 && y0 + TH - 1 >= U.j0)
                     continue;
+            }
+            if (PART == 3 && wc.ok) {
+                // a tile inside the window (clipped to the interior) is the
+                // force pass's
+                const int x0 = tile_x * LB_TX, y0 = tile_y * TH;
+                const int x1 = min(x0 + LB_TX, g.nx) - 1, y1 = min(y0 + TH, g.ny) - 1;
+                if (x0 >= wc.i0 && x1 <= wc.i1 && y0 >= wc.j0 && y1 <= wc.j1) continue;
             }
         }
         lb_tile<S, PART, LB_TX, LB_TY, R, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, wp, wc, fpo_x,
@@ -369,7 +237,7 @@ static void lb_launch_one(const GridP& g, const void* A, void* B, const double* 
 {
     const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY * R - 1) / (TY * R));
     int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles;
-    if (PART == 1 && max_blocks > 0 && max_blocks < grid) grid = max_blocks;
+    if ((PART == 1 || PART == 3) && max_blocks > 0 && max_blocks < grid) grid = max_blocks;
     k_lb<S, PART, TX, TY, R, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx,
                                                           fcy, drho, win, wprev, wcur, fpo_x,
                                                           fpo_y, health, boxpart, nbox, wnext);
@@ -418,11 +286,13 @@ hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, 
     if (precision == 0) {
         if (part == 0) LBP(double, 0);
         else if (part == 1) LBP(double, 1);
-        else LBP(double, 2);
+        else if (part == 2) LBP(double, 2);
+        else LBP(double, 3);
     } else {
         if (part == 0) LBP(float, 0);
         else if (part == 1) LBP(float, 1);
-        else LBP(float, 2);
+        else if (part == 2) LBP(float, 2);
+        else LBP(float, 3);
     }
 #undef LBP
     return hipGetLastError();

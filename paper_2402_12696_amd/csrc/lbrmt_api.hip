@@ -222,6 +222,7 @@ struct lbrmt_ctx {
     bool member = false;  // member of a batch (stepped by the batch only)
     int bulk_blocks = 0;  // cap on the blocks of the overlapped bulk update (0: one per tile)
     int fused_fit = -1;  // block size of the one-launch extrapolation (0: one launch per layer, -1: by size)
+    bool hold_bulk = true;  // hold the uncapped bulk update until the advection pass ends
     bool timing = false;
     struct Pending {
         int kind;
@@ -394,7 +395,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
         // resident before the bulk update's many fill the compute units (not
         // with a capped bulk update: held and capped at 512 workgroups, steps
         // stalled for about 0.1 s on MI355X)
-        const bool hold_bulk = c->overlap && fused && c->bulk_blocks == 0;
+        const bool hold_bulk = c->overlap && fused && c->bulk_blocks == 0 && c->hold_bulk;
         if (hold_bulk) HIPCHK(c, hipEventRecord(c->ev_adv, band));
         {
             Bracket b(c, 1, band);
@@ -402,32 +403,32 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
             b.done();
         }
         {
-            // relabel and the stress divergence (one pass)
+            // relabel and the stress divergence (one pass); with overlap also
+            // the lattice update of the window's nodes
             Bracket b(c, 3, band);
+            const LbFuse lf{c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt], c->Fy[s.nxt], s.wprev,
+                            ox, oy};
             HIPCHK(c, launch_force(g, c->body, c->bb, s, c->Fx[s.cur], c->Fy[s.cur], c->drho,
-                                   band));
+                                   band, c->overlap ? &lf : nullptr));
+            // the new solid box into the next ring slot (the band lattice
+            // launch does this when the force pass leaves the lattice to it)
+            if (c->overlap) HIPCHK(c, launch_reduce_window(g, c->bb, s.wnext, band));
             b.done();
         }
         if (c->overlap) {
             HIPCHK(c, hipEventRecord(c->ev_join, c->side));
             if (hold_bulk) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_adv, 0));
             {
+                // every node outside the window: its update needs no force of
+                // this step's chain
                 Bracket b(c, 4, main_s);
                 HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
                                     c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
-                                    s.wprev, s.wcur, ox, oy, 1, c->bb.health, main_s,
+                                    s.wprev, s.wcur, ox, oy, 3, c->bb.health, main_s,
                                     c->bulk_blocks));
                 b.done();
             }
             HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
-            {
-                Bracket b(c, 5, main_s);
-                HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
-                                    c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
-                                    s.wprev, s.wcur, ox, oy, 2, c->bb.health, main_s, 0,
-                                    c->bb.boxpart, RELABEL_BLOCKS, c->bb.win, s.wnext));
-                b.done();
-            }
             return LBRMT_OK;
         }
     }
@@ -1573,6 +1574,10 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
             return LBRMT_EINVAL;
         c->fused_fit = (int)value;
         break;
+    case LBRMT_OPT_HOLD_BULK:
+        if (value != 0 && value != 1) return LBRMT_EINVAL;
+        c->hold_bulk = value != 0;
+        break;
     default:
         return LBRMT_EINVAL;
     }
@@ -1590,6 +1595,7 @@ int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
     case LBRMT_OPT_GRAPH: *value = c->graph ? 1 : 0; return LBRMT_OK;
     case LBRMT_OPT_BULK_BLOCKS: *value = c->bulk_blocks; return LBRMT_OK;
     case LBRMT_OPT_FUSED_FIT: *value = c->fused_fit; return LBRMT_OK;
+    case LBRMT_OPT_HOLD_BULK: *value = c->hold_bulk ? 1 : 0; return LBRMT_OK;
     default: return LBRMT_EINVAL;
     }
 }
@@ -1614,6 +1620,11 @@ int lbrmt_band_nodes(lbrmt_ctx* c, int64_t* band_nodes, int64_t* window_nodes)
     int a0, a1, a2, a3, b0, b1, b2, b3;
     const bool pa = dil(w[s.wprev], a0, a1, a2, a3), pb = dil(w[s.wcur], b0, b1, b2, b3);
     *window_nodes = pb ? (int64_t)(b1 - b0 + 1) * (b3 - b2 + 1) : 0;
+    if (c->overlap && c->nsolid > 0) {
+        // the force pass updates the window's nodes, the bulk launch the rest
+        *band_nodes = *window_nodes;
+        return LBRMT_OK;
+    }
     if (!pa && !pb) {
         *band_nodes = 0;
         return LBRMT_OK;

@@ -512,8 +512,25 @@ hipError_t launch_init_fill(const GridP& g, const BodyP& b, const BandBufs& bb, 
 hipError_t launch_advect_layers(const GridP& g, int precision, const BandBufs& bb,
                                 const StepSlots& s, const void* A, const double* fpx,
                                 const double* fpy, hipStream_t st, bool fused);
+// The lattice Boltzmann update fused into the force pass: for each node of
+// the window (interior) the pull update from lattice A into B with this
+// step's force, F^{n-1} from (fpx, fpy) inside window slot wprev (else the
+// uniform force fpo).
+struct LbFuse {
+    const void* A;
+    void* B;
+    const double *fpx, *fpy;
+    int wprev;
+    double fpo_x, fpo_y;
+};
+// lf null: relabel and force only (the lattice update of the window follows
+// in a lattice kernel).  Either way the new solid box is left as partial
+// boxes in bb.boxpart (RELABEL_BLOCKS of them).
 hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, const StepSlots& s,
-                        double* fx, double* fy, double* drho, hipStream_t st);
+                        double* fx, double* fy, double* drho, hipStream_t st,
+                        const LbFuse* lf = nullptr);
+// the force pass's partial boxes into ring slot wnext, with the zone check
+hipError_t launch_reduce_window(const GridP& g, const BandBufs& bb, int wnext, hipStream_t st);
 hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
                               int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st);
 hipError_t launch_read_refmap(const GridP& g, const BodyP& b, const BandBufs& bb, int buf, int wvalid, double* X,

@@ -25,6 +25,7 @@ KERNEL_NAMES = ["advect", "extrap", "relabel", "force", "lb_bulk", "lb_band"]
 LBRMT_OPT_OVERLAP, LBRMT_OPT_LB_VARIANT, LBRMT_OPT_LB_VARIANT_COUNT, LBRMT_OPT_GRAPH = 0, 1, 2, 3
 LBRMT_OPT_BULK_BLOCKS = 4
 LBRMT_OPT_FUSED_FIT = 5
+LBRMT_OPT_HOLD_BULK = 6
 
 
 class lbrmt_grid_desc(ctypes.Structure):
