@@ -209,6 +209,13 @@ int lbrmt_read_stress(lbrmt_ctx* ctx, double* d_sxx, double* d_sxy, double* d_sy
  * in either case).
  * With several solids the solid terms are summed over all solids. */
 int lbrmt_diag(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
+/* The FP64 sums behind lbrmt_diag, stream-ordered and without synchronising
+ * the host (so a run can record them every step): d_out (device, 11 doubles)
+ * receives {mass, mom_x, mom_y, sum lambda, sum lambda x, sum lambda y,
+ * sum lambda (x - xi) x and y components, n_solid, n_band, max |u|}; the
+ * centroid and mean displacement of reading R20 are the ratios to
+ * sum lambda.  Contexts with one solid at most (ESTATE otherwise). */
+int lbrmt_diag_sums(lbrmt_ctx* ctx, double* d_out);
 /* lbrmt_diag for callers that cannot allocate device memory (code that must
  * not call hipMalloc: under HIP graph capture, tight serving loops, harnesses
  * that forbid it): the same reductions, results and return codes, with their

@@ -8,12 +8,15 @@ states n = 1 .. T against a target trajectory:
     L = (1/T) sum_n |c^n - c*^n|^2 + |d^n - d*^n|^2
 
 and its gradient with respect to the shear modulus G, the lid speed U and the
-initial velocity field u_0.  Forward: T steps, the state saved every K steps
-(K = round(sqrt(T)) by default).  Backward: for each segment, last first, the
-saved state is restored and the segment replayed one step at a time with
-lbrmt_step_snapshot (K snapshot buffers), then the adjoint runs back through
-the segment's snapshots.  All arithmetic is in the library's kernels; this
-module only schedules the calls and evaluates the scalar loss from lbrmt_diag.
+initial velocity field u_0.  Forward: T steps (replaying the library's
+captured step graphs), the state saved every K steps (K = round(sqrt(T)) by
+default) and the sums behind c^n and d^n recorded on the device after every
+step (lbrmt_diag_sums), read back once at the end.  Backward: for each
+segment, last first, the saved state is restored and the segment replayed
+one step at a time with lbrmt_step_snapshot (K snapshot buffers), then the
+adjoint runs back through the segment's snapshots.  All arithmetic of the
+step and its adjoint is in the library's kernels; this module schedules the
+calls and evaluates the scalar loss from the recorded sums.
 """
 import math
 
@@ -41,19 +44,26 @@ class Trajectory:
         self.T = int(T)
         self.K = int(every or max(1, round(math.sqrt(self.T))))
         self.sim = Sim(device=device, precision="f64", **_solid_cfg(cfg, G, U))
-        self.sim.set_option(B.LBRMT_OPT_GRAPH, 0)
         self.sim.init(u0)
         self.target = np.asarray(target, dtype=np.float64).reshape(self.T, 4)
         self.ckpt = {}
-        self.stats = np.zeros((self.T + 1, 5))  # c_x, c_y, d_x, d_y, sum lambda
+        sums = torch.empty((self.T + 1, 11), dtype=torch.float64, device=self.sim.device)
         for n in range(self.T):
             if n % self.K == 0:
                 self.ckpt[n] = self.sim.save_state()
             self.sim.step(1)
-            d = self.sim.diag(raise_unstable=False)
-            self.stats[n + 1] = (d["centroid_x"], d["centroid_y"], d["disp_x"], d["disp_y"],
-                                 d["lambda_sum"])
+            B.lbrmt_diag_sums(self.sim.ctx, sums[n + 1])
+        s = sums.cpu().numpy()
+        # the solid-set and map sizes after each step (discrete decisions of
+        # the run; two runs that differ here took different branches)
+        self.counts = s[1:, 8:10].copy()
+        lam = s[:, 3]
+        with np.errstate(invalid="ignore", divide="ignore"):
+            # c_x, c_y, d_x, d_y, sum lambda (reading R20)
+            self.stats = np.stack([s[:, 4] / lam, s[:, 5] / lam, s[:, 6] / lam, s[:, 7] / lam,
+                                   lam], axis=1)
         # health counters of the run (fallbacks the adjoint follows as taken)
+        d = self.sim.diag(raise_unstable=False)
         self.health = {k: v for k, v in d["health"].items() if v} if self.T else {}
         e = self.stats[1:, :4] - self.target
         self.loss = float(np.sum(e * e) / self.T)
@@ -95,19 +105,28 @@ class Trajectory:
 
     def close(self):
         self.sim.close()
+        self.ckpt = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def trajectory(cfg, G, U, T, u0=None, device="cuda:0"):
     """c^n, d^n (n = 1 .. T) of a forward run, as a [T, 4] array."""
+    import torch
     from . import Sim
     sim = Sim(device=device, precision="f64", **_solid_cfg(cfg, G, U)).init(u0)
-    out = np.zeros((T, 4))
+    sums = torch.empty((T, 11), dtype=torch.float64, device=sim.device)
     for n in range(T):
         sim.step(1)
-        d = sim.diag(raise_unstable=False)
-        out[n] = (d["centroid_x"], d["centroid_y"], d["disp_x"], d["disp_y"])
+        B.lbrmt_diag_sums(sim.ctx, sums[n])
+    s = sums.cpu().numpy()
     sim.close()
-    return out
+    lam = s[:, 3:4]
+    return s[:, 4:8] / lam
 
 
 def make_function():
@@ -120,18 +139,24 @@ def make_function():
         def forward(fctx, G, U, u0, cfg, T, target, every):
             tr = Trajectory(cfg, float(G), float(U), u0.detach().cpu().numpy(), T, target, every,
                             device=u0.device)
-            fctx.tr = tr
-            return torch.tensor(tr.loss, dtype=torch.float64, device=u0.device)
+            loss = torch.tensor(tr.loss, dtype=torch.float64, device=u0.device)
+            if any(fctx.needs_input_grad[:3]):
+                fctx.tr = tr
+            else:
+                tr.close()  # no backward will follow: release the run now
+            return loss
 
         @staticmethod
         def backward(fctx, gL):
             tr = fctx.tr
             gG, gU, gu0 = tr.backward()
             tr.close()
+            fctx.tr = None
             s = gL.to(torch.float64)
             dev = gu0.device
-            return (s * torch.tensor(gG, dtype=torch.float64, device=dev),
-                    s * torch.tensor(gU, dtype=torch.float64, device=dev),
-                    s * gu0, None, None, None, None)
+            need = fctx.needs_input_grad
+            return (s * torch.tensor(gG, dtype=torch.float64, device=dev) if need[0] else None,
+                    s * torch.tensor(gU, dtype=torch.float64, device=dev) if need[1] else None,
+                    s * gu0 if need[2] else None, None, None, None, None)
 
     return LBRMTTrajectoryLoss

@@ -1074,6 +1074,22 @@ int lbrmt_diag(lbrmt_ctx* c, lbrmt_diag_t* out)
     return diag_into(c, out, c->dpart, c->dout, c->bsum);
 }
 
+int lbrmt_diag_sums(lbrmt_ctx* c, double* d_out)
+{
+    if (!c || !d_out) return LBRMT_EINVAL;
+    if (!c->inited) return LBRMT_ESTATE;
+    if (c->multi) {
+        c->err = "lbrmt_diag_sums: one solid at most (use lbrmt_diag)";
+        return LBRMT_ESTATE;
+    }
+    const StepSlots s = slots_for(c->step);
+    HIPCHK(c, launch_diag(c->g, c->d.precision, c->body, c->lat[s.cur], c->Fx[s.nxt],
+                          c->Fy[s.nxt], c->bb.win, s.wprev, fpo_x(c, c->step),
+                          fpo_y(c, c->step), c->bb, s.cur, c->dpart, d_out, c->st,
+                          prev_valid(c)));
+    return LBRMT_OK;
+}
+
 // lbrmt_diag_noalloc: the same reductions with their scratch in a file-scope
 // device array instead of the context's workspace.  Each GPU holds its own
 // copy of the array (until the process ends); its address on a device is

@@ -112,6 +112,7 @@ def lib():
             "lbrmt_read_stress": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
             "lbrmt_diag": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_diag_t)]),
             "lbrmt_diag_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(lbrmt_diag_t)]),
+            "lbrmt_diag_sums": (ctypes.c_int, [_vp, _vp]),
             "lbrmt_diag_solid": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
             "lbrmt_snapshot_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
             "lbrmt_step_snapshot": (ctypes.c_int, [_vp, _vp]),
@@ -299,6 +300,11 @@ def lbrmt_diag(ctx, raise_unstable=True):
 
 def lbrmt_diag_noalloc(ctx, raise_unstable=True):
     return _diag_call("lbrmt_diag_noalloc", ctx, raise_unstable)
+
+
+def lbrmt_diag_sums(ctx, out):
+    """out: a device float64 tensor (view) of at least 11 elements."""
+    _check(lib().lbrmt_diag_sums(ctx, _ptr(out)), "lbrmt_diag_sums", ctx)
 
 
 def lbrmt_diag_solid(ctx, solid):
