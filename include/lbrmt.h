@@ -97,8 +97,9 @@ typedef struct {
  * half-edges), and the density rho_f + sum_i lambda_i (rho_s,i - rho_f) /
  * max(1, sum_i lambda_i).  A solid whose zone comes closer than `layers`
  * nodes to its window's border raises LBRMT_H_WINDOW_CLIP (the window does
- * not move; results are wrong from then on).  Not available with several
- * solids: lbrmt_read_stress, the checkpoint calls, the tile-shape options. */
+ * not move; results are wrong from then on, and lbrmt_diag returns
+ * EUNSTABLE).  Not available with several solids: the tile-shape options,
+ * the autotuners and the adjoint. */
 
 /* One solid (Sec. 3.6 "mat_const"/"object"): a disc (shape 0) of radius a, or
  * an ellipse (shape 1) of semi-axes a and b whose a axis makes the angle theta
@@ -135,7 +136,11 @@ typedef struct {
     int64_t step;            /* completed steps                                  */
     double mass;             /* sum_nodes sum_i f_i                              */
     double mom_x, mom_y;     /* sum_nodes (sum_i c_i f_i + F/2)                  */
-    double centroid_x, centroid_y; /* sum lambda x / sum lambda, lambda = 1 - H(phi) */
+    /* the solid's centroid and mean displacement, weighted by its fraction
+     * lambda = 1 - H(phi) (Eq. (2_3_heaviside)); the paper tracks a solid's
+     * centroid (Sec. 4.1, Fig. 4_1_ldc) without defining it, this is the
+     * smooth (differentiable) reading */
+    double centroid_x, centroid_y; /* sum lambda x / sum lambda                  */
     double disp_x, disp_y;   /* sum lambda (x - xi) / sum lambda                 */
     double max_u;            /* max |u|                                          */
     double n_solid;          /* nodes with phi < 0                               */
@@ -196,11 +201,15 @@ int lbrmt_read_macro(lbrmt_ctx* ctx, double* d_rho, double* d_ux, double* d_uy);
 int lbrmt_read_populations(lbrmt_ctx* ctx, double* d_f9);
 /* force density F used by the last step (Eq. (2_4_F_divs)) */
 int lbrmt_read_force(lbrmt_ctx* ctx, double* d_fx, double* d_fy);
-/* reference map xi = (X, Y) and level set phi of solid `solid`; NaN where the
- * node holds no reference map.  Any pointer may be NULL. */
+/* reference map xi = (X, Y) and level set phi = phi0(xi) of solid `solid`
+ * on the fixed grid (Sec. 3, Fig. 3_mmap: each solid's own map over its solid
+ * nodes and extrapolation zone); NaN where the node holds no map of that
+ * solid.  Any pointer may be NULL. */
 int lbrmt_read_refmap(lbrmt_ctx* ctx, int32_t solid, double* d_X, double* d_Y, double* d_phi);
 /* node average of the four blended half-edge solid stresses (1-H) tau_s
- * (Eqs. (3_3_solid_stress), (2_4_smooth_stress)); xx, xy, yy planes. */
+ * (Eqs. (3_3_solid_stress), (2_4_smooth_stress)); xx, xy, yy planes.  With
+ * several solids the global half-edge stress of Eq. (3_6_global_stress):
+ * the normalised blend plus the contact stress of every pair. */
 int lbrmt_read_stress(lbrmt_ctx* ctx, double* d_sxx, double* d_sxy, double* d_syy);
 
 /* Reductions of the current state into host memory (synchronises the stream).
@@ -213,7 +222,7 @@ int lbrmt_diag(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
  * the host (so a run can record them every step): d_out (device, 11 doubles)
  * receives {mass, mom_x, mom_y, sum lambda, sum lambda x, sum lambda y,
  * sum lambda (x - xi) x and y components, n_solid, n_band, max |u|}; the
- * centroid and mean displacement of reading R20 are the ratios to
+ * centroid and mean displacement of lbrmt_diag_t are the ratios to
  * sum lambda.  Contexts with one solid at most (ESTATE otherwise). */
 int lbrmt_diag_sums(lbrmt_ctx* ctx, double* d_out);
 /* lbrmt_diag for callers that cannot allocate device memory (code that must
@@ -235,7 +244,12 @@ int lbrmt_diag_noalloc(lbrmt_ctx* ctx, lbrmt_diag_t* host_out);
 int lbrmt_diag_solid(lbrmt_ctx* ctx, int32_t solid, double* host_out6);
 
 /* Checkpoint: an opaque device blob of lbrmt_state_bytes bytes holding the
- * whole step state; load restores it bit for bit (same context shape). */
+ * whole step state (with several solids: every solid's maps, window and
+ * region, the force-block stamps and lists); load restores it bit for bit
+ * into a context of the same shape (grid, precision, solid count and window
+ * sizes), whatever that context held before, and returns EINVAL with a
+ * message for a blob of another shape.  Save and load synchronise the
+ * context's stream; the buffer is the caller's. */
 int lbrmt_state_bytes(const lbrmt_ctx* ctx, size_t* bytes);
 int lbrmt_save_state(lbrmt_ctx* ctx, void* d_buf);
 int lbrmt_load_state(lbrmt_ctx* ctx, const void* d_buf);

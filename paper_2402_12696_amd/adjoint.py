@@ -59,7 +59,8 @@ class Trajectory:
         self.counts = s[1:, 8:10].copy()
         lam = s[:, 3]
         with np.errstate(invalid="ignore", divide="ignore"):
-            # c_x, c_y, d_x, d_y, sum lambda (reading R20)
+            # lambda-weighted centroid (c_x, c_y) and mean displacement
+            # (d_x, d_y) of the solid, and the weight sum lambda
             self.stats = np.stack([s[:, 4] / lam, s[:, 5] / lam, s[:, 6] / lam, s[:, 7] / lam,
                                    lam], axis=1)
         # health counters of the run (fallbacks the adjoint follows as taken)

@@ -1950,12 +1950,17 @@ __device__ __forceinline__ C contact_f(C x, C eps)
 }
 
 // force density and density excess of lattice node (gi, gj) from the solids
-// sl[0 .. ns) (index order) of its block
+// sl[0 .. ns) (index order) of its block.  mode 0: force and density excess
+// (fxo, fyo, drho: lattice planes); 1: density excess only; 2: the node
+// average of the four global half-edge solid stresses (blend and contact)
+// into fxo, fyo, drho as the xx, xy, yy planes of a read ([ny][nx]), with no
+// health counts.
 template <typename C>
 __device__ void mb_node(const GridP& lg, const MbBody* __restrict__ bodies, const int* sl,
                         int ns, int buf, int wcur, int gi, int gj, double* fxo, double* fyo,
-                        double* drho, bool drho_only, unsigned* health)
+                        double* drho, int mode, unsigned* health)
 {
+    const bool drho_only = mode == 1;
     C acc[4][3], lse[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
@@ -1988,7 +1993,8 @@ __device__ void mb_node(const GridP& lg, const MbBody* __restrict__ bodies, cons
             C t[3];
             // each edge is counted once: by its far node (the L and B edges)
             edge_tau<C>(g, B.b, sX, sY, sP, a, b, MB_EDGE[e][2], MB_EDGE[e][3], MB_EDGE[e][4],
-                        MB_EDGE[e][5], MB_EDGE[e][6], e == 0 || e == 2, health, t);
+                        MB_EDGE[e][5], MB_EDGE[e][6], mode == 0 && (e == 0 || e == 2), health,
+                        t);
             acc[e][0] += t[0];
             acc[e][1] += t[1];
             acc[e][2] += t[2];
@@ -1996,7 +2002,7 @@ __device__ void mb_node(const GridP& lg, const MbBody* __restrict__ bodies, cons
     }
     const long long n = (long long)gj * lg.pitch + gi;
     const C dr = lsum > C(1) ? dacc / lsum : dacc;
-    drho[n] = (double)dr;
+    if (mode != 2) drho[n] = (double)dr;
     if (drho_only) return;
 #pragma unroll
     for (int e = 0; e < 4; e++)
@@ -2061,6 +2067,13 @@ __device__ void mb_node(const GridP& lg, const MbBody* __restrict__ bodies, cons
             }
         }
     }
+    if (mode == 2) {
+        const long long r = (long long)gj * lg.nx + gi;
+        fxo[r] = (double)((acc[0][0] + acc[1][0] + acc[2][0] + acc[3][0]) / C(4));
+        fyo[r] = (double)((acc[0][1] + acc[1][1] + acc[2][1] + acc[3][1]) / C(4));
+        drho[r] = (double)((acc[0][2] + acc[1][2] + acc[2][2] + acc[3][2]) / C(4));
+        return;
+    }
     // Eq. (3_3_div_solid_stress) on the node's four edges, buoyancy of the
     // mixture and the fluid's share of the external force
     C fx = (acc[1][0] - acc[0][0]) + (acc[3][1] - acc[2][1]);
@@ -2074,24 +2087,25 @@ __device__ void mb_node(const GridP& lg, const MbBody* __restrict__ bodies, cons
     fyo[n] = (double)fy;
 }
 
+// mode as mb_node; list null: every force block (nblk_all of them)
 template <typename C>
 __global__ __launch_bounds__(256) void k_mb_combine(GridP lg, const MbBody* __restrict__ bodies,
                                                     int nb, int buf, int wcur,
                                                     const int* __restrict__ list,
                                                     const int* __restrict__ count,
                                                     int* count_clear, int nbx, double* fx,
-                                                    double* fy, double* drho, int drho_only,
-                                                    unsigned* health)
+                                                    double* fy, double* drho, int mode,
+                                                    unsigned* health, int nblk_all)
 {
     static_assert(FB * FB == 256, "one thread per node of a force block");
     if (blockIdx.x == 0 && threadIdx.x == 0 && count_clear) *count_clear = 0;
     __shared__ int sl[MB_MAX_PER_BLOCK];
     __shared__ int wcnt[4];
     __shared__ int ns;
-    const int nblk = *count;
+    const int nblk = list ? *count : nblk_all;
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     for (int t = blockIdx.x; t < nblk; t += gridDim.x) {
-        const int blk = list[t];
+        const int blk = list ? list[t] : t;
         const int bx0 = (blk % nbx) * FB, by0 = (blk / nbx) * FB;
         if (threadIdx.x == 0) ns = 0;
         __syncthreads();
@@ -2112,7 +2126,7 @@ __global__ __launch_bounds__(256) void k_mb_combine(GridP lg, const MbBody* __re
             for (int u = 0; u < w; u++) off += wcnt[u];
             if (hit) {
                 if (off < MB_MAX_PER_BLOCK) sl[off] = k;
-                else atomicAdd(&health[7], 1u);
+                else if (mode != 2) atomicAdd(&health[7], 1u);
             }
             __syncthreads();
             if (threadIdx.x == 0) ns = min(ns + wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3],
@@ -2121,8 +2135,7 @@ __global__ __launch_bounds__(256) void k_mb_combine(GridP lg, const MbBody* __re
         }
         const int gi = bx0 + threadIdx.x % FB, gj = by0 + threadIdx.x / FB;
         if (gi < lg.nx && gj < lg.ny)
-            mb_node<C>(lg, bodies, sl, ns, buf, wcur, gi, gj, fx, fy, drho, drho_only != 0,
-                       health);
+            mb_node<C>(lg, bodies, sl, ns, buf, wcur, gi, gj, fx, fy, drho, mode, health);
         __syncthreads();
     }
 }
@@ -2135,11 +2148,40 @@ hipError_t launch_mb_combine(const GridP& lg, int precision, const MbBody* bodie
     if (precision == 0)
         k_mb_combine<double><<<MB_COMBINE_BLOCKS, 256, 0, st>>>(
             lg, bodies, nb, buf, wcur, list, count, count_clear, nbx, fx, fy, drho,
-            drho_only ? 1 : 0, health);
+            drho_only ? 1 : 0, health, 0);
     else
         k_mb_combine<float><<<MB_COMBINE_BLOCKS, 256, 0, st>>>(
             lg, bodies, nb, buf, wcur, list, count, count_clear, nbx, fx, fy, drho,
-            drho_only ? 1 : 0, health);
+            drho_only ? 1 : 0, health, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mb_read_stress(const GridP& lg, int precision, const MbBody* bodies, int nb,
+                                 int buf, int wslot, int nbx, int nby, double* sxx, double* sxy,
+                                 double* syy, unsigned* health, hipStream_t st)
+{
+    if (precision == 0)
+        k_mb_combine<double><<<MB_COMBINE_BLOCKS, 256, 0, st>>>(
+            lg, bodies, nb, buf, wslot, nullptr, nullptr, nullptr, nbx, sxx, sxy, syy, 2, health,
+            nbx * nby);
+    else
+        k_mb_combine<float><<<MB_COMBINE_BLOCKS, 256, 0, st>>>(
+            lg, bodies, nb, buf, wslot, nullptr, nullptr, nullptr, nbx, sxx, sxy, syy, 2, health,
+            nbx * nby);
+    return hipGetLastError();
+}
+
+// the region boxes of the solids from a saved copy of the solid table (every
+// other field of a table entry is fixed by the context)
+__global__ void k_mb_copy_reg(const MbBody* __restrict__ src, MbBody* dst, int nb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nb) dst[k].reg = src[k].reg;
+}
+
+hipError_t launch_mb_copy_reg(const MbBody* src, MbBody* dst, int nb, hipStream_t st)
+{
+    k_mb_copy_reg<<<(nb + 255) / 256, 256, 0, st>>>(src, dst, nb);
     return hipGetLastError();
 }
 

@@ -1003,11 +1003,12 @@ int lbrmt_read_stress(lbrmt_ctx* c, double* sxx, double* sxy, double* syy)
 {
     if (!c || !sxx || !sxy || !syy) return LBRMT_EINVAL;
     if (!c->inited) return LBRMT_ESTATE;
-    if (c->multi) {
-        c->err = "lbrmt_read_stress: not available with several solids";
-        return LBRMT_ESTATE;
-    }
     const StepSlots s = slots_for(c->step);
+    if (c->multi) {
+        HIPCHK(c, launch_mb_read_stress(c->g, c->d.precision, c->mbd, c->nsolid, s.cur, s.wprev,
+                                        c->L.nbx, c->L.nby, sxx, sxy, syy, c->bb.health, c->st));
+        return LBRMT_OK;
+    }
     HIPCHK(c, launch_read_stress(c->g, c->body, c->bb, s.cur, s.wprev, sxx, sxy, syy, c->st));
     return LBRMT_OK;
 }
@@ -1406,6 +1407,12 @@ struct StateHeader {
     uint64_t lat_bytes, plane_bytes, pplane_bytes;
 };
 
+// Blob layout.  One solid: header, lattice, F^{n-1}, xi, phi, window ring and
+// health.  Several solids (off[4..7] differ): the two force-block stamp
+// arrays with the block-list counters and the device step counter, the
+// solid table (only its region boxes are restored: the rest is fixed by the
+// context), and every solid's block (its maps of both steps, tags, lists and
+// window ring), then the health counters.
 static size_t state_layout(const lbrmt_ctx* c, size_t off[8])
 {
     size_t o = 0;
@@ -1418,11 +1425,44 @@ static size_t state_layout(const lbrmt_ctx* c, size_t off[8])
     off[1] = take(c->L.lat_bytes);     // lattice A
     off[2] = take(c->L.plane * 8);     // F^{n-1} x
     off[3] = take(c->L.plane * 8);     // F^{n-1} y
+    if (c->multi) {
+        const size_t nblk = (size_t)c->L.nbx * c->L.nby;
+        off[4] = take(2 * nblk * 4);                        // stamps
+        off[5] = take(2 * 4 + 8);                           // list counters, step counter
+        off[6] = take((size_t)c->nsolid * sizeof(MbBody));  // solid table
+        off[7] = take((size_t)c->nsolid * c->L.body_bytes + LBRMT_H_COUNT * sizeof(unsigned));
+        return o;
+    }
     off[4] = take(c->L.pplane * c->L.rm_es);    // X
     off[5] = take(c->L.pplane * c->L.rm_es);    // Y
     off[6] = take(c->L.pplane * c->L.rm_es);    // phi
     off[7] = take(3 * sizeof(Win) + LBRMT_H_COUNT * sizeof(unsigned));
     return o;
+}
+
+// the several-solid parts of a blob (off from state_layout); load: blob -> ctx
+static int state_copy_mb(lbrmt_ctx* c, char* b, const size_t off[8], bool load)
+{
+    const hipMemcpyKind D2D = hipMemcpyDeviceToDevice;
+    const size_t nblk = (size_t)c->L.nbx * c->L.nby;
+    const size_t bodies = (size_t)c->nsolid * c->L.body_bytes;
+    char* bod = c->ws + c->L.off_bodies;
+    auto cp = [&](void* ctxp, size_t boff, size_t n) {
+        return load ? hipMemcpyAsync(ctxp, b + boff, n, D2D, c->st)
+                    : hipMemcpyAsync(b + boff, ctxp, n, D2D, c->st);
+    };
+    for (int k = 0; k < 2; k++) HIPCHK(c, cp(c->stamp[k], off[4] + k * nblk * 4, nblk * 4));
+    HIPCHK(c, cp(c->mcount, off[5], 2 * 4));
+    HIPCHK(c, cp(c->dstep, off[5] + 8, 8));
+    if (load) {
+        HIPCHK(c, launch_mb_copy_reg((const MbBody*)(b + off[6]), c->mbd, c->nsolid, c->st));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(b + off[6], c->mbd, (size_t)c->nsolid * sizeof(MbBody), D2D,
+                                 c->st));
+    }
+    HIPCHK(c, cp(bod, off[7], bodies));
+    HIPCHK(c, cp(c->bb.health, off[7] + bodies, LBRMT_H_COUNT * sizeof(unsigned)));
+    return LBRMT_OK;
 }
 
 int lbrmt_state_bytes(const lbrmt_ctx* c, size_t* bytes)
@@ -1437,10 +1477,6 @@ int lbrmt_save_state(lbrmt_ctx* c, void* buf)
 {
     if (!c || !buf) return LBRMT_EINVAL;
     if (!c->inited) return LBRMT_ESTATE;
-    if (c->multi) {
-        c->err = "checkpoints are not available with several solids";
-        return LBRMT_ESTATE;
-    }
     size_t off[8];
     state_layout(c, off);
     char* b = (char*)buf;
@@ -1451,6 +1487,14 @@ int lbrmt_save_state(lbrmt_ctx* c, void* buf)
     HIPCHK(c, hipMemcpyAsync(b + off[1], c->lat[s.cur], c->L.lat_bytes, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[2], c->Fx[s.nxt], c->L.plane * 8, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[3], c->Fy[s.nxt], c->L.plane * 8, D2D, c->st));
+    if (c->multi) {
+        h.pplane_bytes = c->L.body_bytes;
+        int rc = state_copy_mb(c, b, off, false);
+        if (rc != LBRMT_OK) return rc;
+        HIPCHK(c, hipMemcpyAsync(b + off[0], &h, sizeof h, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));  // h lives on this stack frame
+        return LBRMT_OK;
+    }
     HIPCHK(c, hipMemcpyAsync(b + off[4], c->bb.X[s.cur], c->L.pplane * c->L.rm_es, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[5], c->bb.Y[s.cur], c->L.pplane * c->L.rm_es, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(b + off[6], c->bb.phi[s.cur], c->L.pplane * c->L.rm_es, D2D, c->st));
@@ -1464,7 +1508,7 @@ int lbrmt_save_state(lbrmt_ctx* c, void* buf)
 
 int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
 {
-    if (c && (c->member || c->multi)) return LBRMT_ESTATE;
+    if (c && c->member) return LBRMT_ESTATE;
     if (!c || !buf) return LBRMT_EINVAL;
     size_t off[8];
     state_layout(c, off);
@@ -1472,9 +1516,10 @@ int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
     StateHeader h;
     HIPCHK(c, hipMemcpyAsync(&h, b + off[0], sizeof h, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    const uint64_t shape_bytes = c->multi ? c->L.body_bytes : c->L.pplane * c->L.rm_es;
     if (h.magic != STATE_MAGIC || h.version != STATE_VERSION || h.nx != c->d.nx ||
         h.ny != c->d.ny || h.precision != c->d.precision || h.nsolid != c->nsolid ||
-        h.lat_bytes != c->L.lat_bytes || h.step < 0) {
+        h.lat_bytes != c->L.lat_bytes || h.pplane_bytes != shape_bytes || h.step < 0) {
         c->err = "state blob does not match this context";
         return LBRMT_EINVAL;
     }
@@ -1484,6 +1529,12 @@ int lbrmt_load_state(lbrmt_ctx* c, const void* buf)
     HIPCHK(c, hipMemcpyAsync(c->lat[s.cur], b + off[1], c->L.lat_bytes, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->Fx[s.nxt], b + off[2], c->L.plane * 8, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->Fy[s.nxt], b + off[3], c->L.plane * 8, D2D, c->st));
+    if (c->multi) {
+        int rc = state_copy_mb(c, (char*)b, off, true);
+        if (rc != LBRMT_OK) return rc;
+        c->inited = true;
+        return LBRMT_OK;
+    }
     HIPCHK(c, hipMemcpyAsync(c->bb.X[s.cur], b + off[4], c->L.pplane * c->L.rm_es, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bb.Y[s.cur], b + off[5], c->L.pplane * c->L.rm_es, D2D, c->st));
     HIPCHK(c, hipMemcpyAsync(c->bb.phi[s.cur], b + off[6], c->L.pplane * c->L.rm_es, D2D, c->st));

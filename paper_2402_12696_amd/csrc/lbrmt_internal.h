@@ -556,6 +556,13 @@ hipError_t launch_mb_combine(const GridP& lg, int precision, const MbBody* bodie
                              int buf, int wcur, const int* list, const int* count,
                              int* count_clear, int nbx, double* fx, double* fy, double* drho,
                              bool drho_only, unsigned* health, hipStream_t st);
+// node averages of the global half-edge solid stresses of the state whose
+// maps are in buffer buf over window slot wslot, into [ny][nx] planes
+hipError_t launch_mb_read_stress(const GridP& lg, int precision, const MbBody* bodies, int nb,
+                                 int buf, int wslot, int nbx, int nby, double* sxx, double* sxy,
+                                 double* syy, unsigned* health, hipStream_t st);
+// the region boxes of the solid table dst from a saved copy src (device)
+hipError_t launch_mb_copy_reg(const MbBody* src, MbBody* dst, int nb, hipStream_t st);
 hipError_t launch_mb_read_refmap(const GridP& lg, int precision, const MbBody* bodies, int k,
                                  int buf, int wvalid, double* X, double* Y, double* phi,
                                  hipStream_t st);

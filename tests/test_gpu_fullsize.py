@@ -9,7 +9,8 @@ the box), which shears and carries the disc from the first step: after 100
 steps its map has moved by ~1 node, so the advection, the extrapolation of a
 curved map, the stress and the coupled collision are all exercised at full
 size.  FP64 and FP32 are compared with the same oracle run, FP64 on the
-deviations of Sec. 8(c) too."""
+deviations (rho - rho_f, xi - x, each velocity
+component) too."""
 import numpy as np
 import pytest
 

@@ -204,3 +204,72 @@ def test_suspension_recipe_at_reduced_size_matches_oracle():
     # scale (from rest, gravity 1e-6 alone leaves max |u| ~ 1e-6 at step 1)
     cfg = workloads.suspension(n=384, nbody=8, seed=7)
     _run(cfg, (1, 10, 50), u0=workloads.uniform_velocity(384, 384, 0.01, 0.005))
+
+
+@pytest.mark.parametrize("cfgf,u0f,steps", [
+    (_cavity3, None, 60),
+    (_touching_periodic, "shear", 40),
+])
+def test_stress_with_several_solids_matches_oracle(cfgf, u0f, steps):
+    # the global half-edge stress of Eq. (3_6_global_stress) (blend of the
+    # solids normalised by their summed fraction, plus the contact stress of
+    # every pair) averaged over a node's four edges; the bar is the single-
+    # solid one (a first difference of xi divided by small map gradients)
+    cfg = cfgf()
+    u0 = None
+    if u0f == "shear":
+        n = cfg["nx"]
+        u0 = np.zeros((2, n, n))
+        x = np.arange(n) + 0.5
+        u0[0][:, x < n / 2 + 0.5] = 0.03
+        u0[0][:, x >= n / 2 + 0.5] = -0.03
+    sim, ref = _sim(cfg, u0=u0), Oracle(**cfg).init(u0)
+    sim.step(steps)
+    ref.step(steps)
+    s, rs = _np(sim.stress()), ref.stress()
+    for name, a, b in zip(("sxx", "sxy", "syy"), s, rs):
+        assert np.max(np.abs(b)) > 0, name
+        err = rel(a, b)
+        print(name, f"{err:.2e}", flush=True)
+        assert err < 1e-9, name
+    # reading the stress changes neither the state nor the health counters
+    sim.step(1)
+    ref.step(1)
+    compare_mb(sim, ref, 1e-10, f"step {steps + 1} after the read")
+    assert all(v == 0 for v in sim.diag()["health"].values())
+    sim.close()
+
+
+def test_checkpoint_resume_is_bitwise_with_several_solids():
+    cfg = _windowed()
+    n = cfg["nx"]
+    rng = np.random.default_rng(11)
+    u0 = workloads.uniform_velocity(n, n, 0.02, -0.01) + rng.normal(0.0, 5e-4, size=(2, n, n))
+
+    def fields(s):
+        return _np(s.macro()) + sum((_np(s.refmap(k)) for k in range(4)), []) + _np(s.force())
+
+    a = _sim(cfg, u0=u0).step(37)
+    blob = a.save_state()
+    a.step(50)
+    ra = fields(a)
+    # into a fresh context, and into one that has run on from other data
+    b = _sim(cfg)
+    b.load_state(blob)
+    assert b.step_count == 37
+    b.step(50)
+    c = _sim(cfg, u0=u0).step(61)
+    c.load_state(blob)
+    assert c.step_count == 37
+    c.step(50)
+    for s in (b, c):
+        for x, y in zip(ra, fields(s)):
+            assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0))
+        assert all(v == 0 for v in s.diag()["health"].values())
+    # a blob of another solid count is refused
+    cfg3 = dict(cfg, solids=cfg["solids"][:3])
+    d = _sim(cfg3)
+    with pytest.raises(RuntimeError, match="does not match"):
+        d.load_state(blob)
+    for s in (a, b, c, d):
+        s.close()

@@ -37,7 +37,7 @@ def rel(a, b):
 def compare(sim, ref, tol=TOL64, what="", dev_tol=None, eps=1.5):
     """Errors of the GPU state against the oracle's (printed); asserts rho,
     ux, uy, X, Y within tol.  With dev_tol it also asserts the stricter
-    errors of Sec. 8(c)'s deviations -- rho - rho_f, xi - x (over the nodes
+    errors of the deviations -- rho - rho_f, xi - x (over the nodes
     with phi < eps), and each velocity component against its own maximum --
     wherever the reference deviation is well above rounding (|rho - rho_f| >
     1e-9, |xi - x| > 1e-6, a component above 1 % of max |u|)."""
@@ -66,7 +66,7 @@ def compare(sim, ref, tol=TOL64, what="", dev_tol=None, eps=1.5):
             errs["X"] = rel(X[mr], RX[mr])
             errs["Y"] = rel(Y[mr], RY[mr])
             # the displacement over the nodes with phi < eps (the solid and
-            # its blur zone), the set of Sec. 8(c)'s xi norm; farther zone
+            # its blur zone), where the xi deviation is measured; farther zone
             # layers are extrapolations of extrapolations, where the rounding
             # of |xi| ~ n is amplified layer by layer
             y, x = np.mgrid[0:ref.ny, 0:ref.nx] + 0.5
@@ -221,7 +221,8 @@ def test_partial_graphs_equal_eager_launches():
 
 
 def test_lid_with_fluid_density_matches_oracle():
-    # reading R6 with rho_w = rho_f (lid_rho_mode 1) on a compressible cavity
+    # the moving-lid term with rho_w = rho_f (lid_rho_mode 1) on a
+    # compressible cavity
     cfg = workloads.cavity_disc_64()
     cfg["solid"]["rho_s"] = 1.3
     cfg["gravity"] = (0.0, -1e-4)

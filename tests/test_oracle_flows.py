@@ -154,7 +154,7 @@ def test_rigid_translation(shape):
 
 
 def test_lid_with_fluid_density_conserves_mass_and_differs_only_where_rho_does():
-    # reading R6, lid_rho_mode 1: the moving-lid term uses rho_f instead of the
+    # lid_rho_mode 1: the moving-lid term uses rho_f instead of the
     # node's density.  Both lid links of a top node still cancel (mass is
     # exact); a flow whose top-row density stays rho_f is unchanged, and a
     # compressible cavity flow is not.

@@ -12,9 +12,9 @@ missing normal factor, the wrong buoyancy) changes the result:
   intercept of a weighted least-squares fit computed here independently
   (numpy lstsq on sqrt(w)-scaled rows), with the valid set, the scan-window
   growth and the weights written from the paper's steps (i)-(iii).
-* The solid fraction of a half-edge (reading R10: 1 - H at the mean level set
+* The solid fraction of a half-edge (1 - H at the mean level set
   of its two nodes), through the node stress of a uniform shear.
-* The buoyancy of a heavy solid (reading R14: (1 - H)(rho_s - rho_f) g), through
+* The buoyancy of a heavy solid ((1 - H)(rho_s - rho_f) g per node), through
   the force and the first step's momentum change in a periodic box.
 """
 import numpy as np
@@ -106,9 +106,9 @@ def _wls_intercept(lay, Xv, Yv, phin, jt, it, l, r_max, det_rel):
     """Sec. 3.2 for target (jt, it) of layer l on padded arrays: grow the
     square scan window from half-width 2 until it holds at least three valid
     nodes (solid, or set in an earlier layer) and the weighted normal matrix
-    is well posed (reading R11); weights 2^-(|di| + |dj|), times the positive
+    is well posed; weights 2^-(|di| + |dj|), times the positive
     part of the cosine between d = x_t - x_k and the level-set normal for
-    layers 1 and 2 (reading R12); the value at the target is the intercept of
+    layers 1 and 2; the value at the target is the intercept of
     xi ~ A dx + B dy + C in target-centred coordinates."""
     ny, nx = lay.shape
     nrm = None
