@@ -341,12 +341,15 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         that these blocks are resident before the bulk
  *                         update fills the compute units.  Results are
  *                         bitwise identical.
- *   LBRMT_OPT_HOLD_BULK   1 (default): with overlap, the one-launch
+ *   LBRMT_OPT_HOLD_BULK   -1 (default): with overlap, the one-launch
  *                         extrapolation and an uncapped bulk update, the bulk
- *                         update starts when the advection pass has ended;
- *                         0: it starts with the step.  A capped bulk update
- *                         (LBRMT_OPT_BULK_BLOCKS > 0) is never held.
- *                         Results are bitwise identical.
+ *                         update starts when the advection pass has ended; a
+ *                         capped one (LBRMT_OPT_BULK_BLOCKS > 0) starts with
+ *                         the step.  1: held, and a cap is refused (EINVAL,
+ *                         either order of the two calls: a held and capped
+ *                         bulk update once stalled the step for about 0.1 s
+ *                         and is not offered).  0: never held.  Results are
+ *                         bitwise identical.
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,

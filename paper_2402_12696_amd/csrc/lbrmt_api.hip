@@ -222,7 +222,9 @@ struct lbrmt_ctx {
     bool member = false;  // member of a batch (stepped by the batch only)
     int bulk_blocks = 0;  // cap on the blocks of the overlapped bulk update (0: one per tile)
     int fused_fit = -1;  // block size of the one-launch extrapolation (0: one launch per layer, -1: by size)
-    bool hold_bulk = true;  // hold the uncapped bulk update until the advection pass ends
+    // hold the bulk update until the advection pass ends: -1 when it is
+    // uncapped (default), 1 always (refused with a cap), 0 never
+    int hold_bulk = -1;
     bool timing = false;
     struct Pending {
         int kind;
@@ -395,7 +397,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s)
         // resident before the bulk update's many fill the compute units (not
         // with a capped bulk update: held and capped at 512 workgroups, steps
         // stalled for about 0.1 s on MI355X)
-        const bool hold_bulk = c->overlap && fused && c->bulk_blocks == 0 && c->hold_bulk;
+        const bool hold_bulk = c->overlap && fused && c->bulk_blocks == 0 && c->hold_bulk != 0;
         if (hold_bulk) HIPCHK(c, hipEventRecord(c->ev_adv, band));
         {
             Bracket b(c, 1, band);
@@ -1633,6 +1635,10 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
         break;
     case LBRMT_OPT_BULK_BLOCKS:
         if (value < 0 || value > (1 << 24)) return LBRMT_EINVAL;
+        if (value > 0 && c->hold_bulk == 1) {
+            c->err = "a capped bulk update cannot be held (LBRMT_OPT_HOLD_BULK is 1)";
+            return LBRMT_EINVAL;
+        }
         c->bulk_blocks = (int)value;
         break;
     case LBRMT_OPT_FUSED_FIT:
@@ -1642,8 +1648,14 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
         c->fused_fit = (int)value;
         break;
     case LBRMT_OPT_HOLD_BULK:
-        if (value != 0 && value != 1) return LBRMT_EINVAL;
-        c->hold_bulk = value != 0;
+        if (value < -1 || value > 1) return LBRMT_EINVAL;
+        if (value == 1 && c->bulk_blocks > 0) {
+            // the held and capped combination stalled the stream for about
+            // 0.1 s per step once; it is not offered
+            c->err = "a capped bulk update cannot be held (LBRMT_OPT_BULK_BLOCKS > 0)";
+            return LBRMT_EINVAL;
+        }
+        c->hold_bulk = (int)value;
         break;
     default:
         return LBRMT_EINVAL;
@@ -1662,7 +1674,7 @@ int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
     case LBRMT_OPT_GRAPH: *value = c->graph ? 1 : 0; return LBRMT_OK;
     case LBRMT_OPT_BULK_BLOCKS: *value = c->bulk_blocks; return LBRMT_OK;
     case LBRMT_OPT_FUSED_FIT: *value = c->fused_fit; return LBRMT_OK;
-    case LBRMT_OPT_HOLD_BULK: *value = c->hold_bulk ? 1 : 0; return LBRMT_OK;
+    case LBRMT_OPT_HOLD_BULK: *value = c->hold_bulk; return LBRMT_OK;
     default: return LBRMT_EINVAL;
     }
 }

@@ -78,6 +78,31 @@ def test_fused_fit_option_values():
     sim.close()
 
 
+def test_hold_option_refuses_a_held_and_capped_bulk_update():
+    # a held bulk update with a cap on its workgroups is refused in either
+    # order of the two calls; -1 (default) holds only an uncapped update
+    from paper_2402_12696_amd import Sim
+    from paper_2402_12696_amd import lbrmt as B
+    sim = Sim(device="cuda:0", precision="f64", **workloads.cavity_disc_64())
+    assert sim.get_option(B.LBRMT_OPT_HOLD_BULK) == -1
+    sim.set_option(B.LBRMT_OPT_BULK_BLOCKS, 512)        # default hold: allowed
+    with pytest.raises(B.LBRMTError, match="cannot be held"):
+        sim.set_option(B.LBRMT_OPT_HOLD_BULK, 1)
+    assert sim.get_option(B.LBRMT_OPT_HOLD_BULK) == -1
+    sim.set_option(B.LBRMT_OPT_BULK_BLOCKS, 0)
+    sim.set_option(B.LBRMT_OPT_HOLD_BULK, 1)
+    with pytest.raises(B.LBRMTError, match="cannot be held"):
+        sim.set_option(B.LBRMT_OPT_BULK_BLOCKS, 512)
+    assert sim.get_option(B.LBRMT_OPT_BULK_BLOCKS) == 0
+    for v in (0, -1):
+        sim.set_option(B.LBRMT_OPT_HOLD_BULK, v)
+        assert sim.get_option(B.LBRMT_OPT_HOLD_BULK) == v
+    for v in (2, -2):
+        with pytest.raises(B.LBRMTError):
+            sim.set_option(B.LBRMT_OPT_HOLD_BULK, v)
+    sim.close()
+
+
 def test_autotune_steps_chooses_a_mode_and_steps_like_lbrmt_step():
     from paper_2402_12696_amd import Sim
     from paper_2402_12696_amd import lbrmt as B
