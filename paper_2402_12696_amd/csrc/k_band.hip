@@ -335,8 +335,11 @@ __device__ __forceinline__ bool upwind_d(C vel, C X0, C Y0, bool okm1, bool okm2
 // sets, the nine populations and the previous force) is issued before any is
 // used; addresses of absent nodes are clamped to the node itself.  S is both
 // the population and the reference-map storage type (FP64: xi; FP32:
-// population deviations and displacement).
-template <typename S>
+// population deviations and displacement).  LATCHK: every lattice node the
+// pull gather reads must lie in D (with the chain beside the bulk update,
+// the nodes of D are the ones the previous step's force pass updated); a
+// solid node on D's rim is counted as an advection miss and keeps its value.
+template <typename S, bool LATCHK = false>
 __device__ __forceinline__ void advect_node(const GridP& g, const S* __restrict__ A,
                                             const double* __restrict__ fpx,
                                             const double* __restrict__ fpy,
@@ -364,6 +367,25 @@ __device__ __forceinline__ void advect_node(const GridP& g, const S* __restrict_
     ip = ip >= g.lnx ? (g.lpx ? 0 : g.lnx - 1) : ip;
     jm = jm < 0 ? (g.lpy ? g.lny - 1 : 0) : jm;
     jp = jp >= g.lny ? (g.lpy ? 0 : g.lny - 1) : jp;
+    bool lat_ok = true;
+    if (LATCHK) {
+        // D is a rectangle holding (i, j): the four axis neighbours decide
+        int iw = i - 1, ie = i + 1, js = j - 1, jn = j + 1;
+        if (g.px) {
+            iw = wrap_axis(iw, g.nx);
+            ie = wrap_axis(ie, g.nx);
+        }
+        if (g.py) {
+            js = wrap_axis(js, g.ny);
+            jn = wrap_axis(jn, g.ny);
+        }
+        lat_ok = (bw || D.has(iw, j)) && (be || D.has(ie, j)) && (bs || D.has(i, js)) &&
+                 (bn || D.has(i, jn));
+        if (!lat_ok) {
+            im = ip = li;
+            jm = jp = lj;
+        }
+    }
     const long long r0 = (long long)lj * g.pitch, rm = (long long)jm * g.pitch,
                     rp = (long long)jp * g.pitch, n = r0 + li;
     // ---- all loads
@@ -401,7 +423,7 @@ __device__ __forceinline__ void advect_node(const GridP& g, const S* __restrict_
                                  okq[3], xs[2], ys[2], xs[3], ys[3], dXx, dYx);
     const bool oky = upwind_d<C>(v, X0, Y0, okq[4], okq[5], xs[4], ys[4], xs[5], ys[5], okq[6],
                                  okq[7], xs[6], ys[6], xs[7], ys[7], dXy, dYy);
-    if (!okx || !oky) {
+    if (!okx || !oky || !lat_ok) {
         atomicAdd(&health[0], 1u);
         X1[k] = X0;
         Y1[k] = Y0;
@@ -439,7 +461,7 @@ constexpr int DRW = DTX + 2 * MAX_LAYERS, DRH = DTY + 2 * MAX_LAYERS;
 // phi^n < 0, inside the previous window} is read from the level set, the
 // tile's solid nodes are tagged and advected (Sec. 3.1) in the same pass, and
 // the tags of the window are all written here.
-template <int LC, bool ADV, typename S, bool PRE = false>
+template <int LC, bool ADV, typename S, bool PRE = false, bool LATCHK = false>
 __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ win, int wslot,
                                              int wprev, int8_t* tag, int* lists, int* lcount,
                                              unsigned* health, const S* __restrict__ A,
@@ -583,7 +605,7 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
                 const int cx = e % DTX, cy = e / DTX;
                 const int x = x0 + cx, y = y0 + cy;
                 if (W.has(x, y) && sol[(cy + L) * DRW + cx + L])
-                    advect_node<S>(g, A, fpx, fpy, X, Y, phi, X1, Y1, D, x, y, health);
+                    advect_node<S, LATCHK>(g, A, fpx, fpy, X, Y, phi, X1, Y1, D, x, y, health);
             }
         }
         __syncthreads();
@@ -613,8 +635,8 @@ __global__ __launch_bounds__(256) void k_advect_dt(GridP g, const S* __restrict_
                                                    unsigned* health, int* ff_flag, int* ff_list,
                                                    int* ff_n)
 {
-    dt_tile_body<LC, true, S, true>(g, win, wcur, wprev, tag, lists, lcount, health, A, fpx, fpy,
-                                    X, Y, phi, X1, Y1, ff_flag, ff_list, ff_n);
+    dt_tile_body<LC, true, S, true, true>(g, win, wcur, wprev, tag, lists, lcount, health, A,
+                                          fpx, fpy, X, Y, phi, X1, Y1, ff_flag, ff_list, ff_n);
 }
 
 template <int LC, typename S>
