@@ -977,15 +977,14 @@ __device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const 
 
 // fit_target with the scan windows read from the block's staged copy of the
 // zone ((li, lj): the target's place in it)
+// (use_n, nxh, nyh: the normal weight of layers 1 and 2, found by the caller
+// as target_normal finds it)
 template <typename T>
-__device__ __forceinline__ bool fit_target_lds(const GridP& g, const Rect& D, int l, int i, int j,
-                                               int li, int lj, int sub, int rlim,
-                                               const T* __restrict__ phin, const int8_t* st,
-                                               const T* sx, const T* sy, int rw, T& xo, T& yo,
-                                               bool& cut)
+__device__ __forceinline__ bool fit_target_lds(const GridP& g, int l, int li, int lj, int sub,
+                                               int rlim, const int8_t* st, const T* sx,
+                                               const T* sy, int rw, T& xo, T& yo, bool& cut,
+                                               bool use_n, double nxh, double nyh)
 {
-    double nxh, nyh;
-    const bool use_n = target_normal<T>(g, D, l, i, j, sub, phin, nxh, nyh);
     cut = false;
     for (int r = 2; r <= g.r_max; r++) {
         if (r > rlim) {
@@ -1148,7 +1147,11 @@ __device__ void fit_rest(const GridP& g, const Rect& W, const Rect& D, int8_t* t
 // blocks find), then a block barrier, then layer l + 1.  The block works on a
 // copy in LDS: the tags and the advected solid values of the tile and a
 // margin of M_1 + 2 nodes are staged once, and each fitted value (or failure)
-// goes into the copy; only the tile's own targets are written back.  A scan
+// goes into the copy; only the tile's own targets are written back.  The
+// level-set normals of the layer-1 and layer-2 targets (the weights of
+// Eq. (3_2_extrap_weight)) are found before the layers, all their loads in
+// one round; a tile with more such targets than FF_NORMALS is stopped
+// before its first layer.  A scan
 // window of half-width 2 around a target within M_l of the tile stays within
 // M_l + 2 = M_{l-1}, where the copy holds every earlier layer, and layer-1
 // windows read solid nodes only, which the copy holds across the margin.  A
@@ -1156,8 +1159,9 @@ __device__ void fit_rest(const GridP& g, const Rect& W, const Rect& D, int8_t* t
 // the tile is listed, with the layer, for k_fit_rest, which finishes the
 // listed tiles layer by layer; the tile's layers before that one are final.
 // reach = 2; reach = 1 stops every tile with a target on the rim of its
-// margin at layer 2 (k_fit_rest then fits most of the zone: a check of that
-// launch).  Walled axes only (a window across a periodic seam would
+// margin at layer 2, and every tile with more than 64 targets in layers 1
+// and 2 before its first layer (k_fit_rest then fits most of the zone: a
+// check of that launch).  Walled axes only (a window across a periodic seam would
 // reach another tile's nodes).
 template <typename T, int NT>
 __device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __restrict__ win,
@@ -1176,7 +1180,14 @@ __device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __rest
     __shared__ short lst[RW * RW];  // the block's targets, layer by layer (places in the copy)
     __shared__ short cand[RW * RW];  // the same, in staging order
     __shared__ int s_cnt[FF_LAYERS + 1], s_base[FF_LAYERS + 2], s_fill[FF_LAYERS + 1];
-    __shared__ int s_n, s_cut, s_fail;
+    // per layer: a target needed a wider window than the copy holds; targets
+    // whose fit failed (own nodes)
+    __shared__ int s_cut[FF_LAYERS + 1], s_fail[FF_LAYERS + 1];
+    __shared__ int s_n;
+    // the level-set normals of the first FF_NORMALS layer-1 and layer-2
+    // targets (in list order), found before the layers (flag 1: exists)
+    __shared__ double s_nx[FF_NORMALS], s_ny[FF_NORMALS];
+    __shared__ int8_t s_nok[FF_NORMALS];
     const int ntile = *ff_n;
     if (blockIdx.x >= ntile) return;
     const Rect W = window_of(win, wcur, g);
@@ -1186,32 +1197,56 @@ __device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __rest
     const int S = 2 * (L - 1) + 2, rw = FF_TILE + 2 * S;  // margin of the copy, its width
     const int ntx = (W.i1 - W.i0 + FF_TILE) / FF_TILE;
     const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
+    constexpr int NIT = (RW * RW + NT - 1) / NT;  // staged nodes per thread
+    // normal slots in use (reach 1, a check of k_fit_rest: few, so that
+    // most tiles are stopped before their first layer)
+    const int ncap = reach == 1 ? 64 : FF_NORMALS;
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
         const int t = ff_list[k];
         const int x0 = W.i0 + (t % ntx) * FF_TILE, y0 = W.j0 + (t / ntx) * FF_TILE;
         __syncthreads();  // the previous tile's shared state is no longer read
-        if (threadIdx.x == 0) {
-            s_n = 0;
-            s_cut = 0;
-            s_fail = 0;
-        }
+        if (threadIdx.x == 0) s_n = 0;
         if (threadIdx.x <= FF_LAYERS) {
             s_cnt[threadIdx.x] = 0;
             s_fill[threadIdx.x] = 0;
+            s_cut[threadIdx.x] = 0;
+            s_fail[threadIdx.x] = 0;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < rw * rw; e += NT) {
+        // staging in two rounds of loads: every tag of the thread's nodes,
+        // then the values of its solid nodes
+        int8_t tvs[NIT];
+#pragma unroll
+        for (int u = 0; u < NIT; u++) {
+            const int e = threadIdx.x + u * NT;
             const int x = x0 - S + e % rw, y = y0 - S + e / rw;
-            const bool in = W.has(x, y);
+            const bool in = e < rw * rw && W.has(x, y);
             const long long kq = pidx(g, in ? x : W.i0, in ? y : W.j0);
-            int8_t tv = in ? tag[kq] : (int8_t)TAG_NONE;
+            tvs[u] = in ? tag[kq] : (int8_t)TAG_NONE;
+        }
+        T xs[NIT], ys[NIT];
+#pragma unroll
+        for (int u = 0; u < NIT; u++) {
+            const int e = threadIdx.x + u * NT;
+            const int x = x0 - S + e % rw, y = y0 - S + e / rw;
             // the owner of a margin node may have marked it failed already:
             // it is fitted here again, to the same verdict
-            if (tv > 0) tv = (int8_t)(tv & (TAG_FAIL - 1));
-            st[e] = tv;
+            if (tvs[u] > 0) tvs[u] = (int8_t)(tvs[u] & (TAG_FAIL - 1));
+            const bool solid = e < rw * rw && tvs[u] == TAG_SOLID;
+            const long long kq = pidx(g, solid ? x : W.i0, solid ? y : W.j0);
+            xs[u] = solid ? X1[kq] : T(0);
+            ys[u] = solid ? Y1[kq] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NIT; u++) {
+            const int e = threadIdx.x + u * NT;
+            if (e >= rw * rw) continue;
+            const int x = x0 - S + e % rw, y = y0 - S + e / rw;
+            const int tv = tvs[u];
+            st[e] = (int8_t)tv;
             if (tv == TAG_SOLID) {
-                sx[e] = X1[kq];
-                sy[e] = Y1[kq];
+                sx[e] = xs[u];
+                sy[e] = ys[u];
             }
             // a layer-l node is this block's target within M_l of the tile
             if (tv >= 1 && tv <= L) {
@@ -1237,6 +1272,40 @@ __device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __rest
             lst[s_base[l] + atomicAdd(&s_fill[l], 1)] = (short)q;
         }
         __syncthreads();
+        // the outward normals of phi^n of the layer-1 and layer-2 targets
+        // (weights of Eq. (3_2_extrap_weight)), all loads in one round: the
+        // same values and arithmetic as target_normal
+        {
+            // (none when they do not fit: the tile is stopped below)
+            const int n12 = s_base[min(L, 2) + 1] <= ncap ? s_base[min(L, 2) + 1] : 0;
+            for (int a = threadIdx.x; a < n12; a += NT) {
+                const int q = lst[a];
+                const int i = x0 - S + q % rw, j = y0 - S + q / rw;
+                const long long ke = ref_index(g, D, i + 1, j), kw = ref_index(g, D, i - 1, j);
+                const long long kn = ref_index(g, D, i, j + 1), ks = ref_index(g, D, i, j - 1);
+                const long long k0 = pidx(g, i, j);
+                const T pe = phin[ke >= 0 ? ke : k0], pw = phin[kw >= 0 ? kw : k0];
+                const T pn = phin[kn >= 0 ? kn : k0], ps = phin[ks >= 0 ? ks : k0];
+                double nxh = 0.0, nyh = 0.0;
+                const bool ok = normal_from(ke >= 0 ? (double)pe : INFINITY,
+                                            kw >= 0 ? (double)pw : INFINITY,
+                                            kn >= 0 ? (double)pn : INFINITY,
+                                            ks >= 0 ? (double)ps : INFINITY, nxh, nyh);
+                s_nx[a] = nxh;
+                s_ny[a] = nyh;
+                s_nok[a] = ok ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        // more layer-1 and layer-2 targets than normal slots: the tile is
+        // stopped before its first layer (k_fit_rest fits it)
+        if (s_base[min(L, 2) + 1] > ncap) {
+            if (threadIdx.x == 0) {
+                cut_layer[t] = (int8_t)1;
+                cut_tiles[atomicAdd(ncut, 1)] = t;
+            }
+            continue;
+        }
         for (int l = 1; l <= L; l++) {
             const int M = 2 * (L - l);
             const int n = s_cnt[l];
@@ -1250,10 +1319,14 @@ __device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __rest
                 const int i = x0 - S + li, j = y0 - S + lj;
                 const int rlim = min(g.r_max, min(min(li - (S - K), S + FF_TILE - 1 + K - li),
                                                   min(lj - (S - K), S + FF_TILE - 1 + K - lj)));
+                // the normal found above (layers 1 and 2)
+                const int pos = l <= 2 ? s_base[l] + a : 0;
+                const bool use_n = l <= 2 && s_nok[pos] != 0;
+                const double nxh = use_n ? s_nx[pos] : 0.0, nyh = use_n ? s_ny[pos] : 0.0;
                 T xo = T(0), yo = T(0);
                 bool cut;
-                const bool done = fit_target_lds<T>(g, D, l, i, j, li, lj, sub, rlim, phin, st,
-                                                    sx, sy, rw, xo, yo, cut);
+                const bool done = fit_target_lds<T>(g, l, li, lj, sub, rlim, st, sx, sy, rw, xo,
+                                                    yo, cut, use_n, nxh, nyh);
                 if (sub == 0) {
                     const bool own = i >= x0 && i < x0 + FF_TILE && j >= y0 && j < y0 + FF_TILE;
                     const long long kt = pidx(g, i, j);
@@ -1265,28 +1338,28 @@ __device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __rest
                             Y1[kt] = yo;
                         }
                     } else if (cut) {
-                        s_cut = 1;
+                        s_cut[l] = 1;
                     } else {
                         st[q] = (int8_t)(l | TAG_FAIL);
                         if (own) {
                             tag[kt] = (int8_t)(l | TAG_FAIL);
-                            atomicAdd(&s_fail, 1);
+                            atomicAdd(&s_fail[l], 1);
                         }
                     }
                 }
             }
+            // one barrier per layer: the decision reads this layer's flags,
+            // which the next layer does not write
             __syncthreads();
-            const bool stop = s_cut != 0;
+            const bool stop = s_cut[l] != 0;
             if (threadIdx.x == 0) {
                 if (stop) {
                     cut_layer[t] = (int8_t)l;
                     cut_tiles[atomicAdd(ncut, 1)] = t;
-                } else if (s_fail > 0) {
-                    atomicAdd(&health[1], (unsigned)s_fail);
+                } else if (s_fail[l] > 0) {
+                    atomicAdd(&health[1], (unsigned)s_fail[l]);
                 }
-                s_fail = 0;
             }
-            __syncthreads();
             if (stop) break;
         }
     }

@@ -30,6 +30,7 @@ constexpr int FF_LAYERS = 11;         // fused extrapolation: most layers
 constexpr int FF_BLOCKS = 256;        // fused extrapolation: blocks striding over its tile list
 constexpr int FF_NO_CUT = 127;        // tile not stopped (cut_layer)
 constexpr int FF_REST_THREADS = 256;  // fused extrapolation: the one-block pass
+constexpr int FF_NORMALS = 1024;      // fused extrapolation: layer-1/2 normals found up front
 constexpr int FF_BATCH_BLOCKS = 64;   // fused extrapolation of a batch: blocks per member
 
 // Several solids: the lattice is cut into force blocks of FB x FB nodes;
