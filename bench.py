@@ -48,12 +48,14 @@ def lb_bytes_per_node(precision):
 
 def traffic_from_profile(kernel, workload, precision):
     """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
-    when none exists or the kernel source changed since it was taken."""
+    when none exists or the lattice-update sources (k_lb.hip, lb_node.h)
+    changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_counters.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    src = open(os.path.join(ROOT, "paper_2402_12696_amd", "csrc", "k_lb.hip"), "rb").read()
+    csrc = os.path.join(ROOT, "paper_2402_12696_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, n), "rb").read() for n in ("k_lb.hip", "lb_node.h"))
     digest = hashlib.sha256(src).hexdigest()[:16]
     m = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
@@ -408,7 +410,10 @@ def main():
     mlups = nodes / (ms * 1e-3) / 1e6
 
     bulk_ms, bulk_n = kt["lb_bulk"]
-    bulk_nodes = nodes - band if kt["lb_band"][1] > 0 else nodes
+    # with overlap (the library default) the bulk launch updates every node
+    # outside the window (the force pass updates the window's nodes, which
+    # lbrmt_band_nodes reports then); without it, every node
+    bulk_nodes = nodes - band if (kt["lb_band"][1] > 0 or args.overlap != 0) else nodes
     bpn = lb_bytes_per_node(args.precision)
     alg_bytes = bpn * bulk_nodes
     achieved = alg_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None
