@@ -95,11 +95,14 @@ typedef struct {
  * fraction where it exceeds one, Eq. (3_6_global_stress)), the contact stress
  * of every overlapping pair (Eqs. (3_6_collision_stress) to (3_6_normal), on
  * half-edges), and the density rho_f + sum_i lambda_i (rho_s,i - rho_f) /
- * max(1, sum_i lambda_i).  A solid whose zone comes closer than `layers`
- * nodes to its window's border raises LBRMT_H_WINDOW_CLIP (the window does
- * not move; results are wrong from then on, and lbrmt_diag returns
- * EUNSTABLE).  Not available with several solids: the tile-shape options,
- * the autotuners and the adjoint. */
+ * max(1, sum_i lambda_i).  A body_window window follows its solid: after a
+ * step whose zone (the solid's box dilated by `layers`) comes within 4 nodes
+ * of the window's border, the window moves so that the box is centred (the
+ * maps move with it; no value changes).  A zone that would cross the seam of
+ * a whole-axis window (which cannot move) raises LBRMT_H_WINDOW_CLIP:
+ * results are wrong from then on, and lbrmt_diag returns EUNSTABLE.  Not
+ * available with several solids: the tile-shape options, the autotuners and
+ * the adjoint. */
 
 /* One solid (Sec. 3.6 "mat_const"/"object"): a disc (shape 0) of radius a, or
  * an ellipse (shape 1) of semi-axes a and b whose a axis makes the angle theta
@@ -370,12 +373,17 @@ int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);
 int lbrmt_band_nodes(lbrmt_ctx* ctx, int64_t* band_nodes, int64_t* window_nodes);
 
 /* ---------------------------------------------------------------- autotuner
- * Times every lattice tile shape (LBRMT_OPT_LB_VARIANT values) on the current
- * state, reps launches each, and selects the fastest (results do not depend
- * on the shape).  The timed launches read the state's lattice and write the
- * other lattice, which the next step overwrites, so the state is unchanged.
- * best_variant / best_ms (nullable): the choice and its time per launch.
- * Synchronises the stream.  ESTATE before init or on a batch member. */
+ * Times every lattice tile shape (LBRMT_OPT_LB_VARIANT values: tile width
+ * 32-512 x height 1-8 threads, i.e. 1-8 waves per workgroup, 1, 2 or 4 nodes
+ * per thread, nontemporal stores or not) on the current state, reps launches
+ * each, and selects the fastest (results do not depend on the shape).  The
+ * timed launches read the state's lattice and write the other lattice, which
+ * the next step overwrites, so the state is unchanged.  The choice is
+ * remembered for the process per (nx, ny, precision): contexts created later
+ * with the same grid start with it (lbrmt_batch_autotune: per member count,
+ * total nodes and precision, for batches).  best_variant / best_ms
+ * (nullable): the choice and its time per launch.  Synchronises the stream.
+ * ESTATE before init or on a batch member. */
 int lbrmt_autotune(lbrmt_ctx* ctx, int32_t reps, int32_t* best_variant, double* best_ms);
 
 /* Chooses LBRMT_OPT_FUSED_FIT between the one-launch extrapolation (1024) and

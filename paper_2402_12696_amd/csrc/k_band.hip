@@ -2266,17 +2266,121 @@ hipError_t launch_mb_read_stress(const GridP& lg, int precision, const MbBody* b
     return hipGetLastError();
 }
 
-// the region boxes of the solids from a saved copy of the solid table (every
-// other field of a table entry is fixed by the context)
-__global__ void k_mb_copy_reg(const MbBody* __restrict__ src, MbBody* dst, int nb)
+// a solid's window origin in its table entries
+__device__ void mb_set_origin(MbBody& B, const MbTabs& tabs, int k, int ox, int oy)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nb) dst[k].reg = src[k].reg;
+    B.g.ox = ox;
+    B.g.oy = oy;
+    for (int p = 0; p < 7; p++) {
+        tabs.adv[p][k].g.ox = ox;
+        tabs.adv[p][k].g.oy = oy;
+        tabs.lay[p][k].g.ox = ox;
+        tabs.lay[p][k].g.oy = oy;
+        tabs.fit[p][k].g.ox = ox;
+        tabs.fit[p][k].g.oy = oy;
+        tabs.edg[p][k].g.ox = ox;
+        tabs.edg[p][k].g.oy = oy;
+    }
 }
 
-hipError_t launch_mb_copy_reg(const MbBody* src, MbBody* dst, int nb, hipStream_t st)
+// the region boxes and window origins of the solids from a saved copy of the
+// solid table (every other field of a table entry is fixed by the context)
+__global__ void k_mb_copy_reg(const MbBody* __restrict__ src, MbBody* dst, int nb, MbTabs tabs)
 {
-    k_mb_copy_reg<<<(nb + 255) / 256, 256, 0, st>>>(src, dst, nb);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nb) {
+        dst[k].reg = src[k].reg;
+        mb_set_origin(dst[k], tabs, k, src[k].g.ox, src[k].g.oy);
+    }
+}
+
+hipError_t launch_mb_copy_reg(const MbBody* src, MbBody* dst, int nb, const MbTabs& tabs,
+                              hipStream_t st)
+{
+    k_mb_copy_reg<<<(nb + 255) / 256, 256, 0, st>>>(src, dst, nb, tabs);
+    return hipGetLastError();
+}
+
+// the shift of one sub-window axis: 0 while the zone [lo - L, hi + L] keeps
+// MB_RECENTRE_MARGIN nodes from both ends of [0, n), else the move that puts
+// the box's middle at the window's middle
+__device__ __forceinline__ int recentre_shift(int lo, int hi, int L, int n)
+{
+    if (lo - L >= MB_RECENTRE_MARGIN && hi + L <= n - 1 - MB_RECENTRE_MARGIN) return 0;
+    const int mid2 = lo + hi;  // twice the box's middle
+    return (mid2 - (n - 1)) / 2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mb_recentre(MbBody* bodies, MbTabs tabs, int buf,
+                                                     int wa, int wb)
+{
+    const int k = blockIdx.x;
+    MbBody& B = bodies[k];
+    __shared__ int s_dx, s_dy;
+    if (threadIdx.x == 0) {
+        const GridP& g = B.g;
+        const Win a = B.win[wa], b = B.win[wb];
+        const bool av = a.i0 <= a.i1 && a.j0 <= a.j1, bv = b.i0 <= b.i1 && b.j0 <= b.j1;
+        int dx = 0, dy = 0;
+        if (av || bv) {
+            const int i0 = min(av ? a.i0 : b.i0, bv ? b.i0 : a.i0);
+            const int i1 = max(av ? a.i1 : b.i1, bv ? b.i1 : a.i1);
+            const int j0 = min(av ? a.j0 : b.j0, bv ? b.j0 : a.j0);
+            const int j1 = max(av ? a.j1 : b.j1, bv ? b.j1 : a.j1);
+            if (g.wx) dx = recentre_shift(i0, i1, g.layers, g.nx);
+            if (g.wy) dy = recentre_shift(j0, j1, g.layers, g.ny);
+        }
+        s_dx = dx;
+        s_dy = dy;
+    }
+    __syncthreads();
+    const int dx = s_dx, dy = s_dy;
+    if (dx == 0 && dy == 0) return;
+    const GridP& g = B.g;
+    T* X = (T*)B.X[buf];
+    T* Y = (T*)B.Y[buf];
+    T* P = (T*)B.phi[buf];
+    T* tX = (T*)B.X[1 - buf];
+    T* tY = (T*)B.Y[1 - buf];
+    T* tP = (T*)B.phi[1 - buf];
+    // padded window (-PAD .. n + PAD - 1 on each axis, row pitch pp): node
+    // (i, j) of the moved window is node (i + dx, j + dy) of the old one
+    const int wpx = g.nx + 2 * PAD, wpy = g.ny + 2 * PAD;
+    const long long N = (long long)g.pp * wpy;
+    for (long long e = threadIdx.x; e < N; e += blockDim.x) {
+        const int pi = (int)(e % g.pp), pj = (int)(e / g.pp);
+        const int si = pi + dx, sj = pj + dy;
+        const bool in = pi < wpx && si >= 0 && si < wpx && sj >= 0 && sj < wpy;
+        const long long q = in ? (long long)sj * g.pp + si : 0;
+        tX[e] = in ? X[q] : T(0);
+        tY[e] = in ? Y[q] : T(0);
+        tP[e] = in ? P[q] : T(INFINITY);
+    }
+    __syncthreads();
+    for (long long e = threadIdx.x; e < N; e += blockDim.x) {
+        X[e] = tX[e];
+        Y[e] = tY[e];
+        P[e] = tP[e];
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; q++) {
+            Win& w = B.win[q];
+            if (w.i0 > w.i1 || w.j0 > w.j1) continue;
+            w.i0 -= dx;
+            w.i1 -= dx;
+            w.j0 -= dy;
+            w.j1 -= dy;
+        }
+        mb_set_origin(B, tabs, k, g.ox + dx, g.oy + dy);
+    }
+}
+
+hipError_t launch_mb_recentre(int precision, MbBody* bodies, int nb, const MbTabs& tabs, int buf,
+                              int wa, int wb, hipStream_t st)
+{
+    if (precision == 0) k_mb_recentre<double><<<nb, 256, 0, st>>>(bodies, tabs, buf, wa, wb);
+    else k_mb_recentre<float><<<nb, 256, 0, st>>>(bodies, tabs, buf, wa, wb);
     return hipGetLastError();
 }
 

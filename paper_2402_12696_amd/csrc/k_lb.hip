@@ -208,8 +208,10 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb_mb(
     (void)TH;
 }
 
-// Tile shapes of the lattice Boltzmann update (one thread per node); the
-// variant is chosen per context (lbrmt_set_option) by measurement.
+// Tile shapes of the lattice Boltzmann update: tx x ty threads (tx * ty / 64
+// waves per workgroup), r nodes per thread (rows ty apart), nontemporal
+// stores or not; the variant is chosen per context (lbrmt_set_option) by
+// measurement (lbrmt_autotune).
 struct LbVariant {
     int tx, ty, r;
     bool nt;
@@ -218,7 +220,11 @@ constexpr LbVariant LB_VARIANTS[] = {
     {64, 4, 1, false}, {128, 2, 1, false}, {256, 1, 1, false}, {64, 4, 1, true},
     {128, 2, 1, true}, {256, 1, 1, true},  {32, 8, 1, false},  {64, 2, 1, false},
     {256, 1, 2, true}, {256, 1, 4, true},  {512, 1, 1, true},  {512, 1, 2, true},
-    {128, 2, 2, true}, {256, 1, 2, false}};
+    {128, 2, 2, true}, {256, 1, 2, false},
+    // eight waves per workgroup, one or two waves, and eight waves with two
+    // nodes per thread
+    {64, 8, 1, true},  {128, 4, 1, true},  {256, 2, 1, true},  {128, 1, 1, true},
+    {64, 1, 1, true},  {128, 4, 2, true}};
 constexpr int N_LB_VARIANTS = sizeof(LB_VARIANTS) / sizeof(LB_VARIANTS[0]);
 
 int lb_variant_count() { return N_LB_VARIANTS; }
@@ -268,6 +274,12 @@ static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, con
     case 11: LBV(512, 1, 2, true); break;
     case 12: LBV(128, 2, 2, true); break;
     case 13: LBV(256, 1, 2, false); break;
+    case 14: LBV(64, 8, 1, true); break;
+    case 15: LBV(128, 4, 1, true); break;
+    case 16: LBV(256, 2, 1, true); break;
+    case 17: LBV(128, 1, 1, true); break;
+    case 18: LBV(64, 1, 1, true); break;
+    case 19: LBV(128, 4, 2, true); break;
     default: LBV(64, 4, 1, false); break;
     }
 #undef LBV
@@ -317,6 +329,12 @@ static void lb_batch_variant(int v, const LbArgs* args, const int* tile_sim, int
     case 11: LBB(512, 1, 2, true); break;
     case 12: LBB(128, 2, 2, true); break;
     case 13: LBB(256, 1, 2, false); break;
+    case 14: LBB(64, 8, 1, true); break;
+    case 15: LBB(128, 4, 1, true); break;
+    case 16: LBB(256, 2, 1, true); break;
+    case 17: LBB(128, 1, 1, true); break;
+    case 18: LBB(64, 1, 1, true); break;
+    case 19: LBB(128, 4, 2, true); break;
     default: LBB(64, 4, 1, false); break;
     }
 #undef LBB

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -322,8 +323,22 @@ static int collect_timing(lbrmt_ctx* c)
 static double fpo_x(const lbrmt_ctx* c, long long n) { return n == 0 ? 0.0 : c->d.fext_x; }
 static double fpo_y(const lbrmt_ctx* c, long long n) { return n == 0 ? 0.0 : c->d.fext_y; }
 
+// the per-phase argument tables of the several-solid chain
+static MbTabs mb_tabs(const lbrmt_ctx* c)
+{
+    MbTabs t{};
+    for (int p = 0; p < 7; p++) {
+        t.adv[p] = c->mtab[p].adv;
+        t.lay[p] = c->mtab[p].lay;
+        t.fit[p] = c->mtab[p].fit;
+        t.edg[p] = c->mtab[p].edg;
+    }
+    return t;
+}
+
 // several solids, step n on stream st: the chain of every solid (relabel
-// only), the force blocks and the combined forces, the lattice update
+// only), the force blocks and the combined forces, the sub-windows that need
+// to follow their solids, the lattice update
 static int enqueue_step_mb(lbrmt_ctx* c, long long n, hipStream_t st)
 {
     const StepSlots s = slots_for(n);
@@ -340,6 +355,11 @@ static int enqueue_step_mb(lbrmt_ctx* c, long long n, hipStream_t st)
                                     &c->mcount[s.cur], &c->mcount[s.nxt], c->L.nbx,
                                     c->Fx[s.cur], c->Fy[s.cur], c->drho, false, c->bb.health,
                                     st));
+        // the maps of step n + 1 are in buffer s.nxt, their boxes in slots
+        // s.wcur (validity) and s.wnext (solid set)
+        if (c->mg.wx || c->mg.wy)
+            HIPCHK(c, launch_mb_recentre(prec, c->mbd, nb, mb_tabs(c), s.nxt, s.wcur, s.wnext,
+                                         st));
     }
     HIPCHK(c, launch_lb_mb(c->g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt],
                            c->Fx[s.nxt], c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho,
@@ -550,6 +570,26 @@ int lbrmt_workspace_bytes(const lbrmt_grid_desc* d, int32_t max_solids, size_t* 
     return LBRMT_OK;
 }
 
+// Lattice tile variants chosen by lbrmt_autotune / lbrmt_batch_autotune,
+// remembered for the process: per (nx, ny, precision) for a context, per
+// (member count, node total, precision) for a batch.  Contexts and batches
+// created later with the same key start with the remembered variant.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, long long, long long, int>, int> g_tuned;
+
+static int tuned_variant(int kind, long long a, long long b, int precision, int fallback)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(kind, a, b, precision));
+    return it == g_tuned.end() ? fallback : it->second;
+}
+
+static void remember_variant(int kind, long long a, long long b, int precision, int v)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(kind, a, b, precision)] = v;
+}
+
 static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t bytes,
                        void* stream, lbrmt_ctx** out, bool member)
 {
@@ -560,8 +600,10 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
     if (bytes < L.total) return LBRMT_EWORKSPACE;
     lbrmt_ctx* c = new lbrmt_ctx();
     c->d = *d;
-    // measured fastest tile shapes: 64 x 4 (FP64), 256 x 1 (FP32), nontemporal stores
+    // measured fastest tile shapes: 64 x 4 (FP64), 256 x 1 (FP32), nontemporal
+    // stores; or the variant an earlier lbrmt_autotune chose for this shape
     c->lb_variant = d->precision == LBRMT_FP64 ? 3 : 5;
+    if (!member) c->lb_variant = tuned_variant(0, d->nx, d->ny, d->precision, c->lb_variant);
     c->L = L;
     c->max_solids = max_solids;
     c->st = (hipStream_t)stream;
@@ -1439,9 +1481,9 @@ struct StateHeader {
 // Blob layout.  One solid: header, lattice, F^{n-1}, xi, phi, window ring and
 // health.  Several solids (off[4..7] differ): the two force-block stamp
 // arrays with the block-list counters and the device step counter, the
-// solid table (only its region boxes are restored: the rest is fixed by the
-// context), and every solid's block (its maps of both steps, tags, lists and
-// window ring), then the health counters.
+// solid table (only its region boxes and window origins are restored: the
+// rest is fixed by the context), and every solid's block (its maps of both
+// steps, tags, lists and window ring), then the health counters.
 static size_t state_layout(const lbrmt_ctx* c, size_t off[8])
 {
     size_t o = 0;
@@ -1484,7 +1526,8 @@ static int state_copy_mb(lbrmt_ctx* c, char* b, const size_t off[8], bool load)
     HIPCHK(c, cp(c->mcount, off[5], 2 * 4));
     HIPCHK(c, cp(c->dstep, off[5] + 8, 8));
     if (load) {
-        HIPCHK(c, launch_mb_copy_reg((const MbBody*)(b + off[6]), c->mbd, c->nsolid, c->st));
+        HIPCHK(c, launch_mb_copy_reg((const MbBody*)(b + off[6]), c->mbd, c->nsolid, mb_tabs(c),
+                                     c->st));
     } else {
         HIPCHK(c, hipMemcpyAsync(b + off[6], c->mbd, (size_t)c->nsolid * sizeof(MbBody), D2D,
                                  c->st));
@@ -1791,6 +1834,7 @@ int lbrmt_autotune(lbrmt_ctx* c, int32_t reps, int32_t* best_variant, double* be
     (void)hipEventDestroy(b);
     int rc = lbrmt_set_option(c, LBRMT_OPT_LB_VARIANT, best);
     if (rc != LBRMT_OK) return rc;
+    remember_variant(0, c->d.nx, c->d.ny, c->d.precision, best);
     if (best_variant) *best_variant = best;
     if (best_ms) *best_ms = best_t / reps;
     return LBRMT_OK;
@@ -1868,6 +1912,7 @@ struct lbrmt_batch {
     size_t tile_cap = 0;
     int total_tiles = 0;
     int lb_variant = 3;
+    long long nodes = 0;  // interior nodes of all members (the autotune key)
     bool graph = true;
     int fused_fit = 0;  // 1024: one extrapolation launch if every member can; 0 (-1): per layer
     hipGraphExec_t gexec = nullptr;
@@ -2082,6 +2127,8 @@ int lbrmt_batch_create(const lbrmt_grid_desc* descs, const lbrmt_solid_desc* sol
     b->precision = descs[0].precision;
     b->layers = descs[0].layers;
     b->lb_variant = b->precision == LBRMT_FP64 ? 3 : 5;
+    for (int k = 0; k < n; k++) b->nodes += (long long)descs[k].nx * descs[k].ny;
+    b->lb_variant = tuned_variant(1, n, b->nodes, b->precision, b->lb_variant);
     b->st = (hipStream_t)stream;
     b->ws = (char*)ws;
     size_t o = B.tables;
@@ -2251,6 +2298,7 @@ int lbrmt_batch_autotune(lbrmt_batch* b, int32_t reps, int32_t* best_variant, do
     (void)keep;
     int rc = lbrmt_batch_set_option(b, LBRMT_OPT_LB_VARIANT, best);
     if (rc != LBRMT_OK) return rc;
+    remember_variant(1, b->n, b->nodes, b->precision, best);
     if (best_variant) *best_variant = best;
     if (best_ms) *best_ms = best_t / reps;
     return LBRMT_OK;

@@ -42,6 +42,8 @@ constexpr int MB_BAND_BLOCKS = 16;    // relabel: two partial boxes per block
 constexpr int MB_FIT_THREADS = 1024;  // one block per solid runs all its layers
 constexpr int MB_MAX_PER_BLOCK = 32;  // solids overlapping one force block
 constexpr int MB_COMBINE_BLOCKS = 2048;
+// a sub-window moves when its solid's zone comes this close to its border
+constexpr int MB_RECENTRE_MARGIN = 4;
 
 // Axis-aligned box of the interior solid nodes of one body (i0 > i1: empty).
 // The working window of a step is this box dilated by `layers` nodes.
@@ -562,8 +564,26 @@ hipError_t launch_mb_combine(const GridP& lg, int precision, const MbBody* bodie
 hipError_t launch_mb_read_stress(const GridP& lg, int precision, const MbBody* bodies, int nb,
                                  int buf, int wslot, int nbx, int nby, double* sxx, double* sxy,
                                  double* syy, unsigned* health, hipStream_t st);
-// the region boxes of the solid table dst from a saved copy src (device)
-hipError_t launch_mb_copy_reg(const MbBody* src, MbBody* dst, int nb, hipStream_t st);
+// the chain's per-phase argument tables of a several-solid context (each
+// entry holds a copy of its solid's window geometry)
+struct MbTabs {
+    AdvectArgs* adv[7];
+    LayersArgs* lay[7];
+    FitArgs* fit[7];
+    EdgesArgs* edg[7];
+};
+// the region boxes and window origins of the solid table dst (and of the
+// argument tables) from a saved copy src (device)
+hipError_t launch_mb_copy_reg(const MbBody* src, MbBody* dst, int nb, const MbTabs& tabs,
+                              hipStream_t st);
+// moves the sub-window of every solid whose zone (its boxes in ring slots wa
+// and wb, dilated by the layers) comes within MB_RECENTRE_MARGIN nodes of the
+// window's border, so that the boxes are centred: the maps of buffer buf
+// move within the window (through the other buffer, free between steps),
+// the ring boxes shift, and the origin changes in the solid table and the
+// argument tables; every node keeps its lattice position and value
+hipError_t launch_mb_recentre(int precision, MbBody* bodies, int nb, const MbTabs& tabs, int buf,
+                              int wa, int wb, hipStream_t st);
 hipError_t launch_mb_read_refmap(const GridP& lg, int precision, const MbBody* bodies, int k,
                                  int buf, int wvalid, double* X, double* Y, double* phi,
                                  hipStream_t st);

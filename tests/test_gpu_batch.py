@@ -90,6 +90,15 @@ def test_autotuners_keep_state_and_results():
         single = Sim(device="cuda:0", **c).init().step(40)
         _same(_fields(batch.member(k)), _fields(single), f"batch autotune member {k}")
         single.close()
+    # the choices are remembered per grid (per batch shape) and precision
+    again = Sim(device="cuda:0", **cfg)
+    assert again.get_option(1) == a.get_option(1)
+    other = Sim(device="cuda:0", **dict(cfg, nx=72, ny=64))
+    assert other.get_option(1) == 3   # FP64 default: 64 x 4, nontemporal
+    batch2 = Batch(cfgs)
+    assert batch2.get_option(1) == batch.get_option(1)
+    for s in (again, other, batch2):
+        s.close()
     batch.close()
 
 

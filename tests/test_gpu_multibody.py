@@ -273,3 +273,48 @@ def test_checkpoint_resume_is_bitwise_with_several_solids():
         d.load_state(blob)
     for s in (a, b, c, d):
         s.close()
+
+
+def _drifting():
+    # periodic both ways with 64-node sub-windows; a stream carries the solids
+    # 30 and 18 nodes in 600 steps, farther than their windows' margins, so
+    # each window has to follow its solid (several moves per solid)
+    return workloads.make(nx=128, ny=128, tau=0.8, periodic_x=True, periodic_y=True,
+                          gravity=(0.0, -1e-5), body_window=64,
+                          solids=[dict(cx=40.0, cy=50.0, R=8.0, G=0.01, rho_s=1.2),
+                                  dict(cx=90.0, cy=80.0, R=9.0, G=0.015, rho_s=1.0,
+                                       shape="ellipse", b=6.0, theta=0.4)])
+
+
+def _drift_u0(n=128):
+    rng = np.random.default_rng(3)
+    return workloads.uniform_velocity(n, n, 0.05, 0.03) + rng.normal(0.0, 5e-4, size=(2, n, n))
+
+
+def test_windows_follow_drifting_solids_and_match_oracle():
+    # without the moves the zones would leave their windows (window_clip);
+    # with them every node keeps its lattice position and value
+    _run(_drifting(), (1, 150, 300, 600), "f64", 1e-10, u0=_drift_u0())
+
+
+def test_moved_windows_survive_checkpoints_and_graph_replay():
+    cfg, u0 = _drifting(), _drift_u0()
+
+    def fields(s):
+        return _np(s.macro()) + sum((_np(s.refmap(k)) for k in range(2)), [])
+
+    a = _sim(cfg, u0=u0).step(400)
+    blob = a.save_state()
+    a.step(200)
+    b = _sim(cfg)
+    b.load_state(blob)
+    b.step(200)
+    e = _sim(cfg, u0=u0)
+    e.set_option(3, 0)  # eager launches
+    e.step(600)
+    for s in (b, e):
+        for x, y in zip(fields(a), fields(s)):
+            assert np.array_equal(np.nan_to_num(x, nan=-9.0), np.nan_to_num(y, nan=-9.0))
+        assert all(v == 0 for v in s.diag()["health"].values())
+    for s in (a, b, e):
+        s.close()
