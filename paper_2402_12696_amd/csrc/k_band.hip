@@ -461,7 +461,8 @@ constexpr int DRW = DTX + 2 * MAX_LAYERS, DRH = DTY + 2 * MAX_LAYERS;
 // phi^n < 0, inside the previous window} is read from the level set, the
 // tile's solid nodes are tagged and advected (Sec. 3.1) in the same pass, and
 // the tags of the window are all written here.
-template <int LC, bool ADV, typename S, bool PRE = false, bool LATCHK = false>
+template <int LC, bool ADV, typename S, bool PRE = false, bool LATCHK = false,
+          bool SPLIT = false>
 __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ win, int wslot,
                                              int wprev, int8_t* tag, int* lists, int* lcount,
                                              unsigned* health, const S* __restrict__ A,
@@ -486,7 +487,34 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
     const int ntx = (w + DTX - 1) / DTX, nty = (h + DTY - 1) / DTY;
     const int rw = DTX + 2 * L, rh = DTY + 2 * L;  // region in use
     const int lane = __lane_id();
-    for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
+    // SPLIT (one solid): when the grid has at least ADV_MIN_WORKERS blocks
+    // beyond the tiles, block t < ntile takes tile t without its advection,
+    // and the blocks beyond advect the solid nodes of the window, 256 nodes
+    // of it (row-major over its interior part) at a time, one per thread:
+    // interior tiles no longer advect 512 nodes each while boundary tiles
+    // idle.  The solid set is the same (interior, phi^n < 0, inside D), and
+    // each node's advection is the same arithmetic, so the bits are too.
+    const int ntile = ntx * nty;
+    bool adv_here = ADV;
+    if (SPLIT && ADV && (int)gridDim.x - ntile >= ADV_MIN_WORKERS) {
+        adv_here = false;
+        if ((int)blockIdx.x >= ntile) {
+            const int i0 = max(W.i0, 0), i1 = min(W.i1, g.nx - 1);
+            const int j0 = max(W.j0, 0), j1 = min(W.j1, g.ny - 1);
+            if (i0 > i1 || j0 > j1) return;
+            const int ww = i1 - i0 + 1;
+            const long long nn = (long long)ww * (j1 - j0 + 1);
+            const int nwork = gridDim.x - ntile;
+            for (long long e = (long long)(blockIdx.x - ntile) * blockDim.x + threadIdx.x; e < nn;
+                 e += (long long)nwork * blockDim.x) {
+                const int x = i0 + (int)(e % ww), y = j0 + (int)(e / ww);
+                if (D.has(x, y) && phi[pidx(g, x, y)] < S(0))
+                    advect_node<S, LATCHK>(g, A, fpx, fpy, X, Y, phi, X1, Y1, D, x, y, health);
+            }
+            return;
+        }
+    }
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
         const int x0 = W.i0 + (t % ntx) * DTX, y0 = W.j0 + (t / ntx) * DTY;
         if (threadIdx.x <= MAX_LAYERS) cnt[threadIdx.x] = 0;
         // solid flags of the region (nodes outside the window hold none).
@@ -599,7 +627,7 @@ __device__ __forceinline__ void dt_tile_body(GridP g, const Win* __restrict__ wi
                 else atomicAdd(&health[7], 1u);  // beyond the sub-list capacity
             }
         }
-        if (ADV) {
+        if (adv_here) {
             // advection of the tile's solid nodes
             for (int e = threadIdx.x; e < DTX * DTY; e += blockDim.x) {
                 const int cx = e % DTX, cy = e / DTX;
@@ -635,8 +663,9 @@ __global__ __launch_bounds__(256) void k_advect_dt(GridP g, const S* __restrict_
                                                    unsigned* health, int* ff_flag, int* ff_list,
                                                    int* ff_n)
 {
-    dt_tile_body<LC, true, S, true, true>(g, win, wcur, wprev, tag, lists, lcount, health, A,
-                                          fpx, fpy, X, Y, phi, X1, Y1, ff_flag, ff_list, ff_n);
+    dt_tile_body<LC, true, S, true, true, true>(g, win, wcur, wprev, tag, lists, lcount, health,
+                                                A, fpx, fpy, X, Y, phi, X1, Y1, ff_flag, ff_list,
+                                                ff_n);
 }
 
 template <int LC, typename S>

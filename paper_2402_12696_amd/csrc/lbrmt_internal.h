@@ -21,6 +21,7 @@ constexpr int MAX_LAYERS = 31;
 constexpr int BOX_BLOCKS = 512;       // initial solid box
 constexpr int RELABEL_BLOCKS = 2048;  // relabel: one partial box per block
 constexpr int DT_BLOCKS = 2048;       // distance transform
+constexpr int ADV_MIN_WORKERS = 256;  // advection blocks beside the distance transform (one solid)
 constexpr int FIT_BLOCKS = 256;       // one extrapolation layer
 constexpr int FIT_LANES = 8;          // lanes sharing one extrapolation target
 constexpr int LCOUNT_PAD = 32;        // layer counters 128 B apart
