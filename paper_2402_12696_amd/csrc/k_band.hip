@@ -1119,17 +1119,24 @@ __global__ __launch_bounds__(1024) void kb_fit_layers(const FitArgs* __restrict_
 // scan windows up to r_max, the per-layer path's fit), then clears that list
 // and the list of zone tiles.  With no tile stopped it only clears the lists.
 template <typename T, int NT>
-__device__ void fit_rest(const GridP& g, const Rect& W, const Rect& D, int8_t* tag,
-                         const int* __restrict__ lists, const int* __restrict__ lcount,
-                         const T* __restrict__ phin, T* X1, T* Y1, unsigned* health,
-                         int8_t* cut_layer, const int* cut_tiles, int* ncut, int* ff_flag,
-                         const int* ff_list, int* ff_n)
+__device__ void fit_rest(const GridP& g, const Win* __restrict__ win, int wcur, int wprev,
+                         int8_t* tag, const int* __restrict__ lists,
+                         const int* __restrict__ lcount, const T* __restrict__ phin, T* X1,
+                         T* Y1, unsigned* health, int8_t* cut_layer, const int* cut_tiles,
+                         int* ncut, int* ff_flag, const int* ff_list, int* ff_n)
 {
     constexpr int NG = NT / FIT_LANES;
+    // this thread's first list entry is loaded together with the two counters
+    // (the list holds one entry per fused-extrapolation tile of the grid, at
+    // least one); the windows are read only when a tile was stopped
+    const int a0 = threadIdx.x;
+    const int e0 = ff_list[min((long long)a0, fused_tiles(g.nx, g.ny) - 1)];
     const int nt = *ff_n, nc = *ncut;
     const long long cap = g.lcap;
     const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
     if (nc > 0) {
+        const Rect W = window_of(win, wcur, g);
+        const Rect D = window_of(win, wprev, g);
         const int ntx = (W.i1 - W.i0 + FF_TILE) / FF_TILE;
         for (int l = 1; l <= g.layers; l++) {
             for (int s = 0; s < NSUB; s++) {
@@ -1159,7 +1166,7 @@ __device__ void fit_rest(const GridP& g, const Rect& W, const Rect& D, int8_t* t
         }
     }
     // the lists of the next step start empty
-    for (int a = threadIdx.x; a < nt; a += NT) ff_flag[ff_list[a]] = 0;
+    for (int a = threadIdx.x; a < nt; a += NT) ff_flag[a == a0 ? e0 : ff_list[a]] = 0;
     for (int a = threadIdx.x; a < nc; a += NT) cut_layer[cut_tiles[a]] = FF_NO_CUT;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1421,9 +1428,8 @@ template <typename T>
 __global__ __launch_bounds__(FF_REST_THREADS) void kb_fit_rest(const FitArgs* __restrict__ args)
 {
     const FitArgs& a = args[blockIdx.y];
-    const Rect W = window_of(a.win, a.wcur, a.g);
-    const Rect D = window_of(a.win, a.wprev, a.g);
-    fit_rest<T, FF_REST_THREADS>(a.g, W, D, a.tag, a.lists, a.lcount, (const T*)a.phin,
+    fit_rest<T, FF_REST_THREADS>(a.g, a.win, a.wcur, a.wprev, a.tag, a.lists, a.lcount,
+                                 (const T*)a.phin,
                                  (T*)a.X1, (T*)a.Y1, a.health, a.cut_layer, a.cut_tiles, a.ncut,
                                  a.ff_flag, a.ff_list, a.ff_n);
 }
@@ -1437,10 +1443,8 @@ __global__ __launch_bounds__(FF_REST_THREADS) void k_fit_rest(
     T* X1, T* Y1, unsigned* health, int8_t* cut_layer, const int* cut_tiles, int* ncut,
     int* ff_flag, const int* ff_list, int* ff_n)
 {
-    const Rect W = window_of(win, wcur, g);
-    const Rect D = window_of(win, wprev, g);
-    fit_rest<T, FF_REST_THREADS>(g, W, D, tag, lists, lcount, phin, X1, Y1, health, cut_layer,
-                                 cut_tiles, ncut, ff_flag, ff_list, ff_n);
+    fit_rest<T, FF_REST_THREADS>(g, win, wcur, wprev, tag, lists, lcount, phin, X1, Y1, health,
+                                 cut_layer, cut_tiles, ncut, ff_flag, ff_list, ff_n);
 }
 
 hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
@@ -1835,8 +1839,8 @@ __global__ __launch_bounds__(256) void k_reduce_window(GridP g, const int* __res
                                                        int nbox, Win* win, int wnext,
                                                        unsigned* health)
 {
-    reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
-    if (threadIdx.x == 0) check_zone(g, win[wnext], health);
+    const Win r = reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
+    if (threadIdx.x == 0) check_zone(g, r, health);
 }
 
 hipError_t launch_reduce_window(const GridP& g, const BandBufs& bb, int wnext, hipStream_t st)

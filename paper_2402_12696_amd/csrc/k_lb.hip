@@ -116,8 +116,8 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     unsigned* __restrict__ health, const int* __restrict__ boxpart, int nbox, int wnext)
 {
     if ((PART == 0 || PART == 2) && nbox > 0 && blockIdx.x == 0) {
-        reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
-        if (threadIdx.x == 0) check_zone(g, win[wnext], health);
+        const Win r = reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
+        if (threadIdx.x == 0) check_zone(g, r, health);
     }
     constexpr int TH = LB_TY * R;
     const int ntx = (g.nx + LB_TX - 1) / LB_TX;
@@ -179,8 +179,8 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void kb_lb(const LbArgs* __restrict__
     const int local = t - a.tile_base;
     // the member's first tile reduces the force pass's partial boxes
     if (local == 0 && a.nbox > 0) {
-        reduce_boxes(a.boxpart, a.nbox, &a.winw[a.wnext], nullptr);
-        if (threadIdx.x == 0) check_zone(a.g, a.winw[a.wnext], a.health);
+        const Win r = reduce_boxes(a.boxpart, a.nbox, &a.winw[a.wnext], nullptr);
+        if (threadIdx.x == 0) check_zone(a.g, r, a.health);
     }
     const int ntx = (a.g.nx + LB_TX - 1) / LB_TX;
     const Rect wp = window_of(a.win, a.wprev, a.g);

@@ -134,13 +134,15 @@ __device__ __forceinline__ int wave_max(int v)
 }
 
 // Reduces n partial boxes {i0, i1, j0, j1} (one block; every thread calls it)
-// into *dst0 (and *dst1 when not null); an empty result is the empty box.
+// into *dst0 (and *dst1 when not null), and returns it in thread 0; an empty
+// result is the empty box.
 // SAME_KERNEL: the partials were written by other blocks of the running
 // kernel (read through volatile loads after the last-block handshake);
 // otherwise by an earlier kernel (plain loads, all issued at once).
 template <bool SAME_KERNEL = false>
-__device__ inline void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1)
+__device__ inline Win reduce_boxes(const int* part, int n, Win* dst0, Win* dst1)
 {
+    Win r{};
     __shared__ int sb[4][16];
     int a0 = 0x3fffffff, a1 = -0x3fffffff, a2 = 0x3fffffff, a3 = -0x3fffffff;
     if (SAME_KERNEL) {
@@ -152,13 +154,24 @@ __device__ inline void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1
             a3 = max(a3, q[3]);
         }
     } else {
+        // eight partials per thread in flight at a time
+        constexpr int NB = 8;
         const int4* p4 = reinterpret_cast<const int4*>(part);
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            const int4 q = p4[k];
-            a0 = min(a0, q.x);
-            a1 = max(a1, q.y);
-            a2 = min(a2, q.z);
-            a3 = max(a3, q.w);
+        for (int k0 = threadIdx.x; k0 < n; k0 += NB * blockDim.x) {
+            int4 q[NB];
+#pragma unroll
+            for (int u = 0; u < NB; u++) {
+                const int k = k0 + u * blockDim.x;
+                q[u] = p4[k < n ? k : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < NB; u++) {
+                if (k0 + u * (int)blockDim.x >= n) continue;
+                a0 = min(a0, q[u].x);
+                a1 = max(a1, q[u].y);
+                a2 = min(a2, q[u].z);
+                a3 = max(a3, q[u].w);
+            }
         }
     }
     a0 = wave_min(a0);
@@ -181,7 +194,6 @@ __device__ inline void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1
             a2 = min(a2, sb[2][w]);
             a3 = max(a3, sb[3][w]);
         }
-        Win r;
         r.i0 = a0;
         r.i1 = a1;
         r.j0 = a2;
@@ -191,6 +203,7 @@ __device__ inline void reduce_boxes(const int* part, int n, Win* dst0, Win* dst1
         if (dst1) *dst1 = r;
     }
     __syncthreads();
+    return r;  // the box, in thread 0
 }
 
 // A zone (box dilated by `layers`) that would cross a periodic seam of a
@@ -506,7 +519,7 @@ hipError_t launch_layers(const GridP& g, const BandBufs& bb, int wslot, hipStrea
 hipError_t launch_extrapolate(const GridP& g, const BandBufs& bb, const StepSlots& s,
                               hipStream_t st, int fused_threads);
 inline bool fused_fit_ok(const GridP& g) { return !g.px && !g.py && g.layers <= FF_LAYERS; }
-inline long long fused_tiles(int nx, int ny)
+__host__ __device__ inline long long fused_tiles(int nx, int ny)
 {
     return (long long)((nx + 2 * PAD + FF_TILE - 1) / FF_TILE) *
            ((ny + 2 * PAD + FF_TILE - 1) / FF_TILE);
