@@ -1803,6 +1803,9 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
                                                double* o0, double* o1, double* o2, int* lcount,
                                                unsigned* health, LbFuse lf)
 {
+    // beside the bulk lattice update (MODE 3) the force pass is on the
+    // critical path: its waves take the issue slots of a SIMD first
+    if (MODE == 3) __builtin_amdgcn_s_setprio(3);
     edges_body<MODE, C>(g, b, win, wvalid, boxpart, whole_grid, X, Y, phi, tag, phi1, o0, o1,
                         o2, lcount, health, lf);
 }
