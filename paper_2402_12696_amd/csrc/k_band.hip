@@ -725,14 +725,24 @@ __device__ __forceinline__ double det3(double a00, double a01, double a02, doubl
 // the target.  The normal matrix and its well-posedness test are kept in
 // double (sums of w dx dy with w a power of two, or the normal weight of the
 // first two layers); the right-hand sides are accumulated in the storage
-// precision C of the reference map.
-template <typename C>
+// precision C of the reference map.  MT = float is exact where the weights
+// are the powers of two alone and r <= FIT_EXACT_R: every term w a b (w =
+// 2^-(|a|+|b|) >= 2^-16, |a|, |b| <= 8) is a multiple of 2^-16, and every
+// partial sum of them stays below 2^6 in magnitude, so 22 bits hold it: the
+// float sums equal the double ones bit for bit, at half the cost.
+constexpr int FIT_EXACT_R = 8;
+// layers from 3 on weigh by powers of two alone: their sums can run in float
+__host__ __device__ __forceinline__ bool float_sums(const GridP& g, int l)
+{
+    return l >= 3 && g.r_max <= FIT_EXACT_R;
+}
+template <typename C, typename MT = double>
 struct Fit {
-    double M00, M01, M02, M11, M12, M22;
+    MT M00, M01, M02, M11, M12, M22;
     C bX0, bX1, bX2, bY0, bY1, bY2;
     __device__ __forceinline__ void zero()
     {
-        M00 = M01 = M02 = M11 = M12 = M22 = 0.0;
+        M00 = M01 = M02 = M11 = M12 = M22 = MT(0);
         bX0 = bX1 = bX2 = bY0 = bY1 = bY2 = C(0);
     }
     // one valid node at offset (a, b) from the target, weight of Eq. (3_2_extrap_weight)
@@ -745,13 +755,13 @@ struct Fit {
             const double dn = (ddx * nxh + ddy * nyh) / sqrt(ddx * ddx + ddy * ddy);
             wt = dn * wt > 0.0 ? dn * wt : 0.0;
         }
-        const double dx = a, dy = b;
-        M00 += wt * dx * dx;
-        M01 += wt * dx * dy;
-        M02 += wt * dx;
-        M11 += wt * dy * dy;
-        M12 += wt * dy;
-        M22 += wt;
+        const MT w = MT(wt), dx = MT(a), dy = MT(b);
+        M00 += w * dx * dx;
+        M01 += w * dx * dy;
+        M02 += w * dx;
+        M11 += w * dy * dy;
+        M12 += w * dy;
+        M22 += w;
         const C wc = C(wt), cx = C(a), cy = C(b);
         bX0 += wc * cx * xv;
         bX1 += wc * cy * xv;
@@ -763,16 +773,17 @@ struct Fit {
     // intercept of the weighted linear fit, if well posed
     __device__ __forceinline__ bool solve(double det_rel, C& x, C& y) const
     {
-        const double det = det3(M00, M01, M02, M01, M11, M12, M02, M12, M22);
-        if (!(det > det_rel * M22 * M22 * M22)) return false;
+        const double m00 = M00, m01 = M01, m02 = M02, m11 = M11, m12 = M12, m22 = M22;
+        const double det = det3(m00, m01, m02, m01, m11, m12, m02, m12, m22);
+        if (!(det > det_rel * m22 * m22 * m22)) return false;
         if (sizeof(C) == 8) {
-            x = C(det3(M00, M01, bX0, M01, M11, bX1, M02, M12, bX2) / det);
-            y = C(det3(M00, M01, bY0, M01, M11, bY1, M02, M12, bY2) / det);
+            x = C(det3(m00, m01, bX0, m01, m11, bX1, m02, m12, bX2) / det);
+            y = C(det3(m00, m01, bY0, m01, m11, bY1, m02, m12, bY2) / det);
         } else {
             // Cramer in float: the cofactors of the third column weigh the
             // right-hand sides
-            const C c0 = C(M01 * M12 - M11 * M02), c1 = C(M01 * M02 - M00 * M12);
-            const C c2 = C(M00 * M11 - M01 * M01), id = C(1.0 / det);
+            const C c0 = C(m01 * m12 - m11 * m02), c1 = C(m01 * m02 - m00 * m12);
+            const C c2 = C(m00 * m11 - m01 * m01), id = C(1.0 / det);
             x = (c0 * bX0 + c1 * bX1 + c2 * bX2) * id;
             y = (c0 * bY0 + c1 * bY1 + c2 * bY2) * id;
         }
@@ -833,11 +844,11 @@ __device__ __forceinline__ V group_sum(V v)
 // to this lane: node q goes to lane q mod FIT_LANES; each lane issues the
 // loads of PER nodes before adding them.  The offsets (a, b) of node q are
 // stepped along instead of divided out.
-template <typename T>
+template <typename T, typename MT>
 __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l, int i, int j,
                                            int kt, int r, int sub, bool use_n, double nxh,
                                            double nyh, const int8_t* tag, const T* X1,
-                                           const T* Y1, Fit<T>& f, int& count)
+                                           const T* Y1, Fit<T, MT>& f, int& count)
 {
     constexpr int PER = 4;  // window nodes per lane and pass: 25 of r = 2 in one pass
     const int side = 2 * r + 1, nq = side * side;
@@ -879,8 +890,9 @@ __device__ __forceinline__ void fit_window(const GridP& g, const Rect& W, int l,
 
 // the group's sums reduced across its lanes, then the intercept, if the
 // window held three valid nodes and the fit is well posed
-template <typename T>
-__device__ __forceinline__ bool fit_finish(const GridP& g, Fit<T>& f, int count, T& xo, T& yo)
+template <typename T, typename MT>
+__device__ __forceinline__ bool fit_finish(const GridP& g, Fit<T, MT>& f, int count, T& xo,
+                                           T& yo)
 {
     count = group_sum(count);
     if (count < 3) return false;
@@ -901,26 +913,26 @@ __device__ __forceinline__ bool fit_finish(const GridP& g, Fit<T>& f, int count,
 
 // scan window of half-width r = side / 2: reduced normal equations and the
 // intercept, if the window holds three valid nodes and the fit is well posed
-template <typename T>
+template <typename T, typename MT>
 __device__ __forceinline__ bool fit_at(const GridP& g, const Rect& W, int l, int i, int j, int kt,
                                        int r, int sub, bool use_n, double nxh, double nyh,
                                        const int8_t* tag, const T* X1, const T* Y1, T& xo, T& yo)
 {
-    Fit<T> f;
-    f.zero();
     int count = 0;
-    fit_window<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, f, count);
-    return fit_finish<T>(g, f, count, xo, yo);
+    Fit<T, MT> f;
+    f.zero();
+    fit_window<T, MT>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, f, count);
+    return fit_finish<T, MT>(g, f, count, xo, yo);
 }
 
 // fit_window over the block's staged copy of the zone (tags st, values sx,
 // sy on a row-major region of rw columns; (li, lj) the target's place in it):
 // the same nodes in the same lanes and the same order of additions, so the
 // same bits
-template <typename T>
+template <typename T, typename MT>
 __device__ __forceinline__ void fit_window_lds(int l, int li, int lj, int r, int sub, bool use_n,
                                                double nxh, double nyh, const int8_t* st,
-                                               const T* sx, const T* sy, int rw, Fit<T>& f,
+                                               const T* sx, const T* sy, int rw, Fit<T, MT>& f,
                                                int& count)
 {
     constexpr int PER = 4;
@@ -984,7 +996,7 @@ __device__ __forceinline__ bool target_normal(const GridP& g, const Rect& D, int
     return normal_from(pe, pw, pn, ps, nxh, nyh);
 }
 
-template <typename T>
+template <typename T, typename MT>
 __device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const Rect& D, int l,
                                            int kt, int i, int j, int sub, int rlim,
                                            const int8_t* tag, const T* __restrict__ phin,
@@ -998,7 +1010,7 @@ __device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const 
             cut = true;
             return false;
         }
-        if (fit_at<T>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, xo, yo))
+        if (fit_at<T, MT>(g, W, l, i, j, kt, r, sub, use_n, nxh, nyh, tag, X1, Y1, xo, yo))
             return true;
     }
     return false;
@@ -1008,7 +1020,7 @@ __device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const 
 // zone ((li, lj): the target's place in it)
 // (use_n, nxh, nyh: the normal weight of layers 1 and 2, found by the caller
 // as target_normal finds it)
-template <typename T>
+template <typename T, typename MT>
 __device__ __forceinline__ bool fit_target_lds(const GridP& g, int l, int li, int lj, int sub,
                                                int rlim, const int8_t* st, const T* sx,
                                                const T* sy, int rw, T& xo, T& yo, bool& cut,
@@ -1020,11 +1032,11 @@ __device__ __forceinline__ bool fit_target_lds(const GridP& g, int l, int li, in
             cut = true;
             return false;
         }
-        Fit<T> f;
-        f.zero();
         int count = 0;
-        fit_window_lds<T>(l, li, lj, r, sub, use_n, nxh, nyh, st, sx, sy, rw, f, count);
-        if (fit_finish<T>(g, f, count, xo, yo)) return true;
+        Fit<T, MT> f;
+        f.zero();
+        fit_window_lds<T, MT>(l, li, lj, r, sub, use_n, nxh, nyh, st, sx, sy, rw, f, count);
+        if (fit_finish<T, MT>(g, f, count, xo, yo)) return true;
     }
     return false;
 }
@@ -1036,7 +1048,7 @@ __device__ __forceinline__ bool fit_target_lds(const GridP& g, int l, int li, in
 // come only from earlier layers, so targets of one layer never read each
 // other.  With displacement storage the fit of d = xi - x gives the fit of xi
 // minus x at the target, since the weighted fit reproduces linear fields.
-template <typename T>
+template <typename T, typename MT>
 __device__ __forceinline__ void layer_fit_body(GridP g, const Win* __restrict__ win,
                                                    int wcur, int wprev, int l, int8_t* tag,
                                                    const int* __restrict__ lists,
@@ -1064,8 +1076,8 @@ __device__ __forceinline__ void layer_fit_body(GridP g, const Win* __restrict__ 
         const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
         T xo = T(0), yo = T(0);
         bool cut;
-        const bool done = fit_target<T>(g, W, D, l, kt, i, j, sub, g.r_max, tag, phin, X1, Y1,
-                                        xo, yo, cut);
+        const bool done = fit_target<T, MT>(g, W, D, l, kt, i, j, sub, g.r_max, tag, phin, X1,
+                                            Y1, xo, yo, cut);
         if (sub == 0) {
             if (done) {
                 X1[kt] = xo;
@@ -1086,7 +1098,11 @@ __global__ __launch_bounds__(256) void k_layer_fit(GridP g, const Win* __restric
                                                    const T* __restrict__ phin, T* X1, T* Y1,
                                                    unsigned* health)
 {
-    layer_fit_body<T>(g, win, wcur, wprev, l, tag, lists, lcount, phin, X1, Y1, health);
+    if (float_sums(g, l))
+        layer_fit_body<T, float>(g, win, wcur, wprev, l, tag, lists, lcount, phin, X1, Y1, health);
+    else
+        layer_fit_body<T, double>(g, win, wcur, wprev, l, tag, lists, lcount, phin, X1, Y1,
+                                  health);
 }
 
 template <typename T>
@@ -1094,8 +1110,12 @@ __global__ __launch_bounds__(256) void kb_layer_fit(const FitArgs* __restrict__ 
 {
     const FitArgs& a = args[blockIdx.y];
     if (l > a.g.layers) return;
-    layer_fit_body<T>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
-                      (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+    if (float_sums(a.g, l))
+        layer_fit_body<T, float>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
+                                 (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+    else
+        layer_fit_body<T, double>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
+                                  (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
 }
 
 // Every layer of one solid in one block (several solids: a solid's layers
@@ -1107,8 +1127,12 @@ __global__ __launch_bounds__(1024) void kb_fit_layers(const FitArgs* __restrict_
 {
     const FitArgs& a = args[blockIdx.y];
     for (int l = 1; l <= layers; l++) {
-        layer_fit_body<T>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
-                          (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+        if (float_sums(a.g, l))
+            layer_fit_body<T, float>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
+                                     (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+        else
+            layer_fit_body<T, double>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
+                                      (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
         __syncthreads();
     }
 }
@@ -1149,7 +1173,11 @@ __device__ void fit_rest(const GridP& g, const Win* __restrict__ win, int wcur, 
                     if (cut_layer[t] > l) continue;
                     T xo = T(0), yo = T(0);
                     bool cut;
-                    const bool done = fit_target<T>(g, W, D, l, kt, i, j, sub, g.r_max, tag,
+                    const bool done =
+                        float_sums(g, l)
+                            ? fit_target<T, float>(g, W, D, l, kt, i, j, sub, g.r_max, tag, phin,
+                                                   X1, Y1, xo, yo, cut)
+                            : fit_target<T, double>(g, W, D, l, kt, i, j, sub, g.r_max, tag,
                                                     phin, X1, Y1, xo, yo, cut);
                     if (sub == 0) {
                         if (done) {
@@ -1361,7 +1389,11 @@ __device__ __forceinline__ void fit_fused_body(const GridP& g, const Win* __rest
                 const double nxh = use_n ? s_nx[pos] : 0.0, nyh = use_n ? s_ny[pos] : 0.0;
                 T xo = T(0), yo = T(0);
                 bool cut;
-                const bool done = fit_target_lds<T>(g, l, li, lj, sub, rlim, st, sx, sy, rw, xo,
+                const bool done =
+                    float_sums(g, l)
+                        ? fit_target_lds<T, float>(g, l, li, lj, sub, rlim, st, sx, sy, rw, xo,
+                                                   yo, cut, use_n, nxh, nyh)
+                        : fit_target_lds<T, double>(g, l, li, lj, sub, rlim, st, sx, sy, rw, xo,
                                                     yo, cut, use_n, nxh, nyh);
                 if (sub == 0) {
                     const bool own = i >= x0 && i < x0 + FF_TILE && j >= y0 && j < y0 + FF_TILE;
