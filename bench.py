@@ -10,9 +10,9 @@ Prints ONE JSON line: whole-job MLUPS (interior nodes x steps / s), the roofline
 of the dominant kernel (the lattice Boltzmann update of the tiles outside the
 solid band, timed with HIP events on its own stream), and the CPU oracle timed
 on a bounded sample of the same workload (all OpenMP threads, and one).
-During the untimed warm-up the extrapolation launch mode (all layers in one
-launch, or one launch per layer) is chosen by timing whole steps
-(lbrmt_autotune_steps; --no-autotune keeps the library default); the choice
+The extrapolation launch mode (all layers in one launch, or one launch per
+layer) is the library's default for the grid; --autotune chooses it during
+the untimed warm-up by timing whole steps (lbrmt_autotune_steps).  The mode
 is reported in extra.extrapolation_launch.
 """
 import argparse
@@ -65,7 +65,7 @@ def traffic_from_profile(kernel, workload, precision):
 
 
 def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_variant=None,
-            autotune=True):
+            autotune=False):
     import torch
     from paper_2402_12696_amd import Sim
     from paper_2402_12696_amd.lbrmt import LBRMT_OPT_LB_VARIANT, LBRMT_OPT_OVERLAP
@@ -78,9 +78,10 @@ def run_gpu(cfg, precision, steps, warmup, timing_steps, overlap=None, lb_varian
     sim.step(warmup)
     torch.cuda.synchronize()
     progress(f"{precision}: {warmup} warm-up steps done; choosing the extrapolation launch")
-    # extrapolation launch mode (one launch for all layers, or one per layer)
-    # chosen by timing whole steps, untimed here; the steps it takes are extra
-    # warm-up
+    # extrapolation launch mode (one launch for all layers, or one per layer):
+    # the library's default (-1: one launch when the bulk update is uncapped,
+    # as here), or with autotune chosen by timing whole steps, untimed; the
+    # steps it takes are extra warm-up
     if autotune:
         fused, _ = sim.autotune_steps(60)
     else:
@@ -307,7 +308,53 @@ def cpu_baseline(cfg, seconds=15.0):
             "sample": f"{n} steps of {cfg['name']} after 1 warm-up step "
                       f"({t:.1f} s, OpenMP threads {threads})",
             "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
-            "single_thread": _oracle_one_thread(cfg)}
+            "single_thread": _oracle_one_thread(cfg),
+            "parity_vs_gpu": parity_vs_oracle(cfg)}
+
+
+def parity_vs_oracle(cfg, precision="f64", steps=20, amp=0.01, cells=4, seed=7):
+    """The GPU step against the CPU oracle at full size on a deforming
+    solid: the workload's grid, disc and parameters with a seeded cellular
+    flow (amplitude amp) that shears and carries the disc from the first
+    step; errors after `steps` steps of both: rho, each velocity component
+    against its own maximum, xi, and the deviations rho - rho_f and xi - x
+    (over the nodes with phi < eps); node and solid sets must agree."""
+    import numpy as np
+    import workloads
+    from oracle import Oracle
+    from paper_2402_12696_amd import Sim
+    c = dict(cfg)
+    c.pop("steps", None)
+    c.pop("name", None)
+    u0 = workloads.cellular_velocity(c["nx"], c["ny"], amp, cells, seed)
+    ref = Oracle(**c).init(u0)
+    ref.step(steps)
+    sim = Sim(device="cuda:0", precision=precision, **c).init(u0)
+    sim.step(steps)
+    rho, ux, uy = (t.cpu().numpy() for t in sim.macro())
+    X, Y, P = (t.cpu().numpy() for t in sim.refmap())
+    sim.close()
+    rr, ru, rv = ref.macro()
+    RX, RY, RP = ref.refmap()
+
+    def rel(a, b):
+        m = np.max(np.abs(b))
+        return float(np.max(np.abs(a - b)) / m) if m > 0 else float(np.max(np.abs(a)))
+
+    mg, mr = ~np.isnan(X), ~np.isnan(RX)
+    same = bool(np.array_equal(mg, mr) and np.array_equal(P[mg] < 0, RP[mr] < 0))
+    y, x = np.mgrid[0:c["ny"], 0:c["nx"]] + 0.5
+    ms = mr & (RP < c.get("eps", 1.5))
+    rf = c.get("rho_f", 1.0)
+    return {"workload": f"{cfg['name']} with a cellular flow (amp {amp}, {cells} cells, seed {seed})",
+            "precision": precision, "steps": steps, "node_sets_equal": same,
+            "rho": rel(rho, rr), "ux": rel(ux, ru), "uy": rel(uy, rv),
+            "xi": max(rel(X[mr], RX[mr]), rel(Y[mr], RY[mr])),
+            "rho_minus_rho_f": rel(rho - rf, rr - rf),
+            "xi_minus_x": max(rel(X[ms] - x[ms], RX[ms] - x[ms]),
+                              rel(Y[ms] - y[ms], RY[ms] - y[ms])),
+            "max_xi_minus_x": float(max(np.max(np.abs(RX[ms] - x[ms])),
+                                        np.max(np.abs(RY[ms] - y[ms]))))}
 
 
 def _cpu_model():
@@ -356,8 +403,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--warmup", type=int, default=120)
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the extrapolation launch mode by timing whole steps "
+                         "(default: the library's choice for the grid)")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the library's default extrapolation launch mode")
+                    help="the default; kept for older command lines")
     ap.add_argument("--workload", default="cavity_disc_2048")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--timing-steps", type=int, default=300)
@@ -406,7 +456,7 @@ def main():
     nodes = cfg["nx"] * cfg["ny"]
     ms, kt, band, window, diag = run_gpu(cfg, args.precision, args.steps, args.warmup,
                                          args.timing_steps, args.overlap, args.lb_variant,
-                                         not args.no_autotune)
+                                         args.autotune and not args.no_autotune)
     mlups = nodes / (ms * 1e-3) / 1e6
 
     bulk_ms, bulk_n = kt["lb_bulk"]
@@ -447,7 +497,8 @@ def main():
              "health": diag["health"]}
     if args.precision == "f64" and not args.no_f32:
         ms32, kt32, _, _, d32 = run_gpu(cfg, "f32", args.steps, args.warmup, args.timing_steps,
-                                        args.overlap, args.lb_variant, not args.no_autotune)
+                                        args.overlap, args.lb_variant,
+                                        args.autotune and not args.no_autotune)
         b32 = step_bytes("f32", nodes, int(d32["n_band"]))
         extra["f32"] = {"ms_per_step": ms32, "mlups": nodes / (ms32 * 1e-3) / 1e6,
                         "speedup_vs_f64": ms / ms32,
