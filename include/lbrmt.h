@@ -353,6 +353,15 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         bulk update once stalled the step for about 0.1 s
  *                         and is not offered).  0: never held.  Results are
  *                         bitwise identical.
+ *   LBRMT_OPT_BULK_EARLY  0 .. 1000: when the bulk update is held, this
+ *                         many thousandths of its tiles (the first rows of
+ *                         the grid) are updated by a launch of their own
+ *                         that starts as soon as the previous step's chain
+ *                         has ended, beside the advection pass; the held
+ *                         launch takes the other tiles.  -1 (default): 500
+ *                         on grids of 2048 x 2048 nodes or more, else 0.
+ *                         Ignored while kernel timing is on.  Results are
+ *                         bitwise identical.
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,
@@ -361,7 +370,8 @@ typedef enum {
     LBRMT_OPT_GRAPH = 3,
     LBRMT_OPT_BULK_BLOCKS = 4,
     LBRMT_OPT_FUSED_FIT = 5,
-    LBRMT_OPT_HOLD_BULK = 6
+    LBRMT_OPT_HOLD_BULK = 6,
+    LBRMT_OPT_BULK_EARLY = 7
 } lbrmt_option;
 int lbrmt_set_option(lbrmt_ctx* ctx, int32_t option, int64_t value);
 int lbrmt_get_option(const lbrmt_ctx* ctx, int32_t option, int64_t* value);

@@ -770,6 +770,36 @@ struct Fit {
         bY1 += wc * cy * yv;
         bY2 += wc * yv;
     }
+    // add() for a node that may not be valid (v false: every sum gets a
+    // signed zero, which leaves its bits as skipping the node does, since no
+    // sum that starts at +0 ever holds -0)
+    __device__ __forceinline__ void add_if(bool v, int a, int b, bool use_n, double nxh,
+                                           double nyh, C xv, C yv)
+    {
+        double wt = v ? ldexp(1.0, -(abs(a) + abs(b))) : 0.0;
+        if (use_n) {
+            const double ddx = -(double)a, ddy = -(double)b;
+            // (a valid node is never the target itself, so d2 > 0 for it)
+            const double d2 = ddx * ddx + ddy * ddy;
+            const double dn = (ddx * nxh + ddy * nyh) / sqrt(d2 > 0.0 ? d2 : 1.0);
+            wt = dn * wt > 0.0 ? dn * wt : 0.0;
+        }
+        const MT w = MT(wt), dx = MT(a), dy = MT(b);
+        M00 += w * dx * dx;
+        M01 += w * dx * dy;
+        M02 += w * dx;
+        M11 += w * dy * dy;
+        M12 += w * dy;
+        M22 += w;
+        const C wc = C(wt), cx = C(a), cy = C(b);
+        const C xs = v ? xv : C(0), ys = v ? yv : C(0);
+        bX0 += wc * cx * xs;
+        bX1 += wc * cy * xs;
+        bX2 += wc * xs;
+        bY0 += wc * cx * ys;
+        bY1 += wc * cy * ys;
+        bY2 += wc * ys;
+    }
     // intercept of the weighted linear fit, if well posed
     __device__ __forceinline__ bool solve(double det_rel, C& x, C& y) const
     {
@@ -926,47 +956,39 @@ __device__ __forceinline__ bool fit_at(const GridP& g, const Rect& W, int l, int
 }
 
 // fit_window over the block's staged copy of the zone (tags st, values sx,
-// sy on a row-major region of rw columns; (li, lj) the target's place in it):
-// the same nodes in the same lanes and the same order of additions, so the
-// same bits
+// sy on a row-major region of rw columns; (li, lj) the target's place in it)
+// for the window of half-width 2 (side 5, 25 nodes), the only one the copy is
+// searched with: the same nodes in the same lanes and the same order of
+// additions as fit_window (lane sub takes nodes sub + 8 u, u = 0 .. 3, below
+// 25), every slot added through add_if, so the same bits without a branch
+// per node
 template <typename T, typename MT>
-__device__ __forceinline__ void fit_window_lds(int l, int li, int lj, int r, int sub, bool use_n,
-                                               double nxh, double nyh, const int8_t* st,
-                                               const T* sx, const T* sy, int rw, Fit<T, MT>& f,
-                                               int& count)
+__device__ __forceinline__ void fit_window_lds_r2(int l, int li, int lj, int sub, bool use_n,
+                                                  double nxh, double nyh, const int8_t* st,
+                                                  const T* sx, const T* sy, int rw,
+                                                  Fit<T, MT>& f, int& count)
 {
-    constexpr int PER = 4;
-    const int side = 2 * r + 1, nq = side * side;
-    int a = sub % side - r, b = sub / side - r;
-    for (int q0 = sub; q0 < nq; q0 += PER * FIT_LANES) {
-        int kk[PER], aa[PER], bb[PER], tk[PER];
-        T xv[PER], yv[PER];
+    constexpr int PER = 4, SIDE = 5, NQ = SIDE * SIDE;
+    static_assert(PER * FIT_LANES >= NQ && (PER - 1) * FIT_LANES < NQ,
+                  "one pass of PER nodes per lane covers the window");
+    const int base = lj * rw + li;
+    int tk[PER];
+    T xv[PER], yv[PER];
 #pragma unroll
-        for (int u = 0; u < PER; u++) {
-            aa[u] = a;
-            bb[u] = b;
-            kk[u] = q0 + u * FIT_LANES < nq ? (lj + b) * rw + li + a : -1;
-            a += FIT_LANES;
-            while (a > r) {
-                a -= side;
-                b += 1;
-            }
-        }
-        // every read before any use (a value read for a node that holds none
-        // is never used)
+    for (int u = 0; u < PER; u++) {
+        const int q = sub + u * FIT_LANES;
+        // (a slot past the window reads the target's own place, never used)
+        const int k = q < NQ ? base + (q / SIDE - 2) * rw + q % SIDE - 2 : base;
+        tk[u] = st[k];
+        xv[u] = sx[k];
+        yv[u] = sy[k];
+    }
 #pragma unroll
-        for (int u = 0; u < PER; u++) {
-            const int k = kk[u] >= 0 ? kk[u] : 0;
-            tk[u] = st[k];
-            xv[u] = sx[k];
-            yv[u] = sy[k];
-        }
-#pragma unroll
-        for (int u = 0; u < PER; u++) {
-            if (kk[u] < 0 || !tag_valid_before(tk[u], l)) continue;
-            count++;
-            f.add(aa[u], bb[u], use_n, nxh, nyh, xv[u], yv[u]);
-        }
+    for (int u = 0; u < PER; u++) {
+        const int q = sub + u * FIT_LANES;
+        const bool v = q < NQ && tag_valid_before(tk[u], l);
+        count += v ? 1 : 0;
+        f.add_if(v, q % SIDE - 2, q / SIDE - 2, use_n, nxh, nyh, xv[u], yv[u]);
     }
 }
 
@@ -1016,8 +1038,12 @@ __device__ __forceinline__ bool fit_target(const GridP& g, const Rect& W, const 
     return false;
 }
 
-// fit_target with the scan windows read from the block's staged copy of the
-// zone ((li, lj): the target's place in it)
+// fit_target with the scan window read from the block's staged copy of the
+// zone ((li, lj): the target's place in it), of half-width 2 only: a target
+// whose fit needs a wider window, or whose window of half-width 2 reaches
+// beyond the copy (rlim < 2), is not fitted (cut set, unless r_max is 2 and
+// the fit has failed for good); k_fit_rest then fits it with the full search,
+// which finds the same bits for the window of half-width 2
 // (use_n, nxh, nyh: the normal weight of layers 1 and 2, found by the caller
 // as target_normal finds it)
 template <typename T, typename MT>
@@ -1026,18 +1052,14 @@ __device__ __forceinline__ bool fit_target_lds(const GridP& g, int l, int li, in
                                                const T* sy, int rw, T& xo, T& yo, bool& cut,
                                                bool use_n, double nxh, double nyh)
 {
-    cut = false;
-    for (int r = 2; r <= g.r_max; r++) {
-        if (r > rlim) {
-            cut = true;
-            return false;
-        }
-        int count = 0;
-        Fit<T, MT> f;
-        f.zero();
-        fit_window_lds<T, MT>(l, li, lj, r, sub, use_n, nxh, nyh, st, sx, sy, rw, f, count);
-        if (fit_finish<T, MT>(g, f, count, xo, yo)) return true;
-    }
+    cut = rlim < 2;
+    if (cut) return false;
+    int count = 0;
+    Fit<T, MT> f;
+    f.zero();
+    fit_window_lds_r2<T, MT>(l, li, lj, sub, use_n, nxh, nyh, st, sx, sy, rw, f, count);
+    if (fit_finish<T, MT>(g, f, count, xo, yo)) return true;
+    cut = g.r_max > 2;
     return false;
 }
 
@@ -1219,7 +1241,8 @@ __device__ void fit_rest(const GridP& g, const Win* __restrict__ win, int wcur, 
 // window of half-width 2 around a target within M_l of the tile stays within
 // M_l + 2 = M_{l-1}, where the copy holds every earlier layer, and layer-1
 // windows read solid nodes only, which the copy holds across the margin.  A
-// target that needs a wider window than that stops the tile at that layer:
+// target whose fit needs a wider window than that (fewer than three valid
+// nodes in it, or an ill-posed fit) stops the tile at that layer:
 // the tile is listed, with the layer, for k_fit_rest, which finishes the
 // listed tiles layer by layer; the tile's layers before that one are final.
 // reach = 2; reach = 1 stops every tile with a target on the rim of its

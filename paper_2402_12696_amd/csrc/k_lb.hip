@@ -113,7 +113,8 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     GridP g, const S* __restrict__ A, S* __restrict__ B, const double* __restrict__ fpx,
     const double* __restrict__ fpy, const double* __restrict__ fcx, const double* __restrict__ fcy,
     const double* __restrict__ drho, Win* win, int wprev, int wcur, double fpo_x, double fpo_y,
-    unsigned* __restrict__ health, const int* __restrict__ boxpart, int nbox, int wnext)
+    unsigned* __restrict__ health, const int* __restrict__ boxpart, int nbox, int wnext,
+    int tile0, int tile1)
 {
     if ((PART == 0 || PART == 2) && nbox > 0 && blockIdx.x == 0) {
         const Win r = reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
@@ -137,10 +138,12 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
         t_step = gridDim.x;
         t_end = untx * unty;
     } else {
-        // one tile per block, or a capped grid striding over the tiles
-        t_begin = xcd_remap(blockIdx.x, gridDim.x);
+        // one tile per block, or a capped grid striding over the tiles, of
+        // the tiles tile0 .. tile1 - 1 (PART 3; the others take all)
+        const int first = PART == 3 ? tile0 : 0;
+        t_begin = first + xcd_remap(blockIdx.x, gridDim.x);
         t_step = gridDim.x;
-        t_end = ntx * nty;
+        t_end = PART == 3 ? min(tile1, ntx * nty) : ntx * nty;
     }
     for (int t = t_begin; t < t_end; t += t_step) {
         int tile_x, tile_y;
@@ -234,19 +237,27 @@ void lb_variant_tile(int v, int* tx, int* ty)
     *ty = LB_VARIANTS[v].ty * LB_VARIANTS[v].r;
 }
 
+// PART 3 takes tiles [frac0, frac1) / 1000 of the grid's tiles (row by row)
 template <typename S, int PART, int TX, int TY, int R, bool NT>
 static void lb_launch_one(const GridP& g, const void* A, void* B, const double* fpx,
                           const double* fpy, const double* fcx, const double* fcy,
                           const double* drho, Win* win, int wprev, int wcur, double fpo_x,
                           double fpo_y, int max_blocks, unsigned* health, hipStream_t st,
-                          const int* boxpart, int nbox, int wnext)
+                          const int* boxpart, int nbox, int wnext, int frac0, int frac1)
 {
     const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY * R - 1) / (TY * R));
-    int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : ntiles;
+    int t0 = 0, t1 = ntiles;
+    if (PART == 3) {
+        t0 = (int)((long long)ntiles * frac0 / 1000);
+        t1 = (int)((long long)ntiles * frac1 / 1000);
+    }
+    if (t1 <= t0) return;
+    int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : t1 - t0;
     if ((PART == 1 || PART == 3) && max_blocks > 0 && max_blocks < grid) grid = max_blocks;
     k_lb<S, PART, TX, TY, R, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx,
                                                           fcy, drho, win, wprev, wcur, fpo_x,
-                                                          fpo_y, health, boxpart, nbox, wnext);
+                                                          fpo_y, health, boxpart, nbox, wnext,
+                                                          t0, t1);
 }
 
 template <typename S, int PART>
@@ -254,12 +265,13 @@ static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, con
                               const double* fpy, const double* fcx, const double* fcy,
                               const double* drho, Win* win, int wprev, int wcur,
                               double fpo_x, double fpo_y, int max_blocks, unsigned* health,
-                              hipStream_t st, const int* boxpart, int nbox, int wnext)
+                              hipStream_t st, const int* boxpart, int nbox, int wnext,
+                              int frac0, int frac1)
 {
 #define LBV(TX, TY, R, NT)                                                                       \
     lb_launch_one<S, PART, TX, TY, R, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
                                           fpo_x, fpo_y, max_blocks, health, st, boxpart, nbox,  \
-                                          wnext)
+                                          wnext, frac0, frac1)
     switch (v) {
     case 1: LBV(128, 2, 1, false); break;
     case 2: LBV(256, 1, 1, false); break;
@@ -289,12 +301,13 @@ hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, 
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
                      const double* drho, Win* win, int wprev, int wcur, double fpo_x,
                      double fpo_y, int part, unsigned* health, hipStream_t st, int max_blocks,
-                     const int* boxpart, int nbox, Win* winw, int wnext)
+                     const int* boxpart, int nbox, Win* winw, int wnext, int frac0, int frac1)
 {
     (void)winw;
 #define LBP(S, PARTV)                                                                        \
     lb_launch_variant<S, PARTV>(variant, g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
-                                fpo_x, fpo_y, max_blocks, health, st, boxpart, nbox, wnext)
+                                fpo_x, fpo_y, max_blocks, health, st, boxpart, nbox, wnext,  \
+                                frac0, frac1)
     if (precision == 0) {
         if (part == 0) LBP(double, 0);
         else if (part == 1) LBP(double, 1);

@@ -219,6 +219,10 @@ struct lbrmt_ctx {
     // steps 6 + p .. 6 + p + r - 1 (r < 6): replayed for step runs that do not
     // start or end on a six-step boundary, captured on first use
     hipGraphExec_t pexec[GRAPH_STEPS][GRAPH_STEPS] = {};
+    // the captured graphs of gexec and pexec, kept until their executable
+    // graphs are destroyed
+    hipGraph_t gsrc = nullptr;
+    hipGraph_t psrc[GRAPH_STEPS][GRAPH_STEPS] = {};
     bool graph = true;  // replay captured six-step graphs
     bool member = false;  // member of a batch (stepped by the batch only)
     int bulk_blocks = 0;  // cap on the blocks of the overlapped bulk update (0: one per tile)
@@ -226,6 +230,9 @@ struct lbrmt_ctx {
     // hold the bulk update until the advection pass ends: -1 when it is
     // uncapped (default), 1 always (refused with a cap), 0 never
     int hold_bulk = -1;
+    // thousandths of a held bulk update's tiles launched early, when the
+    // previous step's chain ends (-1: by grid size)
+    int bulk_early = -1;
     bool timing = false;
     struct Pending {
         int kind;
@@ -380,6 +387,18 @@ static StampValid prev_valid(const lbrmt_ctx* c)
 // Block size of the one-launch extrapolation (default 1024; one launch per
 // layer, 0, by default when the bulk update's workgroups are capped), 0 for
 // one launch per layer.
+// The early part of a held bulk update: -1 (default) takes half the tiles on
+// grids of 2048^2 nodes or more, where the bulk update outlasts the chain's
+// latency-bound head (MI355X, cavity with a disc, ms/step without -> with:
+// 2048^2 FP64 0.1730 -> 0.1653, FP32 0.1121 -> 0.1086; 3072^2 FP64 0.3836 ->
+// 0.3711), and none on smaller ones, where it only slows the advection pass
+// beside it (1024^2 FP64 0.0796 -> 0.0854)
+static int bulk_early(const lbrmt_ctx* c)
+{
+    if (c->bulk_early >= 0) return c->bulk_early;
+    return (long long)c->d.nx * c->d.ny >= 2048ll * 2048 ? 500 : 0;
+}
+
 static int fused_threads(const lbrmt_ctx* c)
 {
     if (c->fused_fit >= 0) return c->fused_fit;
@@ -460,17 +479,31 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s, bool firs
         if (c->overlap) {
             // the waits below bind to the records of the previous step: they
             // are enqueued before this step's records of the same events
+            // the early tiles of a held bulk update: after the previous
+            // step's chain (the window of this step, the lattice rows of the
+            // previous one and its readers of this step's target lattice are
+            // then final), beside this step's chain, whose kernels write no
+            // lattice node outside the window and read none this launch
+            // writes
+            const int early = hold_bulk && !c->timing ? bulk_early(c) : 0;
+            if (early > 0) {
+                if (!first) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
+                HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt],
+                                    c->Fx[s.nxt], c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur],
+                                    c->drho, c->bb.win, s.wprev, s.wcur, ox, oy, 3,
+                                    c->bb.health, main_s, 0, nullptr, 0, nullptr, 0, 0, early));
+            }
             if (hold_bulk) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_adv, 0));
             else if (!first) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
             HIPCHK(c, hipEventRecord(c->ev_join, c->side));
             {
-                // every node outside the window: its update needs no force of
-                // this step's chain
+                // every node outside the window (but the early tiles): its
+                // update needs no force of this step's chain
                 Bracket b(c, 4, main_s);
                 HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
                                     c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
                                     s.wprev, s.wcur, ox, oy, 3, c->bb.health, main_s,
-                                    c->bulk_blocks));
+                                    c->bulk_blocks, nullptr, 0, nullptr, 0, early, 1000));
                 b.done();
             }
             if (last) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
@@ -491,7 +524,9 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s, bool firs
 // enqueue identical launches (every buffer parity and ring slot repeats with
 // period six), so such a graph replays any run of r steps that starts at a
 // step count = p mod 6, p + r <= 6.
-static int capture_steps(lbrmt_ctx* c, int p, int r, hipGraphExec_t* out)
+// The captured graph goes to *src, kept (as the executable graph needs
+// nothing of it) until the executable graph is destroyed.
+static int capture_steps(lbrmt_ctx* c, int p, int r, hipGraphExec_t* out, hipGraph_t* src)
 {
     hipGraph_t graph = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
@@ -505,15 +540,35 @@ static int capture_steps(lbrmt_ctx* c, int p, int r, hipGraphExec_t* out)
     }
     if (e != hipSuccess) return fail(c, "hipStreamEndCapture", e);
     e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
         *out = nullptr;
         return fail(c, "hipGraphInstantiate", e);
     }
+    *src = graph;
     return LBRMT_OK;
 }
 
-static int build_graph(lbrmt_ctx* c) { return capture_steps(c, 0, GRAPH_STEPS, &c->gexec); }
+static int build_graph(lbrmt_ctx* c)
+{
+    return capture_steps(c, 0, GRAPH_STEPS, &c->gexec, &c->gsrc);
+}
+
+// every executable graph, then the graph it was made from
+static void destroy_graphs(lbrmt_ctx* c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->gsrc) (void)hipGraphDestroy(c->gsrc);
+    c->gexec = nullptr;
+    c->gsrc = nullptr;
+    for (int p = 0; p < GRAPH_STEPS; p++)
+        for (int r = 0; r < GRAPH_STEPS; r++) {
+            if (c->pexec[p][r]) (void)hipGraphExecDestroy(c->pexec[p][r]);
+            if (c->psrc[p][r]) (void)hipGraphDestroy(c->psrc[p][r]);
+            c->pexec[p][r] = nullptr;
+            c->psrc[p][r] = nullptr;
+        }
+}
 
 // Destroy every captured graph (after synchronising the stream that replays
 // them): they bake the launch configuration and the solids in.
@@ -524,14 +579,7 @@ static int drop_graphs(lbrmt_ctx* c)
         for (int r = 0; r < GRAPH_STEPS; r++) any = any || c->pexec[p][r];
     if (!any) return LBRMT_OK;
     HIPCHK(c, hipStreamSynchronize(c->st));
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-    for (int p = 0; p < GRAPH_STEPS; p++)
-        for (int r = 0; r < GRAPH_STEPS; r++)
-            if (c->pexec[p][r]) {
-                (void)hipGraphExecDestroy(c->pexec[p][r]);
-                c->pexec[p][r] = nullptr;
-            }
+    destroy_graphs(c);
     return LBRMT_OK;
 }
 
@@ -724,17 +772,15 @@ int lbrmt_create(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, size_t 
 void lbrmt_destroy(lbrmt_ctx* c)
 {
     if (!c) return;
-    if (c->st) (void)hipStreamSynchronize(c->st);
+    // (st may be the null stream: it is synchronised too)
+    (void)hipStreamSynchronize(c->st);
     if (c->side) (void)hipStreamSynchronize(c->side);
     for (auto& p : c->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    for (int p = 0; p < GRAPH_STEPS; p++)
-        for (int r = 0; r < GRAPH_STEPS; r++)
-            if (c->pexec[p][r]) (void)hipGraphExecDestroy(c->pexec[p][r]);
+    destroy_graphs(c);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_adv) (void)hipEventDestroy(c->ev_adv);
@@ -1005,7 +1051,7 @@ int lbrmt_step(lbrmt_ctx* c, int64_t nsteps)
             // up to the next six-step boundary, or the end of the run
             const int r = (int)std::min<int64_t>(left, GRAPH_STEPS - p);
             if (!c->pexec[p][r]) {
-                int rc = capture_steps(c, p, r, &c->pexec[p][r]);
+                int rc = capture_steps(c, p, r, &c->pexec[p][r], &c->psrc[p][r]);
                 if (rc != LBRMT_OK) return rc;
             }
             HIPCHK(c, hipGraphLaunch(c->pexec[p][r], c->st));
@@ -1727,6 +1773,10 @@ int lbrmt_set_option(lbrmt_ctx* c, int32_t option, int64_t value)
         }
         c->hold_bulk = (int)value;
         break;
+    case LBRMT_OPT_BULK_EARLY:
+        if (value < -1 || value > 1000) return LBRMT_EINVAL;
+        c->bulk_early = (int)value;
+        break;
     default:
         return LBRMT_EINVAL;
     }
@@ -1745,6 +1795,7 @@ int lbrmt_get_option(const lbrmt_ctx* c, int32_t option, int64_t* value)
     case LBRMT_OPT_BULK_BLOCKS: *value = c->bulk_blocks; return LBRMT_OK;
     case LBRMT_OPT_FUSED_FIT: *value = c->fused_fit; return LBRMT_OK;
     case LBRMT_OPT_HOLD_BULK: *value = c->hold_bulk; return LBRMT_OK;
+    case LBRMT_OPT_BULK_EARLY: *value = c->bulk_early; return LBRMT_OK;
     default: return LBRMT_EINVAL;
     }
 }
@@ -1916,6 +1967,7 @@ struct lbrmt_batch {
     bool graph = true;
     int fused_fit = 0;  // 1024: one extrapolation launch if every member can; 0 (-1): per layer
     hipGraphExec_t gexec = nullptr;
+    hipGraph_t gsrc = nullptr;  // the captured graph of gexec
     long long step = 0;
     bool inited = false;
     std::string err;
@@ -2079,11 +2131,12 @@ int batch_graph(lbrmt_batch* b)
     }
     if (e != hipSuccess) return bfail(b, "hipStreamEndCapture", e);
     e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
         b->gexec = nullptr;
         return bfail(b, "hipGraphInstantiate", e);
     }
+    b->gsrc = graph;  // kept until the executable graph is destroyed
     return LBRMT_OK;
 }
 
@@ -2094,6 +2147,8 @@ void batch_drop_graph(lbrmt_batch* b)
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
     }
+    if (b->gsrc) (void)hipGraphDestroy(b->gsrc);
+    b->gsrc = nullptr;
 }
 
 }  // namespace
@@ -2168,8 +2223,10 @@ int lbrmt_batch_create(const lbrmt_grid_desc* descs, const lbrmt_solid_desc* sol
 void lbrmt_batch_destroy(lbrmt_batch* b)
 {
     if (!b) return;
-    if (b->st) (void)hipStreamSynchronize(b->st);
+    // (st may be the null stream: it is synchronised too)
+    (void)hipStreamSynchronize(b->st);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->gsrc) (void)hipGraphDestroy(b->gsrc);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (auto c : b->m) lbrmt_destroy(c);
     delete b;

@@ -471,13 +471,14 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
 hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const int* tile_sim,
                            int total_tiles, hipStream_t st);
 // PART 0 / 2 launches with nbox > 0 also reduce the force pass's partial
-// boxes (boxpart) into ring slot wnext of win
+// boxes (boxpart) into ring slot wnext of win.  PART 3 updates the tiles
+// [frac0, frac1) / 1000 of the grid's tiles (none if that range is empty).
 hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
                      const double* drho, Win* win, int wprev, int wcur, double fpo_x,
                      double fpo_y, int part, unsigned* health, hipStream_t st,
                      int max_blocks = 0, const int* boxpart = nullptr, int nbox = 0,
-                     Win* winw = nullptr, int wnext = 0);
+                     Win* winw = nullptr, int wnext = 0, int frac0 = 0, int frac1 = 1000);
 int lb_variant_count();
 void lb_variant_tile(int v, int* tx, int* ty);
 // drho0 (several solids): the density excess of every node, instead of the

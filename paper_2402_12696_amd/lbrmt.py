@@ -26,6 +26,7 @@ LBRMT_OPT_OVERLAP, LBRMT_OPT_LB_VARIANT, LBRMT_OPT_LB_VARIANT_COUNT, LBRMT_OPT_G
 LBRMT_OPT_BULK_BLOCKS = 4
 LBRMT_OPT_FUSED_FIT = 5
 LBRMT_OPT_HOLD_BULK = 6
+LBRMT_OPT_BULK_EARLY = 7
 
 
 class lbrmt_grid_desc(ctypes.Structure):

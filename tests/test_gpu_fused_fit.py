@@ -103,6 +103,47 @@ def test_hold_option_refuses_a_held_and_capped_bulk_update():
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_early_bulk_tiles_are_bitwise_the_single_bulk_launch(prec):
+    # part of the held bulk update launched when the previous step's chain
+    # ends: the same state after graph replays (whole and partial six-step
+    # runs) and eager steps, for several fractions, the whole grid included
+    from paper_2402_12696_amd import Sim
+    from paper_2402_12696_amd import lbrmt as B
+
+    def run(early, graph=True):
+        sim = Sim(device="cuda:0", precision=prec, **workloads.cavity_disc_256())
+        sim.set_option(B.LBRMT_OPT_GRAPH, 1 if graph else 0)
+        sim.set_option(B.LBRMT_OPT_BULK_EARLY, early)
+        assert sim.get_option(B.LBRMT_OPT_BULK_EARLY) == early
+        sim.init()
+        for n in (7, 12, 5, 30, 1):
+            sim.step(n)
+        out = _state(sim)
+        sim.close()
+        return out
+
+    ref = run(0)
+    assert not any(ref[6].values()), ref[6]
+    for early in (1, 150, 500, 1000, -1):
+        assert _equal(ref, run(early)), early
+    assert _equal(ref, run(300, graph=False))
+
+
+def test_early_bulk_option_values():
+    from paper_2402_12696_amd import Sim
+    from paper_2402_12696_amd import lbrmt as B
+    sim = Sim(device="cuda:0", precision="f64", **workloads.cavity_disc_64())
+    assert sim.get_option(B.LBRMT_OPT_BULK_EARLY) == -1
+    for v in (0, 1000, -1):
+        sim.set_option(B.LBRMT_OPT_BULK_EARLY, v)
+        assert sim.get_option(B.LBRMT_OPT_BULK_EARLY) == v
+    for v in (-2, 1001):
+        with pytest.raises(B.LBRMTError):
+            sim.set_option(B.LBRMT_OPT_BULK_EARLY, v)
+    sim.close()
+
+
 def test_autotune_steps_chooses_a_mode_and_steps_like_lbrmt_step():
     from paper_2402_12696_amd import Sim
     from paper_2402_12696_amd import lbrmt as B
