@@ -128,7 +128,8 @@ typedef enum {
     LBRMT_H_DETJ = 3,        /* half-edge with det(grad xi) <= detJ_min          */
     LBRMT_H_DETJ_SOLID = 4,  /* ... of those, edges with solid fraction > 1/2    */
     LBRMT_H_NONFINITE = 5,   /* nodes whose density is not finite or <= 0        */
-    LBRMT_H_WINDOW_CLIP = 6, /* a solid's zone reached its window's border       */
+    LBRMT_H_WINDOW_CLIP = 6, /* a solid's zone reached its window's border (one
+                                solid: also its box moved down > 2 rows in a step) */
     LBRMT_H_LIST_OVERFLOW = 7, /* list entries dropped at capacity (layer lists;
                                   solids met by one force block beyond 32)      */
     LBRMT_H_COUNT = 8
@@ -353,15 +354,19 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         bulk update once stalled the step for about 0.1 s
  *                         and is not offered).  0: never held.  Results are
  *                         bitwise identical.
- *   LBRMT_OPT_BULK_EARLY  0 .. 1000: when the bulk update is held, this
- *                         many thousandths of its tiles (the first rows of
- *                         the grid) are updated by a launch of their own
- *                         that starts as soon as the previous step's chain
- *                         has ended, beside the advection pass; the held
- *                         launch takes the other tiles.  -1 (default): 500
- *                         on grids of 2048 x 2048 nodes or more, else 0.
- *                         Ignored while kernel timing is on.  Results are
- *                         bitwise identical.
+ *   LBRMT_OPT_BULK_EARLY  0 .. 1000: when the bulk update is held, of the
+ *                         first this many thousandths of its tiles (the first
+ *                         rows of the grid) those wholly below the previous
+ *                         step's window by more than 2 rows are updated by a
+ *                         launch of their own, which starts when the
+ *                         previous step's bulk update has ended, beside the
+ *                         end of that step's chain and this step's
+ *                         advection pass; the held launch takes the other
+ *                         tiles.  -1 (default): 300 on grids of 2048 x 2048
+ *                         nodes or more, else 0.  Ignored while kernel timing
+ *                         is on.  Results are bitwise identical.  (A solid
+ *                         box whose lower edge moves down by more than 2
+ *                         rows in one step is counted in LBRMT_H_WINDOW_CLIP.)
  * EINVAL for an unknown option or value. */
 typedef enum {
     LBRMT_OPT_OVERLAP = 0,

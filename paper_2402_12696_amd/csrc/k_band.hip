@@ -1893,17 +1893,27 @@ hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, cons
 
 // one block: the force pass's partial boxes into ring slot wnext, and the
 // zone check of the new window (what the band lattice launch does otherwise)
+// (also counts a box whose lower edge moved down by more than
+// BULK_EARLY_GAP rows from the current one: the early part of the next
+// step's bulk update assumes it does not)
 __global__ __launch_bounds__(256) void k_reduce_window(GridP g, const int* __restrict__ boxpart,
-                                                       int nbox, Win* win, int wnext,
+                                                       int nbox, Win* win, int wcur, int wnext,
                                                        unsigned* health)
 {
+    const Win cur = win[wcur];
     const Win r = reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
-    if (threadIdx.x == 0) check_zone(g, r, health);
+    if (threadIdx.x == 0) {
+        check_zone(g, r, health);
+        if (r.i0 <= r.i1 && cur.i0 <= cur.i1 && r.j0 < cur.j0 - BULK_EARLY_GAP)
+            atomicAdd(&health[6], 1u);
+    }
 }
 
-hipError_t launch_reduce_window(const GridP& g, const BandBufs& bb, int wnext, hipStream_t st)
+hipError_t launch_reduce_window(const GridP& g, const BandBufs& bb, int wcur, int wnext,
+                                hipStream_t st)
 {
-    k_reduce_window<<<1, 256, 0, st>>>(g, bb.boxpart, RELABEL_BLOCKS, bb.win, wnext, bb.health);
+    k_reduce_window<<<1, 256, 0, st>>>(g, bb.boxpart, RELABEL_BLOCKS, bb.win, wcur, wnext,
+                                       bb.health);
     return hipGetLastError();
 }
 

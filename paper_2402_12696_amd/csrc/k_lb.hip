@@ -114,7 +114,7 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     const double* __restrict__ fpy, const double* __restrict__ fcx, const double* __restrict__ fcy,
     const double* __restrict__ drho, Win* win, int wprev, int wcur, double fpo_x, double fpo_y,
     unsigned* __restrict__ health, const int* __restrict__ boxpart, int nbox, int wnext,
-    int tile0, int tile1)
+    int tile0, int tile1, int split)
 {
     if ((PART == 0 || PART == 2) && nbox > 0 && blockIdx.x == 0) {
         const Win r = reduce_boxes(boxpart, nbox, &win[wnext], nullptr);
@@ -124,7 +124,15 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
     const int ntx = (g.nx + LB_TX - 1) / LB_TX;
     const int nty = (g.ny + TH - 1) / TH;
     const Rect wp = window_of(win, wprev, g);
-    const Rect wc = window_of(win, wcur, g);
+    // PART 3, split 1: the early launch, which may run before this step's
+    // window is written, never reads it (its tiles lie below every node it
+    // can hold)
+    const Rect wc = PART == 3 && split == 1 ? Rect{0, -1, 0, -1, false} : window_of(win, wcur, g);
+    // PART 3 split into an early and a held launch: the tile rows wholly
+    // below the previous step's window by more than BULK_EARLY_GAP rows (none
+    // without one) go to the early launch, up to its range tile0 .. tile1 - 1
+    const int far_end = PART == 3 && split != 0 && wp.ok && wp.j0 - BULK_EARLY_GAP > 0
+                            ? (wp.j0 - BULK_EARLY_GAP) / TH * ntx : 0;
     const Rect U = band_region(g, wp, wc);
     int t_begin, t_step, t_end;
     int utx0 = 0, uty0 = 0, untx = 1;
@@ -139,11 +147,15 @@ __global__ __launch_bounds__(LB_TX* LB_TY) void k_lb(
         t_end = untx * unty;
     } else {
         // one tile per block, or a capped grid striding over the tiles, of
-        // the tiles tile0 .. tile1 - 1 (PART 3; the others take all)
-        const int first = PART == 3 ? tile0 : 0;
+        // the tiles tile0 .. tile1 - 1 (PART 3; the others take all).  Split
+        // 1 (early): the tiles of 0 .. tile1 - 1 before far_end; split 2
+        // (held): every tile from min(tile0, far_end) on, striding
+        int first = PART == 3 ? tile0 : 0;
+        t_end = PART == 3 ? min(tile1, ntx * nty) : ntx * nty;
+        if (PART == 3 && split == 1) t_end = min(t_end, far_end);
+        if (PART == 3 && split == 2) first = min(tile0, far_end);
         t_begin = first + xcd_remap(blockIdx.x, gridDim.x);
         t_step = gridDim.x;
-        t_end = PART == 3 ? min(tile1, ntx * nty) : ntx * nty;
     }
     for (int t = t_begin; t < t_end; t += t_step) {
         int tile_x, tile_y;
@@ -243,7 +255,8 @@ static void lb_launch_one(const GridP& g, const void* A, void* B, const double* 
                           const double* fpy, const double* fcx, const double* fcy,
                           const double* drho, Win* win, int wprev, int wcur, double fpo_x,
                           double fpo_y, int max_blocks, unsigned* health, hipStream_t st,
-                          const int* boxpart, int nbox, int wnext, int frac0, int frac1)
+                          const int* boxpart, int nbox, int wnext, int frac0, int frac1,
+                          int split)
 {
     const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY * R - 1) / (TY * R));
     int t0 = 0, t1 = ntiles;
@@ -251,13 +264,17 @@ static void lb_launch_one(const GridP& g, const void* A, void* B, const double* 
         t0 = (int)((long long)ntiles * frac0 / 1000);
         t1 = (int)((long long)ntiles * frac1 / 1000);
     }
-    if (t1 <= t0) return;
+    // (the held launch also takes the early range's tiles that the early
+    // launch leaves, so it runs, striding, even when its own range is empty)
+    const bool held = PART == 3 && split == 2;
+    if (t1 <= t0 && !held) return;
     int grid = PART == 2 ? (ntiles < 2048 ? ntiles : 2048) : t1 - t0;
+    if (held && grid < 256) grid = ntiles < 256 ? ntiles : 256;
     if ((PART == 1 || PART == 3) && max_blocks > 0 && max_blocks < grid) grid = max_blocks;
     k_lb<S, PART, TX, TY, R, NT><<<grid, TX * TY, 0, st>>>(g, (const S*)A, (S*)B, fpx, fpy, fcx,
                                                           fcy, drho, win, wprev, wcur, fpo_x,
                                                           fpo_y, health, boxpart, nbox, wnext,
-                                                          t0, t1);
+                                                          t0, t1, split);
 }
 
 template <typename S, int PART>
@@ -266,12 +283,12 @@ static void lb_launch_variant(int v, const GridP& g, const void* A, void* B, con
                               const double* drho, Win* win, int wprev, int wcur,
                               double fpo_x, double fpo_y, int max_blocks, unsigned* health,
                               hipStream_t st, const int* boxpart, int nbox, int wnext,
-                              int frac0, int frac1)
+                              int frac0, int frac1, int split)
 {
 #define LBV(TX, TY, R, NT)                                                                       \
     lb_launch_one<S, PART, TX, TY, R, NT>(g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
                                           fpo_x, fpo_y, max_blocks, health, st, boxpart, nbox,  \
-                                          wnext, frac0, frac1)
+                                          wnext, frac0, frac1, split)
     switch (v) {
     case 1: LBV(128, 2, 1, false); break;
     case 2: LBV(256, 1, 1, false); break;
@@ -301,13 +318,14 @@ hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, 
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
                      const double* drho, Win* win, int wprev, int wcur, double fpo_x,
                      double fpo_y, int part, unsigned* health, hipStream_t st, int max_blocks,
-                     const int* boxpart, int nbox, Win* winw, int wnext, int frac0, int frac1)
+                     const int* boxpart, int nbox, Win* winw, int wnext, int frac0, int frac1,
+                     int split)
 {
     (void)winw;
 #define LBP(S, PARTV)                                                                        \
     lb_launch_variant<S, PARTV>(variant, g, A, B, fpx, fpy, fcx, fcy, drho, win, wprev, wcur, \
                                 fpo_x, fpo_y, max_blocks, health, st, boxpart, nbox, wnext,  \
-                                frac0, frac1)
+                                frac0, frac1, split)
     if (precision == 0) {
         if (part == 0) LBP(double, 0);
         else if (part == 1) LBP(double, 1);

@@ -205,7 +205,11 @@ struct lbrmt_ctx {
     hipStream_t st = nullptr;
     hipStream_t side = nullptr;
     hipStream_t cap = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_adv = nullptr, ev_bulk = nullptr;
+    // the cross-stream events of step n are those of slot n mod 6: inside a
+    // captured sequence no event is recorded twice, and a wait on the
+    // previous step's record names that step's event
+    hipEvent_t ev_fork[GRAPH_STEPS] = {}, ev_join[GRAPH_STEPS] = {}, ev_adv[GRAPH_STEPS] = {},
+               ev_bulk[GRAPH_STEPS] = {};
     char* ws = nullptr;
     void* lat[2];
     double *Fx[2], *Fy[2], *drho;
@@ -387,16 +391,16 @@ static StampValid prev_valid(const lbrmt_ctx* c)
 // Block size of the one-launch extrapolation (default 1024; one launch per
 // layer, 0, by default when the bulk update's workgroups are capped), 0 for
 // one launch per layer.
-// The early part of a held bulk update: -1 (default) takes half the tiles on
-// grids of 2048^2 nodes or more, where the bulk update outlasts the chain's
-// latency-bound head (MI355X, cavity with a disc, ms/step without -> with:
-// 2048^2 FP64 0.1730 -> 0.1653, FP32 0.1121 -> 0.1086; 3072^2 FP64 0.3836 ->
-// 0.3711), and none on smaller ones, where it only slows the advection pass
-// beside it (1024^2 FP64 0.0796 -> 0.0854)
+// The early part of a held bulk update: -1 (default) takes the far tiles of
+// the first 30 % on grids of 2048^2 nodes or more, where the bulk update
+// outlasts the chain's latency-bound head (MI355X, cavity with a disc,
+// ms/step without -> with: 2048^2 FP64 0.1732 -> 0.1624, FP32 0.1124 ->
+// 0.1072), and none on smaller ones, where it only slows the advection pass
+// beside it (1024^2 FP64 0.0796 -> 0.0854 with half the tiles)
 static int bulk_early(const lbrmt_ctx* c)
 {
     if (c->bulk_early >= 0) return c->bulk_early;
-    return (long long)c->d.nx * c->d.ny >= 2048ll * 2048 ? 500 : 0;
+    return (long long)c->d.nx * c->d.ny >= 2048ll * 2048 ? 300 : 0;
 }
 
 static int fused_threads(const lbrmt_ctx* c)
@@ -426,12 +430,16 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s, bool firs
     const GridP& g = c->g;
     const int prec = c->d.precision;
     const double ox = fpo_x(c, n), oy = fpo_y(c, n);
+    const int ek = (int)(n % GRAPH_STEPS), ep = (int)((n + GRAPH_STEPS - 1) % GRAPH_STEPS);
+    hipEvent_t ev_fork = c->ev_fork[ek], ev_adv = c->ev_adv[ek], ev_join = c->ev_join[ek];
+    hipEvent_t ev_bulk = c->ev_bulk[ek];
+    hipEvent_t prev_join = c->ev_join[ep], prev_bulk = c->ev_bulk[ep];
     if (c->nsolid > 0) {
         hipStream_t band = main_s;
         if (c->overlap) {
             if (first) {
-                HIPCHK(c, hipEventRecord(c->ev_fork, main_s));
-                HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+                HIPCHK(c, hipEventRecord(ev_fork, main_s));
+                HIPCHK(c, hipStreamWaitEvent(c->side, ev_fork, 0));
             }
             band = c->side;
         }
@@ -452,7 +460,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s, bool firs
         // with a capped bulk update: held and capped at 512 workgroups, steps
         // stalled for about 0.1 s on MI355X)
         const bool hold_bulk = c->overlap && fused && c->bulk_blocks == 0 && c->hold_bulk != 0;
-        if (hold_bulk) HIPCHK(c, hipEventRecord(c->ev_adv, band));
+        if (hold_bulk) HIPCHK(c, hipEventRecord(ev_adv, band));
         {
             Bracket b(c, 1, band);
             HIPCHK(c, launch_extrapolate(g, c->bb, s, band, fused ? ff : 0));
@@ -462,7 +470,7 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s, bool firs
         // step's is ordered by the fork).  Not before the extrapolation: the
         // wait delays its launch until the bulk update has filled the
         // compute units (FP64 step 0.179 -> 0.213 ms)
-        if (c->overlap && !first) HIPCHK(c, hipStreamWaitEvent(band, c->ev_bulk, 0));
+        if (c->overlap && !first) HIPCHK(c, hipStreamWaitEvent(band, prev_bulk, 0));
         {
             // relabel and the stress divergence (one pass); with overlap also
             // the lattice update of the window's nodes
@@ -473,29 +481,30 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s, bool firs
                                    band, c->overlap ? &lf : nullptr));
             // the new solid box into the next ring slot (the band lattice
             // launch does this when the force pass leaves the lattice to it)
-            if (c->overlap) HIPCHK(c, launch_reduce_window(g, c->bb, s.wnext, band));
+            if (c->overlap) HIPCHK(c, launch_reduce_window(g, c->bb, s.wcur, s.wnext, band));
             b.done();
         }
         if (c->overlap) {
-            // the waits below bind to the records of the previous step: they
-            // are enqueued before this step's records of the same events
-            // the early tiles of a held bulk update: after the previous
-            // step's chain (the window of this step, the lattice rows of the
-            // previous one and its readers of this step's target lattice are
-            // then final), beside this step's chain, whose kernels write no
-            // lattice node outside the window and read none this launch
-            // writes
+            // prev_join and prev_bulk are the previous step's events
+            // the early tiles of a held bulk update: the tile rows of its
+            // range that lie wholly below the previous step's window (by more
+            // than BULK_EARLY_GAP rows), launched after the previous step's
+            // bulk update alone.  The chain of the previous step writes the
+            // lattice and the forces only inside that window, and reads the
+            // lattice only there and one node around it; this step's window
+            // lies above those rows (its box moves down by BULK_EARLY_GAP rows
+            // at most, else health[6] counts it), and the launch reads
+            // neither this step's window nor a force plane
             const int early = hold_bulk && !c->timing ? bulk_early(c) : 0;
-            if (early > 0) {
-                if (!first) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
+            if (early > 0)
                 HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt],
                                     c->Fx[s.nxt], c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur],
                                     c->drho, c->bb.win, s.wprev, s.wcur, ox, oy, 3,
-                                    c->bb.health, main_s, 0, nullptr, 0, nullptr, 0, 0, early));
-            }
-            if (hold_bulk) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_adv, 0));
-            else if (!first) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
-            HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+                                    c->bb.health, main_s, 0, nullptr, 0, nullptr, 0, 0, early,
+                                    1));
+            if (hold_bulk) HIPCHK(c, hipStreamWaitEvent(main_s, ev_adv, 0));
+            else if (!first) HIPCHK(c, hipStreamWaitEvent(main_s, prev_join, 0));
+            HIPCHK(c, hipEventRecord(ev_join, c->side));
             {
                 // every node outside the window (but the early tiles): its
                 // update needs no force of this step's chain
@@ -503,11 +512,12 @@ static int enqueue_step(lbrmt_ctx* c, long long n, hipStream_t main_s, bool firs
                 HIPCHK(c, launch_lb(g, prec, c->lb_variant, c->lat[s.cur], c->lat[s.nxt], c->Fx[s.nxt],
                                     c->Fy[s.nxt], c->Fx[s.cur], c->Fy[s.cur], c->drho, c->bb.win,
                                     s.wprev, s.wcur, ox, oy, 3, c->bb.health, main_s,
-                                    c->bulk_blocks, nullptr, 0, nullptr, 0, early, 1000));
+                                    c->bulk_blocks, nullptr, 0, nullptr, 0, early, 1000,
+                                    early > 0 ? 2 : 0));
                 b.done();
             }
-            if (last) HIPCHK(c, hipStreamWaitEvent(main_s, c->ev_join, 0));
-            else HIPCHK(c, hipEventRecord(c->ev_bulk, main_s));
+            if (last) HIPCHK(c, hipStreamWaitEvent(main_s, ev_join, 0));
+            else HIPCHK(c, hipEventRecord(ev_bulk, main_s));
             return LBRMT_OK;
         }
     }
@@ -750,10 +760,12 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
     }
     hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_adv, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_bulk, hipEventDisableTiming);
+    for (int k = 0; k < GRAPH_STEPS; k++) {
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_adv[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_bulk[k], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         int rc = fail(c, "stream/event creation", e);
         lbrmt_destroy(c);
@@ -781,10 +793,12 @@ void lbrmt_destroy(lbrmt_ctx* c)
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     destroy_graphs(c);
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
-    if (c->ev_adv) (void)hipEventDestroy(c->ev_adv);
-    if (c->ev_bulk) (void)hipEventDestroy(c->ev_bulk);
+    for (int k = 0; k < GRAPH_STEPS; k++) {
+        if (c->ev_fork[k]) (void)hipEventDestroy(c->ev_fork[k]);
+        if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+        if (c->ev_adv[k]) (void)hipEventDestroy(c->ev_adv[k]);
+        if (c->ev_bulk[k]) (void)hipEventDestroy(c->ev_bulk[k]);
+    }
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->side) (void)hipStreamDestroy(c->side);
     delete c;

@@ -45,6 +45,11 @@ constexpr int MB_MAX_PER_BLOCK = 32;  // solids overlapping one force block
 constexpr int MB_COMBINE_BLOCKS = 2048;
 // a sub-window moves when its solid's zone comes this close to its border
 constexpr int MB_RECENTRE_MARGIN = 4;
+// the early part of a held bulk update takes tile rows wholly below the
+// previous step's window by more than this many rows; a solid box whose
+// lower edge moves down by more than this in one step is counted in
+// health[6] (the early launch may then have updated nodes of the window)
+constexpr int BULK_EARLY_GAP = 2;
 
 // Axis-aligned box of the interior solid nodes of one body (i0 > i1: empty).
 // The working window of a step is this box dilated by `layers` nodes.
@@ -472,13 +477,19 @@ hipError_t launch_lb_batch(int precision, int variant, const LbArgs* args, const
                            int total_tiles, hipStream_t st);
 // PART 0 / 2 launches with nbox > 0 also reduce the force pass's partial
 // boxes (boxpart) into ring slot wnext of win.  PART 3 updates the tiles
-// [frac0, frac1) / 1000 of the grid's tiles (none if that range is empty).
+// [frac0, frac1) / 1000 of the grid's tiles (none if that range is empty);
+// split 1 (the early launch, frac0 = 0): of those only the tile rows wholly
+// below the previous step's window by more than BULK_EARLY_GAP rows, without
+// reading this step's window; split 2 (the held launch, frac0 = the early
+// launch's frac1): also the tiles of the early range the early launch
+// leaves, striding from the first of them.
 hipError_t launch_lb(const GridP& g, int precision, int variant, const void* A, void* B,
                      const double* fpx, const double* fpy, const double* fcx, const double* fcy,
                      const double* drho, Win* win, int wprev, int wcur, double fpo_x,
                      double fpo_y, int part, unsigned* health, hipStream_t st,
                      int max_blocks = 0, const int* boxpart = nullptr, int nbox = 0,
-                     Win* winw = nullptr, int wnext = 0, int frac0 = 0, int frac1 = 1000);
+                     Win* winw = nullptr, int wnext = 0, int frac0 = 0, int frac1 = 1000,
+                     int split = 0);
 int lb_variant_count();
 void lb_variant_tile(int v, int* tx, int* ty);
 // drho0 (several solids): the density excess of every node, instead of the
@@ -548,7 +559,8 @@ hipError_t launch_force(const GridP& g, const BodyP& b, const BandBufs& bb, cons
                         double* fx, double* fy, double* drho, hipStream_t st,
                         const LbFuse* lf = nullptr);
 // the force pass's partial boxes into ring slot wnext, with the zone check
-hipError_t launch_reduce_window(const GridP& g, const BandBufs& bb, int wnext, hipStream_t st);
+hipError_t launch_reduce_window(const GridP& g, const BandBufs& bb, int wcur, int wnext,
+                                hipStream_t st);
 hipError_t launch_read_stress(const GridP& g, const BodyP& b, const BandBufs& bb, int buf,
                               int wvalid, double* sxx, double* sxy, double* syy, hipStream_t st);
 hipError_t launch_read_refmap(const GridP& g, const BodyP& b, const BandBufs& bb, int buf, int wvalid, double* X,
