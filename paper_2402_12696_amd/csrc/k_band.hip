@@ -1142,19 +1142,143 @@ __global__ __launch_bounds__(256) void kb_layer_fit(const FitArgs* __restrict__ 
 
 // Every layer of one solid in one block (several solids: a solid's layers
 // are short, so one block per solid runs them in order, separated by block
-// barriers, instead of one launch per layer over all solids).  The barrier
-// makes a layer's fitted values visible to the next layer's block.
-template <typename T>
-__global__ __launch_bounds__(1024) void kb_fit_layers(const FitArgs* __restrict__ args, int layers)
+// barriers that make a layer's fitted values visible to the next layer,
+// instead of one launch per layer over all solids), on an LDS copy of its
+// window dilated by 2 (tags, and the map values of its solid nodes and of each node
+// fitted so far), as the one-launch single-solid kernel does for a tile: a
+// scan window of half-width 2 around a target (which lies in the window) is
+// read from the copy.  The copy is laid out in unwrapped coordinates, each
+// node holding what its periodic image holds, so it is kept only while no
+// two of its nodes are images of one node (the copy no wider than a period).
+// A target whose fit needs a wider window takes the global path (fit_target,
+// the full search from half-width 2, on the values written back so far), and
+// so does every target of a solid whose copy would exceed MB_FIT_LDS_NODES
+// nodes or a period.  The same per-target arithmetic as layer_fit_body, so
+// the same bits.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ args, int layers)
 {
+    __shared__ int8_t st[MB_FIT_LDS_NODES];
+    __shared__ T sx[MB_FIT_LDS_NODES], sy[MB_FIT_LDS_NODES];
+    __shared__ int s_ns[(MAX_LAYERS + 1) * NSUB];  // sub-list lengths, read once
+    constexpr int NG = NT / FIT_LANES;
     const FitArgs& a = args[blockIdx.y];
+    const GridP& g = a.g;
+    const Rect W = window_of(a.win, a.wcur, g);
+    const Rect D = window_of(a.win, a.wprev, g);
+    if (!W.ok) return;
+    const int bx0 = W.i0 - 2, by0 = W.j0 - 2;
+    const int bw = W.i1 - W.i0 + 5, bh = W.j1 - W.j0 + 5;
+    if ((long long)bw * bh > MB_FIT_LDS_NODES || (g.px && bw > g.nx) || (g.py && bh > g.ny)) {
+        for (int l = 1; l <= layers; l++) {
+            if (float_sums(g, l))
+                layer_fit_body<T, float>(g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
+                                         (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+            else
+                layer_fit_body<T, double>(g, a.win, a.wcur, a.wprev, l, a.tag, a.lists,
+                                          a.lcount, (const T*)a.phin, (T*)a.X1, (T*)a.Y1,
+                                          a.health);
+            __syncthreads();
+        }
+        return;
+    }
+    T* X1 = (T*)a.X1;
+    T* Y1 = (T*)a.Y1;
+    const T* phin = (const T*)a.phin;
+    const long long cap = g.lcap;
+    // the copy: nodes outside the window hold no value (as in fit_window,
+    // which wraps a node's periodic axes before the window test); the loads
+    // of U nodes per thread are issued before their stores
+    constexpr int U = 4;
+    const int nn = bw * bh;
+    for (int e0 = threadIdx.x; e0 < nn; e0 += U * NT) {
+        int8_t tv[U];
+        T xv[U], yv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int e = e0 + u * NT;
+            int x = bx0 + e % bw, y = by0 + e / bw;
+            if (g.px) x = wrap_axis(x, g.nx);
+            if (g.py) y = wrap_axis(y, g.ny);
+            const bool in = e < nn && W.has(x, y);
+            const long long k = pidx(g, in ? x : W.i0, in ? y : W.j0);
+            tv[u] = in ? a.tag[k] : (int8_t)TAG_NONE;
+            xv[u] = in ? X1[k] : T(0);
+            yv[u] = in ? Y1[k] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int e = e0 + u * NT;
+            if (e >= nn) break;
+            st[e] = tv[u];
+            sx[e] = xv[u];
+            sy[e] = yv[u];
+        }
+    }
+    for (int q = threadIdx.x; q < (layers + 1) * NSUB; q += NT)
+        s_ns[q] = (int)min((long long)a.lcount[q * LCOUNT_PAD], cap);
+    __syncthreads();
+    // group grp takes sub-list grp mod NSUB, as layer_fit_body does, so the
+    // sub-lists of a layer are fitted side by side; the list entry a group
+    // fits next is loaded while it fits the current one (the lists are
+    // complete before the kernel starts)
+    static_assert(NG % NSUB == 0, "whole groups per sub-list");
+    constexpr int AS = NG / NSUB;
+    const int sub = threadIdx.x % FIT_LANES, grp = threadIdx.x / FIT_LANES;
+    const int sl = grp % NSUB, a0 = grp / NSUB;
+    int knext = a0 < s_ns[NSUB + sl] ? a.lists[(NSUB + sl) * cap + a0] : 0;
     for (int l = 1; l <= layers; l++) {
-        if (float_sums(a.g, l))
-            layer_fit_body<T, float>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
-                                     (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
-        else
-            layer_fit_body<T, double>(a.g, a.win, a.wcur, a.wprev, l, a.tag, a.lists, a.lcount,
-                                      (const T*)a.phin, (T*)a.X1, (T*)a.Y1, a.health);
+        const int* list = a.lists + (l * NSUB + sl) * cap;
+        const int ns = s_ns[l * NSUB + sl];
+        // every lane of a group runs the same trip counts
+        for (int at = a0; at < ns; at += AS) {
+            const int kt = knext;
+            knext = at + AS < ns ? list[at + AS] : 0;
+            const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
+            const int li = i - bx0, lj = j - by0;
+            double nxh, nyh;
+            const bool use_n = target_normal<T>(g, D, l, i, j, sub, phin, nxh, nyh);
+            T xo = T(0), yo = T(0);
+            bool done, cut;
+            int count = 0;
+            if (float_sums(g, l)) {
+                Fit<T, float> f;
+                f.zero();
+                fit_window_lds_r2<T, float>(l, li, lj, sub, use_n, nxh, nyh, st, sx, sy, bw,
+                                            f, count);
+                done = fit_finish<T, float>(g, f, count, xo, yo);
+                if (!done && g.r_max > 2)
+                    done = fit_target<T, float>(g, W, D, l, kt, i, j, sub, g.r_max, a.tag,
+                                                phin, X1, Y1, xo, yo, cut);
+            } else {
+                Fit<T, double> f;
+                f.zero();
+                fit_window_lds_r2<T, double>(l, li, lj, sub, use_n, nxh, nyh, st, sx, sy,
+                                             bw, f, count);
+                done = fit_finish<T, double>(g, f, count, xo, yo);
+                if (!done && g.r_max > 2)
+                    done = fit_target<T, double>(g, W, D, l, kt, i, j, sub, g.r_max, a.tag,
+                                                 phin, X1, Y1, xo, yo, cut);
+            }
+            if (sub == 0) {
+                const int q = lj * bw + li;
+                if (done) {
+                    sx[q] = xo;
+                    sy[q] = yo;
+                    X1[kt] = xo;
+                    Y1[kt] = yo;
+                } else {
+                    st[q] = (int8_t)(l | TAG_FAIL);
+                    a.tag[kt] = (int8_t)(l | TAG_FAIL);
+                    atomicAdd(&a.health[1], 1u);
+                }
+            }
+        }
+        if (l < layers) {
+            const int n1 = s_ns[(l + 1) * NSUB + sl];
+            knext = a0 < n1 ? a.lists[((l + 1) * NSUB + sl) * cap + a0] : 0;
+        }
+        // the layer's values (copy and global) before the next layer reads them
         __syncthreads();
     }
 }
@@ -2601,7 +2725,7 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
                              int band_blocks, bool fused)
 {
     const dim3 gb(band_blocks, nsim), gd(dt_blocks, nsim), gf(fit_blocks, nsim);
-    // fit_blocks == 0: every layer of a member in one block of MB_FIT_THREADS;
+    // fit_blocks == 0: every layer of a member in one block (kb_fit_lds);
     // fused: every layer of a member in one launch over its zone tiles (the
     // members' advection pass lists those tiles)
     const dim3 g1(1, nsim), gz(FF_BATCH_BLOCKS, nsim);
@@ -2611,9 +2735,11 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
         if (fused) {
             kb_fit_fused<double><<<gz, 1024, 0, st>>>(t.fit);
             kb_fit_rest<double><<<g1, FF_REST_THREADS, 0, st>>>(t.fit);
-        } else if (fit_blocks == 0) kb_fit_layers<double><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
-        else
+        } else if (fit_blocks == 0) {
+            kb_fit_lds<double, MB_FIT_THREADS_F64><<<g1, MB_FIT_THREADS_F64, 0, st>>>(t.fit, layers);
+        } else {
             for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
+        }
         if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg);
         else kb_force<0, double><<<gb, 256, 0, st>>>(t.edg);
     } else {
@@ -2622,9 +2748,11 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
         if (fused) {
             kb_fit_fused<float><<<gz, 1024, 0, st>>>(t.fit);
             kb_fit_rest<float><<<g1, FF_REST_THREADS, 0, st>>>(t.fit);
-        } else if (fit_blocks == 0) kb_fit_layers<float><<<g1, MB_FIT_THREADS, 0, st>>>(t.fit, layers);
-        else
+        } else if (fit_blocks == 0) {
+            kb_fit_lds<float, MB_FIT_THREADS_F32><<<g1, MB_FIT_THREADS_F32, 0, st>>>(t.fit, layers);
+        } else {
             for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
+        }
         if (relabel_only) kb_force<2, float><<<gb, 256, 0, st>>>(t.edg);
         else kb_force<0, float><<<gb, 256, 0, st>>>(t.edg);
     }

@@ -40,7 +40,12 @@ constexpr int FB_LOG = 4;
 constexpr int FB = 1 << FB_LOG;
 constexpr int MB_DT_BLOCKS = 16;      // per solid (a multiple of NSUB)
 constexpr int MB_BAND_BLOCKS = 16;    // relabel: two partial boxes per block
-constexpr int MB_FIT_THREADS = 1024;  // one block per solid runs all its layers
+// one block per solid runs all its layers; 768 threads leave 170 registers a
+// lane (1024 would leave 128, and both precisions would spill)
+constexpr int MB_FIT_THREADS_F64 = 768;
+constexpr int MB_FIT_THREADS_F32 = 768;
+// nodes of a several-solid fit block's LDS copy (its window dilated by 2)
+constexpr int MB_FIT_LDS_NODES = 8192;
 constexpr int MB_MAX_PER_BLOCK = 32;  // solids overlapping one force block
 constexpr int MB_COMBINE_BLOCKS = 2048;
 // a sub-window moves when its solid's zone comes this close to its border
