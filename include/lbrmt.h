@@ -338,8 +338,9 @@ int lbrmt_kernel_time(lbrmt_ctx* ctx, const char* name, double* avg_ms, int64_t*
  *                         0: one launch per layer; 1: 1024 threads with the
  *                         margin check one node tighter, so that the second
  *                         launch finishes most tiles (a check of that
- *                         launch); -1 (default): 1024, or 0 when
- *                         LBRMT_OPT_BULK_BLOCKS caps the bulk update.  With
+ *                         launch); -1 (default): 512 in FP64 and 1024
+ *                         in FP32, or 0 when LBRMT_OPT_BULK_BLOCKS caps
+ *                         the bulk update.  With
  *                         overlap and no cap, the bulk lattice update then
  *                         starts when the advection pass has finished, so
  *                         that these blocks are resident before the bulk
