@@ -1169,6 +1169,11 @@ __global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ arg
     __shared__ int8_t st[MB_FIT_LDS_NODES];
     __shared__ T sx[MB_FIT_LDS_NODES], sy[MB_FIT_LDS_NODES];
     __shared__ int s_ns[(MAX_LAYERS + 1) * NSUB];  // sub-list lengths, read once
+    // FP32: phi^n of the copy's nodes inside the previous window (+inf
+    // elsewhere, as ref_index leaves it), for the normals of layers 1 and 2
+    // (in FP64 the copy of phi^n would not fit beside the map values)
+    constexpr bool SPHI = sizeof(T) == 4;
+    __shared__ T sp[SPHI ? MB_FIT_LDS_NODES : 1];
     constexpr int NG = NT / FIT_LANES;
     const FitArgs& a = args[blockIdx.y];
     const GridP& g = a.g;
@@ -1201,7 +1206,7 @@ __global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ arg
     const int nn = bw * bh;
     for (int e0 = threadIdx.x; e0 < nn; e0 += U * NT) {
         int8_t tv[U];
-        T xv[U], yv[U];
+        T xv[U], yv[U], pv[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int e = e0 + u * NT;
@@ -1213,6 +1218,10 @@ __global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ arg
             tv[u] = in ? a.tag[k] : (int8_t)TAG_NONE;
             xv[u] = in ? X1[k] : T(0);
             yv[u] = in ? Y1[k] : T(0);
+            if constexpr (SPHI) {
+                const bool ind = e < nn && D.has(x, y);
+                pv[u] = ind ? phin[pidx(g, ind ? x : W.i0, ind ? y : W.j0)] : T(INFINITY);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -1221,6 +1230,7 @@ __global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ arg
             st[e] = tv[u];
             sx[e] = xv[u];
             sy[e] = yv[u];
+            if constexpr (SPHI) sp[e] = pv[u];
         }
     }
     for (int q = threadIdx.x; q < (layers + 1) * NSUB; q += NT)
@@ -1245,7 +1255,25 @@ __global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ arg
             const int i = kt % g.pp - PAD, j = kt / g.pp - PAD;
             const int li = i - bx0, lj = j - by0;
             double nxh, nyh;
-            const bool use_n = target_normal<T>(g, D, l, i, j, sub, phin, nxh, nyh);
+            bool use_n;
+            if constexpr (SPHI) {
+                // target_normal with the four neighbours read from the copy
+                nxh = nyh = 0.0;
+                use_n = false;
+                if (l <= 2) {
+                    double p = INFINITY;
+                    if (sub < 4) {
+                        const int di = sub == 0 ? 1 : sub == 1 ? -1 : 0;
+                        const int dj = sub == 2 ? 1 : sub == 3 ? -1 : 0;
+                        p = (double)sp[(lj + dj) * bw + li + di];
+                    }
+                    const double pe = __shfl(p, 0, FIT_LANES), pw = __shfl(p, 1, FIT_LANES);
+                    const double pn = __shfl(p, 2, FIT_LANES), ps = __shfl(p, 3, FIT_LANES);
+                    use_n = normal_from(pe, pw, pn, ps, nxh, nyh);
+                }
+            } else {
+                use_n = target_normal<T>(g, D, l, i, j, sub, phin, nxh, nyh);
+            }
             T xo = T(0), yo = T(0);
             bool done, cut;
             int count = 0;
