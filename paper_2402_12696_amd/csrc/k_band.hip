@@ -677,9 +677,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 5 : 1, 8))) void k_advect_dt
 // fewer rounds (FP32 step 0.634 -> 0.619 ms; FP64 0.998 -> 0.994)
 template <int LC, typename S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void kb_advect_dt(
-    const AdvectArgs* __restrict__ args)
+    const AdvectArgs* __restrict__ args, const int* __restrict__ ord)
 {
-    const AdvectArgs& a = args[blockIdx.y];
+    const AdvectArgs& a = args[ord ? ord[blockIdx.y] : blockIdx.y];
     dt_tile_body<LC, true, S>(a.g, a.win, a.wcur, a.wprev, a.tag, a.lists, a.lcount, a.health,
                               (const S*)a.A, a.fpx, a.fpy, (const S*)a.X, (const S*)a.Y,
                               (const S*)a.phi, (S*)a.X1, (S*)a.Y1, a.ff_flag, a.ff_list, a.ff_n);
@@ -1164,7 +1164,8 @@ __global__ __launch_bounds__(256) void kb_layer_fit(const FitArgs* __restrict__ 
 // nodes or a period.  The same per-target arithmetic as layer_fit_body, so
 // the same bits.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ args, int layers)
+__global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ args, int layers,
+                                                  const int* __restrict__ ord)
 {
     __shared__ int8_t st[MB_FIT_LDS_NODES];
     __shared__ T sx[MB_FIT_LDS_NODES], sy[MB_FIT_LDS_NODES];
@@ -1175,7 +1176,7 @@ __global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ arg
     constexpr bool SPHI = sizeof(T) == 4;
     __shared__ T sp[SPHI ? MB_FIT_LDS_NODES : 1];
     constexpr int NG = NT / FIT_LANES;
-    const FitArgs& a = args[blockIdx.y];
+    const FitArgs& a = args[ord ? ord[blockIdx.y] : blockIdx.y];
     const GridP& g = a.g;
     const Rect W = window_of(a.win, a.wcur, g);
     const Rect D = window_of(a.win, a.wprev, g);
@@ -2766,26 +2767,28 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
     // members' advection pass lists those tiles)
     const dim3 g1(1, nsim), gz(FF_BATCH_BLOCKS, nsim);
     if (precision == 0) {
-        if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv);
-        else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv);
+        if (layers == 11) kb_advect_dt<11, double><<<gd, 256, 0, st>>>(t.adv, t.ord);
+        else kb_advect_dt<0, double><<<gd, 256, 0, st>>>(t.adv, t.ord);
         if (fused) {
             kb_fit_fused<double><<<gz, 1024, 0, st>>>(t.fit);
             kb_fit_rest<double><<<g1, FF_REST_THREADS, 0, st>>>(t.fit);
         } else if (fit_blocks == 0) {
-            kb_fit_lds<double, MB_FIT_THREADS_F64><<<g1, MB_FIT_THREADS_F64, 0, st>>>(t.fit, layers);
+            kb_fit_lds<double, MB_FIT_THREADS_F64><<<g1, MB_FIT_THREADS_F64, 0, st>>>(t.fit, layers,
+                                                                                 t.ord);
         } else {
             for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
         }
         if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg);
         else kb_force<0, double><<<gb, 256, 0, st>>>(t.edg);
     } else {
-        if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv);
-        else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv);
+        if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv, t.ord);
+        else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv, t.ord);
         if (fused) {
             kb_fit_fused<float><<<gz, 1024, 0, st>>>(t.fit);
             kb_fit_rest<float><<<g1, FF_REST_THREADS, 0, st>>>(t.fit);
         } else if (fit_blocks == 0) {
-            kb_fit_lds<float, MB_FIT_THREADS_F32><<<g1, MB_FIT_THREADS_F32, 0, st>>>(t.fit, layers);
+            kb_fit_lds<float, MB_FIT_THREADS_F32><<<g1, MB_FIT_THREADS_F32, 0, st>>>(t.fit, layers,
+                                                                                t.ord);
         } else {
             for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
         }

@@ -116,7 +116,7 @@ struct Layout {
     // several solids
     int nbx, nby;
     size_t off_stamp[2], off_mlist[2], off_mcount, off_dstep, off_mbtab, off_tabs, off_bsum,
-        off_bodies, body_bytes;
+        off_mord, off_bodies, body_bytes;
 };
 
 Layout make_layout(const lbrmt_grid_desc* d, int max_solids = 1)
@@ -183,6 +183,7 @@ Layout make_layout(const lbrmt_grid_desc* d, int max_solids = 1)
                                                      sizeof(FitArgs) + sizeof(EdgesArgs)) +
                                4 * ALIGN));
         L.off_bsum = take((size_t)max_solids * 7 * 8);
+        L.off_mord = take((size_t)max_solids * 4);
         L.body_bytes = body_layout(d, mb_geom(d)).total;
         L.off_bodies = take((size_t)max_solids * L.body_bytes);
     }
@@ -254,6 +255,7 @@ struct lbrmt_ctx {
     std::vector<MbBody> mbh;   // host copy of the solid table
     MbBody* mbd = nullptr;     // device table
     BatchTables mtab[7];       // chain argument tables, phases as for batches
+    int* mord = nullptr;       // solids by decreasing size (rows of the chain's block grids)
     int* stamp[2] = {nullptr, nullptr};
     int* mlist[2] = {nullptr, nullptr};
     int* mcount = nullptr;
@@ -742,6 +744,7 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
         c->dstep = (long long*)(c->ws + L.off_dstep);
         c->mbd = (MbBody*)(c->ws + L.off_mbtab);
         c->bsum = (double*)(c->ws + L.off_bsum);
+        c->mord = (int*)(c->ws + L.off_mord);
         char* t = c->ws + L.off_tabs;
         auto carve = [&](size_t bytes_) {
             char* p_ = t;
@@ -754,6 +757,7 @@ static int create_impl(const lbrmt_grid_desc* d, int32_t max_solids, void* ws, s
             c->mtab[p].fit = (FitArgs*)carve(max_solids * sizeof(FitArgs));
             c->mtab[p].edg = (EdgesArgs*)carve(max_solids * sizeof(EdgesArgs));
             c->mtab[p].lb = nullptr;
+            c->mtab[p].ord = c->mord;
         }
     }
     if (member) {
@@ -933,6 +937,20 @@ static int mb_tables(lbrmt_ctx* c)
     std::vector<LayersArgs> lay(nb);
     std::vector<FitArgs> fit(nb);
     std::vector<EdgesArgs> edg(nb);
+    // the advection and extrapolation passes (a group of blocks, or one
+    // block, per solid; more than the GPU holds at once) start the largest
+    // solids first, so that the last blocks to start are the shortest: their
+    // block rows take the solids by decreasing semi-axis sum (each solid's
+    // work is its own, so the order changes no result)
+    std::vector<int> ord(nb);
+    for (int k = 0; k < nb; k++) ord[k] = k;
+    auto size_of = [&](int k) {
+        const BodyP& b = c->mbh[k].b;
+        return b.R + (b.shape == 1 ? b.Rb : b.R);
+    };
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int x, int y) { return size_of(x) > size_of(y); });
+    HIPCHK(c, hipMemcpyAsync(c->mord, ord.data(), nb * sizeof(int), hipMemcpyHostToDevice, c->st));
     for (int p = 0; p < 7; p++) {
         const long long nstep = p == 6 ? 0 : (p == 0 ? 6 : p);
         const StepSlots s = slots_for(nstep);

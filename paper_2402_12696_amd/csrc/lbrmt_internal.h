@@ -310,6 +310,9 @@ struct BatchTables {
     FitArgs* fit;
     EdgesArgs* edg;
     LbArgs* lb;
+    // the table row that block row y of the advection and extrapolation
+    // passes takes (null: row y)
+    const int* ord = nullptr;
 };
 // blocks per member of the batched reference-map kernels (the distance
 // transform count is a multiple of NSUB and at most DT_BLOCKS, which the list
