@@ -2027,9 +2027,10 @@ __global__ __launch_bounds__(256) void k_edges(GridP g, BodyP b, Win* win, int w
 }
 
 template <int MODE, typename C>
-__global__ __launch_bounds__(256) void kb_force(const EdgesArgs* __restrict__ args)
+__global__ __launch_bounds__(256) void kb_force(const EdgesArgs* __restrict__ args,
+                                                const int* __restrict__ ord)
 {
-    const EdgesArgs& a = args[blockIdx.y];
+    const EdgesArgs& a = args[ord ? ord[blockIdx.y] : blockIdx.y];
     edges_body<MODE, C>(a.g, a.b, a.win, a.wvalid, a.boxpart, 0, (C*)a.X, (C*)a.Y, nullptr,
                         a.tag, (C*)a.phi, a.o0, a.o1, a.o2, a.lcount, a.health, LbFuse{});
 }
@@ -2778,8 +2779,8 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
         } else {
             for (int l = 1; l <= layers; l++) kb_layer_fit<double><<<gf, 256, 0, st>>>(t.fit, l);
         }
-        if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg);
-        else kb_force<0, double><<<gb, 256, 0, st>>>(t.edg);
+        if (relabel_only) kb_force<2, double><<<gb, 256, 0, st>>>(t.edg, t.ord);
+        else kb_force<0, double><<<gb, 256, 0, st>>>(t.edg, t.ord);
     } else {
         if (layers == 11) kb_advect_dt<11, float><<<gd, 256, 0, st>>>(t.adv, t.ord);
         else kb_advect_dt<0, float><<<gd, 256, 0, st>>>(t.adv, t.ord);
@@ -2792,8 +2793,8 @@ hipError_t launch_batch_band(int precision, const BatchTables& t, int nsim, int 
         } else {
             for (int l = 1; l <= layers; l++) kb_layer_fit<float><<<gf, 256, 0, st>>>(t.fit, l);
         }
-        if (relabel_only) kb_force<2, float><<<gb, 256, 0, st>>>(t.edg);
-        else kb_force<0, float><<<gb, 256, 0, st>>>(t.edg);
+        if (relabel_only) kb_force<2, float><<<gb, 256, 0, st>>>(t.edg, t.ord);
+        else kb_force<0, float><<<gb, 256, 0, st>>>(t.edg, t.ord);
     }
     return hipGetLastError();
 }
