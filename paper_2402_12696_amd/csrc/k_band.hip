@@ -1152,17 +1152,18 @@ __global__ __launch_bounds__(256) void kb_layer_fit(const FitArgs* __restrict__ 
 // are short, so one block per solid runs them in order, separated by block
 // barriers that make a layer's fitted values visible to the next layer,
 // instead of one launch per layer over all solids), on an LDS copy of its
-// window dilated by 2 (tags, and the map values of its solid nodes and of each node
-// fitted so far), as the one-launch single-solid kernel does for a tile: a
-// scan window of half-width 2 around a target (which lies in the window) is
-// read from the copy.  The copy is laid out in unwrapped coordinates, each
-// node holding what its periodic image holds, so it is kept only while no
-// two of its nodes are images of one node (the copy no wider than a period).
-// A target whose fit needs a wider window takes the global path (fit_target,
-// the full search from half-width 2, on the values written back so far), and
-// so does every target of a solid whose copy would exceed MB_FIT_LDS_NODES
-// nodes or a period.  The same per-target arithmetic as layer_fit_body, so
-// the same bits.
+// window dilated by 2 (tags and map values; each fitted value is written to
+// the copy as well as to HBM), as the one-launch single-solid kernel does
+// for a tile: a scan window of half-width 2 around a target (which lies in
+// the window) is read from the copy.  The copy is laid out in unwrapped
+// coordinates, each node holding what its periodic image holds, so it is
+// kept only while no two of its nodes are images of one node (the copy no
+// wider than a period).  A target whose fit needs a wider window takes the
+// global path (fit_target, the full search from half-width 2, on the values
+// written back so far), and so does every target of a solid whose copy
+// would exceed MB_FIT_LDS_NODES nodes or a period.  The same per-target
+// arithmetic as layer_fit_body, so the same bits.  Block row y takes table
+// row ord[y] (row y when ord is null).
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void kb_fit_lds(const FitArgs* __restrict__ args, int layers,
                                                   const int* __restrict__ ord)
