@@ -58,7 +58,9 @@ constexpr int MB_FIT_THREADS_F32 = 768;
 // nodes of a several-solid fit block's LDS copy (its window dilated by 2)
 constexpr int MB_FIT_LDS_NODES = 8192;
 constexpr int MB_MAX_PER_BLOCK = 32;  // solids overlapping one force block
-constexpr int MB_COMBINE_BLOCKS = 2048;
+// force combine of several solids: blocks striding over the stamped force
+// blocks (4096: suspension FP32 step 0.5416 -> 0.5370 ms against 2048)
+constexpr int MB_COMBINE_BLOCKS = 4096;
 // a sub-window moves when its solid's zone comes this close to its border
 constexpr int MB_RECENTRE_MARGIN = 4;
 // the early part of a held bulk update takes tile rows wholly below the
